@@ -1,0 +1,204 @@
+/*
+ * reloc.h -- C ABI of the MI355X (gfx950) regression-forest relocaliser.
+ *
+ * The operation is the per-sub-scene relocaliser of Golodetz et al.,
+ * "Collaborative Large-Scale Dense 3D Reconstruction with Online Inter-Agent
+ * Pose Optimisation": a regression forest trained online from the posed
+ * RGB-D frames of one agent (Sec. 3.3), which, given an RGB-D frame of
+ * another agent's scene, either fails or returns an estimated pose of that
+ * frame in its own coordinate system (Sec. 3.3.1, Fig. 4). Its leaves hold a
+ * bounded set of 3D modes (at most 10 in the configurations here; Sec. 4.2.1);
+ * new forests start with empty leaves and improve as frames arrive
+ * (Sec. 4.3.1); their training samples can be deleted once trained
+ * (Sec. 4.3.2). A relocalisation is correct within 5 cm and 5 degrees
+ * (Table 2). The paper treats the relocaliser as a black box; the rules for
+ * features, reservoirs, modes, hypotheses, energies and culls are this
+ * library's definition and are the same rules the CPU oracle implements.
+ *
+ * Conventions
+ *  - Every function returns an int status: 0 = RELOC_OK, < 0 = error,
+ *    > 0 = a relocalisation outcome that is not an error (RELOC_FAIL_*).
+ *    No exception crosses the ABI.
+ *  - Frames are caller-owned DEVICE pointers: depth uint16 [H][W] in mm,
+ *    rgb uint8 [H][W][3], contiguous, row-major. They are read in stream
+ *    order during the call; the library keeps no reference afterwards.
+ *  - Poses are host arrays: row-major float64 4x4 camera-to-world; the
+ *    translation column is the camera centre.
+ *  - Streams are hipStream_t passed as void* (NULL = the null stream).
+ *    reloc_relocalise is synchronous on its stream (it writes a host pose);
+ *    every other call is stream-asynchronous.
+ *  - A forest handle owns all of its device memory and is not thread-safe;
+ *    different handles are independent.
+ */
+#ifndef RELOC_H
+#define RELOC_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum reloc_status {
+    RELOC_OK = 0,
+    RELOC_FAIL_NO_VALID_PIXELS = 1,  /* the query frame has no depth in [depth_min, depth_max] */
+    RELOC_FAIL_NO_MODES = 2,         /* the forest has never received a sample */
+    RELOC_FAIL_NO_HYPOTHESIS = 3,    /* no hypothesis passed its checks in max_tries tries */
+    RELOC_E_ARG = -1,                /* null pointer, bad size, bad parameter, non-rigid pose */
+    RELOC_E_NOMEM = -2,              /* device allocation failed */
+    RELOC_E_HIP = -3,                /* a HIP runtime call failed */
+    RELOC_E_STATE = -4,              /* operation not valid in this state (e.g. adapt after drop) */
+    RELOC_E_RANGE = -5               /* a value does not fit the packed device layout */
+};
+
+typedef struct reloc_forest reloc_forest;
+
+typedef struct {
+    int32_t width, height;           /* frame size in pixels */
+    float fx, fy, cx, cy;            /* pinhole intrinsics in pixels */
+} reloc_intrinsics;
+
+/* Method parameters. reloc_params_default fills the 320x240 single-attempt
+ * configuration: 5 trees of depth 10, 256-entry reservoirs, <= 10 modes,
+ * 256 hypotheses, 64 pixels per cull round. */
+typedef struct {
+    int32_t n_trees;          /* T, 1..16 */
+    int32_t depth;            /* D: 2^D leaves and 2^D - 1 split nodes per tree, 1..16 */
+    int32_t reservoir_size;   /* R samples kept per leaf, 1..1024 */
+    int32_t max_modes;        /* M modes per leaf, 1..32 */
+    uint64_t seed;            /* forest seed: split parameters and reservoir draws */
+    int32_t depth_min_mm, depth_max_mm;   /* valid depth range (inclusive) */
+    int32_t offset_pxmm;      /* split offsets uniform in [-O, O] px*mm at the reference focal length */
+    int32_t f_ref_px16;       /* reference focal length in 1/16 px */
+    int32_t thr_depth_mm;     /* depth-split thresholds uniform in [-thr, thr] mm */
+    int32_t thr_rgb;          /* colour-split thresholds uniform in [-thr, thr] */
+    int32_t dens_radius_mm;   /* mode finding: density radius */
+    int32_t link_radius_mm;   /* mode finding: link radius */
+    int32_t min_cluster;      /* minimum cluster size; <= 0 means max(3, R / 64) */
+    int32_t cov_reg_mm2;      /* covariance regulariser added to the diagonal */
+    int32_t n_hypotheses;     /* N pose hypotheses per attempt, 1..4096 */
+    int32_t batch_pixels;     /* B pixels scored per cull round, 1..2048 */
+    int32_t max_tries;        /* tries per hypothesis, 1..1024 */
+    int32_t refine;           /* 1: Kabsch refinement of the survivors on their inliers */
+    int32_t rgb_tol;          /* hypothesis modes must match the pixel colour within this, per channel */
+    float rigid_ratio2;       /* squared-distance ratio bound between camera and world triangles */
+    float min_pair2_m2;       /* minimum squared distance between hypothesis camera points */
+    float min_area2_m4;       /* minimum |e1 x e2|^2 of the hypothesis camera triangle */
+    float resid_m;            /* maximum residual of a hypothesis on its own three points */
+    float inlier_m;           /* inlier radius around the best mode */
+} reloc_params;
+
+/* Fills *out with the defaults described above. */
+int reloc_params_default(reloc_params *out);
+
+/* Creates a forest on the current device: draws the split parameters from
+ * `p->seed` on the GPU and allocates reservoirs (T * 2^D * R * 16 B), slot
+ * stamps (T * 2^D * R * 4 B) and modes (T * 2^D * M * 48 B), all empty.
+ * Returns RELOC_E_ARG for out-of-range parameters, RELOC_E_RANGE when the
+ * offsets or thresholds do not fit the packed 8-byte split nodes. */
+int reloc_forest_create(const reloc_params *p, void *stream, reloc_forest **out);
+
+/* Frees the forest after the work queued on its streams has finished. */
+int reloc_forest_destroy(reloc_forest *f);
+
+/* Online adaptation with one posed frame (Sec. 3.3: the relocaliser is
+ * trained online from the agent's posed frames). For every tree, the valid
+ * pixels are offered to their leaves in raster order; leaf reservoirs follow
+ * Algorithm R with counter-based draws keyed by (tree, leaf, k). Leaves that
+ * changed are marked for mode extraction. `K->width * K->height` pixels are
+ * read from depth_dev / rgb_dev. Asynchronous on `stream`. Errors:
+ * RELOC_E_ARG (null pointer, bad intrinsics, pose not a rigid motion),
+ * RELOC_E_STATE (reservoirs dropped). */
+int reloc_adapt_frame(reloc_forest *f, const uint16_t *depth_dev, const uint8_t *rgb_dev,
+                      const reloc_intrinsics *K, const double pose_c2w[16], void *stream);
+
+/* Extracts the modes of every leaf changed since the last call (at most
+ * max_modes per leaf; Sec. 4.2.1). Relocalisation calls it implicitly.
+ * Asynchronous on `stream`. */
+int reloc_update_modes(reloc_forest *f, void *stream);
+
+/* Relocalises one RGB-D frame (Fig. 4): features and traversal of every
+ * valid pixel, n_hypotheses three-point Kabsch hypotheses, preemptive
+ * scoring with halving culls and inlier refinement. On RELOC_OK writes the
+ * pose (camera-to-world, host array) and the inlier fraction of the final
+ * hypothesis; on RELOC_FAIL_* writes the identity and 0. n_hypotheses <= 0
+ * uses the forest's parameter. pixel_weights_dev (may be NULL) is a device
+ * array of H*W uint32 integer sampling weights for the hypothesis pixel
+ * picks (learned proposal); NULL picks uniformly over valid pixels.
+ * Synchronous on `stream`. */
+int reloc_relocalise(reloc_forest *f, const uint16_t *depth_dev, const uint8_t *rgb_dev,
+                     const reloc_intrinsics *K, uint64_t attempt_seed, int32_t n_hypotheses,
+                     const uint32_t *pixel_weights_dev, double pose_c2w_out[16], float *score_out,
+                     void *stream);
+
+/* Builds every pending mode, then frees the reservoirs and slot stamps (the
+ * paper deletes a relocaliser's training data once it is trained,
+ * Sec. 4.3.2). Relocalisation results are unchanged; further adaptation
+ * returns RELOC_E_STATE. */
+int reloc_forest_drop_reservoirs(reloc_forest *f, void *stream);
+
+/* Device bytes currently held by the forest. */
+int reloc_forest_memory(const reloc_forest *f, uint64_t *bytes_out);
+
+/* A short English description of a status code (static storage). */
+const char *reloc_status_string(int code);
+
+/* ---- per-kernel timing (for measurement; off by default) ----
+ * When enabled, every kernel the library launches is bracketed by two HIP
+ * events recorded on the stream it is launched on. reloc_profile_read sums
+ * the elapsed times of all recorded launches of one kernel (waiting for them
+ * to finish); reloc_profile_kernels writes the comma-separated kernel names
+ * seen so far into `names` (NUL-terminated, truncated to cap - 1 bytes);
+ * reloc_profile_reset forgets all launches. Process-wide; not for use while a
+ * stream is being captured into a graph. */
+int reloc_profile_enable(int on);
+int reloc_profile_reset(void);
+int reloc_profile_read(const char *kernel, double *total_ms, int64_t *launches);
+int reloc_profile_kernels(char *names, int32_t cap);
+
+/* ---- parity and debug exports: synchronous copies into caller HOST buffers ---- */
+
+/* split nodes [T * (2^D - 1)] followed by the 8 per-pixel feature nodes;
+ * kind 0 = depth, 1..3 = colour channel */
+int reloc_debug_nodes(const reloc_forest *f, int32_t *kind, int32_t *dx, int32_t *dy, int32_t *thr);
+/* replaces the split nodes (same layout); RELOC_E_RANGE if a value does not pack */
+int reloc_debug_set_nodes(reloc_forest *f, const int32_t *kind, const int32_t *dx, const int32_t *dy,
+                          const int32_t *thr);
+/* leaf index per tree and pixel, [T][H*W], -1 for invalid pixels */
+int reloc_debug_leaves(reloc_forest *f, const uint16_t *depth_dev, const uint8_t *rgb_dev,
+                       const reloc_intrinsics *K, int32_t *leaves_host, void *stream);
+/* the 8 per-pixel feature responses, [H*W][8], 0 for invalid pixels */
+int reloc_debug_features8(reloc_forest *f, const uint16_t *depth_dev, const uint8_t *rgb_dev,
+                          const reloc_intrinsics *K, int32_t *feat_host, void *stream);
+/* reservoir entries (16 B: int32 x, y, z mm; uint8 r, g, b, pad) of leaves
+ * [leaf0, leaf0 + n) of tree t, [n][R], and their counters [n] */
+int reloc_debug_reservoir(const reloc_forest *f, int32_t t, int32_t leaf0, int32_t n, void *entries_host,
+                          uint32_t *counters_host);
+/* modes (48 B: float mu[3], sinv[6], kappa; int32 n; uint8 rgb[3], pad) of
+ * leaves [leaf0, leaf0 + n) of tree t, [n][M], and their counts [n] */
+int reloc_debug_modes(reloc_forest *f, int32_t t, int32_t leaf0, int32_t n, void *modes_host,
+                      int32_t *n_modes_host);
+/* modes of an arbitrary point set (host entries, n <= 4096) computed by the
+ * GPU mode kernel with the forest's parameters */
+int reloc_debug_modes_from_points(reloc_forest *f, const void *entries_host, int32_t n, void *modes_host,
+                                  int32_t *n_modes_host);
+
+/* Trace of the most recent reloc_relocalise on this forest (capacities in
+ * elements; any pointer may be NULL):
+ *   hyp_try [N]: first passing try or -1;  hyp_pose [N][12]: initial R then t
+ *   n_rounds; n_alive [rounds]; alive [rounds][N]; energy [rounds][N];
+ *   n_inliers [rounds][N] (by position in alive);  final_hyp; pool_size */
+typedef struct {
+    int32_t cap_hyp, cap_rounds;
+    int32_t *pool_size, *hyp_try;
+    double *hyp_pose;
+    int32_t *n_rounds, *n_alive, *alive;
+    float *energy;
+    int32_t *n_inliers, *final_hyp;
+} reloc_trace;
+int reloc_debug_trace(const reloc_forest *f, reloc_trace *tr);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

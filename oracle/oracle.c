@@ -123,7 +123,7 @@ int oracle_forest_create(const oracle_params *p, oracle_forest **out)
     if (!p || !out) return ORACLE_E_ARG;
     if (p->n_trees < 1 || p->n_trees > 16 || p->depth < 1 || p->depth > 20 || p->reservoir_size < 1 ||
         p->max_modes < 1 || p->max_modes > 64 || p->offset_pxmm < 0 || p->batch_pixels < 1 ||
-        p->n_hypotheses < 1 || p->max_tries < 1)
+        p->n_hypotheses < 1 || p->max_tries < 1 || p->cov_reg_mm2 < 1)
         return ORACLE_E_ARG;
     oracle_forest *f = (oracle_forest *)calloc(1, sizeof(*f));
     if (!f) return ORACLE_E_NOMEM;

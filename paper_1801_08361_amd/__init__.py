@@ -1,0 +1,302 @@
+"""Python binding of libreloc (the gfx950 forest relocaliser behind include/reloc.h).
+
+Argument marshalling only: every step of adaptation and relocalisation runs
+in the HIP kernels of libreloc.so. Frames are torch tensors on the GPU
+(depth uint16 [H, W] in mm, rgb uint8 [H, W, 3]); torch supplies device
+memory and the current stream. There is no CPU fallback: if the library is
+not built, loading fails loudly.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Optional, Sequence, Tuple
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libreloc.so")
+
+OK = 0
+FAIL_NO_VALID_PIXELS = 1
+FAIL_NO_MODES = 2
+FAIL_NO_HYPOTHESIS = 3
+E_ARG = -1
+E_NOMEM = -2
+E_HIP = -3
+E_STATE = -4
+E_RANGE = -5
+
+
+class RelocError(RuntimeError):
+    def __init__(self, code: int, what: str):
+        super().__init__(f"{what}: {status_string(code)} ({code})")
+        self.code = code
+
+
+class reloc_params(C.Structure):
+    _fields_ = [
+        ("n_trees", C.c_int32), ("depth", C.c_int32), ("reservoir_size", C.c_int32), ("max_modes", C.c_int32),
+        ("seed", C.c_uint64),
+        ("depth_min_mm", C.c_int32), ("depth_max_mm", C.c_int32), ("offset_pxmm", C.c_int32),
+        ("f_ref_px16", C.c_int32), ("thr_depth_mm", C.c_int32), ("thr_rgb", C.c_int32),
+        ("dens_radius_mm", C.c_int32), ("link_radius_mm", C.c_int32), ("min_cluster", C.c_int32),
+        ("cov_reg_mm2", C.c_int32),
+        ("n_hypotheses", C.c_int32), ("batch_pixels", C.c_int32), ("max_tries", C.c_int32), ("refine", C.c_int32),
+        ("rgb_tol", C.c_int32),
+        ("rigid_ratio2", C.c_float), ("min_pair2_m2", C.c_float), ("min_area2_m4", C.c_float),
+        ("resid_m", C.c_float), ("inlier_m", C.c_float),
+    ]
+
+
+class reloc_intrinsics(C.Structure):
+    _fields_ = [("width", C.c_int32), ("height", C.c_int32), ("fx", C.c_float), ("fy", C.c_float),
+                ("cx", C.c_float), ("cy", C.c_float)]
+
+
+class reloc_trace(C.Structure):
+    _fields_ = [("cap_hyp", C.c_int32), ("cap_rounds", C.c_int32),
+                ("pool_size", C.c_void_p), ("hyp_try", C.c_void_p), ("hyp_pose", C.c_void_p),
+                ("n_rounds", C.c_void_p), ("n_alive", C.c_void_p), ("alive", C.c_void_p),
+                ("energy", C.c_void_p), ("n_inliers", C.c_void_p), ("final_hyp", C.c_void_p)]
+
+
+ENTRY_DTYPE = np.dtype([("x", "<i4"), ("y", "<i4"), ("z", "<i4"), ("r", "u1"), ("g", "u1"), ("b", "u1"),
+                        ("pad", "u1")])
+MODE_DTYPE = np.dtype([("mu", "<f4", 3), ("sinv", "<f4", 6), ("kappa", "<f4"), ("n", "<i4"),
+                       ("rgb", "u1", 3), ("pad", "u1")])
+
+_lib = None
+
+_SIGS = {
+    "reloc_params_default": [C.c_void_p],
+    "reloc_forest_create": [C.c_void_p, C.c_void_p, C.c_void_p],
+    "reloc_forest_destroy": [C.c_void_p],
+    "reloc_adapt_frame": [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p],
+    "reloc_update_modes": [C.c_void_p, C.c_void_p],
+    "reloc_relocalise": [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_uint64, C.c_int32, C.c_void_p,
+                         C.c_void_p, C.c_void_p, C.c_void_p],
+    "reloc_forest_drop_reservoirs": [C.c_void_p, C.c_void_p],
+    "reloc_forest_memory": [C.c_void_p, C.c_void_p],
+    "reloc_status_string": [C.c_int],
+    "reloc_debug_nodes": [C.c_void_p] * 5,
+    "reloc_debug_set_nodes": [C.c_void_p] * 5,
+    "reloc_debug_leaves": [C.c_void_p] * 6,
+    "reloc_debug_features8": [C.c_void_p] * 6,
+    "reloc_debug_reservoir": [C.c_void_p, C.c_int32, C.c_int32, C.c_int32, C.c_void_p, C.c_void_p],
+    "reloc_debug_modes": [C.c_void_p, C.c_int32, C.c_int32, C.c_int32, C.c_void_p, C.c_void_p],
+    "reloc_debug_modes_from_points": [C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p],
+    "reloc_debug_trace": [C.c_void_p, C.c_void_p],
+    "reloc_profile_enable": [C.c_int],
+    "reloc_profile_reset": [],
+    "reloc_profile_read": [C.c_char_p, C.c_void_p, C.c_void_p],
+    "reloc_profile_kernels": [C.c_char_p, C.c_int32],
+}
+
+
+def lib() -> C.CDLL:
+    """Loads libreloc.so (built by build.py); raises if it is missing."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"libreloc.so is not built ({LIB_PATH}); run paper_1801_08361_amd/build.py")
+        L = C.CDLL(LIB_PATH)
+        for name, args in _SIGS.items():
+            fn = getattr(L, name)
+            fn.argtypes = args
+            fn.restype = C.c_int
+        L.reloc_status_string.restype = C.c_char_p
+        _lib = L
+    return _lib
+
+
+def status_string(code: int) -> str:
+    return lib().reloc_status_string(int(code)).decode()
+
+
+def _check(code: int, what: str) -> int:
+    if code < 0:
+        raise RelocError(code, what)
+    return code
+
+
+def profile_enable(on: bool = True) -> None:
+    _check(lib().reloc_profile_enable(1 if on else 0), "reloc_profile_enable")
+
+
+def profile_reset() -> None:
+    _check(lib().reloc_profile_reset(), "reloc_profile_reset")
+
+
+def profile_read(kernel: str) -> Tuple[float, int]:
+    """(total milliseconds, launches) of one kernel since the last reset."""
+    ms = C.c_double(0)
+    n = C.c_int64(0)
+    _check(lib().reloc_profile_read(kernel.encode(), C.byref(ms), C.byref(n)), "reloc_profile_read")
+    return ms.value, n.value
+
+
+def profile_kernels() -> list:
+    buf = C.create_string_buffer(8192)
+    _check(lib().reloc_profile_kernels(buf, 8192), "reloc_profile_kernels")
+    return [k for k in buf.value.decode().split(",") if k]
+
+
+def params_default(**kw) -> reloc_params:
+    p = reloc_params()
+    _check(lib().reloc_params_default(C.byref(p)), "reloc_params_default")
+    for k, v in kw.items():
+        if not hasattr(p, k):
+            raise AttributeError(k)
+        setattr(p, k, v)
+    return p
+
+
+def _stream(stream) -> Optional[int]:
+    if stream is not None:
+        return int(stream)
+    import torch
+    return torch.cuda.current_stream().cuda_stream
+
+
+def _frame(depth, rgb, K) -> Tuple[int, int, reloc_intrinsics]:
+    import torch
+    if not (isinstance(depth, torch.Tensor) and isinstance(rgb, torch.Tensor)):
+        raise TypeError("depth and rgb must be torch tensors on the GPU")
+    if depth.dtype != torch.uint16 or rgb.dtype != torch.uint8 or not depth.is_cuda or not rgb.is_cuda:
+        raise TypeError("depth must be uint16 and rgb uint8, both on the GPU")
+    if not depth.is_contiguous() or not rgb.is_contiguous():
+        raise ValueError("frames must be contiguous")
+    H, W = depth.shape
+    if tuple(rgb.shape) != (H, W, 3):
+        raise ValueError("rgb must be [H, W, 3] matching depth [H, W]")
+    fx, fy, cx, cy = (float(k) for k in K)
+    return depth.data_ptr(), rgb.data_ptr(), reloc_intrinsics(W, H, fx, fy, cx, cy)
+
+
+def _pose(T) -> np.ndarray:
+    return np.ascontiguousarray(np.asarray(T, dtype=np.float64).reshape(16))
+
+
+class Forest:
+    """One sub-scene relocaliser held on the GPU (reloc_forest)."""
+
+    def __init__(self, params: Optional[reloc_params] = None, stream=None, **kw):
+        self.params = params if params is not None else params_default(**kw)
+        self._h = C.c_void_p()
+        _check(lib().reloc_forest_create(C.byref(self.params), _stream(stream), C.byref(self._h)),
+               "reloc_forest_create")
+        self.T = self.params.n_trees
+        self.L = 1 << self.params.depth
+        self.R = self.params.reservoir_size
+        self.M = self.params.max_modes
+
+    @property
+    def handle(self) -> C.c_void_p:
+        return self._h
+
+    def close(self) -> None:
+        if self._h is not None and self._h.value and _lib is not None:
+            _lib.reloc_forest_destroy(self._h)
+        self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- the method --------------------------------------------------------
+
+    def adapt_frame(self, depth, rgb, K, pose, stream=None) -> None:
+        d, c, k = _frame(depth, rgb, K)
+        T = _pose(pose)
+        _check(lib().reloc_adapt_frame(self._h, d, c, C.byref(k), T.ctypes.data, _stream(stream)),
+               "reloc_adapt_frame")
+
+    def update_modes(self, stream=None) -> None:
+        _check(lib().reloc_update_modes(self._h, _stream(stream)), "reloc_update_modes")
+
+    def relocalise(self, depth, rgb, K, seed: int, n_hyp: int = 0, weights=None, stream=None):
+        """Returns (status, pose 4x4 float64, score)."""
+        d, c, k = _frame(depth, rgb, K)
+        pose = np.zeros(16)
+        score = C.c_float(0)
+        w = None
+        if weights is not None:
+            w = weights.data_ptr()
+        rc = lib().reloc_relocalise(self._h, d, c, C.byref(k), C.c_uint64(seed), int(n_hyp), w,
+                                    pose.ctypes.data, C.byref(score), _stream(stream))
+        _check(rc, "reloc_relocalise")
+        return rc, pose.reshape(4, 4), score.value
+
+    def drop_reservoirs(self, stream=None) -> None:
+        _check(lib().reloc_forest_drop_reservoirs(self._h, _stream(stream)), "reloc_forest_drop_reservoirs")
+
+    def memory(self) -> int:
+        b = C.c_uint64(0)
+        _check(lib().reloc_forest_memory(self._h, C.byref(b)), "reloc_forest_memory")
+        return b.value
+
+    # -- parity and debug exports -------------------------------------------
+
+    def nodes(self):
+        n = self.T * (self.L - 1) + 8
+        arrs = [np.zeros(n, dtype=np.int32) for _ in range(4)]
+        _check(lib().reloc_debug_nodes(self._h, *[a.ctypes.data for a in arrs]), "reloc_debug_nodes")
+        return tuple(arrs)
+
+    def set_nodes(self, kind, dx, dy, thr) -> None:
+        arrs = [np.ascontiguousarray(a, dtype=np.int32) for a in (kind, dx, dy, thr)]
+        _check(lib().reloc_debug_set_nodes(self._h, *[a.ctypes.data for a in arrs]), "reloc_debug_set_nodes")
+
+    def leaves(self, depth, rgb, K, stream=None) -> np.ndarray:
+        d, c, k = _frame(depth, rgb, K)
+        out = np.zeros((self.T, k.width * k.height), dtype=np.int32)
+        _check(lib().reloc_debug_leaves(self._h, d, c, C.byref(k), out.ctypes.data, _stream(stream)),
+               "reloc_debug_leaves")
+        return out
+
+    def features8(self, depth, rgb, K, stream=None) -> np.ndarray:
+        d, c, k = _frame(depth, rgb, K)
+        out = np.zeros((k.width * k.height, 8), dtype=np.int32)
+        _check(lib().reloc_debug_features8(self._h, d, c, C.byref(k), out.ctypes.data, _stream(stream)),
+               "reloc_debug_features8")
+        return out
+
+    def reservoir(self, t: int, leaf0: int = 0, n: int = 1):
+        e = np.zeros((n, self.R), dtype=ENTRY_DTYPE)
+        cnt = np.zeros(n, dtype=np.uint32)
+        _check(lib().reloc_debug_reservoir(self._h, t, leaf0, n, e.ctypes.data, cnt.ctypes.data),
+               "reloc_debug_reservoir")
+        return e, cnt
+
+    def counters(self, t: int, leaf0: int = 0, n: Optional[int] = None) -> np.ndarray:
+        n = self.L - leaf0 if n is None else n
+        cnt = np.zeros(n, dtype=np.uint32)
+        _check(lib().reloc_debug_reservoir(self._h, t, leaf0, n, None, cnt.ctypes.data), "reloc_debug_reservoir")
+        return cnt
+
+    def modes(self, t: int, leaf0: int = 0, n: int = 1):
+        m = np.zeros((n, self.M), dtype=MODE_DTYPE)
+        nm = np.zeros(n, dtype=np.int32)
+        _check(lib().reloc_debug_modes(self._h, t, leaf0, n, m.ctypes.data, nm.ctypes.data), "reloc_debug_modes")
+        return m, nm
+
+    def modes_from_points(self, pts: np.ndarray):
+        pts = np.ascontiguousarray(pts, dtype=ENTRY_DTYPE)
+        m = np.zeros(self.M, dtype=MODE_DTYPE)
+        nm = C.c_int32(0)
+        _check(lib().reloc_debug_modes_from_points(self._h, pts.ctypes.data if len(pts) else None, len(pts),
+                                                   m.ctypes.data, C.byref(nm)), "reloc_debug_modes_from_points")
+        return m[: nm.value].copy()
+
+    def trace(self, n_hyp: int, rounds: int = 16):
+        b = dict(pool_size=np.zeros(1, np.int32), hyp_try=np.full(n_hyp, -2, np.int32),
+                 hyp_pose=np.zeros((n_hyp, 12)), n_rounds=np.zeros(1, np.int32),
+                 n_alive=np.zeros(rounds, np.int32), alive=np.full((rounds, n_hyp), -1, np.int32),
+                 energy=np.zeros((rounds, n_hyp), np.float32), final_hyp=np.full(1, -1, np.int32))
+        tr = reloc_trace(cap_hyp=n_hyp, cap_rounds=rounds, n_inliers=None,
+                         **{k: v.ctypes.data for k, v in b.items()})
+        _check(lib().reloc_debug_trace(self._h, C.byref(tr)), "reloc_debug_trace")
+        return b

@@ -1,0 +1,423 @@
+// Internal definitions shared by the HIP translation units of libreloc.
+//
+// Everything here is gfx950 device code or host glue for it. Floating-point
+// code is compiled with -ffp-contract=off: each operation is the IEEE
+// operation written, and fused multiply-adds appear only where the method
+// defines one (fmaf). Integer parts (features, traversal, reservoir ranks and
+// slots, cluster membership) are exact by construction.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "reloc.h"
+
+namespace rl {
+
+// ---------------------------------------------------------------------------
+// status helpers
+// ---------------------------------------------------------------------------
+
+#define RL_HIP(expr)                                      \
+    do {                                                  \
+        hipError_t e_ = (expr);                           \
+        if (e_ != hipSuccess) return RELOC_E_HIP;         \
+    } while (0)
+
+// optional per-kernel event timing (prof.hip)
+bool prof_on();
+void *prof_begin(const char *name, hipStream_t s);
+void prof_end(const char *name, void *tok, hipStream_t s);
+
+#define RL_LAUNCH(name, kern, grid, block, smem, stream, ...)                  \
+    do {                                                                      \
+        void *tok_ = prof_on() ? prof_begin(name, stream) : nullptr;          \
+        hipLaunchKernelGGL(kern, grid, block, smem, stream, __VA_ARGS__);     \
+        prof_end(name, tok_, stream);                                         \
+    } while (0)
+
+// ---------------------------------------------------------------------------
+// device data layouts
+// ---------------------------------------------------------------------------
+
+// one reservoir sample: world position in integer mm and the pixel colour
+struct Entry {
+    int32_t x, y, z;
+    uint32_t rgb;     // r | g << 8 | b << 16
+};
+static_assert(sizeof(Entry) == 16, "entry layout");
+
+// one leaf mode: mean (m), inverse covariance (m^-2: xx xy xz yy yz zz),
+// kappa = -log(pi) + 0.5 (3 log 2 pi + log det Sigma), cluster size, colour
+struct Mode {
+    float mu[3];
+    float sinv[6];
+    float kappa;
+    int32_t n;
+    uint32_t rgb;
+};
+static_assert(sizeof(Mode) == 48, "mode layout");
+
+// one pose hypothesis: FP64 pose and its FP32 rounding used for scoring
+struct Hyp {
+    double R[9], t[3];
+    float R32[9], t32[3];
+};
+
+// correspondence sums: n, sum c (3), sum w (3), sum c w^T (9, row a col b),
+// sum c c^T (xx xy xz yy yz zz)
+constexpr int NSUM = 22;
+
+// result of one attempt, copied to the host
+struct Result {
+    double pose[16];
+    float score;
+    int32_t status;
+    int32_t n_rounds;
+    int32_t final_hyp;
+    int32_t pool_size;
+    int32_t n_valid;
+    int32_t pad[2];
+};
+
+constexpr uint64_t TAG_FOREST = 1, TAG_RESERVOIR = 2, TAG_HYP = 3, TAG_PIX = 4;
+
+constexpr int GROUP = 8;        // energy partial sums run over 8 consecutive draws
+constexpr int CHUNK = 4096;     // pixels per reservoir-rank chunk
+constexpr int MAX_HYP = 4096;
+constexpr int MAX_B = 2048;
+constexpr int MAX_R = 1024;
+constexpr int MAX_ROUNDS = 13;  // ceil(log2(MAX_HYP)) + 1
+
+// ---------------------------------------------------------------------------
+// Philox4x64-10 (Salmon et al., SC 2011) and the integer range map
+// ---------------------------------------------------------------------------
+
+struct U4 { uint64_t x[4]; };
+
+__device__ __forceinline__ U4 philox(uint64_t c0, uint64_t c1, uint64_t c2, uint64_t c3, uint64_t k0,
+                                     uint64_t k1)
+{
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        if (r > 0) {
+            k0 += 0x9E3779B97F4A7C15ull;
+            k1 += 0xBB67AE8584CAA73Bull;
+        }
+        const uint64_t m0 = 0xD2E7470EE14C6C93ull, m1 = 0xCA5A826395121157ull;
+        uint64_t lo0 = m0 * c0, hi0 = __umul64hi(m0, c0);
+        uint64_t lo1 = m1 * c2, hi1 = __umul64hi(m1, c2);
+        uint64_t n0 = hi1 ^ c1 ^ k0;
+        uint64_t n2 = hi0 ^ c3 ^ k1;
+        c0 = n0; c1 = lo1; c2 = n2; c3 = lo0;
+    }
+    U4 o;
+    o.x[0] = c0; o.x[1] = c1; o.x[2] = c2; o.x[3] = c3;
+    return o;
+}
+
+// floor(u * n / 2^64)
+__device__ __forceinline__ uint64_t uniform_int(uint64_t u, uint64_t n) { return __umul64hi(u, n); }
+
+// ---------------------------------------------------------------------------
+// packed split node (8 bytes): kind 2 bits | dx 21 | dy 21 | thr 20 (signed)
+// ---------------------------------------------------------------------------
+
+constexpr int32_t NODE_OFF_MAX = (1 << 20) - 1;
+constexpr int32_t NODE_THR_MAX = (1 << 19) - 1;
+
+__host__ __device__ __forceinline__ uint64_t pack_node(int32_t kind, int32_t dx, int32_t dy, int32_t thr)
+{
+    return (uint64_t)(uint32_t)(kind & 3) | ((uint64_t)((uint32_t)dx & 0x1FFFFFu) << 2) |
+           ((uint64_t)((uint32_t)dy & 0x1FFFFFu) << 23) | ((uint64_t)((uint32_t)thr & 0xFFFFFu) << 44);
+}
+
+__host__ __device__ __forceinline__ void unpack_node(uint64_t w, int32_t &kind, int32_t &dx, int32_t &dy,
+                                                     int32_t &thr)
+{
+    kind = (int32_t)(w & 3u);
+    dx = (int32_t)((int64_t)(w << 41) >> 43);
+    dy = (int32_t)((int64_t)(w << 20) >> 43);
+    thr = (int32_t)((int64_t)w >> 44);
+}
+
+// ---------------------------------------------------------------------------
+// frames
+// ---------------------------------------------------------------------------
+
+struct Frame {
+    const uint16_t *__restrict__ depth;
+    const uint8_t *__restrict__ rgb;
+    int32_t W, H;
+    float fx, fy, cx, cy;
+    int32_t Fx, Fy;       // focal lengths in 1/16 px, rounded half up
+    int32_t dmin, dmax, Fref;
+};
+
+__device__ __forceinline__ bool valid_depth(const Frame &fr, uint32_t d)
+{
+    return (int32_t)d >= fr.dmin && (int32_t)d <= fr.dmax;
+}
+
+// camera-frame point, one IEEE float operation at a time in this order
+__device__ __forceinline__ void cam_point(const Frame &fr, int u, int v, uint32_t d, float c[3])
+{
+    float z = (float)d * 0.001f;
+    c[0] = ((float)u - fr.cx) * z / fr.fx;
+    c[1] = ((float)v - fr.cy) * z / fr.fy;
+    c[2] = z;
+}
+
+// Response of a packed node at pixel (u, v) with valid depth d (mm). The probe
+// offset is trunc(delta * F / (d * F_ref)); all products fit in 32 bits (the
+// host checks |delta| * F < 2^31). Depth probes outside the image or on an
+// invalid depth read 65535; colour probes clamp to the border.
+__device__ __forceinline__ int32_t node_response(const Frame &fr, uint64_t w, int u, int v, int32_t d,
+                                                 int32_t &thr)
+{
+    int32_t kind, dx, dy;
+    unpack_node(w, kind, dx, dy, thr);
+    int32_t den = d * fr.Fref;
+    int32_t qx = u + (dx * fr.Fx) / den;
+    int32_t qy = v + (dy * fr.Fy) / den;
+    if (kind == 0) {
+        int32_t dq = 65535;
+        if (qx >= 0 && qx < fr.W && qy >= 0 && qy < fr.H) {
+            uint32_t z = fr.depth[qy * fr.W + qx];
+            if (valid_depth(fr, z)) dq = (int32_t)z;
+        }
+        return dq - d;
+    }
+    int c = kind - 1;
+    qx = qx < 0 ? 0 : (qx > fr.W - 1 ? fr.W - 1 : qx);
+    qy = qy < 0 ? 0 : (qy > fr.H - 1 ? fr.H - 1 : qy);
+    return (int32_t)fr.rgb[(qy * fr.W + qx) * 3 + c] - (int32_t)fr.rgb[(v * fr.W + u) * 3 + c];
+}
+
+// implicit heap: children of node i are 2i+1 (left) and 2i+2 (right); go
+// right iff response >= threshold; leaf = i - (L - 1)
+__device__ __forceinline__ int32_t traverse(const uint64_t *__restrict__ tree, int32_t L, const Frame &fr, int u,
+                                            int v, int32_t d)
+{
+    int32_t i = 0;
+    while (i < L - 1) {
+        int32_t thr;
+        int32_t r = node_response(fr, tree[i], u, v, d, thr);
+        i = 2 * i + 1 + (r >= thr ? 1 : 0);
+    }
+    return i - (L - 1);
+}
+
+// ---------------------------------------------------------------------------
+// FP64 rigid alignment from correspondence sums (Horn's unit-quaternion
+// method, 1987: the rotation maximising tr(R H^T) is given by the eigenvector
+// of the largest eigenvalue of a symmetric 4x4 matrix built from H)
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ void sums_add_point(double s[NSUM], const float c[3], const float w[3])
+{
+    double cd[3] = {c[0], c[1], c[2]}, wd[3] = {w[0], w[1], w[2]};
+    s[0] = s[0] + 1.0;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        s[1 + a] = s[1 + a] + cd[a];
+        s[4 + a] = s[4 + a] + wd[a];
+    }
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int b = 0; b < 3; ++b) s[7 + a * 3 + b] = s[7 + a * 3 + b] + cd[a] * wd[b];
+    s[16] = s[16] + cd[0] * cd[0];
+    s[17] = s[17] + cd[0] * cd[1];
+    s[18] = s[18] + cd[0] * cd[2];
+    s[19] = s[19] + cd[1] * cd[1];
+    s[20] = s[20] + cd[1] * cd[2];
+    s[21] = s[21] + cd[2] * cd[2];
+}
+
+// largest-eigenvalue eigenvector of a symmetric 4x4 matrix by cyclic Jacobi
+__device__ __forceinline__ void jacobi4_top(double A[16], double q[4])
+{
+    double V[16];
+#pragma unroll
+    for (int i = 0; i < 16; ++i) V[i] = (i % 5 == 0) ? 1.0 : 0.0;
+    for (int sweep = 0; sweep < 16; ++sweep) {
+        double off = 0.0, diag = 0.0;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            diag += A[i * 4 + i] * A[i * 4 + i];
+#pragma unroll
+            for (int j = i + 1; j < 4; ++j) off += A[i * 4 + j] * A[i * 4 + j];
+        }
+        if (!(off > 1e-30 * diag)) break;
+#pragma unroll
+        for (int p = 0; p < 3; ++p)
+#pragma unroll
+            for (int r = p + 1; r < 4; ++r) {
+                double apq = A[p * 4 + r];
+                if (apq == 0.0) continue;
+                double tau = (A[r * 4 + r] - A[p * 4 + p]) / (2.0 * apq);
+                double t = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
+                double c = 1.0 / sqrt(1.0 + t * t), s = t * c;
+                // A <- J^T A J with J the rotation in the (p, r) plane
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    double akp = A[k * 4 + p], akr = A[k * 4 + r];
+                    A[k * 4 + p] = c * akp - s * akr;
+                    A[k * 4 + r] = s * akp + c * akr;
+                }
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    double apk = A[p * 4 + k], ark = A[r * 4 + k];
+                    A[p * 4 + k] = c * apk - s * ark;
+                    A[r * 4 + k] = s * apk + c * ark;
+                }
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    double vkp = V[k * 4 + p], vkr = V[k * 4 + r];
+                    V[k * 4 + p] = c * vkp - s * vkr;
+                    V[k * 4 + r] = s * vkp + c * vkr;
+                }
+            }
+    }
+    int best = 0;
+#pragma unroll
+    for (int i = 1; i < 4; ++i)
+        if (A[i * 4 + i] > A[best * 4 + best]) best = i;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) q[k] = V[k * 4 + best];
+}
+
+// Pose from sums. Succeeds when n >= 3 and the camera points are spread in two
+// directions: with S their centred scatter, the sum of S's principal 2x2
+// minors must reach 1e-4 * n * trace(S).
+__device__ __forceinline__ bool pose_from_sums(const double s[NSUM], double R[9], double t[3])
+{
+    double n = s[0];
+    if (n < 3.0) return false;
+    const double *c = s + 1, *w = s + 4, *cw = s + 7, *cc = s + 16;
+    double H[9], S[6];
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int b = 0; b < 3; ++b) H[a * 3 + b] = cw[a * 3 + b] - (c[a] * w[b]) / n;
+    S[0] = cc[0] - (c[0] * c[0]) / n;
+    S[1] = cc[1] - (c[0] * c[1]) / n;
+    S[2] = cc[2] - (c[0] * c[2]) / n;
+    S[3] = cc[3] - (c[1] * c[1]) / n;
+    S[4] = cc[4] - (c[1] * c[2]) / n;
+    S[5] = cc[5] - (c[2] * c[2]) / n;
+    double I2 = ((S[0] * S[3] - S[1] * S[1]) + (S[0] * S[5] - S[2] * S[2])) + (S[3] * S[5] - S[4] * S[4]);
+    double tr = (S[0] + S[3]) + S[5];
+    if (!(I2 >= (1e-4 * n) * tr)) return false;
+    double Sxx = H[0], Sxy = H[1], Sxz = H[2], Syx = H[3], Syy = H[4], Syz = H[5], Szx = H[6], Szy = H[7],
+           Szz = H[8];
+    double N[16] = {Sxx + Syy + Szz, Syz - Szy,       Szx - Sxz,        Sxy - Syx,
+                    Syz - Szy,       Sxx - Syy - Szz, Sxy + Syx,        Szx + Sxz,
+                    Szx - Sxz,       Sxy + Syx,       -Sxx + Syy - Szz, Syz + Szy,
+                    Sxy - Syx,       Szx + Sxz,       Syz + Szy,        -Sxx - Syy + Szz};
+    double q[4];
+    jacobi4_top(N, q);
+    double qn = sqrt(q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3]);
+    double q0 = q[0] / qn, qx = q[1] / qn, qy = q[2] / qn, qz = q[3] / qn;
+    R[0] = q0 * q0 + qx * qx - qy * qy - qz * qz;
+    R[1] = 2.0 * (qx * qy - q0 * qz);
+    R[2] = 2.0 * (qx * qz + q0 * qy);
+    R[3] = 2.0 * (qy * qx + q0 * qz);
+    R[4] = q0 * q0 - qx * qx + qy * qy - qz * qz;
+    R[5] = 2.0 * (qy * qz - q0 * qx);
+    R[6] = 2.0 * (qz * qx - q0 * qy);
+    R[7] = 2.0 * (qz * qy + q0 * qx);
+    R[8] = q0 * q0 - qx * qx - qy * qy + qz * qz;
+    double cm[3], wm[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        cm[k] = c[k] / n;
+        wm[k] = w[k] / n;
+    }
+#pragma unroll
+    for (int k = 0; k < 3; ++k)
+        t[k] = wm[k] - ((R[k * 3 + 0] * cm[0] + R[k * 3 + 1] * cm[1]) + R[k * 3 + 2] * cm[2]);
+    return true;
+}
+
+// energy term of one mode at y (FP32, fused exactly as written):
+// d = y - mu; a = Sigma^-1 d; q = d . a; term = 0.5 q + kappa
+__device__ __forceinline__ float mode_term(const Mode &m, float y0, float y1, float y2, float &d0, float &d1,
+                                           float &d2)
+{
+    d0 = y0 - m.mu[0];
+    d1 = y1 - m.mu[1];
+    d2 = y2 - m.mu[2];
+    const float *s = m.sinv;
+    float a0 = fmaf(s[2], d2, fmaf(s[1], d1, s[0] * d0));
+    float a1 = fmaf(s[4], d2, fmaf(s[3], d1, s[1] * d0));
+    float a2 = fmaf(s[5], d2, fmaf(s[4], d1, s[2] * d0));
+    float q = fmaf(d2, a2, fmaf(d1, a1, d0 * a0));
+    return fmaf(0.5f, q, m.kappa);
+}
+
+// float -> uint32 key that sorts like the float (no NaN, no -0 here)
+__device__ __forceinline__ uint32_t float_key(float f)
+{
+    uint32_t b = __float_as_uint(f);
+    return (b & 0x80000000u) ? ~b : (b | 0x80000000u);
+}
+
+// ---------------------------------------------------------------------------
+// the forest handle
+// ---------------------------------------------------------------------------
+
+struct Forest {
+    reloc_params p;
+    int T, D, L, R, M;
+    int device;
+    // forest state
+    uint64_t *nodes = nullptr;     // [T][L-1] then 8 extra
+    uint32_t *counter = nullptr;   // [T][L]
+    uint32_t *base = nullptr;      // [T][L]
+    Entry *res = nullptr;          // [T][L][R]
+    uint32_t *stamp = nullptr;     // [T][L][R]
+    Mode *modes = nullptr;         // [T][L][M]
+    int32_t *nmodes = nullptr;     // [T][L]
+    uint32_t *dirty = nullptr;     // [T][L]
+    uint32_t *dirty_list = nullptr;
+    uint32_t *dirty_count = nullptr;
+    unsigned long long *total_samples = nullptr;
+    bool maybe_dirty = false;
+    bool dropped = false;
+    // per-frame scratch (grows with the frame size)
+    int64_t cap_P = 0;
+    int32_t *leaves = nullptr;     // [T][P]
+    uint16_t *rank = nullptr;      // [T][P]
+    int32_t *slot = nullptr;       // [T][P]
+    uint32_t *kval = nullptr;      // [T][P]
+    uint16_t *chunk_cnt = nullptr; // [T][C][L]
+    uint32_t *chunk_pref = nullptr;// [T][C][L]
+    int32_t *pool = nullptr;       // [P]
+    int32_t *blockcnt = nullptr;   // [P / 1024 + 1]
+    int32_t *pool_size = nullptr;  // [1]
+    // relocalisation scratch (fixed maxima)
+    Hyp *hyp = nullptr;            // [MAX_HYP]
+    double *hyp_init = nullptr;    // [MAX_HYP][12]
+    int32_t *hyp_try = nullptr;    // [MAX_HYP]
+    float *energy = nullptr;       // [MAX_HYP]
+    double *sums = nullptr;        // [MAX_HYP][NSUM]
+    int32_t *alive = nullptr;      // [MAX_HYP]
+    int32_t *n_alive = nullptr;    // [2]: current, initial
+    int32_t *rounds_done = nullptr;// [1]
+    float4 *draws = nullptr;       // [MAX_B] camera point, pixel index bits
+    float *partial = nullptr;      // [MAX_B / GROUP][MAX_HYP]
+    uint16_t *inl = nullptr;       // [MAX_HYP][MAX_B]
+    int32_t *tr_alive = nullptr;   // [MAX_ROUNDS][MAX_HYP]
+    float *tr_energy = nullptr;    // [MAX_ROUNDS][MAX_HYP]
+    int32_t *tr_n_alive = nullptr; // [MAX_ROUNDS]
+    Result *result = nullptr;      // device
+    Result *result_host = nullptr; // pinned
+    int32_t last_N = 0;
+    uint64_t bytes = 0;
+};
+
+}  // namespace rl
+
+struct reloc_forest : public rl::Forest {};
