@@ -221,7 +221,8 @@ def test_relocalise_failures(dev, adapted_pair):
     d0, c0 = sc.render_query(2)
     d, c = to_dev(d0, c0, dev)
     banner("failure: zero depth")
-    assert g.relocalise(d * 0, c, sc.K, seed=1)[0] == rl.FAIL_NO_VALID_PIXELS
+    import torch
+    assert g.relocalise(torch.zeros_like(d), c, sc.K, seed=1)[0] == rl.FAIL_NO_VALID_PIXELS
     banner("failure: empty forest")
     e = rl.Forest(rl.params_default())
     assert e.relocalise(d, c, sc.K, seed=1)[0] == rl.FAIL_NO_MODES
