@@ -131,6 +131,68 @@ int reloc_relocalise(reloc_forest *f, const uint16_t *depth_dev, const uint8_t *
                      const uint32_t *pixel_weights_dev, double pose_c2w_out[16], float *score_out,
                      void *stream);
 
+/* Everything one attempt reports. */
+typedef struct {
+    double pose_c2w[16];     /* camera-to-world; identity on failure */
+    float score;             /* inlier fraction of the returned hypothesis over all draws scored */
+    int32_t status;          /* RELOC_OK or RELOC_FAIL_* */
+    int32_t n_rounds;        /* cull rounds run */
+    int32_t final_hyp;       /* index of the returned hypothesis, -1 on failure */
+    int32_t pool_size;       /* valid pixels of the frame */
+    int32_t n_valid;         /* hypotheses that passed their checks */
+    uint64_t mode_evals;     /* (hypothesis, draw, mode) energy terms evaluated */
+    uint64_t pair_evals;     /* (hypothesis, draw) pairs scored */
+} reloc_result;
+
+/* reloc_relocalise with the full result. Synchronous on `stream`. */
+int reloc_relocalise_ex(reloc_forest *f, const uint16_t *depth_dev, const uint8_t *rgb_dev,
+                        const reloc_intrinsics *K, uint64_t attempt_seed, int32_t n_hypotheses,
+                        const uint32_t *pixel_weights_dev, reloc_result *result_out, void *stream);
+
+/* ---- batched relocalisation ----
+ * Many attempts, against one or several forests, with frames of different
+ * sizes and different hypothesis counts, run as one launch of a captured
+ * HIP graph whose kernels walk ragged per-attempt work lists. Each attempt's
+ * result is bit-identical to reloc_relocalise_ex on the same arguments (the
+ * same kernels run both; the plain call is a batch of one). Not in the
+ * paper, which schedules one attempt at a time (Sec. 3.3.1, Sec. 4.3.1). */
+typedef struct {
+    reloc_forest *forest;              /* target forest */
+    const uint16_t *depth_dev;         /* device depth [H][W] mm */
+    const uint8_t *rgb_dev;            /* device rgb [H][W][3] */
+    reloc_intrinsics K;
+    uint64_t seed;                     /* attempt seed (hypothesis and pixel draws) */
+    int32_t n_hypotheses;              /* <= 0: the forest's parameter */
+    const uint32_t *pixel_weights_dev; /* device [H*W] pick weights, or NULL for uniform picks */
+} reloc_attempt;
+
+typedef struct reloc_batch reloc_batch;
+
+/* A batch handle caches, per batch shape (attempt count and each attempt's
+ * frame size, hypothesis count and forest dimensions), a scratch arena and an
+ * instantiated graph. Not thread-safe. */
+int reloc_batch_create(reloc_batch **out);
+int reloc_batch_destroy(reloc_batch *b);
+
+/* Runs n >= 1 attempts and writes n results to results_host. The first call
+ * with a new shape captures its graph and, with tuning on, times a few
+ * schedules (draws per scoring unit, persistent grid size, XCD-contiguous
+ * unit order) and keeps the fastest; results do not depend on the schedule.
+ * Synchronous on `stream`. RELOC_E_ARG for a bad attempt (its index is not
+ * reported; check attempts individually with reloc_relocalise_ex). */
+int reloc_relocalise_batch(reloc_batch *b, const reloc_attempt *attempts, int32_t n,
+                           reloc_result *results_host, void *stream);
+
+/* 1 (default): tune schedules on the first call of each shape; 0: use the
+ * fixed default schedule. */
+int reloc_batch_set_tuning(reloc_batch *b, int32_t on);
+
+/* Text description of the schedule chosen for the most recent shape. */
+int reloc_batch_schedule(const reloc_batch *b, char *desc, int32_t cap);
+
+/* Device bytes held by the batch handle (arenas of cached shapes). */
+int reloc_batch_memory(const reloc_batch *b, uint64_t *bytes_out);
+
 /* Builds every pending mode, then frees the reservoirs and slot stamps (the
  * paper deletes a relocaliser's training data once it is trained,
  * Sec. 4.3.2). Relocalisation results are unchanged; further adaptation

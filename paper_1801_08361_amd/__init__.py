@@ -61,6 +61,24 @@ class reloc_trace(C.Structure):
                 ("energy", C.c_void_p), ("n_inliers", C.c_void_p), ("final_hyp", C.c_void_p)]
 
 
+class reloc_result(C.Structure):
+    _fields_ = [("pose_c2w", C.c_double * 16), ("score", C.c_float), ("status", C.c_int32),
+                ("n_rounds", C.c_int32), ("final_hyp", C.c_int32), ("pool_size", C.c_int32),
+                ("n_valid", C.c_int32), ("mode_evals", C.c_uint64), ("pair_evals", C.c_uint64)]
+
+    def as_dict(self) -> dict:
+        return dict(pose=np.array(self.pose_c2w[:], dtype=np.float64).reshape(4, 4), score=self.score,
+                    status=self.status, n_rounds=self.n_rounds, final_hyp=self.final_hyp,
+                    pool_size=self.pool_size, n_valid=self.n_valid, mode_evals=self.mode_evals,
+                    pair_evals=self.pair_evals)
+
+
+class reloc_attempt(C.Structure):
+    _fields_ = [("forest", C.c_void_p), ("depth_dev", C.c_void_p), ("rgb_dev", C.c_void_p),
+                ("K", reloc_intrinsics), ("seed", C.c_uint64), ("n_hypotheses", C.c_int32),
+                ("pixel_weights_dev", C.c_void_p)]
+
+
 ENTRY_DTYPE = np.dtype([("x", "<i4"), ("y", "<i4"), ("z", "<i4"), ("r", "u1"), ("g", "u1"), ("b", "u1"),
                         ("pad", "u1")])
 MODE_DTYPE = np.dtype([("mu", "<f4", 3), ("sinv", "<f4", 6), ("kappa", "<f4"), ("n", "<i4"),
@@ -91,6 +109,14 @@ _SIGS = {
     "reloc_profile_reset": [],
     "reloc_profile_read": [C.c_char_p, C.c_void_p, C.c_void_p],
     "reloc_profile_kernels": [C.c_char_p, C.c_int32],
+    "reloc_relocalise_ex": [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_uint64, C.c_int32, C.c_void_p,
+                            C.c_void_p, C.c_void_p],
+    "reloc_batch_create": [C.c_void_p],
+    "reloc_batch_destroy": [C.c_void_p],
+    "reloc_relocalise_batch": [C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p],
+    "reloc_batch_set_tuning": [C.c_void_p, C.c_int32],
+    "reloc_batch_schedule": [C.c_void_p, C.c_char_p, C.c_int32],
+    "reloc_batch_memory": [C.c_void_p, C.c_void_p],
 }
 
 
@@ -230,6 +256,16 @@ class Forest:
         _check(rc, "reloc_relocalise")
         return rc, pose.reshape(4, 4), score.value
 
+    def relocalise_ex(self, depth, rgb, K, seed: int, n_hyp: int = 0, weights=None, stream=None) -> dict:
+        """Full result of one plain attempt (reloc_relocalise_ex) as a dict."""
+        d, c, k = _frame(depth, rgb, K)
+        res = reloc_result()
+        w = weights.data_ptr() if weights is not None else None
+        rc = lib().reloc_relocalise_ex(self._h, d, c, C.byref(k), C.c_uint64(seed), int(n_hyp), w, C.byref(res),
+                                       _stream(stream))
+        _check(rc, "reloc_relocalise_ex")
+        return res.as_dict()
+
     def drop_reservoirs(self, stream=None) -> None:
         _check(lib().reloc_forest_drop_reservoirs(self._h, _stream(stream)), "reloc_forest_drop_reservoirs")
 
@@ -300,3 +336,51 @@ class Forest:
                          **{k: v.ctypes.data for k, v in b.items()})
         _check(lib().reloc_debug_trace(self._h, C.byref(tr)), "reloc_debug_trace")
         return b
+
+
+class Batch:
+    """A reloc_batch handle: many attempts (any forests, frame sizes and
+    hypothesis counts) per call, run as one captured graph launch."""
+
+    def __init__(self, tune: bool = True):
+        self._h = C.c_void_p()
+        _check(lib().reloc_batch_create(C.byref(self._h)), "reloc_batch_create")
+        self.set_tuning(tune)
+
+    def close(self) -> None:
+        if self._h is not None and self._h.value and _lib is not None:
+            _lib.reloc_batch_destroy(self._h)
+        self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_tuning(self, on: bool) -> None:
+        _check(lib().reloc_batch_set_tuning(self._h, 1 if on else 0), "reloc_batch_set_tuning")
+
+    def schedule(self) -> str:
+        buf = C.create_string_buffer(512)
+        _check(lib().reloc_batch_schedule(self._h, buf, 512), "reloc_batch_schedule")
+        return buf.value.decode()
+
+    def memory(self) -> int:
+        b = C.c_uint64(0)
+        _check(lib().reloc_batch_memory(self._h, C.byref(b)), "reloc_batch_memory")
+        return b.value
+
+    def run(self, attempts: Sequence[dict], stream=None) -> list:
+        """attempts: dicts with forest, depth, rgb, K, seed, and optionally
+        n_hyp and weights. Returns one result dict per attempt."""
+        n = len(attempts)
+        arr = (reloc_attempt * n)()
+        for i, a in enumerate(attempts):
+            d, c, k = _frame(a["depth"], a["rgb"], a["K"])
+            w = a.get("weights")
+            arr[i] = reloc_attempt(a["forest"].handle, d, c, k, int(a["seed"]), int(a.get("n_hyp", 0)),
+                                   w.data_ptr() if w is not None else None)
+        res = (reloc_result * n)()
+        _check(lib().reloc_relocalise_batch(self._h, arr, n, res, _stream(stream)), "reloc_relocalise_batch")
+        return [r.as_dict() for r in res]

@@ -68,17 +68,8 @@ struct Hyp {
 // sum c c^T (xx xy xz yy yz zz)
 constexpr int NSUM = 22;
 
-// result of one attempt, copied to the host
-struct Result {
-    double pose[16];
-    float score;
-    int32_t status;
-    int32_t n_rounds;
-    int32_t final_hyp;
-    int32_t pool_size;
-    int32_t n_valid;
-    int32_t pad[2];
-};
+// result of one attempt: the public reloc_result
+using Result = reloc_result;
 
 constexpr uint64_t TAG_FOREST = 1, TAG_RESERVOIR = 2, TAG_HYP = 3, TAG_PIX = 4;
 
@@ -87,6 +78,7 @@ constexpr int CHUNK = 4096;     // pixels per reservoir-rank chunk
 constexpr int MAX_HYP = 4096;
 constexpr int MAX_B = 2048;
 constexpr int MAX_R = 1024;
+constexpr int MAX_TM = 512;     // modes over all trees of one pixel (T * M)
 constexpr int MAX_ROUNDS = 13;  // ceil(log2(MAX_HYP)) + 1
 
 // ---------------------------------------------------------------------------
@@ -379,6 +371,7 @@ struct Forest {
     Entry *res = nullptr;          // [T][L][R]
     uint32_t *stamp = nullptr;     // [T][L][R]
     Mode *modes = nullptr;         // [T][L][M]
+    uint32_t *mode_rgb = nullptr;  // [T][L][M] colour of each mode (compact copy for hypothesis picks)
     int32_t *nmodes = nullptr;     // [T][L]
     uint32_t *dirty = nullptr;     // [T][L]
     uint32_t *dirty_list = nullptr;
@@ -386,7 +379,7 @@ struct Forest {
     unsigned long long *total_samples = nullptr;
     bool maybe_dirty = false;
     bool dropped = false;
-    // per-frame scratch (grows with the frame size)
+    // per-frame adaptation scratch (grows with the frame size)
     int64_t cap_P = 0;
     int32_t *leaves = nullptr;     // [T][P]
     uint16_t *rank = nullptr;      // [T][P]
@@ -394,30 +387,94 @@ struct Forest {
     uint32_t *kval = nullptr;      // [T][P]
     uint16_t *chunk_cnt = nullptr; // [T][C][L]
     uint32_t *chunk_pref = nullptr;// [T][C][L]
-    int32_t *pool = nullptr;       // [P]
-    int32_t *blockcnt = nullptr;   // [P / 1024 + 1]
-    int32_t *pool_size = nullptr;  // [1]
-    // relocalisation scratch (fixed maxima)
-    Hyp *hyp = nullptr;            // [MAX_HYP]
-    double *hyp_init = nullptr;    // [MAX_HYP][12]
-    int32_t *hyp_try = nullptr;    // [MAX_HYP]
-    float *energy = nullptr;       // [MAX_HYP]
-    double *sums = nullptr;        // [MAX_HYP][NSUM]
-    int32_t *alive = nullptr;      // [MAX_HYP]
-    int32_t *n_alive = nullptr;    // [2]: current, initial
-    int32_t *rounds_done = nullptr;// [1]
-    float4 *draws = nullptr;       // [MAX_B] camera point, pixel index bits
-    float *partial = nullptr;      // [MAX_B / GROUP][MAX_HYP]
-    uint16_t *inl = nullptr;       // [MAX_HYP][MAX_B]
-    int32_t *tr_alive = nullptr;   // [MAX_ROUNDS][MAX_HYP]
-    float *tr_energy = nullptr;    // [MAX_ROUNDS][MAX_HYP]
-    int32_t *tr_n_alive = nullptr; // [MAX_ROUNDS]
-    Result *result = nullptr;      // device
-    Result *result_host = nullptr; // pinned
-    int32_t last_N = 0;
+    // the plain relocalisation path: a batch of one attempt
+    reloc_batch *plain = nullptr;
     uint64_t bytes = 0;
 };
+
+// ---------------------------------------------------------------------------
+// one relocalisation attempt as the device sees it (ragged batches)
+// ---------------------------------------------------------------------------
+
+struct Attempt {
+    Frame fr;
+    // the target forest (read-only here)
+    const uint64_t *nodes;
+    const int32_t *nmodes;
+    const Mode *modes;
+    const uint32_t *mode_rgb;
+    const unsigned long long *total_samples;
+    const uint32_t *weights;       // [P] integer pick weights or null
+    int32_t T, L, M, P, N, B, max_tries, rgb_tol, refine, rounds;
+    float ratio2, min_pair2, min_area2, inl2;
+    double resid2;
+    uint64_t seed;
+    // scratch owned by the batch
+    int32_t *leaves;               // [T][P]
+    int32_t *pool;                 // [P]
+    int32_t *blockcnt;             // [nb]
+    unsigned long long *blockw;    // [nb] weight sums per pixel block
+    unsigned long long *cdf;       // [P] inclusive weight prefix over the pool
+    int32_t *misc;                 // [0] pool size [1] live [2] valid [3] rounds done
+    Hyp *hyp;                      // [N]
+    double *hyp_init;              // [N][12]
+    int32_t *hyp_try;              // [N]
+    float *energy;                 // [N]
+    double *sums;                  // [N][NSUM] running inlier sums
+    double *rsums;                 // [N][NSUM] this round's inlier sums
+    int32_t *alive;                // [N]
+    int32_t *pos;                  // [N] position of a hypothesis in the live list when scored
+    float4 *draws;                 // [B] camera point, pixel index bits
+    float *e;                      // [B][N] per-draw energy of each live position
+    uint16_t *inl;                 // [B][N] best-mode id of an inlier, 0xFFFF otherwise
+    unsigned long long *stats;     // [0] mode evaluations [1] pair evaluations [2] round mode count
+    int32_t *tr_alive;             // [MAX_ROUNDS][N]
+    float *tr_energy;              // [MAX_ROUNDS][N]
+    int32_t *tr_n_alive;           // [MAX_ROUNDS]
+    Result *result;
+};
+
+// work-unit layout of one stage over a batch: the units of attempt a are
+// [off[a], off[a+1]); off has n + 1 entries
+struct Stage {
+    const int32_t *off;
+    int32_t n;
+    int32_t total;
+    int32_t xcd;     // 1: units of each XCD's workgroups are contiguous
+};
+
+// Units walked by this workgroup in a persistent loop
+//   for (u = start; u < end; u += step)
+// Workgroups are dispatched round robin over the 8 XCDs; with xcd set (the
+// grid is then a multiple of 8), XCD x walks the x-th contiguous eighth of
+// the units, so that the units of one attempt share an L2.
+__device__ __forceinline__ void unit_range(const Stage &S, int &start, int &end, int &step)
+{
+    if (S.xcd) {
+        int x = (int)(blockIdx.x % 8u), chunk = (S.total + 7) / 8;
+        start = x * chunk + (int)(blockIdx.x / 8u);
+        end = min((x + 1) * chunk, S.total);
+        step = (int)(gridDim.x / 8u);
+    } else {
+        start = (int)blockIdx.x;
+        end = S.total;
+        step = (int)gridDim.x;
+    }
+}
+
+__device__ __forceinline__ int attempt_of(const Stage &S, int u)
+{
+    int lo = 0, hi = S.n - 1;
+    while (lo < hi) {
+        int mid = (lo + hi + 1) >> 1;
+        if (S.off[mid] <= u) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
 
 }  // namespace rl
 
 struct reloc_forest : public rl::Forest {};
+
+// releases a forest's plain-path batch (relocalise.hip)
+void rl_free_plain(rl::Forest *f);

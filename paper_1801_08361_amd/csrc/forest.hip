@@ -349,7 +349,8 @@ static inline size_t mode_smem(int cap) { return (size_t)7 * 4 * (cap > 0 ? cap 
 // forest (roots by pointer jumping); clusters of at least `minc` points are
 // ranked by (size descending, root ascending) and the first M become modes.
 __device__ void leaf_modes(const Entry *__restrict__ pts, int n, int n_total, int cap, const ModeParams mp,
-                           Mode *__restrict__ out, int32_t *__restrict__ n_out, char *smem)
+                           Mode *__restrict__ out, uint32_t *__restrict__ rgb_out, int32_t *__restrict__ n_out,
+                           char *smem)
 {
     int32_t *X = (int32_t *)smem;
     int32_t *Y = X + cap;
@@ -494,6 +495,7 @@ __device__ void leaf_modes(const Entry *__restrict__ pts, int n, int n_total, in
         md.rgb = (uint32_t)(a[9] / (unsigned long long)nmm) | ((uint32_t)(a[10] / (unsigned long long)nmm) << 8) |
                  ((uint32_t)(a[11] / (unsigned long long)nmm) << 16);
         out[tid] = md;
+        if (rgb_out) rgb_out[tid] = md.rgb;
     }
     if (tid == 0) *n_out = nm;
     __syncthreads();
@@ -504,7 +506,8 @@ __global__ void __launch_bounds__(MODE_THREADS) k_modes(const uint32_t *__restri
                                                         const uint32_t *__restrict__ count,
                                                         const uint32_t *__restrict__ counter,
                                                         const Entry *__restrict__ res, ModeParams mp,
-                                                        Mode *__restrict__ modes, int32_t *__restrict__ nmodes)
+                                                        Mode *__restrict__ modes, uint32_t *__restrict__ mode_rgb,
+                                                        int32_t *__restrict__ nmodes)
 {
     extern __shared__ char smem[];
     uint32_t n_list = *count;
@@ -512,7 +515,8 @@ __global__ void __launch_bounds__(MODE_THREADS) k_modes(const uint32_t *__restri
         uint32_t li = list[it];
         uint32_t k = counter[li];
         int n = k < (uint32_t)mp.R ? (int)k : mp.R;
-        leaf_modes(res + (int64_t)li * mp.R, n, n, mp.R, mp, modes + (int64_t)li * mp.M, nmodes + li, smem);
+        leaf_modes(res + (int64_t)li * mp.R, n, n, mp.R, mp, modes + (int64_t)li * mp.M, mode_rgb + (int64_t)li * mp.M,
+                   nmodes + li, smem);
     }
 }
 
@@ -529,7 +533,7 @@ __global__ void __launch_bounds__(MODE_THREADS) k_modes_points(const Entry *__re
                                                                Mode *__restrict__ out, int32_t *__restrict__ n_out)
 {
     extern __shared__ char smem[];
-    leaf_modes(pts, n, n, n, mp, out, n_out, smem);
+    leaf_modes(pts, n, n, n, mp, out, nullptr, n_out, smem);
 }
 
 static ModeParams mode_params(const Forest *f)
@@ -552,17 +556,14 @@ static int ensure_frame_scratch(Forest *f, int64_t P, hipStream_t s)
 {
     if (P <= f->cap_P) return RELOC_OK;
     int64_t C_old = (f->cap_P + CHUNK - 1) / CHUNK;
-    int64_t nb_old = f->cap_P / 1024 + 1;
     dfree(f, &f->leaves, (size_t)f->T * f->cap_P);
     dfree(f, &f->rank, (size_t)f->T * f->cap_P);
     dfree(f, &f->slot, (size_t)f->T * f->cap_P);
     dfree(f, &f->kval, (size_t)f->T * f->cap_P);
     dfree(f, &f->chunk_cnt, (size_t)f->T * C_old * f->L);
     dfree(f, &f->chunk_pref, (size_t)f->T * C_old * f->L);
-    dfree(f, &f->pool, (size_t)f->cap_P);
-    dfree(f, &f->blockcnt, (size_t)nb_old);
+    f->cap_P = 0;
     int64_t C = (P + CHUNK - 1) / CHUNK;
-    int64_t nb = P / 1024 + 1;
     int rc = RELOC_OK;
     rc |= dalloc(f, &f->leaves, (size_t)f->T * P, s);
     rc |= dalloc(f, &f->rank, (size_t)f->T * P, s);
@@ -570,8 +571,6 @@ static int ensure_frame_scratch(Forest *f, int64_t P, hipStream_t s)
     rc |= dalloc(f, &f->kval, (size_t)f->T * P, s);
     rc |= dalloc(f, &f->chunk_cnt, (size_t)f->T * C * f->L, s);
     rc |= dalloc(f, &f->chunk_pref, (size_t)f->T * C * f->L, s);
-    rc |= dalloc(f, &f->pool, (size_t)P, s);
-    rc |= dalloc(f, &f->blockcnt, (size_t)nb, s);
     if (rc) return RELOC_E_NOMEM;
     RL_HIP(hipMemsetAsync(f->chunk_cnt, 0, (size_t)f->T * C * f->L * sizeof(uint16_t), s));
     f->cap_P = P;
@@ -585,7 +584,7 @@ int update_modes(Forest *f, hipStream_t s)
     ModeParams mp = mode_params(f);
     int grid = std::min(f->T * f->L, 4096);
     RL_LAUNCH("k_modes", k_modes, dim3(grid), dim3(MODE_THREADS), mode_smem(f->R), s, f->dirty_list, f->dirty_count,
-                       f->counter, f->res, mp, f->modes, f->nmodes);
+                       f->counter, f->res, mp, f->modes, f->mode_rgb, f->nmodes);
     RL_LAUNCH("k_modes_done", k_modes_done, dim3(1), dim3(1024), 0, s, f->dirty_list, f->dirty_count, f->dirty);
     RL_HIP(hipGetLastError());
     f->maybe_dirty = false;
@@ -660,28 +659,7 @@ static void forest_free(Forest *f)
     dfree(f, &f->kval, (size_t)f->T * f->cap_P);
     dfree(f, &f->chunk_cnt, (size_t)f->T * C * f->L);
     dfree(f, &f->chunk_pref, (size_t)f->T * C * f->L);
-    dfree(f, &f->pool, (size_t)f->cap_P);
-    dfree(f, &f->blockcnt, (size_t)(f->cap_P / 1024 + 1));
-    dfree(f, &f->pool_size, 1);
-    dfree(f, &f->hyp, MAX_HYP);
-    dfree(f, &f->hyp_init, (size_t)MAX_HYP * 12);
-    dfree(f, &f->hyp_try, MAX_HYP);
-    dfree(f, &f->energy, MAX_HYP);
-    dfree(f, &f->sums, (size_t)MAX_HYP * NSUM);
-    dfree(f, &f->alive, MAX_HYP);
-    dfree(f, &f->n_alive, 2);
-    dfree(f, &f->rounds_done, 1);
-    dfree(f, &f->draws, MAX_B);
-    dfree(f, &f->partial, (size_t)(MAX_B / GROUP) * MAX_HYP);
-    dfree(f, &f->inl, (size_t)MAX_HYP * MAX_B);
-    dfree(f, &f->tr_alive, (size_t)MAX_ROUNDS * MAX_HYP);
-    dfree(f, &f->tr_energy, (size_t)MAX_ROUNDS * MAX_HYP);
-    dfree(f, &f->tr_n_alive, MAX_ROUNDS);
-    dfree(f, &f->result, 1);
-    if (f->result_host) {
-        (void)hipHostFree(f->result_host);
-        f->result_host = nullptr;
-    }
+    dfree(f, &f->mode_rgb, TL * f->M);
 }
 
 extern "C" int reloc_forest_create(const reloc_params *p, void *stream, reloc_forest **out)
@@ -709,23 +687,8 @@ extern "C" int reloc_forest_create(const reloc_params *p, void *stream, reloc_fo
     rc |= dalloc(f, &f->dirty_list, TL, s);
     rc |= dalloc(f, &f->dirty_count, 1, s);
     rc |= dalloc(f, &f->total_samples, 1, s);
-    rc |= dalloc(f, &f->pool_size, 1, s);
-    rc |= dalloc(f, &f->hyp, MAX_HYP, s);
-    rc |= dalloc(f, &f->hyp_init, (size_t)MAX_HYP * 12, s);
-    rc |= dalloc(f, &f->hyp_try, MAX_HYP, s);
-    rc |= dalloc(f, &f->energy, MAX_HYP, s);
-    rc |= dalloc(f, &f->sums, (size_t)MAX_HYP * NSUM, s);
-    rc |= dalloc(f, &f->alive, MAX_HYP, s);
-    rc |= dalloc(f, &f->n_alive, 2, s);
-    rc |= dalloc(f, &f->rounds_done, 1, s);
-    rc |= dalloc(f, &f->draws, MAX_B, s);
-    rc |= dalloc(f, &f->partial, (size_t)(MAX_B / GROUP) * MAX_HYP, s);
-    rc |= dalloc(f, &f->inl, (size_t)MAX_HYP * MAX_B, s);
-    rc |= dalloc(f, &f->tr_alive, (size_t)MAX_ROUNDS * MAX_HYP, s);
-    rc |= dalloc(f, &f->tr_energy, (size_t)MAX_ROUNDS * MAX_HYP, s);
-    rc |= dalloc(f, &f->tr_n_alive, MAX_ROUNDS, s);
-    rc |= dalloc(f, &f->result, 1, s);
-    if (rc || hipHostMalloc((void **)&f->result_host, sizeof(Result), hipHostMallocDefault) != hipSuccess) {
+    rc |= dalloc(f, &f->mode_rgb, TL * f->M, s);
+    if (rc) {
         forest_free(f);
         delete f;
         return RELOC_E_NOMEM;
@@ -757,6 +720,7 @@ extern "C" int reloc_forest_destroy(reloc_forest *f)
 {
     if (!f) return RELOC_E_ARG;
     (void)hipDeviceSynchronize();
+    rl_free_plain(f);
     forest_free(f);
     delete f;
     return RELOC_OK;

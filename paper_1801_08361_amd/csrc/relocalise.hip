@@ -1,117 +1,222 @@
-// Relocalisation of one RGB-D frame on the GPU: query pool, three-point
-// Kabsch hypotheses, preemptive scoring with halving culls and inlier
-// refinement.
+// Relocalisation on the GPU: query pool, three-point Kabsch hypotheses,
+// preemptive scoring with halving culls and inlier refinement, for a ragged
+// batch of attempts (the plain call is a batch of one).
 //
-// Layout of the work:
+// Every stage is a persistent kernel over the stage's work units; attempt a
+// owns units [off[a], off[a+1]) (frame blocks, hypotheses, draw blocks,
+// (hypothesis block, draw chunk) pairs, survivors). A whole batch is one
+// captured HIP graph. Layout of the work inside an attempt:
 //  - hypotheses: one wavefront per hypothesis, one lane per try; the first
 //    passing try (lowest lane, then lowest chunk of 64 tries) defines it;
-//  - scoring: one wavefront holds 64 live hypotheses (one per lane) and one
-//    group of 8 consecutive draws; the draw's modes are wave-uniform, so they
-//    come through scalar loads and every lane evaluates its own pose against
-//    them; partial energies are written per (group, hypothesis) and summed in
-//    group order by the cull;
-//  - cull: one workgroup sorts the live hypotheses by (energy, index) in LDS
-//    and keeps the first half (rounded up);
-//  - refinement: one wavefront per survivor, lanes over the round's draws,
-//    FP64 inlier sums combined by an xor butterfly, then Horn's method.
+//  - scoring: one wavefront holds 64 live hypotheses (one per lane) and a
+//    chunk of draws; each draw's modes are staged once in LDS and read back
+//    as wave-uniform broadcasts while every lane evaluates its own pose;
+//    per-draw energies go to memory and the cull sums them in the defined
+//    order (groups of 8 draws);
+//  - cull: one workgroup per attempt sorts the live hypotheses by
+//    (energy, index) in LDS and keeps the first half, rounded up;
+//  - refinement: one wavefront per survivor sums its inliers of the round
+//    (lanes over draws, xor butterfly), then one lane per survivor updates
+//    the running sums and re-aligns (Horn's method, FP64).
 #include <math.h>
+#include <stdio.h>
 #include <string.h>
 
 #include <algorithm>
+#include <new>
+#include <string>
+#include <vector>
 
 #include "common.h"
 
 namespace rl {
 
 int update_modes(Forest *f, hipStream_t s);
-int traverse_frame(Forest *f, const Frame &fr, hipStream_t s);
 int frame_from(const Forest *f, const uint16_t *depth, const uint8_t *rgb, const reloc_intrinsics *K, Frame &fr);
 
-// ---------------------------------------------------------------------------
-// query pool: valid pixels in raster order
-// ---------------------------------------------------------------------------
-
+constexpr int PIX_BLOCK = 256;
 constexpr int POOL_BLOCK = 1024;
+constexpr int DRAW_BLOCK = 256;
+constexpr int CULL_THREADS = 1024;
 
 __device__ __forceinline__ uint64_t lanemask_lt() { return (1ull << __lane_id()) - 1ull; }
 
-__global__ void __launch_bounds__(POOL_BLOCK) k_pool_count(Frame fr, int32_t *__restrict__ blockcnt)
+#define FOR_UNITS(S, u)                 \
+    int u##0_, u##1_, u##s_;            \
+    unit_range(S, u##0_, u##1_, u##s_); \
+    for (int u = u##0_; u < u##1_; u += u##s_)
+
+// round r of attempt A runs when no later round has started and at least one
+// (r = 0) or more than one (r > 0) hypothesis is live
+__device__ __forceinline__ bool round_active(const Attempt &A, int r)
 {
-    int P = fr.W * fr.H;
-    int p = blockIdx.x * POOL_BLOCK + threadIdx.x;
-    bool ok = p < P && valid_depth(fr, fr.depth[p]);
-    int n = __syncthreads_count(ok);
-    if (threadIdx.x == 0) blockcnt[blockIdx.x] = n;
+    int done = A.misc[3], na = A.misc[1];
+    return done == r && (r == 0 ? na >= 1 : na > 1);
 }
 
-// exclusive scan of the block counts (one workgroup), pool size
-__global__ void __launch_bounds__(1024) k_pool_scan(int32_t *__restrict__ blockcnt, int nb,
-                                                    int32_t *__restrict__ pool_size)
+// ---------------------------------------------------------------------------
+// features and traversal of every pixel
+// ---------------------------------------------------------------------------
+
+__global__ void __launch_bounds__(PIX_BLOCK) k_b_leaves(const Attempt *__restrict__ att, Stage S)
+{
+    FOR_UNITS(S, u) {
+        const int a = attempt_of(S, u);
+        const Attempt &A = att[a];
+        const int p = (u - S.off[a]) * PIX_BLOCK + (int)threadIdx.x;
+        if (p >= A.P) continue;
+        const Frame fr = A.fr;
+        const int uu = p % fr.W, vv = p / fr.W;
+        const uint32_t d = fr.depth[p];
+        const bool ok = valid_depth(fr, d);
+        for (int t = 0; t < A.T; ++t) {
+            int32_t leaf = ok ? traverse(A.nodes + (int64_t)t * (A.L - 1), A.L, fr, uu, vv, (int32_t)d) : -1;
+            A.leaves[(int64_t)t * A.P + p] = leaf;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// query pool (valid pixels in raster order) and the pick-weight prefix
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ unsigned long long wave_incl_scan_u64(unsigned long long x)
+{
+    const int lane = __lane_id();
+    for (int o = 1; o < 64; o <<= 1) {
+        unsigned long long y = __shfl_up(x, o, 64);
+        if (lane >= o) x += y;
+    }
+    return x;
+}
+
+__global__ void __launch_bounds__(POOL_BLOCK) k_b_pool_count(const Attempt *__restrict__ att, Stage S)
+{
+    __shared__ unsigned long long wsum[POOL_BLOCK / 64];
+    FOR_UNITS(S, u) {
+        const int a = attempt_of(S, u);
+        const Attempt &A = att[a];
+        const int b = u - S.off[a];
+        const int p = b * POOL_BLOCK + (int)threadIdx.x;
+        const bool ok = p < A.P && valid_depth(A.fr, A.fr.depth[p]);
+        const int n = __syncthreads_count(ok);
+        if (A.weights) {
+            unsigned long long w = ok ? (unsigned long long)A.weights[p] : 0ull;
+            w = wave_incl_scan_u64(w);
+            if (__lane_id() == 63) wsum[threadIdx.x / 64] = w;
+            __syncthreads();
+            if (threadIdx.x == 0) {
+                unsigned long long tot = 0;
+                for (int k = 0; k < POOL_BLOCK / 64; ++k) tot += wsum[k];
+                A.blockw[b] = tot;
+            }
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) A.blockcnt[b] = n;
+    }
+}
+
+// per attempt: exclusive scans of the block counts and weights, pool size,
+// and the attempt's counters reset
+__global__ void __launch_bounds__(1024) k_b_pool_scan(const Attempt *__restrict__ att, Stage S)
 {
     __shared__ int32_t wsum[16];
+    __shared__ unsigned long long wsumw[16];
     __shared__ int32_t carry;
-    if (threadIdx.x == 0) carry = 0;
-    __syncthreads();
+    __shared__ unsigned long long carryw;
     const int lane = __lane_id(), wave = threadIdx.x / 64;
-    for (int base = 0; base < nb; base += 1024) {
-        int i = base + threadIdx.x;
-        int v = i < nb ? blockcnt[i] : 0;
-        int x = v;
-        for (int o = 1; o < 64; o <<= 1) {
-            int y = __shfl_up(x, o, 64);
-            if (lane >= o) x += y;
+    FOR_UNITS(S, u) {
+        const Attempt &A = att[u];
+        const int nb = (A.P + POOL_BLOCK - 1) / POOL_BLOCK;
+        if (threadIdx.x == 0) {
+            carry = 0;
+            carryw = 0ull;
         }
-        if (lane == 63) wsum[wave] = x;
         __syncthreads();
-        int woff = 0;
-        for (int w = 0; w < wave; ++w) woff += wsum[w];
-        int excl = carry + woff + x - v;
-        __syncthreads();
-        if (i < nb) blockcnt[i] = excl;
-        if (threadIdx.x == 1023) carry = excl + v;
+        for (int base = 0; base < nb; base += 1024) {
+            const int i = base + (int)threadIdx.x;
+            const int v = i < nb ? A.blockcnt[i] : 0;
+            const unsigned long long vw = (i < nb && A.weights) ? A.blockw[i] : 0ull;
+            int x = v;
+            for (int o = 1; o < 64; o <<= 1) {
+                int y = __shfl_up(x, o, 64);
+                if (lane >= o) x += y;
+            }
+            unsigned long long xw = wave_incl_scan_u64(vw);
+            if (lane == 63) {
+                wsum[wave] = x;
+                wsumw[wave] = xw;
+            }
+            __syncthreads();
+            int woff = 0;
+            unsigned long long woffw = 0ull;
+            for (int w = 0; w < wave; ++w) {
+                woff += wsum[w];
+                woffw += wsumw[w];
+            }
+            const int excl = carry + woff + x - v;
+            const unsigned long long exclw = carryw + woffw + xw - vw;
+            __syncthreads();
+            if (i < nb) {
+                A.blockcnt[i] = excl;
+                if (A.weights) A.blockw[i] = exclw;
+            }
+            if (threadIdx.x == 1023) {
+                carry = excl + v;
+                carryw = exclw + vw;
+            }
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) {
+            A.misc[0] = carry;
+            A.misc[1] = 0;
+            A.misc[2] = 0;
+            A.misc[3] = 0;
+            A.stats[0] = 0ull;
+            A.stats[1] = 0ull;
+            A.stats[2] = 0ull;
+        }
         __syncthreads();
     }
-    if (threadIdx.x == 0) *pool_size = carry;
 }
 
-__global__ void __launch_bounds__(POOL_BLOCK) k_pool_write(Frame fr, const int32_t *__restrict__ blockoff,
-                                                           int32_t *__restrict__ pool)
+__global__ void __launch_bounds__(POOL_BLOCK) k_b_pool_write(const Attempt *__restrict__ att, Stage S)
 {
     __shared__ int32_t wcnt[POOL_BLOCK / 64];
-    int P = fr.W * fr.H;
-    int p = blockIdx.x * POOL_BLOCK + threadIdx.x;
-    bool ok = p < P && valid_depth(fr, fr.depth[p]);
-    uint64_t m = __ballot(ok);
-    const int wave = threadIdx.x / 64;
-    if (__lane_id() == 0) wcnt[wave] = __popcll(m);
-    __syncthreads();
-    int off = blockoff[blockIdx.x];
-    for (int w = 0; w < wave; ++w) off += wcnt[w];
-    if (ok) pool[off + __popcll(m & lanemask_lt())] = p;
+    __shared__ unsigned long long wsw[POOL_BLOCK / 64];
+    FOR_UNITS(S, u) {
+        const int a = attempt_of(S, u);
+        const Attempt &A = att[a];
+        const int b = u - S.off[a];
+        const int p = b * POOL_BLOCK + (int)threadIdx.x;
+        const bool ok = p < A.P && valid_depth(A.fr, A.fr.depth[p]);
+        const uint64_t m = __ballot(ok);
+        const int wave = threadIdx.x / 64;
+        const unsigned long long w = (ok && A.weights) ? (unsigned long long)A.weights[p] : 0ull;
+        const unsigned long long wi = wave_incl_scan_u64(w);
+        if (__lane_id() == 63) {
+            wcnt[wave] = __popcll(m);
+            wsw[wave] = wi;
+        }
+        __syncthreads();
+        int off = A.blockcnt[b];
+        unsigned long long offw = A.weights ? A.blockw[b] : 0ull;
+        for (int k = 0; k < wave; ++k) {
+            off += wcnt[k];
+            offw += wsw[k];
+        }
+        if (ok) {
+            const int idx = off + __popcll(m & lanemask_lt());
+            A.pool[idx] = p;
+            if (A.weights) A.cdf[idx] = offw + wi;
+        }
+        __syncthreads();
+    }
 }
 
 // ---------------------------------------------------------------------------
 // hypotheses
 // ---------------------------------------------------------------------------
-
-struct HypArgs {
-    Frame fr;
-    const int32_t *__restrict__ pool;
-    const int32_t *__restrict__ pool_size;
-    const int32_t *__restrict__ leaves;
-    const int32_t *__restrict__ nmodes;
-    const Mode *__restrict__ modes;
-    int T, L, M, P;
-    int max_tries, rgb_tol;
-    float ratio2, min_pair2, min_area2;
-    double resid2;
-    uint64_t seed;
-    Hyp *__restrict__ hyp;
-    double *__restrict__ hyp_init;
-    int32_t *__restrict__ hyp_try;
-    float *__restrict__ energy;
-    double *__restrict__ sums;
-};
 
 __device__ __forceinline__ float sq3(const float a[3], const float b[3])
 {
@@ -125,60 +230,76 @@ __device__ __forceinline__ bool rgb_close(uint32_t a, uint32_t r, uint32_t g, ui
     return abs(dr) <= tol && abs(dg) <= tol && abs(db) <= tol;
 }
 
-// one try: draws, mode picks, FP32 checks, FP64 alignment and residuals
-__device__ bool try_hypothesis(const HypArgs &A, int np, uint64_t h, uint64_t tau, double R[9], double t[3])
+// pool index for draw u: uniform, or the first pool entry whose inclusive
+// weight prefix exceeds floor(u * total / 2^64)
+__device__ __forceinline__ int pick_pool(const Attempt &A, int np, uint64_t u)
 {
-    U4 a = philox(h, tau, 0, 0, A.seed, TAG_HYP);
-    U4 b = philox(h, tau, 1, 0, A.seed, TAG_HYP);
+    if (!A.weights) return (int)uniform_int(u, (uint64_t)np);
+    const unsigned long long total = A.cdf[np - 1];
+    if (total == 0ull) return (int)uniform_int(u, (uint64_t)np);
+    const unsigned long long r = uniform_int(u, total);
+    int lo = 0, hi = np - 1;
+    while (lo < hi) {
+        int mid = lo + ((hi - lo) >> 1);
+        if (A.cdf[mid] > r) hi = mid; else lo = mid + 1;
+    }
+    return lo;
+}
+
+// one try: draws, colour-consistent mode picks, FP32 checks, FP64 alignment
+// and residuals
+__device__ bool try_hypothesis(const Attempt &A, int np, uint64_t h, uint64_t tau, double R[9], double t[3])
+{
+    const U4 a = philox(h, tau, 0, 0, A.seed, TAG_HYP);
+    const U4 b = philox(h, tau, 1, 0, A.seed, TAG_HYP);
     int pi[3];
     float c[3][3], w[3][3];
     for (int j = 0; j < 3; ++j) {
-        pi[j] = (int)uniform_int(a.x[j], (uint64_t)np);
-        int p = A.pool[pi[j]];
-        uint32_t pr = A.fr.rgb[p * 3], pg = A.fr.rgb[p * 3 + 1], pb = A.fr.rgb[p * 3 + 2];
+        pi[j] = pick_pool(A, np, a.x[j]);
+        const int p = A.pool[pi[j]];
+        const uint32_t pr = A.fr.rgb[p * 3], pg = A.fr.rgb[p * 3 + 1], pb = A.fr.rgb[p * 3 + 2];
+        int li[16], nm[16];
+        for (int tt = 0; tt < A.T; ++tt) li[tt] = tt * A.L + A.leaves[(int64_t)tt * A.P + p];
+        for (int tt = 0; tt < A.T; ++tt) nm[tt] = A.nmodes[li[tt]];
         int cnt = 0;
         for (int tt = 0; tt < A.T; ++tt) {
-            int li = tt * A.L + A.leaves[(int64_t)tt * A.P + p];
-            int nm = A.nmodes[li];
-            const Mode *mb = A.modes + (int64_t)li * A.M;
-            for (int m = 0; m < nm; ++m) cnt += rgb_close(mb[m].rgb, pr, pg, pb, A.rgb_tol) ? 1 : 0;
+            const uint32_t *cr = A.mode_rgb + (int64_t)li[tt] * A.M;
+            for (int m = 0; m < nm[tt]; ++m) cnt += rgb_close(cr[m], pr, pg, pb, A.rgb_tol) ? 1 : 0;
         }
         if (cnt == 0) return false;
         int sel = (int)uniform_int(b.x[j], (uint64_t)cnt);
-        const Mode *pick = nullptr;
-        for (int tt = 0; tt < A.T && !pick; ++tt) {
-            int li = tt * A.L + A.leaves[(int64_t)tt * A.P + p];
-            int nm = A.nmodes[li];
-            const Mode *mb = A.modes + (int64_t)li * A.M;
-            for (int m = 0; m < nm; ++m)
-                if (rgb_close(mb[m].rgb, pr, pg, pb, A.rgb_tol)) {
+        int64_t pick = -1;
+        for (int tt = 0; tt < A.T && pick < 0; ++tt) {
+            const uint32_t *cr = A.mode_rgb + (int64_t)li[tt] * A.M;
+            for (int m = 0; m < nm[tt]; ++m)
+                if (rgb_close(cr[m], pr, pg, pb, A.rgb_tol)) {
                     if (sel == 0) {
-                        pick = &mb[m];
+                        pick = (int64_t)li[tt] * A.M + m;
                         break;
                     }
                     sel--;
                 }
         }
-        int u = p % A.fr.W, v = p / A.fr.W;
-        cam_point(A.fr, u, v, A.fr.depth[p], c[j]);
-        w[j][0] = pick->mu[0];
-        w[j][1] = pick->mu[1];
-        w[j][2] = pick->mu[2];
+        cam_point(A.fr, p % A.fr.W, p / A.fr.W, A.fr.depth[p], c[j]);
+        const Mode &md = A.modes[pick];
+        w[j][0] = md.mu[0];
+        w[j][1] = md.mu[1];
+        w[j][2] = md.mu[2];
     }
     if (pi[0] == pi[1] || pi[0] == pi[2] || pi[1] == pi[2]) return false;
     const int EA[3] = {0, 0, 1}, EB[3] = {1, 2, 2};
     for (int e = 0; e < 3; ++e) {
-        float dc = sq3(c[EA[e]], c[EB[e]]);
-        float dw = sq3(w[EA[e]], w[EB[e]]);
+        const float dc = sq3(c[EA[e]], c[EB[e]]);
+        const float dw = sq3(w[EA[e]], w[EB[e]]);
         if (!(dc >= A.min_pair2)) return false;
         if (!(dw <= A.ratio2 * dc)) return false;
         if (!(dc <= A.ratio2 * dw)) return false;
     }
-    float e1[3] = {c[1][0] - c[0][0], c[1][1] - c[0][1], c[1][2] - c[0][2]};
-    float e2[3] = {c[2][0] - c[0][0], c[2][1] - c[0][1], c[2][2] - c[0][2]};
-    float cx = e1[1] * e2[2] - e1[2] * e2[1];
-    float cy = e1[2] * e2[0] - e1[0] * e2[2];
-    float cz = e1[0] * e2[1] - e1[1] * e2[0];
+    const float e1[3] = {c[1][0] - c[0][0], c[1][1] - c[0][1], c[1][2] - c[0][2]};
+    const float e2[3] = {c[2][0] - c[0][0], c[2][1] - c[0][1], c[2][2] - c[0][2]};
+    const float cx = e1[1] * e2[2] - e1[2] * e2[1];
+    const float cy = e1[2] * e2[0] - e1[0] * e2[2];
+    const float cz = e1[0] * e2[1] - e1[1] * e2[0];
     if (!((cx * cx + cy * cy) + cz * cz >= A.min_area2)) return false;
     double s[NSUM];
     for (int k = 0; k < NSUM; ++k) s[k] = 0.0;
@@ -193,73 +314,79 @@ __device__ bool try_hypothesis(const HypArgs &A, int np, uint64_t h, uint64_t ta
     return true;
 }
 
-__global__ void __launch_bounds__(64) k_hypgen(HypArgs A)
+__global__ void __launch_bounds__(64) k_b_hypgen(const Attempt *__restrict__ att, Stage S)
 {
-    const int h = blockIdx.x, lane = __lane_id();
-    const int np = *A.pool_size;
-    int found = -1;
-    double R[9], t[3];
-    for (int chunk = 0; chunk * 64 < A.max_tries && found < 0; ++chunk) {
-        int tau = chunk * 64 + lane;
-        bool ok = tau < A.max_tries && np > 0 && try_hypothesis(A, np, (uint64_t)h, (uint64_t)tau, R, t);
-        uint64_t m = __ballot(ok);
-        if (m) {
-            int first = __ffsll((unsigned long long)m) - 1;
-            found = chunk * 64 + first;
-            if (lane == first) {
-                Hyp hy;
-                for (int k = 0; k < 9; ++k) {
-                    hy.R[k] = R[k];
-                    hy.R32[k] = (float)R[k];
+    FOR_UNITS(S, u) {
+        const int a = attempt_of(S, u);
+        const Attempt &A = att[a];
+        const int h = u - S.off[a];
+        const int lane = __lane_id();
+        const int np = A.misc[0];
+        int found = -1;
+        double R[9], t[3];
+        for (int chunk = 0; chunk * 64 < A.max_tries && found < 0; ++chunk) {
+            const int tau = chunk * 64 + lane;
+            const bool ok = tau < A.max_tries && np > 0 && try_hypothesis(A, np, (uint64_t)h, (uint64_t)tau, R, t);
+            const uint64_t m = __ballot(ok);
+            if (m) {
+                const int first = __ffsll((unsigned long long)m) - 1;
+                found = chunk * 64 + first;
+                if (lane == first) {
+                    Hyp hy;
+                    for (int k = 0; k < 9; ++k) {
+                        hy.R[k] = R[k];
+                        hy.R32[k] = (float)R[k];
+                    }
+                    for (int k = 0; k < 3; ++k) {
+                        hy.t[k] = t[k];
+                        hy.t32[k] = (float)t[k];
+                    }
+                    A.hyp[h] = hy;
+                    for (int k = 0; k < 9; ++k) A.hyp_init[(int64_t)h * 12 + k] = R[k];
+                    for (int k = 0; k < 3; ++k) A.hyp_init[(int64_t)h * 12 + 9 + k] = t[k];
                 }
-                for (int k = 0; k < 3; ++k) {
-                    hy.t[k] = t[k];
-                    hy.t32[k] = (float)t[k];
-                }
-                A.hyp[h] = hy;
-                for (int k = 0; k < 9; ++k) A.hyp_init[(int64_t)h * 12 + k] = R[k];
-                for (int k = 0; k < 3; ++k) A.hyp_init[(int64_t)h * 12 + 9 + k] = t[k];
             }
         }
+        if (lane == 0) {
+            A.hyp_try[h] = found;
+            A.energy[h] = 0.0f;
+        }
+        if (lane < NSUM) A.sums[(int64_t)h * NSUM + lane] = 0.0;
     }
-    if (lane == 0) {
-        A.hyp_try[h] = found;
-        A.energy[h] = 0.0f;
-    }
-    if (lane < NSUM) A.sums[(int64_t)h * NSUM + lane] = 0.0;
 }
 
 // live list = valid hypotheses in index order
-__global__ void __launch_bounds__(1024) k_alive_init(const int32_t *__restrict__ hyp_try, int N,
-                                                     int32_t *__restrict__ alive, int32_t *__restrict__ n_alive,
-                                                     int32_t *__restrict__ rounds_done)
+__global__ void __launch_bounds__(1024) k_b_alive_init(const Attempt *__restrict__ att, Stage S)
 {
     __shared__ int32_t wcnt[16];
     __shared__ int32_t carry;
-    if (threadIdx.x == 0) carry = 0;
-    __syncthreads();
     const int wave = threadIdx.x / 64;
-    for (int base = 0; base < N; base += 1024) {
-        int h = base + threadIdx.x;
-        bool ok = h < N && hyp_try[h] >= 0;
-        uint64_t m = __ballot(ok);
-        if (__lane_id() == 0) wcnt[wave] = __popcll(m);
+    FOR_UNITS(S, u) {
+        const Attempt &A = att[u];
+        if (threadIdx.x == 0) carry = 0;
         __syncthreads();
-        int off = carry;
-        for (int w = 0; w < wave; ++w) off += wcnt[w];
-        if (ok) alive[off + __popcll(m & lanemask_lt())] = h;
-        __syncthreads();
+        for (int base = 0; base < A.N; base += 1024) {
+            const int h = base + (int)threadIdx.x;
+            const bool ok = h < A.N && A.hyp_try[h] >= 0;
+            const uint64_t m = __ballot(ok);
+            if (__lane_id() == 0) wcnt[wave] = __popcll(m);
+            __syncthreads();
+            int off = carry;
+            for (int w = 0; w < wave; ++w) off += wcnt[w];
+            if (ok) A.alive[off + __popcll(m & lanemask_lt())] = h;
+            __syncthreads();
+            if (threadIdx.x == 0) {
+                int tot = 0;
+                for (int w = 0; w < 16; ++w) tot += wcnt[w];
+                carry += tot;
+            }
+            __syncthreads();
+        }
         if (threadIdx.x == 0) {
-            int tot = 0;
-            for (int w = 0; w < 16; ++w) tot += wcnt[w];
-            carry += tot;
+            A.misc[1] = carry;
+            A.misc[2] = carry;
         }
         __syncthreads();
-    }
-    if (threadIdx.x == 0) {
-        n_alive[0] = carry;
-        n_alive[1] = carry;
-        rounds_done[0] = 0;
     }
 }
 
@@ -267,190 +394,250 @@ __global__ void __launch_bounds__(1024) k_alive_init(const int32_t *__restrict__
 // preemptive rounds
 // ---------------------------------------------------------------------------
 
-struct RoundArgs {
-    Frame fr;
-    const int32_t *__restrict__ pool;
-    const int32_t *__restrict__ pool_size;
-    const int32_t *__restrict__ leaves;
-    const int32_t *__restrict__ nmodes;
-    const Mode *__restrict__ modes;
-    int T, L, M, P, B, N;
-    uint64_t seed;
-    float inl2;
-    int refine;
-    Hyp *hyp;
-    float *energy;
-    double *sums;
-    int32_t *alive;
-    int32_t *n_alive;
-    int32_t *rounds_done;
-    float4 *draws;
-    float *partial;
-    uint16_t *inl;
-    int32_t *tr_alive;
-    float *tr_energy;
-    int32_t *tr_n_alive;
-};
-
-// round r runs when r == 0 and at least one hypothesis is live, or r > 0 and
-// more than one is
-__global__ void k_draw(RoundArgs A, int r)
+__global__ void __launch_bounds__(DRAW_BLOCK) k_b_draw(const Attempt *__restrict__ att, Stage S, int r)
 {
-    int na = A.n_alive[0];
-    if (r == 0 ? na < 1 : na <= 1) return;
-    if (A.rounds_done[0] != r) return;
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
-    int np = *A.pool_size;
-    if (i < A.B) {
-        U4 u = philox((uint64_t)r, (uint64_t)i, 0, 0, A.seed, TAG_PIX);
-        int p = A.pool[uniform_int(u.x[0], (uint64_t)np)];
+    FOR_UNITS(S, u) {
+        const int a = attempt_of(S, u);
+        const Attempt &A = att[a];
+        if (!round_active(A, r)) continue;
+        const int i = (u - S.off[a]) * DRAW_BLOCK + (int)threadIdx.x;
+        if (i >= A.B) continue;
+        const int np = A.misc[0];
+        const U4 x = philox((uint64_t)r, (uint64_t)i, 0, 0, A.seed, TAG_PIX);
+        const int p = A.pool[uniform_int(x.x[0], (uint64_t)np)];
         float c[3];
         cam_point(A.fr, p % A.fr.W, p / A.fr.W, A.fr.depth[p], c);
         A.draws[i] = make_float4(c[0], c[1], c[2], __int_as_float(p));
+        int cnt = 0;
+        for (int t = 0; t < A.T; ++t) cnt += A.nmodes[t * A.L + A.leaves[(int64_t)t * A.P + p]];
+        atomicAdd(&A.stats[2], (unsigned long long)cnt);
     }
 }
 
-__global__ void k_round_mark(RoundArgs A, int r)
-{
-    int na = A.n_alive[0];
-    if (r == 0 ? na < 1 : na <= 1) return;
-    if (A.rounds_done[0] == r) A.rounds_done[0] = r + 1;
-}
+// LDS image of one mode: mu (3), sinv (6), kappa, id = tree * M + mode, pad
+constexpr int SMODE = 12;
 
-__global__ void __launch_bounds__(64) k_score(RoundArgs A, int r)
+// One unit: 64 live hypotheses (lanes) x `dpu` consecutive draws.
+__global__ void __launch_bounds__(64) k_b_score(const Attempt *__restrict__ att, Stage S, int r, int dpu)
 {
-    if (A.rounds_done[0] != r + 1) return;
-    const int na = A.n_alive[0];
-    const int a0 = blockIdx.x * 64;
-    if (a0 >= na) return;
-    const int a = a0 + __lane_id();
-    const bool act = a < na;
-    const int h = act ? A.alive[a] : A.alive[a0];
-    const Hyp &hy = A.hyp[h];
-    float R0 = hy.R32[0], R1 = hy.R32[1], R2 = hy.R32[2], R3 = hy.R32[3], R4 = hy.R32[4], R5 = hy.R32[5],
-          R6 = hy.R32[6], R7 = hy.R32[7], R8 = hy.R32[8];
-    float t0 = hy.t32[0], t1 = hy.t32[1], t2 = hy.t32[2];
-    const int g = blockIdx.y;
-    const int i0 = g * GROUP, i1 = min(i0 + GROUP, A.B);
-    float gsum = 0.0f;
-    for (int i = i0; i < i1; ++i) {
-        const float4 dr = A.draws[i];
-        const int p = __float_as_int(dr.w);
-        const float y0 = fmaf(R0, dr.x, fmaf(R1, dr.y, fmaf(R2, dr.z, t0)));
-        const float y1 = fmaf(R3, dr.x, fmaf(R4, dr.y, fmaf(R5, dr.z, t1)));
-        const float y2 = fmaf(R6, dr.x, fmaf(R7, dr.y, fmaf(R8, dr.z, t2)));
-        float best = INFINITY, b0 = 0.0f, b1 = 0.0f, b2 = 0.0f;
-        int bid = 0xFFFF;
-        for (int tt = 0; tt < A.T; ++tt) {
-            const int li = tt * A.L + A.leaves[(int64_t)tt * A.P + p];
-            const int nm = A.nmodes[li];
-            const Mode *mb = A.modes + (int64_t)li * A.M;
-            for (int m = 0; m < nm; ++m) {
-                float d0, d1, d2;
-                float term = mode_term(mb[m], y0, y1, y2, d0, d1, d2);
+    extern __shared__ __align__(16) float smode[];
+    __shared__ int32_t s_ex[16], s_leaf[16];
+    const int lane = __lane_id();
+    FOR_UNITS(S, u) {
+        const int a = attempt_of(S, u);
+        const Attempt &A = att[a];
+        if (!round_active(A, r)) continue;
+        const int na = A.misc[1];
+        const int nch = (A.B + dpu - 1) / dpu;
+        const int local = u - S.off[a];
+        const int a0 = (local / nch) * 64;
+        const int ch = local % nch;
+        if (a0 >= na) continue;
+        const int ap = a0 + lane;
+        const bool act = ap < na;
+        const int h = A.alive[act ? ap : a0];
+        const Hyp &hy = A.hyp[h];
+        const float R0 = hy.R32[0], R1 = hy.R32[1], R2 = hy.R32[2], R3 = hy.R32[3], R4 = hy.R32[4],
+                    R5 = hy.R32[5], R6 = hy.R32[6], R7 = hy.R32[7], R8 = hy.R32[8];
+        const float t0 = hy.t32[0], t1 = hy.t32[1], t2 = hy.t32[2];
+        const int i1 = min((ch + 1) * dpu, A.B);
+        for (int i = ch * dpu; i < i1; ++i) {
+            const float4 dr = A.draws[i];
+            const int p = __float_as_int(dr.w);
+            // stage the draw's modes in (tree, mode) order
+            int leaf = 0, nm = 0;
+            if (lane < A.T) {
+                leaf = A.leaves[(int64_t)lane * A.P + p];
+                nm = A.nmodes[lane * A.L + leaf];
+            }
+            int incl = nm;
+            for (int o = 1; o < 16; o <<= 1) {
+                int y = __shfl_up(incl, o, 64);
+                if (lane >= o) incl += y;
+            }
+            const int cnt = __shfl(incl, A.T - 1, 64);
+            if (lane < A.T) {
+                s_ex[lane] = incl - nm;
+                s_leaf[lane] = leaf;
+            }
+            __syncthreads();
+            for (int j = lane; j < cnt; j += 64) {
+                // the mode's tree: the last tree whose first mode index is <= j
+                int tj = 0;
+                for (int t = 1; t < A.T; ++t)
+                    if (j >= s_ex[t]) tj = t;
+                const int m = j - s_ex[tj];
+                const Mode md = A.modes[((int64_t)tj * A.L + s_leaf[tj]) * A.M + m];
+                float *dst = smode + j * SMODE;
+                dst[0] = md.mu[0]; dst[1] = md.mu[1]; dst[2] = md.mu[2];
+                dst[3] = md.sinv[0]; dst[4] = md.sinv[1]; dst[5] = md.sinv[2];
+                dst[6] = md.sinv[3]; dst[7] = md.sinv[4]; dst[8] = md.sinv[5];
+                dst[9] = md.kappa;
+                dst[10] = __int_as_float(tj * A.M + m);
+                dst[11] = 0.0f;
+            }
+            __syncthreads();
+            const float y0 = fmaf(R0, dr.x, fmaf(R1, dr.y, fmaf(R2, dr.z, t0)));
+            const float y1 = fmaf(R3, dr.x, fmaf(R4, dr.y, fmaf(R5, dr.z, t1)));
+            const float y2 = fmaf(R6, dr.x, fmaf(R7, dr.y, fmaf(R8, dr.z, t2)));
+            float best = INFINITY;
+            int bj = -1;
+            for (int j = 0; j < cnt; ++j) {
+                const float4 q0 = *(const float4 *)(smode + j * SMODE);
+                const float4 q1 = *(const float4 *)(smode + j * SMODE + 4);
+                const float2 q2 = *(const float2 *)(smode + j * SMODE + 8);
+                const float d0 = y0 - q0.x, d1 = y1 - q0.y, d2 = y2 - q0.z;
+                const float s0 = q0.w, s1 = q1.x, s2 = q1.y, s3 = q1.z, s4 = q1.w, s5 = q2.x;
+                const float a0v = fmaf(s2, d2, fmaf(s1, d1, s0 * d0));
+                const float a1v = fmaf(s4, d2, fmaf(s3, d1, s1 * d0));
+                const float a2v = fmaf(s5, d2, fmaf(s4, d1, s2 * d0));
+                const float q = fmaf(d2, a2v, fmaf(d1, a1v, d0 * a0v));
+                const float term = fmaf(0.5f, q, q2.y);
                 if (term < best) {
                     best = term;
-                    bid = tt * A.M + m;
-                    b0 = d0;
-                    b1 = d1;
-                    b2 = d2;
+                    bj = j;
                 }
             }
-        }
-        float e = best < 0.0f ? best : 0.0f;
-        gsum = gsum + e;
-        bool in = bid != 0xFFFF && (b0 * b0 + b1 * b1) + b2 * b2 <= A.inl2;
-        if (act) A.inl[(int64_t)h * A.B + i] = in ? (uint16_t)bid : (uint16_t)0xFFFF;
-    }
-    if (act) A.partial[(int64_t)g * A.N + a] = gsum;
-}
-
-constexpr int CULL_THREADS = 1024;
-
-__global__ void __launch_bounds__(CULL_THREADS) k_cull(RoundArgs A, int r)
-{
-    if (A.rounds_done[0] != r + 1) return;
-    __shared__ unsigned long long keys[MAX_HYP];
-    const int na = A.n_alive[0];
-    const int G = (A.B + GROUP - 1) / GROUP;
-    int n2 = 1;
-    while (n2 < na) n2 <<= 1;
-    for (int a = threadIdx.x; a < n2; a += CULL_THREADS) {
-        if (a < na) {
-            int h = A.alive[a];
-            float S = 0.0f;
-            for (int g = 0; g < G; ++g) S = S + A.partial[(int64_t)g * A.N + a];
-            float E = A.energy[h] + S;
-            A.energy[h] = E;
-            keys[a] = ((unsigned long long)float_key(E) << 32) | (unsigned)h;
-            if (r < MAX_ROUNDS) {
-                A.tr_alive[r * MAX_HYP + a] = h;
-                A.tr_energy[r * MAX_HYP + a] = E;
+            const float e = best < 0.0f ? best : 0.0f;
+            bool in = false;
+            uint16_t id = 0xFFFF;
+            if (bj >= 0) {
+                const float *mb = smode + bj * SMODE;
+                const float d0 = y0 - mb[0], d1 = y1 - mb[1], d2 = y2 - mb[2];
+                in = (d0 * d0 + d1 * d1) + d2 * d2 <= A.inl2;
+                id = (uint16_t)__float_as_int(mb[10]);
             }
-        } else {
-            keys[a] = ~0ull;
-        }
-    }
-    __syncthreads();
-    for (int k = 2; k <= n2; k <<= 1) {
-        for (int j = k >> 1; j > 0; j >>= 1) {
-            for (int i = threadIdx.x; i < n2; i += CULL_THREADS) {
-                int ixj = i ^ j;
-                if (ixj > i) {
-                    unsigned long long x = keys[i], y = keys[ixj];
-                    bool asc = (i & k) == 0;
-                    if ((x > y) == asc) {
-                        keys[i] = y;
-                        keys[ixj] = x;
-                    }
-                }
+            if (act) {
+                A.e[(int64_t)i * A.N + ap] = e;
+                A.inl[(int64_t)i * A.N + ap] = in ? id : (uint16_t)0xFFFF;
             }
             __syncthreads();
         }
     }
-    const int keep = (na + 1) / 2;
-    for (int a = threadIdx.x; a < keep; a += CULL_THREADS) A.alive[a] = (int32_t)(keys[a] & 0xFFFFFFFFull);
-    if (threadIdx.x == 0) {
-        if (r < MAX_ROUNDS) A.tr_n_alive[r] = na;
-        A.n_alive[0] = keep;
+}
+
+// one workgroup per attempt: energies in the defined order, bitonic sort of
+// (energy key, index), keep the first ceil(n / 2)
+__global__ void __launch_bounds__(CULL_THREADS) k_b_cull(const Attempt *__restrict__ att, Stage S, int r)
+{
+    __shared__ unsigned long long keys[MAX_HYP];
+    FOR_UNITS(S, u) {
+        const Attempt &A = att[u];
+        if (!round_active(A, r)) continue;
+        const int na = A.misc[1];
+        int n2 = 1;
+        while (n2 < na) n2 <<= 1;
+        for (int ap = threadIdx.x; ap < n2; ap += CULL_THREADS) {
+            if (ap < na) {
+                const int h = A.alive[ap];
+                float Ssum = 0.0f, g = 0.0f;
+                for (int i = 0; i < A.B; ++i) {
+                    g = g + A.e[(int64_t)i * A.N + ap];
+                    if ((i % GROUP) == GROUP - 1 || i == A.B - 1) {
+                        Ssum = Ssum + g;
+                        g = 0.0f;
+                    }
+                }
+                const float E = A.energy[h] + Ssum;
+                A.energy[h] = E;
+                A.pos[h] = ap;
+                keys[ap] = ((unsigned long long)float_key(E) << 32) | (unsigned)h;
+                if (r < MAX_ROUNDS) {
+                    A.tr_alive[r * A.N + ap] = h;
+                    A.tr_energy[r * A.N + ap] = E;
+                }
+            } else {
+                keys[ap] = ~0ull;
+            }
+        }
+        __syncthreads();
+        for (int k = 2; k <= n2; k <<= 1) {
+            for (int j = k >> 1; j > 0; j >>= 1) {
+                for (int i = threadIdx.x; i < n2; i += CULL_THREADS) {
+                    const int ixj = i ^ j;
+                    if (ixj > i) {
+                        const unsigned long long x = keys[i], y = keys[ixj];
+                        const bool asc = (i & k) == 0;
+                        if ((x > y) == asc) {
+                            keys[i] = y;
+                            keys[ixj] = x;
+                        }
+                    }
+                }
+                __syncthreads();
+            }
+        }
+        const int keep = (na + 1) / 2;
+        for (int ap = threadIdx.x; ap < keep; ap += CULL_THREADS) A.alive[ap] = (int32_t)(keys[ap] & 0xFFFFFFFFull);
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            if (r < MAX_ROUNDS) A.tr_n_alive[r] = na;
+            A.stats[0] += (unsigned long long)na * A.stats[2];
+            A.stats[1] += (unsigned long long)na * (unsigned long long)A.B;
+            A.stats[2] = 0ull;
+            A.misc[1] = keep;
+            A.misc[3] = r + 1;
+        }
+        __syncthreads();
     }
 }
 
-// wave per survivor: this round's inliers (lane-strided sums in draw order,
-// xor butterfly), running sums, Kabsch refinement
-__global__ void __launch_bounds__(64) k_refine(RoundArgs A, int r)
+// one wavefront per survivor: this round's inliers, lane-strided in draw
+// order, combined by an xor butterfly (every lane ends with the same sums)
+__global__ void __launch_bounds__(64) k_b_refine_sums(const Attempt *__restrict__ att, Stage S, int r)
 {
-    if (A.rounds_done[0] != r + 1) return;
-    const int na = A.n_alive[0];
-    const int a = blockIdx.x;
-    if (a >= na) return;
-    const int h = A.alive[a];
     const int lane = __lane_id();
-    double s[NSUM];
+    FOR_UNITS(S, u) {
+        const int a = attempt_of(S, u);
+        const Attempt &A = att[a];
+        if (A.misc[3] != r + 1) continue;
+        const int sidx = u - S.off[a];
+        if (sidx >= A.misc[1]) continue;
+        const int h = A.alive[sidx];
+        const int ap = A.pos[h];
+        double s[NSUM];
 #pragma unroll
-    for (int k = 0; k < NSUM; ++k) s[k] = 0.0;
-    for (int i = lane; i < A.B; i += 64) {
-        uint16_t id = A.inl[(int64_t)h * A.B + i];
-        if (id == 0xFFFF) continue;
-        float4 dr = A.draws[i];
-        int p = __float_as_int(dr.w);
-        int tt = id / A.M, m = id % A.M;
-        int li = tt * A.L + A.leaves[(int64_t)tt * A.P + p];
-        const Mode &md = A.modes[(int64_t)li * A.M + m];
-        float c[3] = {dr.x, dr.y, dr.z};
-        float w[3] = {md.mu[0], md.mu[1], md.mu[2]};
-        sums_add_point(s, c, w);
+        for (int k = 0; k < NSUM; ++k) s[k] = 0.0;
+        for (int i = lane; i < A.B; i += 64) {
+            const uint16_t id = A.inl[(int64_t)i * A.N + ap];
+            if (id == 0xFFFF) continue;
+            const float4 dr = A.draws[i];
+            const int p = __float_as_int(dr.w);
+            const int tt = id / A.M, m = id % A.M;
+            const int li = tt * A.L + A.leaves[(int64_t)tt * A.P + p];
+            const Mode &md = A.modes[(int64_t)li * A.M + m];
+            const float c[3] = {dr.x, dr.y, dr.z};
+            const float w[3] = {md.mu[0], md.mu[1], md.mu[2]};
+            sums_add_point(s, c, w);
+        }
+#pragma unroll
+        for (int o = 32; o >= 1; o >>= 1)
+#pragma unroll
+            for (int k = 0; k < NSUM; ++k) s[k] = s[k] + __shfl_xor(s[k], o, 64);
+        double mine = 0.0;
+#pragma unroll
+        for (int k = 0; k < NSUM; ++k)
+            if (lane == k) mine = s[k];
+        if (lane < NSUM) A.rsums[(int64_t)h * NSUM + lane] = mine;
     }
-#pragma unroll
-    for (int o = 32; o >= 1; o >>= 1)
-#pragma unroll
-        for (int k = 0; k < NSUM; ++k) s[k] = s[k] + __shfl_xor(s[k], o, 64);
-    if (lane == 0) {
-        double *run = A.sums + (int64_t)h * NSUM;
+}
+
+// one lane per survivor: running sums and Kabsch refinement
+__global__ void __launch_bounds__(64) k_b_refine_solve(const Attempt *__restrict__ att, Stage S, int r)
+{
+    FOR_UNITS(S, u) {
+        const int a = attempt_of(S, u);
+        const Attempt &A = att[a];
+        if (A.misc[3] != r + 1) continue;
+        const int sidx = (u - S.off[a]) * 64 + __lane_id();
+        if (sidx >= A.misc[1]) continue;
+        const int h = A.alive[sidx];
         double tot[NSUM];
+        double *run = A.sums + (int64_t)h * NSUM;
+        const double *rs = A.rsums + (int64_t)h * NSUM;
 #pragma unroll
         for (int k = 0; k < NSUM; ++k) {
-            tot[k] = run[k] + s[k];
+            tot[k] = run[k] + rs[k];
             run[k] = tot[k];
         }
         double R[9], t[3];
@@ -468,35 +655,42 @@ __global__ void __launch_bounds__(64) k_refine(RoundArgs A, int r)
     }
 }
 
-__global__ void k_finish(RoundArgs A, const unsigned long long *__restrict__ total_samples,
-                         Result *__restrict__ res)
+__global__ void __launch_bounds__(64) k_b_finish(const Attempt *__restrict__ att, Stage S)
 {
-    if (threadIdx.x != 0) return;
-    Result o;
-    for (int k = 0; k < 16; ++k) o.pose[k] = (k % 5 == 0) ? 1.0 : 0.0;
-    o.score = 0.0f;
-    o.pad[0] = o.pad[1] = 0;
-    o.pool_size = *A.pool_size;
-    o.n_valid = A.n_alive[1];
-    o.n_rounds = A.rounds_done[0];
-    o.final_hyp = -1;
-    if (o.pool_size == 0) {
-        o.status = RELOC_FAIL_NO_VALID_PIXELS;
-    } else if (o.n_valid == 0) {
-        o.status = *total_samples == 0ull ? RELOC_FAIL_NO_MODES : RELOC_FAIL_NO_HYPOTHESIS;
-    } else {
-        int h = A.alive[0];
-        const Hyp &hy = A.hyp[h];
-        for (int rr = 0; rr < 3; ++rr) {
-            for (int c = 0; c < 3; ++c) o.pose[rr * 4 + c] = hy.R[rr * 3 + c];
-            o.pose[rr * 4 + 3] = hy.t[rr];
+    FOR_UNITS(S, u) {
+        if (threadIdx.x != 0) continue;
+        const Attempt &A = att[u];
+        Result o;
+        for (int k = 0; k < 16; ++k) o.pose_c2w[k] = (k % 5 == 0) ? 1.0 : 0.0;
+        o.score = 0.0f;
+        o.pool_size = A.misc[0];
+        o.n_valid = A.misc[2];
+        o.n_rounds = A.misc[3];
+        o.final_hyp = -1;
+        o.mode_evals = A.stats[0];
+        o.pair_evals = A.stats[1];
+        if (o.pool_size == 0) {
+            o.status = RELOC_FAIL_NO_VALID_PIXELS;
+        } else if (o.n_valid == 0) {
+            o.status = *A.total_samples == 0ull ? RELOC_FAIL_NO_MODES : RELOC_FAIL_NO_HYPOTHESIS;
+        } else {
+            const int h = A.alive[0];
+            const Hyp &hy = A.hyp[h];
+            for (int rr = 0; rr < 3; ++rr) {
+                for (int c = 0; c < 3; ++c) o.pose_c2w[rr * 4 + c] = hy.R[rr * 3 + c];
+                o.pose_c2w[rr * 4 + 3] = hy.t[rr];
+            }
+            o.score = (float)(A.sums[(int64_t)h * NSUM] / ((double)o.n_rounds * (double)A.B));
+            o.status = RELOC_OK;
+            o.final_hyp = h;
         }
-        o.score = (float)(A.sums[(int64_t)h * NSUM] / ((double)o.n_rounds * (double)A.B));
-        o.status = RELOC_OK;
-        o.final_hyp = h;
+        *A.result = o;
     }
-    *res = o;
 }
+
+// ---------------------------------------------------------------------------
+// host: batch plans, graphs and schedules
+// ---------------------------------------------------------------------------
 
 static int rounds_for(int N)
 {
@@ -505,53 +699,425 @@ static int rounds_for(int N)
     return r < 1 ? 1 : r;
 }
 
-// Queues one attempt on `s` (no host synchronisation); the result lands in
-// f->result.
-int relocalise_async(Forest *f, const Frame &fr, uint64_t seed, int N, hipStream_t s)
-{
-    int rc = update_modes(f, s);
-    if (rc) return rc;
-    rc = traverse_frame(f, fr, s);
-    if (rc) return rc;
-    int64_t P = (int64_t)fr.W * fr.H;
-    int nb = (int)((P + POOL_BLOCK - 1) / POOL_BLOCK);
-    RL_LAUNCH("k_pool_count", k_pool_count, dim3(nb), dim3(POOL_BLOCK), 0, s, fr, f->blockcnt);
-    RL_LAUNCH("k_pool_scan", k_pool_scan, dim3(1), dim3(1024), 0, s, f->blockcnt, nb, f->pool_size);
-    RL_LAUNCH("k_pool_write", k_pool_write, dim3(nb), dim3(POOL_BLOCK), 0, s, fr, f->blockcnt, f->pool);
+struct Sched {
+    int dpu;         // draws per scoring unit
+    int grid;        // persistent grid of the scoring kernel (0: one workgroup per unit)
+    int xcd;         // XCD-contiguous unit order
+};
 
-    HypArgs H;
-    H.fr = fr; H.pool = f->pool; H.pool_size = f->pool_size; H.leaves = f->leaves; H.nmodes = f->nmodes;
-    H.modes = f->modes; H.T = f->T; H.L = f->L; H.M = f->M; H.P = (int)P;
-    H.max_tries = f->p.max_tries; H.rgb_tol = f->p.rgb_tol;
-    H.ratio2 = f->p.rigid_ratio2; H.min_pair2 = f->p.min_pair2_m2; H.min_area2 = f->p.min_area2_m4;
-    H.resid2 = (double)f->p.resid_m * (double)f->p.resid_m;
-    H.seed = seed; H.hyp = f->hyp; H.hyp_init = f->hyp_init; H.hyp_try = f->hyp_try; H.energy = f->energy;
-    H.sums = f->sums;
-    RL_LAUNCH("k_hypgen", k_hypgen, dim3(N), dim3(64), 0, s, H);
-    RL_LAUNCH("k_alive_init", k_alive_init, dim3(1), dim3(1024), 0, s, f->hyp_try, N, f->alive, f->n_alive,
-                       f->rounds_done);
-
-    RoundArgs A;
-    A.fr = fr; A.pool = f->pool; A.pool_size = f->pool_size; A.leaves = f->leaves; A.nmodes = f->nmodes;
-    A.modes = f->modes; A.T = f->T; A.L = f->L; A.M = f->M; A.P = (int)P; A.B = f->p.batch_pixels; A.N = N;
-    A.seed = seed; A.inl2 = f->p.inlier_m * f->p.inlier_m; A.refine = f->p.refine;
-    A.hyp = f->hyp; A.energy = f->energy; A.sums = f->sums; A.alive = f->alive; A.n_alive = f->n_alive;
-    A.rounds_done = f->rounds_done; A.draws = f->draws; A.partial = f->partial; A.inl = f->inl;
-    A.tr_alive = f->tr_alive; A.tr_energy = f->tr_energy; A.tr_n_alive = f->tr_n_alive;
-    const int rounds = rounds_for(N);
-    const int G = (A.B + GROUP - 1) / GROUP;
-    int bound = N;   // live hypotheses at the start of round r are at most ceil(N / 2^r)
-    for (int r = 0; r < rounds; ++r) {
-        RL_LAUNCH("k_draw", k_draw, dim3((A.B + 255) / 256), dim3(256), 0, s, A, r);
-        RL_LAUNCH("k_round_mark", k_round_mark, dim3(1), dim3(1), 0, s, A, r);
-        RL_LAUNCH("k_score", k_score, dim3((bound + 63) / 64, G), dim3(64), 0, s, A, r);
-        RL_LAUNCH("k_cull", k_cull, dim3(1), dim3(CULL_THREADS), 0, s, A, r);
-        bound = (bound + 1) / 2;
-        RL_LAUNCH("k_refine", k_refine, dim3(bound), dim3(64), 0, s, A, r);
+struct Shape {
+    int W, H, N, B, T, L, M, weights;
+    bool operator==(const Shape &o) const
+    {
+        return W == o.W && H == o.H && N == o.N && B == o.B && T == o.T && L == o.L && M == o.M &&
+               weights == o.weights;
     }
-    RL_LAUNCH("k_finish", k_finish, dim3(1), dim3(64), 0, s, A, f->total_samples, f->result);
+};
+
+struct Plan {
+    std::vector<Shape> shape;
+    int n = 0, rounds = 0, tm_max = 1;
+    char *arena = nullptr;
+    size_t arena_bytes = 0;
+    Attempt *d_att = nullptr;
+    Attempt *h_att = nullptr;       // pinned
+    Result *h_res = nullptr;        // pinned
+    std::vector<Attempt> slices;    // scratch pointers per attempt
+    int32_t *d_off = nullptr;       // stage offsets of the chosen schedule
+    hipGraphExec_t exec = nullptr;
+    Sched sched{1, 0, 0};
+    std::string desc;
+    uint64_t last_use = 0;
+};
+
+}  // namespace rl
+
+struct reloc_batch {
+    std::vector<rl::Plan *> plans;
+    int tune = 1;
+    uint64_t clock = 0;
+    uint64_t bytes = 0;
+    hipStream_t cap = nullptr;
+    std::string last_desc;
+};
+
+namespace rl {
+
+static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+// scratch of one attempt, carved from `base` (nullptr: sizing pass)
+static size_t carve(const Shape &s, char *base, Attempt &A)
+{
+    const int64_t P = (int64_t)s.W * s.H;
+    const int nb = (int)((P + POOL_BLOCK - 1) / POOL_BLOCK);
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        char *p = base ? base + off : nullptr;
+        off += align256(bytes);
+        return p;
+    };
+    A.leaves = (int32_t *)take((size_t)s.T * P * 4);
+    A.pool = (int32_t *)take((size_t)P * 4);
+    A.blockcnt = (int32_t *)take((size_t)nb * 4);
+    A.blockw = (unsigned long long *)take((size_t)nb * 8);
+    A.cdf = (unsigned long long *)take(s.weights ? (size_t)P * 8 : 8);
+    A.misc = (int32_t *)take(16);
+    A.hyp = (Hyp *)take((size_t)s.N * sizeof(Hyp));
+    A.hyp_init = (double *)take((size_t)s.N * 12 * 8);
+    A.hyp_try = (int32_t *)take((size_t)s.N * 4);
+    A.energy = (float *)take((size_t)s.N * 4);
+    A.sums = (double *)take((size_t)s.N * NSUM * 8);
+    A.rsums = (double *)take((size_t)s.N * NSUM * 8);
+    A.alive = (int32_t *)take((size_t)s.N * 4);
+    A.pos = (int32_t *)take((size_t)s.N * 4);
+    A.draws = (float4 *)take((size_t)s.B * 16);
+    A.e = (float *)take((size_t)s.B * s.N * 4);
+    A.inl = (uint16_t *)take((size_t)s.B * s.N * 2);
+    A.stats = (unsigned long long *)take(3 * 8);
+    A.tr_alive = (int32_t *)take((size_t)MAX_ROUNDS * s.N * 4);
+    A.tr_energy = (float *)take((size_t)MAX_ROUNDS * s.N * 4);
+    A.tr_n_alive = (int32_t *)take((size_t)MAX_ROUNDS * 4);
+    A.result = (Result *)take(sizeof(Result));
+    return off;
+}
+
+static void free_plan(reloc_batch *b, Plan *pl)
+{
+    if (!pl) return;
+    if (pl->exec) (void)hipGraphExecDestroy(pl->exec);
+    if (pl->arena) (void)hipFree(pl->arena);
+    if (pl->d_att) (void)hipFree(pl->d_att);
+    if (pl->d_off) (void)hipFree(pl->d_off);
+    if (pl->h_att) (void)hipHostFree(pl->h_att);
+    if (pl->h_res) (void)hipHostFree(pl->h_res);
+    b->bytes -= pl->arena_bytes;
+    delete pl;
+}
+
+// stages of one schedule in launch order
+struct Stages {
+    Stage pix, pb, att, hyp, draw;
+    std::vector<Stage> score, refine, solve;
+};
+
+// host offsets of every stage for schedule `sc`: pix, pb, att, hyp, draw,
+// then per round (score, refine, solve)
+static std::vector<int32_t> offsets(const Plan *pl, const Sched &sc)
+{
+    const int n = pl->n, R = pl->rounds;
+    const int n_stage = 5 + 3 * R;
+    std::vector<int32_t> off((size_t)n_stage * (n + 1), 0);
+    auto fill = [&](int k, auto units) {
+        int32_t *o = off.data() + (size_t)k * (n + 1);
+        o[0] = 0;
+        for (int a = 0; a < n; ++a) o[a + 1] = o[a] + units(a);
+    };
+    auto P = [&](int a) { return (int64_t)pl->shape[a].W * pl->shape[a].H; };
+    fill(0, [&](int a) { return (int)((P(a) + PIX_BLOCK - 1) / PIX_BLOCK); });
+    fill(1, [&](int a) { return (int)((P(a) + POOL_BLOCK - 1) / POOL_BLOCK); });
+    fill(2, [&](int) { return 1; });
+    fill(3, [&](int a) { return pl->shape[a].N; });
+    fill(4, [&](int a) { return (pl->shape[a].B + DRAW_BLOCK - 1) / DRAW_BLOCK; });
+    auto bound = [&](int a, int rr) {
+        int bnd = pl->shape[a].N;
+        for (int k = 0; k < rr; ++k) bnd = (bnd + 1) / 2;
+        return bnd;
+    };
+    for (int r = 0; r < R; ++r) {
+        fill(5 + 3 * r, [&](int a) {
+            if (r >= rounds_for(pl->shape[a].N)) return 0;
+            return ((bound(a, r) + 63) / 64) * ((pl->shape[a].B + sc.dpu - 1) / sc.dpu);
+        });
+        fill(6 + 3 * r, [&](int a) { return r >= rounds_for(pl->shape[a].N) ? 0 : bound(a, r + 1); });
+        fill(7 + 3 * r, [&](int a) { return r >= rounds_for(pl->shape[a].N) ? 0 : (bound(a, r + 1) + 63) / 64; });
+    }
+    return off;
+}
+
+static Stages stages_of(const Plan *pl, const Sched &sc, const int32_t *d_off, const std::vector<int32_t> &off)
+{
+    const int n = pl->n;
+    auto mk = [&](int k) {
+        Stage s;
+        s.off = d_off + (size_t)k * (n + 1);
+        s.n = n;
+        s.total = off[(size_t)k * (n + 1) + n];
+        s.xcd = sc.xcd;
+        return s;
+    };
+    Stages st;
+    st.pix = mk(0); st.pb = mk(1); st.att = mk(2); st.hyp = mk(3); st.draw = mk(4);
+    for (int r = 0; r < pl->rounds; ++r) {
+        st.score.push_back(mk(5 + 3 * r));
+        st.refine.push_back(mk(6 + 3 * r));
+        st.solve.push_back(mk(7 + 3 * r));
+    }
+    return st;
+}
+
+static unsigned grid_of(const Stage &s, int cap, int xcd)
+{
+    int g = s.total < 1 ? 1 : s.total;
+    if (cap > 0 && g > cap) g = cap;
+    if (xcd) g = ((g + 7) / 8) * 8;
+    return (unsigned)g;
+}
+
+// enqueues every kernel of the batch on `s`
+static int enqueue(const Plan *pl, const Sched &sc, const Stages &st, hipStream_t s)
+{
+    const Attempt *d = pl->d_att;
+    const int cap = 4096;
+    RL_LAUNCH("k_b_leaves", k_b_leaves, dim3(grid_of(st.pix, cap, sc.xcd)), dim3(PIX_BLOCK), 0, s, d, st.pix);
+    RL_LAUNCH("k_b_pool_count", k_b_pool_count, dim3(grid_of(st.pb, cap, sc.xcd)), dim3(POOL_BLOCK), 0, s, d, st.pb);
+    RL_LAUNCH("k_b_pool_scan", k_b_pool_scan, dim3(grid_of(st.att, cap, 0)), dim3(1024), 0, s, d, st.att);
+    RL_LAUNCH("k_b_pool_write", k_b_pool_write, dim3(grid_of(st.pb, cap, sc.xcd)), dim3(POOL_BLOCK), 0, s, d, st.pb);
+    RL_LAUNCH("k_b_hypgen", k_b_hypgen, dim3(grid_of(st.hyp, 0, sc.xcd)), dim3(64), 0, s, d, st.hyp);
+    RL_LAUNCH("k_b_alive_init", k_b_alive_init, dim3(grid_of(st.att, cap, 0)), dim3(1024), 0, s, d, st.att);
+    const size_t smem = (size_t)pl->tm_max * SMODE * sizeof(float);
+    for (int r = 0; r < pl->rounds; ++r) {
+        RL_LAUNCH("k_b_draw", k_b_draw, dim3(grid_of(st.draw, cap, sc.xcd)), dim3(DRAW_BLOCK), 0, s, d, st.draw, r);
+        RL_LAUNCH("k_b_score", k_b_score, dim3(grid_of(st.score[r], sc.grid, sc.xcd)), dim3(64), smem, s, d,
+                  st.score[r], r, sc.dpu);
+        RL_LAUNCH("k_b_cull", k_b_cull, dim3(grid_of(st.att, cap, 0)), dim3(CULL_THREADS), 0, s, d, st.att, r);
+        RL_LAUNCH("k_b_refine_sums", k_b_refine_sums, dim3(grid_of(st.refine[r], 0, sc.xcd)), dim3(64), 0, s, d,
+                  st.refine[r], r);
+        RL_LAUNCH("k_b_refine_solve", k_b_refine_solve, dim3(grid_of(st.solve[r], 0, sc.xcd)), dim3(64), 0, s, d,
+                  st.solve[r], r);
+    }
+    RL_LAUNCH("k_b_finish", k_b_finish, dim3(grid_of(st.att, cap, 0)), dim3(64), 0, s, d, st.att);
     RL_HIP(hipGetLastError());
-    f->last_N = N;
+    return RELOC_OK;
+}
+
+// captures the batch for schedule `sc` with its own offsets buffer
+static int capture(reloc_batch *b, const Plan *pl, const Sched &sc, int32_t **d_off_out, hipGraphExec_t *out)
+{
+    const std::vector<int32_t> off = offsets(pl, sc);
+    int32_t *d_off = nullptr;
+    RL_HIP(hipMalloc((void **)&d_off, off.size() * 4));
+    if (hipMemcpy(d_off, off.data(), off.size() * 4, hipMemcpyHostToDevice) != hipSuccess) {
+        (void)hipFree(d_off);
+        return RELOC_E_HIP;
+    }
+    const Stages st = stages_of(pl, sc, d_off, off);
+    if (!b->cap && hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking) != hipSuccess) {
+        (void)hipFree(d_off);
+        return RELOC_E_HIP;
+    }
+    const bool was_on = prof_on();
+    if (was_on) reloc_profile_enable(0);
+    hipGraph_t g = nullptr;
+    int rc = RELOC_OK;
+    if (hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal) != hipSuccess) rc = RELOC_E_HIP;
+    if (!rc) {
+        rc = enqueue(pl, sc, st, b->cap);
+        if (hipStreamEndCapture(b->cap, &g) != hipSuccess && !rc) rc = RELOC_E_HIP;
+    }
+    if (was_on) reloc_profile_enable(1);
+    if (!rc && hipGraphInstantiate(out, g, nullptr, nullptr, 0) != hipSuccess) rc = RELOC_E_HIP;
+    if (g) (void)hipGraphDestroy(g);
+    if (rc) {
+        (void)hipFree(d_off);
+        return rc;
+    }
+    *d_off_out = d_off;
+    return RELOC_OK;
+}
+
+static std::string sched_desc(const Sched &s)
+{
+    char buf[160];
+    if (s.grid)
+        snprintf(buf, sizeof(buf), "draws_per_unit=%d score_grid=%d xcd_contiguous=%d", s.dpu, s.grid, s.xcd);
+    else
+        snprintf(buf, sizeof(buf), "draws_per_unit=%d score_grid=per-unit xcd_contiguous=%d", s.dpu, s.xcd);
+    return buf;
+}
+
+// runs the plan once: the graph, or, while per-kernel timing is on, the same
+// kernels launched one by one so that each launch can be timed
+static int run_plan(Plan *pl, hipStream_t s)
+{
+    if (prof_on()) {
+        const std::vector<int32_t> off = offsets(pl, pl->sched);
+        return enqueue(pl, pl->sched, stages_of(pl, pl->sched, pl->d_off, off), s);
+    }
+    RL_HIP(hipGraphLaunch(pl->exec, s));
+    return RELOC_OK;
+}
+
+static int tune(reloc_batch *b, Plan *pl, hipStream_t s)
+{
+    std::vector<Sched> cands;
+    cands.push_back({1, 0, 0});
+    if (b->tune) {
+        cands.push_back({1, 0, 1});
+        cands.push_back({2, 0, 1});
+        cands.push_back({4, 0, 1});
+        cands.push_back({1, 2048, 1});
+        cands.push_back({2, 1024, 1});
+    }
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    RL_HIP(hipEventCreate(&e0));
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return RELOC_E_HIP;
+    }
+    float best_ms = 1e30f;
+    hipGraphExec_t best = nullptr;
+    int32_t *best_off = nullptr;
+    Sched best_s = cands[0];
+    int rc = RELOC_OK;
+    for (const Sched &c : cands) {
+        hipGraphExec_t ex = nullptr;
+        int32_t *d_off = nullptr;
+        rc = capture(b, pl, c, &d_off, &ex);
+        if (rc) break;
+        float ms = 0.0f;
+        if (cands.size() > 1) {
+            // one warm launch, one timed launch; every launch recomputes the
+            // same results from the uploaded descriptors
+            if (hipGraphLaunch(ex, s) != hipSuccess || hipEventRecord(e0, s) != hipSuccess ||
+                hipGraphLaunch(ex, s) != hipSuccess || hipEventRecord(e1, s) != hipSuccess ||
+                hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+                (void)hipGraphExecDestroy(ex);
+                (void)hipFree(d_off);
+                rc = RELOC_E_HIP;
+                break;
+            }
+        }
+        if (ms < best_ms) {
+            if (best) (void)hipGraphExecDestroy(best);
+            if (best_off) (void)hipFree(best_off);
+            best = ex;
+            best_off = d_off;
+            best_ms = ms;
+            best_s = c;
+        } else {
+            (void)hipGraphExecDestroy(ex);
+            (void)hipFree(d_off);
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (rc) {
+        if (best) (void)hipGraphExecDestroy(best);
+        if (best_off) (void)hipFree(best_off);
+        return rc;
+    }
+    pl->exec = best;
+    pl->d_off = best_off;
+    pl->sched = best_s;
+    pl->desc = sched_desc(best_s) + (cands.size() > 1 ? " (tuned)" : " (fixed)");
+    return RELOC_OK;
+}
+
+static Plan *find_or_make_plan(reloc_batch *b, const std::vector<Shape> &shape, int tm_max, int *rc)
+{
+    for (Plan *p : b->plans)
+        if (p->shape.size() == shape.size() && std::equal(shape.begin(), shape.end(), p->shape.begin()) &&
+            p->tm_max == tm_max) {
+            p->last_use = ++b->clock;
+            return p;
+        }
+    if (b->plans.size() >= 8) {     // evict the least recently used shape
+        auto it = std::min_element(b->plans.begin(), b->plans.end(),
+                                   [](Plan *x, Plan *y) { return x->last_use < y->last_use; });
+        free_plan(b, *it);
+        b->plans.erase(it);
+    }
+    Plan *pl = new (std::nothrow) Plan();
+    if (!pl) {
+        *rc = RELOC_E_NOMEM;
+        return nullptr;
+    }
+    pl->shape = shape;
+    pl->n = (int)shape.size();
+    pl->tm_max = tm_max;
+    for (const Shape &s : shape) pl->rounds = std::max(pl->rounds, rounds_for(s.N));
+    size_t total = 0;
+    pl->slices.resize(pl->n);
+    std::vector<size_t> at(pl->n);
+    for (int a = 0; a < pl->n; ++a) {
+        at[a] = total;
+        total += carve(shape[a], nullptr, pl->slices[a]);
+    }
+    pl->arena_bytes = total;
+    if (hipMalloc((void **)&pl->arena, total) != hipSuccess ||
+        hipMalloc((void **)&pl->d_att, sizeof(Attempt) * pl->n) != hipSuccess ||
+        hipHostMalloc((void **)&pl->h_att, sizeof(Attempt) * pl->n, hipHostMallocDefault) != hipSuccess ||
+        hipHostMalloc((void **)&pl->h_res, sizeof(Result) * pl->n, hipHostMallocDefault) != hipSuccess) {
+        pl->arena_bytes = 0;
+        free_plan(b, pl);
+        *rc = RELOC_E_NOMEM;
+        return nullptr;
+    }
+    b->bytes += total;
+    for (int a = 0; a < pl->n; ++a) carve(shape[a], pl->arena + at[a], pl->slices[a]);
+    pl->last_use = ++b->clock;
+    b->plans.push_back(pl);
+    return pl;
+}
+
+// validates and runs a batch; results land in pl->h_res (pinned)
+static int run_batch(reloc_batch *b, const reloc_attempt *att, int n, hipStream_t s, Plan **plan_out)
+{
+    if (!b || !att || n < 1) return RELOC_E_ARG;
+    std::vector<Shape> shape(n);
+    std::vector<Frame> frames(n);
+    int tm_max = 1;
+    for (int a = 0; a < n; ++a) {
+        const reloc_attempt &x = att[a];
+        Forest *f = x.forest;
+        if (!f) return RELOC_E_ARG;
+        int rc = frame_from(f, x.depth_dev, x.rgb_dev, &x.K, frames[a]);
+        if (rc) return rc;
+        const int N = x.n_hypotheses > 0 ? x.n_hypotheses : f->p.n_hypotheses;
+        if (N > MAX_HYP || f->T * f->M > MAX_TM) return RELOC_E_ARG;
+        shape[a] = Shape{frames[a].W, frames[a].H, N, f->p.batch_pixels, f->T, f->L, f->M,
+                         x.pixel_weights_dev ? 1 : 0};
+        tm_max = std::max(tm_max, f->T * f->M);
+    }
+    for (int a = 0; a < n; ++a) {   // pending modes of every forest involved
+        int rc = update_modes(att[a].forest, s);
+        if (rc) return rc;
+    }
+    int rc = RELOC_OK;
+    Plan *pl = find_or_make_plan(b, shape, tm_max, &rc);
+    if (!pl) return rc;
+    for (int a = 0; a < n; ++a) {
+        const reloc_attempt &x = att[a];
+        const Forest *f = x.forest;
+        Attempt A = pl->slices[a];
+        A.fr = frames[a];
+        A.nodes = f->nodes;
+        A.nmodes = f->nmodes;
+        A.modes = f->modes;
+        A.mode_rgb = f->mode_rgb;
+        A.total_samples = f->total_samples;
+        A.weights = x.pixel_weights_dev;
+        A.T = f->T; A.L = f->L; A.M = f->M; A.P = frames[a].W * frames[a].H;
+        A.N = shape[a].N; A.B = f->p.batch_pixels; A.max_tries = f->p.max_tries; A.rgb_tol = f->p.rgb_tol;
+        A.refine = f->p.refine; A.rounds = rounds_for(A.N);
+        A.ratio2 = f->p.rigid_ratio2; A.min_pair2 = f->p.min_pair2_m2; A.min_area2 = f->p.min_area2_m4;
+        A.inl2 = f->p.inlier_m * f->p.inlier_m;
+        A.resid2 = (double)f->p.resid_m * (double)f->p.resid_m;
+        A.seed = x.seed;
+        pl->h_att[a] = A;
+    }
+    RL_HIP(hipMemcpyAsync(pl->d_att, pl->h_att, sizeof(Attempt) * n, hipMemcpyHostToDevice, s));
+    if (!pl->exec) {
+        rc = tune(b, pl, s);
+        if (rc) return rc;
+    }
+    b->last_desc = pl->desc;
+    rc = run_plan(pl, s);
+    if (rc) return rc;
+    for (int a = 0; a < n; ++a)
+        RL_HIP(hipMemcpyAsync(&pl->h_res[a], pl->slices[a].result, sizeof(Result), hipMemcpyDeviceToHost, s));
+    RL_HIP(hipStreamSynchronize(s));
+    if (plan_out) *plan_out = pl;
     return RELOC_OK;
 }
 
@@ -559,50 +1125,142 @@ int relocalise_async(Forest *f, const Frame &fr, uint64_t seed, int N, hipStream
 
 using namespace rl;
 
+// ---------------------------------------------------------------------------
+// C ABI
+// ---------------------------------------------------------------------------
+
+extern "C" int reloc_batch_create(reloc_batch **out)
+{
+    if (!out) return RELOC_E_ARG;
+    *out = new (std::nothrow) reloc_batch();
+    return *out ? RELOC_OK : RELOC_E_NOMEM;
+}
+
+extern "C" int reloc_batch_destroy(reloc_batch *b)
+{
+    if (!b) return RELOC_E_ARG;
+    (void)hipDeviceSynchronize();
+    for (Plan *p : b->plans) free_plan(b, p);
+    b->plans.clear();
+    if (b->cap) (void)hipStreamDestroy(b->cap);
+    delete b;
+    return RELOC_OK;
+}
+
+extern "C" int reloc_batch_set_tuning(reloc_batch *b, int32_t on)
+{
+    if (!b) return RELOC_E_ARG;
+    b->tune = on ? 1 : 0;
+    return RELOC_OK;
+}
+
+extern "C" int reloc_batch_schedule(const reloc_batch *b, char *desc, int32_t cap)
+{
+    if (!b || !desc || cap < 1) return RELOC_E_ARG;
+    const int n = (int)b->last_desc.size() < cap - 1 ? (int)b->last_desc.size() : cap - 1;
+    memcpy(desc, b->last_desc.data(), (size_t)n);
+    desc[n] = 0;
+    return RELOC_OK;
+}
+
+extern "C" int reloc_batch_memory(const reloc_batch *b, uint64_t *bytes_out)
+{
+    if (!b || !bytes_out) return RELOC_E_ARG;
+    *bytes_out = b->bytes;
+    return RELOC_OK;
+}
+
+extern "C" int reloc_relocalise_batch(reloc_batch *b, const reloc_attempt *attempts, int32_t n,
+                                      reloc_result *results_host, void *stream)
+{
+    if (!results_host) return RELOC_E_ARG;
+    Plan *pl = nullptr;
+    const int rc = run_batch(b, attempts, n, (hipStream_t)stream, &pl);
+    if (rc) return rc;
+    memcpy(results_host, pl->h_res, sizeof(Result) * n);
+    return RELOC_OK;
+}
+
+static int plain(reloc_forest *f, const uint16_t *depth_dev, const uint8_t *rgb_dev, const reloc_intrinsics *K,
+                 uint64_t seed, int32_t n_hypotheses, const uint32_t *weights, reloc_result *out, void *stream)
+{
+    if (!f || !K || !out) return RELOC_E_ARG;
+    if (!f->plain) {
+        reloc_batch *b = nullptr;
+        const int rc = reloc_batch_create(&b);
+        if (rc) return rc;
+        b->tune = 0;
+        f->plain = b;
+    }
+    reloc_attempt x;
+    x.forest = f;
+    x.depth_dev = depth_dev;
+    x.rgb_dev = rgb_dev;
+    x.K = *K;
+    x.seed = seed;
+    x.n_hypotheses = n_hypotheses;
+    x.pixel_weights_dev = weights;
+    return reloc_relocalise_batch(f->plain, &x, 1, out, stream);
+}
+
+extern "C" int reloc_relocalise_ex(reloc_forest *f, const uint16_t *depth_dev, const uint8_t *rgb_dev,
+                                   const reloc_intrinsics *K, uint64_t attempt_seed, int32_t n_hypotheses,
+                                   const uint32_t *pixel_weights_dev, reloc_result *result_out, void *stream)
+{
+    const int rc = plain(f, depth_dev, rgb_dev, K, attempt_seed, n_hypotheses, pixel_weights_dev, result_out, stream);
+    if (rc) return rc;
+    return result_out->status;
+}
+
 extern "C" int reloc_relocalise(reloc_forest *f, const uint16_t *depth_dev, const uint8_t *rgb_dev,
                                 const reloc_intrinsics *K, uint64_t attempt_seed, int32_t n_hypotheses,
                                 const uint32_t *pixel_weights_dev, double pose_c2w_out[16], float *score_out,
                                 void *stream)
 {
-    if (!f || !pose_c2w_out || !score_out) return RELOC_E_ARG;
-    if (pixel_weights_dev) return RELOC_E_ARG;   // weighted picks: see the learned-proposal entry points
-    Frame fr;
-    int rc = frame_from(f, depth_dev, rgb_dev, K, fr);
+    if (!pose_c2w_out || !score_out) return RELOC_E_ARG;
+    reloc_result r;
+    const int rc = plain(f, depth_dev, rgb_dev, K, attempt_seed, n_hypotheses, pixel_weights_dev, &r, stream);
     if (rc) return rc;
-    int N = n_hypotheses > 0 ? n_hypotheses : f->p.n_hypotheses;
-    if (N > MAX_HYP) return RELOC_E_ARG;
-    hipStream_t s = (hipStream_t)stream;
-    rc = relocalise_async(f, fr, attempt_seed, N, s);
-    if (rc) return rc;
-    RL_HIP(hipMemcpyAsync(f->result_host, f->result, sizeof(Result), hipMemcpyDeviceToHost, s));
-    RL_HIP(hipStreamSynchronize(s));
-    const Result &o = *f->result_host;
-    memcpy(pose_c2w_out, o.pose, sizeof(o.pose));
-    *score_out = o.score;
-    return o.status;
+    memcpy(pose_c2w_out, r.pose_c2w, sizeof(r.pose_c2w));
+    *score_out = r.score;
+    return r.status;
 }
 
 extern "C" int reloc_debug_trace(const reloc_forest *f, reloc_trace *tr)
 {
     if (!f || !tr) return RELOC_E_ARG;
+    const reloc_batch *b = f->plain;
+    if (!b || b->plans.empty()) return RELOC_E_STATE;
+    const Plan *pl = *std::max_element(b->plans.begin(), b->plans.end(),
+                                       [](Plan *x, Plan *y) { return x->last_use < y->last_use; });
     RL_HIP(hipDeviceSynchronize());
-    const Result &o = *f->result_host;
-    int N = f->last_N;
+    const Attempt &A = pl->slices[0];
+    const Result &o = pl->h_res[0];
+    const int N = pl->shape[0].N;
     if (tr->pool_size) *tr->pool_size = o.pool_size;
     if (tr->final_hyp) *tr->final_hyp = o.final_hyp;
     if (tr->n_rounds) *tr->n_rounds = o.n_rounds;
-    int nh = std::min(N, tr->cap_hyp);
-    if (tr->hyp_try) RL_HIP(hipMemcpy(tr->hyp_try, f->hyp_try, (size_t)nh * 4, hipMemcpyDeviceToHost));
-    if (tr->hyp_pose) RL_HIP(hipMemcpy(tr->hyp_pose, f->hyp_init, (size_t)nh * 12 * 8, hipMemcpyDeviceToHost));
-    int nr = std::min(std::min(o.n_rounds, tr->cap_rounds), MAX_ROUNDS);
-    if (tr->n_alive) RL_HIP(hipMemcpy(tr->n_alive, f->tr_n_alive, (size_t)nr * 4, hipMemcpyDeviceToHost));
+    const int nh = std::min(N, tr->cap_hyp);
+    if (tr->hyp_try) RL_HIP(hipMemcpy(tr->hyp_try, A.hyp_try, (size_t)nh * 4, hipMemcpyDeviceToHost));
+    if (tr->hyp_pose) RL_HIP(hipMemcpy(tr->hyp_pose, A.hyp_init, (size_t)nh * 12 * 8, hipMemcpyDeviceToHost));
+    const int nr = std::min(std::min(o.n_rounds, tr->cap_rounds), MAX_ROUNDS);
+    if (tr->n_alive) RL_HIP(hipMemcpy(tr->n_alive, A.tr_n_alive, (size_t)nr * 4, hipMemcpyDeviceToHost));
     for (int r = 0; r < nr; ++r) {
         if (tr->alive)
-            RL_HIP(hipMemcpy(tr->alive + (size_t)r * tr->cap_hyp, f->tr_alive + (size_t)r * MAX_HYP, (size_t)nh * 4,
+            RL_HIP(hipMemcpy(tr->alive + (size_t)r * tr->cap_hyp, A.tr_alive + (size_t)r * N, (size_t)nh * 4,
                              hipMemcpyDeviceToHost));
         if (tr->energy)
-            RL_HIP(hipMemcpy(tr->energy + (size_t)r * tr->cap_hyp, f->tr_energy + (size_t)r * MAX_HYP,
-                             (size_t)nh * 4, hipMemcpyDeviceToHost));
+            RL_HIP(hipMemcpy(tr->energy + (size_t)r * tr->cap_hyp, A.tr_energy + (size_t)r * N, (size_t)nh * 4,
+                             hipMemcpyDeviceToHost));
     }
     return RELOC_OK;
+}
+
+// releases a forest's plain-path batch (called when the forest is destroyed)
+void rl_free_plain(Forest *f)
+{
+    if (f->plain) {
+        reloc_batch_destroy(f->plain);
+        f->plain = nullptr;
+    }
 }

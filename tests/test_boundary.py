@@ -1,0 +1,77 @@
+"""CPU checks of the C ABI boundary: the built library loads, exports every
+function include/reloc.h declares, its structs have the layout the header
+implies, and argument errors come back as status codes (no GPU needed)."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "reloc.h")
+
+
+def declared_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(reloc_[a-z0-9_]+)\s*\(", src)))
+
+
+def test_every_declared_symbol_is_exported():
+    import paper_1801_08361_amd as rl
+    L = rl.lib()
+    names = declared_functions()
+    assert len(names) >= 25
+    missing = [n for n in names if not hasattr(L, n)]
+    assert not missing, missing
+    # and the binding wraps each of them
+    assert set(names) <= set(rl._SIGS), set(names) - set(rl._SIGS)
+
+
+def test_struct_layouts():
+    import paper_1801_08361_amd as rl
+    assert C.sizeof(rl.reloc_intrinsics) == 24
+    assert C.sizeof(rl.reloc_result) == 168
+    assert C.sizeof(rl.reloc_attempt) == 72
+    assert C.sizeof(rl.reloc_params) == 4 * 4 + 8 + 4 * 15 + 4 * 5
+    assert rl.ENTRY_DTYPE.itemsize == 16 and rl.MODE_DTYPE.itemsize == 48
+
+
+def test_defaults_match_the_oracle():
+    import oracle
+    import paper_1801_08361_amd as rl
+    from tests.gpu_util import FIELDS
+    a = rl.params_default()
+    b = oracle.default_params()
+    for f in FIELDS:
+        assert getattr(a, f) == getattr(b, f), f
+
+
+def test_argument_errors_without_gpu():
+    import paper_1801_08361_amd as rl
+    L = rl.lib()
+    assert L.reloc_params_default(None) == rl.E_ARG
+    out = C.c_void_p()
+    assert L.reloc_forest_create(None, None, C.byref(out)) == rl.E_ARG
+    p = rl.params_default(depth=0)
+    assert L.reloc_forest_create(C.byref(p), None, C.byref(out)) == rl.E_ARG
+    p = rl.params_default(offset_pxmm=1 << 21)
+    assert L.reloc_forest_create(C.byref(p), None, C.byref(out)) == rl.E_RANGE
+    p = rl.params_default(cov_reg_mm2=0)
+    assert L.reloc_forest_create(C.byref(p), None, C.byref(out)) == rl.E_ARG
+    assert L.reloc_forest_destroy(None) == rl.E_ARG
+    assert L.reloc_relocalise(None, None, None, None, 0, 0, None, None, None, None) == rl.E_ARG
+    assert L.reloc_relocalise_batch(None, None, 0, None, None) == rl.E_ARG
+    assert L.reloc_batch_destroy(None) == rl.E_ARG
+    for code in (0, 1, 2, 3, -1, -2, -3, -4, -5, 99):
+        assert isinstance(rl.status_string(code), str)
+    with pytest.raises(rl.RelocError):
+        rl._check(-1, "x")
+
+
+def test_no_cpu_fallback_when_library_missing(tmp_path, monkeypatch):
+    import paper_1801_08361_amd as rl
+    monkeypatch.setattr(rl, "LIB_PATH", str(tmp_path / "missing.so"))
+    monkeypatch.setattr(rl, "_lib", None)
+    with pytest.raises(RuntimeError):
+        rl.lib()
