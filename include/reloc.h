@@ -260,6 +260,11 @@ typedef struct {
 } reloc_trace;
 int reloc_debug_trace(const reloc_forest *f, reloc_trace *tr);
 
+/* Host run of the work-unit ownership rule of the persistent kernels: for a
+ * stage of `total` units on a grid of `grid` workgroups, owners_host[u] =
+ * number of workgroups that process unit u (every entry must be 1). */
+int reloc_debug_unit_owners(int32_t xcd, int32_t total, int32_t grid, int32_t *owners_host);
+
 #ifdef __cplusplus
 }
 #endif

@@ -102,6 +102,15 @@ def lib():
         L.oracle_svd3.argtypes = [vp, vp, vp, vp]
         L.oracle_relocalise.argtypes = [vp, vp, vp, i32, i32, vp, u64, i32, vp, vp, vp, vp]
         L.oracle_pose_success.argtypes = [vp, vp, vp, vp]
+        L.oracle_verify.argtypes = [vp, vp, i32, i32, vp, vp, vp]
+        L.oracle_bf16.argtypes = [C.c_float]
+        L.oracle_bf16.restype = C.c_float
+        L.oracle_features24.argtypes = [vp, vp, vp, i32, i32, vp, vp, i32, vp]
+        L.oracle_label.argtypes = [vp, vp, vp, i32, i32, vp, vp, vp, i32, vp]
+        L.oracle_mlp_init.argtypes = [u64, vp]
+        L.oracle_mlp_init.restype = None
+        L.oracle_mlp_forward.argtypes = [vp, vp, i32, vp]
+        L.oracle_mlp_grad.argtypes = [vp, vp, vp, i32, vp, vp]
         _lib = L
     return _lib
 
@@ -286,6 +295,78 @@ class Forest:
         if rc < 0:
             raise ValueError(rc)
         return rc, pose.reshape(4, 4), score.value, bufs
+
+
+MLP_NPARAM = 5825
+
+
+def verify(da, db):
+    """(valid fraction of da, mean |da - db| in m over pixels valid in both, accept)"""
+    a = np.ascontiguousarray(_np(da), dtype=np.uint16)
+    b = np.ascontiguousarray(_np(db), dtype=np.uint16)
+    H, W = a.shape
+    vf = C.c_double(0); mu = C.c_double(0); acc = C.c_int(0)
+    rc = lib().oracle_verify(_p(a), _p(b), W, H, C.byref(vf), C.byref(mu), C.byref(acc))
+    if rc != 0:
+        raise ValueError(rc)
+    return vf.value, mu.value, bool(acc.value)
+
+
+def bf16(x: float) -> float:
+    return float(lib().oracle_bf16(C.c_float(x)))
+
+
+def mlp_init(seed: int) -> np.ndarray:
+    w = np.zeros(MLP_NPARAM, dtype=np.float32)
+    lib().oracle_mlp_init(C.c_uint64(seed), _p(w))
+    return w
+
+
+def mlp_forward(w: np.ndarray, x: np.ndarray) -> np.ndarray:
+    w = np.ascontiguousarray(w, dtype=np.float32)
+    x = np.ascontiguousarray(x, dtype=np.float32).reshape(-1, 24)
+    z = np.zeros(len(x))
+    assert lib().oracle_mlp_forward(_p(w), _p(x), len(x), _p(z)) == 0
+    return z
+
+
+def mlp_grad(w: np.ndarray, x: np.ndarray, y: np.ndarray):
+    w = np.ascontiguousarray(w, dtype=np.float32)
+    x = np.ascontiguousarray(x, dtype=np.float32).reshape(-1, 24)
+    y = np.ascontiguousarray(y, dtype=np.uint8)
+    g = np.zeros(MLP_NPARAM)
+    loss = C.c_double(0)
+    assert lib().oracle_mlp_grad(_p(w), _p(x), _p(y), len(x), _p(g), C.byref(loss)) == 0
+    return g, loss.value
+
+
+def _forest_features24(self, depth, rgb, K, pix) -> np.ndarray:
+    d = _np(depth).astype(np.uint16, copy=False)
+    c = _np(rgb).astype(np.uint8, copy=False)
+    H, W = d.shape
+    pix = np.ascontiguousarray(pix, dtype=np.int32)
+    out = np.zeros((len(pix), 24), dtype=np.float32)
+    rc = lib().oracle_features24(self._h, _p(d), _p(c), W, H, _p(_K(K)), _p(pix), len(pix), _p(out))
+    if rc != 0:
+        raise ValueError(rc)
+    return out
+
+
+def _forest_label(self, depth, rgb, K, pose, pix) -> np.ndarray:
+    d = _np(depth).astype(np.uint16, copy=False)
+    c = _np(rgb).astype(np.uint8, copy=False)
+    H, W = d.shape
+    pix = np.ascontiguousarray(pix, dtype=np.int32)
+    T = np.ascontiguousarray(pose, dtype=np.float64).reshape(16)
+    out = np.zeros(len(pix), dtype=np.uint8)
+    rc = lib().oracle_label(self._h, _p(d), _p(c), W, H, _p(_K(K)), _p(T), _p(pix), len(pix), _p(out))
+    if rc != 0:
+        raise ValueError(rc)
+    return out
+
+
+Forest.features24 = _forest_features24
+Forest.label = _forest_label
 
 
 def rc_ok(rc: int) -> bool:

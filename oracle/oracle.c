@@ -1161,3 +1161,256 @@ int oracle_pose_success(const double est[16], const double gt[16], double *dt_m,
     if (dang_deg) *dang_deg = ang;
     return (dt <= 0.05 && ang <= 5.0) ? 1 : 0;
 }
+
+/* ------------------------------------------------------------------------ */
+/* depth-difference verification (Sec. 3.3.1, Eqs. 3-4)                    */
+/* ------------------------------------------------------------------------ */
+
+/* Omega is every pixel, Omega_s the pixels where D_s > 0; the proposed pose
+ * is plausible if |Omega_a| / |Omega| > 0.5, and the mean of |D_a - D_b| over
+ * Omega_a intersect Omega_b must be below 5 cm. Sums are exact integers. */
+int oracle_verify(const uint16_t *da, const uint16_t *db, int W, int H, double *valid_frac, double *mu_m,
+                  int *accept)
+{
+    if (!da || !db || W < 1 || H < 1 || !valid_frac || !mu_m || !accept) return ORACLE_E_ARG;
+    size_t P = (size_t)W * H;
+    uint64_t na = 0, nab = 0, sum = 0;
+    for (size_t p = 0; p < P; ++p) {
+        if (da[p] > 0) na++;
+        if (da[p] > 0 && db[p] > 0) {
+            nab++;
+            sum += (uint64_t)(da[p] > db[p] ? da[p] - db[p] : db[p] - da[p]);
+        }
+    }
+    *valid_frac = (double)na / (double)P;
+    *mu_m = nab ? ((double)sum / (double)nab) / 1000.0 : INFINITY;
+    *accept = (*valid_frac > 0.5 && *mu_m < 0.05) ? 1 : 0;
+    return ORACLE_OK;
+}
+
+/* ------------------------------------------------------------------------ */
+/* learned proposal                                                         */
+/* ------------------------------------------------------------------------ */
+
+enum { TAG_MLP_INIT = 5 };
+
+float oracle_bf16(float x)
+{
+    uint32_t b;
+    memcpy(&b, &x, 4);
+    if ((b & 0x7F800000u) == 0x7F800000u) {          /* inf or nan: truncate, keep nan quiet */
+        b &= 0xFFFF0000u;
+        if ((b & 0x007F0000u) == 0 && (x != x)) b |= 0x00400000u;
+    } else {
+        b = (b + 0x7FFFu + ((b >> 16) & 1u)) & 0xFFFF0000u;
+    }
+    float y;
+    memcpy(&y, &b, 4);
+    return y;
+}
+
+/* Per-pixel inputs, in this order:
+ *   0      depth / 5000
+ *   1..8   the 8 extra feature responses: depth ones clamped to +-5000 mm and
+ *          divided by 1000, colour ones divided by 255
+ *   9..20  for the 3 modes of M(p) with the largest weight pi = n / min(k, R)
+ *          (ties: lower (tree, mode)): pi and -log(Sigma^-1_ii) / 10 for
+ *          i = x, y, z; zeros when there are fewer modes
+ *   21     mean reservoir fill: sum over trees of min(k, R) / (T R)
+ *   22, 23 u / W, v / H */
+int oracle_features24(oracle_forest *f, const uint16_t *depth, const uint8_t *rgb, int W, int H, const float K[4],
+                      const int32_t *pix, int n, float *x)
+{
+    if (!frame_args_ok(f, depth, rgb, W, H, K) || (!pix && n > 0) || (!x && n > 0) || n < 0) return ORACLE_E_ARG;
+    frame_ctx fc;
+    make_ctx(f, depth, rgb, W, H, K, &fc);
+    for (int i = 0; i < n; ++i) {
+        float *o = x + (size_t)i * 24;
+        for (int k = 0; k < 24; ++k) o[k] = 0.0f;
+        int p = pix[i];
+        if (p < 0 || p >= W * H) return ORACLE_E_ARG;
+        uint32_t d = depth[p];
+        if (!valid_depth(&f->p, d)) continue;
+        int u = p % W, v = p / W;
+        o[0] = (float)d / 5000.0f;
+        for (int j = 0; j < 8; ++j) {
+            int32_t r = feature(&fc, &f->extra[j], u, v, (int32_t)d);
+            if (f->extra[j].kind == 0) {
+                if (r > 5000) r = 5000;
+                if (r < -5000) r = -5000;
+                o[1 + j] = (float)r / 1000.0f;
+            } else {
+                o[1 + j] = (float)r / 255.0f;
+            }
+        }
+        float best_pi[3] = {-1.0f, -1.0f, -1.0f};
+        const oracle_mode *best_m[3] = {NULL, NULL, NULL};
+        int64_t fill = 0;
+        for (int t = 0; t < f->T; ++t) {
+            int32_t leaf = traverse(f, &fc, t, u, v, (int32_t)d);
+            ensure_modes(f, t, leaf);
+            size_t li = (size_t)t * f->L + leaf;
+            uint32_t k = f->counter[li];
+            uint32_t cap = k < (uint32_t)f->R ? k : (uint32_t)f->R;
+            fill += cap;
+            for (int m = 0; m < f->nmodes[li]; ++m) {
+                const oracle_mode *md = &f->modes[li * f->M + m];
+                float pi = (float)md->n / (float)cap;
+                /* insert keeping the first (lowest (tree, mode)) among equals */
+                for (int s = 0; s < 3; ++s)
+                    if (pi > best_pi[s]) {
+                        for (int q = 2; q > s; --q) { best_pi[q] = best_pi[q - 1]; best_m[q] = best_m[q - 1]; }
+                        best_pi[s] = pi;
+                        best_m[s] = md;
+                        break;
+                    }
+            }
+        }
+        for (int s = 0; s < 3; ++s) {
+            if (!best_m[s]) continue;
+            o[9 + 4 * s] = best_pi[s];
+            o[10 + 4 * s] = -logf(best_m[s]->sinv[0]) / 10.0f;
+            o[11 + 4 * s] = -logf(best_m[s]->sinv[3]) / 10.0f;
+            o[12 + 4 * s] = -logf(best_m[s]->sinv[5]) / 10.0f;
+        }
+        o[21] = (float)fill / (float)((int64_t)f->T * f->R);
+        o[22] = (float)u / (float)W;
+        o[23] = (float)v / (float)H;
+    }
+    return ORACLE_OK;
+}
+
+/* The world point is y = R c + t with the pose rounded to FP32 and the same
+ * fused chain as scoring; a pixel is an inlier (label 1) iff some mode of its
+ * leaves is within 5 cm: (d0 d0 + d1 d1) + d2 d2 <= 0.05^2 in FP32. */
+int oracle_label(oracle_forest *f, const uint16_t *depth, const uint8_t *rgb, int W, int H, const float K[4],
+                 const double pose[16], const int32_t *pix, int n, uint8_t *label)
+{
+    if (!frame_args_ok(f, depth, rgb, W, H, K) || !pose || (!pix && n > 0) || (!label && n > 0) || n < 0)
+        return ORACLE_E_ARG;
+    frame_ctx fc;
+    make_ctx(f, depth, rgb, W, H, K, &fc);
+    float R32[9], t32[3];
+    for (int r = 0; r < 3; ++r) {
+        for (int c = 0; c < 3; ++c) R32[r * 3 + c] = (float)pose[r * 4 + c];
+        t32[r] = (float)pose[r * 4 + 3];
+    }
+    const float lim = 0.05f * 0.05f;
+    for (int i = 0; i < n; ++i) {
+        label[i] = 0;
+        int p = pix[i];
+        if (p < 0 || p >= W * H) return ORACLE_E_ARG;
+        uint32_t d = depth[p];
+        if (!valid_depth(&f->p, d)) continue;
+        int u = p % W, v = p / W;
+        float c[3], y[3];
+        cam_point(u, v, d, K, c);
+        for (int k = 0; k < 3; ++k)
+            y[k] = fmaf(R32[k * 3 + 0], c[0], fmaf(R32[k * 3 + 1], c[1], fmaf(R32[k * 3 + 2], c[2], t32[k])));
+        for (int t = 0; t < f->T && !label[i]; ++t) {
+            int32_t leaf = traverse(f, &fc, t, u, v, (int32_t)d);
+            ensure_modes(f, t, leaf);
+            size_t li = (size_t)t * f->L + leaf;
+            for (int m = 0; m < f->nmodes[li]; ++m) {
+                const oracle_mode *md = &f->modes[li * f->M + m];
+                float d0 = y[0] - md->mu[0], d1 = y[1] - md->mu[1], d2 = y[2] - md->mu[2];
+                if ((d0 * d0 + d1 * d1) + d2 * d2 <= lim) {
+                    label[i] = 1;
+                    break;
+                }
+            }
+        }
+    }
+    return ORACLE_OK;
+}
+
+void oracle_mlp_init(uint64_t seed, float *w)
+{
+    /* Glorot-uniform weights from Philox (key (seed, 5), counter (k, 0, 0, 0)),
+     * zero biases */
+    const int fi[3] = {24, 64, 64}, fo[3] = {64, 64, 1};
+    const int off[3] = {0, 24 * 64 + 64, 24 * 64 + 64 + 64 * 64 + 64};
+    const int cnt[3] = {24 * 64, 64 * 64, 64};
+    for (int k = 0; k < ORACLE_MLP_NPARAM; ++k) w[k] = 0.0f;
+    for (int l = 0; l < 3; ++l) {
+        float a = sqrtf(6.0f / (float)(fi[l] + fo[l]));
+        for (int k = 0; k < cnt[l]; ++k) {
+            uint64_t u[4];
+            draw(seed, TAG_MLP_INIT, (uint64_t)(off[l] + k), 0, 0, 0, u);
+            float r = (float)(u[0] >> 40) / 16777216.0f;
+            w[off[l] + k] = (2.0f * r - 1.0f) * a;
+        }
+    }
+}
+
+#define O_W1 0
+#define O_B1 (24 * 64)
+#define O_W2 (O_B1 + 64)
+#define O_B2 (O_W2 + 64 * 64)
+#define O_W3 (O_B2 + 64)
+#define O_B3 (O_W3 + 64)
+
+/* forward of one row; activations are accumulated in FP64, rounded to FP32
+ * and then to bfloat16 as the GPU stores them */
+static double mlp_row(const float *w, const float *xin, double xb[24], double h1p[64], double h1[64], double h2p[64],
+                      double h2[64])
+{
+    for (int i = 0; i < 24; ++i) xb[i] = oracle_bf16(xin[i]);
+    for (int j = 0; j < 64; ++j) {
+        double a = 0.0;
+        for (int i = 0; i < 24; ++i) a += (double)oracle_bf16(w[O_W1 + j * 24 + i]) * xb[i];
+        a += (double)w[O_B1 + j];
+        h1p[j] = a;
+        h1[j] = a > 0.0 ? (double)oracle_bf16((float)a) : 0.0;
+    }
+    for (int j = 0; j < 64; ++j) {
+        double a = 0.0;
+        for (int i = 0; i < 64; ++i) a += (double)oracle_bf16(w[O_W2 + j * 64 + i]) * h1[i];
+        a += (double)w[O_B2 + j];
+        h2p[j] = a;
+        h2[j] = a > 0.0 ? (double)oracle_bf16((float)a) : 0.0;
+    }
+    double z = 0.0;
+    for (int i = 0; i < 64; ++i) z += (double)oracle_bf16(w[O_W3 + i]) * h2[i];
+    return z + (double)w[O_B3];
+}
+
+int oracle_mlp_forward(const float *w, const float *x, int n, double *z)
+{
+    if (!w || (!x && n > 0) || (!z && n > 0) || n < 0) return ORACLE_E_ARG;
+    double xb[24], h1p[64], h1[64], h2p[64], h2[64];
+    for (int r = 0; r < n; ++r) z[r] = mlp_row(w, x + (size_t)r * 24, xb, h1p, h1, h2p, h2);
+    return ORACLE_OK;
+}
+
+int oracle_mlp_grad(const float *w, const float *x, const uint8_t *y, int n, double *grad, double *loss)
+{
+    if (!w || !x || !y || !grad || !loss || n < 1) return ORACLE_E_ARG;
+    for (int k = 0; k < ORACLE_MLP_NPARAM; ++k) grad[k] = 0.0;
+    double L = 0.0;
+    double xb[24], h1p[64], h1[64], h2p[64], h2[64], d2[64], d1[64];
+    for (int r = 0; r < n; ++r) {
+        double z = mlp_row(w, x + (size_t)r * 24, xb, h1p, h1, h2p, h2);
+        double t = y[r] ? 1.0 : 0.0;
+        L += (z > 0 ? z : 0.0) - z * t + log1p(exp(-fabs(z)));
+        double dz = (1.0 / (1.0 + exp(-z)) - t) / (double)n;
+        for (int i = 0; i < 64; ++i) grad[O_W3 + i] += dz * h2[i];
+        grad[O_B3] += dz;
+        for (int j = 0; j < 64; ++j) d2[j] = h2p[j] > 0.0 ? dz * (double)oracle_bf16(w[O_W3 + j]) : 0.0;
+        for (int j = 0; j < 64; ++j) {
+            for (int i = 0; i < 64; ++i) grad[O_W2 + j * 64 + i] += d2[j] * h1[i];
+            grad[O_B2 + j] += d2[j];
+        }
+        for (int i = 0; i < 64; ++i) {
+            double a = 0.0;
+            for (int j = 0; j < 64; ++j) a += d2[j] * (double)oracle_bf16(w[O_W2 + j * 64 + i]);
+            d1[i] = h1p[i] > 0.0 ? a : 0.0;
+        }
+        for (int j = 0; j < 64; ++j) {
+            for (int i = 0; i < 24; ++i) grad[O_W1 + j * 24 + i] += d1[j] * xb[i];
+            grad[O_B1 + j] += d1[j];
+        }
+    }
+    *loss = L / (double)n;
+    return ORACLE_OK;
+}

@@ -122,6 +122,30 @@ int  oracle_relocalise(oracle_forest *f, const uint16_t *depth, const uint8_t *r
 
 int  oracle_pose_success(const double est[16], const double gt[16], double *dt_m, double *dang_deg);
 
+/* ---- depth-difference verification (Sec. 3.3.1, Eqs. 3-4) ----
+ * valid fraction |Omega_a| / |Omega| of the rendered depth da, and the mean
+ * absolute depth difference over pixels valid (> 0) in both, in metres;
+ * accept iff the fraction exceeds 0.5 and the mean is below 5 cm. */
+int  oracle_verify(const uint16_t *da, const uint16_t *db, int W, int H, double *valid_frac, double *mu_m,
+                   int *accept);
+
+/* ---- learned proposal: a 24-64-64-1 MLP over per-pixel features ---- */
+#define ORACLE_MLP_NPARAM 5825   /* W1[64][24] b1[64] W2[64][64] b2[64] w3[64] b3 */
+float oracle_bf16(float x);      /* round to the nearest bfloat16, ties to even */
+/* 24 features of each listed valid pixel (FP32, before bfloat16 rounding) */
+int  oracle_features24(oracle_forest *f, const uint16_t *depth, const uint8_t *rgb, int W, int H, const float K[4],
+                       const int32_t *pix, int n, float *x /* [n][24] */);
+/* 1 iff some mode of the pixel's leaves lies within 5 cm of its world point
+ * under `pose` (the labeller of the learned proposal) */
+int  oracle_label(oracle_forest *f, const uint16_t *depth, const uint8_t *rgb, int W, int H, const float K[4],
+                  const double pose[16], const int32_t *pix, int n, uint8_t *label);
+void oracle_mlp_init(uint64_t seed, float *w /* [5825] */);
+/* logits of n rows (inputs rounded to bfloat16 here) */
+int  oracle_mlp_forward(const float *w, const float *x, int n, double *z);
+/* mean binary cross-entropy of n rows and its gradient in FP64 */
+int  oracle_mlp_grad(const float *w, const float *x, const uint8_t *y, int n, double *grad /* [5825] */,
+                     double *loss);
+
 #ifdef __cplusplus
 }
 #endif

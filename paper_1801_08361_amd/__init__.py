@@ -117,7 +117,15 @@ _SIGS = {
     "reloc_batch_set_tuning": [C.c_void_p, C.c_int32],
     "reloc_batch_schedule": [C.c_void_p, C.c_char_p, C.c_int32],
     "reloc_batch_memory": [C.c_void_p, C.c_void_p],
+    "reloc_debug_unit_owners": [C.c_int32, C.c_int32, C.c_int32, C.c_void_p],
 }
+
+
+def unit_owners(xcd: int, total: int, grid: int) -> np.ndarray:
+    """Host run of the persistent kernels' work-unit ownership rule."""
+    out = np.zeros(max(total, 1), dtype=np.int32)
+    _check(lib().reloc_debug_unit_owners(int(xcd), int(total), int(grid), out.ctypes.data), "reloc_debug_unit_owners")
+    return out[:total]
 
 
 def lib() -> C.CDLL:

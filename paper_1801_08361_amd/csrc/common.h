@@ -443,23 +443,31 @@ struct Stage {
     int32_t xcd;     // 1: units of each XCD's workgroups are contiguous
 };
 
-// Units walked by this workgroup in a persistent loop
+// Units walked by workgroup `b` of a grid of `g` in a persistent loop
 //   for (u = start; u < end; u += step)
-// Workgroups are dispatched round robin over the 8 XCDs; with xcd set (the
-// grid is then a multiple of 8), XCD x walks the x-th contiguous eighth of
-// the units, so that the units of one attempt share an L2.
+// Workgroups are dispatched round robin over the 8 XCDs; with xcd set and a
+// grid that is a whole multiple of 8, XCD x walks the x-th contiguous eighth
+// of the units, so that the units of one attempt share an L2. Any other grid
+// walks the units round robin. Either way every unit has exactly one owner and
+// step >= 1.
+__host__ __device__ __forceinline__ void unit_range_of(int xcd, int total, unsigned b, unsigned g, int &start,
+                                                       int &end, int &step)
+{
+    if (xcd && g >= 8u && (g % 8u) == 0u) {
+        const int x = (int)(b % 8u), chunk = (total + 7) / 8;
+        start = x * chunk + (int)(b / 8u);
+        end = x * chunk + chunk < total ? x * chunk + chunk : total;
+        step = (int)(g / 8u);
+    } else {
+        start = (int)b;
+        end = total;
+        step = (int)g;
+    }
+}
+
 __device__ __forceinline__ void unit_range(const Stage &S, int &start, int &end, int &step)
 {
-    if (S.xcd) {
-        int x = (int)(blockIdx.x % 8u), chunk = (S.total + 7) / 8;
-        start = x * chunk + (int)(blockIdx.x / 8u);
-        end = min((x + 1) * chunk, S.total);
-        step = (int)(gridDim.x / 8u);
-    } else {
-        start = (int)blockIdx.x;
-        end = S.total;
-        step = (int)gridDim.x;
-    }
+    unit_range_of(S.xcd, S.total, blockIdx.x, gridDim.x, start, end, step);
 }
 
 __device__ __forceinline__ int attempt_of(const Stage &S, int u)

@@ -205,8 +205,8 @@ __global__ void __launch_bounds__(POOL_BLOCK) k_b_pool_write(const Attempt *__re
             off += wcnt[k];
             offw += wsw[k];
         }
-        if (ok) {
-            const int idx = off + __popcll(m & lanemask_lt());
+        const int idx = off + __popcll(m & lanemask_lt());
+        if (ok && idx < A.P) {
             A.pool[idx] = p;
             if (A.weights) A.cdf[idx] = offw + wi;
         }
@@ -868,24 +868,27 @@ static int enqueue(const Plan *pl, const Sched &sc, const Stages &st, hipStream_
 {
     const Attempt *d = pl->d_att;
     const int cap = 4096;
+    // one workgroup per attempt: plain round-robin ownership
+    Stage att = st.att;
+    att.xcd = 0;
     RL_LAUNCH("k_b_leaves", k_b_leaves, dim3(grid_of(st.pix, cap, sc.xcd)), dim3(PIX_BLOCK), 0, s, d, st.pix);
     RL_LAUNCH("k_b_pool_count", k_b_pool_count, dim3(grid_of(st.pb, cap, sc.xcd)), dim3(POOL_BLOCK), 0, s, d, st.pb);
-    RL_LAUNCH("k_b_pool_scan", k_b_pool_scan, dim3(grid_of(st.att, cap, 0)), dim3(1024), 0, s, d, st.att);
+    RL_LAUNCH("k_b_pool_scan", k_b_pool_scan, dim3(grid_of(att, cap, 0)), dim3(1024), 0, s, d, att);
     RL_LAUNCH("k_b_pool_write", k_b_pool_write, dim3(grid_of(st.pb, cap, sc.xcd)), dim3(POOL_BLOCK), 0, s, d, st.pb);
     RL_LAUNCH("k_b_hypgen", k_b_hypgen, dim3(grid_of(st.hyp, 0, sc.xcd)), dim3(64), 0, s, d, st.hyp);
-    RL_LAUNCH("k_b_alive_init", k_b_alive_init, dim3(grid_of(st.att, cap, 0)), dim3(1024), 0, s, d, st.att);
+    RL_LAUNCH("k_b_alive_init", k_b_alive_init, dim3(grid_of(att, cap, 0)), dim3(1024), 0, s, d, att);
     const size_t smem = (size_t)pl->tm_max * SMODE * sizeof(float);
     for (int r = 0; r < pl->rounds; ++r) {
         RL_LAUNCH("k_b_draw", k_b_draw, dim3(grid_of(st.draw, cap, sc.xcd)), dim3(DRAW_BLOCK), 0, s, d, st.draw, r);
         RL_LAUNCH("k_b_score", k_b_score, dim3(grid_of(st.score[r], sc.grid, sc.xcd)), dim3(64), smem, s, d,
                   st.score[r], r, sc.dpu);
-        RL_LAUNCH("k_b_cull", k_b_cull, dim3(grid_of(st.att, cap, 0)), dim3(CULL_THREADS), 0, s, d, st.att, r);
+        RL_LAUNCH("k_b_cull", k_b_cull, dim3(grid_of(att, cap, 0)), dim3(CULL_THREADS), 0, s, d, att, r);
         RL_LAUNCH("k_b_refine_sums", k_b_refine_sums, dim3(grid_of(st.refine[r], 0, sc.xcd)), dim3(64), 0, s, d,
                   st.refine[r], r);
         RL_LAUNCH("k_b_refine_solve", k_b_refine_solve, dim3(grid_of(st.solve[r], 0, sc.xcd)), dim3(64), 0, s, d,
                   st.solve[r], r);
     }
-    RL_LAUNCH("k_b_finish", k_b_finish, dim3(grid_of(st.att, cap, 0)), dim3(64), 0, s, d, st.att);
+    RL_LAUNCH("k_b_finish", k_b_finish, dim3(grid_of(att, cap, 0)), dim3(64), 0, s, d, att);
     RL_HIP(hipGetLastError());
     return RELOC_OK;
 }
@@ -1252,6 +1255,22 @@ extern "C" int reloc_debug_trace(const reloc_forest *f, reloc_trace *tr)
         if (tr->energy)
             RL_HIP(hipMemcpy(tr->energy + (size_t)r * tr->cap_hyp, A.tr_energy + (size_t)r * N, (size_t)nh * 4,
                              hipMemcpyDeviceToHost));
+    }
+    return RELOC_OK;
+}
+
+extern "C" int reloc_debug_unit_owners(int32_t xcd, int32_t total, int32_t grid, int32_t *owners_host)
+{
+    if (!owners_host || total < 0 || grid < 1) return RELOC_E_ARG;
+    for (int u = 0; u < total; ++u) owners_host[u] = 0;
+    for (int b = 0; b < grid; ++b) {
+        int start, end, step;
+        unit_range_of(xcd, total, (unsigned)b, (unsigned)grid, start, end, step);
+        if (step < 1) return RELOC_E_STATE;
+        for (int u = start; u < end; u += step) {
+            if (u < 0 || u >= total) return RELOC_E_STATE;
+            owners_host[u]++;
+        }
     }
     return RELOC_OK;
 }

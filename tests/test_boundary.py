@@ -5,6 +5,7 @@ import ctypes as C
 import os
 import re
 
+import numpy as np
 import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
@@ -67,6 +68,19 @@ def test_argument_errors_without_gpu():
         assert isinstance(rl.status_string(code), str)
     with pytest.raises(rl.RelocError):
         rl._check(-1, "x")
+
+
+@pytest.mark.parametrize("xcd", [0, 1])
+def test_every_work_unit_has_exactly_one_owner(xcd):
+    """The persistent kernels' unit ownership (run here on the host): every
+    unit is processed by exactly one workgroup for any grid, including grids
+    that are not a multiple of 8 under the XCD-contiguous order (a grid of 14
+    once gave two owners to some units)."""
+    import paper_1801_08361_amd as rl
+    for total in (0, 1, 5, 7, 8, 9, 14, 63, 64, 65, 1000, 4097):
+        for grid in (1, 2, 3, 7, 8, 9, 14, 16, 24, 64, 256, 1000, 2048, 4096, 5000):
+            own = rl.unit_owners(xcd, total, grid)
+            assert np.all(own == 1), (xcd, total, grid, own)
 
 
 def test_no_cpu_fallback_when_library_missing(tmp_path, monkeypatch):
