@@ -205,6 +205,79 @@ int reloc_forest_memory(const reloc_forest *f, uint64_t *bytes_out);
 /* A short English description of a status code (static storage). */
 const char *reloc_status_string(int code);
 
+/* ---- verification of a proposed pose (Sec. 3.3.1, Eqs. 3-4) ----
+ * da_dev, db_dev: device depth images [H][W] in mm, da the frame being
+ * relocalised and db a rendering of the scene at the proposed pose; a pixel is
+ * valid in an image when its depth is > 0. valid_frac = (pixels valid in da)
+ * / (W H); mu_m = mean |da - db| over pixels valid in both, in metres
+ * (+inf when there are none); accept = valid_frac > 0.5 and mu_m < 0.05.
+ * Sums are exact integers. Synchronous on `stream`; allocates a 24-byte
+ * device scratch per call. */
+int reloc_verify(const uint16_t *da_dev, const uint16_t *db_dev, int32_t W, int32_t H, double *valid_frac,
+                 double *mu_m, int32_t *accept, void *stream);
+
+/* ---- learned proposal (an extension; the paper picks pixels uniformly) ----
+ * A 24-64-64-1 MLP (ReLU, ReLU, sigmoid) scores each valid pixel of a query
+ * frame with the probability that one of its leaf modes lies within 5 cm of
+ * its world point. floor(sigma 65536) + 1 becomes the pixel's pick weight for
+ * hypothesis generation (reloc_relocalise_ex / reloc_attempt
+ * pixel_weights_dev); scoring and culls stay uniform.
+ *
+ * Parameters: 5825 FP32 values, in this order: W1 [64][24], b1 [64],
+ * W2 [64][64], b2 [64], w3 [64], b3 (rows are output units). The products
+ * run on bfloat16 copies of the inputs, W1, W2, w3 and the hidden
+ * activations (round to nearest even), with FP32 accumulation; biases stay
+ * FP32. Rows of inputs are bfloat16 [n][32], the 24 inputs then 8 zeros,
+ * 16-byte aligned (RELOC_E_ARG otherwise).
+ *
+ * Per-pixel inputs (reloc_pixel_features), zeros for a pixel with invalid
+ * depth: 0 depth / 5000; 1..8 the 8 extra feature responses (depth ones
+ * clamped to +-5000 mm and divided by 1000, colour ones divided by 255);
+ * 9..20 for the 3 modes of the pixel's leaves with the largest weight
+ * pi = n / min(k, R) (ties: lower (tree, mode)): pi, then -log(Sigma^-1_ii) / 10
+ * for i = x, y, z (zeros when there are fewer modes); 21 the mean reservoir
+ * fill sum_t min(k_t, R) / (T R); 22, 23 u / W, v / H. */
+typedef struct reloc_mlp reloc_mlp;
+
+/* Glorot-uniform weights from Philox (key (seed, 5), counter (k, 0, 0, 0),
+ * a = sqrt(6 / (fan_in + fan_out)), w = (2 r - 1) a with r the top 24 bits of
+ * the first output over 2^24), zero biases, zero Adam state. */
+int reloc_mlp_create(uint64_t seed, void *stream, reloc_mlp **out);
+int reloc_mlp_destroy(reloc_mlp *m);
+/* synchronous copies of the 5825 FP32 parameters */
+int reloc_mlp_get_weights(const reloc_mlp *m, float *w_host);
+int reloc_mlp_set_weights(reloc_mlp *m, const float *w_host);
+/* Gradient of the mean logistic loss over n rows (x_dev [n][32] bfloat16,
+ * y_dev [n] uint8 labels 0/1) into grad_host [5825], the mean loss into
+ * *loss_host (may be NULL). Synchronous on `stream`. */
+int reloc_mlp_gradient(reloc_mlp *m, const uint16_t *x_dev, const uint8_t *y_dev, int32_t n, float *grad_host,
+                       float *loss_host, void *stream);
+/* Adam (beta 0.9, 0.999, eps 1e-8, learning rate lr) over `epochs` passes of
+ * max(1, n_rows / batch_rows) minibatches; minibatch s of epoch e draws its
+ * batch_rows rows uniformly with replacement by Philox (key (seed, 6),
+ * counter (e, s, j, 0)). epoch_loss_host[e] (may be NULL) receives the mean
+ * loss of the last minibatch of epoch e. Synchronous when epoch_loss_host is
+ * given, stream-asynchronous otherwise. */
+int reloc_mlp_train(reloc_mlp *m, const uint16_t *x_dev, const uint8_t *y_dev, int32_t n_rows, int32_t epochs,
+                    int32_t batch_rows, float lr, uint64_t seed, float *epoch_loss_host, void *stream);
+/* logits z_dev [n] of rows x_dev [n][32] */
+int reloc_mlp_logits(reloc_mlp *m, const uint16_t *x_dev, int32_t n, float *z_dev, void *stream);
+/* pick weights weights_dev [H*W] (0 for invalid pixels) and, if prob_dev is
+ * not NULL, sigmoid outputs prob_dev [H*W] of every pixel of a query frame */
+int reloc_mlp_pixel_weights(reloc_mlp *m, reloc_forest *f, const uint16_t *depth_dev, const uint8_t *rgb_dev,
+                            const reloc_intrinsics *K, uint32_t *weights_dev, float *prob_dev, void *stream);
+/* inputs of the pixels pix_dev [n] (indices v W + u): bfloat16 rows
+ * x_dev [n][32] and, if xf_dev is not NULL, the FP32 values xf_dev [n][24] */
+int reloc_pixel_features(reloc_forest *f, const uint16_t *depth_dev, const uint8_t *rgb_dev,
+                         const reloc_intrinsics *K, const int32_t *pix_dev, int32_t n, uint16_t *x_dev, float *xf_dev,
+                         void *stream);
+/* training labels: label_dev[i] = 1 iff a mode of pixel pix_dev[i]'s leaves
+ * lies within 5 cm of its world point under pose_c2w (rounded to FP32; the
+ * squared distance is (d0 d0 + d1 d1) + d2 d2 in FP32), else 0 */
+int reloc_label_pixels(reloc_forest *f, const uint16_t *depth_dev, const uint8_t *rgb_dev, const reloc_intrinsics *K,
+                       const double pose_c2w[16], const int32_t *pix_dev, int32_t n, uint8_t *label_dev,
+                       void *stream);
+
 /* ---- per-kernel timing (for measurement; off by default) ----
  * When enabled, every kernel the library launches is bracketed by two HIP
  * events recorded on the stream it is launched on. reloc_profile_read sums
@@ -264,6 +337,11 @@ int reloc_debug_trace(const reloc_forest *f, reloc_trace *tr);
  * stage of `total` units on a grid of `grid` workgroups, owners_host[u] =
  * number of workgroups that process unit u (every entry must be 1). */
 int reloc_debug_unit_owners(int32_t xcd, int32_t total, int32_t grid, int32_t *owners_host);
+
+/* One 16x16 product C = A B on the matrix cores as the MLP kernels issue it
+ * (bfloat16 operands, FP32 accumulation): a_host [16][32] row-major A,
+ * bt_host [16][32] row-major B^T, c_host [16][16] row-major C. Synchronous. */
+int reloc_debug_mfma_probe(const uint16_t *a_host, const uint16_t *bt_host, float *c_host);
 
 #ifdef __cplusplus
 }

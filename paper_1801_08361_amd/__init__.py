@@ -118,7 +118,26 @@ _SIGS = {
     "reloc_batch_schedule": [C.c_void_p, C.c_char_p, C.c_int32],
     "reloc_batch_memory": [C.c_void_p, C.c_void_p],
     "reloc_debug_unit_owners": [C.c_int32, C.c_int32, C.c_int32, C.c_void_p],
+    "reloc_verify": [C.c_void_p, C.c_void_p, C.c_int32, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p,
+                     C.c_void_p],
+    "reloc_mlp_create": [C.c_uint64, C.c_void_p, C.c_void_p],
+    "reloc_mlp_destroy": [C.c_void_p],
+    "reloc_mlp_get_weights": [C.c_void_p, C.c_void_p],
+    "reloc_mlp_set_weights": [C.c_void_p, C.c_void_p],
+    "reloc_mlp_gradient": [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p],
+    "reloc_mlp_train": [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32, C.c_int32, C.c_int32, C.c_float, C.c_uint64,
+                        C.c_void_p, C.c_void_p],
+    "reloc_mlp_logits": [C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p],
+    "reloc_mlp_pixel_weights": [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+                                C.c_void_p],
+    "reloc_pixel_features": [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p,
+                             C.c_void_p, C.c_void_p],
+    "reloc_label_pixels": [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32,
+                           C.c_void_p, C.c_void_p],
+    "reloc_debug_mfma_probe": [C.c_void_p, C.c_void_p, C.c_void_p],
 }
+
+MLP_NPARAM = 5825
 
 
 def unit_owners(xcd: int, total: int, grid: int) -> np.ndarray:
@@ -392,3 +411,147 @@ class Batch:
         res = (reloc_result * n)()
         _check(lib().reloc_relocalise_batch(self._h, arr, n, res, _stream(stream)), "reloc_relocalise_batch")
         return [r.as_dict() for r in res]
+
+
+# -- verification and the learned proposal -------------------------------------
+
+
+def verify(da, db) -> Tuple[float, float, bool]:
+    """Depth-difference verification of a proposed pose (reloc_verify):
+    returns (valid fraction of da, mean |da - db| in metres, accepted)."""
+    import torch
+    for t in (da, db):
+        if not (isinstance(t, torch.Tensor) and t.dtype == torch.uint16 and t.is_cuda and t.is_contiguous()):
+            raise TypeError("depth images must be contiguous uint16 tensors on the GPU")
+    if da.shape != db.shape or da.dim() != 2:
+        raise ValueError("depth images must both be [H, W]")
+    H, W = da.shape
+    vf, mu, acc = C.c_double(0), C.c_double(0), C.c_int32(0)
+    _check(lib().reloc_verify(da.data_ptr(), db.data_ptr(), W, H, C.byref(vf), C.byref(mu), C.byref(acc),
+                              _stream(None)), "reloc_verify")
+    return vf.value, mu.value, bool(acc.value)
+
+
+def _dev_tensor(t, dtype, shape=None):
+    import torch
+    if not (isinstance(t, torch.Tensor) and t.dtype == dtype and t.is_cuda and t.is_contiguous()):
+        raise TypeError(f"expected a contiguous {dtype} tensor on the GPU")
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError(f"expected shape {tuple(shape)}, got {tuple(t.shape)}")
+    return t.data_ptr()
+
+
+def pixel_features(forest: "Forest", depth, rgb, K, pix, with_fp32: bool = False, stream=None):
+    """MLP inputs of the pixels `pix` (int32 GPU tensor of v W + u): bfloat16
+    rows [n, 32] as int16 bit patterns and, optionally, FP32 values [n, 24]."""
+    import torch
+    d, c, k = _frame(depth, rgb, K)
+    n = int(pix.numel())
+    _dev_tensor(pix, torch.int32)
+    x = torch.empty((n, 32), dtype=torch.int16, device=depth.device)
+    xf = torch.empty((n, 24), dtype=torch.float32, device=depth.device) if with_fp32 else None
+    _check(lib().reloc_pixel_features(forest.handle, d, c, C.byref(k), pix.data_ptr(), n, x.data_ptr(),
+                                      xf.data_ptr() if xf is not None else None, _stream(stream)),
+           "reloc_pixel_features")
+    return (x, xf) if with_fp32 else x
+
+
+def label_pixels(forest: "Forest", depth, rgb, K, pose, pix, stream=None):
+    """Inlier labels (uint8 GPU tensor) of the pixels `pix` under `pose`."""
+    import torch
+    d, c, k = _frame(depth, rgb, K)
+    n = int(pix.numel())
+    _dev_tensor(pix, torch.int32)
+    T = _pose(pose)
+    y = torch.empty(n, dtype=torch.uint8, device=depth.device)
+    _check(lib().reloc_label_pixels(forest.handle, d, c, C.byref(k), T.ctypes.data, pix.data_ptr(), n,
+                                    y.data_ptr(), _stream(stream)), "reloc_label_pixels")
+    return y
+
+
+def mfma_probe(a: np.ndarray, bt: np.ndarray) -> np.ndarray:
+    """C = A B of bfloat16 bit patterns a [16, 32] and bt = B^T [16, 32] on the
+    matrix cores (reloc_debug_mfma_probe)."""
+    a = np.ascontiguousarray(a, dtype=np.uint16)
+    bt = np.ascontiguousarray(bt, dtype=np.uint16)
+    assert a.shape == (16, 32) and bt.shape == (16, 32)
+    c = np.zeros((16, 16), dtype=np.float32)
+    _check(lib().reloc_debug_mfma_probe(a.ctypes.data, bt.ctypes.data, c.ctypes.data), "reloc_debug_mfma_probe")
+    return c
+
+
+class Mlp:
+    """The learned proposal network on the GPU (reloc_mlp)."""
+
+    def __init__(self, seed: int, stream=None):
+        self._h = C.c_void_p()
+        _check(lib().reloc_mlp_create(C.c_uint64(seed), _stream(stream), C.byref(self._h)), "reloc_mlp_create")
+
+    @property
+    def handle(self) -> C.c_void_p:
+        return self._h
+
+    def close(self) -> None:
+        if self._h is not None and self._h.value and _lib is not None:
+            _lib.reloc_mlp_destroy(self._h)
+        self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def weights(self) -> np.ndarray:
+        w = np.zeros(MLP_NPARAM, dtype=np.float32)
+        _check(lib().reloc_mlp_get_weights(self._h, w.ctypes.data), "reloc_mlp_get_weights")
+        return w
+
+    def set_weights(self, w: np.ndarray) -> None:
+        w = np.ascontiguousarray(w, dtype=np.float32)
+        assert w.shape == (MLP_NPARAM,)
+        _check(lib().reloc_mlp_set_weights(self._h, w.ctypes.data), "reloc_mlp_set_weights")
+
+    def gradient(self, x, y, stream=None) -> Tuple[np.ndarray, float]:
+        import torch
+        n = int(y.numel())
+        _dev_tensor(x, torch.int16, (n, 32))
+        _dev_tensor(y, torch.uint8)
+        g = np.zeros(MLP_NPARAM, dtype=np.float32)
+        loss = C.c_float(0)
+        _check(lib().reloc_mlp_gradient(self._h, x.data_ptr(), y.data_ptr(), n, g.ctypes.data, C.byref(loss),
+                                        _stream(stream)), "reloc_mlp_gradient")
+        return g, loss.value
+
+    def train(self, x, y, epochs: int, batch_rows: int = 4096, lr: float = 1e-3, seed: int = 0,
+              stream=None) -> np.ndarray:
+        import torch
+        n = int(y.numel())
+        _dev_tensor(x, torch.int16, (n, 32))
+        _dev_tensor(y, torch.uint8)
+        losses = np.zeros(max(epochs, 1), dtype=np.float32)
+        _check(lib().reloc_mlp_train(self._h, x.data_ptr(), y.data_ptr(), n, int(epochs), int(batch_rows),
+                                     C.c_float(lr), C.c_uint64(seed), losses.ctypes.data, _stream(stream)),
+               "reloc_mlp_train")
+        return losses[:epochs]
+
+    def logits(self, x, stream=None):
+        import torch
+        n = int(x.shape[0])
+        _dev_tensor(x, torch.int16, (n, 32))
+        z = torch.empty(n, dtype=torch.float32, device=x.device)
+        _check(lib().reloc_mlp_logits(self._h, x.data_ptr(), n, z.data_ptr(), _stream(stream)), "reloc_mlp_logits")
+        return z
+
+    def pixel_weights(self, forest: "Forest", depth, rgb, K, with_prob: bool = False, stream=None):
+        """Pick weights (int32 GPU tensor [H*W], uint32 values) of every pixel
+        of a query frame, and optionally the sigmoid outputs."""
+        import torch
+        d, c, k = _frame(depth, rgb, K)
+        P = k.width * k.height
+        w = torch.empty(P, dtype=torch.int32, device=depth.device)
+        pr = torch.empty(P, dtype=torch.float32, device=depth.device) if with_prob else None
+        _check(lib().reloc_mlp_pixel_weights(self._h, forest.handle, d, c, C.byref(k), w.data_ptr(),
+                                             pr.data_ptr() if pr is not None else None, _stream(stream)),
+               "reloc_mlp_pixel_weights")
+        return (w, pr) if with_prob else w

@@ -227,6 +227,27 @@ __device__ __forceinline__ void sums_add_point(double s[NSUM], const float c[3],
     s[21] = s[21] + cd[2] * cd[2];
 }
 
+// FP64 reciprocal and reciprocal square root: the hardware estimates refined
+// by two Newton steps each (full precision to within an ulp or two; the
+// Jacobi rotations below only need c^2 + s^2 = 1 to that accuracy)
+__device__ __forceinline__ double rcp_nr(double x)
+{
+    double r = __builtin_amdgcn_rcp(x);
+    double e = fma(-x, r, 1.0);
+    r = fma(r, e, r);
+    e = fma(-x, r, 1.0);
+    return fma(r, e, r);
+}
+
+__device__ __forceinline__ double rsq_nr(double x)
+{
+    double y = __builtin_amdgcn_rsq(x);
+    const double h = 0.5 * x;
+    y = y * fma(-h * y, y, 1.5);
+    y = y * fma(-h * y, y, 1.5);
+    return y;
+}
+
 // largest-eigenvalue eigenvector of a symmetric 4x4 matrix by cyclic Jacobi
 __device__ __forceinline__ void jacobi4_top(double A[16], double q[4])
 {
@@ -248,9 +269,18 @@ __device__ __forceinline__ void jacobi4_top(double A[16], double q[4])
             for (int r = p + 1; r < 4; ++r) {
                 double apq = A[p * 4 + r];
                 if (apq == 0.0) continue;
-                double tau = (A[r * 4 + r] - A[p * 4 + p]) / (2.0 * apq);
-                double t = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
-                double c = 1.0 / sqrt(1.0 + t * t), s = t * c;
+                const double tau = (A[r * 4 + r] - A[p * 4 + p]) * rcp_nr(2.0 * apq);
+                const double at = fabs(tau);
+                // t = sign(tau) / (|tau| + sqrt(1 + tau^2)), ~ 1 / (2 tau) for huge tau
+                double t;
+                if (at < 1e100) {
+                    const double x = fma(tau, tau, 1.0);
+                    t = rcp_nr(at + x * rsq_nr(x));
+                } else {
+                    t = rcp_nr(2.0 * at);
+                }
+                if (tau < 0.0) t = -t;
+                const double c = rsq_nr(fma(t, t, 1.0)), s = t * c;
                 // A <- J^T A J with J the rotation in the (p, r) plane
 #pragma unroll
                 for (int k = 0; k < 4; ++k) {
@@ -421,11 +451,10 @@ struct Attempt {
     int32_t *hyp_try;              // [N]
     float *energy;                 // [N]
     double *sums;                  // [N][NSUM] running inlier sums
-    double *rsums;                 // [N][NSUM] this round's inlier sums
     int32_t *alive;                // [N]
     int32_t *pos;                  // [N] position of a hypothesis in the live list when scored
     float4 *draws;                 // [B] camera point, pixel index bits
-    float *e;                      // [B][N] per-draw energy of each live position
+    float *gs;                     // [ceil(B / GROUP)][N] energy sum of each group of GROUP draws, per live position
     uint16_t *inl;                 // [B][N] best-mode id of an inlier, 0xFFFF otherwise
     unsigned long long *stats;     // [0] mode evaluations [1] pair evaluations [2] round mode count
     int32_t *tr_alive;             // [MAX_ROUNDS][N]

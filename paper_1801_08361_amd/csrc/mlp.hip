@@ -1,15 +1,19 @@
 // Learned proposal on the GPU: a 24-64-64-1 MLP (ReLU, ReLU, sigmoid) that
 // predicts, per pixel, the probability that one of its leaf modes lies within
 // 5 cm of its true world point. Its output becomes integer pick weights for
-// the three pixel picks of every hypothesis try; the uniform preemptive
-// scoring stays the judge.
+// the three pixel picks of every hypothesis try; uniform preemptive scoring
+// stays the judge.
 //
 // Matrix products run on the gfx950 matrix cores (v_mfma_f32_16x16x32_bf16:
 // bfloat16 operands, FP32 accumulation). One wavefront owns a tile of 64 rows:
-// forward (two MFMA layers and a VALU output dot), loss, and backward (the
-// weight-gradient and input-gradient products are MFMA as well), all staged
-// in LDS; per-wavefront gradient partials are summed in a fixed order, then
-// Adam updates the FP32 master weights and refreshes their bfloat16 copies.
+// forward (two MFMA layers and an FP32 output dot), loss, and backward (weight
+// gradients and the hidden-layer input gradient are MFMA as well), staged in
+// LDS; per-tile gradient partials are summed in a fixed order, then Adam
+// updates the FP32 master weights and their bfloat16 copies are refreshed.
+//
+// Also here: the per-pixel inputs, the inlier labeller that trains the MLP
+// from verified poses, and the depth-difference verifier of the paper
+// (Sec. 3.3.1, Eqs. 3-4) that decides which poses count as verified.
 #include <math.h>
 #include <string.h>
 
@@ -34,7 +38,9 @@ constexpr int QW1 = 0, QW2 = 2048, QW2T = 2048 + 4096, QW3 = 2048 + 8192, NQ = 2
 constexpr uint64_t TAG_MLP_INIT = 5, TAG_MLP_BATCH = 6;
 constexpr int ROWS = 64;         // rows per wavefront tile
 
-struct Mlp {
+}  // namespace rl
+
+struct reloc_mlp {
     float *w = nullptr;          // [NP] FP32 master weights
     float *m = nullptr, *v = nullptr;
     float *grad = nullptr;       // [NP + 1]: gradient, then the loss
@@ -46,16 +52,11 @@ struct Mlp {
     int step = 0;
 };
 
-}  // namespace rl
-
-struct reloc_mlp : public rl::Mlp {};
-
 namespace rl {
 
-__host__ __device__ __forceinline__ uint16_t f2bf(float x)
+__device__ __forceinline__ uint16_t f2bf(float x)
 {
-    uint32_t b;
-    memcpy(&b, &x, 4);
+    const uint32_t b = __float_as_uint(x);
     if ((b & 0x7F800000u) == 0x7F800000u) {
         uint16_t h = (uint16_t)(b >> 16);
         if ((b & 0x007FFFFFu) && !(h & 0x7F)) h |= 0x40;
@@ -74,8 +75,8 @@ __device__ __forceinline__ bf16x8 load8(const uint16_t *p)
 
 // 16x16 tile of A (16 rows, K-contiguous, stride lda) times B given as B^T
 // (16 columns, K-contiguous, stride ldb), K a multiple of 32, accumulated into
-// acc. Lane l supplies row / column (l & 15) and k-block 8 (l >> 4); the
-// result holds column (l & 15), rows 4 (l >> 4) + i.
+// acc. Lane l supplies row / column (l & 15) and the k-block 8 (l >> 4) .. +7;
+// the result holds column (l & 15), rows 4 (l >> 4) + i, i < 4.
 __device__ __forceinline__ floatx4 mfma_tile(const uint16_t *A, int lda, const uint16_t *Bt, int ldb, int K,
                                              floatx4 acc)
 {
@@ -88,23 +89,34 @@ __device__ __forceinline__ floatx4 mfma_tile(const uint16_t *A, int lda, const u
     return acc;
 }
 
+// one 16x32 by 32x16 product of host-given tiles (checks the lane layout)
+__global__ void __launch_bounds__(64) k_mfma_probe(const uint16_t *__restrict__ A, const uint16_t *__restrict__ Bt,
+                                                   float *__restrict__ C)
+{
+    floatx4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
+    acc = mfma_tile(A, 32, Bt, 32, 32, acc);
+    const int l = __lane_id();
+    for (int i = 0; i < 4; ++i) C[(4 * (l >> 4) + i) * 16 + (l & 15)] = acc[i];
+}
+
 // ---------------------------------------------------------------------------
 // initialisation and bfloat16 copies
 // ---------------------------------------------------------------------------
 
+// Glorot-uniform weights from Philox (key (seed, 5), counter (k, 0, 0, 0)),
+// zero biases
 __global__ void k_mlp_init(float *__restrict__ w, uint64_t seed)
 {
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= NP) return;
-    int l = -1, o = 0, fi = 0, fo = 0;
-    if (k < OB1) { l = 0; o = OW1; fi = 24; fo = 64; }
-    else if (k >= OW2 && k < OB2) { l = 1; o = OW2; fi = 64; fo = 64; }
-    else if (k >= OW3 && k < OB3) { l = 2; o = OW3; fi = 64; fo = 1; }
-    if (l < 0) {
+    int fi = 0, fo = 0;
+    if (k < OB1) { fi = 24; fo = 64; }
+    else if (k >= OW2 && k < OB2) { fi = 64; fo = 64; }
+    else if (k >= OW3 && k < OB3) { fi = 64; fo = 1; }
+    if (!fi) {
         w[k] = 0.0f;
         return;
     }
-    (void)o;
     const float a = sqrtf(6.0f / (float)(fi + fo));
     const U4 u = philox((uint64_t)k, 0, 0, 0, seed, TAG_MLP_INIT);
     const float r = (float)(u.x[0] >> 40) / 16777216.0f;
@@ -128,22 +140,29 @@ __global__ void k_mlp_pack(const float *__restrict__ w, uint16_t *__restrict__ q
 }
 
 // ---------------------------------------------------------------------------
-// forward of one 64-row tile held in LDS (sX row-major [64][32])
+// one 64-row tile in LDS
 // ---------------------------------------------------------------------------
 
-struct TileLds {
+struct __align__(16) TileLds {
     uint16_t X[ROWS * 32], XT[32 * ROWS];
     uint16_t H1[ROWS * 64], H1T[64 * ROWS];
-    uint16_t H2[ROWS * 64], H2T[64 * ROWS];
+    uint16_t H2[ROWS * 64];
     uint16_t Db[ROWS * 64], DT[64 * ROWS];
-    float D[ROWS * 65];
     float z[ROWS], dz[ROWS];
 };
+
+// X (row-major) -> XT
+__device__ __forceinline__ void tile_transpose_x(TileLds &S)
+{
+    const int l = __lane_id();
+    for (int k = 0; k < 32; ++k) S.XT[k * ROWS + l] = S.X[l * 32 + k];
+    __syncthreads();
+}
 
 __device__ void tile_forward(TileLds &S, const uint16_t *__restrict__ q, const float *__restrict__ w)
 {
     const int l = __lane_id(), col = l & 15, r0 = (l >> 4) * 4;
-    // layer 1: H1 = relu(X W1^T + b1)
+    // layer 1: H1 = relu(X W1^T + b1), stored bfloat16
     for (int ti = 0; ti < 4; ++ti)
         for (int tj = 0; tj < 4; ++tj) {
             floatx4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
@@ -169,68 +188,71 @@ __device__ void tile_forward(TileLds &S, const uint16_t *__restrict__ q, const f
             for (int i = 0; i < 4; ++i) {
                 const int row = 16 * ti + r0 + i;
                 const float hv = acc[i] + b;
-                const uint16_t h = hv > 0.0f ? f2bf(hv) : (uint16_t)0;
-                S.H2[row * 64 + c] = h;
-                S.H2T[c * ROWS + row] = h;
+                S.H2[row * 64 + c] = hv > 0.0f ? f2bf(hv) : (uint16_t)0;
             }
         }
     __syncthreads();
     // output: z = w3 . h2 + b3 (FP32, lane = row)
     float z = 0.0f;
-    for (int j = 0; j < 64; ++j) z = fmaf(bf2f(q[QW3 + j]), bf2f(S.H2T[j * ROWS + l]), z);
+    for (int j = 0; j < 64; ++j) z = fmaf(bf2f(q[QW3 + j]), bf2f(S.H2[l * 64 + j]), z);
     S.z[l] = z + w[OB3];
     __syncthreads();
 }
 
-// backward of the tile: gradient partials (NP values) and the loss sum of the
-// valid rows into `out`; dz = (sigmoid(z) - y) * inv_n
-__device__ void tile_backward(TileLds &S, const uint16_t *__restrict__ q, const uint8_t *yrow, int nvalid,
-                              float inv_n, float *__restrict__ out)
+// column sums of a 4-row-per-lane tile value over the 4 row groups of a wave
+__device__ __forceinline__ float col_sum(float s)
+{
+    s += __shfl_xor(s, 16, 64);
+    s += __shfl_xor(s, 32, 64);
+    return s;
+}
+
+// backward of the tile: gradient partial (NP values) and the loss sum of the
+// valid rows (entry NP) into `out`; dz = (sigmoid(z) - y) * inv_n
+__device__ void tile_backward(TileLds &S, const uint16_t *__restrict__ q, const uint8_t *ys, int nvalid, float inv_n,
+                              float *__restrict__ out)
 {
     const int l = __lane_id(), col = l & 15, r0 = (l >> 4) * 4;
     {
         const float z = S.z[l];
         float dz = 0.0f, loss = 0.0f;
         if (l < nvalid) {
-            const float y = yrow[l] ? 1.0f : 0.0f;
+            const float y = ys[l] ? 1.0f : 0.0f;
             dz = (1.0f / (1.0f + expf(-z)) - y) * inv_n;
             loss = fmaxf(z, 0.0f) - z * y + log1pf(expf(-fabsf(z)));
         }
         S.dz[l] = dz;
-        // loss of the tile: wave sum in lane order
         for (int o = 32; o >= 1; o >>= 1) loss += __shfl_xor(loss, o, 64);
         if (l == 0) out[NP] = loss;
     }
     __syncthreads();
-    // dw3[j] = sum_rows dz h2, db3 = sum dz (lane = j)
-    {
-        float g = 0.0f;
-        for (int row = 0; row < ROWS; ++row) g = fmaf(S.dz[row], bf2f(S.H2[row * 64 + l]), g);
+    {   // dw3[j] = sum_rows dz h2 (lane = j), db3 = sum dz
+        float g = 0.0f, b = 0.0f;
+        for (int row = 0; row < ROWS; ++row) {
+            g = fmaf(S.dz[row], bf2f(S.H2[row * 64 + l]), g);
+            b += S.dz[row];
+        }
         out[OW3 + l] = g;
-        float b = 0.0f;
-        for (int row = 0; row < ROWS; ++row) b += S.dz[row];
         if (l == 0) out[OB3] = b;
     }
-    // dH2 = dz w3 [h2 > 0]
-    for (int ti = 0; ti < 4; ++ti)
-        for (int tj = 0; tj < 4; ++tj) {
-            const int c = 16 * tj + col;
-            const float w3 = bf2f(q[QW3 + c]);
+    // dH2 = dz w3 [h2 > 0]; db2 = column sums
+    for (int tj = 0; tj < 4; ++tj) {
+        const int c = 16 * tj + col;
+        const float w3 = bf2f(q[QW3 + c]);
+        float bs = 0.0f;
+        for (int ti = 0; ti < 4; ++ti)
             for (int i = 0; i < 4; ++i) {
                 const int row = 16 * ti + r0 + i;
                 const float d = S.H2[row * 64 + c] ? S.dz[row] * w3 : 0.0f;
-                S.D[row * 65 + c] = d;
+                bs += d;
                 const uint16_t h = f2bf(d);
                 S.Db[row * 64 + c] = h;
                 S.DT[c * ROWS + row] = h;
             }
-        }
-    __syncthreads();
-    {   // db2 (lane = output unit)
-        float b = 0.0f;
-        for (int row = 0; row < ROWS; ++row) b += S.D[row * 65 + l];
-        out[OB2 + l] = b;
+        bs = col_sum(bs);
+        if (l < 16) out[OB2 + c] = bs;
     }
+    __syncthreads();
     // dW2 = dH2^T H1
     for (int ti = 0; ti < 4; ++ti)
         for (int tj = 0; tj < 4; ++tj) {
@@ -239,25 +261,27 @@ __device__ void tile_backward(TileLds &S, const uint16_t *__restrict__ q, const 
             for (int i = 0; i < 4; ++i) out[OW2 + (16 * ti + r0 + i) * 64 + 16 * tj + col] = acc[i];
         }
     __syncthreads();
-    // dH1 = dH2 W2 [h1 > 0]
-    for (int ti = 0; ti < 4; ++ti)
-        for (int tj = 0; tj < 4; ++tj) {
-            floatx4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
-            acc = mfma_tile(S.Db + 16 * ti * 64, 64, q + QW2T + 16 * tj * 64, 64, 64, acc);
-            const int c = 16 * tj + col;
+    // dH1 = dH2 W2 [h1 > 0] (into DT, transposed); db1 = column sums
+    for (int tj = 0; tj < 4; ++tj) {
+        const int c = 16 * tj + col;
+        float bs = 0.0f;
+        floatx4 acc[4];
+        for (int ti = 0; ti < 4; ++ti) {
+            floatx4 a0 = {0.0f, 0.0f, 0.0f, 0.0f};
+            acc[ti] = mfma_tile(S.Db + 16 * ti * 64, 64, q + QW2T + 16 * tj * 64, 64, 64, a0);
+        }
+        __syncthreads();
+        for (int ti = 0; ti < 4; ++ti)
             for (int i = 0; i < 4; ++i) {
                 const int row = 16 * ti + r0 + i;
-                const float d = S.H1[row * 64 + c] ? acc[i] : 0.0f;
-                S.D[row * 65 + c] = d;
+                const float d = S.H1[row * 64 + c] ? acc[ti][i] : 0.0f;
+                bs += d;
                 S.DT[c * ROWS + row] = f2bf(d);
             }
-        }
-    __syncthreads();
-    {   // db1
-        float b = 0.0f;
-        for (int row = 0; row < ROWS; ++row) b += S.D[row * 65 + l];
-        out[OB1 + l] = b;
+        bs = col_sum(bs);
+        if (l < 16) out[OB1 + c] = bs;
     }
+    __syncthreads();
     // dW1 = dH1^T X (input columns 24..31 are padding)
     for (int ti = 0; ti < 4; ++ti)
         for (int tj = 0; tj < 2; ++tj) {
@@ -270,23 +294,21 @@ __device__ void tile_backward(TileLds &S, const uint16_t *__restrict__ q, const 
     __syncthreads();
 }
 
-// loads rows (row indices, or r0 + t when idx is null) into the tile
+// rows r0.. of X (or the rows listed in idx) into the tile
 __device__ void tile_load(TileLds &S, const uint16_t *__restrict__ X, const int32_t *__restrict__ idx, int r0, int n)
 {
     const int l = __lane_id();
     const int row = r0 + l;
+    uint4 *d = (uint4 *)(S.X + l * 32);
     if (row < n) {
         const int64_t src = idx ? idx[row] : row;
         const uint4 *s = (const uint4 *)(X + src * 32);
-        uint4 *d = (uint4 *)(S.X + l * 32);
         for (int k = 0; k < 4; ++k) d[k] = s[k];
     } else {
-        uint4 *d = (uint4 *)(S.X + l * 32);
         for (int k = 0; k < 4; ++k) d[k] = make_uint4(0, 0, 0, 0);
     }
     __syncthreads();
-    for (int k = 0; k < 32; ++k) S.XT[k * ROWS + l] = S.X[l * 32 + k];
-    __syncthreads();
+    tile_transpose_x(S);
 }
 
 __global__ void __launch_bounds__(64) k_mlp_fwd_bwd(const uint16_t *__restrict__ X, const uint8_t *__restrict__ Y,
@@ -300,11 +322,12 @@ __global__ void __launch_bounds__(64) k_mlp_fwd_bwd(const uint16_t *__restrict__
     tile_load(S, X, idx, r0, n);
     const int row = r0 + l;
     ys[l] = row < n ? Y[idx ? idx[row] : row] : 0;
+    __syncthreads();
     tile_forward(S, q, w);
     tile_backward(S, q, ys, min(ROWS, n - r0), inv_n, partial + (int64_t)tile * (NP + 1));
 }
 
-// fixed-order sum of the tile partials
+// fixed-order sum of the tile partials (gradient and loss)
 __global__ void k_mlp_reduce(const float *__restrict__ partial, int tiles, float *__restrict__ grad)
 {
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
@@ -315,15 +338,10 @@ __global__ void k_mlp_reduce(const float *__restrict__ partial, int tiles, float
 }
 
 __global__ void k_mlp_adam(float *__restrict__ w, float *__restrict__ m, float *__restrict__ v,
-                           const float *__restrict__ grad, float lr, float c1, float c2, int clear)
+                           const float *__restrict__ grad, float lr, float c1, float c2)
 {
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= NP) return;
-    if (clear) {
-        m[k] = 0.0f;
-        v[k] = 0.0f;
-        return;
-    }
     const float g = grad[k];
     const float mk = 0.9f * m[k] + 0.1f * g;
     const float vk = 0.999f * v[k] + 0.001f * g * g;
@@ -332,7 +350,8 @@ __global__ void k_mlp_adam(float *__restrict__ w, float *__restrict__ m, float *
     w[k] -= lr * (mk / c1) / (sqrtf(vk / c2) + 1e-8f);
 }
 
-// minibatch rows of step s: uniform with replacement from Philox
+// rows of minibatch `step` of `epoch`: uniform with replacement (Philox key
+// (seed, 6), counter (epoch, step, j, 0))
 __global__ void k_mlp_rows(int32_t *__restrict__ rows, int nb, int n_rows, uint64_t seed, int epoch, int step)
 {
     const int j = blockIdx.x * blockDim.x + threadIdx.x;
@@ -353,7 +372,7 @@ __global__ void __launch_bounds__(64) k_mlp_logits(const uint16_t *__restrict__ 
 }
 
 // ---------------------------------------------------------------------------
-// per-pixel features (the MLP input)
+// per-pixel inputs, labels, verification
 // ---------------------------------------------------------------------------
 
 struct FeatArgs {
@@ -365,10 +384,10 @@ struct FeatArgs {
     int T, L, M, R;
 };
 
-// The 24 inputs of one valid pixel, FP32, in the order and with the scales
-// documented in the oracle (depth / 5000; the 8 extra responses; pi and
-// -log(Sigma^-1_ii) / 10 of the 3 heaviest modes; mean reservoir fill; u / W,
-// v / H).
+// The 24 inputs of one pixel (zeros for an invalid one), FP32: depth / 5000;
+// the 8 extra responses (depth clamped to +-5000 mm over 1000, colour over
+// 255); pi = n / min(k, R) and -log(Sigma^-1_ii) / 10 of the 3 heaviest modes
+// of M(p) (ties: lower (tree, mode)); mean reservoir fill; u / W, v / H.
 __device__ void pixel_features(const FeatArgs &A, int p, float x[24])
 {
     for (int k = 0; k < 24; ++k) x[k] = 0.0f;
@@ -429,17 +448,56 @@ __global__ void k_pixel_features(FeatArgs A, const int32_t *__restrict__ pix, in
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
+    const int p = pix[i];
     float x[24];
-    pixel_features(A, pix[i], x);
+    if (p >= 0 && p < A.fr.W * A.fr.H) pixel_features(A, p, x);
+    else
+        for (int k = 0; k < 24; ++k) x[k] = 0.0f;
     for (int k = 0; k < 32; ++k) X[(int64_t)i * 32 + k] = k < 24 ? f2bf(x[k]) : (uint16_t)0;
     if (XF)
         for (int k = 0; k < 24; ++k) XF[(int64_t)i * 24 + k] = x[k];
 }
 
-// inlier labels of listed pixels under a pose (FP32, the scoring transform)
-__global__ void k_label(FeatArgs A, Pose32Args pose, const int32_t *__restrict__ pix, int n, uint8_t *__restrict__ lab);
+struct PoseF {
+    float R[9], t[3];
+};
 
-// every pixel of a frame: features, forward, pick weight floor(sigma 65536) + 1
+// 1 iff a mode of the pixel's leaves lies within 5 cm of y = R c + t (FP32,
+// the scoring transform)
+__global__ void k_label(FeatArgs A, PoseF P, const int32_t *__restrict__ pix, int n, uint8_t *__restrict__ lab)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int p = pix[i];
+    uint8_t out = 0;
+    if (p >= 0 && p < A.fr.W * A.fr.H) {
+        const uint32_t d = A.fr.depth[p];
+        if (valid_depth(A.fr, d)) {
+            const int u = p % A.fr.W, v = p / A.fr.W;
+            float c[3];
+            cam_point(A.fr, u, v, d, c);
+            float y[3];
+            for (int k = 0; k < 3; ++k)
+                y[k] = fmaf(P.R[k * 3 + 0], c[0], fmaf(P.R[k * 3 + 1], c[1], fmaf(P.R[k * 3 + 2], c[2], P.t[k])));
+            const float lim = 0.05f * 0.05f;
+            for (int t = 0; t < A.T && !out; ++t) {
+                const int32_t leaf = traverse(A.nodes + (int64_t)t * (A.L - 1), A.L, A.fr, u, v, (int32_t)d);
+                const int64_t li = (int64_t)t * A.L + leaf;
+                for (int m = 0; m < A.nmodes[li]; ++m) {
+                    const Mode &md = A.modes[li * A.M + m];
+                    const float d0 = y[0] - md.mu[0], d1 = y[1] - md.mu[1], d2 = y[2] - md.mu[2];
+                    if ((d0 * d0 + d1 * d1) + d2 * d2 <= lim) {
+                        out = 1;
+                        break;
+                    }
+                }
+            }
+        }
+    }
+    lab[i] = out;
+}
+
+// every pixel of a frame: inputs, forward, pick weight floor(sigma 65536) + 1
 // for valid pixels, 0 otherwise
 __global__ void __launch_bounds__(64) k_mlp_pixels(FeatArgs A, const uint16_t *__restrict__ q,
                                                    const float *__restrict__ w, uint32_t *__restrict__ weights,
@@ -455,8 +513,7 @@ __global__ void __launch_bounds__(64) k_mlp_pixels(FeatArgs A, const uint16_t *_
         for (int k = 0; k < 24; ++k) x[k] = 0.0f;
     for (int k = 0; k < 32; ++k) S.X[l * 32 + k] = k < 24 ? f2bf(x[k]) : (uint16_t)0;
     __syncthreads();
-    for (int k = 0; k < 32; ++k) S.XT[k * ROWS + l] = S.X[l * 32 + k];
-    __syncthreads();
+    tile_transpose_x(S);
     tile_forward(S, q, w);
     if (p < P) {
         const bool ok = valid_depth(A.fr, A.fr.depth[p]);
@@ -466,4 +523,331 @@ __global__ void __launch_bounds__(64) k_mlp_pixels(FeatArgs A, const uint16_t *_
     }
 }
 
+// Eqs. 3-4: counts of pixels valid in da and in both, and the integer sum of
+// |da - db| over pixels valid in both
+__global__ void k_verify(const uint16_t *__restrict__ da, const uint16_t *__restrict__ db, int P,
+                         unsigned long long *__restrict__ acc)
+{
+    unsigned long long na = 0, nab = 0, sum = 0;
+    for (int p = blockIdx.x * blockDim.x + threadIdx.x; p < P; p += gridDim.x * blockDim.x) {
+        const uint32_t a = da[p], b = db[p];
+        na += a > 0u;
+        if (a > 0u && b > 0u) {
+            nab++;
+            sum += a > b ? a - b : b - a;
+        }
+    }
+    for (int o = 32; o >= 1; o >>= 1) {
+        na += __shfl_xor(na, o, 64);
+        nab += __shfl_xor(nab, o, 64);
+        sum += __shfl_xor(sum, o, 64);
+    }
+    if (__lane_id() == 0) {
+        atomicAdd(&acc[0], na);
+        atomicAdd(&acc[1], nab);
+        atomicAdd(&acc[2], sum);
+    }
+}
+
+__global__ void k_zero_u64(unsigned long long *p, int n)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0ull;
+}
+
+static FeatArgs feat_args(const Forest *f, const Frame &fr)
+{
+    FeatArgs A;
+    A.fr = fr;
+    A.nodes = f->nodes;
+    A.nmodes = f->nmodes;
+    A.modes = f->modes;
+    A.counter = f->counter;
+    A.T = f->T; A.L = f->L; A.M = f->M; A.R = f->R;
+    return A;
+}
+
+static int ensure_tiles(reloc_mlp *m, int tiles)
+{
+    if (tiles <= m->cap_tiles) return RELOC_OK;
+    if (m->partial) (void)hipFree(m->partial);
+    m->partial = nullptr;
+    m->cap_tiles = 0;
+    RL_HIP(hipMalloc((void **)&m->partial, (size_t)tiles * (NP + 1) * sizeof(float)));
+    m->cap_tiles = tiles;
+    return RELOC_OK;
+}
+
+static int ensure_rows(reloc_mlp *m, int n)
+{
+    if (n <= m->cap_rows) return RELOC_OK;
+    if (m->rows) (void)hipFree(m->rows);
+    m->rows = nullptr;
+    m->cap_rows = 0;
+    RL_HIP(hipMalloc((void **)&m->rows, (size_t)n * sizeof(int32_t)));
+    m->cap_rows = n;
+    return RELOC_OK;
+}
+
+// gradient of the mean loss over rows (idx or 0..n-1) into m->grad
+static int mlp_gradient(reloc_mlp *m, const uint16_t *X, const uint8_t *Y, const int32_t *idx, int n, hipStream_t s)
+{
+    const int tiles = (n + ROWS - 1) / ROWS;
+    int rc = ensure_tiles(m, tiles);
+    if (rc) return rc;
+    RL_LAUNCH("k_mlp_fwd_bwd", k_mlp_fwd_bwd, dim3(tiles), dim3(64), 0, s, X, Y, idx, n, 1.0f / (float)n, m->q, m->w,
+              m->partial);
+    RL_LAUNCH("k_mlp_reduce", k_mlp_reduce, dim3((NP + 1 + 255) / 256), dim3(256), 0, s, m->partial, tiles, m->grad);
+    RL_HIP(hipGetLastError());
+    return RELOC_OK;
+}
+
+static int mlp_pack(reloc_mlp *m, hipStream_t s)
+{
+    RL_LAUNCH("k_mlp_pack", k_mlp_pack, dim3(16), dim3(256), 0, s, m->w, m->q);
+    RL_HIP(hipGetLastError());
+    return RELOC_OK;
+}
+
 }  // namespace rl
+
+using namespace rl;
+
+// ---------------------------------------------------------------------------
+// C ABI
+// ---------------------------------------------------------------------------
+
+static void mlp_free(reloc_mlp *m)
+{
+    (void)hipFree(m->w);
+    (void)hipFree(m->m);
+    (void)hipFree(m->v);
+    (void)hipFree(m->grad);
+    (void)hipFree(m->partial);
+    (void)hipFree(m->q);
+    (void)hipFree(m->rows);
+}
+
+extern "C" int reloc_mlp_create(uint64_t seed, void *stream, reloc_mlp **out)
+{
+    if (!out) return RELOC_E_ARG;
+    *out = nullptr;
+    hipStream_t s = (hipStream_t)stream;
+    reloc_mlp *m = new (std::nothrow) reloc_mlp();
+    if (!m) return RELOC_E_NOMEM;
+    if (hipMalloc((void **)&m->w, NP * 4) != hipSuccess || hipMalloc((void **)&m->m, NP * 4) != hipSuccess ||
+        hipMalloc((void **)&m->v, NP * 4) != hipSuccess || hipMalloc((void **)&m->grad, (NP + 1) * 4) != hipSuccess ||
+        hipMalloc((void **)&m->q, NQ * 2) != hipSuccess) {
+        mlp_free(m);
+        delete m;
+        return RELOC_E_NOMEM;
+    }
+    if (hipMemsetAsync(m->m, 0, NP * 4, s) != hipSuccess || hipMemsetAsync(m->v, 0, NP * 4, s) != hipSuccess) {
+        mlp_free(m);
+        delete m;
+        return RELOC_E_HIP;
+    }
+    RL_LAUNCH("k_mlp_init", k_mlp_init, dim3((NP + 255) / 256), dim3(256), 0, s, m->w, seed);
+    if (mlp_pack(m, s)) {
+        mlp_free(m);
+        delete m;
+        return RELOC_E_HIP;
+    }
+    *out = m;
+    return RELOC_OK;
+}
+
+extern "C" int reloc_mlp_destroy(reloc_mlp *m)
+{
+    if (!m) return RELOC_E_ARG;
+    (void)hipDeviceSynchronize();
+    mlp_free(m);
+    delete m;
+    return RELOC_OK;
+}
+
+extern "C" int reloc_mlp_get_weights(const reloc_mlp *m, float *w_host)
+{
+    if (!m || !w_host) return RELOC_E_ARG;
+    RL_HIP(hipDeviceSynchronize());
+    RL_HIP(hipMemcpy(w_host, m->w, NP * 4, hipMemcpyDeviceToHost));
+    return RELOC_OK;
+}
+
+extern "C" int reloc_mlp_set_weights(reloc_mlp *m, const float *w_host)
+{
+    if (!m || !w_host) return RELOC_E_ARG;
+    RL_HIP(hipDeviceSynchronize());
+    RL_HIP(hipMemcpy(m->w, w_host, NP * 4, hipMemcpyHostToDevice));
+    int rc = mlp_pack(m, 0);
+    if (rc) return rc;
+    RL_HIP(hipDeviceSynchronize());
+    return RELOC_OK;
+}
+
+extern "C" int reloc_mlp_gradient(reloc_mlp *m, const uint16_t *x_dev, const uint8_t *y_dev, int32_t n,
+                                  float *grad_host, float *loss_host, void *stream)
+{
+    if (!m || !x_dev || !y_dev || n < 1 || !grad_host || ((uintptr_t)x_dev & 15)) return RELOC_E_ARG;
+    hipStream_t s = (hipStream_t)stream;
+    int rc = mlp_gradient(m, x_dev, y_dev, nullptr, n, s);
+    if (rc) return rc;
+    std::vector<float> g(NP + 1);
+    RL_HIP(hipMemcpyAsync(g.data(), m->grad, (NP + 1) * 4, hipMemcpyDeviceToHost, s));
+    RL_HIP(hipStreamSynchronize(s));
+    memcpy(grad_host, g.data(), NP * 4);
+    if (loss_host) *loss_host = g[NP] / (float)n;
+    return RELOC_OK;
+}
+
+extern "C" int reloc_mlp_train(reloc_mlp *m, const uint16_t *x_dev, const uint8_t *y_dev, int32_t n_rows,
+                               int32_t epochs, int32_t batch_rows, float lr, uint64_t seed, float *epoch_loss_host,
+                               void *stream)
+{
+    if (!m || !x_dev || !y_dev || n_rows < 1 || epochs < 0 || batch_rows < 1 || !(lr > 0.0f) ||
+        ((uintptr_t)x_dev & 15))
+        return RELOC_E_ARG;
+    hipStream_t s = (hipStream_t)stream;
+    int rc = ensure_rows(m, batch_rows);
+    if (rc) return rc;
+    const int steps = std::max(1, n_rows / batch_rows);
+    std::vector<float> g(NP + 1);
+    for (int e = 0; e < epochs; ++e) {
+        double loss = 0.0;
+        for (int st = 0; st < steps; ++st) {
+            RL_LAUNCH("k_mlp_rows", k_mlp_rows, dim3((batch_rows + 255) / 256), dim3(256), 0, s, m->rows, batch_rows,
+                      n_rows, seed, e, st);
+            rc = mlp_gradient(m, x_dev, y_dev, m->rows, batch_rows, s);
+            if (rc) return rc;
+            m->step++;
+            const float c1 = 1.0f - powf(0.9f, (float)m->step), c2 = 1.0f - powf(0.999f, (float)m->step);
+            RL_LAUNCH("k_mlp_adam", k_mlp_adam, dim3((NP + 255) / 256), dim3(256), 0, s, m->w, m->m, m->v, m->grad, lr,
+                      c1, c2);
+            rc = mlp_pack(m, s);
+            if (rc) return rc;
+            if (epoch_loss_host && st == steps - 1) {
+                RL_HIP(hipMemcpyAsync(g.data(), m->grad, (NP + 1) * 4, hipMemcpyDeviceToHost, s));
+                RL_HIP(hipStreamSynchronize(s));
+                loss = g[NP] / (double)batch_rows;
+            }
+        }
+        if (epoch_loss_host) epoch_loss_host[e] = (float)loss;
+    }
+    RL_HIP(hipGetLastError());
+    return RELOC_OK;
+}
+
+extern "C" int reloc_mlp_logits(reloc_mlp *m, const uint16_t *x_dev, int32_t n, float *z_dev, void *stream)
+{
+    if (!m || !x_dev || !z_dev || n < 1 || ((uintptr_t)x_dev & 15)) return RELOC_E_ARG;
+    RL_LAUNCH("k_mlp_logits", k_mlp_logits, dim3((n + ROWS - 1) / ROWS), dim3(64), 0, (hipStream_t)stream, x_dev, n,
+              m->q, m->w, z_dev);
+    RL_HIP(hipGetLastError());
+    return RELOC_OK;
+}
+
+extern "C" int reloc_mlp_pixel_weights(reloc_mlp *m, reloc_forest *f, const uint16_t *depth_dev,
+                                       const uint8_t *rgb_dev, const reloc_intrinsics *K, uint32_t *weights_dev,
+                                       float *prob_dev, void *stream)
+{
+    if (!m || !f || !weights_dev) return RELOC_E_ARG;
+    Frame fr;
+    int rc = frame_from(f, depth_dev, rgb_dev, K, fr);
+    if (rc) return rc;
+    hipStream_t s = (hipStream_t)stream;
+    rc = update_modes(f, s);
+    if (rc) return rc;
+    const int P = fr.W * fr.H;
+    RL_LAUNCH("k_mlp_pixels", k_mlp_pixels, dim3((P + ROWS - 1) / ROWS), dim3(64), 0, s, feat_args(f, fr), m->q, m->w,
+              weights_dev, prob_dev);
+    RL_HIP(hipGetLastError());
+    return RELOC_OK;
+}
+
+extern "C" int reloc_pixel_features(reloc_forest *f, const uint16_t *depth_dev, const uint8_t *rgb_dev,
+                                    const reloc_intrinsics *K, const int32_t *pix_dev, int32_t n, uint16_t *x_dev,
+                                    float *xf_dev, void *stream)
+{
+    if (!f || n < 0 || (n > 0 && (!pix_dev || !x_dev))) return RELOC_E_ARG;
+    Frame fr;
+    int rc = frame_from(f, depth_dev, rgb_dev, K, fr);
+    if (rc) return rc;
+    hipStream_t s = (hipStream_t)stream;
+    rc = update_modes(f, s);
+    if (rc) return rc;
+    if (n == 0) return RELOC_OK;
+    RL_LAUNCH("k_pixel_features", k_pixel_features, dim3((n + 127) / 128), dim3(128), 0, s, feat_args(f, fr), pix_dev,
+              n, x_dev, xf_dev);
+    RL_HIP(hipGetLastError());
+    return RELOC_OK;
+}
+
+extern "C" int reloc_label_pixels(reloc_forest *f, const uint16_t *depth_dev, const uint8_t *rgb_dev,
+                                  const reloc_intrinsics *K, const double pose_c2w[16], const int32_t *pix_dev,
+                                  int32_t n, uint8_t *label_dev, void *stream)
+{
+    if (!f || !pose_c2w || n < 0 || (n > 0 && (!pix_dev || !label_dev))) return RELOC_E_ARG;
+    Frame fr;
+    int rc = frame_from(f, depth_dev, rgb_dev, K, fr);
+    if (rc) return rc;
+    hipStream_t s = (hipStream_t)stream;
+    rc = update_modes(f, s);
+    if (rc) return rc;
+    if (n == 0) return RELOC_OK;
+    PoseF P;
+    for (int r = 0; r < 3; ++r) {
+        for (int c = 0; c < 3; ++c) P.R[r * 3 + c] = (float)pose_c2w[r * 4 + c];
+        P.t[r] = (float)pose_c2w[r * 4 + 3];
+    }
+    RL_LAUNCH("k_label", k_label, dim3((n + 127) / 128), dim3(128), 0, s, feat_args(f, fr), P, pix_dev, n, label_dev);
+    RL_HIP(hipGetLastError());
+    return RELOC_OK;
+}
+
+extern "C" int reloc_verify(const uint16_t *da_dev, const uint16_t *db_dev, int32_t W, int32_t H, double *valid_frac,
+                            double *mu_m, int32_t *accept, void *stream)
+{
+    if (!da_dev || !db_dev || W < 1 || H < 1 || !valid_frac || !mu_m || !accept) return RELOC_E_ARG;
+    hipStream_t s = (hipStream_t)stream;
+    unsigned long long *acc = nullptr;
+    RL_HIP(hipMalloc((void **)&acc, 3 * sizeof(unsigned long long)));
+    const int P = W * H;
+    RL_LAUNCH("k_zero_u64", k_zero_u64, dim3(1), dim3(64), 0, s, acc, 3);
+    RL_LAUNCH("k_verify", k_verify, dim3((unsigned)std::min((P + 255) / 256, 1024)), dim3(256), 0, s, da_dev, db_dev,
+              P, acc);
+    unsigned long long h[3] = {0, 0, 0};
+    hipError_t e = hipMemcpyAsync(h, acc, sizeof(h), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    (void)hipFree(acc);
+    RL_HIP(e);
+    *valid_frac = (double)h[0] / (double)P;
+    *mu_m = h[1] ? ((double)h[2] / (double)h[1]) / 1000.0 : INFINITY;
+    *accept = (*valid_frac > 0.5 && *mu_m < 0.05) ? 1 : 0;
+    return RELOC_OK;
+}
+
+extern "C" int reloc_debug_mfma_probe(const uint16_t *a_host, const uint16_t *bt_host, float *c_host)
+{
+    if (!a_host || !bt_host || !c_host) return RELOC_E_ARG;
+    uint16_t *a = nullptr, *b = nullptr;
+    float *c = nullptr;
+    if (hipMalloc((void **)&a, 16 * 32 * 2) != hipSuccess) return RELOC_E_NOMEM;
+    if (hipMalloc((void **)&b, 16 * 32 * 2) != hipSuccess || hipMalloc((void **)&c, 256 * 4) != hipSuccess) {
+        (void)hipFree(a);
+        (void)hipFree(b);
+        return RELOC_E_NOMEM;
+    }
+    int rc = RELOC_OK;
+    if (hipMemcpy(a, a_host, 16 * 32 * 2, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(b, bt_host, 16 * 32 * 2, hipMemcpyHostToDevice) != hipSuccess)
+        rc = RELOC_E_HIP;
+    if (!rc) {
+        hipLaunchKernelGGL(k_mfma_probe, dim3(1), dim3(64), 0, 0, a, b, c);
+        if (hipDeviceSynchronize() != hipSuccess || hipMemcpy(c_host, c, 256 * 4, hipMemcpyDeviceToHost) != hipSuccess)
+            rc = RELOC_E_HIP;
+    }
+    (void)hipFree(a);
+    (void)hipFree(b);
+    (void)hipFree(c);
+    return rc;
+}

@@ -36,7 +36,6 @@ int frame_from(const Forest *f, const uint16_t *depth, const uint8_t *rgb, const
 
 constexpr int PIX_BLOCK = 256;
 constexpr int POOL_BLOCK = 1024;
-constexpr int DRAW_BLOCK = 256;
 constexpr int CULL_THREADS = 1024;
 
 __device__ __forceinline__ uint64_t lanemask_lt() { return (1ull << __lane_id()) - 1ull; }
@@ -394,40 +393,41 @@ __global__ void __launch_bounds__(1024) k_b_alive_init(const Attempt *__restrict
 // preemptive rounds
 // ---------------------------------------------------------------------------
 
-__global__ void __launch_bounds__(DRAW_BLOCK) k_b_draw(const Attempt *__restrict__ att, Stage S, int r)
-{
-    FOR_UNITS(S, u) {
-        const int a = attempt_of(S, u);
-        const Attempt &A = att[a];
-        if (!round_active(A, r)) continue;
-        const int i = (u - S.off[a]) * DRAW_BLOCK + (int)threadIdx.x;
-        if (i >= A.B) continue;
-        const int np = A.misc[0];
-        const U4 x = philox((uint64_t)r, (uint64_t)i, 0, 0, A.seed, TAG_PIX);
-        const int p = A.pool[uniform_int(x.x[0], (uint64_t)np)];
-        float c[3];
-        cam_point(A.fr, p % A.fr.W, p / A.fr.W, A.fr.depth[p], c);
-        A.draws[i] = make_float4(c[0], c[1], c[2], __int_as_float(p));
-        int cnt = 0;
-        for (int t = 0; t < A.T; ++t) cnt += A.nmodes[t * A.L + A.leaves[(int64_t)t * A.P + p]];
-        atomicAdd(&A.stats[2], (unsigned long long)cnt);
-    }
-}
-
 // LDS image of one mode: mu (3), sinv (6), kappa, id = tree * M + mode, pad
 constexpr int SMODE = 12;
+// LDS budget of the modes staged by one scoring workgroup
+constexpr size_t SCORE_LDS = 64 * 1024;
 
-// One unit: 64 live hypotheses (lanes) x `dpu` consecutive draws.
-__global__ void __launch_bounds__(64) k_b_score(const Attempt *__restrict__ att, Stage S, int r, int dpu)
+// wavefronts per scoring workgroup when one draw can have up to tm modes
+static int score_waves(int tm)
+{
+    int w = GROUP;
+    while (w > 1 && (size_t)w * (size_t)tm * SMODE * sizeof(float) > SCORE_LDS) w >>= 1;
+    return w;
+}
+
+// One unit: 64 live hypotheses (lanes) x `dpu` consecutive draws (a multiple
+// of GROUP). The draws of a group are spread over the workgroup's wavefronts;
+// each wavefront draws its pixel (Philox counter (round, draw)), stages the
+// pixel's modes in (tree, mode) order in its own LDS slice, and scores them
+// against its lanes' hypotheses. The group's energies are then summed per
+// lane in draw order and stored; the cull adds the group sums in group
+// order. The units of hypothesis block 0 also publish each draw (camera point
+// and pixel, for refinement) and count its modes.
+__global__ void __launch_bounds__(64 * GROUP) k_b_score(const Attempt *__restrict__ att, Stage S, int r, int dpu,
+                                                        int tm)
 {
     extern __shared__ __align__(16) float smode[];
-    __shared__ int32_t s_ex[16], s_leaf[16];
-    const int lane = __lane_id();
+    __shared__ int32_t s_ex[GROUP][16], s_leaf[GROUP][16];
+    __shared__ float s_e[GROUP][64];
+    const int lane = __lane_id(), wv = (int)(threadIdx.x >> 6), nw = (int)(blockDim.x >> 6);
+    float *sm = smode + (size_t)wv * tm * SMODE;
     FOR_UNITS(S, u) {
         const int a = attempt_of(S, u);
         const Attempt &A = att[a];
         if (!round_active(A, r)) continue;
         const int na = A.misc[1];
+        const int np = A.misc[0];
         const int nch = (A.B + dpu - 1) / dpu;
         const int local = u - S.off[a];
         const int a0 = (local / nch) * 64;
@@ -435,81 +435,101 @@ __global__ void __launch_bounds__(64) k_b_score(const Attempt *__restrict__ att,
         if (a0 >= na) continue;
         const int ap = a0 + lane;
         const bool act = ap < na;
+        const bool publish = a0 == 0;
         const int h = A.alive[act ? ap : a0];
         const Hyp &hy = A.hyp[h];
         const float R0 = hy.R32[0], R1 = hy.R32[1], R2 = hy.R32[2], R3 = hy.R32[3], R4 = hy.R32[4],
                     R5 = hy.R32[5], R6 = hy.R32[6], R7 = hy.R32[7], R8 = hy.R32[8];
         const float t0 = hy.t32[0], t1 = hy.t32[1], t2 = hy.t32[2];
         const int i1 = min((ch + 1) * dpu, A.B);
-        for (int i = ch * dpu; i < i1; ++i) {
-            const float4 dr = A.draws[i];
-            const int p = __float_as_int(dr.w);
-            // stage the draw's modes in (tree, mode) order
-            int leaf = 0, nm = 0;
-            if (lane < A.T) {
-                leaf = A.leaves[(int64_t)lane * A.P + p];
-                nm = A.nmodes[lane * A.L + leaf];
-            }
-            int incl = nm;
-            for (int o = 1; o < 16; o <<= 1) {
-                int y = __shfl_up(incl, o, 64);
-                if (lane >= o) incl += y;
-            }
-            const int cnt = __shfl(incl, A.T - 1, 64);
-            if (lane < A.T) {
-                s_ex[lane] = incl - nm;
-                s_leaf[lane] = leaf;
-            }
-            __syncthreads();
-            for (int j = lane; j < cnt; j += 64) {
-                // the mode's tree: the last tree whose first mode index is <= j
-                int tj = 0;
-                for (int t = 1; t < A.T; ++t)
-                    if (j >= s_ex[t]) tj = t;
-                const int m = j - s_ex[tj];
-                const Mode md = A.modes[((int64_t)tj * A.L + s_leaf[tj]) * A.M + m];
-                float *dst = smode + j * SMODE;
-                dst[0] = md.mu[0]; dst[1] = md.mu[1]; dst[2] = md.mu[2];
-                dst[3] = md.sinv[0]; dst[4] = md.sinv[1]; dst[5] = md.sinv[2];
-                dst[6] = md.sinv[3]; dst[7] = md.sinv[4]; dst[8] = md.sinv[5];
-                dst[9] = md.kappa;
-                dst[10] = __int_as_float(tj * A.M + m);
-                dst[11] = 0.0f;
-            }
-            __syncthreads();
-            const float y0 = fmaf(R0, dr.x, fmaf(R1, dr.y, fmaf(R2, dr.z, t0)));
-            const float y1 = fmaf(R3, dr.x, fmaf(R4, dr.y, fmaf(R5, dr.z, t1)));
-            const float y2 = fmaf(R6, dr.x, fmaf(R7, dr.y, fmaf(R8, dr.z, t2)));
-            float best = INFINITY;
-            int bj = -1;
-            for (int j = 0; j < cnt; ++j) {
-                const float4 q0 = *(const float4 *)(smode + j * SMODE);
-                const float4 q1 = *(const float4 *)(smode + j * SMODE + 4);
-                const float2 q2 = *(const float2 *)(smode + j * SMODE + 8);
-                const float d0 = y0 - q0.x, d1 = y1 - q0.y, d2 = y2 - q0.z;
-                const float s0 = q0.w, s1 = q1.x, s2 = q1.y, s3 = q1.z, s4 = q1.w, s5 = q2.x;
-                const float a0v = fmaf(s2, d2, fmaf(s1, d1, s0 * d0));
-                const float a1v = fmaf(s4, d2, fmaf(s3, d1, s1 * d0));
-                const float a2v = fmaf(s5, d2, fmaf(s4, d1, s2 * d0));
-                const float q = fmaf(d2, a2v, fmaf(d1, a1v, d0 * a0v));
-                const float term = fmaf(0.5f, q, q2.y);
-                if (term < best) {
-                    best = term;
-                    bj = j;
+        for (int g0 = ch * dpu; g0 < i1; g0 += GROUP) {
+            for (int k = 0; k < GROUP / nw; ++k) {
+                const int slot = k * nw + wv;
+                const int i = g0 + slot;
+                const bool has = i < i1;
+                float4 dr = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+                int p = 0;
+                if (has) {
+                    const U4 x = philox((uint64_t)r, (uint64_t)i, 0, 0, A.seed, TAG_PIX);
+                    p = A.pool[uniform_int(x.x[0], (uint64_t)np)];
+                    float c[3];
+                    cam_point(A.fr, p % A.fr.W, p / A.fr.W, A.fr.depth[p], c);
+                    dr = make_float4(c[0], c[1], c[2], __int_as_float(p));
                 }
+                int leaf = 0, nm = 0;
+                if (has && lane < A.T) {
+                    leaf = A.leaves[(int64_t)lane * A.P + p];
+                    nm = A.nmodes[lane * A.L + leaf];
+                }
+                int incl = nm;
+                for (int o = 1; o < 16; o <<= 1) {
+                    int y = __shfl_up(incl, o, 64);
+                    if (lane >= o) incl += y;
+                }
+                const int cnt = __shfl(incl, A.T - 1, 64);
+                if (lane < A.T) {
+                    s_ex[wv][lane] = incl - nm;
+                    s_leaf[wv][lane] = leaf;
+                }
+                if (publish && has && lane == 0) {
+                    A.draws[i] = dr;
+                    if (cnt) atomicAdd(&A.stats[2], (unsigned long long)cnt);
+                }
+                __syncthreads();
+                for (int j = lane; j < cnt; j += 64) {
+                    // the mode's tree: the last tree whose first mode index is <= j
+                    int tj = 0;
+                    for (int t = 1; t < A.T; ++t)
+                        if (j >= s_ex[wv][t]) tj = t;
+                    const int m = j - s_ex[wv][tj];
+                    const Mode md = A.modes[((int64_t)tj * A.L + s_leaf[wv][tj]) * A.M + m];
+                    float *dst = sm + j * SMODE;
+                    dst[0] = md.mu[0]; dst[1] = md.mu[1]; dst[2] = md.mu[2];
+                    dst[3] = md.sinv[0]; dst[4] = md.sinv[1]; dst[5] = md.sinv[2];
+                    dst[6] = md.sinv[3]; dst[7] = md.sinv[4]; dst[8] = md.sinv[5];
+                    dst[9] = md.kappa;
+                    dst[10] = __int_as_float(tj * A.M + m);
+                    dst[11] = 0.0f;
+                }
+                __syncthreads();
+                const float y0 = fmaf(R0, dr.x, fmaf(R1, dr.y, fmaf(R2, dr.z, t0)));
+                const float y1 = fmaf(R3, dr.x, fmaf(R4, dr.y, fmaf(R5, dr.z, t1)));
+                const float y2 = fmaf(R6, dr.x, fmaf(R7, dr.y, fmaf(R8, dr.z, t2)));
+                float best = INFINITY;
+                int bj = -1;
+                for (int j = 0; j < cnt; ++j) {
+                    const float4 q0 = *(const float4 *)(sm + j * SMODE);
+                    const float4 q1 = *(const float4 *)(sm + j * SMODE + 4);
+                    const float2 q2 = *(const float2 *)(sm + j * SMODE + 8);
+                    const float d0 = y0 - q0.x, d1 = y1 - q0.y, d2 = y2 - q0.z;
+                    const float s0 = q0.w, s1 = q1.x, s2 = q1.y, s3 = q1.z, s4 = q1.w, s5 = q2.x;
+                    const float a0v = fmaf(s2, d2, fmaf(s1, d1, s0 * d0));
+                    const float a1v = fmaf(s4, d2, fmaf(s3, d1, s1 * d0));
+                    const float a2v = fmaf(s5, d2, fmaf(s4, d1, s2 * d0));
+                    const float q = fmaf(d2, a2v, fmaf(d1, a1v, d0 * a0v));
+                    const float term = fmaf(0.5f, q, q2.y);
+                    if (term < best) {
+                        best = term;
+                        bj = j;
+                    }
+                }
+                bool in = false;
+                uint16_t id = 0xFFFF;
+                if (bj >= 0) {
+                    const float *mb = sm + bj * SMODE;
+                    const float d0 = y0 - mb[0], d1 = y1 - mb[1], d2 = y2 - mb[2];
+                    in = (d0 * d0 + d1 * d1) + d2 * d2 <= A.inl2;
+                    id = (uint16_t)__float_as_int(mb[10]);
+                }
+                s_e[slot][lane] = best < 0.0f ? best : 0.0f;
+                if (act && has) A.inl[(int64_t)i * A.N + ap] = in ? id : (uint16_t)0xFFFF;
+                __syncthreads();
             }
-            const float e = best < 0.0f ? best : 0.0f;
-            bool in = false;
-            uint16_t id = 0xFFFF;
-            if (bj >= 0) {
-                const float *mb = smode + bj * SMODE;
-                const float d0 = y0 - mb[0], d1 = y1 - mb[1], d2 = y2 - mb[2];
-                in = (d0 * d0 + d1 * d1) + d2 * d2 <= A.inl2;
-                id = (uint16_t)__float_as_int(mb[10]);
-            }
-            if (act) {
-                A.e[(int64_t)i * A.N + ap] = e;
-                A.inl[(int64_t)i * A.N + ap] = in ? id : (uint16_t)0xFFFF;
+            // the group's energy sum per lane, in draw order
+            if (wv == 0) {
+                float g = 0.0f;
+                for (int w = 0; w < GROUP && g0 + w < i1; ++w) g = g + s_e[w][lane];
+                if (act) A.gs[(int64_t)(g0 / GROUP) * A.N + ap] = g;
             }
             __syncthreads();
         }
@@ -530,14 +550,11 @@ __global__ void __launch_bounds__(CULL_THREADS) k_b_cull(const Attempt *__restri
         for (int ap = threadIdx.x; ap < n2; ap += CULL_THREADS) {
             if (ap < na) {
                 const int h = A.alive[ap];
-                float Ssum = 0.0f, g = 0.0f;
-                for (int i = 0; i < A.B; ++i) {
-                    g = g + A.e[(int64_t)i * A.N + ap];
-                    if ((i % GROUP) == GROUP - 1 || i == A.B - 1) {
-                        Ssum = Ssum + g;
-                        g = 0.0f;
-                    }
-                }
+                const int ng = (A.B + GROUP - 1) / GROUP;
+                const float *gs = A.gs + ap;
+                float Ssum = 0.0f;
+#pragma unroll 8
+                for (int k = 0; k < ng; ++k) Ssum = Ssum + gs[(int64_t)k * A.N];
                 const float E = A.energy[h] + Ssum;
                 A.energy[h] = E;
                 A.pos[h] = ap;
@@ -582,9 +599,11 @@ __global__ void __launch_bounds__(CULL_THREADS) k_b_cull(const Attempt *__restri
     }
 }
 
-// one wavefront per survivor: this round's inliers, lane-strided in draw
-// order, combined by an xor butterfly (every lane ends with the same sums)
-__global__ void __launch_bounds__(64) k_b_refine_sums(const Attempt *__restrict__ att, Stage S, int r)
+// One wavefront per survivor: this round's inliers, lane-strided in draw
+// order, combined by an xor butterfly (every lane ends with the same sums);
+// lane 0 adds them to the survivor's running sums and, with refinement on,
+// re-solves its pose from the totals (Kabsch on all of its inliers so far).
+__global__ void __launch_bounds__(64) k_b_refine(const Attempt *__restrict__ att, Stage S, int r)
 {
     const int lane = __lane_id();
     FOR_UNITS(S, u) {
@@ -614,42 +633,24 @@ __global__ void __launch_bounds__(64) k_b_refine_sums(const Attempt *__restrict_
         for (int o = 32; o >= 1; o >>= 1)
 #pragma unroll
             for (int k = 0; k < NSUM; ++k) s[k] = s[k] + __shfl_xor(s[k], o, 64);
-        double mine = 0.0;
+        if (lane == 0) {
+            double *run = A.sums + (int64_t)h * NSUM;
 #pragma unroll
-        for (int k = 0; k < NSUM; ++k)
-            if (lane == k) mine = s[k];
-        if (lane < NSUM) A.rsums[(int64_t)h * NSUM + lane] = mine;
-    }
-}
-
-// one lane per survivor: running sums and Kabsch refinement
-__global__ void __launch_bounds__(64) k_b_refine_solve(const Attempt *__restrict__ att, Stage S, int r)
-{
-    FOR_UNITS(S, u) {
-        const int a = attempt_of(S, u);
-        const Attempt &A = att[a];
-        if (A.misc[3] != r + 1) continue;
-        const int sidx = (u - S.off[a]) * 64 + __lane_id();
-        if (sidx >= A.misc[1]) continue;
-        const int h = A.alive[sidx];
-        double tot[NSUM];
-        double *run = A.sums + (int64_t)h * NSUM;
-        const double *rs = A.rsums + (int64_t)h * NSUM;
-#pragma unroll
-        for (int k = 0; k < NSUM; ++k) {
-            tot[k] = run[k] + rs[k];
-            run[k] = tot[k];
-        }
-        double R[9], t[3];
-        if (A.refine && pose_from_sums(tot, R, t)) {
-            Hyp &hy = A.hyp[h];
-            for (int k = 0; k < 9; ++k) {
-                hy.R[k] = R[k];
-                hy.R32[k] = (float)R[k];
+            for (int k = 0; k < NSUM; ++k) {
+                s[k] = run[k] + s[k];
+                run[k] = s[k];
             }
-            for (int k = 0; k < 3; ++k) {
-                hy.t[k] = t[k];
-                hy.t32[k] = (float)t[k];
+            double R[9], t[3];
+            if (A.refine && pose_from_sums(s, R, t)) {
+                Hyp &hy = A.hyp[h];
+                for (int k = 0; k < 9; ++k) {
+                    hy.R[k] = R[k];
+                    hy.R32[k] = (float)R[k];
+                }
+                for (int k = 0; k < 3; ++k) {
+                    hy.t[k] = t[k];
+                    hy.t32[k] = (float)t[k];
+                }
             }
         }
     }
@@ -700,7 +701,7 @@ static int rounds_for(int N)
 }
 
 struct Sched {
-    int dpu;         // draws per scoring unit
+    int dpu;         // draws per scoring unit, a multiple of GROUP
     int grid;        // persistent grid of the scoring kernel (0: one workgroup per unit)
     int xcd;         // XCD-contiguous unit order
 };
@@ -725,7 +726,7 @@ struct Plan {
     std::vector<Attempt> slices;    // scratch pointers per attempt
     int32_t *d_off = nullptr;       // stage offsets of the chosen schedule
     hipGraphExec_t exec = nullptr;
-    Sched sched{1, 0, 0};
+    Sched sched{GROUP, 0, 0};
     std::string desc;
     uint64_t last_use = 0;
 };
@@ -767,11 +768,10 @@ static size_t carve(const Shape &s, char *base, Attempt &A)
     A.hyp_try = (int32_t *)take((size_t)s.N * 4);
     A.energy = (float *)take((size_t)s.N * 4);
     A.sums = (double *)take((size_t)s.N * NSUM * 8);
-    A.rsums = (double *)take((size_t)s.N * NSUM * 8);
     A.alive = (int32_t *)take((size_t)s.N * 4);
     A.pos = (int32_t *)take((size_t)s.N * 4);
     A.draws = (float4 *)take((size_t)s.B * 16);
-    A.e = (float *)take((size_t)s.B * s.N * 4);
+    A.gs = (float *)take((size_t)((s.B + GROUP - 1) / GROUP) * s.N * 4);
     A.inl = (uint16_t *)take((size_t)s.B * s.N * 2);
     A.stats = (unsigned long long *)take(3 * 8);
     A.tr_alive = (int32_t *)take((size_t)MAX_ROUNDS * s.N * 4);
@@ -796,16 +796,16 @@ static void free_plan(reloc_batch *b, Plan *pl)
 
 // stages of one schedule in launch order
 struct Stages {
-    Stage pix, pb, att, hyp, draw;
-    std::vector<Stage> score, refine, solve;
+    Stage pix, pb, att, hyp;
+    std::vector<Stage> score, refine;
 };
 
-// host offsets of every stage for schedule `sc`: pix, pb, att, hyp, draw,
-// then per round (score, refine, solve)
+// host offsets of every stage for schedule `sc`: pix, pb, att, hyp, then per
+// round (score, refine)
 static std::vector<int32_t> offsets(const Plan *pl, const Sched &sc)
 {
     const int n = pl->n, R = pl->rounds;
-    const int n_stage = 5 + 3 * R;
+    const int n_stage = 4 + 2 * R;
     std::vector<int32_t> off((size_t)n_stage * (n + 1), 0);
     auto fill = [&](int k, auto units) {
         int32_t *o = off.data() + (size_t)k * (n + 1);
@@ -817,19 +817,17 @@ static std::vector<int32_t> offsets(const Plan *pl, const Sched &sc)
     fill(1, [&](int a) { return (int)((P(a) + POOL_BLOCK - 1) / POOL_BLOCK); });
     fill(2, [&](int) { return 1; });
     fill(3, [&](int a) { return pl->shape[a].N; });
-    fill(4, [&](int a) { return (pl->shape[a].B + DRAW_BLOCK - 1) / DRAW_BLOCK; });
     auto bound = [&](int a, int rr) {
         int bnd = pl->shape[a].N;
         for (int k = 0; k < rr; ++k) bnd = (bnd + 1) / 2;
         return bnd;
     };
     for (int r = 0; r < R; ++r) {
-        fill(5 + 3 * r, [&](int a) {
+        fill(4 + 2 * r, [&](int a) {
             if (r >= rounds_for(pl->shape[a].N)) return 0;
             return ((bound(a, r) + 63) / 64) * ((pl->shape[a].B + sc.dpu - 1) / sc.dpu);
         });
-        fill(6 + 3 * r, [&](int a) { return r >= rounds_for(pl->shape[a].N) ? 0 : bound(a, r + 1); });
-        fill(7 + 3 * r, [&](int a) { return r >= rounds_for(pl->shape[a].N) ? 0 : (bound(a, r + 1) + 63) / 64; });
+        fill(5 + 2 * r, [&](int a) { return r >= rounds_for(pl->shape[a].N) ? 0 : bound(a, r + 1); });
     }
     return off;
 }
@@ -846,11 +844,10 @@ static Stages stages_of(const Plan *pl, const Sched &sc, const int32_t *d_off, c
         return s;
     };
     Stages st;
-    st.pix = mk(0); st.pb = mk(1); st.att = mk(2); st.hyp = mk(3); st.draw = mk(4);
+    st.pix = mk(0); st.pb = mk(1); st.att = mk(2); st.hyp = mk(3);
     for (int r = 0; r < pl->rounds; ++r) {
-        st.score.push_back(mk(5 + 3 * r));
-        st.refine.push_back(mk(6 + 3 * r));
-        st.solve.push_back(mk(7 + 3 * r));
+        st.score.push_back(mk(4 + 2 * r));
+        st.refine.push_back(mk(5 + 2 * r));
     }
     return st;
 }
@@ -877,16 +874,14 @@ static int enqueue(const Plan *pl, const Sched &sc, const Stages &st, hipStream_
     RL_LAUNCH("k_b_pool_write", k_b_pool_write, dim3(grid_of(st.pb, cap, sc.xcd)), dim3(POOL_BLOCK), 0, s, d, st.pb);
     RL_LAUNCH("k_b_hypgen", k_b_hypgen, dim3(grid_of(st.hyp, 0, sc.xcd)), dim3(64), 0, s, d, st.hyp);
     RL_LAUNCH("k_b_alive_init", k_b_alive_init, dim3(grid_of(att, cap, 0)), dim3(1024), 0, s, d, att);
-    const size_t smem = (size_t)pl->tm_max * SMODE * sizeof(float);
+    const int nw = score_waves(pl->tm_max);
+    const size_t smem = (size_t)nw * pl->tm_max * SMODE * sizeof(float);
     for (int r = 0; r < pl->rounds; ++r) {
-        RL_LAUNCH("k_b_draw", k_b_draw, dim3(grid_of(st.draw, cap, sc.xcd)), dim3(DRAW_BLOCK), 0, s, d, st.draw, r);
-        RL_LAUNCH("k_b_score", k_b_score, dim3(grid_of(st.score[r], sc.grid, sc.xcd)), dim3(64), smem, s, d,
-                  st.score[r], r, sc.dpu);
+        RL_LAUNCH("k_b_score", k_b_score, dim3(grid_of(st.score[r], sc.grid, sc.xcd)), dim3(64 * nw), smem, s, d,
+                  st.score[r], r, sc.dpu, pl->tm_max);
         RL_LAUNCH("k_b_cull", k_b_cull, dim3(grid_of(att, cap, 0)), dim3(CULL_THREADS), 0, s, d, att, r);
-        RL_LAUNCH("k_b_refine_sums", k_b_refine_sums, dim3(grid_of(st.refine[r], 0, sc.xcd)), dim3(64), 0, s, d,
-                  st.refine[r], r);
-        RL_LAUNCH("k_b_refine_solve", k_b_refine_solve, dim3(grid_of(st.solve[r], 0, sc.xcd)), dim3(64), 0, s, d,
-                  st.solve[r], r);
+        RL_LAUNCH("k_b_refine", k_b_refine, dim3(grid_of(st.refine[r], 0, sc.xcd)), dim3(64), 0, s, d, st.refine[r],
+                  r);
     }
     RL_LAUNCH("k_b_finish", k_b_finish, dim3(grid_of(att, cap, 0)), dim3(64), 0, s, d, att);
     RL_HIP(hipGetLastError());
@@ -953,13 +948,13 @@ static int run_plan(Plan *pl, hipStream_t s)
 static int tune(reloc_batch *b, Plan *pl, hipStream_t s)
 {
     std::vector<Sched> cands;
-    cands.push_back({1, 0, 0});
+    cands.push_back({GROUP, 0, 0});
     if (b->tune) {
-        cands.push_back({1, 0, 1});
-        cands.push_back({2, 0, 1});
-        cands.push_back({4, 0, 1});
-        cands.push_back({1, 2048, 1});
-        cands.push_back({2, 1024, 1});
+        cands.push_back({GROUP, 0, 1});
+        cands.push_back({2 * GROUP, 0, 1});
+        cands.push_back({4 * GROUP, 0, 1});
+        cands.push_back({GROUP, 2048, 1});
+        cands.push_back({2 * GROUP, 1024, 1});
     }
     hipEvent_t e0 = nullptr, e1 = nullptr;
     RL_HIP(hipEventCreate(&e0));

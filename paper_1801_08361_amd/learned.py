@@ -1,0 +1,59 @@
+"""Host side of the learned proposal: gathering labelled training rows from
+posed frames and turning a trained network into pick weights. Every per-pixel
+computation (inputs, labels, training, inference) runs in the library's
+kernels; this module only chooses pixels and concatenates device buffers.
+
+Supervision: a frame whose pose is known (an agent's own tracked frame, or a
+relocalisation accepted by the depth-difference check of Sec. 3.3.1,
+Eqs. 3-4) labels each of its valid pixels 1 when one of the pixel's leaf modes
+lies within 5 cm of the pixel's world point, else 0."""
+from __future__ import annotations
+
+from typing import Iterable, Optional, Tuple
+
+import numpy as np
+
+from . import Forest, Mlp, label_pixels, pixel_features
+
+
+def valid_pixels(depth, depth_min: int, depth_max: int):
+    """int32 device tensor of the pixel indices v W + u with depth in range."""
+    import torch
+    d = depth.reshape(-1).to(torch.int32)
+    return torch.nonzero((d >= depth_min) & (d <= depth_max)).reshape(-1).to(torch.int32).contiguous()
+
+
+def frame_rows(forest: Forest, depth, rgb, K, pose, max_pixels: Optional[int] = None,
+               seed: int = 0) -> Tuple["object", "object"]:
+    """(inputs [n, 32] bfloat16 bits, labels [n] uint8) of the valid pixels of
+    one posed frame, or of max_pixels of them drawn without replacement by a
+    seeded numpy generator."""
+    import torch
+    p = forest.params
+    pix = valid_pixels(depth, p.depth_min_mm, p.depth_max_mm)
+    if max_pixels is not None and pix.numel() > max_pixels:
+        sel = np.sort(np.random.default_rng(seed).choice(pix.numel(), max_pixels, replace=False))
+        pix = pix[torch.from_numpy(sel).to(pix.device)].contiguous()
+    x = pixel_features(forest, depth, rgb, K, pix)
+    y = label_pixels(forest, depth, rgb, K, pose, pix)
+    return x, y
+
+
+def training_rows(forest: Forest, frames: Iterable[tuple], max_pixels: Optional[int] = None, seed: int = 0):
+    """Concatenated rows of frames given as (depth, rgb, K, pose) tuples."""
+    import torch
+    xs, ys = [], []
+    for i, (d, c, K, pose) in enumerate(frames):
+        x, y = frame_rows(forest, d, c, K, pose, max_pixels, seed + i)
+        xs.append(x)
+        ys.append(y)
+    if not xs:
+        raise ValueError("no frames")
+    return torch.cat(xs).contiguous(), torch.cat(ys).contiguous()
+
+
+def train(x, y, seed: int = 1, epochs: int = 8, batch_rows: int = 4096, lr: float = 2e-3) -> Tuple[Mlp, np.ndarray]:
+    """A new network trained on the rows; returns it and the per-epoch loss."""
+    m = Mlp(seed)
+    losses = m.train(x, y, epochs=epochs, batch_rows=batch_rows, lr=lr, seed=seed)
+    return m, losses

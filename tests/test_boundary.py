@@ -64,6 +64,17 @@ def test_argument_errors_without_gpu():
     assert L.reloc_relocalise(None, None, None, None, 0, 0, None, None, None, None) == rl.E_ARG
     assert L.reloc_relocalise_batch(None, None, 0, None, None) == rl.E_ARG
     assert L.reloc_batch_destroy(None) == rl.E_ARG
+    assert L.reloc_verify(None, None, 4, 4, None, None, None, None) == rl.E_ARG
+    assert L.reloc_mlp_create(0, None, None) == rl.E_ARG
+    assert L.reloc_mlp_destroy(None) == rl.E_ARG
+    assert L.reloc_mlp_gradient(None, None, None, 1, None, None, None) == rl.E_ARG
+    assert L.reloc_mlp_train(None, None, None, 1, 1, 1, C.c_float(1e-3), 0, None, None) == rl.E_ARG
+    assert L.reloc_mlp_logits(None, None, 1, None, None) == rl.E_ARG
+    assert L.reloc_mlp_pixel_weights(None, None, None, None, None, None, None, None) == rl.E_ARG
+    assert L.reloc_pixel_features(None, None, None, None, None, 0, None, None, None) == rl.E_ARG
+    assert L.reloc_pixel_features(None, None, None, None, None, -1, None, None, None) == rl.E_ARG
+    assert L.reloc_label_pixels(None, None, None, None, None, None, 0, None, None) == rl.E_ARG
+    assert L.reloc_debug_mfma_probe(None, None, None) == rl.E_ARG
     for code in (0, 1, 2, 3, -1, -2, -3, -4, -5, 99):
         assert isinstance(rl.status_string(code), str)
     with pytest.raises(rl.RelocError):

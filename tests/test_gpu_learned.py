@@ -1,0 +1,286 @@
+"""GPU: the learned proposal and the verifier. The matrix-core lane layout is
+checked against numpy; initialisation, per-pixel inputs, labels and the
+verifier against the oracle (exact where both sides do the same integer or
+FP32 steps); the MLP forward and gradient against the oracle's FP64 network
+(which applies the same bfloat16 roundings); training must lower the loss
+and the trained network must rank inliers above outliers on held-out
+frames."""
+import numpy as np
+import pytest
+
+import synthroom as sr
+from tests.gpu_util import banner, need_gpu, pair, to_dev
+
+pytestmark = pytest.mark.gpu
+
+SMALL_L = dict(n_trees=3, depth=8, reservoir_size=64, max_modes=10, n_hypotheses=64, batch_pixels=64)
+
+
+def bf16_bits(x: np.ndarray) -> np.ndarray:
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(x, dtype=np.float32)).to(torch.bfloat16).view(torch.int16) \
+        .numpy().view(np.uint16)
+
+
+def bits_to_f32(b: np.ndarray) -> np.ndarray:
+    return (b.astype(np.uint32) << 16).view(np.float32)
+
+
+def rows32(x24: np.ndarray) -> np.ndarray:
+    out = np.zeros((len(x24), 32), dtype=np.uint16)
+    out[:, :24] = bf16_bits(x24)
+    return out
+
+
+def test_mfma_lane_layout():
+    need_gpu()
+    import paper_1801_08361_amd as rl
+    rng = np.random.default_rng(0)
+    for trial in range(3):
+        banner(f"mfma probe {trial}")
+        a = bf16_bits(rng.normal(size=(16, 32)))
+        bt = bf16_bits(rng.normal(size=(16, 32)))
+        if trial == 2:   # single nonzero entries locate every lane's rows and columns
+            a = bf16_bits(np.eye(16, 32) * np.arange(1, 17)[:, None])
+        c = rl.mfma_probe(a, bt)
+        ref = bits_to_f32(a).astype(np.float64) @ bits_to_f32(bt).astype(np.float64).T
+        bound = np.abs(bits_to_f32(a)).astype(np.float64) @ np.abs(bits_to_f32(bt)).astype(np.float64).T
+        assert np.all(np.abs(c - ref) <= 1e-6 * bound + 1e-30), trial
+
+
+def test_verify_matches_oracle():
+    dev = need_gpu()
+    import torch
+    import oracle
+    import paper_1801_08361_amd as rl
+    rng = np.random.default_rng(1)
+    cases = []
+    db = rng.integers(500, 4000, size=(61, 97)).astype(np.uint16)
+    cases.append((db + 30, db))
+    da = db.copy(); da[:30] = 0
+    cases.append((da, db))
+    cases.append((db, np.zeros_like(db)))                       # nothing rendered: mu = inf
+    cases.append((np.zeros_like(db), db))
+    big = rng.integers(0, 65535, size=(480, 640)).astype(np.uint16)
+    big2 = np.where(rng.random((480, 640)) < 0.2, 0, big + rng.integers(-40, 40, size=(480, 640))).astype(np.uint16)
+    cases.append((big, big2))
+    cases.append((np.full((1, 1), 1000, np.uint16), np.full((1, 1), 1049, np.uint16)))
+    for i, (a, b) in enumerate(cases):
+        banner(f"verify case {i} {a.shape}")
+        got = rl.verify(torch.from_numpy(a).to(dev), torch.from_numpy(b).to(dev))
+        ref = oracle.verify(a, b)
+        assert got[0] == ref[0] and got[2] == ref[2], (i, got, ref)
+        assert (got[1] == ref[1]) or (np.isinf(got[1]) and np.isinf(ref[1])), (i, got, ref)
+
+
+def test_mlp_init_matches_oracle():
+    need_gpu()
+    import oracle
+    import paper_1801_08361_amd as rl
+    for seed in (0, 42, 12345678901):
+        banner(f"mlp init seed {seed}")
+        m = rl.Mlp(seed)
+        assert np.array_equal(m.weights().view(np.uint32), oracle.mlp_init(seed).view(np.uint32))
+        w = m.weights()
+        w[1536:1600] = np.linspace(-1, 1, 64)
+        m.set_weights(w)
+        assert np.array_equal(m.weights(), w)
+
+
+@pytest.fixture(scope="module")
+def adapted():
+    """The same small forest on the GPU and in the oracle, and its scene."""
+    dev = need_gpu()
+    import oracle
+    import paper_1801_08361_amd as rl
+    pp, po = pair(**SMALL_L)
+    sc = sr.small_scene(610, 160, 120)
+    g = rl.Forest(pp)
+    o = oracle.Forest(po)
+    for k in range(len(sc.adapt_poses)):
+        d, c = sc.render_adapt(k)
+        banner(f"learned forest adapt {k}")
+        g.adapt_frame(*to_dev(d, c, dev), sc.K, sc.adapt_poses[k])
+        o.adapt(d, c, sc.K, sc.adapt_poses[k])
+    return dev, sc, g, o
+
+
+def query_pixels(d: np.ndarray, n: int, seed: int) -> np.ndarray:
+    """valid pixels, invalid pixels and both image corners"""
+    rng = np.random.default_rng(seed)
+    flat = d.reshape(-1)
+    valid = np.flatnonzero((flat >= 500) & (flat <= 5000))
+    invalid = np.flatnonzero((flat < 500) | (flat > 5000))
+    pix = list(rng.choice(valid, min(n, len(valid)), replace=False))
+    pix += list(invalid[:5]) + [0, len(flat) - 1]
+    return np.array(pix, dtype=np.int32)
+
+
+def test_pixel_features_match_oracle(adapted):
+    import torch
+    import paper_1801_08361_amd as rl
+    dev, sc, g, o = adapted
+    for q in (0, 3):
+        d, c = sc.render_query(q)
+        if q == 3:      # a hole of invalid depth
+            d = d.clone(); d[40:60, 50:90] = 0
+        pix = query_pixels(d.numpy(), 500, q)
+        banner(f"pixel features query {q} n={len(pix)}")
+        x, xf = rl.pixel_features(g, *to_dev(d, c, dev), sc.K, torch.from_numpy(pix).to(dev), with_fp32=True)
+        xf = xf.cpu().numpy()
+        ref = o.features24(d.numpy(), c.numpy(), sc.K, pix)
+        exact = [k for k in range(24) if k not in (10, 11, 12, 14, 15, 16, 18, 19, 20)]
+        assert np.array_equal(xf[:, exact], ref[:, exact]), q
+        # -log(Sigma^-1_ii) / 10: logf of the two sides may differ in the last ulp
+        np.testing.assert_allclose(xf, ref, rtol=2e-6, atol=1e-7)
+        xb = x.cpu().numpy().view(np.uint16)
+        assert np.array_equal(xb, rows32(xf)), q
+        assert np.all(xb[:, 24:] == 0)
+    # no pixels: nothing to do, no error
+    rl.pixel_features(g, *to_dev(d, c, dev), sc.K, torch.zeros(0, dtype=torch.int32, device=dev))
+
+
+def test_labels_match_oracle(adapted):
+    import torch
+    import paper_1801_08361_amd as rl
+    dev, sc, g, o = adapted
+    for q in (1, 2, 5):
+        d, c = sc.render_query(q)
+        pix = query_pixels(d.numpy(), 2000, 10 + q)
+        for which, pose in (("true", sc.query_poses[q]), ("other", sc.adapt_poses[0])):
+            banner(f"labels query {q} pose {which}")
+            y = rl.label_pixels(g, *to_dev(d, c, dev), sc.K, pose, torch.from_numpy(pix).to(dev)).cpu().numpy()
+            ref = o.label(d.numpy(), c.numpy(), sc.K, pose, pix)
+            assert np.array_equal(y, ref), (q, which, int((y != ref).sum()))
+            rate = {} if which == "true" else rate
+            rate[which] = y.mean()
+        # the true pose explains many pixels, a wrong one few
+        assert rate["true"] > 0.1 and rate["other"] < 0.5 * rate["true"], (q, rate)
+
+
+def random_weights(seed: int) -> np.ndarray:
+    import oracle
+    rng = np.random.default_rng(seed)
+    w = oracle.mlp_init(seed)
+    w[1536:1600] = rng.normal(scale=0.2, size=64)
+    w[5696:5760] = rng.normal(scale=0.2, size=64)
+    w[5824] = -0.4
+    return w
+
+
+def test_mlp_forward_matches_oracle():
+    dev = need_gpu()
+    import torch
+    import oracle
+    import paper_1801_08361_amd as rl
+    rng = np.random.default_rng(3)
+    m = rl.Mlp(5)
+    for n in (1, 63, 64, 1000):
+        w = random_weights(n)
+        m.set_weights(w)
+        x = rng.normal(size=(n, 24)).astype(np.float32)
+        x = bits_to_f32(bf16_bits(x))              # inputs the GPU receives exactly
+        banner(f"mlp forward n={n}")
+        z = m.logits(torch.from_numpy(rows32(x).view(np.int16)).to(dev)).cpu().numpy()
+        ref = oracle.mlp_forward(w, x)
+        err = np.abs(z - ref)
+        # FP32 accumulation vs FP64: a hidden value may round to the other
+        # neighbouring bfloat16 (one unit in 2^8); the bulk agrees to ~1e-6
+        assert np.all(err <= 5e-3 * (1.0 + np.abs(ref))), (n, err.max())
+        assert np.median(err) <= 1e-5 * (1.0 + np.median(np.abs(ref))), n
+
+
+def test_mlp_gradient_matches_oracle():
+    dev = need_gpu()
+    import torch
+    import oracle
+    import paper_1801_08361_amd as rl
+    rng = np.random.default_rng(4)
+    m = rl.Mlp(6)
+    for n in (1, 64, 777, 4096):
+        w = random_weights(100 + n)
+        m.set_weights(w)
+        x = bits_to_f32(bf16_bits(rng.normal(size=(n, 24)).astype(np.float32)))
+        y = (rng.random(n) < 0.4).astype(np.uint8)
+        banner(f"mlp gradient n={n}")
+        g, loss = m.gradient(torch.from_numpy(rows32(x).view(np.int16)).to(dev), torch.from_numpy(y).to(dev))
+        gr, lr = oracle.mlp_grad(w, x, y)
+        assert loss == pytest.approx(lr, rel=1e-4, abs=1e-6), n
+        cos = float(g @ gr / (np.linalg.norm(g) * np.linalg.norm(gr)))
+        assert cos >= 0.9999, (n, cos)
+        assert np.max(np.abs(g - gr)) <= 1e-2 * np.max(np.abs(gr)), n
+        # every block of the gradient, separately
+        for lo, hi in ((0, 1536), (1536, 1600), (1600, 5696), (5696, 5760), (5760, 5824), (5824, 5825)):
+            if np.any(gr[lo:hi] != 0):
+                assert np.max(np.abs(g[lo:hi] - gr[lo:hi])) <= 2e-2 * np.max(np.abs(gr[lo:hi])) + 1e-7, (n, lo)
+
+
+def test_training_lowers_loss_and_ranks_inliers(adapted):
+    import torch
+    import paper_1801_08361_amd as rl
+    from paper_1801_08361_amd import learned
+    dev, sc, g, o = adapted
+    frames = []
+    for q in range(0, 14):
+        d, c = to_dev(*sc.render_query(q), dev)
+        frames.append((d, c, sc.K, sc.query_poses[q]))
+    banner("training rows")
+    # train on the even queries of the adapted stretch of the path, hold out the odd ones
+    x, y = learned.training_rows(g, frames[0::2])
+    assert x.shape[0] == y.shape[0] > 50000
+    base = float(y.float().mean())
+    assert 0.05 < base < 0.95
+    m = rl.Mlp(9)
+    g0, l0 = m.gradient(x, y)
+    banner("training")
+    losses = m.train(x, y, epochs=6, batch_rows=2048, lr=2e-3, seed=3)
+    g1, l1 = m.gradient(x, y)
+    # better than the untrained network and than the best constant guess
+    h = -(base * np.log(base) + (1 - base) * np.log(1 - base))
+    assert l1 < min(l0, h) - 0.01, (l0, l1, h, losses)
+    # held-out frames: inliers rank above outliers (area under the ROC curve)
+    xh, yh = learned.training_rows(g, frames[1::2])
+    z = m.logits(xh).cpu().numpy().astype(np.float64)
+    yh = yh.cpu().numpy().astype(bool)
+    ranks = np.empty(len(z))
+    ranks[np.argsort(z, kind="stable")] = np.arange(1, len(z) + 1)
+    npos, nneg = int(yh.sum()), int((~yh).sum())
+    auc = (ranks[yh].sum() - npos * (npos + 1) / 2) / (npos * nneg)
+    assert auc > 0.6, auc
+    # pick weights of whole frames are floor(sigma 65536) + 1 of the same network
+    d, c, K, _ = frames[12]
+    banner("pixel weights")
+    wts, prob = m.pixel_weights(g, d, c, K, with_prob=True)
+    wts = wts.cpu().numpy().view(np.uint32)
+    prob = prob.cpu().numpy()
+    flat = d.reshape(-1).cpu().numpy()
+    ok = (flat >= 500) & (flat <= 5000)
+    assert np.all(wts[~ok] == 0) and np.all(prob[~ok] == 0)
+    assert np.array_equal(wts[ok], np.floor(prob[ok] * np.float32(65536.0)).astype(np.uint32) + 1)
+    pix = torch.from_numpy(np.flatnonzero(ok).astype(np.int32)).to(dev)
+    z = m.logits(rl.pixel_features(g, d, c, K, pix)).cpu().numpy()
+    np.testing.assert_allclose(prob[ok], 1.0 / (1.0 + np.exp(-z.astype(np.float64))), rtol=1e-6, atol=1e-7)
+
+
+def test_learned_weights_drive_the_relocaliser(adapted):
+    """The trained network's weights, passed to the relocaliser, give the
+    oracle's result for the same weights (the picks follow the integer CDF)."""
+    import oracle
+    import paper_1801_08361_amd as rl
+    from paper_1801_08361_amd import learned
+    dev, sc, g, o = adapted
+    frames = [(*to_dev(*sc.render_query(q), dev), sc.K, sc.query_poses[q]) for q in range(8)]
+    x, y = learned.training_rows(g, frames)
+    m, _ = learned.train(x, y, seed=2, epochs=3, batch_rows=2048)
+    for q in (8, 9):
+        d, c = sc.render_query(q)
+        dd, cc = to_dev(d, c, dev)
+        wts = m.pixel_weights(g, dd, cc, sc.K)
+        banner(f"learned relocalise query {q}")
+        res = g.relocalise_ex(dd, cc, sc.K, seed=77 + q, n_hyp=64, weights=wts)
+        rc, pose, score = o.relocalise(d.numpy(), c.numpy(), sc.K, seed=77 + q, n_hyp=64,
+                                       weights=wts.cpu().numpy().view(np.uint32))[:3]
+        assert res["status"] == rc
+        if rc == 0:
+            assert np.max(np.abs(res["pose"] - pose)) < 1e-4
+            assert res["score"] == pytest.approx(score, rel=1e-4)
