@@ -338,6 +338,13 @@ int reloc_debug_trace(const reloc_forest *f, reloc_trace *tr);
  * number of workgroups that process unit u (every entry must be 1). */
 int reloc_debug_unit_owners(int32_t xcd, int32_t total, int32_t grid, int32_t *owners_host);
 
+/* Host run of the pose solver's eigenvector step: for n cross-covariance
+ * matrices h_host [n][3][3] (row a, column b: sum of centred c_a w_b), the
+ * unit quaternion (w, x, y, z; sign arbitrary) of the best rotation, or NaNs
+ * where the closed-form step declines (H = 0 or an exactly repeated largest
+ * eigenvalue) and the device falls back to power iteration. */
+int reloc_debug_horn(const double *h_host, int32_t n, double *q_host);
+
 /* One 16x16 product C = A B on the matrix cores as the MLP kernels issue it
  * (bfloat16 operands, FP32 accumulation): a_host [16][32] row-major A,
  * bt_host [16][32] row-major B^T, c_host [16][16] row-major C. Synchronous. */

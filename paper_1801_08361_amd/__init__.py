@@ -135,6 +135,7 @@ _SIGS = {
     "reloc_label_pixels": [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32,
                            C.c_void_p, C.c_void_p],
     "reloc_debug_mfma_probe": [C.c_void_p, C.c_void_p, C.c_void_p],
+    "reloc_debug_horn": [C.c_void_p, C.c_int32, C.c_void_p],
 }
 
 MLP_NPARAM = 5825
@@ -145,6 +146,15 @@ def unit_owners(xcd: int, total: int, grid: int) -> np.ndarray:
     out = np.zeros(max(total, 1), dtype=np.int32)
     _check(lib().reloc_debug_unit_owners(int(xcd), int(total), int(grid), out.ctypes.data), "reloc_debug_unit_owners")
     return out[:total]
+
+
+def horn_quaternions(H: np.ndarray) -> np.ndarray:
+    """Host run of the pose solver's eigenvector step on cross-covariances
+    H [n, 3, 3]; NaN rows where the device would use Jacobi sweeps."""
+    H = np.ascontiguousarray(H, dtype=np.float64).reshape(-1, 9)
+    q = np.zeros((len(H), 4))
+    _check(lib().reloc_debug_horn(H.ctypes.data if len(H) else None, len(H), q.ctypes.data), "reloc_debug_horn")
+    return q
 
 
 def lib() -> C.CDLL:

@@ -81,6 +81,12 @@ constexpr int MAX_R = 1024;
 constexpr int MAX_TM = 512;     // modes over all trees of one pixel (T * M)
 constexpr int MAX_ROUNDS = 13;  // ceil(log2(MAX_HYP)) + 1
 
+// mode colour rows: M colours padded to a multiple of 4 (16-byte rows for
+// vector loads); slots without a mode hold RGB_NONE (a real colour has a zero
+// top byte)
+constexpr uint32_t RGB_NONE = 0xFFFFFFFFu;
+__host__ __device__ __forceinline__ int rgb_stride(int M) { return (M + 3) & ~3; }
+
 // ---------------------------------------------------------------------------
 // Philox4x64-10 (Salmon et al., SC 2011) and the integer range map
 // ---------------------------------------------------------------------------
@@ -227,87 +233,172 @@ __device__ __forceinline__ void sums_add_point(double s[NSUM], const float c[3],
     s[21] = s[21] + cd[2] * cd[2];
 }
 
-// FP64 reciprocal and reciprocal square root: the hardware estimates refined
-// by two Newton steps each (full precision to within an ulp or two; the
-// Jacobi rotations below only need c^2 + s^2 = 1 to that accuracy)
-__device__ __forceinline__ double rcp_nr(double x)
+// Top-eigenspace vector of a symmetric 4x4 matrix by power iteration on
+// N + s I with s = sqrt(tr N^2) (which makes every eigenvalue non-negative,
+// the largest one largest in magnitude), from (1, 0, 0, 0). Only the
+// degenerate inputs that the closed-form step declines come here (N = 0,
+// where it returns (1, 0, 0, 0), or an exactly repeated largest eigenvalue,
+// where any vector of that eigenspace is a best rotation).
+__device__ __forceinline__ void power_top(const double N[16], double q[4])
 {
-    double r = __builtin_amdgcn_rcp(x);
-    double e = fma(-x, r, 1.0);
-    r = fma(r, e, r);
-    e = fma(-x, r, 1.0);
-    return fma(r, e, r);
-}
-
-__device__ __forceinline__ double rsq_nr(double x)
-{
-    double y = __builtin_amdgcn_rsq(x);
-    const double h = 0.5 * x;
-    y = y * fma(-h * y, y, 1.5);
-    y = y * fma(-h * y, y, 1.5);
-    return y;
-}
-
-// largest-eigenvalue eigenvector of a symmetric 4x4 matrix by cyclic Jacobi
-__device__ __forceinline__ void jacobi4_top(double A[16], double q[4])
-{
-    double V[16];
+    double s = 0.0;
 #pragma unroll
-    for (int i = 0; i < 16; ++i) V[i] = (i % 5 == 0) ? 1.0 : 0.0;
-    for (int sweep = 0; sweep < 16; ++sweep) {
-        double off = 0.0, diag = 0.0;
+    for (int k = 0; k < 16; ++k) s = s + N[k] * N[k];
+    s = sqrt(s);
+    q[0] = 1.0; q[1] = 0.0; q[2] = 0.0; q[3] = 0.0;
+    if (!(s > 0.0)) return;
+    for (int it = 0; it < 200; ++it) {
+        double y[4];
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            diag += A[i * 4 + i] * A[i * 4 + i];
+        for (int i = 0; i < 4; ++i)
+            y[i] = ((N[i * 4] * q[0] + N[i * 4 + 1] * q[1]) + (N[i * 4 + 2] * q[2] + N[i * 4 + 3] * q[3])) + s * q[i];
+        const double n = sqrt(((y[0] * y[0] + y[1] * y[1]) + y[2] * y[2]) + y[3] * y[3]);
+        if (!(n > 0.0)) return;
 #pragma unroll
-            for (int j = i + 1; j < 4; ++j) off += A[i * 4 + j] * A[i * 4 + j];
-        }
-        if (!(off > 1e-30 * diag)) break;
-#pragma unroll
-        for (int p = 0; p < 3; ++p)
-#pragma unroll
-            for (int r = p + 1; r < 4; ++r) {
-                double apq = A[p * 4 + r];
-                if (apq == 0.0) continue;
-                const double tau = (A[r * 4 + r] - A[p * 4 + p]) * rcp_nr(2.0 * apq);
-                const double at = fabs(tau);
-                // t = sign(tau) / (|tau| + sqrt(1 + tau^2)), ~ 1 / (2 tau) for huge tau
-                double t;
-                if (at < 1e100) {
-                    const double x = fma(tau, tau, 1.0);
-                    t = rcp_nr(at + x * rsq_nr(x));
-                } else {
-                    t = rcp_nr(2.0 * at);
-                }
-                if (tau < 0.0) t = -t;
-                const double c = rsq_nr(fma(t, t, 1.0)), s = t * c;
-                // A <- J^T A J with J the rotation in the (p, r) plane
-#pragma unroll
-                for (int k = 0; k < 4; ++k) {
-                    double akp = A[k * 4 + p], akr = A[k * 4 + r];
-                    A[k * 4 + p] = c * akp - s * akr;
-                    A[k * 4 + r] = s * akp + c * akr;
-                }
-#pragma unroll
-                for (int k = 0; k < 4; ++k) {
-                    double apk = A[p * 4 + k], ark = A[r * 4 + k];
-                    A[p * 4 + k] = c * apk - s * ark;
-                    A[r * 4 + k] = s * apk + c * ark;
-                }
-#pragma unroll
-                for (int k = 0; k < 4; ++k) {
-                    double vkp = V[k * 4 + p], vkr = V[k * 4 + r];
-                    V[k * 4 + p] = c * vkp - s * vkr;
-                    V[k * 4 + r] = s * vkp + c * vkr;
-                }
-            }
+        for (int i = 0; i < 4; ++i) q[i] = y[i] / n;
     }
-    int best = 0;
+}
+
+// Horn's symmetric 4x4 matrix of the cross-covariance H (H[a][b] = sum of
+// centred c_a w_b): its top eigenvector is the quaternion of the rotation
+// that best maps the c onto the w
+__host__ __device__ __forceinline__ void horn_matrix(const double H[9], double N[16])
+{
+    const double Sxx = H[0], Sxy = H[1], Sxz = H[2], Syx = H[3], Syy = H[4], Syz = H[5], Szx = H[6], Szy = H[7],
+                 Szz = H[8];
+    N[0] = (Sxx + Syy) + Szz; N[1] = Syz - Szy;         N[2] = Szx - Sxz;          N[3] = Sxy - Syx;
+    N[4] = Syz - Szy;         N[5] = (Sxx - Syy) - Szz; N[6] = Sxy + Syx;          N[7] = Szx + Sxz;
+    N[8] = Szx - Sxz;         N[9] = Sxy + Syx;         N[10] = (-Sxx + Syy) - Szz; N[11] = Syz + Szy;
+    N[12] = Sxy - Syx;        N[13] = Szx + Sxz;        N[14] = Syz + Szy;         N[15] = (-Sxx - Syy) + Szz;
+}
+
+// determinant of rows r0 < r1 < r2 and columns c0 < c1 < c2 of a row-major 4x4
+__host__ __device__ __forceinline__ double det3_of(const double A[16], int r0, int r1, int r2, int c0, int c1, int c2)
+{
+    return (A[r0 * 4 + c0] * (A[r1 * 4 + c1] * A[r2 * 4 + c2] - A[r1 * 4 + c2] * A[r2 * 4 + c1]) -
+            A[r0 * 4 + c1] * (A[r1 * 4 + c0] * A[r2 * 4 + c2] - A[r1 * 4 + c2] * A[r2 * 4 + c0])) +
+           A[r0 * 4 + c2] * (A[r1 * 4 + c0] * A[r2 * 4 + c1] - A[r1 * 4 + c1] * A[r2 * 4 + c0]);
+}
+
+// the 3x3 minor of a 4x4 without row i and column j (i, j compile-time after unrolling)
+__host__ __device__ __forceinline__ double minor4(const double A[16], int i, int j)
+{
+    const int r0 = i == 0 ? 1 : 0, r1 = i <= 1 ? 2 : 1, r2 = i <= 2 ? 3 : 2;
+    const int c0 = j == 0 ? 1 : 0, c1 = j <= 1 ? 2 : 1, c2 = j <= 2 ? 3 : 2;
+    return det3_of(A, r0, r1, r2, c0, c1, c2);
+}
+
+// Largest-eigenvalue eigenvector of Horn's traceless 4x4 matrix N built from
+// the 3x3 cross-covariance H (Horn's quaternion method; the eigenvalue step is
+// the quaternion characteristic polynomial method of Theobald). The
+// eigenvalue is the largest root of
+// det(N - l I) = l^4 + c2 l^2 + c1 l + c0 with c2 = -2 |H|_F^2,
+// c1 = -8 det H, c0 = det N, reached by Newton's method from the upper bound
+// sqrt(3) |H|_F (every root is real, so the iterates decrease monotonically
+// onto it). A column of adj(N - l I) (the one on its largest diagonal entry)
+// gives the eigenvector, and one step of inverse iteration with
+// (N - l I), by elimination with partial pivoting, brings it to full
+// accuracy. Returns false when no such column exists or a value is not
+// finite (H = 0, or an exactly repeated largest eigenvalue).
+__host__ __device__ __forceinline__ bool top_eigvec_horn(const double N[16], const double H[9], double q[4])
+{
+    double hf2 = 0.0;
 #pragma unroll
-    for (int i = 1; i < 4; ++i)
-        if (A[i * 4 + i] > A[best * 4 + best]) best = i;
+    for (int k = 0; k < 9; ++k) hf2 = hf2 + H[k] * H[k];
+    const double c2 = -2.0 * hf2;
+    const double detH = (H[0] * (H[4] * H[8] - H[5] * H[7]) - H[1] * (H[3] * H[8] - H[5] * H[6])) +
+                        H[2] * (H[3] * H[7] - H[4] * H[6]);
+    const double c1 = -8.0 * detH;
+    double c0 = 0.0;
 #pragma unroll
-    for (int k = 0; k < 4; ++k) q[k] = V[k * 4 + best];
+    for (int j = 0; j < 4; ++j) c0 = c0 + ((j & 1) ? -N[j] : N[j]) * minor4(N, 0, j);
+    double lam = sqrt(3.0 * hf2);
+    if (!(lam > 0.0)) return false;
+    for (int it = 0; it < 64; ++it) {
+        const double l2 = lam * lam;
+        const double p = ((l2 + c2) * lam + c1) * lam + c0;
+        const double dp = (4.0 * l2 + 2.0 * c2) * lam + c1;
+        if (!(dp > 0.0)) break;
+        const double st = p / dp;
+        if (!(st > 1e-15 * lam)) {
+            if (st > 0.0) lam = lam - st;
+            break;
+        }
+        lam = lam - st;
+    }
+    double A[16];
+#pragma unroll
+    for (int k = 0; k < 16; ++k) A[k] = (k % 5 == 0) ? N[k] - lam : N[k];
+    // adjugate column on the largest diagonal cofactor
+    double d[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) d[j] = minor4(A, j, j);
+    int jm = 0;
+#pragma unroll
+    for (int j = 1; j < 4; ++j)
+        if (fabs(d[j]) > fabs(d[jm])) jm = j;
+    double v[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        double cij = 0.0;
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+            if (j == jm) cij = ((i + j) & 1) ? -minor4(A, i, j) : minor4(A, i, j);
+        v[i] = cij;
+    }
+    double vn = sqrt(((v[0] * v[0] + v[1] * v[1]) + v[2] * v[2]) + v[3] * v[3]);
+    if (!(vn > 0.0) || !(vn < INFINITY)) return false;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) v[i] = v[i] / vn;
+    // one step of inverse iteration: solve (N - l I) x = v
+    const double floor_ = 1e-17 * lam;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        int p = k;
+        double best = fabs(A[k * 4 + k]);
+#pragma unroll
+        for (int i = k + 1; i < 4; ++i)
+            if (fabs(A[i * 4 + k]) > best) {
+                best = fabs(A[i * 4 + k]);
+                p = i;
+            }
+#pragma unroll
+        for (int i = k + 1; i < 4; ++i) {
+            const bool sw = p == i;
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const double a = A[k * 4 + j], b = A[i * 4 + j];
+                A[k * 4 + j] = sw ? b : a;
+                A[i * 4 + j] = sw ? a : b;
+            }
+            const double a = v[k], b = v[i];
+            v[k] = sw ? b : a;
+            v[i] = sw ? a : b;
+        }
+        double piv = A[k * 4 + k];
+        if (fabs(piv) < floor_) piv = piv < 0.0 ? -floor_ : floor_;
+        A[k * 4 + k] = piv;
+#pragma unroll
+        for (int i = k + 1; i < 4; ++i) {
+            const double f = A[i * 4 + k] / piv;
+#pragma unroll
+            for (int j = k + 1; j < 4; ++j) A[i * 4 + j] = A[i * 4 + j] - f * A[k * 4 + j];
+            v[i] = v[i] - f * v[k];
+        }
+    }
+    double x[4];
+#pragma unroll
+    for (int k = 3; k >= 0; --k) {
+        double r = v[k];
+#pragma unroll
+        for (int j = k + 1; j < 4; ++j) r = r - A[k * 4 + j] * x[j];
+        x[k] = r / A[k * 4 + k];
+    }
+    double mx = fmax(fmax(fabs(x[0]), fabs(x[1])), fmax(fabs(x[2]), fabs(x[3])));
+    if (!(mx > 0.0) || !(mx < INFINITY)) return false;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) q[k] = x[k] / mx;
+    return true;
 }
 
 // Pose from sums. Succeeds when n >= 3 and the camera points are spread in two
@@ -332,14 +423,10 @@ __device__ __forceinline__ bool pose_from_sums(const double s[NSUM], double R[9]
     double I2 = ((S[0] * S[3] - S[1] * S[1]) + (S[0] * S[5] - S[2] * S[2])) + (S[3] * S[5] - S[4] * S[4]);
     double tr = (S[0] + S[3]) + S[5];
     if (!(I2 >= (1e-4 * n) * tr)) return false;
-    double Sxx = H[0], Sxy = H[1], Sxz = H[2], Syx = H[3], Syy = H[4], Syz = H[5], Szx = H[6], Szy = H[7],
-           Szz = H[8];
-    double N[16] = {Sxx + Syy + Szz, Syz - Szy,       Szx - Sxz,        Sxy - Syx,
-                    Syz - Szy,       Sxx - Syy - Szz, Sxy + Syx,        Szx + Sxz,
-                    Szx - Sxz,       Sxy + Syx,       -Sxx + Syy - Szz, Syz + Szy,
-                    Sxy - Syx,       Szx + Sxz,       Syz + Szy,        -Sxx - Syy + Szz};
+    double N[16];
+    horn_matrix(H, N);
     double q[4];
-    jacobi4_top(N, q);
+    if (!top_eigvec_horn(N, H, q)) power_top(N, q);
     double qn = sqrt(q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3]);
     double q0 = q[0] / qn, qx = q[1] / qn, qy = q[2] / qn, qz = q[3] / qn;
     R[0] = q0 * q0 + qx * qx - qy * qy - qz * qz;
@@ -401,7 +488,7 @@ struct Forest {
     Entry *res = nullptr;          // [T][L][R]
     uint32_t *stamp = nullptr;     // [T][L][R]
     Mode *modes = nullptr;         // [T][L][M]
-    uint32_t *mode_rgb = nullptr;  // [T][L][M] colour of each mode (compact copy for hypothesis picks)
+    uint32_t *mode_rgb = nullptr;  // [T][L][rgb_stride(M)] colour of each mode (compact copy for hypothesis picks)
     int32_t *nmodes = nullptr;     // [T][L]
     uint32_t *dirty = nullptr;     // [T][L]
     uint32_t *dirty_list = nullptr;
@@ -455,7 +542,7 @@ struct Attempt {
     int32_t *pos;                  // [N] position of a hypothesis in the live list when scored
     float4 *draws;                 // [B] camera point, pixel index bits
     float *gs;                     // [ceil(B / GROUP)][N] energy sum of each group of GROUP draws, per live position
-    uint16_t *inl;                 // [B][N] best-mode id of an inlier, 0xFFFF otherwise
+    int32_t *inl;                  // [B][N] global index (leaf * M + mode) of an inlier's best mode, -1 otherwise
     unsigned long long *stats;     // [0] mode evaluations [1] pair evaluations [2] round mode count
     int32_t *tr_alive;             // [MAX_ROUNDS][N]
     float *tr_energy;              // [MAX_ROUNDS][N]

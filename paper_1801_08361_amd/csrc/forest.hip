@@ -349,8 +349,8 @@ static inline size_t mode_smem(int cap) { return (size_t)7 * 4 * (cap > 0 ? cap 
 // forest (roots by pointer jumping); clusters of at least `minc` points are
 // ranked by (size descending, root ascending) and the first M become modes.
 __device__ void leaf_modes(const Entry *__restrict__ pts, int n, int n_total, int cap, const ModeParams mp,
-                           Mode *__restrict__ out, uint32_t *__restrict__ rgb_out, int32_t *__restrict__ n_out,
-                           char *smem)
+                           Mode *__restrict__ out, uint32_t *__restrict__ rgb_out, int rgb_len,
+                           int32_t *__restrict__ n_out, char *smem)
 {
     int32_t *X = (int32_t *)smem;
     int32_t *Y = X + cap;
@@ -496,6 +496,8 @@ __device__ void leaf_modes(const Entry *__restrict__ pts, int n, int n_total, in
                  ((uint32_t)(a[11] / (unsigned long long)nmm) << 16);
         out[tid] = md;
         if (rgb_out) rgb_out[tid] = md.rgb;
+    } else if (rgb_out && tid < rgb_len) {
+        rgb_out[tid] = RGB_NONE;
     }
     if (tid == 0) *n_out = nm;
     __syncthreads();
@@ -515,7 +517,8 @@ __global__ void __launch_bounds__(MODE_THREADS) k_modes(const uint32_t *__restri
         uint32_t li = list[it];
         uint32_t k = counter[li];
         int n = k < (uint32_t)mp.R ? (int)k : mp.R;
-        leaf_modes(res + (int64_t)li * mp.R, n, n, mp.R, mp, modes + (int64_t)li * mp.M, mode_rgb + (int64_t)li * mp.M,
+        const int ms = rgb_stride(mp.M);
+        leaf_modes(res + (int64_t)li * mp.R, n, n, mp.R, mp, modes + (int64_t)li * mp.M, mode_rgb + (int64_t)li * ms, ms,
                    nmodes + li, smem);
     }
 }
@@ -533,7 +536,7 @@ __global__ void __launch_bounds__(MODE_THREADS) k_modes_points(const Entry *__re
                                                                Mode *__restrict__ out, int32_t *__restrict__ n_out)
 {
     extern __shared__ char smem[];
-    leaf_modes(pts, n, n, n, mp, out, nullptr, n_out, smem);
+    leaf_modes(pts, n, n, n, mp, out, nullptr, 0, n_out, smem);
 }
 
 static ModeParams mode_params(const Forest *f)
@@ -659,7 +662,7 @@ static void forest_free(Forest *f)
     dfree(f, &f->kval, (size_t)f->T * f->cap_P);
     dfree(f, &f->chunk_cnt, (size_t)f->T * C * f->L);
     dfree(f, &f->chunk_pref, (size_t)f->T * C * f->L);
-    dfree(f, &f->mode_rgb, TL * f->M);
+    dfree(f, &f->mode_rgb, TL * rgb_stride(f->M));
 }
 
 extern "C" int reloc_forest_create(const reloc_params *p, void *stream, reloc_forest **out)
@@ -687,7 +690,7 @@ extern "C" int reloc_forest_create(const reloc_params *p, void *stream, reloc_fo
     rc |= dalloc(f, &f->dirty_list, TL, s);
     rc |= dalloc(f, &f->dirty_count, 1, s);
     rc |= dalloc(f, &f->total_samples, 1, s);
-    rc |= dalloc(f, &f->mode_rgb, TL * f->M, s);
+    rc |= dalloc(f, &f->mode_rgb, TL * rgb_stride(f->M), s);
     if (rc) {
         forest_free(f);
         delete f;
@@ -697,6 +700,7 @@ extern "C" int reloc_forest_create(const reloc_params *p, void *stream, reloc_fo
         hipMemsetAsync(f->stamp, 0, TL * f->R * sizeof(uint32_t), s) != hipSuccess ||
         hipMemsetAsync(f->res, 0, TL * f->R * sizeof(Entry), s) != hipSuccess ||
         hipMemsetAsync(f->nmodes, 0, TL * sizeof(int32_t), s) != hipSuccess ||
+        hipMemsetAsync(f->mode_rgb, 0xFF, TL * rgb_stride(f->M) * sizeof(uint32_t), s) != hipSuccess ||
         hipMemsetAsync(f->dirty, 0, TL * sizeof(uint32_t), s) != hipSuccess ||
         hipMemsetAsync(f->dirty_count, 0, sizeof(uint32_t), s) != hipSuccess ||
         hipMemsetAsync(f->total_samples, 0, sizeof(unsigned long long), s) != hipSuccess) {

@@ -3,21 +3,24 @@
 // batch of attempts (the plain call is a batch of one).
 //
 // Every stage is a persistent kernel over the stage's work units; attempt a
-// owns units [off[a], off[a+1]) (frame blocks, hypotheses, draw blocks,
-// (hypothesis block, draw chunk) pairs, survivors). A whole batch is one
-// captured HIP graph. Layout of the work inside an attempt:
+// owns units [off[a], off[a+1]) (frame blocks, hypotheses, (hypothesis block,
+// draw chunk) pairs, survivors). A whole batch is one captured HIP graph.
+// Layout of the work inside an attempt:
 //  - hypotheses: one wavefront per hypothesis, one lane per try; the first
 //    passing try (lowest lane, then lowest chunk of 64 tries) defines it;
-//  - scoring: one wavefront holds 64 live hypotheses (one per lane) and a
-//    chunk of draws; each draw's modes are staged once in LDS and read back
-//    as wave-uniform broadcasts while every lane evaluates its own pose;
-//    per-draw energies go to memory and the cull sums them in the defined
-//    order (groups of 8 draws);
-//  - cull: one workgroup per attempt sorts the live hypotheses by
-//    (energy, index) in LDS and keeps the first half, rounded up;
+//  - scoring: a workgroup holds 64 live hypotheses (one per lane) and a chunk
+//    of draws spread over its wavefronts; each wavefront draws its pixel,
+//    stages the pixel's modes once in LDS and reads them back as broadcasts
+//    while every lane evaluates its own pose; energies are summed per group
+//    of 8 draws in draw order and the group sums go to memory;
+//  - cull: one workgroup per attempt adds the group sums in group order,
+//    sorts the live hypotheses by (energy, index) in LDS and keeps the first
+//    half, rounded up;
 //  - refinement: one wavefront per survivor sums its inliers of the round
-//    (lanes over draws, xor butterfly), then one lane per survivor updates
-//    the running sums and re-aligns (Horn's method, FP64).
+//    (lanes over draws, xor butterfly) into its running sums and the pose is
+//    re-aligned from them (Horn's method, FP64), by lane 0 of that wavefront
+//    in small rounds or by one lane per survivor in a second kernel in large
+//    ones.
 #include <math.h>
 #include <stdio.h>
 #include <string.h>
@@ -245,42 +248,80 @@ __device__ __forceinline__ int pick_pool(const Attempt &A, int np, uint64_t u)
     return lo;
 }
 
+// Colour-consistent modes of one leaf as a bit mask: bit m is set when slot m
+// holds a mode whose colour is within tol of (pr, pg, pb) in every channel.
+// The row is read with 16-byte loads (rgb_stride(M) colours).
+__device__ __forceinline__ uint32_t colour_mask(const uint32_t *__restrict__ row, int Mp, uint32_t pr, uint32_t pg,
+                                                uint32_t pb, int tol)
+{
+    uint32_t mask = 0;
+    for (int q = 0; q < Mp; q += 4) {
+        const uint4 v = *(const uint4 *)(row + q);
+        const uint32_t c[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+        for (int e = 0; e < 4; ++e)
+            if (c[e] != RGB_NONE && rgb_close(c[e], pr, pg, pb, tol)) mask |= 1u << (q + e);
+    }
+    return mask;
+}
+
 // one try: draws, colour-consistent mode picks, FP32 checks, FP64 alignment
-// and residuals
+// and residuals. The pick of pixel j is the sel-th colour-consistent mode in
+// (tree, mode) order, sel = uniform_int(u, count). Loads are issued a stage at
+// a time (pool entries; pixel colours and depths; per pixel, its leaves and
+// then its mode colour rows; the three picked modes) so that each stage
+// waits once.
 __device__ bool try_hypothesis(const Attempt &A, int np, uint64_t h, uint64_t tau, double R[9], double t[3])
 {
     const U4 a = philox(h, tau, 0, 0, A.seed, TAG_HYP);
     const U4 b = philox(h, tau, 1, 0, A.seed, TAG_HYP);
-    int pi[3];
-    float c[3][3], w[3][3];
+    const int Mp = rgb_stride(A.M);
+    int pi[3], p[3];
+#pragma unroll
+    for (int j = 0; j < 3; ++j) pi[j] = pick_pool(A, np, a.x[j]);
+#pragma unroll
+    for (int j = 0; j < 3; ++j) p[j] = A.pool[pi[j]];
+    uint32_t pr[3], pg[3], pb[3], dep[3];
+#pragma unroll
     for (int j = 0; j < 3; ++j) {
-        pi[j] = pick_pool(A, np, a.x[j]);
-        const int p = A.pool[pi[j]];
-        const uint32_t pr = A.fr.rgb[p * 3], pg = A.fr.rgb[p * 3 + 1], pb = A.fr.rgb[p * 3 + 2];
-        int li[16], nm[16];
-        for (int tt = 0; tt < A.T; ++tt) li[tt] = tt * A.L + A.leaves[(int64_t)tt * A.P + p];
-        for (int tt = 0; tt < A.T; ++tt) nm[tt] = A.nmodes[li[tt]];
+        pr[j] = A.fr.rgb[p[j] * 3];
+        pg[j] = A.fr.rgb[p[j] * 3 + 1];
+        pb[j] = A.fr.rgb[p[j] * 3 + 2];
+        dep[j] = A.fr.depth[p[j]];
+    }
+    int64_t pick[3];
+    float c[3][3], w[3][3];
+#pragma unroll 1
+    for (int j = 0; j < 3; ++j) {
+        int li[16];
+#pragma unroll
+        for (int tt = 0; tt < 16; ++tt) li[tt] = tt < A.T ? tt * A.L + A.leaves[(int64_t)tt * A.P + p[j]] : 0;
+        uint32_t mask[16];
         int cnt = 0;
-        for (int tt = 0; tt < A.T; ++tt) {
-            const uint32_t *cr = A.mode_rgb + (int64_t)li[tt] * A.M;
-            for (int m = 0; m < nm[tt]; ++m) cnt += rgb_close(cr[m], pr, pg, pb, A.rgb_tol) ? 1 : 0;
+#pragma unroll
+        for (int tt = 0; tt < 16; ++tt) {
+            mask[tt] = tt < A.T ? colour_mask(A.mode_rgb + (int64_t)li[tt] * Mp, Mp, pr[j], pg[j], pb[j], A.rgb_tol)
+                                : 0u;
+            cnt += __popc(mask[tt]);
         }
         if (cnt == 0) return false;
         int sel = (int)uniform_int(b.x[j], (uint64_t)cnt);
-        int64_t pick = -1;
-        for (int tt = 0; tt < A.T && pick < 0; ++tt) {
-            const uint32_t *cr = A.mode_rgb + (int64_t)li[tt] * A.M;
-            for (int m = 0; m < nm[tt]; ++m)
-                if (rgb_close(cr[m], pr, pg, pb, A.rgb_tol)) {
-                    if (sel == 0) {
-                        pick = (int64_t)li[tt] * A.M + m;
-                        break;
-                    }
-                    sel--;
-                }
+        pick[j] = 0;
+#pragma unroll
+        for (int tt = 0; tt < 16; ++tt) {
+            const int k = __popc(mask[tt]);
+            if (sel >= 0 && sel < k) {
+                uint32_t mm = mask[tt];
+                for (int q = 0; q < sel; ++q) mm &= mm - 1u;
+                pick[j] = (int64_t)li[tt] * A.M + (__ffs(mm) - 1);
+            }
+            sel -= k;
         }
-        cam_point(A.fr, p % A.fr.W, p / A.fr.W, A.fr.depth[p], c[j]);
-        const Mode &md = A.modes[pick];
+        cam_point(A.fr, p[j] % A.fr.W, p[j] / A.fr.W, dep[j], c[j]);
+    }
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+        const Mode &md = A.modes[pick[j]];
         w[j][0] = md.mu[0];
         w[j][1] = md.mu[1];
         w[j][2] = md.mu[2];
@@ -393,7 +434,7 @@ __global__ void __launch_bounds__(1024) k_b_alive_init(const Attempt *__restrict
 // preemptive rounds
 // ---------------------------------------------------------------------------
 
-// LDS image of one mode: mu (3), sinv (6), kappa, id = tree * M + mode, pad
+// LDS image of one mode: mu (3), sinv (6), kappa, global mode index, pad
 constexpr int SMODE = 12;
 // LDS budget of the modes staged by one scoring workgroup
 constexpr size_t SCORE_LDS = 64 * 1024;
@@ -488,7 +529,7 @@ __global__ void __launch_bounds__(64 * GROUP) k_b_score(const Attempt *__restric
                     dst[3] = md.sinv[0]; dst[4] = md.sinv[1]; dst[5] = md.sinv[2];
                     dst[6] = md.sinv[3]; dst[7] = md.sinv[4]; dst[8] = md.sinv[5];
                     dst[9] = md.kappa;
-                    dst[10] = __int_as_float(tj * A.M + m);
+                    dst[10] = __int_as_float((tj * A.L + s_leaf[wv][tj]) * A.M + m);
                     dst[11] = 0.0f;
                 }
                 __syncthreads();
@@ -513,16 +554,14 @@ __global__ void __launch_bounds__(64 * GROUP) k_b_score(const Attempt *__restric
                         bj = j;
                     }
                 }
-                bool in = false;
-                uint16_t id = 0xFFFF;
+                int32_t gid = -1;
                 if (bj >= 0) {
                     const float *mb = sm + bj * SMODE;
                     const float d0 = y0 - mb[0], d1 = y1 - mb[1], d2 = y2 - mb[2];
-                    in = (d0 * d0 + d1 * d1) + d2 * d2 <= A.inl2;
-                    id = (uint16_t)__float_as_int(mb[10]);
+                    if ((d0 * d0 + d1 * d1) + d2 * d2 <= A.inl2) gid = __float_as_int(mb[10]);
                 }
                 s_e[slot][lane] = best < 0.0f ? best : 0.0f;
-                if (act && has) A.inl[(int64_t)i * A.N + ap] = in ? id : (uint16_t)0xFFFF;
+                if (act && has) A.inl[(int64_t)i * A.N + ap] = gid;
                 __syncthreads();
             }
             // the group's energy sum per lane, in draw order
@@ -599,60 +638,126 @@ __global__ void __launch_bounds__(CULL_THREADS) k_b_cull(const Attempt *__restri
     }
 }
 
-// One wavefront per survivor: this round's inliers, lane-strided in draw
-// order, combined by an xor butterfly (every lane ends with the same sums);
-// lane 0 adds them to the survivor's running sums and, with refinement on,
-// re-solves its pose from the totals (Kabsch on all of its inliers so far).
-__global__ void __launch_bounds__(64) k_b_refine(const Attempt *__restrict__ att, Stage S, int r)
+// Refinement of the survivors of round r. A survivor's inliers of the round
+// are summed by one wavefront: lane-strided in draw order, combined by an xor
+// butterfly (every lane ends with the same sums); lane 0 adds them to the
+// survivor's running sums. With refinement on, the pose is then re-solved
+// from the running sums (Kabsch on all of its inliers so far). Small rounds
+// run both steps in one kernel (the solve on lane 0 of each wavefront); large
+// rounds (batches) solve in a second kernel with one lane per survivor, so
+// that the solver's registers do not limit the occupancy of the sums. Both
+// forms do the same arithmetic.
+constexpr int RB = 8;              // draws per lane per load batch in refinement
+constexpr int FUSED_REFINE = 1024; // survivors up to which a round refines in one kernel
+
+// this round's inlier sums of survivor position sidx, added to its running
+// sums by lane 0; returns the hypothesis index
+__device__ __forceinline__ int refine_sums_of(const Attempt &A, int sidx, double s[NSUM])
 {
     const int lane = __lane_id();
+    const int h = A.alive[sidx];
+    const int ap = A.pos[h];
+#pragma unroll
+    for (int k = 0; k < NSUM; ++k) s[k] = 0.0;
+    // lane-strided draws, RB per lane at a time: all inlier ids first, then the
+    // camera points and mode means of the inliers, then the sums in draw order
+    for (int base = 0; base < A.B; base += 64 * RB) {
+        int32_t gid[RB];
+#pragma unroll
+        for (int k = 0; k < RB; ++k) {
+            const int i = base + k * 64 + lane;
+            gid[k] = i < A.B ? A.inl[(int64_t)i * A.N + ap] : -1;
+        }
+        float c[RB][3], w[RB][3];
+#pragma unroll
+        for (int k = 0; k < RB; ++k) {
+            if (gid[k] >= 0) {
+                const float4 dr = A.draws[base + k * 64 + lane];
+                const Mode &md = A.modes[gid[k]];
+                c[k][0] = dr.x; c[k][1] = dr.y; c[k][2] = dr.z;
+                w[k][0] = md.mu[0]; w[k][1] = md.mu[1]; w[k][2] = md.mu[2];
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < RB; ++k)
+            if (gid[k] >= 0) sums_add_point(s, c[k], w[k]);
+    }
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1)
+#pragma unroll
+        for (int k = 0; k < NSUM; ++k) s[k] = s[k] + __shfl_xor(s[k], o, 64);
+    if (lane == 0) {
+        double *run = A.sums + (int64_t)h * NSUM;
+#pragma unroll
+        for (int k = 0; k < NSUM; ++k) {
+            s[k] = run[k] + s[k];
+            run[k] = s[k];
+        }
+    }
+    return h;
+}
+
+// re-solves hypothesis h from its running sums s (refinement on)
+__device__ __forceinline__ void refine_solve_of(const Attempt &A, int h, const double s[NSUM])
+{
+    double R[9], t[3];
+    if (pose_from_sums(s, R, t)) {
+        Hyp &hy = A.hyp[h];
+        for (int k = 0; k < 9; ++k) {
+            hy.R[k] = R[k];
+            hy.R32[k] = (float)R[k];
+        }
+        for (int k = 0; k < 3; ++k) {
+            hy.t[k] = t[k];
+            hy.t32[k] = (float)t[k];
+        }
+    }
+}
+
+// sums and solve in one kernel: one wavefront per survivor
+__global__ void __launch_bounds__(64) k_b_refine(const Attempt *__restrict__ att, Stage S, int r)
+{
     FOR_UNITS(S, u) {
         const int a = attempt_of(S, u);
         const Attempt &A = att[a];
         if (A.misc[3] != r + 1) continue;
         const int sidx = u - S.off[a];
         if (sidx >= A.misc[1]) continue;
-        const int h = A.alive[sidx];
-        const int ap = A.pos[h];
         double s[NSUM];
+        const int h = refine_sums_of(A, sidx, s);
+        if (__lane_id() == 0 && A.refine) refine_solve_of(A, h, s);
+    }
+}
+
+// sums only: one wavefront per survivor
+__global__ void __launch_bounds__(64) k_b_refine_sums(const Attempt *__restrict__ att, Stage S, int r)
+{
+    FOR_UNITS(S, u) {
+        const int a = attempt_of(S, u);
+        const Attempt &A = att[a];
+        if (A.misc[3] != r + 1) continue;
+        const int sidx = u - S.off[a];
+        if (sidx >= A.misc[1]) continue;
+        double s[NSUM];
+        refine_sums_of(A, sidx, s);
+    }
+}
+
+// solve only: one lane per survivor
+__global__ void __launch_bounds__(64) k_b_refine_solve(const Attempt *__restrict__ att, Stage S, int r)
+{
+    FOR_UNITS(S, u) {
+        const int a = attempt_of(S, u);
+        const Attempt &A = att[a];
+        if (A.misc[3] != r + 1 || !A.refine) continue;
+        const int sidx = (u - S.off[a]) * 64 + __lane_id();
+        if (sidx >= A.misc[1]) continue;
+        const int h = A.alive[sidx];
+        double s[NSUM];
+        const double *run = A.sums + (int64_t)h * NSUM;
 #pragma unroll
-        for (int k = 0; k < NSUM; ++k) s[k] = 0.0;
-        for (int i = lane; i < A.B; i += 64) {
-            const uint16_t id = A.inl[(int64_t)i * A.N + ap];
-            if (id == 0xFFFF) continue;
-            const float4 dr = A.draws[i];
-            const int p = __float_as_int(dr.w);
-            const int tt = id / A.M, m = id % A.M;
-            const int li = tt * A.L + A.leaves[(int64_t)tt * A.P + p];
-            const Mode &md = A.modes[(int64_t)li * A.M + m];
-            const float c[3] = {dr.x, dr.y, dr.z};
-            const float w[3] = {md.mu[0], md.mu[1], md.mu[2]};
-            sums_add_point(s, c, w);
-        }
-#pragma unroll
-        for (int o = 32; o >= 1; o >>= 1)
-#pragma unroll
-            for (int k = 0; k < NSUM; ++k) s[k] = s[k] + __shfl_xor(s[k], o, 64);
-        if (lane == 0) {
-            double *run = A.sums + (int64_t)h * NSUM;
-#pragma unroll
-            for (int k = 0; k < NSUM; ++k) {
-                s[k] = run[k] + s[k];
-                run[k] = s[k];
-            }
-            double R[9], t[3];
-            if (A.refine && pose_from_sums(s, R, t)) {
-                Hyp &hy = A.hyp[h];
-                for (int k = 0; k < 9; ++k) {
-                    hy.R[k] = R[k];
-                    hy.R32[k] = (float)R[k];
-                }
-                for (int k = 0; k < 3; ++k) {
-                    hy.t[k] = t[k];
-                    hy.t32[k] = (float)t[k];
-                }
-            }
-        }
+        for (int k = 0; k < NSUM; ++k) s[k] = run[k];
+        refine_solve_of(A, h, s);
     }
 }
 
@@ -772,7 +877,7 @@ static size_t carve(const Shape &s, char *base, Attempt &A)
     A.pos = (int32_t *)take((size_t)s.N * 4);
     A.draws = (float4 *)take((size_t)s.B * 16);
     A.gs = (float *)take((size_t)((s.B + GROUP - 1) / GROUP) * s.N * 4);
-    A.inl = (uint16_t *)take((size_t)s.B * s.N * 2);
+    A.inl = (int32_t *)take((size_t)s.B * s.N * 4);
     A.stats = (unsigned long long *)take(3 * 8);
     A.tr_alive = (int32_t *)take((size_t)MAX_ROUNDS * s.N * 4);
     A.tr_energy = (float *)take((size_t)MAX_ROUNDS * s.N * 4);
@@ -797,15 +902,15 @@ static void free_plan(reloc_batch *b, Plan *pl)
 // stages of one schedule in launch order
 struct Stages {
     Stage pix, pb, att, hyp;
-    std::vector<Stage> score, refine;
+    std::vector<Stage> score, refine, solve;
 };
 
 // host offsets of every stage for schedule `sc`: pix, pb, att, hyp, then per
-// round (score, refine)
+// round (score, refine, solve)
 static std::vector<int32_t> offsets(const Plan *pl, const Sched &sc)
 {
     const int n = pl->n, R = pl->rounds;
-    const int n_stage = 4 + 2 * R;
+    const int n_stage = 4 + 3 * R;
     std::vector<int32_t> off((size_t)n_stage * (n + 1), 0);
     auto fill = [&](int k, auto units) {
         int32_t *o = off.data() + (size_t)k * (n + 1);
@@ -823,11 +928,12 @@ static std::vector<int32_t> offsets(const Plan *pl, const Sched &sc)
         return bnd;
     };
     for (int r = 0; r < R; ++r) {
-        fill(4 + 2 * r, [&](int a) {
+        fill(4 + 3 * r, [&](int a) {
             if (r >= rounds_for(pl->shape[a].N)) return 0;
             return ((bound(a, r) + 63) / 64) * ((pl->shape[a].B + sc.dpu - 1) / sc.dpu);
         });
-        fill(5 + 2 * r, [&](int a) { return r >= rounds_for(pl->shape[a].N) ? 0 : bound(a, r + 1); });
+        fill(5 + 3 * r, [&](int a) { return r >= rounds_for(pl->shape[a].N) ? 0 : bound(a, r + 1); });
+        fill(6 + 3 * r, [&](int a) { return r >= rounds_for(pl->shape[a].N) ? 0 : (bound(a, r + 1) + 63) / 64; });
     }
     return off;
 }
@@ -846,8 +952,9 @@ static Stages stages_of(const Plan *pl, const Sched &sc, const int32_t *d_off, c
     Stages st;
     st.pix = mk(0); st.pb = mk(1); st.att = mk(2); st.hyp = mk(3);
     for (int r = 0; r < pl->rounds; ++r) {
-        st.score.push_back(mk(4 + 2 * r));
-        st.refine.push_back(mk(5 + 2 * r));
+        st.score.push_back(mk(4 + 3 * r));
+        st.refine.push_back(mk(5 + 3 * r));
+        st.solve.push_back(mk(6 + 3 * r));
     }
     return st;
 }
@@ -880,8 +987,15 @@ static int enqueue(const Plan *pl, const Sched &sc, const Stages &st, hipStream_
         RL_LAUNCH("k_b_score", k_b_score, dim3(grid_of(st.score[r], sc.grid, sc.xcd)), dim3(64 * nw), smem, s, d,
                   st.score[r], r, sc.dpu, pl->tm_max);
         RL_LAUNCH("k_b_cull", k_b_cull, dim3(grid_of(att, cap, 0)), dim3(CULL_THREADS), 0, s, d, att, r);
-        RL_LAUNCH("k_b_refine", k_b_refine, dim3(grid_of(st.refine[r], 0, sc.xcd)), dim3(64), 0, s, d, st.refine[r],
-                  r);
+        if (st.refine[r].total <= FUSED_REFINE) {
+            RL_LAUNCH("k_b_refine", k_b_refine, dim3(grid_of(st.refine[r], 0, sc.xcd)), dim3(64), 0, s, d,
+                      st.refine[r], r);
+        } else {
+            RL_LAUNCH("k_b_refine_sums", k_b_refine_sums, dim3(grid_of(st.refine[r], 0, sc.xcd)), dim3(64), 0, s, d,
+                      st.refine[r], r);
+            RL_LAUNCH("k_b_refine_solve", k_b_refine_solve, dim3(grid_of(st.solve[r], 0, sc.xcd)), dim3(64), 0, s,
+                      d, st.solve[r], r);
+        }
     }
     RL_LAUNCH("k_b_finish", k_b_finish, dim3(grid_of(att, cap, 0)), dim3(64), 0, s, d, att);
     RL_HIP(hipGetLastError());
@@ -1266,6 +1380,25 @@ extern "C" int reloc_debug_unit_owners(int32_t xcd, int32_t total, int32_t grid,
             if (u < 0 || u >= total) return RELOC_E_STATE;
             owners_host[u]++;
         }
+    }
+    return RELOC_OK;
+}
+
+extern "C" int reloc_debug_horn(const double *h_host, int32_t n, double *q_host)
+{
+    if (n < 0 || (n > 0 && (!h_host || !q_host))) return RELOC_E_ARG;
+    for (int i = 0; i < n; ++i) {
+        const double *H = h_host + (size_t)i * 9;
+        double N[16];
+        horn_matrix(H, N);
+        double q[4];
+        if (top_eigvec_horn(N, H, q)) {
+            const double qn = sqrt(((q[0] * q[0] + q[1] * q[1]) + q[2] * q[2]) + q[3] * q[3]);
+            for (int k = 0; k < 4; ++k) q[k] = q[k] / qn;
+        } else {
+            for (int k = 0; k < 4; ++k) q[k] = NAN;
+        }
+        for (int k = 0; k < 4; ++k) q_host[(size_t)i * 4 + k] = q[k];
     }
     return RELOC_OK;
 }
