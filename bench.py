@@ -9,10 +9,13 @@ before the timed region. A step relocalises the 50 held-out query frames
 (one plain call each); `value` is relocalisations per second over the timed
 steps.
 
-Also reported (same JSON line, `forms`): the batched form on the mixed
-workload (64 attempts against 8 small-room forests, frame sizes drawn from
-320x240 / 480x360 / 640x480 and hypothesis counts from 256 / 512 / 1024), as
-one batched call versus 64 sequential plain calls.
+Also reported (same JSON line, `forms`): the learned proposal on the
+full-size forest (a network trained on the GPU from verified relocalisations
+of extra frames; learned picks at 256 and 64 hypotheses against uniform picks
+at 256, 64 and 1024), and the batched form on the mixed workload (64 attempts
+against 8 small-room forests, frame sizes drawn from 320x240 / 480x360 /
+640x480 and hypothesis counts from 256 / 512 / 1024) as one batched call
+versus 64 sequential plain calls, then batched + learned at 256 hypotheses.
 
 Per-kernel times come from a separate profiled pass over the same steps
 (HIP events around each launch on its stream; kernels are then launched one
@@ -21,11 +24,12 @@ its algorithmic FLOPs (25 per (hypothesis, draw, mode) energy term, 18 per
 (hypothesis, draw) transform, counted by the kernels themselves) over its
 average duration.
 
-Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-batched]
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-batched] [--no-learned]
 """
 from __future__ import annotations
 
 import argparse
+import gc
 import json
 import os
 import sys
@@ -162,7 +166,87 @@ def plain_full(args, dev):
                 "unit": "TFLOP/s", "frac": achieved / FP32_PEAK_TFLOPS, "traffic": None,
                 "avg_launch_us": avg_s * 1e6, "flops_per_launch": flops / sc_n}
     return dict(sc=sc, value=tot / wall, wall=wall, success=ok / max(tot, 1), n=tot, kernels=kernels, roof=roof,
-                adapt_fps=len(adapt) / t_adapt, modes_s=t_modes, mem=g.memory())
+                adapt_fps=len(adapt) / t_adapt, modes_s=t_modes, mem=g.memory(), forest=g, queries=queries)
+
+
+def train_from_verified(dev, items, max_pixels, seed, epochs):
+    """Rows from frames whose relocalised pose passes the depth-difference
+    check, and a network trained on them. items: (forest, scene, pose, tag)."""
+    import torch
+    from paper_1801_08361_amd import learned as L
+    t0 = time.time()
+    xs, ys = [], []
+    n_ver = 0
+    for forest, sc, T, tag in items:
+        d, c = sc.render_pose(T, noise_tag=tag, device=dev)
+        pose, _ = L.verified_pose(forest, d, c, sc.K, seed=tag, model_depth=lambda P: sc.model_depth(P, device=dev))
+        if pose is None:
+            continue
+        n_ver += 1
+        x, y = L.frame_rows(forest, d, c, sc.K, pose, max_pixels=max_pixels, seed=tag)
+        xs.append(x)
+        ys.append(y)
+    x, y = torch.cat(xs).contiguous(), torch.cat(ys).contiguous()
+    torch.cuda.synchronize()
+    t_rows = time.time() - t0
+    import paper_1801_08361_amd as rl
+    rl.profile_reset()
+    rl.profile_enable(True)
+    t0 = time.time()
+    m, losses = L.train(x, y, seed=seed, epochs=epochs, batch_rows=4096, lr=2e-3)
+    torch.cuda.synchronize()
+    t_train = time.time() - t0
+    rl.profile_enable(False)
+    fb_ms, fb_n = rl.profile_read("k_mlp_fwd_bwd")
+    rl.profile_reset()
+    info = {"frames": len(items), "verified": n_ver, "rows": int(y.numel()), "inlier_rate": float(y.float().mean()),
+            "epochs": epochs, "loss_first": float(losses[0]), "loss_last": float(losses[-1]),
+            "rows_s": round(t_rows, 2), "train_s": round(t_train, 2)}
+    if fb_n:
+        # 64-row tile: forward 2 x 64 x (32 x 64 + 64 x 64 + 64) FLOP, backward twice that
+        flop = 3 * 2 * 64 * (32 * 64 + 64 * 64 + 64)
+        us = fb_ms / fb_n * 1e3
+        info["k_mlp_fwd_bwd"] = {"avg_launch_us": us, "tiles_per_launch": 4096 // 64,
+                                 "achieved_tflops": flop * (4096 // 64) / (us * 1e-6) / 1e12,
+                                 "peak_tflops_bf16": 2500.0}
+    log(f"learned: {n_ver}/{len(items)} verified frames, {info['rows']} rows (inliers {info['inlier_rate']:.3f}), "
+        f"loss {info['loss_first']:.4f} -> {info['loss_last']:.4f}, rows {t_rows:.1f}s, training {t_train:.1f}s")
+    return m, info
+
+
+def learned_full(args, dev, full):
+    """The learned proposal on the full-size forest: a network trained from
+    24 extra frames of the same room whose relocalised poses pass the
+    depth-difference check, then the 50 held-out queries at 256 (and 64)
+    hypotheses with learned pick weights (computed inside the timed region)
+    against uniform picks at 256, 64 and 1024 hypotheses."""
+    import torch
+    sc, g, queries = full["sc"], full["forest"], full["queries"]
+    poses = sc.extra_poses(24, tag=1)
+    m, info = train_from_verified(dev, [(g, sc, T, 100 + k) for k, T in enumerate(poses)], 100_000, 1, 6)
+
+    def run(n_hyp, use):
+        out = []
+        for q, (d, c) in enumerate(queries):
+            w = m.pixel_weights(g, d, c, sc.K) if use else None
+            out.append(g.relocalise_ex(d, c, sc.K, seed=1 + q, n_hyp=n_hyp, weights=w))
+        return out
+
+    forms = {"training": info}
+    for name, n_hyp, use in (("learned_256", 256, True), ("uniform_256", 256, False), ("learned_64", 64, True),
+                             ("uniform_64", 64, False), ("uniform_1024", 1024, False)):
+        run(n_hyp, use)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for s in range(args.steps):
+            res = run(n_hyp, use)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        ok = sum(int(r["status"] == 0 and success(r["pose"], sc.query_poses[q])) for q, r in enumerate(res))
+        forms[name] = {"value": len(queries) * args.steps / wall, "unit": "relocalisations/s",
+                       "success_rate": ok / len(queries), "n_hypotheses": n_hyp}
+        log(f"{name}: {forms[name]['value']:.1f}/s, success {ok}/{len(queries)}")
+    return forms
 
 
 def batched_mixed(args, dev):
@@ -195,11 +279,14 @@ def batched_mixed(args, dev):
         b.run(att)
     log(f"batched schedule: {b.schedule()}")
     torch.cuda.synchronize()
-    t0 = time.perf_counter()
+    runs_b = []
     for s in range(args.steps):
+        t0 = time.perf_counter()
         res = b.run(att)
-    torch.cuda.synchronize()
-    wall_b = time.perf_counter() - t0
+        torch.cuda.synchronize()
+        runs_b.append(time.perf_counter() - t0)
+    wall_b = sum(runs_b)
+    log("batched runs (ms): " + " ".join(f"{t * 1e3:.2f}" for t in runs_b))
 
     def seq():
         return [a["forest"].relocalise_ex(a["depth"], a["rgb"], a["K"], seed=a["seed"], n_hyp=a["n_hyp"])
@@ -219,11 +306,42 @@ def batched_mixed(args, dev):
     n = len(att) * args.steps
     log(f"batched: {n / wall_b:.1f}/s vs sequential plain {n / wall_p:.1f}/s; identical={identical}; "
         f"success {ok}/{len(att)}")
-    return {"batched": {"value": n / wall_b, "unit": "relocalisations/s", "schedule": b.schedule()},
-            "sequential_plain": {"value": n / wall_p, "unit": "relocalisations/s"},
-            "speedup": wall_p / wall_b, "identical_to_plain": identical, "success_rate": ok / len(att),
-            "workload": "64 attempts, 8 forests (320x240 rooms, 5 trees depth 10, R=256, 20 frames each); "
-                        "frames 320x240/480x360/640x480, N in {256, 512, 1024}, B=64"}
+    out = {"batched": {"value": n / wall_b, "unit": "relocalisations/s", "schedule": b.schedule(),
+                       "success_rate": ok / len(att), "runs_ms": [round(t * 1e3, 3) for t in runs_b]},
+           "sequential_plain": {"value": n / wall_p, "unit": "relocalisations/s"},
+           "speedup": wall_p / wall_b, "identical_to_plain": identical, "success_rate": ok / len(att),
+           "workload": "64 attempts, 8 forests (320x240 rooms, 5 trees depth 10, R=256, 20 frames each); "
+                       "frames 320x240/480x360/640x480, N in {256, 512, 1024}, B=64"}
+
+    # batched + learned: one network for the 8 forests, trained from 3 extra
+    # verified frames per room; every attempt at 256 hypotheses with learned
+    # pick weights (computed inside the timed region)
+    items = [(forests[k], scenes[k], T, 200 + 10 * k + j) for k in range(n_forests)
+             for j, T in enumerate(scenes[k].extra_poses(3, tag=2))]
+    m, info = train_from_verified(dev, items, 60_000, 2, 6)
+    out["training"] = info
+
+    def with_weights(n_hyp, use):
+        lst = []
+        for a in att:
+            w = m.pixel_weights(a["forest"], a["depth"], a["rgb"], a["K"]) if use else None
+            lst.append(dict(a, n_hyp=n_hyp, weights=w))
+        return lst
+
+    for name, n_hyp, use in (("batched_learned_256", 256, True), ("batched_uniform_256", 256, False)):
+        bb = rl.Batch(tune=True)
+        bb.run(with_weights(n_hyp, use))
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for s in range(args.steps):
+            res = bb.run(with_weights(n_hyp, use))
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        ok = sum(int(r["status"] == 0 and success(r["pose"], gt)) for r, gt in zip(res, gts))
+        out[name] = {"value": n / wall, "unit": "relocalisations/s", "success_rate": ok / len(att),
+                     "schedule": bb.schedule()}
+        log(f"{name}: {n / wall:.1f}/s, success {ok}/{len(att)}")
+    return out
 
 
 def main():
@@ -233,6 +351,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--no-learned", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="first run one 256 MiB device-to-device copy kernel (reference for HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (every box here has one GPU)",
@@ -241,6 +362,19 @@ def main():
 
     import torch
     dev = torch.device("cuda:0")
+    # Python's cyclic garbage collector can pause the host thread for tens of
+    # milliseconds (measured: 35-45 ms) in the middle of a timed region; it is
+    # switched off for the run (reference counting still frees everything the
+    # bench allocates)
+    gc.collect()
+    gc.disable()
+    if args.copy_calibration:
+        src = torch.ones(1 << 26, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log("copy calibration: 268435456 bytes read, 268435456 bytes written by one copy kernel")
+        del src, dst
     full = plain_full(args, dev)
     out = {
         "metric": "relocalisations/sec at >=95% success (<=5cm/5deg), plain vs batched+learned",
@@ -260,6 +394,8 @@ def main():
         "forest_bytes": full["mem"],
     }
     forms = {"plain_full": {"value": full["value"], "unit": "relocalisations/s", "success_rate": full["success"]}}
+    if not args.no_learned:
+        forms["learned_full"] = learned_full(args, dev, full)
     if not args.no_batched:
         forms["mixed"] = batched_mixed(args, dev)
     out["forms"] = forms

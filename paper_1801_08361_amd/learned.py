@@ -1,7 +1,8 @@
 """Host side of the learned proposal: gathering labelled training rows from
 posed frames and turning a trained network into pick weights. Every per-pixel
-computation (inputs, labels, training, inference) runs in the library's
-kernels; this module only chooses pixels and concatenates device buffers.
+computation (inputs, labels, training, inference, verification) runs in the
+library's kernels; this module only chooses frames and pixels and
+concatenates device buffers.
 
 Supervision: a frame whose pose is known (an agent's own tracked frame, or a
 relocalisation accepted by the depth-difference check of Sec. 3.3.1,
@@ -9,11 +10,11 @@ Eqs. 3-4) labels each of its valid pixels 1 when one of the pixel's leaf modes
 lies within 5 cm of the pixel's world point, else 0."""
 from __future__ import annotations
 
-from typing import Iterable, Optional, Tuple
+from typing import Callable, Iterable, Optional, Tuple
 
 import numpy as np
 
-from . import Forest, Mlp, label_pixels, pixel_features
+from . import Forest, Mlp, label_pixels, pixel_features, verify
 
 
 def valid_pixels(depth, depth_min: int, depth_max: int):
@@ -50,6 +51,19 @@ def training_rows(forest: Forest, frames: Iterable[tuple], max_pixels: Optional[
     if not xs:
         raise ValueError("no frames")
     return torch.cat(xs).contiguous(), torch.cat(ys).contiguous()
+
+
+def verified_pose(forest: Forest, depth, rgb, K, seed: int, model_depth: Callable, n_hyp: int = 0):
+    """Relocalises a frame and checks the result as the paper does before
+    trusting it (Sec. 3.3.1, Eqs. 3-4): the frame's depth against the scene
+    model's depth rendered at the proposed pose (`model_depth(pose)` returns a
+    device uint16 image of the same size). Returns (pose or None, result)."""
+    r = forest.relocalise_ex(depth, rgb, K, seed=seed, n_hyp=n_hyp)
+    if r["status"] != 0:
+        return None, r
+    vf, mu, ok = verify(depth, model_depth(r["pose"]))
+    r["verify"] = (vf, mu, ok)
+    return (r["pose"] if ok else None), r
 
 
 def train(x, y, seed: int = 1, epochs: int = 8, batch_rows: int = 4096, lr: float = 2e-3) -> Tuple[Mlp, np.ndarray]:

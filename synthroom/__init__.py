@@ -326,6 +326,24 @@ class Scene:
         return render(self.room, self.query_poses[k], w, h, device, self.noise_rel,
                       sub_seed(self.seed, 2, k))
 
+    def extra_poses(self, n: int, tag: int = 0) -> np.ndarray:
+        """A second camera path of n poses in the same room (for frames that
+        neither adapt the forest nor serve as held-out queries)."""
+        return make_trajectory(self.room, n, sub_seed(self.seed, 13, tag))
+
+    def render_pose(self, pose: np.ndarray, noise_tag: int, device="cpu", width=None, height=None):
+        """A sensor frame (with the scene's depth noise) from an arbitrary pose."""
+        w = width or self.width
+        h = height or self.height
+        return render(self.room, pose, w, h, device, self.noise_rel, sub_seed(self.seed, 3, noise_tag))
+
+    def model_depth(self, pose: np.ndarray, device="cpu", width=None, height=None):
+        """Noise-free depth of the room model from `pose` (the rendering a
+        proposed pose is verified against)."""
+        w = width or self.width
+        h = height or self.height
+        return render(self.room, pose, w, h, device, 0.0, 0)[0]
+
 
 def small_scene(index: int, width: int = 320, height: int = 240) -> Scene:
     """Single-relocalisation workload: a 5 x 4 x 2.7 m room with 6 boxes, a
