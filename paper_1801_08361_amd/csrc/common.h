@@ -166,18 +166,44 @@ __device__ __forceinline__ void cam_point(const Frame &fr, int u, int v, uint32_
     c[2] = z;
 }
 
+// The divisor of a pixel's probe offsets, d * F_ref, with its FP64 reciprocal
+struct PixelDen {
+    int32_t den;
+    double rden;
+};
+
+__device__ __forceinline__ PixelDen pixel_den(const Frame &fr, int32_t d)
+{
+    PixelDen p;
+    p.den = d * fr.Fref;
+    p.rden = 1.0 / (double)p.den;
+    return p;
+}
+
+// trunc(n / den) exactly, for |n| < 2^31 and 0 < den < 2^31: the FP64
+// estimate |n| * (1 / den) is within 2^-20 / den of the quotient, so its
+// truncation is the quotient or one less, and one integer check settles it
+// (the products stay below 2^32)
+__device__ __forceinline__ int32_t div_trunc(int32_t n, const PixelDen &p)
+{
+    const uint32_t an = (uint32_t)(n < 0 ? -n : n);
+    const uint32_t q0 = (uint32_t)((double)an * p.rden);
+    const uint32_t prod = q0 * (uint32_t)p.den;
+    const uint32_t q = prod > an ? q0 - 1u : (an - prod >= (uint32_t)p.den ? q0 + 1u : q0);
+    return n < 0 ? -(int32_t)q : (int32_t)q;
+}
+
 // Response of a packed node at pixel (u, v) with valid depth d (mm). The probe
 // offset is trunc(delta * F / (d * F_ref)); all products fit in 32 bits (the
 // host checks |delta| * F < 2^31). Depth probes outside the image or on an
 // invalid depth read 65535; colour probes clamp to the border.
-__device__ __forceinline__ int32_t node_response(const Frame &fr, uint64_t w, int u, int v, int32_t d,
-                                                 int32_t &thr)
+__device__ __forceinline__ int32_t node_response_d(const Frame &fr, uint64_t w, int u, int v, int32_t d,
+                                                   const PixelDen &pd, int32_t &thr)
 {
     int32_t kind, dx, dy;
     unpack_node(w, kind, dx, dy, thr);
-    int32_t den = d * fr.Fref;
-    int32_t qx = u + (dx * fr.Fx) / den;
-    int32_t qy = v + (dy * fr.Fy) / den;
+    int32_t qx = u + div_trunc(dx * fr.Fx, pd);
+    int32_t qy = v + div_trunc(dy * fr.Fy, pd);
     if (kind == 0) {
         int32_t dq = 65535;
         if (qx >= 0 && qx < fr.W && qy >= 0 && qy < fr.H) {
@@ -192,15 +218,113 @@ __device__ __forceinline__ int32_t node_response(const Frame &fr, uint64_t w, in
     return (int32_t)fr.rgb[(qy * fr.W + qx) * 3 + c] - (int32_t)fr.rgb[(v * fr.W + u) * 3 + c];
 }
 
+__device__ __forceinline__ int32_t node_response(const Frame &fr, uint64_t w, int u, int v, int32_t d,
+                                                 int32_t &thr)
+{
+    return node_response_d(fr, w, u, v, d, pixel_den(fr, d), thr);
+}
+
 // implicit heap: children of node i are 2i+1 (left) and 2i+2 (right); go
 // right iff response >= threshold; leaf = i - (L - 1)
-__device__ __forceinline__ int32_t traverse(const uint64_t *__restrict__ tree, int32_t L, const Frame &fr, int u,
-                                            int v, int32_t d)
+__device__ __forceinline__ int32_t traverse_d(const uint64_t *__restrict__ tree, int32_t L, const Frame &fr, int u,
+                                              int v, int32_t d, const PixelDen &pd)
 {
     int32_t i = 0;
     while (i < L - 1) {
         int32_t thr;
-        int32_t r = node_response(fr, tree[i], u, v, d, thr);
+        int32_t r = node_response_d(fr, tree[i], u, v, d, pd, thr);
+        i = 2 * i + 1 + (r >= thr ? 1 : 0);
+    }
+    return i - (L - 1);
+}
+
+__device__ __forceinline__ int32_t traverse(const uint64_t *__restrict__ tree, int32_t L, const Frame &fr, int u,
+                                            int v, int32_t d)
+{
+    return traverse_d(tree, L, fr, u, v, d, pixel_den(fr, d));
+}
+
+// ---------------------------------------------------------------------------
+// whole-frame traversal: the workgroup keeps the top levels of its tree in
+// LDS, unpacked and with the offsets already multiplied by the frame's focal
+// lengths; each pixel's divisor and own colour are set up once
+// ---------------------------------------------------------------------------
+
+constexpr int TOP_NODES = 1023;   // levels 0..9, 16 KB unpacked
+
+struct TopNode {
+    int32_t dxF, dyF, thr, kind;
+};
+
+__device__ __forceinline__ void stage_top(TopNode *__restrict__ top, const uint64_t *__restrict__ tree, int ntop,
+                                          const Frame &fr, int tid, int nthreads)
+{
+    for (int k = tid; k < ntop; k += nthreads) {
+        int32_t kind, dx, dy, thr;
+        unpack_node(tree[k], kind, dx, dy, thr);
+        TopNode n;
+        n.dxF = dx * fr.Fx;
+        n.dyF = dy * fr.Fy;
+        n.thr = thr;
+        n.kind = kind;
+        top[k] = n;
+    }
+}
+
+struct PixelCtx {
+    int32_t u, v, d;
+    PixelDen pd;
+    uint32_t own;   // the pixel's own colour, r | g << 8 | b << 16
+};
+
+__device__ __forceinline__ PixelCtx pixel_ctx(const Frame &fr, int u, int v, int32_t d)
+{
+    PixelCtx px;
+    px.u = u;
+    px.v = v;
+    px.d = d;
+    px.pd = pixel_den(fr, d);
+    const int o = (v * fr.W + u) * 3;
+    px.own = (uint32_t)fr.rgb[o] | ((uint32_t)fr.rgb[o + 1] << 8) | ((uint32_t)fr.rgb[o + 2] << 16);
+    return px;
+}
+
+// node_response for offsets already multiplied by the focal lengths
+__device__ __forceinline__ int32_t response_scaled(const Frame &fr, const PixelCtx &px, int32_t dxF, int32_t dyF,
+                                                   int32_t kind)
+{
+    int32_t qx = px.u + div_trunc(dxF, px.pd);
+    int32_t qy = px.v + div_trunc(dyF, px.pd);
+    if (kind == 0) {
+        int32_t dq = 65535;
+        if (qx >= 0 && qx < fr.W && qy >= 0 && qy < fr.H) {
+            const uint32_t z = fr.depth[qy * fr.W + qx];
+            if (valid_depth(fr, z)) dq = (int32_t)z;
+        }
+        return dq - px.d;
+    }
+    qx = qx < 0 ? 0 : (qx > fr.W - 1 ? fr.W - 1 : qx);
+    qy = qy < 0 ? 0 : (qy > fr.H - 1 ? fr.H - 1 : qy);
+    const int32_t own = (int32_t)((px.own >> (8 * (kind - 1))) & 255u);
+    return (int32_t)fr.rgb[(qy * fr.W + qx) * 3 + kind - 1] - own;
+}
+
+// traversal with nodes [0, ntop) (whole top levels) read from the LDS copy
+__device__ __forceinline__ int32_t traverse_top(const TopNode *__restrict__ top, int32_t ntop,
+                                                const uint64_t *__restrict__ tree, int32_t L, const Frame &fr, int u,
+                                                int v, int32_t d)
+{
+    const PixelCtx px = pixel_ctx(fr, u, v, d);
+    int32_t i = 0;
+    while (i < ntop) {
+        const TopNode n = top[i];
+        const int32_t r = response_scaled(fr, px, n.dxF, n.dyF, n.kind);
+        i = 2 * i + 1 + (r >= n.thr ? 1 : 0);
+    }
+    while (i < L - 1) {
+        int32_t kind, dx, dy, thr;
+        unpack_node(tree[i], kind, dx, dy, thr);
+        const int32_t r = response_scaled(fr, px, dx * fr.Fx, dy * fr.Fy, kind);
         i = 2 * i + 1 + (r >= thr ? 1 : 0);
     }
     return i - (L - 1);

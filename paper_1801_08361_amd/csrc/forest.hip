@@ -149,18 +149,25 @@ __global__ void k_gen_nodes(uint64_t *nodes, int T, int L, uint64_t seed, int32_
 // kernels: features and traversal
 // ---------------------------------------------------------------------------
 
-__global__ void k_leaves(const uint64_t *__restrict__ nodes, int T, int L, Frame fr, int32_t *__restrict__ leaves)
+// one thread per (pixel, tree): blockIdx.y is the tree, so the trees' node
+// chains run side by side instead of one after another
+__global__ void __launch_bounds__(256) k_leaves(const uint64_t *__restrict__ nodes, int T, int L, Frame fr,
+                                                int32_t *__restrict__ leaves)
 {
-    int P = fr.W * fr.H;
-    int p = blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= P) return;
+    __shared__ TopNode top[TOP_NODES];
+    const int P = fr.W * fr.H;
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    const int t = blockIdx.y;
+    const uint64_t *tree = nodes + (int64_t)t * (L - 1);
+    const int ntop = L - 1 < TOP_NODES ? L - 1 : TOP_NODES;
+    stage_top(top, tree, ntop, fr, (int)threadIdx.x, (int)blockDim.x);
+    __syncthreads();
+    if (p >= P || t >= T) return;
     int u = p % fr.W, v = p / fr.W;
     uint32_t d = fr.depth[p];
-    bool ok = valid_depth(fr, d);
-    for (int t = 0; t < T; ++t) {
-        int32_t leaf = ok ? traverse(nodes + (int64_t)t * (L - 1), L, fr, u, v, (int32_t)d) : -1;
-        leaves[(int64_t)t * P + p] = leaf;
-    }
+    int32_t leaf = -1;
+    if (valid_depth(fr, d)) leaf = traverse_top(top, ntop, tree, L, fr, u, v, (int32_t)d);
+    leaves[(int64_t)t * P + p] = leaf;
 }
 
 __global__ void k_features8(const uint64_t *__restrict__ extra, Frame fr, int32_t *__restrict__ feat)
@@ -171,9 +178,14 @@ __global__ void k_features8(const uint64_t *__restrict__ extra, Frame fr, int32_
     int u = p % fr.W, v = p / fr.W;
     uint32_t d = fr.depth[p];
     bool ok = valid_depth(fr, d);
+    if (!ok) {
+        for (int j = 0; j < 8; ++j) feat[(int64_t)p * 8 + j] = 0;
+        return;
+    }
+    const PixelDen pd = pixel_den(fr, (int32_t)d);
     for (int j = 0; j < 8; ++j) {
         int32_t thr;
-        feat[(int64_t)p * 8 + j] = ok ? node_response(fr, extra[j], u, v, (int32_t)d, thr) : 0;
+        feat[(int64_t)p * 8 + j] = node_response_d(fr, extra[j], u, v, (int32_t)d, pd, thr);
     }
 }
 
@@ -599,8 +611,8 @@ int traverse_frame(Forest *f, const Frame &fr, hipStream_t s)
     int64_t P = (int64_t)fr.W * fr.H;
     int rc = ensure_frame_scratch(f, P, s);
     if (rc) return rc;
-    RL_LAUNCH("k_leaves", k_leaves, dim3((unsigned)((P + 255) / 256)), dim3(256), 0, s, f->nodes, f->T, f->L, fr,
-                       f->leaves);
+    RL_LAUNCH("k_leaves", k_leaves, dim3((unsigned)((P + 255) / 256), (unsigned)f->T), dim3(256), 0, s, f->nodes,
+              f->T, f->L, fr, f->leaves);
     RL_HIP(hipGetLastError());
     return RELOC_OK;
 }

@@ -395,10 +395,11 @@ __device__ void pixel_features(const FeatArgs &A, int p, float x[24])
     if (!valid_depth(A.fr, d)) return;
     const int u = p % A.fr.W, v = p / A.fr.W;
     x[0] = (float)d / 5000.0f;
+    const PixelDen pd = pixel_den(A.fr, (int32_t)d);
     const uint64_t *extra = A.nodes + (int64_t)A.T * (A.L - 1);
     for (int j = 0; j < 8; ++j) {
         int32_t thr;
-        int32_t r = node_response(A.fr, extra[j], u, v, (int32_t)d, thr);
+        int32_t r = node_response_d(A.fr, extra[j], u, v, (int32_t)d, pd, thr);
         if ((extra[j] & 3u) == 0) {
             r = r > 5000 ? 5000 : (r < -5000 ? -5000 : r);
             x[1 + j] = (float)r / 1000.0f;
@@ -410,7 +411,7 @@ __device__ void pixel_features(const FeatArgs &A, int p, float x[24])
     int64_t best_m[3] = {-1, -1, -1};
     int64_t fill = 0;
     for (int t = 0; t < A.T; ++t) {
-        const int32_t leaf = traverse(A.nodes + (int64_t)t * (A.L - 1), A.L, A.fr, u, v, (int32_t)d);
+        const int32_t leaf = traverse_d(A.nodes + (int64_t)t * (A.L - 1), A.L, A.fr, u, v, (int32_t)d, pd);
         const int64_t li = (int64_t)t * A.L + leaf;
         const uint32_t k = A.counter[li];
         const uint32_t cap = k < (uint32_t)A.R ? k : (uint32_t)A.R;

@@ -60,21 +60,38 @@ __device__ __forceinline__ bool round_active(const Attempt &A, int r)
 // features and traversal of every pixel
 // ---------------------------------------------------------------------------
 
+// unit = (tree, block of PIX_BLOCK pixels): one thread per (pixel, tree), so
+// the trees' node chains run side by side
+// The workgroup keeps the top levels of its unit's tree in LDS, scaled for
+// the attempt's frame (restaged only when the (attempt, tree) pair changes
+// between its units).
 __global__ void __launch_bounds__(PIX_BLOCK) k_b_leaves(const Attempt *__restrict__ att, Stage S)
 {
+    __shared__ TopNode top[TOP_NODES];
+    int cached_a = -1, cached_t = -1;
     FOR_UNITS(S, u) {
         const int a = attempt_of(S, u);
         const Attempt &A = att[a];
-        const int p = (u - S.off[a]) * PIX_BLOCK + (int)threadIdx.x;
-        if (p >= A.P) continue;
+        const int nb = (A.P + PIX_BLOCK - 1) / PIX_BLOCK;
+        const int local = u - S.off[a];
+        const int t = local / nb;
+        const uint64_t *tree = A.nodes + (int64_t)t * (A.L - 1);
+        const int ntop = A.L - 1 < TOP_NODES ? A.L - 1 : TOP_NODES;
         const Frame fr = A.fr;
+        if (a != cached_a || t != cached_t) {
+            __syncthreads();
+            stage_top(top, tree, ntop, fr, (int)threadIdx.x, PIX_BLOCK);
+            __syncthreads();
+            cached_a = a;
+            cached_t = t;
+        }
+        const int p = (local % nb) * PIX_BLOCK + (int)threadIdx.x;
+        if (p >= A.P) continue;
         const int uu = p % fr.W, vv = p / fr.W;
         const uint32_t d = fr.depth[p];
-        const bool ok = valid_depth(fr, d);
-        for (int t = 0; t < A.T; ++t) {
-            int32_t leaf = ok ? traverse(A.nodes + (int64_t)t * (A.L - 1), A.L, fr, uu, vv, (int32_t)d) : -1;
-            A.leaves[(int64_t)t * A.P + p] = leaf;
-        }
+        int32_t leaf = -1;
+        if (valid_depth(fr, d)) leaf = traverse_top(top, ntop, tree, A.L, fr, uu, vv, (int32_t)d);
+        A.leaves[(int64_t)t * A.P + p] = leaf;
     }
 }
 
@@ -918,7 +935,7 @@ static std::vector<int32_t> offsets(const Plan *pl, const Sched &sc)
         for (int a = 0; a < n; ++a) o[a + 1] = o[a] + units(a);
     };
     auto P = [&](int a) { return (int64_t)pl->shape[a].W * pl->shape[a].H; };
-    fill(0, [&](int a) { return (int)((P(a) + PIX_BLOCK - 1) / PIX_BLOCK); });
+    fill(0, [&](int a) { return pl->shape[a].T * (int)((P(a) + PIX_BLOCK - 1) / PIX_BLOCK); });
     fill(1, [&](int a) { return (int)((P(a) + POOL_BLOCK - 1) / POOL_BLOCK); });
     fill(2, [&](int) { return 1; });
     fill(3, [&](int a) { return pl->shape[a].N; });
