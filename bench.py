@@ -218,19 +218,18 @@ def learned_full(args, dev, full):
     """The learned proposal on the full-size forest: a network trained from
     24 extra frames of the same room whose relocalised poses pass the
     depth-difference check, then the 50 held-out queries at 256 (and 64)
-    hypotheses with learned pick weights (computed inside the timed region)
-    against uniform picks at 256, 64 and 1024 hypotheses."""
+    hypotheses with learned pick weights (computed inside the relocalisation
+    graph, so inside the timed region) against uniform picks at 256, 64 and
+    1024 hypotheses."""
     import torch
     sc, g, queries = full["sc"], full["forest"], full["queries"]
     poses = sc.extra_poses(24, tag=1)
     m, info = train_from_verified(dev, [(g, sc, T, 100 + k) for k, T in enumerate(poses)], 100_000, 1, 6)
 
     def run(n_hyp, use):
-        out = []
-        for q, (d, c) in enumerate(queries):
-            w = m.pixel_weights(g, d, c, sc.K) if use else None
-            out.append(g.relocalise_ex(d, c, sc.K, seed=1 + q, n_hyp=n_hyp, weights=w))
-        return out
+        if use:   # pick weights computed inside the relocalisation graph
+            return [g.relocalise_learned(m, d, c, sc.K, seed=1 + q, n_hyp=n_hyp) for q, (d, c) in enumerate(queries)]
+        return [g.relocalise_ex(d, c, sc.K, seed=1 + q, n_hyp=n_hyp) for q, (d, c) in enumerate(queries)]
 
     forms = {"training": info}
     for name, n_hyp, use in (("learned_256", 256, True), ("uniform_256", 256, False), ("learned_64", 64, True),
@@ -315,18 +314,15 @@ def batched_mixed(args, dev):
 
     # batched + learned: one network for the 8 forests, trained from 3 extra
     # verified frames per room; every attempt at 256 hypotheses with learned
-    # pick weights (computed inside the timed region)
+    # pick weights (computed inside the batch graph)
     items = [(forests[k], scenes[k], T, 200 + 10 * k + j) for k in range(n_forests)
              for j, T in enumerate(scenes[k].extra_poses(3, tag=2))]
     m, info = train_from_verified(dev, items, 60_000, 2, 6)
     out["training"] = info
 
     def with_weights(n_hyp, use):
-        lst = []
-        for a in att:
-            w = m.pixel_weights(a["forest"], a["depth"], a["rgb"], a["K"]) if use else None
-            lst.append(dict(a, n_hyp=n_hyp, weights=w))
-        return lst
+        # learned: the batch computes each attempt's pick weights itself
+        return [dict(a, n_hyp=n_hyp, proposal=m) if use else dict(a, n_hyp=n_hyp) for a in att]
 
     for name, n_hyp, use in (("batched_learned_256", 256, True), ("batched_uniform_256", 256, False)):
         bb = rl.Batch(tune=True)

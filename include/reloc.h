@@ -164,6 +164,10 @@ typedef struct {
     uint64_t seed;                     /* attempt seed (hypothesis and pixel draws) */
     int32_t n_hypotheses;              /* <= 0: the forest's parameter */
     const uint32_t *pixel_weights_dev; /* device [H*W] pick weights, or NULL for uniform picks */
+    const struct reloc_mlp *proposal;  /* learned proposal computed inside the batch from the
+                                          attempt's own leaves (same weights as
+                                          reloc_mlp_pixel_weights), or NULL; not together
+                                          with pixel_weights_dev (RELOC_E_ARG) */
 } reloc_attempt;
 
 typedef struct reloc_batch reloc_batch;
@@ -260,6 +264,15 @@ int reloc_mlp_gradient(reloc_mlp *m, const uint16_t *x_dev, const uint8_t *y_dev
  * given, stream-asynchronous otherwise. */
 int reloc_mlp_train(reloc_mlp *m, const uint16_t *x_dev, const uint8_t *y_dev, int32_t n_rows, int32_t epochs,
                     int32_t batch_rows, float lr, uint64_t seed, float *epoch_loss_host, void *stream);
+/* reloc_relocalise_ex with the learned proposal: the pick weights are
+ * computed from the attempt's own leaves inside the same graph (no second
+ * traversal); the result equals reloc_relocalise_ex with the weights of
+ * reloc_mlp_pixel_weights for the same network and frame. The network must
+ * stay alive until the call returns (it is synchronous). */
+int reloc_relocalise_learned(reloc_forest *f, const reloc_mlp *m, const uint16_t *depth_dev,
+                             const uint8_t *rgb_dev, const reloc_intrinsics *K, uint64_t attempt_seed,
+                             int32_t n_hypotheses, reloc_result *result_out, void *stream);
+
 /* logits z_dev [n] of rows x_dev [n][32] */
 int reloc_mlp_logits(reloc_mlp *m, const uint16_t *x_dev, int32_t n, float *z_dev, void *stream);
 /* pick weights weights_dev [H*W] (0 for invalid pixels) and, if prob_dev is

@@ -76,7 +76,7 @@ class reloc_result(C.Structure):
 class reloc_attempt(C.Structure):
     _fields_ = [("forest", C.c_void_p), ("depth_dev", C.c_void_p), ("rgb_dev", C.c_void_p),
                 ("K", reloc_intrinsics), ("seed", C.c_uint64), ("n_hypotheses", C.c_int32),
-                ("pixel_weights_dev", C.c_void_p)]
+                ("pixel_weights_dev", C.c_void_p), ("proposal", C.c_void_p)]
 
 
 ENTRY_DTYPE = np.dtype([("x", "<i4"), ("y", "<i4"), ("z", "<i4"), ("r", "u1"), ("g", "u1"), ("b", "u1"),
@@ -136,6 +136,8 @@ _SIGS = {
                            C.c_void_p, C.c_void_p],
     "reloc_debug_mfma_probe": [C.c_void_p, C.c_void_p, C.c_void_p],
     "reloc_debug_horn": [C.c_void_p, C.c_int32, C.c_void_p],
+    "reloc_relocalise_learned": [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_uint64, C.c_int32,
+                                 C.c_void_p, C.c_void_p],
 }
 
 MLP_NPARAM = 5825
@@ -303,6 +305,16 @@ class Forest:
         _check(rc, "reloc_relocalise_ex")
         return res.as_dict()
 
+    def relocalise_learned(self, mlp: "Mlp", depth, rgb, K, seed: int, n_hyp: int = 0, stream=None) -> dict:
+        """One attempt with the learned proposal computed inside the graph
+        (reloc_relocalise_learned)."""
+        d, c, k = _frame(depth, rgb, K)
+        res = reloc_result()
+        rc = lib().reloc_relocalise_learned(self._h, mlp.handle, d, c, C.byref(k), C.c_uint64(seed), int(n_hyp),
+                                            C.byref(res), _stream(stream))
+        _check(rc, "reloc_relocalise_learned")
+        return res.as_dict()
+
     def drop_reservoirs(self, stream=None) -> None:
         _check(lib().reloc_forest_drop_reservoirs(self._h, _stream(stream)), "reloc_forest_drop_reservoirs")
 
@@ -410,14 +422,17 @@ class Batch:
 
     def run(self, attempts: Sequence[dict], stream=None) -> list:
         """attempts: dicts with forest, depth, rgb, K, seed, and optionally
-        n_hyp and weights. Returns one result dict per attempt."""
+        n_hyp, weights (a device weight tensor) or proposal (an Mlp whose
+        weights are computed inside the batch). Returns one result dict per
+        attempt."""
         n = len(attempts)
         arr = (reloc_attempt * n)()
         for i, a in enumerate(attempts):
             d, c, k = _frame(a["depth"], a["rgb"], a["K"])
             w = a.get("weights")
+            m = a.get("proposal")
             arr[i] = reloc_attempt(a["forest"].handle, d, c, k, int(a["seed"]), int(a.get("n_hyp", 0)),
-                                   w.data_ptr() if w is not None else None)
+                                   w.data_ptr() if w is not None else None, m.handle if m is not None else None)
         res = (reloc_result * n)()
         _check(lib().reloc_relocalise_batch(self._h, arr, n, res, _stream(stream)), "reloc_relocalise_batch")
         return [r.as_dict() for r in res]

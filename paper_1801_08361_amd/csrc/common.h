@@ -613,6 +613,7 @@ struct Forest {
     uint32_t *stamp = nullptr;     // [T][L][R]
     Mode *modes = nullptr;         // [T][L][M]
     uint32_t *mode_rgb = nullptr;  // [T][L][rgb_stride(M)] colour of each mode (compact copy for hypothesis picks)
+    float4 *leaf_in = nullptr;     // [T][L][4] per-leaf summary for the learned proposal's inputs
     int32_t *nmodes = nullptr;     // [T][L]
     uint32_t *dirty = nullptr;     // [T][L]
     uint32_t *dirty_list = nullptr;
@@ -646,7 +647,10 @@ struct Attempt {
     const uint32_t *mode_rgb;
     const unsigned long long *total_samples;
     const uint32_t *weights;       // [P] integer pick weights or null
-    int32_t T, L, M, P, N, B, max_tries, rgb_tol, refine, rounds;
+    const float4 *leaf_in;         // [T][L][4] per-leaf summaries (learned inputs)
+    const uint16_t *mq;            // learned proposal: bfloat16 weight copies, or null
+    const float *mw;               // learned proposal: FP32 parameters
+    int32_t T, L, M, R, P, N, B, max_tries, rgb_tol, refine, rounds;
     float ratio2, min_pair2, min_area2, inl2;
     double resid2;
     uint64_t seed;
@@ -656,6 +660,7 @@ struct Attempt {
     int32_t *blockcnt;             // [nb]
     unsigned long long *blockw;    // [nb] weight sums per pixel block
     unsigned long long *cdf;       // [P] inclusive weight prefix over the pool
+    uint32_t *wbuf;                // [P] learned pick weights (learned proposal only)
     int32_t *misc;                 // [0] pool size [1] live [2] valid [3] rounds done
     Hyp *hyp;                      // [N]
     double *hyp_init;              // [N][12]
@@ -723,6 +728,10 @@ __device__ __forceinline__ int attempt_of(const Stage &S, int u)
 }  // namespace rl
 
 struct reloc_forest : public rl::Forest {};
+
+// the learned proposal's device parameters (mlp.hip)
+const uint16_t *rl_mlp_q(const reloc_mlp *m);
+const float *rl_mlp_w(const reloc_mlp *m);
 
 // releases a forest's plain-path batch (relocalise.hip)
 void rl_free_plain(rl::Forest *f);

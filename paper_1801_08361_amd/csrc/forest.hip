@@ -515,13 +515,17 @@ __device__ void leaf_modes(const Entry *__restrict__ pts, int n, int n_total, in
     __syncthreads();
 }
 
-// persistent over the dirty-leaf list
+// persistent over the dirty-leaf list; also refreshes each leaf's summary
+// for the learned proposal's inputs: {min(k, R), number of modes kept (<= 3)}
+// and, for its first three modes (the heaviest: modes are ranked by size),
+// {pi = n / min(k, R), -log(Sigma^-1_xx) / 10, -log(Sigma^-1_yy) / 10,
+// -log(Sigma^-1_zz) / 10}
 __global__ void __launch_bounds__(MODE_THREADS) k_modes(const uint32_t *__restrict__ list,
                                                         const uint32_t *__restrict__ count,
                                                         const uint32_t *__restrict__ counter,
                                                         const Entry *__restrict__ res, ModeParams mp,
                                                         Mode *__restrict__ modes, uint32_t *__restrict__ mode_rgb,
-                                                        int32_t *__restrict__ nmodes)
+                                                        int32_t *__restrict__ nmodes, float4 *__restrict__ leaf_in)
 {
     extern __shared__ char smem[];
     uint32_t n_list = *count;
@@ -532,6 +536,25 @@ __global__ void __launch_bounds__(MODE_THREADS) k_modes(const uint32_t *__restri
         const int ms = rgb_stride(mp.M);
         leaf_modes(res + (int64_t)li * mp.R, n, n, mp.R, mp, modes + (int64_t)li * mp.M, mode_rgb + (int64_t)li * ms, ms,
                    nmodes + li, smem);
+        // leaf_modes ends with a barrier: the modes and their count are visible
+        const int tid = (int)threadIdx.x;
+        if (tid < 4) {
+            const int nm = nmodes[li];
+            const int n3 = nm < 3 ? nm : 3;
+            float4 q = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+            if (tid == 0) {
+                q.x = __uint_as_float((uint32_t)n);
+                q.y = __int_as_float(n3);
+            } else if (tid - 1 < n3) {
+                const Mode md = modes[(int64_t)li * mp.M + tid - 1];
+                q.x = (float)md.n / (float)n;
+                q.y = -logf(md.sinv[0]) / 10.0f;
+                q.z = -logf(md.sinv[3]) / 10.0f;
+                q.w = -logf(md.sinv[5]) / 10.0f;
+            }
+            leaf_in[(int64_t)li * 4 + tid] = q;
+        }
+        __syncthreads();
     }
 }
 
@@ -599,7 +622,7 @@ int update_modes(Forest *f, hipStream_t s)
     ModeParams mp = mode_params(f);
     int grid = std::min(f->T * f->L, 4096);
     RL_LAUNCH("k_modes", k_modes, dim3(grid), dim3(MODE_THREADS), mode_smem(f->R), s, f->dirty_list, f->dirty_count,
-                       f->counter, f->res, mp, f->modes, f->mode_rgb, f->nmodes);
+                       f->counter, f->res, mp, f->modes, f->mode_rgb, f->nmodes, f->leaf_in);
     RL_LAUNCH("k_modes_done", k_modes_done, dim3(1), dim3(1024), 0, s, f->dirty_list, f->dirty_count, f->dirty);
     RL_HIP(hipGetLastError());
     f->maybe_dirty = false;
@@ -675,6 +698,7 @@ static void forest_free(Forest *f)
     dfree(f, &f->chunk_cnt, (size_t)f->T * C * f->L);
     dfree(f, &f->chunk_pref, (size_t)f->T * C * f->L);
     dfree(f, &f->mode_rgb, TL * rgb_stride(f->M));
+    dfree(f, &f->leaf_in, TL * 4);
 }
 
 extern "C" int reloc_forest_create(const reloc_params *p, void *stream, reloc_forest **out)
@@ -703,6 +727,7 @@ extern "C" int reloc_forest_create(const reloc_params *p, void *stream, reloc_fo
     rc |= dalloc(f, &f->dirty_count, 1, s);
     rc |= dalloc(f, &f->total_samples, 1, s);
     rc |= dalloc(f, &f->mode_rgb, TL * rgb_stride(f->M), s);
+    rc |= dalloc(f, &f->leaf_in, TL * 4, s);
     if (rc) {
         forest_free(f);
         delete f;
@@ -713,6 +738,7 @@ extern "C" int reloc_forest_create(const reloc_params *p, void *stream, reloc_fo
         hipMemsetAsync(f->res, 0, TL * f->R * sizeof(Entry), s) != hipSuccess ||
         hipMemsetAsync(f->nmodes, 0, TL * sizeof(int32_t), s) != hipSuccess ||
         hipMemsetAsync(f->mode_rgb, 0xFF, TL * rgb_stride(f->M) * sizeof(uint32_t), s) != hipSuccess ||
+        hipMemsetAsync(f->leaf_in, 0, TL * 4 * sizeof(float4), s) != hipSuccess ||
         hipMemsetAsync(f->dirty, 0, TL * sizeof(uint32_t), s) != hipSuccess ||
         hipMemsetAsync(f->dirty_count, 0, sizeof(uint32_t), s) != hipSuccess ||
         hipMemsetAsync(f->total_samples, 0, sizeof(unsigned long long), s) != hipSuccess) {

@@ -21,22 +21,12 @@
 #include <new>
 #include <vector>
 
-#include "common.h"
+#include "mlp_dev.h"
 
 namespace rl {
 
 int update_modes(Forest *f, hipStream_t s);
 int frame_from(const Forest *f, const uint16_t *depth, const uint8_t *rgb, const reloc_intrinsics *K, Frame &fr);
-
-typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
-typedef float floatx4 __attribute__((ext_vector_type(4)));
-
-constexpr int NP = 5825;
-constexpr int OW1 = 0, OB1 = 1536, OW2 = 1600, OB2 = 5696, OW3 = 5760, OB3 = 5824;
-// bfloat16 copies: W1 padded to [64][32], W2 [64][64], W2^T [64][64], w3 [64]
-constexpr int QW1 = 0, QW2 = 2048, QW2T = 2048 + 4096, QW3 = 2048 + 8192, NQ = 2048 + 8192 + 64;
-constexpr uint64_t TAG_MLP_INIT = 5, TAG_MLP_BATCH = 6;
-constexpr int ROWS = 64;         // rows per wavefront tile
 
 }  // namespace rl
 
@@ -53,41 +43,6 @@ struct reloc_mlp {
 };
 
 namespace rl {
-
-__device__ __forceinline__ uint16_t f2bf(float x)
-{
-    const uint32_t b = __float_as_uint(x);
-    if ((b & 0x7F800000u) == 0x7F800000u) {
-        uint16_t h = (uint16_t)(b >> 16);
-        if ((b & 0x007FFFFFu) && !(h & 0x7F)) h |= 0x40;
-        return h;
-    }
-    return (uint16_t)((b + 0x7FFFu + ((b >> 16) & 1u)) >> 16);
-}
-
-__device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
-
-__device__ __forceinline__ bf16x8 load8(const uint16_t *p)
-{
-    const uint4 v = *(const uint4 *)p;
-    return __builtin_bit_cast(bf16x8, v);
-}
-
-// 16x16 tile of A (16 rows, K-contiguous, stride lda) times B given as B^T
-// (16 columns, K-contiguous, stride ldb), K a multiple of 32, accumulated into
-// acc. Lane l supplies row / column (l & 15) and the k-block 8 (l >> 4) .. +7;
-// the result holds column (l & 15), rows 4 (l >> 4) + i, i < 4.
-__device__ __forceinline__ floatx4 mfma_tile(const uint16_t *A, int lda, const uint16_t *Bt, int ldb, int K,
-                                             floatx4 acc)
-{
-    const int l = __lane_id(), r = l & 15, kb = (l >> 4) * 8;
-    for (int k0 = 0; k0 < K; k0 += 32) {
-        const bf16x8 a = load8(A + r * lda + k0 + kb);
-        const bf16x8 b = load8(Bt + r * ldb + k0 + kb);
-        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc, 0, 0, 0);
-    }
-    return acc;
-}
 
 // one 16x32 by 32x16 product of host-given tiles (checks the lane layout)
 __global__ void __launch_bounds__(64) k_mfma_probe(const uint16_t *__restrict__ A, const uint16_t *__restrict__ Bt,
@@ -156,46 +111,6 @@ __device__ __forceinline__ void tile_transpose_x(TileLds &S)
 {
     const int l = __lane_id();
     for (int k = 0; k < 32; ++k) S.XT[k * ROWS + l] = S.X[l * 32 + k];
-    __syncthreads();
-}
-
-__device__ void tile_forward(TileLds &S, const uint16_t *__restrict__ q, const float *__restrict__ w)
-{
-    const int l = __lane_id(), col = l & 15, r0 = (l >> 4) * 4;
-    // layer 1: H1 = relu(X W1^T + b1), stored bfloat16
-    for (int ti = 0; ti < 4; ++ti)
-        for (int tj = 0; tj < 4; ++tj) {
-            floatx4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
-            acc = mfma_tile(S.X + 16 * ti * 32, 32, q + QW1 + 16 * tj * 32, 32, 32, acc);
-            const int c = 16 * tj + col;
-            const float b = w[OB1 + c];
-            for (int i = 0; i < 4; ++i) {
-                const int row = 16 * ti + r0 + i;
-                const float hv = acc[i] + b;
-                const uint16_t h = hv > 0.0f ? f2bf(hv) : (uint16_t)0;
-                S.H1[row * 64 + c] = h;
-                S.H1T[c * ROWS + row] = h;
-            }
-        }
-    __syncthreads();
-    // layer 2: H2 = relu(H1 W2^T + b2)
-    for (int ti = 0; ti < 4; ++ti)
-        for (int tj = 0; tj < 4; ++tj) {
-            floatx4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
-            acc = mfma_tile(S.H1 + 16 * ti * 64, 64, q + QW2 + 16 * tj * 64, 64, 64, acc);
-            const int c = 16 * tj + col;
-            const float b = w[OB2 + c];
-            for (int i = 0; i < 4; ++i) {
-                const int row = 16 * ti + r0 + i;
-                const float hv = acc[i] + b;
-                S.H2[row * 64 + c] = hv > 0.0f ? f2bf(hv) : (uint16_t)0;
-            }
-        }
-    __syncthreads();
-    // output: z = w3 . h2 + b3 (FP32, lane = row)
-    float z = 0.0f;
-    for (int j = 0; j < 64; ++j) z = fmaf(bf2f(q[QW3 + j]), bf2f(S.H2[l * 64 + j]), z);
-    S.z[l] = z + w[OB3];
     __syncthreads();
 }
 
@@ -323,7 +238,7 @@ __global__ void __launch_bounds__(64) k_mlp_fwd_bwd(const uint16_t *__restrict__
     const int row = r0 + l;
     ys[l] = row < n ? Y[idx ? idx[row] : row] : 0;
     __syncthreads();
-    tile_forward(S, q, w);
+    tile_forward<TileLds, true>(S, q, w);
     tile_backward(S, q, ys, min(ROWS, n - r0), inv_n, partial + (int64_t)tile * (NP + 1));
 }
 
@@ -364,85 +279,23 @@ __global__ void __launch_bounds__(64) k_mlp_logits(const uint16_t *__restrict__ 
                                                    const uint16_t *__restrict__ q, const float *__restrict__ w,
                                                    float *__restrict__ z)
 {
-    __shared__ TileLds S;
+    __shared__ FwdTile S;
     const int r0 = blockIdx.x * ROWS, l = __lane_id();
-    tile_load(S, X, nullptr, r0, n);
-    tile_forward(S, q, w);
+    uint4 *d = (uint4 *)(S.X + l * 32);
+    if (r0 + l < n) {
+        const uint4 *src = (const uint4 *)(X + (int64_t)(r0 + l) * 32);
+        for (int k = 0; k < 4; ++k) d[k] = src[k];
+    } else {
+        for (int k = 0; k < 4; ++k) d[k] = make_uint4(0, 0, 0, 0);
+    }
+    __syncthreads();
+    tile_forward<FwdTile, false>(S, q, w);
     if (r0 + l < n) z[r0 + l] = S.z[l];
 }
 
 // ---------------------------------------------------------------------------
 // per-pixel inputs, labels, verification
 // ---------------------------------------------------------------------------
-
-struct FeatArgs {
-    Frame fr;
-    const uint64_t *nodes;       // [T][L-1] then 8 extra
-    const int32_t *nmodes;
-    const Mode *modes;
-    const uint32_t *counter;
-    int T, L, M, R;
-};
-
-// The 24 inputs of one pixel (zeros for an invalid one), FP32: depth / 5000;
-// the 8 extra responses (depth clamped to +-5000 mm over 1000, colour over
-// 255); pi = n / min(k, R) and -log(Sigma^-1_ii) / 10 of the 3 heaviest modes
-// of M(p) (ties: lower (tree, mode)); mean reservoir fill; u / W, v / H.
-__device__ void pixel_features(const FeatArgs &A, int p, float x[24])
-{
-    for (int k = 0; k < 24; ++k) x[k] = 0.0f;
-    const uint32_t d = A.fr.depth[p];
-    if (!valid_depth(A.fr, d)) return;
-    const int u = p % A.fr.W, v = p / A.fr.W;
-    x[0] = (float)d / 5000.0f;
-    const PixelDen pd = pixel_den(A.fr, (int32_t)d);
-    const uint64_t *extra = A.nodes + (int64_t)A.T * (A.L - 1);
-    for (int j = 0; j < 8; ++j) {
-        int32_t thr;
-        int32_t r = node_response_d(A.fr, extra[j], u, v, (int32_t)d, pd, thr);
-        if ((extra[j] & 3u) == 0) {
-            r = r > 5000 ? 5000 : (r < -5000 ? -5000 : r);
-            x[1 + j] = (float)r / 1000.0f;
-        } else {
-            x[1 + j] = (float)r / 255.0f;
-        }
-    }
-    float best_pi[3] = {-1.0f, -1.0f, -1.0f};
-    int64_t best_m[3] = {-1, -1, -1};
-    int64_t fill = 0;
-    for (int t = 0; t < A.T; ++t) {
-        const int32_t leaf = traverse_d(A.nodes + (int64_t)t * (A.L - 1), A.L, A.fr, u, v, (int32_t)d, pd);
-        const int64_t li = (int64_t)t * A.L + leaf;
-        const uint32_t k = A.counter[li];
-        const uint32_t cap = k < (uint32_t)A.R ? k : (uint32_t)A.R;
-        fill += cap;
-        const int nm = A.nmodes[li];
-        for (int m = 0; m < nm; ++m) {
-            const float pi = (float)A.modes[li * A.M + m].n / (float)cap;
-            for (int s = 0; s < 3; ++s)
-                if (pi > best_pi[s]) {
-                    for (int qq = 2; qq > s; --qq) {
-                        best_pi[qq] = best_pi[qq - 1];
-                        best_m[qq] = best_m[qq - 1];
-                    }
-                    best_pi[s] = pi;
-                    best_m[s] = li * A.M + m;
-                    break;
-                }
-        }
-    }
-    for (int s = 0; s < 3; ++s) {
-        if (best_m[s] < 0) continue;
-        const Mode &md = A.modes[best_m[s]];
-        x[9 + 4 * s] = best_pi[s];
-        x[10 + 4 * s] = -logf(md.sinv[0]) / 10.0f;
-        x[11 + 4 * s] = -logf(md.sinv[3]) / 10.0f;
-        x[12 + 4 * s] = -logf(md.sinv[5]) / 10.0f;
-    }
-    x[21] = (float)fill / (float)((int64_t)A.T * A.R);
-    x[22] = (float)u / (float)A.fr.W;
-    x[23] = (float)v / (float)A.fr.H;
-}
 
 __global__ void k_pixel_features(FeatArgs A, const int32_t *__restrict__ pix, int n, uint16_t *__restrict__ X,
                                  float *__restrict__ XF)
@@ -504,7 +357,7 @@ __global__ void __launch_bounds__(64) k_mlp_pixels(FeatArgs A, const uint16_t *_
                                                    const float *__restrict__ w, uint32_t *__restrict__ weights,
                                                    float *__restrict__ prob)
 {
-    __shared__ TileLds S;
+    __shared__ FwdTile S;
     const int P = A.fr.W * A.fr.H;
     const int l = __lane_id();
     const int p = blockIdx.x * ROWS + l;
@@ -512,14 +365,14 @@ __global__ void __launch_bounds__(64) k_mlp_pixels(FeatArgs A, const uint16_t *_
     if (p < P) pixel_features(A, p, x);
     else
         for (int k = 0; k < 24; ++k) x[k] = 0.0f;
-    for (int k = 0; k < 32; ++k) S.X[l * 32 + k] = k < 24 ? f2bf(x[k]) : (uint16_t)0;
+    store_row(S, x);
     __syncthreads();
-    tile_transpose_x(S);
-    tile_forward(S, q, w);
+    tile_forward<FwdTile, false>(S, q, w);
     if (p < P) {
         const bool ok = valid_depth(A.fr, A.fr.depth[p]);
-        const float sg = 1.0f / (1.0f + expf(-S.z[l]));
-        weights[p] = ok ? (uint32_t)floorf(sg * 65536.0f) + 1u : 0u;
+        float sg = 0.0f;
+        const uint32_t wt = pick_weight(S.z[l], &sg);
+        weights[p] = ok ? wt : 0u;
         if (prob) prob[p] = ok ? sg : 0.0f;
     }
 }
@@ -563,7 +416,7 @@ static FeatArgs feat_args(const Forest *f, const Frame &fr)
     A.nodes = f->nodes;
     A.nmodes = f->nmodes;
     A.modes = f->modes;
-    A.counter = f->counter;
+    A.leaf_in = f->leaf_in;
     A.T = f->T; A.L = f->L; A.M = f->M; A.R = f->R;
     return A;
 }
@@ -617,6 +470,9 @@ using namespace rl;
 // ---------------------------------------------------------------------------
 // C ABI
 // ---------------------------------------------------------------------------
+
+const uint16_t *rl_mlp_q(const reloc_mlp *m) { return m->q; }
+const float *rl_mlp_w(const reloc_mlp *m) { return m->w; }
 
 static void mlp_free(reloc_mlp *m)
 {

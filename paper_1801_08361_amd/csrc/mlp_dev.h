@@ -1,0 +1,208 @@
+// Device code of the learned proposal shared by the MLP kernels and the
+// relocalisation graph: bfloat16 helpers, the 16x16x32 matrix-core tile, the
+// forward pass of a 64-row tile, and the 24 per-pixel inputs.
+#pragma once
+
+#include "common.h"
+
+namespace rl {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+
+// parameters (FP32): W1 [64][24], b1 [64], W2 [64][64], b2 [64], w3 [64], b3
+constexpr int NP = 5825;
+constexpr int OW1 = 0, OB1 = 1536, OW2 = 1600, OB2 = 5696, OW3 = 5760, OB3 = 5824;
+// bfloat16 copies: W1 padded to [64][32], W2 [64][64], W2^T [64][64], w3 [64]
+constexpr int QW1 = 0, QW2 = 2048, QW2T = 2048 + 4096, QW3 = 2048 + 8192, NQ = 2048 + 8192 + 64;
+constexpr uint64_t TAG_MLP_INIT = 5, TAG_MLP_BATCH = 6;
+constexpr int ROWS = 64;         // rows per wavefront tile
+
+// round to nearest even; NaN stays a quiet NaN
+__device__ __forceinline__ uint16_t f2bf(float x)
+{
+    const uint32_t b = __float_as_uint(x);
+    if ((b & 0x7F800000u) == 0x7F800000u) {
+        uint16_t h = (uint16_t)(b >> 16);
+        if ((b & 0x007FFFFFu) && !(h & 0x7F)) h |= 0x40;
+        return h;
+    }
+    return (uint16_t)((b + 0x7FFFu + ((b >> 16) & 1u)) >> 16);
+}
+
+__device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
+
+__device__ __forceinline__ bf16x8 load8(const uint16_t *p)
+{
+    const uint4 v = *(const uint4 *)p;
+    return __builtin_bit_cast(bf16x8, v);
+}
+
+// 16x16 tile of A (16 rows, K-contiguous, stride lda) times B given as B^T
+// (16 columns, K-contiguous, stride ldb), K a multiple of 32, accumulated into
+// acc. Lane l supplies row / column (l & 15) and the k-block 8 (l >> 4) .. +7;
+// the result holds column (l & 15), rows 4 (l >> 4) + i, i < 4.
+__device__ __forceinline__ floatx4 mfma_tile(const uint16_t *A, int lda, const uint16_t *Bt, int ldb, int K,
+                                             floatx4 acc)
+{
+    const int l = __lane_id(), r = l & 15, kb = (l >> 4) * 8;
+    for (int k0 = 0; k0 < K; k0 += 32) {
+        const bf16x8 a = load8(A + r * lda + k0 + kb);
+        const bf16x8 b = load8(Bt + r * ldb + k0 + kb);
+        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc, 0, 0, 0);
+    }
+    return acc;
+}
+
+// LDS of a forward-only tile
+struct __align__(16) FwdTile {
+    uint16_t X[ROWS * 32];
+    uint16_t H1[ROWS * 64];
+    uint16_t H2[ROWS * 64];
+    float z[ROWS];
+};
+
+// Forward pass of the 64 rows in S.X (bfloat16, 24 inputs + 8 zeros): H1, H2
+// in bfloat16, logits in S.z. With kTrans the tile also keeps H1 transposed
+// (for the weight gradient of layer 2).
+template <class Tile, bool kTrans>
+__device__ void tile_forward(Tile &S, const uint16_t *__restrict__ q, const float *__restrict__ w)
+{
+    const int l = __lane_id(), col = l & 15, r0 = (l >> 4) * 4;
+    // layer 1: H1 = relu(X W1^T + b1), stored bfloat16
+#pragma unroll 1
+    for (int ti = 0; ti < 4; ++ti)
+        for (int tj = 0; tj < 4; ++tj) {
+            floatx4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
+            acc = mfma_tile(S.X + 16 * ti * 32, 32, q + QW1 + 16 * tj * 32, 32, 32, acc);
+            const int c = 16 * tj + col;
+            const float b = w[OB1 + c];
+            for (int i = 0; i < 4; ++i) {
+                const int row = 16 * ti + r0 + i;
+                const float hv = acc[i] + b;
+                const uint16_t h = hv > 0.0f ? f2bf(hv) : (uint16_t)0;
+                S.H1[row * 64 + c] = h;
+                if constexpr (kTrans) S.H1T[c * ROWS + row] = h;
+            }
+        }
+    __syncthreads();
+    // layer 2: H2 = relu(H1 W2^T + b2)
+#pragma unroll 1
+    for (int ti = 0; ti < 4; ++ti)
+        for (int tj = 0; tj < 4; ++tj) {
+            floatx4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
+            acc = mfma_tile(S.H1 + 16 * ti * 64, 64, q + QW2 + 16 * tj * 64, 64, 64, acc);
+            const int c = 16 * tj + col;
+            const float b = w[OB2 + c];
+            for (int i = 0; i < 4; ++i) {
+                const int row = 16 * ti + r0 + i;
+                const float hv = acc[i] + b;
+                S.H2[row * 64 + c] = hv > 0.0f ? f2bf(hv) : (uint16_t)0;
+            }
+        }
+    __syncthreads();
+    // output: z = w3 . h2 + b3 (FP32, lane = row)
+    float z = 0.0f;
+    for (int j = 0; j < 64; ++j) z = fmaf(bf2f(q[QW3 + j]), bf2f(S.H2[l * 64 + j]), z);
+    S.z[l] = z + w[OB3];
+    __syncthreads();
+}
+
+// what the per-pixel inputs need from a forest and a frame
+struct FeatArgs {
+    Frame fr;
+    const uint64_t *nodes;       // [T][L-1] then 8 extra
+    const int32_t *nmodes;
+    const Mode *modes;
+    const float4 *leaf_in;       // [T][L][4] per-leaf summaries written with the modes
+    int T, L, M, R;
+};
+
+// The 24 inputs of valid pixel (u, v) with depth d, FP32: depth / 5000; the 8
+// extra responses (depth clamped to +-5000 mm over 1000, colour over 255);
+// pi = n / min(k, R) and -log(Sigma^-1_ii) / 10 of the 3 heaviest modes of the
+// pixel's leaves (ties: lower (tree, mode)); mean reservoir fill; u / W,
+// v / H. leaf_of(t) gives the pixel's leaf in tree t. A leaf's modes are
+// ranked by size, so its pi never increase with the mode index and only its
+// first three modes can be among the three heaviest; their values come from
+// the leaf's summary, computed with the same operations when the modes are
+// built.
+template <class LeafOf>
+__device__ __forceinline__ void pixel_inputs(const FeatArgs &A, int u, int v, uint32_t d, LeafOf leaf_of,
+                                             float x[24])
+{
+    for (int k = 0; k < 24; ++k) x[k] = 0.0f;
+    x[0] = (float)d / 5000.0f;
+    const PixelDen pd = pixel_den(A.fr, (int32_t)d);
+    const uint64_t *extra = A.nodes + (int64_t)A.T * (A.L - 1);
+    for (int j = 0; j < 8; ++j) {
+        int32_t thr;
+        int32_t r = node_response_d(A.fr, extra[j], u, v, (int32_t)d, pd, thr);
+        if ((extra[j] & 3u) == 0) {
+            r = r > 5000 ? 5000 : (r < -5000 ? -5000 : r);
+            x[1 + j] = (float)r / 1000.0f;
+        } else {
+            x[1 + j] = (float)r / 255.0f;
+        }
+    }
+    // the heaviest three over the leaves' first three modes, ties to the lower
+    // (tree, mode): each leaf's summary holds min(k, R), its mode count (<= 3)
+    // and (pi, -log(Sigma^-1_ii) / 10) of those modes
+    float4 b0 = make_float4(-1.0f, 0.0f, 0.0f, 0.0f), b1 = b0, b2 = b0;
+    bool h0 = false, h1 = false, h2 = false;
+    int64_t fill = 0;
+    for (int t = 0; t < A.T; ++t) {
+        const float4 *S = A.leaf_in + ((int64_t)t * A.L + leaf_of(t)) * 4;
+        const float4 head = S[0];
+        fill += (int64_t)__float_as_uint(head.x);
+        const int n3 = __float_as_int(head.y);
+        for (int m = 0; m < n3; ++m) {
+            const float4 c = S[1 + m];
+            if (c.x > b0.x) {
+                b2 = b1; h2 = h1; b1 = b0; h1 = h0; b0 = c; h0 = true;
+            } else if (c.x > b1.x) {
+                b2 = b1; h2 = h1; b1 = c; h1 = true;
+            } else if (c.x > b2.x) {
+                b2 = c; h2 = true;
+            }
+        }
+    }
+    if (h0) { x[9] = b0.x; x[10] = b0.y; x[11] = b0.z; x[12] = b0.w; }
+    if (h1) { x[13] = b1.x; x[14] = b1.y; x[15] = b1.z; x[16] = b1.w; }
+    if (h2) { x[17] = b2.x; x[18] = b2.y; x[19] = b2.z; x[20] = b2.w; }
+    x[21] = (float)fill / (float)((int64_t)A.T * A.R);
+    x[22] = (float)u / (float)A.fr.W;
+    x[23] = (float)v / (float)A.fr.H;
+}
+
+// the same with the leaves found by traversal (zeros for an invalid pixel)
+__device__ __forceinline__ void pixel_features(const FeatArgs &A, int p, float x[24])
+{
+    const uint32_t d = A.fr.depth[p];
+    if (!valid_depth(A.fr, d)) {
+        for (int k = 0; k < 24; ++k) x[k] = 0.0f;
+        return;
+    }
+    const int u = p % A.fr.W, v = p / A.fr.W;
+    const PixelDen pd = pixel_den(A.fr, (int32_t)d);
+    pixel_inputs(A, u, v, d,
+                 [&](int t) { return traverse_d(A.nodes + (int64_t)t * (A.L - 1), A.L, A.fr, u, v, (int32_t)d, pd); },
+                 x);
+}
+
+// lane l's inputs as row l of the tile (bfloat16, 8 zeros of padding)
+__device__ __forceinline__ void store_row(FwdTile &S, const float x[24])
+{
+    const int l = __lane_id();
+    for (int k = 0; k < 32; ++k) S.X[l * 32 + k] = k < 24 ? f2bf(x[k]) : (uint16_t)0;
+}
+
+// pick weight of a valid pixel from its logit: floor(sigmoid(z) 65536) + 1
+__device__ __forceinline__ uint32_t pick_weight(float z, float *prob)
+{
+    const float sg = 1.0f / (1.0f + expf(-z));
+    if (prob) *prob = sg;
+    return (uint32_t)floorf(sg * 65536.0f) + 1u;
+}
+
+}  // namespace rl

@@ -30,7 +30,7 @@
 #include <string>
 #include <vector>
 
-#include "common.h"
+#include "mlp_dev.h"
 
 namespace rl {
 
@@ -92,6 +92,44 @@ __global__ void __launch_bounds__(PIX_BLOCK) k_b_leaves(const Attempt *__restric
         int32_t leaf = -1;
         if (valid_depth(fr, d)) leaf = traverse_top(top, ntop, tree, A.L, fr, uu, vv, (int32_t)d);
         A.leaves[(int64_t)t * A.P + p] = leaf;
+    }
+}
+
+// Learned pick weights from the attempt's own leaves (attempts with a
+// proposal network only): one wavefront per 64 pixels, the 24 inputs of each
+// valid pixel, the network's forward pass on the matrix cores, and
+// floor(sigmoid 65536) + 1 (0 for an invalid pixel), exactly as the
+// stand-alone weight kernel computes them after its own traversal.
+__global__ void __launch_bounds__(64) k_b_weights(const Attempt *__restrict__ att, Stage S)
+{
+    __shared__ FwdTile T;
+    const int l = __lane_id();
+    FOR_UNITS(S, u) {
+        const int a = attempt_of(S, u);
+        const Attempt &A = att[a];
+        const int p = (u - S.off[a]) * ROWS + l;
+        FeatArgs F;
+        F.fr = A.fr;
+        F.nodes = A.nodes;
+        F.nmodes = A.nmodes;
+        F.modes = A.modes;
+        F.leaf_in = A.leaf_in;
+        F.T = A.T; F.L = A.L; F.M = A.M; F.R = A.R;
+        float x[24];
+        for (int k = 0; k < 24; ++k) x[k] = 0.0f;
+        bool ok = false;
+        if (p < A.P) {
+            const uint32_t d = A.fr.depth[p];
+            ok = valid_depth(A.fr, d);
+            if (ok)
+                pixel_inputs(F, p % A.fr.W, p / A.fr.W, d, [&](int t) { return A.leaves[(int64_t)t * A.P + p]; },
+                             x);
+        }
+        __syncthreads();   // the previous unit's tile is no longer read
+        store_row(T, x);
+        __syncthreads();
+        tile_forward<FwdTile, false>(T, A.mq, A.mw);
+        if (p < A.P) A.wbuf[p] = ok ? pick_weight(T.z[l], nullptr) : 0u;
     }
 }
 
@@ -829,7 +867,7 @@ struct Sched {
 };
 
 struct Shape {
-    int W, H, N, B, T, L, M, weights;
+    int W, H, N, B, T, L, M, weights;   // weights: 0 uniform, 1 given, 2 learned in the graph
     bool operator==(const Shape &o) const
     {
         return W == o.W && H == o.H && N == o.N && B == o.B && T == o.T && L == o.L && M == o.M &&
@@ -884,6 +922,7 @@ static size_t carve(const Shape &s, char *base, Attempt &A)
     A.blockcnt = (int32_t *)take((size_t)nb * 4);
     A.blockw = (unsigned long long *)take((size_t)nb * 8);
     A.cdf = (unsigned long long *)take(s.weights ? (size_t)P * 8 : 8);
+    A.wbuf = (uint32_t *)take(s.weights == 2 ? (size_t)P * 4 : 4);
     A.misc = (int32_t *)take(16);
     A.hyp = (Hyp *)take((size_t)s.N * sizeof(Hyp));
     A.hyp_init = (double *)take((size_t)s.N * 12 * 8);
@@ -918,16 +957,16 @@ static void free_plan(reloc_batch *b, Plan *pl)
 
 // stages of one schedule in launch order
 struct Stages {
-    Stage pix, pb, att, hyp;
+    Stage pix, pb, att, hyp, wts;
     std::vector<Stage> score, refine, solve;
 };
 
-// host offsets of every stage for schedule `sc`: pix, pb, att, hyp, then per
-// round (score, refine, solve)
+// host offsets of every stage for schedule `sc`: pix, pb, att, hyp, wts, then
+// per round (score, refine, solve)
 static std::vector<int32_t> offsets(const Plan *pl, const Sched &sc)
 {
     const int n = pl->n, R = pl->rounds;
-    const int n_stage = 4 + 3 * R;
+    const int n_stage = 5 + 3 * R;
     std::vector<int32_t> off((size_t)n_stage * (n + 1), 0);
     auto fill = [&](int k, auto units) {
         int32_t *o = off.data() + (size_t)k * (n + 1);
@@ -939,18 +978,19 @@ static std::vector<int32_t> offsets(const Plan *pl, const Sched &sc)
     fill(1, [&](int a) { return (int)((P(a) + POOL_BLOCK - 1) / POOL_BLOCK); });
     fill(2, [&](int) { return 1; });
     fill(3, [&](int a) { return pl->shape[a].N; });
+    fill(4, [&](int a) { return pl->shape[a].weights == 2 ? (int)((P(a) + ROWS - 1) / ROWS) : 0; });
     auto bound = [&](int a, int rr) {
         int bnd = pl->shape[a].N;
         for (int k = 0; k < rr; ++k) bnd = (bnd + 1) / 2;
         return bnd;
     };
     for (int r = 0; r < R; ++r) {
-        fill(4 + 3 * r, [&](int a) {
+        fill(5 + 3 * r, [&](int a) {
             if (r >= rounds_for(pl->shape[a].N)) return 0;
             return ((bound(a, r) + 63) / 64) * ((pl->shape[a].B + sc.dpu - 1) / sc.dpu);
         });
-        fill(5 + 3 * r, [&](int a) { return r >= rounds_for(pl->shape[a].N) ? 0 : bound(a, r + 1); });
-        fill(6 + 3 * r, [&](int a) { return r >= rounds_for(pl->shape[a].N) ? 0 : (bound(a, r + 1) + 63) / 64; });
+        fill(6 + 3 * r, [&](int a) { return r >= rounds_for(pl->shape[a].N) ? 0 : bound(a, r + 1); });
+        fill(7 + 3 * r, [&](int a) { return r >= rounds_for(pl->shape[a].N) ? 0 : (bound(a, r + 1) + 63) / 64; });
     }
     return off;
 }
@@ -967,11 +1007,11 @@ static Stages stages_of(const Plan *pl, const Sched &sc, const int32_t *d_off, c
         return s;
     };
     Stages st;
-    st.pix = mk(0); st.pb = mk(1); st.att = mk(2); st.hyp = mk(3);
+    st.pix = mk(0); st.pb = mk(1); st.att = mk(2); st.hyp = mk(3); st.wts = mk(4);
     for (int r = 0; r < pl->rounds; ++r) {
-        st.score.push_back(mk(4 + 3 * r));
-        st.refine.push_back(mk(5 + 3 * r));
-        st.solve.push_back(mk(6 + 3 * r));
+        st.score.push_back(mk(5 + 3 * r));
+        st.refine.push_back(mk(6 + 3 * r));
+        st.solve.push_back(mk(7 + 3 * r));
     }
     return st;
 }
@@ -993,6 +1033,8 @@ static int enqueue(const Plan *pl, const Sched &sc, const Stages &st, hipStream_
     Stage att = st.att;
     att.xcd = 0;
     RL_LAUNCH("k_b_leaves", k_b_leaves, dim3(grid_of(st.pix, cap, sc.xcd)), dim3(PIX_BLOCK), 0, s, d, st.pix);
+    if (st.wts.total > 0)
+        RL_LAUNCH("k_b_weights", k_b_weights, dim3(grid_of(st.wts, cap, sc.xcd)), dim3(64), 0, s, d, st.wts);
     RL_LAUNCH("k_b_pool_count", k_b_pool_count, dim3(grid_of(st.pb, cap, sc.xcd)), dim3(POOL_BLOCK), 0, s, d, st.pb);
     RL_LAUNCH("k_b_pool_scan", k_b_pool_scan, dim3(grid_of(att, cap, 0)), dim3(1024), 0, s, d, att);
     RL_LAUNCH("k_b_pool_write", k_b_pool_write, dim3(grid_of(st.pb, cap, sc.xcd)), dim3(POOL_BLOCK), 0, s, d, st.pb);
@@ -1199,13 +1241,13 @@ static int run_batch(reloc_batch *b, const reloc_attempt *att, int n, hipStream_
     for (int a = 0; a < n; ++a) {
         const reloc_attempt &x = att[a];
         Forest *f = x.forest;
-        if (!f) return RELOC_E_ARG;
+        if (!f || (x.proposal && x.pixel_weights_dev)) return RELOC_E_ARG;
         int rc = frame_from(f, x.depth_dev, x.rgb_dev, &x.K, frames[a]);
         if (rc) return rc;
         const int N = x.n_hypotheses > 0 ? x.n_hypotheses : f->p.n_hypotheses;
         if (N > MAX_HYP || f->T * f->M > MAX_TM) return RELOC_E_ARG;
         shape[a] = Shape{frames[a].W, frames[a].H, N, f->p.batch_pixels, f->T, f->L, f->M,
-                         x.pixel_weights_dev ? 1 : 0};
+                         x.proposal ? 2 : (x.pixel_weights_dev ? 1 : 0)};
         tm_max = std::max(tm_max, f->T * f->M);
     }
     for (int a = 0; a < n; ++a) {   // pending modes of every forest involved
@@ -1225,7 +1267,11 @@ static int run_batch(reloc_batch *b, const reloc_attempt *att, int n, hipStream_
         A.modes = f->modes;
         A.mode_rgb = f->mode_rgb;
         A.total_samples = f->total_samples;
-        A.weights = x.pixel_weights_dev;
+        A.weights = x.proposal ? A.wbuf : x.pixel_weights_dev;
+        A.leaf_in = f->leaf_in;
+        A.R = f->R;
+        A.mq = x.proposal ? rl_mlp_q(x.proposal) : nullptr;
+        A.mw = x.proposal ? rl_mlp_w(x.proposal) : nullptr;
         A.T = f->T; A.L = f->L; A.M = f->M; A.P = frames[a].W * frames[a].H;
         A.N = shape[a].N; A.B = f->p.batch_pixels; A.max_tries = f->p.max_tries; A.rgb_tol = f->p.rgb_tol;
         A.refine = f->p.refine; A.rounds = rounds_for(A.N);
@@ -1311,7 +1357,8 @@ extern "C" int reloc_relocalise_batch(reloc_batch *b, const reloc_attempt *attem
 }
 
 static int plain(reloc_forest *f, const uint16_t *depth_dev, const uint8_t *rgb_dev, const reloc_intrinsics *K,
-                 uint64_t seed, int32_t n_hypotheses, const uint32_t *weights, reloc_result *out, void *stream)
+                 uint64_t seed, int32_t n_hypotheses, const uint32_t *weights, const reloc_mlp *proposal,
+                 reloc_result *out, void *stream)
 {
     if (!f || !K || !out) return RELOC_E_ARG;
     if (!f->plain) {
@@ -1329,6 +1376,7 @@ static int plain(reloc_forest *f, const uint16_t *depth_dev, const uint8_t *rgb_
     x.seed = seed;
     x.n_hypotheses = n_hypotheses;
     x.pixel_weights_dev = weights;
+    x.proposal = proposal;
     return reloc_relocalise_batch(f->plain, &x, 1, out, stream);
 }
 
@@ -1336,7 +1384,18 @@ extern "C" int reloc_relocalise_ex(reloc_forest *f, const uint16_t *depth_dev, c
                                    const reloc_intrinsics *K, uint64_t attempt_seed, int32_t n_hypotheses,
                                    const uint32_t *pixel_weights_dev, reloc_result *result_out, void *stream)
 {
-    const int rc = plain(f, depth_dev, rgb_dev, K, attempt_seed, n_hypotheses, pixel_weights_dev, result_out, stream);
+    const int rc = plain(f, depth_dev, rgb_dev, K, attempt_seed, n_hypotheses, pixel_weights_dev, nullptr, result_out,
+                         stream);
+    if (rc) return rc;
+    return result_out->status;
+}
+
+extern "C" int reloc_relocalise_learned(reloc_forest *f, const reloc_mlp *m, const uint16_t *depth_dev,
+                                        const uint8_t *rgb_dev, const reloc_intrinsics *K, uint64_t attempt_seed,
+                                        int32_t n_hypotheses, reloc_result *result_out, void *stream)
+{
+    if (!m) return RELOC_E_ARG;
+    const int rc = plain(f, depth_dev, rgb_dev, K, attempt_seed, n_hypotheses, nullptr, m, result_out, stream);
     if (rc) return rc;
     return result_out->status;
 }
@@ -1348,7 +1407,7 @@ extern "C" int reloc_relocalise(reloc_forest *f, const uint16_t *depth_dev, cons
 {
     if (!pose_c2w_out || !score_out) return RELOC_E_ARG;
     reloc_result r;
-    const int rc = plain(f, depth_dev, rgb_dev, K, attempt_seed, n_hypotheses, pixel_weights_dev, &r, stream);
+    const int rc = plain(f, depth_dev, rgb_dev, K, attempt_seed, n_hypotheses, pixel_weights_dev, nullptr, &r, stream);
     if (rc) return rc;
     memcpy(pose_c2w_out, r.pose_c2w, sizeof(r.pose_c2w));
     *score_out = r.score;

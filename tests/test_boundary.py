@@ -33,7 +33,7 @@ def test_struct_layouts():
     import paper_1801_08361_amd as rl
     assert C.sizeof(rl.reloc_intrinsics) == 24
     assert C.sizeof(rl.reloc_result) == 168
-    assert C.sizeof(rl.reloc_attempt) == 72
+    assert C.sizeof(rl.reloc_attempt) == 80
     assert C.sizeof(rl.reloc_params) == 4 * 4 + 8 + 4 * 15 + 4 * 5
     assert rl.ENTRY_DTYPE.itemsize == 16 and rl.MODE_DTYPE.itemsize == 48
 
@@ -75,6 +75,7 @@ def test_argument_errors_without_gpu():
     assert L.reloc_pixel_features(None, None, None, None, None, -1, None, None, None) == rl.E_ARG
     assert L.reloc_label_pixels(None, None, None, None, None, None, 0, None, None) == rl.E_ARG
     assert L.reloc_debug_mfma_probe(None, None, None) == rl.E_ARG
+    assert L.reloc_relocalise_learned(None, None, None, None, None, 0, 0, None, None) == rl.E_ARG
     for code in (0, 1, 2, 3, -1, -2, -3, -4, -5, 99):
         assert isinstance(rl.status_string(code), str)
     with pytest.raises(rl.RelocError):

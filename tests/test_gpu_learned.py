@@ -284,3 +284,37 @@ def test_learned_weights_drive_the_relocaliser(adapted):
         if rc == 0:
             assert np.max(np.abs(res["pose"] - pose)) < 1e-4
             assert res["score"] == pytest.approx(score, rel=1e-4)
+
+
+def test_learned_in_graph_equals_given_weights(adapted):
+    """The proposal computed inside the relocalisation graph (from the
+    attempt's own leaves) gives the same result as passing the stand-alone
+    kernel's weights; and a batch of such attempts equals the plain calls."""
+    import paper_1801_08361_amd as rl
+    dev, sc, g, o = adapted
+    m = rl.Mlp(21)
+    w = random_weights(21)
+    m.set_weights(w)
+    atts = []
+    for q in (3, 6, 11):
+        d, c = to_dev(*sc.render_query(q), dev)
+        banner(f"learned in graph query {q}")
+        wts = m.pixel_weights(g, d, c, sc.K)
+        r1 = g.relocalise_ex(d, c, sc.K, seed=500 + q, n_hyp=64, weights=wts)
+        r2 = g.relocalise_learned(m, d, c, sc.K, seed=500 + q, n_hyp=64)
+        for k in ("status", "score", "final_hyp", "n_rounds", "n_valid", "mode_evals", "pair_evals", "pool_size"):
+            assert r1[k] == r2[k], (q, k)
+        assert np.array_equal(r1["pose"], r2["pose"]), q
+        atts.append(dict(forest=g, depth=d, rgb=c, K=sc.K, seed=500 + q, n_hyp=64, proposal=m))
+        atts.append(dict(forest=g, depth=d, rgb=c, K=sc.K, seed=700 + q, n_hyp=32))
+    banner("learned in a batch")
+    res = rl.Batch(tune=True).run(atts)
+    for a, r in zip(atts, res):
+        if "proposal" in a:
+            p = g.relocalise_learned(m, a["depth"], a["rgb"], a["K"], seed=a["seed"], n_hyp=a["n_hyp"])
+        else:
+            p = g.relocalise_ex(a["depth"], a["rgb"], a["K"], seed=a["seed"], n_hyp=a["n_hyp"])
+        assert r["status"] == p["status"] and np.array_equal(r["pose"], p["pose"]) and r["score"] == p["score"]
+    import paper_1801_08361_amd as rl2
+    with pytest.raises(rl2.RelocError):
+        rl.Batch().run([dict(atts[0], weights=m.pixel_weights(g, atts[0]["depth"], atts[0]["rgb"], sc.K))])
