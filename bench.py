@@ -24,7 +24,7 @@ its algorithmic FLOPs (25 per (hypothesis, draw, mode) energy term, 18 per
 (hypothesis, draw) transform, counted by the kernels themselves) over its
 average duration.
 
-Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-batched] [--no-learned]
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-batched] [--no-learned] [--queue]
 """
 from __future__ import annotations
 
@@ -233,7 +233,8 @@ def learned_full(args, dev, full):
 
     forms = {"training": info}
     for name, n_hyp, use in (("learned_256", 256, True), ("uniform_256", 256, False), ("learned_64", 64, True),
-                             ("uniform_64", 64, False), ("uniform_1024", 1024, False)):
+                             ("uniform_64", 64, False), ("learned_16", 16, True), ("uniform_16", 16, False),
+                             ("uniform_1024", 1024, False)):
         run(n_hyp, use)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -242,9 +243,10 @@ def learned_full(args, dev, full):
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
         ok = sum(int(r["status"] == 0 and success(r["pose"], sc.query_poses[q])) for q, r in enumerate(res))
+        valid = sum(r["n_valid"] for r in res) / len(res)
         forms[name] = {"value": len(queries) * args.steps / wall, "unit": "relocalisations/s",
-                       "success_rate": ok / len(queries), "n_hypotheses": n_hyp}
-        log(f"{name}: {forms[name]['value']:.1f}/s, success {ok}/{len(queries)}")
+                       "success_rate": ok / len(queries), "n_hypotheses": n_hyp, "mean_valid_hypotheses": valid}
+        log(f"{name}: {forms[name]['value']:.1f}/s, success {ok}/{len(queries)}, valid hypotheses {valid:.1f}")
     return forms
 
 
@@ -334,9 +336,96 @@ def batched_mixed(args, dev):
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
         ok = sum(int(r["status"] == 0 and success(r["pose"], gt)) for r, gt in zip(res, gts))
+        valid = sum(r["n_valid"] for r in res) / len(res)
         out[name] = {"value": n / wall, "unit": "relocalisations/s", "success_rate": ok / len(att),
-                     "schedule": bb.schedule()}
-        log(f"{name}: {n / wall:.1f}/s, success {ok}/{len(att)}")
+                     "mean_valid_hypotheses": valid, "schedule": bb.schedule()}
+        log(f"{name}: {n / wall:.1f}/s, success {ok}/{len(att)}, valid hypotheses {valid:.1f}")
+    return out
+
+
+def queue_form(args, dev):
+    """Collaborative-scale queue: 16 full-size forests (depth 15, R = 1024),
+    each adapted on every second frame of its own room's path; 1024 queued
+    attempts, 30 % with a frame from the target's room (a correct answer
+    exists) and the rest from other rooms (the correct answer is a rejection),
+    frame sizes mixed from 320x240 to 640x480. Batched plain at 1024
+    hypotheses against batched + learned at 256 (timed: the relocalisation
+    calls only). Every returned pose is then checked, outside the timed
+    region, with the depth-difference test (Sec. 3.3.1, Eqs. 3-4) against the
+    target room's model depth at that pose; success counts accepted correct
+    poses over the attempts with overlap, the false-positive rate accepted
+    wrong poses over all accepted ones."""
+    import torch
+    import paper_1801_08361_amd as rl
+    import synthroom as sr
+    n_f = 16
+    t0 = time.time()
+    scenes = [sr.full_scene(100 + k) for k in range(n_f)]
+    forests = []
+    for sc in scenes:
+        g = rl.Forest(full_params())
+        for k in range(0, len(sc.adapt_poses), 2):
+            d, c = sc.render_adapt(k, device=dev)
+            g.adapt_frame(d, c, sc.K, sc.adapt_poses[k])
+        g.update_modes()
+        forests.append(g)
+    torch.cuda.synchronize()
+    log(f"queue: {n_f} forests adapted in {time.time() - t0:.1f}s ({forests[0].memory() / 2**30:.2f} GiB each)")
+    t0 = time.time()
+    plan = sr.queue_attempts(1024, n_f, len(scenes[0].query_poses))
+    att = []
+    for a in plan:
+        d, c = scenes[a["source"]].render_query(a["query"], device=dev, width=a["width"], height=a["height"])
+        att.append(dict(forest=forests[a["forest"]], depth=d.contiguous(), rgb=c.contiguous(),
+                        K=sr.intrinsics(a["width"], a["height"]), seed=a["seed"]))
+    torch.cuda.synchronize()
+    log(f"queue: {len(att)} frames rendered in {time.time() - t0:.1f}s")
+    items = [(forests[k], scenes[k], T, 300 + 10 * k + j) for k in range(n_f)
+             for j, T in enumerate(scenes[k].extra_poses(2, tag=3))]
+    m, info = train_from_verified(dev, items, 100_000, 3, 6)
+
+    def judge(res):
+        n_overlap = sum(int(a["overlap"]) for a in plan)
+        acc = correct = fp = 0
+        for a, r, x in zip(plan, res, att):
+            if r["status"] != 0:
+                continue
+            md = scenes[a["forest"]].model_depth(r["pose"], device=dev, width=a["width"], height=a["height"])
+            if not rl.verify(x["depth"], md)[2]:
+                continue
+            acc += 1
+            good = a["overlap"] and success(r["pose"], scenes[a["source"]].query_poses[a["query"]])
+            correct += int(good)
+            fp += int(not good)
+        return {"accepted": acc, "accepted_correct": correct, "false_positives": fp,
+                "attempts_with_overlap": n_overlap, "success_rate": correct / max(n_overlap, 1),
+                "false_positive_rate": fp / max(acc, 1)}
+
+    out = {"training": info,
+           "workload": "16 full-size forests (5 trees depth 15, R=1024, 100 frames each); 1024 attempts, 30% from "
+                       "the target's room; frames 320x240/480x360/640x480; B=500"}
+    for name, n_hyp, use in (("batched_plain_1024", 1024, False), ("batched_learned_256", 256, True)):
+        lst = [dict(x, n_hyp=n_hyp, proposal=m) if use else dict(x, n_hyp=n_hyp) for x in att]
+        b = rl.Batch(tune=True)
+        b.run(lst)
+        torch.cuda.synchronize()
+        runs = []
+        for s in range(args.steps):
+            t1 = time.perf_counter()
+            res = b.run(lst)
+            torch.cuda.synchronize()
+            runs.append(time.perf_counter() - t1)
+        j = judge(res)
+        out[name] = dict({"value": len(lst) * args.steps / sum(runs), "unit": "relocalisations/s",
+                          "runs_ms": [round(t * 1e3, 2) for t in runs], "schedule": b.schedule()}, **j)
+        log(f"queue {name}: {out[name]['value']:.1f}/s; accepted {j['accepted']}, correct {j['accepted_correct']} "
+            f"of {j['attempts_with_overlap']} with overlap, false positives {j['false_positives']}")
+        del b
+    t1 = time.perf_counter()
+    res = [x["forest"].relocalise_ex(x["depth"], x["rgb"], x["K"], seed=x["seed"], n_hyp=1024) for x in att]
+    torch.cuda.synchronize()
+    out["sequential_plain_1024"] = {"value": len(att) / (time.perf_counter() - t1), "unit": "relocalisations/s"}
+    log(f"queue sequential plain: {out['sequential_plain_1024']['value']:.1f}/s")
     return out
 
 
@@ -348,6 +437,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-learned", action="store_true")
+    ap.add_argument("--queue", action="store_true",
+                    help="also run the collaborative-scale queue (16 full-size forests, 1024 attempts; minutes)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run one 256 MiB device-to-device copy kernel (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -394,6 +485,8 @@ def main():
         forms["learned_full"] = learned_full(args, dev, full)
     if not args.no_batched:
         forms["mixed"] = batched_mixed(args, dev)
+    if args.queue:
+        forms["queue"] = queue_form(args, dev)
     out["forms"] = forms
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(full["sc"])

@@ -384,3 +384,22 @@ def batched_attempts(n_attempts: int = 64, n_forests: int = 8, seed_tag: int = 3
         out.append(dict(forest=f, width=s[0], height=s[1], n_hyp=n, query=q,
                         seed=int(g.integers(1, 1 << 62))))
     return out
+
+
+def queue_attempts(n_attempts: int, n_forests: int, n_queries: int, overlap: float = 0.3, seed_tag: int = 5):
+    """Cross-agent attempt queue: each attempt targets a forest uniformly; with
+    probability `overlap` its frame comes from the target's own room (a held-out
+    query pose of that room, so a correct relocalisation exists), otherwise
+    from another room (the correct outcome is a rejection). Frame sizes are
+    uniform over {320x240, 480x360, 640x480}."""
+    g = rng(seed_tag, n_attempts, n_forests)
+    sizes = [(320, 240), (480, 360), (640, 480)]
+    out = []
+    for a in range(n_attempts):
+        f = int(g.integers(0, n_forests))
+        same = bool(g.random() < overlap)
+        src = f if same else int((f + 1 + g.integers(0, n_forests - 1)) % n_forests)
+        s = sizes[int(g.integers(0, 3))]
+        out.append(dict(forest=f, source=src, overlap=same, width=s[0], height=s[1],
+                        query=int(g.integers(0, n_queries)), seed=int(g.integers(1, 1 << 62))))
+    return out
