@@ -668,7 +668,7 @@ struct Attempt {
     float *energy;                 // [N]
     double *sums;                  // [N][NSUM] running inlier sums
     int32_t *alive;                // [N]
-    int32_t *pos;                  // [N] position of a hypothesis in the live list when scored
+    int32_t *pos;                  // [N] survivor i's position in the list it was scored in
     float4 *draws;                 // [B] camera point, pixel index bits
     float *gs;                     // [ceil(B / GROUP)][N] energy sum of each group of GROUP draws, per live position
     int32_t *inl;                  // [B][N] global index (leaf * M + mode) of an inlier's best mode, -1 otherwise

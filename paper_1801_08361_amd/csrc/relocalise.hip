@@ -320,13 +320,32 @@ __device__ __forceinline__ uint32_t colour_mask(const uint32_t *__restrict__ row
     return mask;
 }
 
+// the same for rows of at most 12 colours, with the row's loads issued
+// before any test
+__device__ __forceinline__ uint32_t colour_mask12(const uint32_t *__restrict__ row, int Mp, uint32_t pr,
+                                                  uint32_t pg, uint32_t pb, int tol)
+{
+    const uint4 none = make_uint4(RGB_NONE, RGB_NONE, RGB_NONE, RGB_NONE);
+    const uint4 *r4 = (const uint4 *)row;
+    const uint4 v0 = r4[0];
+    const uint4 v1 = Mp > 4 ? r4[1] : none;
+    const uint4 v2 = Mp > 8 ? r4[2] : none;
+    const uint32_t c[12] = {v0.x, v0.y, v0.z, v0.w, v1.x, v1.y, v1.z, v1.w, v2.x, v2.y, v2.z, v2.w};
+    uint32_t mask = 0;
+#pragma unroll
+    for (int e = 0; e < 12; ++e)
+        if (c[e] != RGB_NONE && rgb_close(c[e], pr, pg, pb, tol)) mask |= 1u << e;
+    return mask;
+}
+
 // one try: draws, colour-consistent mode picks, FP32 checks, FP64 alignment
 // and residuals. The pick of pixel j is the sel-th colour-consistent mode in
 // (tree, mode) order, sel = uniform_int(u, count). Loads are issued a stage at
 // a time (pool entries; pixel colours and depths; per pixel, its leaves and
 // then its mode colour rows; the three picked modes) so that each stage
 // waits once.
-__device__ bool try_hypothesis(const Attempt &A, int np, uint64_t h, uint64_t tau, double R[9], double t[3])
+__device__ bool try_hypothesis(const Attempt &A, int np, uint64_t h, uint64_t tau, double R[9], double t[3],
+                               int32_t *__restrict__ s_li, uint32_t *__restrict__ s_mask)
 {
     const U4 a = philox(h, tau, 0, 0, A.seed, TAG_HYP);
     const U4 b = philox(h, tau, 1, 0, A.seed, TAG_HYP);
@@ -346,29 +365,40 @@ __device__ bool try_hypothesis(const Attempt &A, int np, uint64_t h, uint64_t ta
     }
     int64_t pick[3];
     float c[3][3], w[3][3];
-#pragma unroll 1
+#pragma unroll
     for (int j = 0; j < 3; ++j) {
-        int li[16];
-#pragma unroll
-        for (int tt = 0; tt < 16; ++tt) li[tt] = tt < A.T ? tt * A.L + A.leaves[(int64_t)tt * A.P + p[j]] : 0;
-        uint32_t mask[16];
+        // this lane's leaf and colour mask per tree, in LDS columns (stride 64)
+#pragma unroll 4
+        for (int tt = 0; tt < A.T; ++tt) s_li[tt * 64] = tt * A.L + A.leaves[(int64_t)tt * A.P + p[j]];
         int cnt = 0;
-#pragma unroll
-        for (int tt = 0; tt < 16; ++tt) {
-            mask[tt] = tt < A.T ? colour_mask(A.mode_rgb + (int64_t)li[tt] * Mp, Mp, pr[j], pg[j], pb[j], A.rgb_tol)
-                                : 0u;
-            cnt += __popc(mask[tt]);
+        if (Mp <= 12) {
+            // up to 12 modes per leaf: each row's three 16-byte loads are
+            // issued together, four trees at a time
+#pragma unroll 4
+            for (int tt = 0; tt < A.T; ++tt) {
+                const uint32_t mk =
+                    colour_mask12(A.mode_rgb + (int64_t)s_li[tt * 64] * Mp, Mp, pr[j], pg[j], pb[j], A.rgb_tol);
+                s_mask[tt * 64] = mk;
+                cnt += __popc(mk);
+            }
+        } else {
+            for (int tt = 0; tt < A.T; ++tt) {
+                const uint32_t mk =
+                    colour_mask(A.mode_rgb + (int64_t)s_li[tt * 64] * Mp, Mp, pr[j], pg[j], pb[j], A.rgb_tol);
+                s_mask[tt * 64] = mk;
+                cnt += __popc(mk);
+            }
         }
         if (cnt == 0) return false;
         int sel = (int)uniform_int(b.x[j], (uint64_t)cnt);
         pick[j] = 0;
-#pragma unroll
-        for (int tt = 0; tt < 16; ++tt) {
-            const int k = __popc(mask[tt]);
+        for (int tt = 0; tt < A.T; ++tt) {
+            const uint32_t mk = s_mask[tt * 64];
+            const int k = __popc(mk);
             if (sel >= 0 && sel < k) {
-                uint32_t mm = mask[tt];
+                uint32_t mm = mk;
                 for (int q = 0; q < sel; ++q) mm &= mm - 1u;
-                pick[j] = (int64_t)li[tt] * A.M + (__ffs(mm) - 1);
+                pick[j] = (int64_t)s_li[tt * 64] * A.M + (__ffs(mm) - 1);
             }
             sel -= k;
         }
@@ -411,6 +441,10 @@ __device__ bool try_hypothesis(const Attempt &A, int np, uint64_t h, uint64_t ta
 
 __global__ void __launch_bounds__(64) k_b_hypgen(const Attempt *__restrict__ att, Stage S)
 {
+    // per lane (column) and tree (row): leaf index and colour mask of the pixel
+    // being picked (T <= 16)
+    __shared__ int32_t s_li[16 * 64];
+    __shared__ uint32_t s_mask[16 * 64];
     FOR_UNITS(S, u) {
         const int a = attempt_of(S, u);
         const Attempt &A = att[a];
@@ -421,7 +455,8 @@ __global__ void __launch_bounds__(64) k_b_hypgen(const Attempt *__restrict__ att
         double R[9], t[3];
         for (int chunk = 0; chunk * 64 < A.max_tries && found < 0; ++chunk) {
             const int tau = chunk * 64 + lane;
-            const bool ok = tau < A.max_tries && np > 0 && try_hypothesis(A, np, (uint64_t)h, (uint64_t)tau, R, t);
+            const bool ok = tau < A.max_tries && np > 0 &&
+                            try_hypothesis(A, np, (uint64_t)h, (uint64_t)tau, R, t, s_li + lane, s_mask + lane);
             const uint64_t m = __ballot(ok);
             if (m) {
                 const int first = __ffsll((unsigned long long)m) - 1;
@@ -630,16 +665,26 @@ __global__ void __launch_bounds__(64 * GROUP) k_b_score(const Attempt *__restric
     }
 }
 
-// one workgroup per attempt: energies in the defined order, bitonic sort of
-// (energy key, index), keep the first ceil(n / 2)
+// One workgroup per attempt: energies in the defined order, bitonic sort of
+// keys (energy key << 32 | index << 12 | position), which orders by
+// (energy, index); keep the first ceil(n / 2), with each survivor's position
+// in this round's list (where its inliers were stored). Compare-exchange
+// distances of 64 and more go through LDS with a barrier; shorter ones run in
+// registers across the lanes of a wavefront.
+__device__ __forceinline__ unsigned long long cull_key(float E, int h, int ap)
+{
+    return ((unsigned long long)float_key(E) << 32) | ((unsigned long long)(uint32_t)h << 12) | (uint32_t)ap;
+}
+
 __global__ void __launch_bounds__(CULL_THREADS) k_b_cull(const Attempt *__restrict__ att, Stage S, int r)
 {
     __shared__ unsigned long long keys[MAX_HYP];
+    const int lane = __lane_id(), wave = (int)(threadIdx.x >> 6);
     FOR_UNITS(S, u) {
         const Attempt &A = att[u];
         if (!round_active(A, r)) continue;
         const int na = A.misc[1];
-        int n2 = 1;
+        int n2 = 64;
         while (n2 < na) n2 <<= 1;
         for (int ap = threadIdx.x; ap < n2; ap += CULL_THREADS) {
             if (ap < na) {
@@ -651,8 +696,7 @@ __global__ void __launch_bounds__(CULL_THREADS) k_b_cull(const Attempt *__restri
                 for (int k = 0; k < ng; ++k) Ssum = Ssum + gs[(int64_t)k * A.N];
                 const float E = A.energy[h] + Ssum;
                 A.energy[h] = E;
-                A.pos[h] = ap;
-                keys[ap] = ((unsigned long long)float_key(E) << 32) | (unsigned)h;
+                keys[ap] = cull_key(E, h, ap);
                 if (r < MAX_ROUNDS) {
                     A.tr_alive[r * A.N + ap] = h;
                     A.tr_energy[r * A.N + ap] = E;
@@ -663,7 +707,8 @@ __global__ void __launch_bounds__(CULL_THREADS) k_b_cull(const Attempt *__restri
         }
         __syncthreads();
         for (int k = 2; k <= n2; k <<= 1) {
-            for (int j = k >> 1; j > 0; j >>= 1) {
+            int j = k >> 1;
+            for (; j >= 64; j >>= 1) {
                 for (int i = threadIdx.x; i < n2; i += CULL_THREADS) {
                     const int ixj = i ^ j;
                     if (ixj > i) {
@@ -677,9 +722,28 @@ __global__ void __launch_bounds__(CULL_THREADS) k_b_cull(const Attempt *__restri
                 }
                 __syncthreads();
             }
+            // j < 64: partners are lanes of the same wavefront (n2 is a
+            // multiple of 64, so every wavefront's block is whole)
+            for (int base = wave * 64; base < n2; base += CULL_THREADS) {
+                const int i = base + lane;
+                unsigned long long x = keys[i];
+                const bool asc = (i & k) == 0;
+                for (int jj = j; jj > 0; jj >>= 1) {
+                    const unsigned long long y = __shfl_xor(x, jj, 64);
+                    const bool lower = (lane & jj) == 0;
+                    const unsigned long long lo = x < y ? x : y, hi = x < y ? y : x;
+                    x = (lower == asc) ? lo : hi;
+                }
+                keys[i] = x;
+            }
+            __syncthreads();
         }
         const int keep = (na + 1) / 2;
-        for (int ap = threadIdx.x; ap < keep; ap += CULL_THREADS) A.alive[ap] = (int32_t)(keys[ap] & 0xFFFFFFFFull);
+        for (int i = threadIdx.x; i < keep; i += CULL_THREADS) {
+            const unsigned long long key = keys[i];
+            A.alive[i] = (int32_t)((key >> 12) & 0xFFFFFull);
+            A.pos[i] = (int32_t)(key & 0xFFFull);
+        }
         __syncthreads();
         if (threadIdx.x == 0) {
             if (r < MAX_ROUNDS) A.tr_n_alive[r] = na;
@@ -711,7 +775,7 @@ __device__ __forceinline__ int refine_sums_of(const Attempt &A, int sidx, double
 {
     const int lane = __lane_id();
     const int h = A.alive[sidx];
-    const int ap = A.pos[h];
+    const int ap = A.pos[sidx];
 #pragma unroll
     for (int k = 0; k < NSUM; ++k) s[k] = 0.0;
     // lane-strided draws, RB per lane at a time: all inlier ids first, then the
