@@ -106,7 +106,59 @@ def cpu_baseline(sc, budget_s: float = 25.0):
                       f"{ok}/{n} within 5 cm/5 deg"}
 
 
-def plain_full(args, dev):
+HBM_PEAK_GBS = 8000.0              # MI355X HBM3E (published)
+BF16_PEAK_TFLOPS = 2500.0          # MI355X dense BF16 matrix (published)
+MLP_FLOP_PER_PIXEL = 2 * (24 * 64 + 64 * 64 + 64)   # one forward pass of the 24-64-64-1 network
+
+
+def profiled(run):
+    """Runs `run()` once with per-kernel HIP-event timing (kernels launched one
+    by one); returns (its result, {kernel: (total ms, launches)})."""
+    import torch
+    import paper_1801_08361_amd as rl
+    rl.profile_reset()
+    rl.profile_enable(True)
+    res = run()
+    torch.cuda.synchronize()
+    rl.profile_enable(False)
+    kernels = {k: rl.profile_read(k) for k in rl.profile_kernels()}
+    rl.profile_reset()
+    return res, kernels
+
+
+def rooflines(kernels, res, attempts):
+    """Roofline entries of one profiled pass: the scoring kernel (FP32 ALU,
+    FLOPs counted by the kernels), the traversal kernel (algorithmic bytes: 2 B
+    depth + 3 B colour read and 4 B leaf index written per pixel and tree) and,
+    where learned pick weights were computed in the pass, the weight kernel
+    (one network forward pass per pixel on the matrix cores). `attempts` are
+    (pixels, trees, learned) per attempt; `dominant` is the kernel with the
+    largest total time."""
+    out = {}
+
+    def entry(name, bound, work, peak, unit):
+        ms, n = kernels.get(name, (0.0, 0))
+        if not n or ms <= 0:
+            return None
+        avg_s = ms / n * 1e-3
+        achieved = work / n / avg_s / (1e12 if unit == "TFLOP/s" else 1e9)
+        return {"kernel": name, "bound": bound, "achieved": achieved, "peak": peak, "unit": unit,
+                "frac": achieved / peak, "traffic": None, "avg_launch_us": avg_s * 1e6,
+                "work_per_launch": work / n, "launches": n}
+
+    flops = sum(r["mode_evals"] * FLOP_PER_MODE_TERM + r["pair_evals"] * FLOP_PER_PAIR for r in res)
+    out["k_b_score"] = entry("k_b_score", "alu", flops, FP32_PEAK_TFLOPS, "TFLOP/s")
+    leaf_bytes = sum(P * (5 + 4 * T) for P, T, _ in attempts)
+    out["k_b_leaves"] = entry("k_b_leaves", "hbm", leaf_bytes, HBM_PEAK_GBS, "GB/s")
+    mlp = sum(P * MLP_FLOP_PER_PIXEL for P, _, learned in attempts if learned)
+    if mlp:
+        out["k_b_weights"] = entry("k_b_weights", "mfma", mlp, BF16_PEAK_TFLOPS, "TFLOP/s")
+    out = {k: v for k, v in out.items() if v is not None}
+    out["dominant"] = max(kernels.items(), key=lambda kv: kv[1][0])[0] if kernels else None
+    return out
+
+
+def plain_full(args, dev, batched: bool = True):
     import numpy as np
     import torch
     import paper_1801_08361_amd as rl
@@ -148,24 +200,16 @@ def plain_full(args, dev):
     log(f"plain full: {tot / wall:.1f} relocalisations/s, success {ok}/{tot}")
 
     # profiled pass: the same step with per-kernel events
-    rl.profile_reset()
-    rl.profile_enable(True)
-    res = step()
-    torch.cuda.synchronize()
-    rl.profile_enable(False)
-    kernels = {k: rl.profile_read(k) for k in rl.profile_kernels()}
-    rl.profile_reset()
-    flops = sum(r["mode_evals"] * FLOP_PER_MODE_TERM + r["pair_evals"] * FLOP_PER_PAIR for r in res)
-    sc_ms, sc_n = kernels.get("k_b_score", (0.0, 0))
+    res, kernels = profiled(step)
     log("kernel totals over one profiled step: " +
         ", ".join(f"{k}={v[0]:.2f}ms/{v[1]}" for k, v in sorted(kernels.items(), key=lambda kv: -kv[1][0])))
-    roof = None
-    if sc_n:
-        avg_s = sc_ms / sc_n * 1e-3
-        achieved = flops / sc_n / avg_s / 1e12
-        roof = {"kernel": "k_b_score", "bound": "alu", "achieved": achieved, "peak": FP32_PEAK_TFLOPS,
-                "unit": "TFLOP/s", "frac": achieved / FP32_PEAK_TFLOPS, "traffic": None,
-                "avg_launch_us": avg_s * 1e6, "flops_per_launch": flops / sc_n}
+    P = queries[0][0].numel()
+    roofs = rooflines(kernels, res, [(P, g.T, False)] * len(queries))
+    roof = roofs.get("k_b_score")
+    if not batched:
+        return dict(sc=sc, value=tot / wall, wall=wall, success=ok / max(tot, 1), n=tot, kernels=kernels, roof=roof,
+                    rooflines=roofs, adapt_fps=len(adapt) / t_adapt, modes_s=t_modes, mem=g.memory(), forest=g,
+                    queries=queries, batched=None)
     # the same 50 queries as one batched call (bit-identical results)
     b = rl.Batch(tune=True)
     att = [dict(forest=g, depth=d, rgb=c, K=sc.K, seed=1 + q) for q, (d, c) in enumerate(queries)]
@@ -179,13 +223,16 @@ def plain_full(args, dev):
         runs.append(time.perf_counter() - t1)
     ok_b = sum(int(r["status"] == 0 and success(r["pose"], sc.query_poses[q])) for q, r in enumerate(res_b))
     same = all(r["status"] == p["status"] and np.array_equal(r["pose"], p["pose"]) for r, p in zip(res_b, res))
+    _, kernels_b = profiled(lambda: b.run(att))
     batched = {"value": len(att) * args.steps / sum(runs), "unit": "relocalisations/s",
                "success_rate": ok_b / len(att), "identical_to_plain": same, "schedule": b.schedule(),
-               "runs_ms": [round(t * 1e3, 2) for t in runs]}
+               "runs_ms": [round(t * 1e3, 2) for t in runs],
+               "rooflines": rooflines(kernels_b, res_b, [(P, g.T, False)] * len(att))}
     log(f"full-size batched (50 queries per call): {batched['value']:.1f}/s, success {ok_b}/{len(att)}, "
         f"identical={same}")
     del b
     return dict(sc=sc, value=tot / wall, wall=wall, success=ok / max(tot, 1), n=tot, kernels=kernels, roof=roof,
+                rooflines=roofs,
                 adapt_fps=len(adapt) / t_adapt, modes_s=t_modes, mem=g.memory(), forest=g, queries=queries,
                 batched=batched)
 
@@ -267,6 +314,10 @@ def learned_full(args, dev, full):
         valid = sum(r["n_valid"] for r in res) / len(res)
         forms[name] = {"value": len(queries) * args.steps / wall, "unit": "relocalisations/s",
                        "success_rate": ok / len(queries), "n_hypotheses": n_hyp, "mean_valid_hypotheses": valid}
+        if name in ("learned_256", "uniform_256"):
+            res_prof, kernels = profiled(lambda: run(n_hyp, use))
+            P = queries[0][0].numel()
+            forms[name]["rooflines"] = rooflines(kernels, res_prof, [(P, g.T, use)] * len(queries))
         log(f"{name}: {forms[name]['value']:.1f}/s, success {ok}/{len(queries)}, valid hypotheses {valid:.1f}")
     return forms
 
@@ -328,8 +379,11 @@ def batched_mixed(args, dev):
     n = len(att) * args.steps
     log(f"batched: {n / wall_b:.1f}/s vs sequential plain {n / wall_p:.1f}/s; identical={identical}; "
         f"success {ok}/{len(att)}")
+    shapes = [(a["depth"].numel(), a["forest"].T) for a in att]
+    res_prof, kernels_b = profiled(lambda: b.run(att))
     out = {"batched": {"value": n / wall_b, "unit": "relocalisations/s", "schedule": b.schedule(),
-                       "success_rate": ok / len(att), "runs_ms": [round(t * 1e3, 3) for t in runs_b]},
+                       "success_rate": ok / len(att), "runs_ms": [round(t * 1e3, 3) for t in runs_b],
+                       "rooflines": rooflines(kernels_b, res_prof, [(P, T, False) for P, T in shapes])},
            "sequential_plain": {"value": n / wall_p, "unit": "relocalisations/s"},
            "speedup": wall_p / wall_b, "identical_to_plain": identical, "success_rate": ok / len(att),
            "workload": "64 attempts, 8 forests (320x240 rooms, 5 trees depth 10, R=256, 20 frames each); "
@@ -358,8 +412,10 @@ def batched_mixed(args, dev):
         wall = time.perf_counter() - t0
         ok = sum(int(r["status"] == 0 and success(r["pose"], gt)) for r, gt in zip(res, gts))
         valid = sum(r["n_valid"] for r in res) / len(res)
+        res_prof, kernels_b = profiled(lambda: bb.run(with_weights(n_hyp, use)))
         out[name] = {"value": n / wall, "unit": "relocalisations/s", "success_rate": ok / len(att),
-                     "mean_valid_hypotheses": valid, "schedule": bb.schedule()}
+                     "mean_valid_hypotheses": valid, "schedule": bb.schedule(),
+                     "rooflines": rooflines(kernels_b, res_prof, [(P, T, use) for P, T in shapes])}
         log(f"{name}: {n / wall:.1f}/s, success {ok}/{len(att)}, valid hypotheses {valid:.1f}")
     return out
 
@@ -456,7 +512,8 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--no-batched", action="store_true",
+                    help="skip the batched forms (the full-size batch of the 50 queries and the mixed workload)")
     ap.add_argument("--no-learned", action="store_true")
     ap.add_argument("--queue", action="store_true",
                     help="also run the collaborative-scale queue (16 full-size forests, 1024 attempts; minutes)")
@@ -477,13 +534,15 @@ def main():
     gc.collect()
     gc.disable()
     if args.copy_calibration:
+        # an elementwise kernel (not a DMA copy, which counters do not see)
+        # that reads 256 MiB once and writes 256 MiB once
         src = torch.ones(1 << 26, dtype=torch.float32, device=dev)
         dst = torch.empty_like(src)
-        dst.copy_(src)
+        torch.mul(src, 1.0, out=dst)
         torch.cuda.synchronize()
-        log("copy calibration: 268435456 bytes read, 268435456 bytes written by one copy kernel")
+        log("copy calibration: 268435456 bytes read, 268435456 bytes written by one elementwise kernel")
         del src, dst
-    full = plain_full(args, dev)
+    full = plain_full(args, dev, batched=not args.no_batched)
     out = {
         "metric": "relocalisations/sec at >=95% success (<=5cm/5deg), plain vs batched+learned",
         "value": full["value"],
@@ -501,8 +560,10 @@ def main():
         "adapt_frames_per_s": full["adapt_fps"],
         "forest_bytes": full["mem"],
     }
-    forms = {"plain_full": {"value": full["value"], "unit": "relocalisations/s", "success_rate": full["success"]},
-             "batched_full": full["batched"]}
+    forms = {"plain_full": {"value": full["value"], "unit": "relocalisations/s", "success_rate": full["success"],
+                            "rooflines": full["rooflines"]}}
+    if full["batched"] is not None:
+        forms["batched_full"] = full["batched"]
     if not args.no_learned:
         forms["learned_full"] = learned_full(args, dev, full)
     if not args.no_batched:

@@ -358,6 +358,13 @@ int reloc_debug_unit_owners(int32_t xcd, int32_t total, int32_t grid, int32_t *o
  * eigenvalue) and the device falls back to power iteration. */
 int reloc_debug_horn(const double *h_host, int32_t n, double *q_host);
 
+/* Host run of the probe-offset division (the truncating quotient of the
+ * depth-adaptive offset of Sec. 3.2's features, delta F / (d F_ref), formed by
+ * multiplication): q_host[i] = trunc(n_host[i] / den_host[i]) for count
+ * entries, host arrays. RELOC_E_ARG if a divisor is below 1 or a numerator is
+ * -2^31 (the kernels' range is |n| < 2^31, 1 <= den < 2^31). */
+int reloc_debug_div(const int32_t *n_host, const int32_t *den_host, int32_t count, int32_t *q_host);
+
 /* One 16x16 product C = A B on the matrix cores as the MLP kernels issue it
  * (bfloat16 operands, FP32 accumulation): a_host [16][32] row-major A,
  * bt_host [16][32] row-major B^T, c_host [16][16] row-major C. Synchronous. */

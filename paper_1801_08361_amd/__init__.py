@@ -136,6 +136,7 @@ _SIGS = {
                            C.c_void_p, C.c_void_p],
     "reloc_debug_mfma_probe": [C.c_void_p, C.c_void_p, C.c_void_p],
     "reloc_debug_horn": [C.c_void_p, C.c_int32, C.c_void_p],
+    "reloc_debug_div": [C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p],
     "reloc_relocalise_learned": [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_uint64, C.c_int32,
                                  C.c_void_p, C.c_void_p],
 }
@@ -152,10 +153,22 @@ def unit_owners(xcd: int, total: int, grid: int) -> np.ndarray:
 
 def horn_quaternions(H: np.ndarray) -> np.ndarray:
     """Host run of the pose solver's eigenvector step on cross-covariances
-    H [n, 3, 3]; NaN rows where the device would use Jacobi sweeps."""
+    H [n, 3, 3]; NaN rows where the device falls back to power iteration."""
     H = np.ascontiguousarray(H, dtype=np.float64).reshape(-1, 9)
     q = np.zeros((len(H), 4))
     _check(lib().reloc_debug_horn(H.ctypes.data if len(H) else None, len(H), q.ctypes.data), "reloc_debug_horn")
+    return q
+
+
+def probe_div(n: np.ndarray, den: np.ndarray) -> np.ndarray:
+    """Host run of the kernels' probe-offset division: trunc(n / den)."""
+    n = np.ascontiguousarray(n, dtype=np.int32)
+    den = np.ascontiguousarray(den, dtype=np.int32)
+    if n.shape != den.shape:
+        raise ValueError("n and den differ in shape")
+    q = np.zeros(n.shape, dtype=np.int32)
+    _check(lib().reloc_debug_div(n.ctypes.data if n.size else None, den.ctypes.data if n.size else None, n.size,
+                                 q.ctypes.data if n.size else None), "reloc_debug_div")
     return q
 
 

@@ -166,30 +166,44 @@ __device__ __forceinline__ void cam_point(const Frame &fr, int u, int v, uint32_
     c[2] = z;
 }
 
-// The divisor of a pixel's probe offsets, d * F_ref, with its FP64 reciprocal
+// The divisor of a pixel's probe offsets, D = d * F_ref, turned into a
+// multiplier for exact truncating division by multiplication (Granlund and
+// Montgomery, 1994): with l = ceil(log2 D) and m = ceil(2^(31 + l) / D), which
+// is below 2^32, every 0 <= a < 2^31 has floor(a / D) = floor(2a m / 2^(32 + l)):
+// the high word of the 32 x 32-bit product (2a) m, shifted right by l.
+// (Write m = (2^(31 + l) + e) / D with 0 <= e < D; then a m / 2^(31 + l)
+// exceeds a / D by less than 2^-l <= 1 / D, which cannot reach the next
+// integer.)
 struct PixelDen {
-    int32_t den;
-    double rden;
+    uint32_t magic;
+    uint32_t shift;
 };
 
-__device__ __forceinline__ PixelDen pixel_den(const Frame &fr, int32_t d)
+__host__ __device__ __forceinline__ PixelDen pixel_den_of(uint32_t D)
 {
     PixelDen p;
-    p.den = d * fr.Fref;
-    p.rden = 1.0 / (double)p.den;
+    const uint32_t l = D > 1u ? 32u - (uint32_t)__builtin_clz(D - 1u) : 0u;
+    p.shift = l;
+    p.magic = (uint32_t)(((1ull << (31u + l)) + (uint64_t)D - 1ull) / (uint64_t)D);
     return p;
 }
 
-// trunc(n / den) exactly, for |n| < 2^31 and 0 < den < 2^31: the FP64
-// estimate |n| * (1 / den) is within 2^-20 / den of the quotient, so its
-// truncation is the quotient or one less, and one integer check settles it
-// (the products stay below 2^32)
-__device__ __forceinline__ int32_t div_trunc(int32_t n, const PixelDen &p)
+__device__ __forceinline__ PixelDen pixel_den(const Frame &fr, int32_t d)
+{
+    return pixel_den_of((uint32_t)(d * fr.Fref));
+}
+
+// floor(a / D) for a2 = 2a, a < 2^31
+__host__ __device__ __forceinline__ uint32_t div_mag2(uint32_t a2, const PixelDen &p)
+{
+    return (uint32_t)(((uint64_t)a2 * (uint64_t)p.magic) >> 32) >> p.shift;
+}
+
+// trunc(n / D) for |n| < 2^31
+__host__ __device__ __forceinline__ int32_t div_trunc(int32_t n, const PixelDen &p)
 {
     const uint32_t an = (uint32_t)(n < 0 ? -n : n);
-    const uint32_t q0 = (uint32_t)((double)an * p.rden);
-    const uint32_t prod = q0 * (uint32_t)p.den;
-    const uint32_t q = prod > an ? q0 - 1u : (an - prod >= (uint32_t)p.den ? q0 + 1u : q0);
+    const uint32_t q = div_mag2(an << 1, p);
     return n < 0 ? -(int32_t)q : (int32_t)q;
 }
 
@@ -252,80 +266,87 @@ __device__ __forceinline__ int32_t traverse(const uint64_t *__restrict__ tree, i
 
 constexpr int TOP_NODES = 1023;   // levels 0..9, 16 KB unpacked
 
-struct TopNode {
-    int32_t dxF, dyF, thr, kind;
+// One pixel of a frame packed for probing: the depth in bits 0-15 (65535
+// where it lies outside the valid range; the host keeps the range below
+// 65535) and the colour r, g, b in bits 16-23, 24-31 and 32-39, so that one
+// 8-byte load serves a probe of either kind.
+__device__ __forceinline__ uint64_t pack_pixel(const Frame &fr, int64_t p)
+{
+    const uint32_t d = fr.depth[p];
+    const uint64_t z = valid_depth(fr, d) ? (uint64_t)d : 65535ull;
+    return z | ((uint64_t)fr.rgb[p * 3] << 16) | ((uint64_t)fr.rgb[p * 3 + 1] << 24) |
+           ((uint64_t)fr.rgb[p * 3 + 2] << 32);
+}
+
+__device__ __forceinline__ bool packed_valid(uint64_t w) { return (w & 0xFFFFull) != 0xFFFFull; }
+
+// A split node prepared for one frame: its offsets multiplied by the focal
+// lengths, as the doubled magnitudes that div_mag2 takes, with their signs,
+// the feature kind and the bit position of the probed channel in a packed
+// pixel word.
+struct ProbeNode {
+    uint32_t ax, ay;   // 2 |dx Fx|, 2 |dy Fy|
+    int32_t thr;
+    uint32_t meta;     // bits 0-1 kind, bit 2 dx < 0, bit 3 dy < 0, bits 8-13 channel shift
 };
 
-__device__ __forceinline__ void stage_top(TopNode *__restrict__ top, const uint64_t *__restrict__ tree, int ntop,
+__device__ __forceinline__ ProbeNode probe_node(uint64_t w, const Frame &fr)
+{
+    int32_t kind, dx, dy, thr;
+    unpack_node(w, kind, dx, dy, thr);
+    const int32_t nx = dx * fr.Fx, ny = dy * fr.Fy;
+    ProbeNode n;
+    n.ax = (uint32_t)(nx < 0 ? -nx : nx) << 1;
+    n.ay = (uint32_t)(ny < 0 ? -ny : ny) << 1;
+    n.thr = thr;
+    n.meta = (uint32_t)kind | (nx < 0 ? 4u : 0u) | (ny < 0 ? 8u : 0u) | ((kind ? 8u + 8u * (uint32_t)kind : 0u) << 8);
+    return n;
+}
+
+__device__ __forceinline__ void stage_top(ProbeNode *__restrict__ top, const uint64_t *__restrict__ tree, int ntop,
                                           const Frame &fr, int tid, int nthreads)
 {
-    for (int k = tid; k < ntop; k += nthreads) {
-        int32_t kind, dx, dy, thr;
-        unpack_node(tree[k], kind, dx, dy, thr);
-        TopNode n;
-        n.dxF = dx * fr.Fx;
-        n.dyF = dy * fr.Fy;
-        n.thr = thr;
-        n.kind = kind;
-        top[k] = n;
-    }
+    for (int k = tid; k < ntop; k += nthreads) top[k] = probe_node(tree[k], fr);
 }
 
-struct PixelCtx {
-    int32_t u, v, d;
-    PixelDen pd;
-    uint32_t own;   // the pixel's own colour, r | g << 8 | b << 16
-};
-
-__device__ __forceinline__ PixelCtx pixel_ctx(const Frame &fr, int u, int v, int32_t d)
+// node_response_d of a prepared node, from the packed frame: `own` is the
+// pixel's own packed word. Branch-free: the probe position is clamped into
+// the image and one word is loaded; a depth probe whose position was clamped
+// reads 65535 instead.
+__device__ __forceinline__ int32_t probe_response(const uint64_t *__restrict__ packed, int W, int H, int u, int v,
+                                                  uint64_t own, const PixelDen &pd, const ProbeNode &n)
 {
-    PixelCtx px;
-    px.u = u;
-    px.v = v;
-    px.d = d;
-    px.pd = pixel_den(fr, d);
-    const int o = (v * fr.W + u) * 3;
-    px.own = (uint32_t)fr.rgb[o] | ((uint32_t)fr.rgb[o + 1] << 8) | ((uint32_t)fr.rgb[o + 2] << 16);
-    return px;
+    const int32_t ox = (int32_t)div_mag2(n.ax, pd), oy = (int32_t)div_mag2(n.ay, pd);
+    const int32_t qx = u + ((n.meta & 4u) ? -ox : ox);
+    const int32_t qy = v + ((n.meta & 8u) ? -oy : oy);
+    const int32_t cx = qx < 0 ? 0 : (qx > W - 1 ? W - 1 : qx);
+    const int32_t cy = qy < 0 ? 0 : (qy > H - 1 ? H - 1 : qy);
+    // a global-memory load at a 32-bit word offset from the frame's base
+    const uint64_t w = ((const __attribute__((address_space(1))) uint64_t *)packed)[(uint32_t)(cy * W + cx)];
+    const uint32_t sh = (n.meta >> 8) & 63u;
+    const uint32_t mask = (n.meta & 3u) ? 0xFFu : 0xFFFFu;
+    uint32_t val = (uint32_t)(w >> sh) & mask;
+    if ((n.meta & 3u) == 0u && (qx != cx || qy != cy)) val = 65535u;
+    return (int32_t)val - (int32_t)((uint32_t)(own >> sh) & mask);
 }
 
-// node_response for offsets already multiplied by the focal lengths
-__device__ __forceinline__ int32_t response_scaled(const Frame &fr, const PixelCtx &px, int32_t dxF, int32_t dyF,
-                                                   int32_t kind)
+// traversal of one tree for a valid pixel (u, v) of a packed frame, with nodes
+// [0, ntop) (whole top levels) read from their prepared LDS copy
+__device__ __forceinline__ int32_t traverse_packed(const ProbeNode *__restrict__ top, int32_t ntop,
+                                                   const uint64_t *__restrict__ tree, int32_t L, const Frame &fr,
+                                                   const uint64_t *__restrict__ packed, int u, int v, uint64_t own)
 {
-    int32_t qx = px.u + div_trunc(dxF, px.pd);
-    int32_t qy = px.v + div_trunc(dyF, px.pd);
-    if (kind == 0) {
-        int32_t dq = 65535;
-        if (qx >= 0 && qx < fr.W && qy >= 0 && qy < fr.H) {
-            const uint32_t z = fr.depth[qy * fr.W + qx];
-            if (valid_depth(fr, z)) dq = (int32_t)z;
-        }
-        return dq - px.d;
-    }
-    qx = qx < 0 ? 0 : (qx > fr.W - 1 ? fr.W - 1 : qx);
-    qy = qy < 0 ? 0 : (qy > fr.H - 1 ? fr.H - 1 : qy);
-    const int32_t own = (int32_t)((px.own >> (8 * (kind - 1))) & 255u);
-    return (int32_t)fr.rgb[(qy * fr.W + qx) * 3 + kind - 1] - own;
-}
-
-// traversal with nodes [0, ntop) (whole top levels) read from the LDS copy
-__device__ __forceinline__ int32_t traverse_top(const TopNode *__restrict__ top, int32_t ntop,
-                                                const uint64_t *__restrict__ tree, int32_t L, const Frame &fr, int u,
-                                                int v, int32_t d)
-{
-    const PixelCtx px = pixel_ctx(fr, u, v, d);
+    const PixelDen pd = pixel_den(fr, (int32_t)(own & 0xFFFFull));
     int32_t i = 0;
     while (i < ntop) {
-        const TopNode n = top[i];
-        const int32_t r = response_scaled(fr, px, n.dxF, n.dyF, n.kind);
+        const ProbeNode n = top[i];
+        const int32_t r = probe_response(packed, fr.W, fr.H, u, v, own, pd, n);
         i = 2 * i + 1 + (r >= n.thr ? 1 : 0);
     }
     while (i < L - 1) {
-        int32_t kind, dx, dy, thr;
-        unpack_node(tree[i], kind, dx, dy, thr);
-        const int32_t r = response_scaled(fr, px, dx * fr.Fx, dy * fr.Fy, kind);
-        i = 2 * i + 1 + (r >= thr ? 1 : 0);
+        const ProbeNode n = probe_node(tree[i], fr);
+        const int32_t r = probe_response(packed, fr.W, fr.H, u, v, own, pd, n);
+        i = 2 * i + 1 + (r >= n.thr ? 1 : 0);
     }
     return i - (L - 1);
 }
@@ -624,6 +645,7 @@ struct Forest {
     // per-frame adaptation scratch (grows with the frame size)
     int64_t cap_P = 0;
     int32_t *leaves = nullptr;     // [T][P]
+    uint64_t *packed = nullptr;    // [P] the frame packed for probing
     uint16_t *rank = nullptr;      // [T][P]
     int32_t *slot = nullptr;       // [T][P]
     uint32_t *kval = nullptr;      // [T][P]
@@ -656,6 +678,7 @@ struct Attempt {
     uint64_t seed;
     // scratch owned by the batch
     int32_t *leaves;               // [T][P]
+    uint64_t *packed;              // [P] the frame packed for probing
     int32_t *pool;                 // [P]
     int32_t *blockcnt;             // [nb]
     unsigned long long *blockw;    // [nb] weight sums per pixel block

@@ -151,10 +151,16 @@ __global__ void k_gen_nodes(uint64_t *nodes, int T, int L, uint64_t seed, int32_
 
 // one thread per (pixel, tree): blockIdx.y is the tree, so the trees' node
 // chains run side by side instead of one after another
-__global__ void __launch_bounds__(256) k_leaves(const uint64_t *__restrict__ nodes, int T, int L, Frame fr,
-                                                int32_t *__restrict__ leaves)
+__global__ void __launch_bounds__(256) k_pack(Frame fr, uint64_t *__restrict__ packed)
 {
-    __shared__ TopNode top[TOP_NODES];
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p < (int64_t)fr.W * fr.H) packed[p] = pack_pixel(fr, p);
+}
+
+__global__ void __launch_bounds__(256) k_leaves(const uint64_t *__restrict__ nodes, int T, int L, Frame fr,
+                                                const uint64_t *__restrict__ packed, int32_t *__restrict__ leaves)
+{
+    __shared__ ProbeNode top[TOP_NODES];
     const int P = fr.W * fr.H;
     const int p = blockIdx.x * blockDim.x + threadIdx.x;
     const int t = blockIdx.y;
@@ -163,10 +169,9 @@ __global__ void __launch_bounds__(256) k_leaves(const uint64_t *__restrict__ nod
     stage_top(top, tree, ntop, fr, (int)threadIdx.x, (int)blockDim.x);
     __syncthreads();
     if (p >= P || t >= T) return;
-    int u = p % fr.W, v = p / fr.W;
-    uint32_t d = fr.depth[p];
+    const uint64_t own = packed[p];
     int32_t leaf = -1;
-    if (valid_depth(fr, d)) leaf = traverse_top(top, ntop, tree, L, fr, u, v, (int32_t)d);
+    if (packed_valid(own)) leaf = traverse_packed(top, ntop, tree, L, fr, packed, p % fr.W, p / fr.W, own);
     leaves[(int64_t)t * P + p] = leaf;
 }
 
@@ -595,6 +600,7 @@ static int ensure_frame_scratch(Forest *f, int64_t P, hipStream_t s)
     if (P <= f->cap_P) return RELOC_OK;
     int64_t C_old = (f->cap_P + CHUNK - 1) / CHUNK;
     dfree(f, &f->leaves, (size_t)f->T * f->cap_P);
+    dfree(f, &f->packed, (size_t)f->cap_P);
     dfree(f, &f->rank, (size_t)f->T * f->cap_P);
     dfree(f, &f->slot, (size_t)f->T * f->cap_P);
     dfree(f, &f->kval, (size_t)f->T * f->cap_P);
@@ -604,6 +610,7 @@ static int ensure_frame_scratch(Forest *f, int64_t P, hipStream_t s)
     int64_t C = (P + CHUNK - 1) / CHUNK;
     int rc = RELOC_OK;
     rc |= dalloc(f, &f->leaves, (size_t)f->T * P, s);
+    rc |= dalloc(f, &f->packed, (size_t)P, s);
     rc |= dalloc(f, &f->rank, (size_t)f->T * P, s);
     rc |= dalloc(f, &f->slot, (size_t)f->T * P, s);
     rc |= dalloc(f, &f->kval, (size_t)f->T * P, s);
@@ -634,8 +641,9 @@ int traverse_frame(Forest *f, const Frame &fr, hipStream_t s)
     int64_t P = (int64_t)fr.W * fr.H;
     int rc = ensure_frame_scratch(f, P, s);
     if (rc) return rc;
+    RL_LAUNCH("k_pack", k_pack, dim3((unsigned)((P + 255) / 256)), dim3(256), 0, s, fr, f->packed);
     RL_LAUNCH("k_leaves", k_leaves, dim3((unsigned)((P + 255) / 256), (unsigned)f->T), dim3(256), 0, s, f->nodes,
-              f->T, f->L, fr, f->leaves);
+              f->T, f->L, fr, f->packed, f->leaves);
     RL_HIP(hipGetLastError());
     return RELOC_OK;
 }
@@ -692,6 +700,7 @@ static void forest_free(Forest *f)
     dfree(f, &f->dirty_count, 1);
     dfree(f, &f->total_samples, 1);
     dfree(f, &f->leaves, (size_t)f->T * f->cap_P);
+    dfree(f, &f->packed, (size_t)f->cap_P);
     dfree(f, &f->rank, (size_t)f->T * f->cap_P);
     dfree(f, &f->slot, (size_t)f->T * f->cap_P);
     dfree(f, &f->kval, (size_t)f->T * f->cap_P);

@@ -67,7 +67,7 @@ __device__ __forceinline__ bool round_active(const Attempt &A, int r)
 // between its units).
 __global__ void __launch_bounds__(PIX_BLOCK) k_b_leaves(const Attempt *__restrict__ att, Stage S)
 {
-    __shared__ TopNode top[TOP_NODES];
+    __shared__ ProbeNode top[TOP_NODES];
     int cached_a = -1, cached_t = -1;
     FOR_UNITS(S, u) {
         const int a = attempt_of(S, u);
@@ -87,10 +87,9 @@ __global__ void __launch_bounds__(PIX_BLOCK) k_b_leaves(const Attempt *__restric
         }
         const int p = (local % nb) * PIX_BLOCK + (int)threadIdx.x;
         if (p >= A.P) continue;
-        const int uu = p % fr.W, vv = p / fr.W;
-        const uint32_t d = fr.depth[p];
+        const uint64_t own = A.packed[p];
         int32_t leaf = -1;
-        if (valid_depth(fr, d)) leaf = traverse_top(top, ntop, tree, A.L, fr, uu, vv, (int32_t)d);
+        if (packed_valid(own)) leaf = traverse_packed(top, ntop, tree, A.L, fr, A.packed, p % fr.W, p / fr.W, own);
         A.leaves[(int64_t)t * A.P + p] = leaf;
     }
 }
@@ -129,7 +128,13 @@ __global__ void __launch_bounds__(64) k_b_weights(const Attempt *__restrict__ at
         store_row(T, x);
         __syncthreads();
         tile_forward<FwdTile, false>(T, A.mq, A.mw);
-        if (p < A.P) A.wbuf[p] = ok ? pick_weight(T.z[l], nullptr) : 0u;
+        const uint32_t w = (p < A.P && ok) ? pick_weight(T.z[l], nullptr) : 0u;
+        if (p < A.P) A.wbuf[p] = w;
+        // the tile's weight sum into its pixel block's (zeroed by k_b_pack;
+        // integer sums, so the order of the additions does not matter)
+        unsigned long long ws = w;
+        for (int o = 32; o > 0; o >>= 1) ws += __shfl_xor(ws, o, 64);
+        if (l == 0 && ws) atomicAdd(&A.blockw[(p - l) / POOL_BLOCK], ws);
     }
 }
 
@@ -147,7 +152,11 @@ __device__ __forceinline__ unsigned long long wave_incl_scan_u64(unsigned long l
     return x;
 }
 
-__global__ void __launch_bounds__(POOL_BLOCK) k_b_pool_count(const Attempt *__restrict__ att, Stage S)
+// unit = block of POOL_BLOCK pixels: the frame packed for probing (one word
+// per pixel), the block's count of valid pixels and, for pick weights given
+// by the caller, the block's weight sum (learned weights computed in the
+// batch add theirs in k_b_weights, onto the zero written here)
+__global__ void __launch_bounds__(POOL_BLOCK) k_b_pack(const Attempt *__restrict__ att, Stage S)
 {
     __shared__ unsigned long long wsum[POOL_BLOCK / 64];
     FOR_UNITS(S, u) {
@@ -155,9 +164,14 @@ __global__ void __launch_bounds__(POOL_BLOCK) k_b_pool_count(const Attempt *__re
         const Attempt &A = att[a];
         const int b = u - S.off[a];
         const int p = b * POOL_BLOCK + (int)threadIdx.x;
-        const bool ok = p < A.P && valid_depth(A.fr, A.fr.depth[p]);
+        bool ok = false;
+        if (p < A.P) {
+            const uint64_t w = pack_pixel(A.fr, p);
+            A.packed[p] = w;
+            ok = packed_valid(w);
+        }
         const int n = __syncthreads_count(ok);
-        if (A.weights) {
+        if (A.weights && !A.mq) {
             unsigned long long w = ok ? (unsigned long long)A.weights[p] : 0ull;
             w = wave_incl_scan_u64(w);
             if (__lane_id() == 63) wsum[threadIdx.x / 64] = w;
@@ -168,6 +182,8 @@ __global__ void __launch_bounds__(POOL_BLOCK) k_b_pool_count(const Attempt *__re
                 A.blockw[b] = tot;
             }
             __syncthreads();
+        } else if (A.weights && threadIdx.x == 0) {
+            A.blockw[b] = 0ull;
         }
         if (threadIdx.x == 0) A.blockcnt[b] = n;
     }
@@ -982,6 +998,7 @@ static size_t carve(const Shape &s, char *base, Attempt &A)
         return p;
     };
     A.leaves = (int32_t *)take((size_t)s.T * P * 4);
+    A.packed = (uint64_t *)take((size_t)P * 8);
     A.pool = (int32_t *)take((size_t)P * 4);
     A.blockcnt = (int32_t *)take((size_t)nb * 4);
     A.blockw = (unsigned long long *)take((size_t)nb * 8);
@@ -1096,10 +1113,10 @@ static int enqueue(const Plan *pl, const Sched &sc, const Stages &st, hipStream_
     // one workgroup per attempt: plain round-robin ownership
     Stage att = st.att;
     att.xcd = 0;
+    RL_LAUNCH("k_b_pack", k_b_pack, dim3(grid_of(st.pb, cap, sc.xcd)), dim3(POOL_BLOCK), 0, s, d, st.pb);
     RL_LAUNCH("k_b_leaves", k_b_leaves, dim3(grid_of(st.pix, cap, sc.xcd)), dim3(PIX_BLOCK), 0, s, d, st.pix);
     if (st.wts.total > 0)
         RL_LAUNCH("k_b_weights", k_b_weights, dim3(grid_of(st.wts, cap, sc.xcd)), dim3(64), 0, s, d, st.wts);
-    RL_LAUNCH("k_b_pool_count", k_b_pool_count, dim3(grid_of(st.pb, cap, sc.xcd)), dim3(POOL_BLOCK), 0, s, d, st.pb);
     RL_LAUNCH("k_b_pool_scan", k_b_pool_scan, dim3(grid_of(att, cap, 0)), dim3(1024), 0, s, d, att);
     RL_LAUNCH("k_b_pool_write", k_b_pool_write, dim3(grid_of(st.pb, cap, sc.xcd)), dim3(POOL_BLOCK), 0, s, d, st.pb);
     RL_LAUNCH("k_b_hypgen", k_b_hypgen, dim3(grid_of(st.hyp, 0, sc.xcd)), dim3(64), 0, s, d, st.hyp);
@@ -1540,6 +1557,15 @@ extern "C" int reloc_debug_horn(const double *h_host, int32_t n, double *q_host)
         }
         for (int k = 0; k < 4; ++k) q_host[(size_t)i * 4 + k] = q[k];
     }
+    return RELOC_OK;
+}
+
+extern "C" int reloc_debug_div(const int32_t *n_host, const int32_t *den_host, int32_t count, int32_t *q_host)
+{
+    if (count < 0 || (count > 0 && (!n_host || !den_host || !q_host))) return RELOC_E_ARG;
+    for (int32_t i = 0; i < count; ++i)
+        if (den_host[i] < 1 || n_host[i] == INT32_MIN) return RELOC_E_ARG;
+    for (int32_t i = 0; i < count; ++i) q_host[i] = div_trunc(n_host[i], pixel_den_of((uint32_t)den_host[i]));
     return RELOC_OK;
 }
 
