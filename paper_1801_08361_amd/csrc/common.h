@@ -692,7 +692,9 @@ struct Attempt {
     double *sums;                  // [N][NSUM] running inlier sums
     int32_t *alive;                // [N]
     int32_t *pos;                  // [N] survivor i's position in the list it was scored in
-    float4 *draws;                 // [B] camera point, pixel index bits
+    float *lpose;                  // [N][12] FP32 pose (R row-major, t) of the hypothesis at each live position
+    float4 *draws;                 // [rounds][B] camera point, pixel index bits of every draw
+    int2 *dtree;                   // [rounds][B][T] per draw and tree: first global mode index (leaf * M), mode count
     float *gs;                     // [ceil(B / GROUP)][N] energy sum of each group of GROUP draws, per live position
     int32_t *inl;                  // [B][N] global index (leaf * M + mode) of an inlier's best mode, -1 otherwise
     unsigned long long *stats;     // [0] mode evaluations [1] pair evaluations [2] round mode count

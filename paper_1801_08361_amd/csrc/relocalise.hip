@@ -7,10 +7,12 @@
 // draw chunk) pairs, survivors). A whole batch is one captured HIP graph.
 // Layout of the work inside an attempt:
 //  - hypotheses: one wavefront per hypothesis, one lane per try; the first
-//    passing try (lowest lane, then lowest chunk of 64 tries) defines it;
+//    passing try (lowest lane, then lowest chunk of 64 tries) defines it; the
+//    same launch stages every round's draws (pixel, camera point, each tree's
+//    leaf modes), one lane per draw;
 //  - scoring: a workgroup holds 64 live hypotheses (one per lane) and a chunk
-//    of draws spread over its wavefronts; each wavefront draws its pixel,
-//    stages the pixel's modes once in LDS and reads them back as broadcasts
+//    of draws spread over its wavefronts; each wavefront takes its draw,
+//    stages the draw's modes once in LDS and reads them back as broadcasts
 //    while every lane evaluates its own pose; energies are summed per group
 //    of 8 draws in draw order and the group sums go to memory;
 //  - cull: one workgroup per attempt adds the group sums in group order,
@@ -39,7 +41,6 @@ int frame_from(const Forest *f, const uint16_t *depth, const uint8_t *rgb, const
 
 constexpr int PIX_BLOCK = 256;
 constexpr int POOL_BLOCK = 1024;
-constexpr int CULL_THREADS = 1024;
 
 __device__ __forceinline__ uint64_t lanemask_lt() { return (1ull << __lane_id()) - 1ull; }
 
@@ -467,6 +468,24 @@ __global__ void __launch_bounds__(64) k_b_hypgen(const Attempt *__restrict__ att
         const int h = u - S.off[a];
         const int lane = __lane_id();
         const int np = A.misc[0];
+        if (h >= A.N) {
+            // units past the hypotheses: every round's draws, one per lane
+            // (Philox counter (round, draw)), with each tree's leaf modes
+            const int gi = (h - A.N) * 64 + lane;
+            if (gi < A.rounds * A.B && np > 0) {
+                const int rr = gi / A.B, i = gi - rr * A.B;
+                const U4 x = philox((uint64_t)rr, (uint64_t)i, 0, 0, A.seed, TAG_PIX);
+                const int p = A.pool[uniform_int(x.x[0], (uint64_t)np)];
+                float c[3];
+                cam_point(A.fr, p % A.fr.W, p / A.fr.W, A.fr.depth[p], c);
+                A.draws[gi] = make_float4(c[0], c[1], c[2], __int_as_float(p));
+                for (int t = 0; t < A.T; ++t) {
+                    const int li = t * A.L + A.leaves[(int64_t)t * A.P + p];
+                    A.dtree[(int64_t)gi * A.T + t] = make_int2(li * A.M, A.nmodes[li]);
+                }
+            }
+            continue;
+        }
         int found = -1;
         double R[9], t[3];
         for (int chunk = 0; chunk * 64 < A.max_tries && found < 0; ++chunk) {
@@ -501,7 +520,7 @@ __global__ void __launch_bounds__(64) k_b_hypgen(const Attempt *__restrict__ att
     }
 }
 
-// live list = valid hypotheses in index order
+// live list = valid hypotheses in index order, with their FP32 poses
 __global__ void __launch_bounds__(1024) k_b_alive_init(const Attempt *__restrict__ att, Stage S)
 {
     __shared__ int32_t wcnt[16];
@@ -513,13 +532,25 @@ __global__ void __launch_bounds__(1024) k_b_alive_init(const Attempt *__restrict
         __syncthreads();
         for (int base = 0; base < A.N; base += 1024) {
             const int h = base + (int)threadIdx.x;
-            const bool ok = h < A.N && A.hyp_try[h] >= 0;
+            // the pose is loaded together with the try index (one round trip)
+            float pz[12];
+            bool ok = false;
+            if (h < A.N) {
+                const Hyp &hy = A.hyp[h];
+                for (int k = 0; k < 9; ++k) pz[k] = hy.R32[k];
+                for (int k = 0; k < 3; ++k) pz[9 + k] = hy.t32[k];
+                ok = A.hyp_try[h] >= 0;
+            }
             const uint64_t m = __ballot(ok);
             if (__lane_id() == 0) wcnt[wave] = __popcll(m);
             __syncthreads();
             int off = carry;
             for (int w = 0; w < wave; ++w) off += wcnt[w];
-            if (ok) A.alive[off + __popcll(m & lanemask_lt())] = h;
+            if (ok) {
+                const int pos = off + __popcll(m & lanemask_lt());
+                A.alive[pos] = h;
+                for (int k = 0; k < 12; ++k) A.lpose[pos * 12 + k] = pz[k];
+            }
             __syncthreads();
             if (threadIdx.x == 0) {
                 int tot = 0;
@@ -553,223 +584,232 @@ static int score_waves(int tm)
     return w;
 }
 
+// Cull of round r of one attempt, by the whole workgroup: energies in the
+// defined order, bitonic sort of keys (energy key << 32 | index << 12 |
+// position), which orders by (energy, index); keep the first ceil(n / 2),
+// with each survivor's position in this round's list (where its inliers were
+// stored). Compare-exchange distances of 64 and more go through LDS (`keys`,
+// room for the attempt's hypothesis count rounded up to a power of two, at
+// least 64) with a barrier; shorter ones run in registers across the lanes of
+// a wavefront.
+__device__ __forceinline__ unsigned long long cull_key(float E, int h, int ap)
+{
+    return ((unsigned long long)float_key(E) << 32) | ((unsigned long long)(uint32_t)h << 12) | (uint32_t)ap;
+}
+
+__device__ void cull_round(const Attempt &A, int r, unsigned long long *__restrict__ keys)
+{
+    const int nt = (int)blockDim.x;
+    const int lane = __lane_id(), wave = (int)(threadIdx.x >> 6);
+    const int na = A.misc[1];
+    int n2 = 64;
+    while (n2 < na) n2 <<= 1;
+    for (int ap = threadIdx.x; ap < n2; ap += nt) {
+        if (ap < na) {
+            const int h = A.alive[ap];
+            const int ng = (A.B + GROUP - 1) / GROUP;
+            const float *gs = A.gs + ap;
+            // group sums in group order, loaded 32 at a time
+            float Ssum = 0.0f;
+            for (int k0 = 0; k0 < ng; k0 += 32) {
+                float v[32];
+#pragma unroll
+                for (int k = 0; k < 32; ++k) v[k] = k0 + k < ng ? gs[(int64_t)(k0 + k) * A.N] : 0.0f;
+#pragma unroll
+                for (int k = 0; k < 32; ++k)
+                    if (k0 + k < ng) Ssum = Ssum + v[k];
+            }
+            const float E = A.energy[h] + Ssum;
+            A.energy[h] = E;
+            keys[ap] = cull_key(E, h, ap);
+            if (r < MAX_ROUNDS) {
+                A.tr_alive[r * A.N + ap] = h;
+                A.tr_energy[r * A.N + ap] = E;
+            }
+        } else {
+            keys[ap] = ~0ull;
+        }
+    }
+    __syncthreads();
+    for (int k = 2; k <= n2; k <<= 1) {
+        int j = k >> 1;
+        for (; j >= 64; j >>= 1) {
+            for (int i = threadIdx.x; i < n2; i += nt) {
+                const int ixj = i ^ j;
+                if (ixj > i) {
+                    const unsigned long long x = keys[i], y = keys[ixj];
+                    const bool asc = (i & k) == 0;
+                    if ((x > y) == asc) {
+                        keys[i] = y;
+                        keys[ixj] = x;
+                    }
+                }
+            }
+            __syncthreads();
+        }
+        // j < 64: partners are lanes of the same wavefront (n2 is a multiple
+        // of 64, so every wavefront's block is whole)
+        for (int base = wave * 64; base < n2; base += nt) {
+            const int i = base + lane;
+            unsigned long long x = keys[i];
+            const bool asc = (i & k) == 0;
+            for (int jj = j; jj > 0; jj >>= 1) {
+                const unsigned long long y = __shfl_xor(x, jj, 64);
+                const bool lower = (lane & jj) == 0;
+                const unsigned long long lo = x < y ? x : y, hi = x < y ? y : x;
+                x = (lower == asc) ? lo : hi;
+            }
+            keys[i] = x;
+        }
+        __syncthreads();
+    }
+    const int keep = (na + 1) / 2;
+    for (int i = threadIdx.x; i < keep; i += nt) {
+        const unsigned long long key = keys[i];
+        A.alive[i] = (int32_t)((key >> 12) & 0xFFFFFull);
+        A.pos[i] = (int32_t)(key & 0xFFFull);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        if (r < MAX_ROUNDS) A.tr_n_alive[r] = na;
+        A.stats[0] += (unsigned long long)na * A.stats[2];
+        A.stats[1] += (unsigned long long)na * (unsigned long long)A.B;
+        A.stats[2] = 0ull;
+        A.misc[1] = keep;
+        A.misc[3] = r + 1;
+    }
+    __syncthreads();
+}
+
+constexpr int CULL_THREADS = 1024;
+
+// one workgroup per attempt
+__global__ void __launch_bounds__(CULL_THREADS) k_b_cull(const Attempt *__restrict__ att, Stage S, int r)
+{
+    __shared__ unsigned long long keys[MAX_HYP];
+    FOR_UNITS(S, u) {
+        const Attempt &A = att[u];
+        if (round_active(A, r)) cull_round(A, r, keys);
+    }
+}
+
 // One unit: 64 live hypotheses (lanes) x `dpu` consecutive draws (a multiple
 // of GROUP). The draws of a group are spread over the workgroup's wavefronts;
-// each wavefront draws its pixel (Philox counter (round, draw)), stages the
-// pixel's modes in (tree, mode) order in its own LDS slice, and scores them
-// against its lanes' hypotheses. The group's energies are then summed per
-// lane in draw order and stored; the cull adds the group sums in group
-// order. The units of hypothesis block 0 also publish each draw (camera point
-// and pixel, for refinement) and count its modes.
+// each wavefront takes its draw (pixel and leaves, staged for every round by
+// the hypothesis kernel), stages the draw's modes in (tree, mode) order in
+// its own LDS slice, and scores them against its lanes' hypotheses. The
+// group's energies are then summed per lane in draw order and stored; the
+// cull adds the group sums in group order. The units of hypothesis block 0
+// also count each draw's modes.
 __global__ void __launch_bounds__(64 * GROUP) k_b_score(const Attempt *__restrict__ att, Stage S, int r, int dpu,
                                                         int tm)
 {
     extern __shared__ __align__(16) float smode[];
-    __shared__ int32_t s_ex[GROUP][16], s_leaf[GROUP][16];
+    __shared__ int32_t s_ex[GROUP][16], s_base[GROUP][16];
     __shared__ float s_e[GROUP][64];
     const int lane = __lane_id(), wv = (int)(threadIdx.x >> 6), nw = (int)(blockDim.x >> 6);
     float *sm = smode + (size_t)wv * tm * SMODE;
     FOR_UNITS(S, u) {
         const int a = attempt_of(S, u);
         const Attempt &A = att[a];
-        if (!round_active(A, r)) continue;
-        const int na = A.misc[1];
-        const int np = A.misc[0];
-        const int nch = (A.B + dpu - 1) / dpu;
         const int local = u - S.off[a];
+        const int na = A.misc[1];
+        const int nch = (A.B + dpu - 1) / dpu;
         const int a0 = (local / nch) * 64;
         const int ch = local % nch;
-        if (a0 >= na) continue;
-        const int ap = a0 + lane;
-        const bool act = ap < na;
-        const bool publish = a0 == 0;
-        const int h = A.alive[act ? ap : a0];
-        const Hyp &hy = A.hyp[h];
-        const float R0 = hy.R32[0], R1 = hy.R32[1], R2 = hy.R32[2], R3 = hy.R32[3], R4 = hy.R32[4],
-                    R5 = hy.R32[5], R6 = hy.R32[6], R7 = hy.R32[7], R8 = hy.R32[8];
-        const float t0 = hy.t32[0], t1 = hy.t32[1], t2 = hy.t32[2];
-        const int i1 = min((ch + 1) * dpu, A.B);
-        for (int g0 = ch * dpu; g0 < i1; g0 += GROUP) {
-            for (int k = 0; k < GROUP / nw; ++k) {
-                const int slot = k * nw + wv;
-                const int i = g0 + slot;
-                const bool has = i < i1;
-                float4 dr = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-                int p = 0;
-                if (has) {
-                    const U4 x = philox((uint64_t)r, (uint64_t)i, 0, 0, A.seed, TAG_PIX);
-                    p = A.pool[uniform_int(x.x[0], (uint64_t)np)];
-                    float c[3];
-                    cam_point(A.fr, p % A.fr.W, p / A.fr.W, A.fr.depth[p], c);
-                    dr = make_float4(c[0], c[1], c[2], __int_as_float(p));
-                }
-                int leaf = 0, nm = 0;
-                if (has && lane < A.T) {
-                    leaf = A.leaves[(int64_t)lane * A.P + p];
-                    nm = A.nmodes[lane * A.L + leaf];
-                }
-                int incl = nm;
-                for (int o = 1; o < 16; o <<= 1) {
-                    int y = __shfl_up(incl, o, 64);
-                    if (lane >= o) incl += y;
-                }
-                const int cnt = __shfl(incl, A.T - 1, 64);
-                if (lane < A.T) {
-                    s_ex[wv][lane] = incl - nm;
-                    s_leaf[wv][lane] = leaf;
-                }
-                if (publish && has && lane == 0) {
-                    A.draws[i] = dr;
-                    if (cnt) atomicAdd(&A.stats[2], (unsigned long long)cnt);
-                }
-                __syncthreads();
-                for (int j = lane; j < cnt; j += 64) {
-                    // the mode's tree: the last tree whose first mode index is <= j
-                    int tj = 0;
-                    for (int t = 1; t < A.T; ++t)
-                        if (j >= s_ex[wv][t]) tj = t;
-                    const int m = j - s_ex[wv][tj];
-                    const Mode md = A.modes[((int64_t)tj * A.L + s_leaf[wv][tj]) * A.M + m];
-                    float *dst = sm + j * SMODE;
-                    dst[0] = md.mu[0]; dst[1] = md.mu[1]; dst[2] = md.mu[2];
-                    dst[3] = md.sinv[0]; dst[4] = md.sinv[1]; dst[5] = md.sinv[2];
-                    dst[6] = md.sinv[3]; dst[7] = md.sinv[4]; dst[8] = md.sinv[5];
-                    dst[9] = md.kappa;
-                    dst[10] = __int_as_float((tj * A.L + s_leaf[wv][tj]) * A.M + m);
-                    dst[11] = 0.0f;
-                }
-                __syncthreads();
-                const float y0 = fmaf(R0, dr.x, fmaf(R1, dr.y, fmaf(R2, dr.z, t0)));
-                const float y1 = fmaf(R3, dr.x, fmaf(R4, dr.y, fmaf(R5, dr.z, t1)));
-                const float y2 = fmaf(R6, dr.x, fmaf(R7, dr.y, fmaf(R8, dr.z, t2)));
-                float best = INFINITY;
-                int bj = -1;
-                for (int j = 0; j < cnt; ++j) {
-                    const float4 q0 = *(const float4 *)(sm + j * SMODE);
-                    const float4 q1 = *(const float4 *)(sm + j * SMODE + 4);
-                    const float2 q2 = *(const float2 *)(sm + j * SMODE + 8);
-                    const float d0 = y0 - q0.x, d1 = y1 - q0.y, d2 = y2 - q0.z;
-                    const float s0 = q0.w, s1 = q1.x, s2 = q1.y, s3 = q1.z, s4 = q1.w, s5 = q2.x;
-                    const float a0v = fmaf(s2, d2, fmaf(s1, d1, s0 * d0));
-                    const float a1v = fmaf(s4, d2, fmaf(s3, d1, s1 * d0));
-                    const float a2v = fmaf(s5, d2, fmaf(s4, d1, s2 * d0));
-                    const float q = fmaf(d2, a2v, fmaf(d1, a1v, d0 * a0v));
-                    const float term = fmaf(0.5f, q, q2.y);
-                    if (term < best) {
-                        best = term;
-                        bj = j;
-                    }
-                }
-                int32_t gid = -1;
-                if (bj >= 0) {
-                    const float *mb = sm + bj * SMODE;
-                    const float d0 = y0 - mb[0], d1 = y1 - mb[1], d2 = y2 - mb[2];
-                    if ((d0 * d0 + d1 * d1) + d2 * d2 <= A.inl2) gid = __float_as_int(mb[10]);
-                }
-                s_e[slot][lane] = best < 0.0f ? best : 0.0f;
-                if (act && has) A.inl[(int64_t)i * A.N + ap] = gid;
-                __syncthreads();
-            }
-            // the group's energy sum per lane, in draw order
-            if (wv == 0) {
-                float g = 0.0f;
-                for (int w = 0; w < GROUP && g0 + w < i1; ++w) g = g + s_e[w][lane];
-                if (act) A.gs[(int64_t)(g0 / GROUP) * A.N + ap] = g;
-            }
-            __syncthreads();
-        }
-    }
-}
-
-// One workgroup per attempt: energies in the defined order, bitonic sort of
-// keys (energy key << 32 | index << 12 | position), which orders by
-// (energy, index); keep the first ceil(n / 2), with each survivor's position
-// in this round's list (where its inliers were stored). Compare-exchange
-// distances of 64 and more go through LDS with a barrier; shorter ones run in
-// registers across the lanes of a wavefront.
-__device__ __forceinline__ unsigned long long cull_key(float E, int h, int ap)
-{
-    return ((unsigned long long)float_key(E) << 32) | ((unsigned long long)(uint32_t)h << 12) | (uint32_t)ap;
-}
-
-__global__ void __launch_bounds__(CULL_THREADS) k_b_cull(const Attempt *__restrict__ att, Stage S, int r)
-{
-    __shared__ unsigned long long keys[MAX_HYP];
-    const int lane = __lane_id(), wave = (int)(threadIdx.x >> 6);
-    FOR_UNITS(S, u) {
-        const Attempt &A = att[u];
-        if (!round_active(A, r)) continue;
-        const int na = A.misc[1];
-        int n2 = 64;
-        while (n2 < na) n2 <<= 1;
-        for (int ap = threadIdx.x; ap < n2; ap += CULL_THREADS) {
-            if (ap < na) {
-                const int h = A.alive[ap];
-                const int ng = (A.B + GROUP - 1) / GROUP;
-                const float *gs = A.gs + ap;
-                float Ssum = 0.0f;
-#pragma unroll 8
-                for (int k = 0; k < ng; ++k) Ssum = Ssum + gs[(int64_t)k * A.N];
-                const float E = A.energy[h] + Ssum;
-                A.energy[h] = E;
-                keys[ap] = cull_key(E, h, ap);
-                if (r < MAX_ROUNDS) {
-                    A.tr_alive[r * A.N + ap] = h;
-                    A.tr_energy[r * A.N + ap] = E;
-                }
-            } else {
-                keys[ap] = ~0ull;
-            }
-        }
-        __syncthreads();
-        for (int k = 2; k <= n2; k <<= 1) {
-            int j = k >> 1;
-            for (; j >= 64; j >>= 1) {
-                for (int i = threadIdx.x; i < n2; i += CULL_THREADS) {
-                    const int ixj = i ^ j;
-                    if (ixj > i) {
-                        const unsigned long long x = keys[i], y = keys[ixj];
-                        const bool asc = (i & k) == 0;
-                        if ((x > y) == asc) {
-                            keys[i] = y;
-                            keys[ixj] = x;
+        if (round_active(A, r) && a0 < na) {
+            const int ap = a0 + lane;
+            const bool act = ap < na;
+            const bool publish = a0 == 0;
+            const float *lp = A.lpose + (act ? ap : a0) * 12;
+            const float R0 = lp[0], R1 = lp[1], R2 = lp[2], R3 = lp[3], R4 = lp[4], R5 = lp[5], R6 = lp[6],
+                        R7 = lp[7], R8 = lp[8];
+            const float t0 = lp[9], t1 = lp[10], t2 = lp[11];
+            const int i1 = min((ch + 1) * dpu, A.B);
+            const int64_t rb = (int64_t)r * A.B;
+            for (int g0 = ch * dpu; g0 < i1; g0 += GROUP) {
+                for (int k = 0; k < GROUP / nw; ++k) {
+                    const int slot = k * nw + wv;
+                    const int i = g0 + slot;
+                    const bool has = i < i1;
+                    float4 dr = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+                    int base = 0, nm = 0;
+                    if (has) {
+                        dr = A.draws[rb + i];
+                        if (lane < A.T) {
+                            const int2 e = A.dtree[(rb + i) * A.T + lane];
+                            base = e.x;
+                            nm = e.y;
                         }
                     }
+                    int incl = nm;
+                    for (int o = 1; o < 16; o <<= 1) {
+                        int y = __shfl_up(incl, o, 64);
+                        if (lane >= o) incl += y;
+                    }
+                    const int cnt = __shfl(incl, A.T - 1, 64);
+                    if (lane < A.T) {
+                        s_ex[wv][lane] = incl - nm;
+                        s_base[wv][lane] = base;
+                    }
+                    if (publish && has && lane == 0 && cnt) atomicAdd(&A.stats[2], (unsigned long long)cnt);
+                    __syncthreads();
+                    for (int j = lane; j < cnt; j += 64) {
+                        // the mode's tree: the last tree whose first mode index is <= j
+                        int tj = 0;
+                        for (int t = 1; t < A.T; ++t)
+                            if (j >= s_ex[wv][t]) tj = t;
+                        const int gidx = s_base[wv][tj] + (j - s_ex[wv][tj]);
+                        const Mode md = A.modes[gidx];
+                        float *dst = sm + j * SMODE;
+                        dst[0] = md.mu[0]; dst[1] = md.mu[1]; dst[2] = md.mu[2];
+                        dst[3] = md.sinv[0]; dst[4] = md.sinv[1]; dst[5] = md.sinv[2];
+                        dst[6] = md.sinv[3]; dst[7] = md.sinv[4]; dst[8] = md.sinv[5];
+                        dst[9] = md.kappa;
+                        dst[10] = __int_as_float(gidx);
+                        dst[11] = 0.0f;
+                    }
+                    __syncthreads();
+                    const float y0 = fmaf(R0, dr.x, fmaf(R1, dr.y, fmaf(R2, dr.z, t0)));
+                    const float y1 = fmaf(R3, dr.x, fmaf(R4, dr.y, fmaf(R5, dr.z, t1)));
+                    const float y2 = fmaf(R6, dr.x, fmaf(R7, dr.y, fmaf(R8, dr.z, t2)));
+                    float best = INFINITY;
+                    int bj = -1;
+                    for (int j = 0; j < cnt; ++j) {
+                        const float4 q0 = *(const float4 *)(sm + j * SMODE);
+                        const float4 q1 = *(const float4 *)(sm + j * SMODE + 4);
+                        const float2 q2 = *(const float2 *)(sm + j * SMODE + 8);
+                        const float d0 = y0 - q0.x, d1 = y1 - q0.y, d2 = y2 - q0.z;
+                        const float s0 = q0.w, s1 = q1.x, s2 = q1.y, s3 = q1.z, s4 = q1.w, s5 = q2.x;
+                        const float a0v = fmaf(s2, d2, fmaf(s1, d1, s0 * d0));
+                        const float a1v = fmaf(s4, d2, fmaf(s3, d1, s1 * d0));
+                        const float a2v = fmaf(s5, d2, fmaf(s4, d1, s2 * d0));
+                        const float q = fmaf(d2, a2v, fmaf(d1, a1v, d0 * a0v));
+                        const float term = fmaf(0.5f, q, q2.y);
+                        if (term < best) {
+                            best = term;
+                            bj = j;
+                        }
+                    }
+                    int32_t gid = -1;
+                    if (bj >= 0) {
+                        const float *mb = sm + bj * SMODE;
+                        const float d0 = y0 - mb[0], d1 = y1 - mb[1], d2 = y2 - mb[2];
+                        if ((d0 * d0 + d1 * d1) + d2 * d2 <= A.inl2) gid = __float_as_int(mb[10]);
+                    }
+                    s_e[slot][lane] = best < 0.0f ? best : 0.0f;
+                    if (act && has) A.inl[(int64_t)i * A.N + ap] = gid;
+                    __syncthreads();
+                }
+                // the group's energy sum per lane, in draw order
+                if (wv == 0) {
+                    float g = 0.0f;
+                    for (int w = 0; w < GROUP && g0 + w < i1; ++w) g = g + s_e[w][lane];
+                    if (act) A.gs[(int64_t)(g0 / GROUP) * A.N + ap] = g;
                 }
                 __syncthreads();
             }
-            // j < 64: partners are lanes of the same wavefront (n2 is a
-            // multiple of 64, so every wavefront's block is whole)
-            for (int base = wave * 64; base < n2; base += CULL_THREADS) {
-                const int i = base + lane;
-                unsigned long long x = keys[i];
-                const bool asc = (i & k) == 0;
-                for (int jj = j; jj > 0; jj >>= 1) {
-                    const unsigned long long y = __shfl_xor(x, jj, 64);
-                    const bool lower = (lane & jj) == 0;
-                    const unsigned long long lo = x < y ? x : y, hi = x < y ? y : x;
-                    x = (lower == asc) ? lo : hi;
-                }
-                keys[i] = x;
-            }
-            __syncthreads();
         }
-        const int keep = (na + 1) / 2;
-        for (int i = threadIdx.x; i < keep; i += CULL_THREADS) {
-            const unsigned long long key = keys[i];
-            A.alive[i] = (int32_t)((key >> 12) & 0xFFFFFull);
-            A.pos[i] = (int32_t)(key & 0xFFFull);
-        }
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            if (r < MAX_ROUNDS) A.tr_n_alive[r] = na;
-            A.stats[0] += (unsigned long long)na * A.stats[2];
-            A.stats[1] += (unsigned long long)na * (unsigned long long)A.B;
-            A.stats[2] = 0ull;
-            A.misc[1] = keep;
-            A.misc[3] = r + 1;
-        }
-        __syncthreads();
     }
 }
 
@@ -785,13 +825,11 @@ __global__ void __launch_bounds__(CULL_THREADS) k_b_cull(const Attempt *__restri
 constexpr int RB = 8;              // draws per lane per load batch in refinement
 constexpr int FUSED_REFINE = 1024; // survivors up to which a round refines in one kernel
 
-// this round's inlier sums of survivor position sidx, added to its running
-// sums by lane 0; returns the hypothesis index
-__device__ __forceinline__ int refine_sums_of(const Attempt &A, int sidx, double s[NSUM])
+// this round's inlier sums of hypothesis h (scored at live position ap),
+// added to its running sums by lane 0
+__device__ __forceinline__ void refine_sums_at(const Attempt &A, int r, int h, int ap, double s[NSUM])
 {
     const int lane = __lane_id();
-    const int h = A.alive[sidx];
-    const int ap = A.pos[sidx];
 #pragma unroll
     for (int k = 0; k < NSUM; ++k) s[k] = 0.0;
     // lane-strided draws, RB per lane at a time: all inlier ids first, then the
@@ -807,7 +845,7 @@ __device__ __forceinline__ int refine_sums_of(const Attempt &A, int sidx, double
 #pragma unroll
         for (int k = 0; k < RB; ++k) {
             if (gid[k] >= 0) {
-                const float4 dr = A.draws[base + k * 64 + lane];
+                const float4 dr = A.draws[(int64_t)r * A.B + base + k * 64 + lane];
                 const Mode &md = A.modes[gid[k]];
                 c[k][0] = dr.x; c[k][1] = dr.y; c[k][2] = dr.z;
                 w[k][0] = md.mu[0]; w[k][1] = md.mu[1]; w[k][2] = md.mu[2];
@@ -829,23 +867,37 @@ __device__ __forceinline__ int refine_sums_of(const Attempt &A, int sidx, double
             run[k] = s[k];
         }
     }
+}
+
+// the same for survivor position sidx; returns the hypothesis index
+__device__ __forceinline__ int refine_sums_of(const Attempt &A, int r, int sidx, double s[NSUM])
+{
+    const int h = A.alive[sidx];
+    refine_sums_at(A, r, h, A.pos[sidx], s);
     return h;
 }
 
-// re-solves hypothesis h from its running sums s (refinement on)
-__device__ __forceinline__ void refine_solve_of(const Attempt &A, int h, const double s[NSUM])
+// re-solves hypothesis h, survivor sidx, from its running sums s when
+// refinement is on, and stores its FP32 pose at its live position
+__device__ __forceinline__ void refine_solve_of(const Attempt &A, int sidx, int h, const double s[NSUM])
 {
     double R[9], t[3];
-    if (pose_from_sums(s, R, t)) {
-        Hyp &hy = A.hyp[h];
+    float *lp = A.lpose + sidx * 12;
+    Hyp &hy = A.hyp[h];
+    if (A.refine && pose_from_sums(s, R, t)) {
         for (int k = 0; k < 9; ++k) {
             hy.R[k] = R[k];
             hy.R32[k] = (float)R[k];
+            lp[k] = (float)R[k];
         }
         for (int k = 0; k < 3; ++k) {
             hy.t[k] = t[k];
             hy.t32[k] = (float)t[k];
+            lp[9 + k] = (float)t[k];
         }
+    } else {
+        for (int k = 0; k < 9; ++k) lp[k] = hy.R32[k];
+        for (int k = 0; k < 3; ++k) lp[9 + k] = hy.t32[k];
     }
 }
 
@@ -859,8 +911,8 @@ __global__ void __launch_bounds__(64) k_b_refine(const Attempt *__restrict__ att
         const int sidx = u - S.off[a];
         if (sidx >= A.misc[1]) continue;
         double s[NSUM];
-        const int h = refine_sums_of(A, sidx, s);
-        if (__lane_id() == 0 && A.refine) refine_solve_of(A, h, s);
+        const int h = refine_sums_of(A, r, sidx, s);
+        if (__lane_id() == 0) refine_solve_of(A, sidx, h, s);
     }
 }
 
@@ -874,7 +926,7 @@ __global__ void __launch_bounds__(64) k_b_refine_sums(const Attempt *__restrict_
         const int sidx = u - S.off[a];
         if (sidx >= A.misc[1]) continue;
         double s[NSUM];
-        refine_sums_of(A, sidx, s);
+        refine_sums_of(A, r, sidx, s);
     }
 }
 
@@ -884,7 +936,7 @@ __global__ void __launch_bounds__(64) k_b_refine_solve(const Attempt *__restrict
     FOR_UNITS(S, u) {
         const int a = attempt_of(S, u);
         const Attempt &A = att[a];
-        if (A.misc[3] != r + 1 || !A.refine) continue;
+        if (A.misc[3] != r + 1) continue;
         const int sidx = (u - S.off[a]) * 64 + __lane_id();
         if (sidx >= A.misc[1]) continue;
         const int h = A.alive[sidx];
@@ -892,7 +944,7 @@ __global__ void __launch_bounds__(64) k_b_refine_solve(const Attempt *__restrict
         const double *run = A.sums + (int64_t)h * NSUM;
 #pragma unroll
         for (int k = 0; k < NSUM; ++k) s[k] = run[k];
-        refine_solve_of(A, h, s);
+        refine_solve_of(A, sidx, h, s);
     }
 }
 
@@ -1012,7 +1064,10 @@ static size_t carve(const Shape &s, char *base, Attempt &A)
     A.sums = (double *)take((size_t)s.N * NSUM * 8);
     A.alive = (int32_t *)take((size_t)s.N * 4);
     A.pos = (int32_t *)take((size_t)s.N * 4);
-    A.draws = (float4 *)take((size_t)s.B * 16);
+    A.lpose = (float *)take((size_t)s.N * 12 * 4);
+    const int rounds = rounds_for(s.N);
+    A.draws = (float4 *)take((size_t)rounds * s.B * 16);
+    A.dtree = (int2 *)take((size_t)rounds * s.B * s.T * 8);
     A.gs = (float *)take((size_t)((s.B + GROUP - 1) / GROUP) * s.N * 4);
     A.inl = (int32_t *)take((size_t)s.B * s.N * 4);
     A.stats = (unsigned long long *)take(3 * 8);
@@ -1058,7 +1113,7 @@ static std::vector<int32_t> offsets(const Plan *pl, const Sched &sc)
     fill(0, [&](int a) { return pl->shape[a].T * (int)((P(a) + PIX_BLOCK - 1) / PIX_BLOCK); });
     fill(1, [&](int a) { return (int)((P(a) + POOL_BLOCK - 1) / POOL_BLOCK); });
     fill(2, [&](int) { return 1; });
-    fill(3, [&](int a) { return pl->shape[a].N; });
+    fill(3, [&](int a) { return pl->shape[a].N + (rounds_for(pl->shape[a].N) * pl->shape[a].B + 63) / 64; });
     fill(4, [&](int a) { return pl->shape[a].weights == 2 ? (int)((P(a) + ROWS - 1) / ROWS) : 0; });
     auto bound = [&](int a, int rr) {
         int bnd = pl->shape[a].N;
