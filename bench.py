@@ -9,20 +9,26 @@ before the timed region. A step relocalises the 50 held-out query frames
 (one plain call each); `value` is relocalisations per second over the timed
 steps.
 
-Also reported (same JSON line, `forms`): the learned proposal on the
-full-size forest (a network trained on the GPU from verified relocalisations
-of extra frames; learned picks at 256 and 64 hypotheses against uniform picks
-at 256, 64 and 1024), and the batched form on the mixed workload (64 attempts
-against 8 small-room forests, frame sizes drawn from 320x240 / 480x360 /
-640x480 and hypothesis counts from 256 / 512 / 1024) as one batched call
-versus 64 sequential plain calls, then batched + learned at 256 hypotheses.
+Also reported (same JSON line, `forms`): the same 50 queries as one batched
+call (bit-identical results); the learned proposal on the full-size forest (a
+network trained on the GPU from verified relocalisations of extra frames;
+learned picks at 256, 64 and 16 hypotheses against uniform picks at 256, 64,
+16 and 1024); and the batched form on the mixed workload (64 attempts against
+8 small-room forests, frame sizes drawn from 320x240 / 480x360 / 640x480 and
+hypothesis counts from 256 / 512 / 1024) as one batched call versus 64
+sequential plain calls, then batched + learned and batched uniform at 256
+hypotheses.
 
-Per-kernel times come from a separate profiled pass over the same steps
-(HIP events around each launch on its stream; kernels are then launched one
-by one instead of as a graph). The roofline line is for the scoring kernel:
+Per-kernel times come from a separate profiled pass over the same work (HIP
+events around each launch on its stream; kernels are then launched one by one
+instead of as a graph). The headline `roofline` is for the scoring kernel:
 its algorithmic FLOPs (25 per (hypothesis, draw, mode) energy term, 18 per
 (hypothesis, draw) transform, counted by the kernels themselves) over its
-average duration.
+average duration, with `traffic` (HBM bytes per launch) taken from the
+committed counter profile while the kernel's sources are unchanged. Every
+form also carries `rooflines`: the scoring kernel, the traversal (HBM, by
+algorithmic bytes) and, for learned forms, the pick-weight kernel (BF16
+matrix FLOPs), plus the kernel with the largest total time.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-batched] [--no-learned] [--queue]
 """
@@ -109,6 +115,33 @@ def cpu_baseline(sc, budget_s: float = 25.0):
 HBM_PEAK_GBS = 8000.0              # MI355X HBM3E (published)
 BF16_PEAK_TFLOPS = 2500.0          # MI355X dense BF16 matrix (published)
 MLP_FLOP_PER_PIXEL = 2 * (24 * 64 + 64 * 64 + 64)   # one forward pass of the 24-64-64-1 network
+
+
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "relocalise_fullsize_hbm_traffic.md")
+SCORE_SOURCES = ("common.h", "mlp_dev.h", "relocalise.hip")
+
+
+def score_traffic():
+    """HBM bytes per launch of the scoring kernel on the full-size workload,
+    from the committed counter profile (FETCH_SIZE and WRITE_SIZE, each scaled
+    by what the counter reads for a kernel of known traffic); None when the
+    kernel's sources differ from those profiled (sha256 recorded there)."""
+    import hashlib
+    import re
+    try:
+        with open(TRAFFIC_PROFILE) as f:
+            text = f.read()
+    except OSError:
+        return None
+    m_bytes = re.search(r"k_b_score traffic bytes per launch: (\d+)", text)
+    m_hash = re.search(r"sources sha256: ([0-9a-f]{64})", text)
+    if not (m_bytes and m_hash):
+        return None
+    h = hashlib.sha256()
+    for name in SCORE_SOURCES:
+        with open(os.path.join(ROOT, "paper_1801_08361_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return int(m_bytes.group(1)) if h.hexdigest() == m_hash.group(1) else None
 
 
 def profiled(run):
@@ -206,6 +239,9 @@ def plain_full(args, dev, batched: bool = True):
     P = queries[0][0].numel()
     roofs = rooflines(kernels, res, [(P, g.T, False)] * len(queries))
     roof = roofs.get("k_b_score")
+    if roof is not None:
+        roof["traffic"] = score_traffic()
+        roof["traffic_source"] = "profiles/relocalise_fullsize_hbm_traffic.md (HBM bytes per launch)"
     if not batched:
         return dict(sc=sc, value=tot / wall, wall=wall, success=ok / max(tot, 1), n=tot, kernels=kernels, roof=roof,
                     rooflines=roofs, adapt_fps=len(adapt) / t_adapt, modes_s=t_modes, mem=g.memory(), forest=g,
