@@ -370,6 +370,11 @@ int reloc_debug_div(const int32_t *n_host, const int32_t *den_host, int32_t coun
  * bt_host [16][32] row-major B^T, c_host [16][16] row-major C. Synchronous. */
 int reloc_debug_mfma_probe(const uint16_t *a_host, const uint16_t *bt_host, float *c_host);
 
+/* The float -> bfloat16 conversion of the network's inference kernels (the
+ * inputs and the two hidden layers), run on the GPU: y_host[i] = bit pattern
+ * of x_host[i] rounded to bfloat16, for n host values. Synchronous. */
+int reloc_debug_bf16(const float *x_host, int32_t n, uint16_t *y_host);
+
 #ifdef __cplusplus
 }
 #endif

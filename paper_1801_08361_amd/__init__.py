@@ -137,6 +137,7 @@ _SIGS = {
     "reloc_debug_mfma_probe": [C.c_void_p, C.c_void_p, C.c_void_p],
     "reloc_debug_horn": [C.c_void_p, C.c_int32, C.c_void_p],
     "reloc_debug_div": [C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p],
+    "reloc_debug_bf16": [C.c_void_p, C.c_int32, C.c_void_p],
     "reloc_relocalise_learned": [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_uint64, C.c_int32,
                                  C.c_void_p, C.c_void_p],
 }
@@ -516,6 +517,16 @@ def mfma_probe(a: np.ndarray, bt: np.ndarray) -> np.ndarray:
     c = np.zeros((16, 16), dtype=np.float32)
     _check(lib().reloc_debug_mfma_probe(a.ctypes.data, bt.ctypes.data, c.ctypes.data), "reloc_debug_mfma_probe")
     return c
+
+
+def bf16_round(x: np.ndarray) -> np.ndarray:
+    """Bit patterns of x rounded to bfloat16 by the inference kernels'
+    conversion on the GPU (reloc_debug_bf16)."""
+    x = np.ascontiguousarray(x, dtype=np.float32).reshape(-1)
+    y = np.zeros(x.shape, dtype=np.uint16)
+    _check(lib().reloc_debug_bf16(x.ctypes.data if x.size else None, x.size, y.ctypes.data if x.size else None),
+           "reloc_debug_bf16")
+    return y
 
 
 class Mlp:

@@ -279,7 +279,7 @@ __global__ void __launch_bounds__(64) k_mlp_logits(const uint16_t *__restrict__ 
                                                    const uint16_t *__restrict__ q, const float *__restrict__ w,
                                                    float *__restrict__ z)
 {
-    __shared__ FwdTile S;
+    __shared__ InTile S;
     const int r0 = blockIdx.x * ROWS, l = __lane_id();
     uint4 *d = (uint4 *)(S.X + l * 32);
     if (r0 + l < n) {
@@ -289,8 +289,8 @@ __global__ void __launch_bounds__(64) k_mlp_logits(const uint16_t *__restrict__ 
         for (int k = 0; k < 4; ++k) d[k] = make_uint4(0, 0, 0, 0);
     }
     __syncthreads();
-    tile_forward<FwdTile, false>(S, q, w);
-    if (r0 + l < n) z[r0 + l] = S.z[l];
+    const float zl = tile_forward_regs(S.X, q, w);
+    if (r0 + l < n) z[r0 + l] = zl;
 }
 
 // ---------------------------------------------------------------------------
@@ -357,7 +357,7 @@ __global__ void __launch_bounds__(64) k_mlp_pixels(FeatArgs A, const uint16_t *_
                                                    const float *__restrict__ w, uint32_t *__restrict__ weights,
                                                    float *__restrict__ prob)
 {
-    __shared__ FwdTile S;
+    __shared__ InTile S;
     const int P = A.fr.W * A.fr.H;
     const int l = __lane_id();
     const int p = blockIdx.x * ROWS + l;
@@ -367,11 +367,11 @@ __global__ void __launch_bounds__(64) k_mlp_pixels(FeatArgs A, const uint16_t *_
         for (int k = 0; k < 24; ++k) x[k] = 0.0f;
     store_row(S, x);
     __syncthreads();
-    tile_forward<FwdTile, false>(S, q, w);
+    const float zl = tile_forward_regs(S.X, q, w);
     if (p < P) {
         const bool ok = valid_depth(A.fr, A.fr.depth[p]);
         float sg = 0.0f;
-        const uint32_t wt = pick_weight(S.z[l], &sg);
+        const uint32_t wt = pick_weight(zl, &sg);
         weights[p] = ok ? wt : 0u;
         if (prob) prob[p] = ok ? sg : 0.0f;
     }
@@ -417,6 +417,7 @@ static FeatArgs feat_args(const Forest *f, const Frame &fr)
     A.nmodes = f->nmodes;
     A.modes = f->modes;
     A.leaf_in = f->leaf_in;
+    A.packed = nullptr;
     A.T = f->T; A.L = f->L; A.M = f->M; A.R = f->R;
     return A;
 }
@@ -681,6 +682,42 @@ extern "C" int reloc_verify(const uint16_t *da_dev, const uint16_t *db_dev, int3
     *mu_m = h[1] ? ((double)h[2] / (double)h[1]) / 1000.0 : INFINITY;
     *accept = (*valid_frac > 0.5 && *mu_m < 0.05) ? 1 : 0;
     return RELOC_OK;
+}
+
+__global__ void k_bf16_probe(const float *__restrict__ x, int n, uint16_t *__restrict__ y)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (2 * i + 1 < n) {
+        const uint32_t p = bf16_pair(x[2 * i], x[2 * i + 1]);
+        y[2 * i] = (uint16_t)(p & 0xFFFFu);
+        y[2 * i + 1] = (uint16_t)(p >> 16);
+    } else if (2 * i < n) {
+        y[2 * i] = (uint16_t)(bf16_pair(x[2 * i], 0.0f) & 0xFFFFu);
+    }
+}
+
+extern "C" int reloc_debug_bf16(const float *x_host, int32_t n, uint16_t *y_host)
+{
+    if (n < 0 || (n > 0 && (!x_host || !y_host))) return RELOC_E_ARG;
+    if (n == 0) return RELOC_OK;
+    float *x = nullptr;
+    uint16_t *y = nullptr;
+    if (hipMalloc((void **)&x, (size_t)n * 4) != hipSuccess) return RELOC_E_NOMEM;
+    if (hipMalloc((void **)&y, (size_t)n * 2) != hipSuccess) {
+        (void)hipFree(x);
+        return RELOC_E_NOMEM;
+    }
+    int rc = RELOC_OK;
+    if (hipMemcpy(x, x_host, (size_t)n * 4, hipMemcpyHostToDevice) != hipSuccess) rc = RELOC_E_HIP;
+    if (!rc) {
+        const int pairs = (n + 1) / 2;
+        hipLaunchKernelGGL(k_bf16_probe, dim3((pairs + 255) / 256), dim3(256), 0, 0, x, n, y);
+        if (hipDeviceSynchronize() != hipSuccess || hipMemcpy(y_host, y, (size_t)n * 2, hipMemcpyDeviceToHost) != hipSuccess)
+            rc = RELOC_E_HIP;
+    }
+    (void)hipFree(x);
+    (void)hipFree(y);
+    return rc;
 }
 
 extern "C" int reloc_debug_mfma_probe(const uint16_t *a_host, const uint16_t *bt_host, float *c_host)

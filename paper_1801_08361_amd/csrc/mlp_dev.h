@@ -32,6 +32,15 @@ __device__ __forceinline__ uint16_t f2bf(float x)
 
 __device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
 
+// two floats to a bfloat16 pair (lo in bits 0-15) by the conversion
+// instruction, which rounds to nearest even like f2bf
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ uint32_t bf16_pair(float lo, float hi)
+{
+    const bf16x2 v = {(__bf16)lo, (__bf16)hi};
+    return __builtin_bit_cast(uint32_t, v);
+}
+
 __device__ __forceinline__ bf16x8 load8(const uint16_t *p)
 {
     const uint4 v = *(const uint4 *)p;
@@ -54,12 +63,10 @@ __device__ __forceinline__ floatx4 mfma_tile(const uint16_t *A, int lda, const u
     return acc;
 }
 
-// LDS of a forward-only tile
-struct __align__(16) FwdTile {
+// LDS of an inference tile: the rows' inputs (the activations stay in
+// registers, tile_forward_regs)
+struct __align__(16) InTile {
     uint16_t X[ROWS * 32];
-    uint16_t H1[ROWS * 64];
-    uint16_t H2[ROWS * 64];
-    float z[ROWS];
 };
 
 // Forward pass of the 64 rows in S.X (bfloat16, 24 inputs + 8 zeros): H1, H2
@@ -108,6 +115,90 @@ __device__ void tile_forward(Tile &S, const uint16_t *__restrict__ q, const floa
     __syncthreads();
 }
 
+// Forward pass of a 64-row tile for inference, with the activations kept in
+// registers. Row i's 32 inputs (bfloat16: 24 and 8 zeros) are X[32 i ..]
+// (LDS); returns the logit of row `lane`. The layers are computed transposed
+// (hidden units x rows), 16 rows at a time: layer 1 leaves lane l holding row
+// (l & 15) and hidden units 16 tj + 4 (l >> 4) + i (tj, i < 4), which are the
+// 8 + 8 k-values that layer 2's B operand needs from that lane for its two
+// 32-wide k-chunks, once W2's columns are taken in the same order: k-slot s of
+// lane group g in chunk c stands for hidden unit 32 c + 16 (s >> 2) + 4 g +
+// (s & 3) in both operands (an MFMA sums the same products whatever the slot
+// order). H1 and H2 are rounded to bfloat16 (nearest even, by the conversion
+// instruction) after bias and ReLU as in tile_forward; the output dot w3 . h2
+// is summed per lane over its 16 hidden units, then over the four lane groups.
+__device__ __forceinline__ float tile_forward_regs(const uint16_t *X, const uint16_t *__restrict__ q,
+                                                   const float *__restrict__ w)
+{
+    const int l = __lane_id(), col = l & 15, g = l >> 4;
+    bf16x8 a1[4], a2[4][2];
+#pragma unroll
+    for (int tj = 0; tj < 4; ++tj) a1[tj] = load8(q + QW1 + (16 * tj + col) * 32 + 8 * g);
+#pragma unroll
+    for (int tk = 0; tk < 4; ++tk)
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+            const uint16_t *row = q + QW2 + (16 * tk + col) * 64 + 32 * c + 4 * g;
+            const uint2 lo = *(const uint2 *)row;          // hidden 32 c + 4 g .. + 3
+            const uint2 hi = *(const uint2 *)(row + 16);   // hidden 32 c + 16 + 4 g .. + 3
+            a2[tk][c] = __builtin_bit_cast(bf16x8, make_uint4(lo.x, lo.y, hi.x, hi.y));
+        }
+    // this lane's biases and output weights (hidden units 16 t + 4 g + i)
+    float b1[16], b2[16], w3[16];
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int hid = 16 * t + 4 * g + i;
+            b1[4 * t + i] = w[OB1 + hid];
+            b2[4 * t + i] = w[OB2 + hid];
+            w3[4 * t + i] = bf2f(q[QW3 + hid]);
+        }
+    float zrow = 0.0f;
+#pragma unroll 1
+    for (int ti = 0; ti < 4; ++ti) {
+        const bf16x8 xb = load8(X + (16 * ti + col) * 32 + 8 * g);
+        uint32_t h1[8];   // bfloat16 pairs: h1 unit 16 tj + 4 g + i at half 4 tj + i
+#pragma unroll
+        for (int tj = 0; tj < 4; ++tj) {
+            floatx4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
+            acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1[tj], xb, acc, 0, 0, 0);
+            float hv[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                hv[i] = acc[i] + b1[4 * tj + i];
+                hv[i] = hv[i] > 0.0f ? hv[i] : 0.0f;
+            }
+            h1[2 * tj] = bf16_pair(hv[0], hv[1]);
+            h1[2 * tj + 1] = bf16_pair(hv[2], hv[3]);
+        }
+        const bf16x8 b2lo = __builtin_bit_cast(bf16x8, make_uint4(h1[0], h1[1], h1[2], h1[3]));
+        const bf16x8 b2hi = __builtin_bit_cast(bf16x8, make_uint4(h1[4], h1[5], h1[6], h1[7]));
+        float z = 0.0f;
+#pragma unroll
+        for (int tk = 0; tk < 4; ++tk) {
+            floatx4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
+            acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a2[tk][0], b2lo, acc, 0, 0, 0);
+            acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a2[tk][1], b2hi, acc, 0, 0, 0);
+            float hv[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                hv[i] = acc[i] + b2[4 * tk + i];
+                hv[i] = hv[i] > 0.0f ? hv[i] : 0.0f;
+            }
+            const uint32_t p01 = bf16_pair(hv[0], hv[1]), p23 = bf16_pair(hv[2], hv[3]);
+            const float h2[4] = {__uint_as_float(p01 << 16), __uint_as_float(p01 & 0xFFFF0000u),
+                                 __uint_as_float(p23 << 16), __uint_as_float(p23 & 0xFFFF0000u)};
+#pragma unroll
+            for (int i = 0; i < 4; ++i) z = fmaf(w3[4 * tk + i], h2[i], z);
+        }
+        z = z + __shfl_xor(z, 16, 64);
+        z = z + __shfl_xor(z, 32, 64);
+        if (ti == g) zrow = z;   // lane 16 g + col is row 16 ti + col
+    }
+    return zrow + w[OB3];
+}
+
 // what the per-pixel inputs need from a forest and a frame
 struct FeatArgs {
     Frame fr;
@@ -115,6 +206,7 @@ struct FeatArgs {
     const int32_t *nmodes;
     const Mode *modes;
     const float4 *leaf_in;       // [T][L][4] per-leaf summaries written with the modes
+    const uint64_t *packed;      // the frame packed for probes, or null (probes read the frame)
     int T, L, M, R;
 };
 
@@ -135,9 +227,15 @@ __device__ __forceinline__ void pixel_inputs(const FeatArgs &A, int u, int v, ui
     x[0] = (float)d / 5000.0f;
     const PixelDen pd = pixel_den(A.fr, (int32_t)d);
     const uint64_t *extra = A.nodes + (int64_t)A.T * (A.L - 1);
+    const uint64_t own = A.packed ? A.packed[v * A.fr.W + u] : 0ull;
     for (int j = 0; j < 8; ++j) {
-        int32_t thr;
-        int32_t r = node_response_d(A.fr, extra[j], u, v, (int32_t)d, pd, thr);
+        int32_t r;
+        if (A.packed) {
+            r = probe_response(A.packed, A.fr.W, A.fr.H, u, v, own, pd, probe_node(extra[j], A.fr));
+        } else {
+            int32_t thr;
+            r = node_response_d(A.fr, extra[j], u, v, (int32_t)d, pd, thr);
+        }
         if ((extra[j] & 3u) == 0) {
             r = r > 5000 ? 5000 : (r < -5000 ? -5000 : r);
             x[1 + j] = (float)r / 1000.0f;
@@ -152,12 +250,15 @@ __device__ __forceinline__ void pixel_inputs(const FeatArgs &A, int u, int v, ui
     bool h0 = false, h1 = false, h2 = false;
     int64_t fill = 0;
     for (int t = 0; t < A.T; ++t) {
+        // the whole summary at once (the mode count selects what is used)
         const float4 *S = A.leaf_in + ((int64_t)t * A.L + leaf_of(t)) * 4;
-        const float4 head = S[0];
+        const float4 head = S[0], m3[3] = {S[1], S[2], S[3]};
         fill += (int64_t)__float_as_uint(head.x);
         const int n3 = __float_as_int(head.y);
-        for (int m = 0; m < n3; ++m) {
-            const float4 c = S[1 + m];
+#pragma unroll
+        for (int m = 0; m < 3; ++m) {
+            if (m >= n3) break;
+            const float4 c = m3[m];
             if (c.x > b0.x) {
                 b2 = b1; h2 = h1; b1 = b0; h1 = h0; b0 = c; h0 = true;
             } else if (c.x > b1.x) {
@@ -191,10 +292,15 @@ __device__ __forceinline__ void pixel_features(const FeatArgs &A, int p, float x
 }
 
 // lane l's inputs as row l of the tile (bfloat16, 8 zeros of padding)
-__device__ __forceinline__ void store_row(FwdTile &S, const float x[24])
+__device__ __forceinline__ void store_row(InTile &S, const float x[24])
 {
     const int l = __lane_id();
-    for (int k = 0; k < 32; ++k) S.X[l * 32 + k] = k < 24 ? f2bf(x[k]) : (uint16_t)0;
+    uint4 *row = (uint4 *)(S.X + l * 32);
+#pragma unroll
+    for (int k = 0; k < 3; ++k)
+        row[k] = make_uint4(bf16_pair(x[8 * k], x[8 * k + 1]), bf16_pair(x[8 * k + 2], x[8 * k + 3]),
+                            bf16_pair(x[8 * k + 4], x[8 * k + 5]), bf16_pair(x[8 * k + 6], x[8 * k + 7]));
+    row[3] = make_uint4(0u, 0u, 0u, 0u);
 }
 
 // pick weight of a valid pixel from its logit: floor(sigmoid(z) 65536) + 1

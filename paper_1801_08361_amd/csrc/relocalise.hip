@@ -102,7 +102,7 @@ __global__ void __launch_bounds__(PIX_BLOCK) k_b_leaves(const Attempt *__restric
 // stand-alone weight kernel computes them after its own traversal.
 __global__ void __launch_bounds__(64) k_b_weights(const Attempt *__restrict__ att, Stage S)
 {
-    __shared__ FwdTile T;
+    __shared__ InTile T;
     const int l = __lane_id();
     FOR_UNITS(S, u) {
         const int a = attempt_of(S, u);
@@ -114,6 +114,7 @@ __global__ void __launch_bounds__(64) k_b_weights(const Attempt *__restrict__ at
         F.nmodes = A.nmodes;
         F.modes = A.modes;
         F.leaf_in = A.leaf_in;
+        F.packed = A.packed;
         F.T = A.T; F.L = A.L; F.M = A.M; F.R = A.R;
         float x[24];
         for (int k = 0; k < 24; ++k) x[k] = 0.0f;
@@ -128,8 +129,8 @@ __global__ void __launch_bounds__(64) k_b_weights(const Attempt *__restrict__ at
         __syncthreads();   // the previous unit's tile is no longer read
         store_row(T, x);
         __syncthreads();
-        tile_forward<FwdTile, false>(T, A.mq, A.mw);
-        const uint32_t w = (p < A.P && ok) ? pick_weight(T.z[l], nullptr) : 0u;
+        const float zl = tile_forward_regs(T.X, A.mq, A.mw);
+        const uint32_t w = (p < A.P && ok) ? pick_weight(zl, nullptr) : 0u;
         if (p < A.P) A.wbuf[p] = w;
         // the tile's weight sum into its pixel block's (zeroed by k_b_pack;
         // integer sums, so the order of the additions does not matter)

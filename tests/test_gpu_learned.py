@@ -48,6 +48,30 @@ def test_mfma_lane_layout():
         assert np.all(np.abs(c - ref) <= 1e-6 * bound + 1e-30), trial
 
 
+def test_bf16_conversion_rounds_to_nearest_even():
+    """The conversion instruction used for the network's inputs and hidden
+    layers against round-to-nearest-even on the float's bit pattern: ties
+    either way, values next to ties, denormals, overflow to infinity."""
+    need_gpu()
+    import paper_1801_08361_amd as rl
+    rng = np.random.default_rng(11)
+    hi = rng.integers(0, 1 << 16, 20000, dtype=np.uint64)
+    lows = np.array([0x0000, 0x0001, 0x7FFF, 0x8000, 0x8001, 0xFFFF], dtype=np.uint64)
+    bits = ((hi[:, None] << 16) | lows[None, :]).reshape(-1)
+    bits = np.concatenate([bits, rng.integers(0, 1 << 32, 50000, dtype=np.uint64),
+                           np.array([0x00000001, 0x00008000, 0x007FFFFF, 0x80008000, 0x7F7FFFFF, 0x7F7F8000,
+                                     0x7F800000, 0xFF800000, 0x00000000, 0x80000000], dtype=np.uint64)])
+    x = bits.astype(np.uint32).view(np.float32)
+    finite = np.isfinite(x) | np.isinf(x)
+    x = x[finite]
+    b = x.view(np.uint32).astype(np.uint64)
+    want = ((b + 0x7FFF + ((b >> 16) & 1)) >> 16).astype(np.uint16)
+    want[np.isinf(x)] = (b[np.isinf(x)] >> 16).astype(np.uint16)
+    got = rl.bf16_round(x)
+    bad = np.flatnonzero(got != want)
+    assert bad.size == 0, [(hex(int(b[i])), hex(int(got[i])), hex(int(want[i]))) for i in bad[:5]]
+
+
 def test_verify_matches_oracle():
     dev = need_gpu()
     import torch
