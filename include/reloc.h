@@ -80,7 +80,7 @@ typedef struct {
     int32_t batch_pixels;     /* B pixels scored per cull round, 1..2048 */
     int32_t max_tries;        /* tries per hypothesis, 1..1024 */
     int32_t refine;           /* 1: Kabsch refinement of the survivors on their inliers */
-    int32_t rgb_tol;          /* hypothesis modes must match the pixel colour within this, per channel */
+    int32_t rgb_tol;          /* hypothesis modes must match the pixel colour within this, per channel (>= 0) */
     float rigid_ratio2;       /* squared-distance ratio bound between camera and world triangles */
     float min_pair2_m2;       /* minimum squared distance between hypothesis camera points */
     float min_area2_m4;       /* minimum |e1 x e2|^2 of the hypothesis camera triangle */

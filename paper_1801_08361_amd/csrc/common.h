@@ -319,8 +319,8 @@ __device__ __forceinline__ int32_t probe_response(const uint64_t *__restrict__ p
     const int32_t ox = (int32_t)div_mag2(n.ax, pd), oy = (int32_t)div_mag2(n.ay, pd);
     const int32_t qx = u + ((n.meta & 4u) ? -ox : ox);
     const int32_t qy = v + ((n.meta & 8u) ? -oy : oy);
-    const int32_t cx = qx < 0 ? 0 : (qx > W - 1 ? W - 1 : qx);
-    const int32_t cy = qy < 0 ? 0 : (qy > H - 1 ? H - 1 : qy);
+    const int32_t cx = max(0, min(qx, W - 1));
+    const int32_t cy = max(0, min(qy, H - 1));
     // a global-memory load at a 32-bit word offset from the frame's base
     const uint64_t w = ((const __attribute__((address_space(1))) uint64_t *)packed)[(uint32_t)(cy * W + cx)];
     const uint32_t sh = (n.meta >> 8) & 63u;

@@ -44,7 +44,7 @@ static int params_check(const reloc_params *p)
         return RELOC_E_ARG;
     if (p->n_hypotheses < 1 || p->n_hypotheses > MAX_HYP || p->batch_pixels < 1 || p->batch_pixels > MAX_B)
         return RELOC_E_ARG;
-    if (p->max_tries < 1 || p->max_tries > 1024 || p->depth_min_mm < 1 || p->depth_max_mm > 65534 ||
+    if (p->max_tries < 1 || p->max_tries > 1024 || p->rgb_tol < 0 || p->depth_min_mm < 1 || p->depth_max_mm > 65534 ||
         p->depth_min_mm > p->depth_max_mm || p->f_ref_px16 < 1)
         return RELOC_E_ARG;
     if (p->offset_pxmm < 0 || p->thr_depth_mm < 0 || p->thr_rgb < 0 || p->dens_radius_mm < 0 ||

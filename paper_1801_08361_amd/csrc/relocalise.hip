@@ -299,10 +299,36 @@ __device__ __forceinline__ float sq3(const float a[3], const float b[3])
     return (dx * dx + dy * dy) + dz * dz;
 }
 
-__device__ __forceinline__ bool rgb_close(uint32_t a, uint32_t r, uint32_t g, uint32_t b, int tol)
+// The colour test of a hypothesis pick, |a_c - p_c| <= tol in each channel,
+// as a window per channel: max(p_c - tol, 0) <= a_c <= min(p_c + tol, 255)
+// (equivalent for colours 0..255 and tol >= 0). Red and green are tested
+// together as two 16-bit lanes; blue is tested with the byte above it, which
+// is 0 for a mode's colour and 0xFF in an empty slot, so empty slots fail.
+typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));
+struct ColourWin {
+    u16x2 lo, hi;       // red, green
+    uint32_t blo, bhi;  // blue
+};
+
+__device__ __forceinline__ ColourWin colour_win(uint32_t r, uint32_t g, uint32_t b, int tol)
 {
-    int dr = (int)(a & 255u) - (int)r, dg = (int)((a >> 8) & 255u) - (int)g, db = (int)((a >> 16) & 255u) - (int)b;
-    return abs(dr) <= tol && abs(dg) <= tol && abs(db) <= tol;
+    auto lo = [&](uint32_t c) { return (unsigned short)((int)c - tol < 0 ? 0 : (int)c - tol); };
+    auto hi = [&](uint32_t c) { return (unsigned short)((int)c + tol > 255 ? 255 : (int)c + tol); };
+    ColourWin w;
+    w.lo = u16x2{lo(r), lo(g)};
+    w.hi = u16x2{hi(r), hi(g)};
+    w.blo = lo(b);
+    w.bhi = hi(b);
+    return w;
+}
+
+__device__ __forceinline__ bool colour_in(uint32_t a, const ColourWin &w)
+{
+    const uint32_t rg = (a & 0xFFu) | ((a << 8) & 0xFF0000u);
+    const u16x2 x = __builtin_bit_cast(u16x2, rg);
+    const u16x2 c = __builtin_elementwise_min(__builtin_elementwise_max(x, w.lo), w.hi);
+    const uint32_t bt = a >> 16;
+    return __builtin_bit_cast(uint32_t, c) == rg && min(max(bt, w.blo), w.bhi) == bt;
 }
 
 // pool index for draw u: uniform, or the first pool entry whose inclusive
@@ -324,8 +350,7 @@ __device__ __forceinline__ int pick_pool(const Attempt &A, int np, uint64_t u)
 // Colour-consistent modes of one leaf as a bit mask: bit m is set when slot m
 // holds a mode whose colour is within tol of (pr, pg, pb) in every channel.
 // The row is read with 16-byte loads (rgb_stride(M) colours).
-__device__ __forceinline__ uint32_t colour_mask(const uint32_t *__restrict__ row, int Mp, uint32_t pr, uint32_t pg,
-                                                uint32_t pb, int tol)
+__device__ __forceinline__ uint32_t colour_mask(const uint32_t *__restrict__ row, int Mp, const ColourWin &w)
 {
     uint32_t mask = 0;
     for (int q = 0; q < Mp; q += 4) {
@@ -333,15 +358,14 @@ __device__ __forceinline__ uint32_t colour_mask(const uint32_t *__restrict__ row
         const uint32_t c[4] = {v.x, v.y, v.z, v.w};
 #pragma unroll
         for (int e = 0; e < 4; ++e)
-            if (c[e] != RGB_NONE && rgb_close(c[e], pr, pg, pb, tol)) mask |= 1u << (q + e);
+            if (colour_in(c[e], w)) mask |= 1u << (q + e);
     }
     return mask;
 }
 
 // the same for rows of at most 12 colours, with the row's loads issued
 // before any test
-__device__ __forceinline__ uint32_t colour_mask12(const uint32_t *__restrict__ row, int Mp, uint32_t pr,
-                                                  uint32_t pg, uint32_t pb, int tol)
+__device__ __forceinline__ uint32_t colour_mask12(const uint32_t *__restrict__ row, int Mp, const ColourWin &w)
 {
     const uint4 none = make_uint4(RGB_NONE, RGB_NONE, RGB_NONE, RGB_NONE);
     const uint4 *r4 = (const uint4 *)row;
@@ -352,7 +376,7 @@ __device__ __forceinline__ uint32_t colour_mask12(const uint32_t *__restrict__ r
     uint32_t mask = 0;
 #pragma unroll
     for (int e = 0; e < 12; ++e)
-        if (c[e] != RGB_NONE && rgb_close(c[e], pr, pg, pb, tol)) mask |= 1u << e;
+        if (colour_in(c[e], w)) mask |= 1u << e;
     return mask;
 }
 
@@ -388,6 +412,7 @@ __device__ bool try_hypothesis(const Attempt &A, int np, uint64_t h, uint64_t ta
         // this lane's leaf and colour mask per tree, in LDS columns (stride 64)
 #pragma unroll 4
         for (int tt = 0; tt < A.T; ++tt) s_li[tt * 64] = tt * A.L + A.leaves[(int64_t)tt * A.P + p[j]];
+        const ColourWin win = colour_win(pr[j], pg[j], pb[j], A.rgb_tol);
         int cnt = 0;
         if (Mp <= 12) {
             // up to 12 modes per leaf: each row's three 16-byte loads are
@@ -395,14 +420,14 @@ __device__ bool try_hypothesis(const Attempt &A, int np, uint64_t h, uint64_t ta
 #pragma unroll 4
             for (int tt = 0; tt < A.T; ++tt) {
                 const uint32_t mk =
-                    colour_mask12(A.mode_rgb + (int64_t)s_li[tt * 64] * Mp, Mp, pr[j], pg[j], pb[j], A.rgb_tol);
+                    colour_mask12(A.mode_rgb + (int64_t)s_li[tt * 64] * Mp, Mp, win);
                 s_mask[tt * 64] = mk;
                 cnt += __popc(mk);
             }
         } else {
             for (int tt = 0; tt < A.T; ++tt) {
                 const uint32_t mk =
-                    colour_mask(A.mode_rgb + (int64_t)s_li[tt * 64] * Mp, Mp, pr[j], pg[j], pb[j], A.rgb_tol);
+                    colour_mask(A.mode_rgb + (int64_t)s_li[tt * 64] * Mp, Mp, win);
                 s_mask[tt * 64] = mk;
                 cnt += __popc(mk);
             }
