@@ -330,26 +330,47 @@ __device__ __forceinline__ int32_t probe_response(const uint64_t *__restrict__ p
     return (int32_t)val - (int32_t)((uint32_t)(own >> sh) & mask);
 }
 
-// traversal of one tree for a valid pixel (u, v) of a packed frame, with nodes
-// [0, ntop) (whole top levels) read from their prepared LDS copy
-__device__ __forceinline__ int32_t traverse_packed(const ProbeNode *__restrict__ top, int32_t ntop,
-                                                   const uint64_t *__restrict__ tree, int32_t L, const Frame &fr,
-                                                   const uint64_t *__restrict__ packed, int u, int v, uint64_t own)
+// Traversal of one tree for K pixels of a packed frame at once (their
+// chains of dependent probe loads interleave): every leaf of a complete tree
+// lies at the same depth, so the K node indices stay on one level. Pixel k is
+// p[k] with packed word own[k]; lanes whose pixel is invalid (ok[k] false)
+// walk with the smallest valid depth on a clamped position and get -1.
+template <int K>
+__device__ __forceinline__ void traverse_packed_k(const ProbeNode *__restrict__ top, int32_t ntop,
+                                                  const uint64_t *__restrict__ tree, int32_t L, const Frame &fr,
+                                                  const uint64_t *__restrict__ packed, const int p[K],
+                                                  const uint64_t own[K], const bool ok[K], int32_t leaf[K])
 {
-    const PixelDen pd = pixel_den(fr, (int32_t)(own & 0xFFFFull));
-    int32_t i = 0;
-    while (i < ntop) {
-        const ProbeNode n = top[i];
-        const int32_t r = probe_response(packed, fr.W, fr.H, u, v, own, pd, n);
-        i = 2 * i + 1 + (r >= n.thr ? 1 : 0);
+    PixelDen pd[K];
+    int u[K], v[K];
+    int32_t i[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        u[k] = p[k] % fr.W;
+        v[k] = p[k] / fr.W;
+        pd[k] = pixel_den(fr, ok[k] ? (int32_t)(own[k] & 0xFFFFull) : fr.dmin);
+        i[k] = 0;
     }
-    while (i < L - 1) {
-        const ProbeNode n = probe_node(tree[i], fr);
-        const int32_t r = probe_response(packed, fr.W, fr.H, u, v, own, pd, n);
-        i = 2 * i + 1 + (r >= n.thr ? 1 : 0);
+    while (i[0] < ntop) {
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            const ProbeNode n = top[i[k]];
+            const int32_t r = probe_response(packed, fr.W, fr.H, u[k], v[k], own[k], pd[k], n);
+            i[k] = 2 * i[k] + 1 + (r >= n.thr ? 1 : 0);
+        }
     }
-    return i - (L - 1);
+    while (i[0] < L - 1) {
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            const ProbeNode n = probe_node(tree[i[k]], fr);
+            const int32_t r = probe_response(packed, fr.W, fr.H, u[k], v[k], own[k], pd[k], n);
+            i[k] = 2 * i[k] + 1 + (r >= n.thr ? 1 : 0);
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < K; ++k) leaf[k] = ok[k] ? i[k] - (L - 1) : -1;
 }
+
 
 // ---------------------------------------------------------------------------
 // FP64 rigid alignment from correspondence sums (Horn's unit-quaternion

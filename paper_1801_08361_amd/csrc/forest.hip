@@ -157,22 +157,37 @@ __global__ void __launch_bounds__(256) k_pack(Frame fr, uint64_t *__restrict__ p
     if (p < (int64_t)fr.W * fr.H) packed[p] = pack_pixel(fr, p);
 }
 
+// block (x) of 4 x 256 pixels and tree (y): each thread walks 4 pixels of
+// the tree together (tid, tid + 256, ...)
+constexpr int LEAF_PIX = 4;
+
 __global__ void __launch_bounds__(256) k_leaves(const uint64_t *__restrict__ nodes, int T, int L, Frame fr,
                                                 const uint64_t *__restrict__ packed, int32_t *__restrict__ leaves)
 {
     __shared__ ProbeNode top[TOP_NODES];
     const int P = fr.W * fr.H;
-    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    const int base = blockIdx.x * (LEAF_PIX * 256) + threadIdx.x;
     const int t = blockIdx.y;
     const uint64_t *tree = nodes + (int64_t)t * (L - 1);
     const int ntop = L - 1 < TOP_NODES ? L - 1 : TOP_NODES;
     stage_top(top, tree, ntop, fr, (int)threadIdx.x, (int)blockDim.x);
     __syncthreads();
-    if (p >= P || t >= T) return;
-    const uint64_t own = packed[p];
-    int32_t leaf = -1;
-    if (packed_valid(own)) leaf = traverse_packed(top, ntop, tree, L, fr, packed, p % fr.W, p / fr.W, own);
-    leaves[(int64_t)t * P + p] = leaf;
+    if (base >= P || t >= T) return;
+    int p[LEAF_PIX];
+    uint64_t own[LEAF_PIX];
+    bool ok[LEAF_PIX];
+#pragma unroll
+    for (int k = 0; k < LEAF_PIX; ++k) {
+        const int q = base + k * 256;
+        p[k] = q < P ? q : P - 1;
+        own[k] = packed[p[k]];
+        ok[k] = q < P && packed_valid(own[k]);
+    }
+    int32_t leaf[LEAF_PIX];
+    traverse_packed_k<LEAF_PIX>(top, ntop, tree, L, fr, packed, p, own, ok, leaf);
+#pragma unroll
+    for (int k = 0; k < LEAF_PIX; ++k)
+        if (base + k * 256 < P) leaves[(int64_t)t * P + base + k * 256] = leaf[k];
 }
 
 __global__ void k_features8(const uint64_t *__restrict__ extra, Frame fr, int32_t *__restrict__ feat)
@@ -642,7 +657,8 @@ int traverse_frame(Forest *f, const Frame &fr, hipStream_t s)
     int rc = ensure_frame_scratch(f, P, s);
     if (rc) return rc;
     RL_LAUNCH("k_pack", k_pack, dim3((unsigned)((P + 255) / 256)), dim3(256), 0, s, fr, f->packed);
-    RL_LAUNCH("k_leaves", k_leaves, dim3((unsigned)((P + 255) / 256), (unsigned)f->T), dim3(256), 0, s, f->nodes,
+    RL_LAUNCH("k_leaves", k_leaves, dim3((unsigned)((P + LEAF_PIX * 256 - 1) / (LEAF_PIX * 256)), (unsigned)f->T),
+              dim3(256), 0, s, f->nodes,
               f->T, f->L, fr, f->packed, f->leaves);
     RL_HIP(hipGetLastError());
     return RELOC_OK;

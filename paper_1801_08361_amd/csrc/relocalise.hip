@@ -40,6 +40,7 @@ int update_modes(Forest *f, hipStream_t s);
 int frame_from(const Forest *f, const uint16_t *depth, const uint8_t *rgb, const reloc_intrinsics *K, Frame &fr);
 
 constexpr int PIX_BLOCK = 256;
+constexpr int PIX_PER_THREAD = 4;   // pixels traversed together by one thread
 constexpr int POOL_BLOCK = 1024;
 
 __device__ __forceinline__ uint64_t lanemask_lt() { return (1ull << __lane_id()) - 1ull; }
@@ -61,8 +62,10 @@ __device__ __forceinline__ bool round_active(const Attempt &A, int r)
 // features and traversal of every pixel
 // ---------------------------------------------------------------------------
 
-// unit = (tree, block of PIX_BLOCK pixels): one thread per (pixel, tree), so
-// the trees' node chains run side by side
+// unit = (tree, block of PIX_PER_THREAD x PIX_BLOCK pixels): each thread
+// walks PIX_PER_THREAD pixels of one tree together (pixels tid, tid +
+// PIX_BLOCK, ...), so that several chains of dependent probe loads are in
+// flight per thread and the trees' units run side by side
 // The workgroup keeps the top levels of its unit's tree in LDS, scaled for
 // the attempt's frame (restaged only when the (attempt, tree) pair changes
 // between its units).
@@ -73,7 +76,8 @@ __global__ void __launch_bounds__(PIX_BLOCK) k_b_leaves(const Attempt *__restric
     FOR_UNITS(S, u) {
         const int a = attempt_of(S, u);
         const Attempt &A = att[a];
-        const int nb = (A.P + PIX_BLOCK - 1) / PIX_BLOCK;
+        constexpr int PU = PIX_PER_THREAD * PIX_BLOCK;
+        const int nb = (A.P + PU - 1) / PU;
         const int local = u - S.off[a];
         const int t = local / nb;
         const uint64_t *tree = A.nodes + (int64_t)t * (A.L - 1);
@@ -86,12 +90,23 @@ __global__ void __launch_bounds__(PIX_BLOCK) k_b_leaves(const Attempt *__restric
             cached_a = a;
             cached_t = t;
         }
-        const int p = (local % nb) * PIX_BLOCK + (int)threadIdx.x;
-        if (p >= A.P) continue;
-        const uint64_t own = A.packed[p];
-        int32_t leaf = -1;
-        if (packed_valid(own)) leaf = traverse_packed(top, ntop, tree, A.L, fr, A.packed, p % fr.W, p / fr.W, own);
-        A.leaves[(int64_t)t * A.P + p] = leaf;
+        const int base = (local % nb) * PU + (int)threadIdx.x;
+        if (base >= A.P) continue;
+        int p[PIX_PER_THREAD];
+        uint64_t own[PIX_PER_THREAD];
+        bool ok[PIX_PER_THREAD];
+#pragma unroll
+        for (int k = 0; k < PIX_PER_THREAD; ++k) {
+            const int q = base + k * PIX_BLOCK;
+            p[k] = q < A.P ? q : A.P - 1;
+            own[k] = A.packed[p[k]];
+            ok[k] = q < A.P && packed_valid(own[k]);
+        }
+        int32_t leaf[PIX_PER_THREAD];
+        traverse_packed_k<PIX_PER_THREAD>(top, ntop, tree, A.L, fr, A.packed, p, own, ok, leaf);
+#pragma unroll
+        for (int k = 0; k < PIX_PER_THREAD; ++k)
+            if (base + k * PIX_BLOCK < A.P) A.leaves[(int64_t)t * A.P + base + k * PIX_BLOCK] = leaf[k];
     }
 }
 
@@ -1136,7 +1151,9 @@ static std::vector<int32_t> offsets(const Plan *pl, const Sched &sc)
         for (int a = 0; a < n; ++a) o[a + 1] = o[a] + units(a);
     };
     auto P = [&](int a) { return (int64_t)pl->shape[a].W * pl->shape[a].H; };
-    fill(0, [&](int a) { return pl->shape[a].T * (int)((P(a) + PIX_BLOCK - 1) / PIX_BLOCK); });
+    fill(0, [&](int a) {
+        return pl->shape[a].T * (int)((P(a) + PIX_PER_THREAD * PIX_BLOCK - 1) / (PIX_PER_THREAD * PIX_BLOCK));
+    });
     fill(1, [&](int a) { return (int)((P(a) + POOL_BLOCK - 1) / POOL_BLOCK); });
     fill(2, [&](int) { return 1; });
     fill(3, [&](int a) { return pl->shape[a].N + (rounds_for(pl->shape[a].N) * pl->shape[a].B + 63) / 64; });
