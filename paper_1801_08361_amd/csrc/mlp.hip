@@ -288,8 +288,9 @@ __global__ void __launch_bounds__(64) k_mlp_logits(const uint16_t *__restrict__ 
     } else {
         for (int k = 0; k < 4; ++k) d[k] = make_uint4(0, 0, 0, 0);
     }
+    stage_head(S, q, w);
     __syncthreads();
-    const float zl = tile_forward_regs(S.X, q, w);
+    const float zl = tile_forward_regs(S, q, w);
     if (r0 + l < n) z[r0 + l] = zl;
 }
 
@@ -366,8 +367,9 @@ __global__ void __launch_bounds__(64) k_mlp_pixels(FeatArgs A, const uint16_t *_
     else
         for (int k = 0; k < 24; ++k) x[k] = 0.0f;
     store_row(S, x);
+    stage_head(S, q, w);
     __syncthreads();
-    const float zl = tile_forward_regs(S.X, q, w);
+    const float zl = tile_forward_regs(S, q, w);
     if (p < P) {
         const bool ok = valid_depth(A.fr, A.fr.depth[p]);
         float sg = 0.0f;

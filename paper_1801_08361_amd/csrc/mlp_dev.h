@@ -67,7 +67,19 @@ __device__ __forceinline__ floatx4 mfma_tile(const uint16_t *A, int lda, const u
 // registers, tile_forward_regs)
 struct __align__(16) InTile {
     uint16_t X[ROWS * 32];
+    float b1[64], b2[64], w3[64];   // biases and output weights (w3 from its bfloat16 copy)
 };
+
+// the tile's copy of the network's biases and output weights (every thread
+// of the workgroup takes part; a barrier must follow before they are read)
+__device__ __forceinline__ void stage_head(InTile &S, const uint16_t *__restrict__ q, const float *__restrict__ w)
+{
+    for (int k = threadIdx.x; k < 64; k += blockDim.x) {
+        S.b1[k] = w[OB1 + k];
+        S.b2[k] = w[OB2 + k];
+        S.w3[k] = bf2f(q[QW3 + k]);
+    }
+}
 
 // Forward pass of the 64 rows in S.X (bfloat16, 24 inputs + 8 zeros): H1, H2
 // in bfloat16, logits in S.z. With kTrans the tile also keeps H1 transposed
@@ -127,9 +139,10 @@ __device__ void tile_forward(Tile &S, const uint16_t *__restrict__ q, const floa
 // order). H1 and H2 are rounded to bfloat16 (nearest even, by the conversion
 // instruction) after bias and ReLU as in tile_forward; the output dot w3 . h2
 // is summed per lane over its 16 hidden units, then over the four lane groups.
-__device__ __forceinline__ float tile_forward_regs(const uint16_t *X, const uint16_t *__restrict__ q,
+__device__ __forceinline__ float tile_forward_regs(const InTile &S, const uint16_t *__restrict__ q,
                                                    const float *__restrict__ w)
 {
+    const uint16_t *X = S.X;
     const int l = __lane_id(), col = l & 15, g = l >> 4;
     bf16x8 a1[4], a2[4][2];
 #pragma unroll
@@ -143,17 +156,6 @@ __device__ __forceinline__ float tile_forward_regs(const uint16_t *X, const uint
             const uint2 hi = *(const uint2 *)(row + 16);   // hidden 32 c + 16 + 4 g .. + 3
             a2[tk][c] = __builtin_bit_cast(bf16x8, make_uint4(lo.x, lo.y, hi.x, hi.y));
         }
-    // this lane's biases and output weights (hidden units 16 t + 4 g + i)
-    float b1[16], b2[16], w3[16];
-#pragma unroll
-    for (int t = 0; t < 4; ++t)
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            const int hid = 16 * t + 4 * g + i;
-            b1[4 * t + i] = w[OB1 + hid];
-            b2[4 * t + i] = w[OB2 + hid];
-            w3[4 * t + i] = bf2f(q[QW3 + hid]);
-        }
     float zrow = 0.0f;
 #pragma unroll 1
     for (int ti = 0; ti < 4; ++ti) {
@@ -163,12 +165,10 @@ __device__ __forceinline__ float tile_forward_regs(const uint16_t *X, const uint
         for (int tj = 0; tj < 4; ++tj) {
             floatx4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
             acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1[tj], xb, acc, 0, 0, 0);
-            float hv[4];
+            const float4 bb = *(const float4 *)(S.b1 + 16 * tj + 4 * g);
+            float hv[4] = {acc[0] + bb.x, acc[1] + bb.y, acc[2] + bb.z, acc[3] + bb.w};
 #pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                hv[i] = acc[i] + b1[4 * tj + i];
-                hv[i] = hv[i] > 0.0f ? hv[i] : 0.0f;
-            }
+            for (int i = 0; i < 4; ++i) hv[i] = hv[i] > 0.0f ? hv[i] : 0.0f;
             h1[2 * tj] = bf16_pair(hv[0], hv[1]);
             h1[2 * tj + 1] = bf16_pair(hv[2], hv[3]);
         }
@@ -180,17 +180,18 @@ __device__ __forceinline__ float tile_forward_regs(const uint16_t *X, const uint
             floatx4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
             acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a2[tk][0], b2lo, acc, 0, 0, 0);
             acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a2[tk][1], b2hi, acc, 0, 0, 0);
-            float hv[4];
+            const float4 bb = *(const float4 *)(S.b2 + 16 * tk + 4 * g);
+            float hv[4] = {acc[0] + bb.x, acc[1] + bb.y, acc[2] + bb.z, acc[3] + bb.w};
 #pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                hv[i] = acc[i] + b2[4 * tk + i];
-                hv[i] = hv[i] > 0.0f ? hv[i] : 0.0f;
-            }
+            for (int i = 0; i < 4; ++i) hv[i] = hv[i] > 0.0f ? hv[i] : 0.0f;
             const uint32_t p01 = bf16_pair(hv[0], hv[1]), p23 = bf16_pair(hv[2], hv[3]);
             const float h2[4] = {__uint_as_float(p01 << 16), __uint_as_float(p01 & 0xFFFF0000u),
                                  __uint_as_float(p23 << 16), __uint_as_float(p23 & 0xFFFF0000u)};
-#pragma unroll
-            for (int i = 0; i < 4; ++i) z = fmaf(w3[4 * tk + i], h2[i], z);
+            const float4 ww = *(const float4 *)(S.w3 + 16 * tk + 4 * g);
+            z = fmaf(ww.x, h2[0], z);
+            z = fmaf(ww.y, h2[1], z);
+            z = fmaf(ww.z, h2[2], z);
+            z = fmaf(ww.w, h2[3], z);
         }
         z = z + __shfl_xor(z, 16, 64);
         z = z + __shfl_xor(z, 32, 64);

@@ -115,7 +115,9 @@ __global__ void __launch_bounds__(PIX_BLOCK) k_b_leaves(const Attempt *__restric
 // valid pixel, the network's forward pass on the matrix cores, and
 // floor(sigmoid 65536) + 1 (0 for an invalid pixel), exactly as the
 // stand-alone weight kernel computes them after its own traversal.
-__global__ void __launch_bounds__(64) k_b_weights(const Attempt *__restrict__ att, Stage S)
+// (at least 4 wavefronts per SIMD: the kernel waits on gathers most of the
+// time, and 4 resident wavefronts with a few spilled registers beat 3 without)
+__global__ void __launch_bounds__(64, 4) k_b_weights(const Attempt *__restrict__ att, Stage S)
 {
     __shared__ InTile T;
     const int l = __lane_id();
@@ -135,16 +137,17 @@ __global__ void __launch_bounds__(64) k_b_weights(const Attempt *__restrict__ at
         for (int k = 0; k < 24; ++k) x[k] = 0.0f;
         bool ok = false;
         if (p < A.P) {
-            const uint32_t d = A.fr.depth[p];
-            ok = valid_depth(A.fr, d);
+            const uint64_t own = A.packed[p];
+            ok = packed_valid(own);
             if (ok)
-                pixel_inputs(F, p % A.fr.W, p / A.fr.W, d, [&](int t) { return A.leaves[(int64_t)t * A.P + p]; },
-                             x);
+                pixel_inputs(F, p % A.fr.W, p / A.fr.W, (uint32_t)(own & 0xFFFFull),
+                             [&](int t) { return A.leaves[(int64_t)t * A.P + p]; }, x);
         }
         __syncthreads();   // the previous unit's tile is no longer read
         store_row(T, x);
+        stage_head(T, A.mq, A.mw);
         __syncthreads();
-        const float zl = tile_forward_regs(T.X, A.mq, A.mw);
+        const float zl = tile_forward_regs(T, A.mq, A.mw);
         const uint32_t w = (p < A.P && ok) ? pick_weight(zl, nullptr) : 0u;
         if (p < A.P) A.wbuf[p] = w;
         // the tile's weight sum into its pixel block's (zeroed by k_b_pack;
