@@ -215,6 +215,42 @@ def test_relocalise_matches_oracle(dev, adapted_pair, q, n_hyp):
     assert abs(scg - sco) < 1e-6
 
 
+@pytest.mark.parametrize("tol", [0, 40, 300])
+def test_relocalise_many_modes_colour_tolerances(dev, tol):
+    """Leaves with more than 12 modes (the general colour-mask path) and
+    colour tolerances at 0, inside the byte range and beyond it."""
+    pp, po = pair(**dict(SMALL, max_modes=20, min_cluster=1, rgb_tol=tol))
+    g, o = make(pp, po)
+    sc = sr.small_scene(12)
+    for k in range(8):
+        d0, c0 = sc.render_adapt(k)
+        d, c = to_dev(d0, c0, dev)
+        banner(f"many modes tol={tol}: adapt frame {k}")
+        g.adapt_frame(d, c, sc.K, sc.adapt_poses[k])
+        o.adapt(d0, c0, sc.K, sc.adapt_poses[k])
+    g.update_modes()
+    _, ng = g.modes(0, 0, g.L)
+    assert ng.max() > 12, ng.max()
+    for q in (3, 6):
+        d0, c0 = sc.render_query(q)
+        d, c = to_dev(d0, c0, dev)
+        banner(f"many modes tol={tol}: relocalise q={q}")
+        sg, Tg, _ = g.relocalise(d, c, sc.K, seed=900 + q, n_hyp=128)
+        tg = g.trace(128)
+        so, To, _, to = o.relocalise(d0, c0, sc.K, seed=900 + q, n_hyp=128, trace=True)
+        assert sg == so
+        assert np.array_equal(tg["hyp_try"], to["hyp_try"]), q
+        if sg == 0:
+            assert np.linalg.norm(Tg[:3, 3] - To[:3, 3]) < 1e-4
+            assert rot_angle_deg(Tg[:3, :3], To[:3, :3]) < 1e-3
+
+
+def test_negative_colour_tolerance_rejected():
+    import paper_1801_08361_amd as rl
+    with pytest.raises(rl.RelocError):
+        rl.Forest(rl.params_default(rgb_tol=-1))
+
+
 def test_relocalise_failures(dev, adapted_pair):
     import paper_1801_08361_amd as rl
     sc, g, o = adapted_pair
