@@ -639,6 +639,12 @@ __device__ __forceinline__ uint32_t float_key(float f)
     return (b & 0x80000000u) ? ~b : (b | 0x80000000u);
 }
 
+// its inverse
+__device__ __forceinline__ float key_float(uint32_t k)
+{
+    return __uint_as_float((k & 0x80000000u) ? (k & 0x7FFFFFFFu) : ~k);
+}
+
 // ---------------------------------------------------------------------------
 // the forest handle
 // ---------------------------------------------------------------------------
@@ -709,7 +715,7 @@ struct Attempt {
     Hyp *hyp;                      // [N]
     double *hyp_init;              // [N][12]
     int32_t *hyp_try;              // [N]
-    float *energy;                 // [N]
+    float *energy;                 // [N] accumulated energy of the hypothesis at each live position
     double *sums;                  // [N][NSUM] running inlier sums
     int32_t *alive;                // [N]
     int32_t *pos;                  // [N] survivor i's position in the list it was scored in

@@ -558,7 +558,6 @@ __global__ void __launch_bounds__(64) k_b_hypgen(const Attempt *__restrict__ att
         }
         if (lane == 0) {
             A.hyp_try[h] = found;
-            A.energy[h] = 0.0f;
         }
         if (lane < NSUM) A.sums[(int64_t)h * NSUM + lane] = 0.0;
     }
@@ -593,6 +592,7 @@ __global__ void __launch_bounds__(1024) k_b_alive_init(const Attempt *__restrict
             if (ok) {
                 const int pos = off + __popcll(m & lanemask_lt());
                 A.alive[pos] = h;
+                A.energy[pos] = 0.0f;
                 for (int k = 0; k < 12; ++k) A.lpose[pos * 12 + k] = pz[k];
             }
             __syncthreads();
@@ -632,7 +632,7 @@ static int score_waves(int tm)
 // defined order, bitonic sort of keys (energy key << 32 | index << 12 |
 // position), which orders by (energy, index); keep the first ceil(n / 2),
 // with each survivor's position in this round's list (where its inliers were
-// stored). Compare-exchange distances of 64 and more go through LDS (`keys`,
+// stored) and its energy at its new position. Compare-exchange distances of 64 and more go through LDS (`keys`,
 // room for the attempt's hypothesis count rounded up to a power of two, at
 // least 64) with a barrier; shorter ones run in registers across the lanes of
 // a wavefront.
@@ -663,8 +663,7 @@ __device__ void cull_round(const Attempt &A, int r, unsigned long long *__restri
                 for (int k = 0; k < 32; ++k)
                     if (k0 + k < ng) Ssum = Ssum + v[k];
             }
-            const float E = A.energy[h] + Ssum;
-            A.energy[h] = E;
+            const float E = A.energy[ap] + Ssum;
             keys[ap] = cull_key(E, h, ap);
             if (r < MAX_ROUNDS) {
                 A.tr_alive[r * A.N + ap] = h;
@@ -712,6 +711,7 @@ __device__ void cull_round(const Attempt &A, int r, unsigned long long *__restri
         const unsigned long long key = keys[i];
         A.alive[i] = (int32_t)((key >> 12) & 0xFFFFFull);
         A.pos[i] = (int32_t)(key & 0xFFFull);
+        A.energy[i] = key_float((uint32_t)(key >> 32));   // read above, before the first barrier
     }
     __syncthreads();
     if (threadIdx.x == 0) {
@@ -870,10 +870,13 @@ constexpr int RB = 8;              // draws per lane per load batch in refinemen
 constexpr int FUSED_REFINE = 1024; // survivors up to which a round refines in one kernel
 
 // this round's inlier sums of hypothesis h (scored at live position ap),
-// added to its running sums by lane 0
+// added to its running sums (every lane ends with the totals; lane 0 stores
+// them)
 __device__ __forceinline__ void refine_sums_at(const Attempt &A, int r, int h, int ap, double s[NSUM])
 {
     const int lane = __lane_id();
+    // the running sums, one per lane, fetched while this round's are formed
+    const double runk = lane < NSUM ? A.sums[(int64_t)h * NSUM + lane] : 0.0;
 #pragma unroll
     for (int k = 0; k < NSUM; ++k) s[k] = 0.0;
     // lane-strided draws, RB per lane at a time: all inlier ids first, then the
@@ -903,13 +906,12 @@ __device__ __forceinline__ void refine_sums_at(const Attempt &A, int r, int h, i
     for (int o = 32; o >= 1; o >>= 1)
 #pragma unroll
         for (int k = 0; k < NSUM; ++k) s[k] = s[k] + __shfl_xor(s[k], o, 64);
+#pragma unroll
+    for (int k = 0; k < NSUM; ++k) s[k] = __shfl(runk, k, 64) + s[k];
     if (lane == 0) {
         double *run = A.sums + (int64_t)h * NSUM;
 #pragma unroll
-        for (int k = 0; k < NSUM; ++k) {
-            s[k] = run[k] + s[k];
-            run[k] = s[k];
-        }
+        for (int k = 0; k < NSUM; ++k) run[k] = s[k];
     }
 }
 
