@@ -309,20 +309,29 @@ __device__ __forceinline__ void stage_top(ProbeNode *__restrict__ top, const uin
     for (int k = tid; k < ntop; k += nthreads) top[k] = probe_node(tree[k], fr);
 }
 
+// A buffer resource over a packed frame of P words (P <= 2^26, checked by
+// the host): probe loads take a 32-bit byte offset from it, and the hardware
+// range-checks them against the P * 8 bytes.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t packed_rsrc(const uint64_t *packed, int P)
+{
+    return __builtin_amdgcn_make_buffer_rsrc((void *)packed, (short)0, P * 8, 0x00020000);
+}
+
 // node_response_d of a prepared node, from the packed frame: `own` is the
 // pixel's own packed word. Branch-free: the probe position is clamped into
 // the image and one word is loaded; a depth probe whose position was clamped
 // reads 65535 instead.
-__device__ __forceinline__ int32_t probe_response(const uint64_t *__restrict__ packed, int W, int H, int u, int v,
+__device__ __forceinline__ int32_t probe_response(__amdgpu_buffer_rsrc_t packed, int W, int H, int u, int v,
                                                   uint64_t own, const PixelDen &pd, const ProbeNode &n)
 {
-    const int32_t ox = (int32_t)div_mag2(n.ax, pd), oy = (int32_t)div_mag2(n.ay, pd);
-    const int32_t qx = u + ((n.meta & 4u) ? -ox : ox);
-    const int32_t qy = v + ((n.meta & 8u) ? -oy : oy);
-    const int32_t cx = max(0, min(qx, W - 1));
-    const int32_t cy = max(0, min(qy, H - 1));
-    // a global-memory load at a 32-bit word offset from the frame's base
-    const uint64_t w = ((const __attribute__((address_space(1))) uint64_t *)packed)[(uint32_t)(cy * W + cx)];
+    const uint32_t ox = div_mag2(n.ax, pd), oy = div_mag2(n.ay, pd);
+    // signed offsets: s = 0 or -1 from the node's sign bits, u + (o ^ s) - s
+    const uint32_t sx = (uint32_t)((int32_t)(n.meta << 29) >> 31), sy = (uint32_t)((int32_t)(n.meta << 28) >> 31);
+    const int32_t qx = (int32_t)(((ox ^ sx) + (uint32_t)u) - sx);
+    const int32_t qy = (int32_t)(((oy ^ sy) + (uint32_t)v) - sy);
+    const int32_t cx = min(max(qx, 0), W - 1);
+    const int32_t cy = min(max(qy, 0), H - 1);
+    const uint64_t w = __builtin_bit_cast(uint64_t, __builtin_amdgcn_raw_buffer_load_b64(packed, (cy * W + cx) * 8, 0, 0));
     const uint32_t sh = (n.meta >> 8) & 63u;
     const uint32_t mask = (n.meta & 3u) ? 0xFFu : 0xFFFFu;
     uint32_t val = (uint32_t)(w >> sh) & mask;
@@ -341,6 +350,7 @@ __device__ __forceinline__ void traverse_packed_k(const ProbeNode *__restrict__ 
                                                   const uint64_t *__restrict__ packed, const int p[K],
                                                   const uint64_t own[K], const bool ok[K], int32_t leaf[K])
 {
+    const __amdgpu_buffer_rsrc_t rs = packed_rsrc(packed, fr.W * fr.H);
     PixelDen pd[K];
     int u[K], v[K];
     int32_t i[K];
@@ -355,7 +365,7 @@ __device__ __forceinline__ void traverse_packed_k(const ProbeNode *__restrict__ 
 #pragma unroll
         for (int k = 0; k < K; ++k) {
             const ProbeNode n = top[i[k]];
-            const int32_t r = probe_response(packed, fr.W, fr.H, u[k], v[k], own[k], pd[k], n);
+            const int32_t r = probe_response(rs, fr.W, fr.H, u[k], v[k], own[k], pd[k], n);
             i[k] = 2 * i[k] + 1 + (r >= n.thr ? 1 : 0);
         }
     }
@@ -363,7 +373,7 @@ __device__ __forceinline__ void traverse_packed_k(const ProbeNode *__restrict__ 
 #pragma unroll
         for (int k = 0; k < K; ++k) {
             const ProbeNode n = probe_node(tree[i[k]], fr);
-            const int32_t r = probe_response(packed, fr.W, fr.H, u[k], v[k], own[k], pd[k], n);
+            const int32_t r = probe_response(rs, fr.W, fr.H, u[k], v[k], own[k], pd[k], n);
             i[k] = 2 * i[k] + 1 + (r >= n.thr ? 1 : 0);
         }
     }

@@ -232,7 +232,8 @@ __device__ __forceinline__ void pixel_inputs(const FeatArgs &A, int u, int v, ui
     for (int j = 0; j < 8; ++j) {
         int32_t r;
         if (A.packed) {
-            r = probe_response(A.packed, A.fr.W, A.fr.H, u, v, own, pd, probe_node(extra[j], A.fr));
+            r = probe_response(packed_rsrc(A.packed, A.fr.W * A.fr.H), A.fr.W, A.fr.H, u, v, own, pd,
+                               probe_node(extra[j], A.fr));
         } else {
             int32_t thr;
             r = node_response_d(A.fr, extra[j], u, v, (int32_t)d, pd, thr);
