@@ -714,7 +714,7 @@ struct Attempt {
     double resid2;
     uint64_t seed;
     // scratch owned by the batch
-    int32_t *leaves;               // [T][P]
+    int32_t *leaves;               // [T][P] leaf of each pixel in each tree (-1: invalid pixel)
     uint64_t *packed;              // [P] the frame packed for probing
     int32_t *pool;                 // [P]
     int32_t *blockcnt;             // [nb]

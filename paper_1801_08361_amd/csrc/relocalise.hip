@@ -418,10 +418,11 @@ __device__ bool try_hypothesis(const Attempt &A, int np, uint64_t h, uint64_t ta
     uint32_t pr[3], pg[3], pb[3], dep[3];
 #pragma unroll
     for (int j = 0; j < 3; ++j) {
-        pr[j] = A.fr.rgb[p[j] * 3];
-        pg[j] = A.fr.rgb[p[j] * 3 + 1];
-        pb[j] = A.fr.rgb[p[j] * 3 + 2];
-        dep[j] = A.fr.depth[p[j]];
+        const uint64_t pw = A.packed[p[j]];   // pool pixels are valid: the word holds their depth
+        dep[j] = (uint32_t)(pw & 0xFFFFull);
+        pr[j] = (uint32_t)(pw >> 16) & 255u;
+        pg[j] = (uint32_t)(pw >> 24) & 255u;
+        pb[j] = (uint32_t)(pw >> 32) & 255u;
     }
     int64_t pick[3];
     float c[3][3], w[3][3];
@@ -521,7 +522,7 @@ __global__ void __launch_bounds__(64) k_b_hypgen(const Attempt *__restrict__ att
                 const U4 x = philox((uint64_t)rr, (uint64_t)i, 0, 0, A.seed, TAG_PIX);
                 const int p = A.pool[uniform_int(x.x[0], (uint64_t)np)];
                 float c[3];
-                cam_point(A.fr, p % A.fr.W, p / A.fr.W, A.fr.depth[p], c);
+                cam_point(A.fr, p % A.fr.W, p / A.fr.W, (uint32_t)(A.packed[p] & 0xFFFFull), c);
                 A.draws[gi] = make_float4(c[0], c[1], c[2], __int_as_float(p));
                 for (int t = 0; t < A.T; ++t) {
                     const int li = t * A.L + A.leaves[(int64_t)t * A.P + p];
