@@ -232,12 +232,6 @@ __device__ __forceinline__ int32_t node_response_d(const Frame &fr, uint64_t w, 
     return (int32_t)fr.rgb[(qy * fr.W + qx) * 3 + c] - (int32_t)fr.rgb[(v * fr.W + u) * 3 + c];
 }
 
-__device__ __forceinline__ int32_t node_response(const Frame &fr, uint64_t w, int u, int v, int32_t d,
-                                                 int32_t &thr)
-{
-    return node_response_d(fr, w, u, v, d, pixel_den(fr, d), thr);
-}
-
 // implicit heap: children of node i are 2i+1 (left) and 2i+2 (right); go
 // right iff response >= threshold; leaf = i - (L - 1)
 __device__ __forceinline__ int32_t traverse_d(const uint64_t *__restrict__ tree, int32_t L, const Frame &fr, int u,
@@ -626,21 +620,6 @@ __device__ __forceinline__ bool pose_from_sums(const double s[NSUM], double R[9]
     return true;
 }
 
-// energy term of one mode at y (FP32, fused exactly as written):
-// d = y - mu; a = Sigma^-1 d; q = d . a; term = 0.5 q + kappa
-__device__ __forceinline__ float mode_term(const Mode &m, float y0, float y1, float y2, float &d0, float &d1,
-                                           float &d2)
-{
-    d0 = y0 - m.mu[0];
-    d1 = y1 - m.mu[1];
-    d2 = y2 - m.mu[2];
-    const float *s = m.sinv;
-    float a0 = fmaf(s[2], d2, fmaf(s[1], d1, s[0] * d0));
-    float a1 = fmaf(s[4], d2, fmaf(s[3], d1, s[1] * d0));
-    float a2 = fmaf(s[5], d2, fmaf(s[4], d1, s[2] * d0));
-    float q = fmaf(d2, a2, fmaf(d1, a1, d0 * a0));
-    return fmaf(0.5f, q, m.kappa);
-}
 
 // float -> uint32 key that sorts like the float (no NaN, no -0 here)
 __device__ __forceinline__ uint32_t float_key(float f)
