@@ -258,30 +258,45 @@ __device__ __forceinline__ int32_t traverse(const uint64_t *__restrict__ tree, i
 // lengths; each pixel's divisor and own colour are set up once
 // ---------------------------------------------------------------------------
 
-constexpr int TOP_NODES = 1023;   // levels 0..9, 16 KB unpacked
+constexpr int TOP_NODES = 1023;   // levels 0..9, 32 KB prepared
 
-// One pixel of a frame packed for probing: the depth in bits 0-15 (65535
-// where it lies outside the valid range; the host keeps the range below
-// 65535) and the colour r, g, b in bits 16-23, 24-31 and 32-39, so that one
-// 8-byte load serves a probe of either kind.
+// One pixel of a frame packed for probing: four 16-bit fields, each holding
+// the complement of its value, so that every probe's response is the pixel's
+// own field minus the probed one and a zero field reads as "no depth". Bits
+// 0-15 hold 65535 - z, where z is the depth, or 65535 outside the valid
+// range (the host keeps the range below 65535), so an invalid pixel's field
+// is 0; bits 16-31, 32-47 and 48-63 hold 255 - r, 255 - g and 255 - b.
 __device__ __forceinline__ uint64_t pack_pixel(const Frame &fr, int64_t p)
 {
     const uint32_t d = fr.depth[p];
-    const uint64_t z = valid_depth(fr, d) ? (uint64_t)d : 65535ull;
-    return z | ((uint64_t)fr.rgb[p * 3] << 16) | ((uint64_t)fr.rgb[p * 3 + 1] << 24) |
-           ((uint64_t)fr.rgb[p * 3 + 2] << 32);
+    const uint64_t z = valid_depth(fr, d) ? (uint64_t)(65535u - d) : 0ull;
+    return z | ((uint64_t)(255u - fr.rgb[p * 3]) << 16) | ((uint64_t)(255u - fr.rgb[p * 3 + 1]) << 32) |
+           ((uint64_t)(255u - fr.rgb[p * 3 + 2]) << 48);
 }
 
-__device__ __forceinline__ bool packed_valid(uint64_t w) { return (w & 0xFFFFull) != 0xFFFFull; }
+__device__ __forceinline__ bool packed_valid(uint64_t w) { return (w & 0xFFFFull) != 0ull; }
+
+// the depth of a packed pixel (65535 where it is invalid)
+__device__ __forceinline__ uint32_t packed_depth(uint64_t w) { return 65535u - (uint32_t)(w & 0xFFFFull); }
+
+// colour channel c (0 r, 1 g, 2 b) of a packed pixel
+__device__ __forceinline__ uint32_t packed_colour(uint64_t w, int c)
+{
+    return 255u - ((uint32_t)(w >> (16 + 16 * c)) & 0xFFFFu);
+}
 
 // A split node prepared for one frame: its offsets multiplied by the focal
-// lengths, as the doubled magnitudes that div_mag2 takes, with their signs,
-// the feature kind and the bit position of the probed channel in a packed
-// pixel word.
+// lengths, as the doubled magnitudes that div_mag2 takes and their signs, the
+// threshold, and where its channel sits in a packed pixel word.
 struct ProbeNode {
     uint32_t ax, ay;   // 2 |dx Fx|, 2 |dy Fy|
+    int32_t sx, sy;    // sign of dx Fx and of dy Fy, +1 or -1
     int32_t thr;
-    uint32_t meta;     // bits 0-1 kind, bit 2 dx < 0, bit 3 dy < 0, bits 8-13 channel shift
+    uint32_t sh;       // bits 0-5: 16 kind, the field's bit position in the word (bits 0-4: in its
+                       // 32-bit half); higher bits are not read
+    uint32_t half;     // byte offset of the field's 32-bit half in the word (0 or 4)
+    uint32_t wout;     // width the field is read with when the probe leaves the image: 0 for a depth
+                       // probe (no depth), 16 for a colour probe (the clamped pixel's colour)
 };
 
 __device__ __forceinline__ ProbeNode probe_node(uint64_t w, const Frame &fr)
@@ -292,8 +307,53 @@ __device__ __forceinline__ ProbeNode probe_node(uint64_t w, const Frame &fr)
     ProbeNode n;
     n.ax = (uint32_t)(nx < 0 ? -nx : nx) << 1;
     n.ay = (uint32_t)(ny < 0 ? -ny : ny) << 1;
+    n.sx = nx < 0 ? -1 : 1;
+    n.sy = ny < 0 ? -1 : 1;
     n.thr = thr;
-    n.meta = (uint32_t)kind | (nx < 0 ? 4u : 0u) | (ny < 0 ? 8u : 0u) | ((kind ? 8u + 8u * (uint32_t)kind : 0u) << 8);
+    n.sh = 16u * (uint32_t)kind;
+    n.half = 2u * (uint32_t)(kind & 2);
+    n.wout = kind ? 16u : 0u;
+    return n;
+}
+
+// A split node as the deep levels of the traversal read it, 16 bytes that do
+// not depend on the frame: x and y hold 2 |dx| and 2 |dy| in bits 0-21 and
+// the offset's sign in bit 31; meta holds 16 kind in bits 0-5, the byte
+// offset of the field's 32-bit half (0 or 4) in bits 6-8 and the width the
+// field is read with outside the image (0 or 16) in bits 9-13.
+struct DeepNode {
+    uint32_t x, y;
+    int32_t thr;
+    uint32_t meta;
+};
+
+__host__ __device__ __forceinline__ DeepNode deep_node(uint64_t w)
+{
+    int32_t kind, dx, dy, thr;
+    unpack_node(w, kind, dx, dy, thr);
+    DeepNode d;
+    d.x = ((uint32_t)(dx < 0 ? -dx : dx) << 1) | (dx < 0 ? 0x80000000u : 0u);
+    d.y = ((uint32_t)(dy < 0 ? -dy : dy) << 1) | (dy < 0 ? 0x80000000u : 0u);
+    d.thr = thr;
+    d.meta = 16u * (uint32_t)kind | ((kind & 2) ? 4u : 0u) << 6 | (kind ? 16u : 0u) << 9;
+    return d;
+}
+
+// probe_node of a DeepNode: the focal lengths (below 2^24, checked by the
+// host) scale 2 |dx| and 2 |dy| with 24-bit multiplies; the signs of dx Fx,
+// dy Fy are those of dx, dy. sh keeps the meta word: only its low 6 bits are
+// read.
+__device__ __forceinline__ ProbeNode probe_node_deep(const DeepNode &d, const Frame &fr)
+{
+    ProbeNode n;
+    n.ax = __umul24(d.x, (uint32_t)fr.Fx);
+    n.ay = __umul24(d.y, (uint32_t)fr.Fy);
+    n.sx = ((int32_t)d.x >> 31) | 1;
+    n.sy = ((int32_t)d.y >> 31) | 1;
+    n.thr = d.thr;
+    n.sh = d.meta;
+    n.half = __builtin_amdgcn_ubfe(d.meta, 6, 3);
+    n.wout = __builtin_amdgcn_ubfe(d.meta, 9, 5);
     return n;
 }
 
@@ -311,68 +371,90 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t packed_rsrc(const uint64_t *pa
     return __builtin_amdgcn_make_buffer_rsrc((void *)packed, (short)0, P * 8, 0x00020000);
 }
 
+// min(max(x, 0), hi) for hi >= 0, in one instruction
+__device__ __forceinline__ int32_t clamp0(int32_t x, int32_t hi)
+{
+    int32_t r;
+    asm("v_med3_i32 %0, %1, 0, %2" : "=v"(r) : "v"(x), "v"(hi));
+    return r;
+}
+
 // node_response_d of a prepared node, from the packed frame: `own` is the
 // pixel's own packed word. Branch-free: the probe position is clamped into
-// the image and one word is loaded; a depth probe whose position was clamped
-// reads 65535 instead.
+// the image and the field's 32-bit half is loaded; a depth probe whose
+// position was clamped reads its field with width 0, that is as "no depth".
+// The offsets stay below 2^23 and W, H below 2^24 (the host checks both), so
+// 24-bit multiplies place the probe.
 __device__ __forceinline__ int32_t probe_response(__amdgpu_buffer_rsrc_t packed, int W, int H, int u, int v,
                                                   uint64_t own, const PixelDen &pd, const ProbeNode &n)
 {
     const uint32_t ox = div_mag2(n.ax, pd), oy = div_mag2(n.ay, pd);
-    // signed offsets: s = 0 or -1 from the node's sign bits, u + (o ^ s) - s
-    const uint32_t sx = (uint32_t)((int32_t)(n.meta << 29) >> 31), sy = (uint32_t)((int32_t)(n.meta << 28) >> 31);
-    const int32_t qx = (int32_t)(((ox ^ sx) + (uint32_t)u) - sx);
-    const int32_t qy = (int32_t)(((oy ^ sy) + (uint32_t)v) - sy);
-    const int32_t cx = min(max(qx, 0), W - 1);
-    const int32_t cy = min(max(qy, 0), H - 1);
-    const uint64_t w = __builtin_bit_cast(uint64_t, __builtin_amdgcn_raw_buffer_load_b64(packed, (cy * W + cx) * 8, 0, 0));
-    const uint32_t sh = (n.meta >> 8) & 63u;
-    const uint32_t mask = (n.meta & 3u) ? 0xFFu : 0xFFFFu;
-    uint32_t val = (uint32_t)(w >> sh) & mask;
-    if ((n.meta & 3u) == 0u && (qx != cx || qy != cy)) val = 65535u;
-    return (int32_t)val - (int32_t)((uint32_t)(own >> sh) & mask);
+    const int32_t qx = __mul24((int32_t)ox, n.sx) + u;
+    const int32_t qy = __mul24((int32_t)oy, n.sy) + v;
+    const int32_t cx = clamp0(qx, W - 1), cy = clamp0(qy, H - 1);
+    const uint32_t at = ((uint32_t)__umul24((uint32_t)cy, (uint32_t)W) + (uint32_t)cx) * 8u + n.half;
+    const uint32_t word = __builtin_bit_cast(uint32_t, __builtin_amdgcn_raw_buffer_load_b32(packed, (int)at, 0, 0));
+    const uint32_t width = (qx != cx || qy != cy) ? n.wout : 16u;
+    const uint32_t probed = __builtin_amdgcn_ubfe(word, n.sh, width);
+    const uint32_t mine = (uint32_t)(own >> (n.sh & 63u)) & 0xFFFFu;
+    return (int32_t)mine - (int32_t)probed;
 }
 
 // Traversal of one tree for K pixels of a packed frame at once (their
 // chains of dependent probe loads interleave): every leaf of a complete tree
 // lies at the same depth, so the K node indices stay on one level. Pixel k is
 // p[k] with packed word own[k]; lanes whose pixel is invalid (ok[k] false)
-// walk with the smallest valid depth on a clamped position and get -1.
+// walk with the smallest valid depth on a clamped position and get -1. In
+// the prepared top levels a node is tracked by its byte offset (32 per node);
+// the levels below read the tree's DeepNodes.
 template <int K>
 __device__ __forceinline__ void traverse_packed_k(const ProbeNode *__restrict__ top, int32_t ntop,
-                                                  const uint64_t *__restrict__ tree, int32_t L, const Frame &fr,
+                                                  const DeepNode *__restrict__ tree, int32_t L, const Frame &fr,
                                                   const uint64_t *__restrict__ packed, const int p[K],
                                                   const uint64_t own[K], const bool ok[K], int32_t leaf[K])
 {
+    static_assert(sizeof(ProbeNode) == 32, "prepared nodes are 32 bytes");
     const __amdgpu_buffer_rsrc_t rs = packed_rsrc(packed, fr.W * fr.H);
     PixelDen pd[K];
     int u[K], v[K];
-    int32_t i[K];
+    uint32_t o[K];
 #pragma unroll
     for (int k = 0; k < K; ++k) {
         u[k] = p[k] % fr.W;
         v[k] = p[k] / fr.W;
-        pd[k] = pixel_den(fr, ok[k] ? (int32_t)(own[k] & 0xFFFFull) : fr.dmin);
-        i[k] = 0;
+        pd[k] = pixel_den(fr, ok[k] ? (int32_t)packed_depth(own[k]) : fr.dmin);
+        o[k] = 0;
     }
-    while (i[0] < ntop) {
+    const uint32_t otop = (uint32_t)ntop * 32u;
+    const char *tb = (const char *)top;
+    while (o[0] < otop) {
 #pragma unroll
         for (int k = 0; k < K; ++k) {
-            const ProbeNode n = top[i[k]];
+            const ProbeNode n = *(const ProbeNode *)__builtin_assume_aligned(tb + o[k], 32);
             const int32_t r = probe_response(rs, fr.W, fr.H, u[k], v[k], own[k], pd[k], n);
-            i[k] = 2 * i[k] + 1 + (r >= n.thr ? 1 : 0);
+            // child 2 i + 1 + (r >= thr) at byte offset 2 o + 32 + 32 (r >= thr)
+            o[k] = 2u * o[k] + (r >= n.thr ? 64u : 32u);
         }
     }
-    while (i[0] < L - 1) {
+    // below: byte offsets into the tree's DeepNodes (16 per node), read
+    // through a buffer resource over its (L - 1) 16 bytes (below 2^20)
+    const __amdgpu_buffer_rsrc_t ts = __builtin_amdgcn_make_buffer_rsrc((void *)tree, (short)0, (L - 1) * 16,
+                                                                        0x00020000);
+    const uint32_t oend = (uint32_t)(L - 1) * 16u;
+#pragma unroll
+    for (int k = 0; k < K; ++k) o[k] >>= 1;
+    while (o[0] < oend) {
 #pragma unroll
         for (int k = 0; k < K; ++k) {
-            const ProbeNode n = probe_node(tree[i[k]], fr);
+            const DeepNode d =
+                __builtin_bit_cast(DeepNode, __builtin_amdgcn_raw_buffer_load_b128(ts, (int)o[k], 0, 0));
+            const ProbeNode n = probe_node_deep(d, fr);
             const int32_t r = probe_response(rs, fr.W, fr.H, u[k], v[k], own[k], pd[k], n);
-            i[k] = 2 * i[k] + 1 + (r >= n.thr ? 1 : 0);
+            o[k] = 2u * o[k] + (r >= n.thr ? 32u : 16u);
         }
     }
 #pragma unroll
-    for (int k = 0; k < K; ++k) leaf[k] = ok[k] ? i[k] - (L - 1) : -1;
+    for (int k = 0; k < K; ++k) leaf[k] = ok[k] ? (int32_t)(o[k] >> 4) - (L - 1) : -1;
 }
 
 
@@ -644,6 +726,7 @@ struct Forest {
     int device;
     // forest state
     uint64_t *nodes = nullptr;     // [T][L-1] then 8 extra
+    DeepNode *deep = nullptr;      // [T][L-1] the split nodes as deep traversal levels read them
     uint32_t *counter = nullptr;   // [T][L]
     uint32_t *base = nullptr;      // [T][L]
     Entry *res = nullptr;          // [T][L][R]
@@ -680,6 +763,7 @@ struct Attempt {
     Frame fr;
     // the target forest (read-only here)
     const uint64_t *nodes;
+    const DeepNode *deep;
     const int32_t *nmodes;
     const Mode *modes;
     const uint32_t *mode_rgb;

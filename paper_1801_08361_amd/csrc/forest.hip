@@ -59,20 +59,29 @@ static int params_check(const reloc_params *p)
 
 static int32_t focal16(float f) { return (int32_t)floor((double)f * 16.0 + 0.5); }
 
-// intrinsics valid, and |offset| * F fits 32 bits (so features stay exact)
+// intrinsics valid, width, height and the focal lengths F in 1/16 px below
+// 2^24, and |offset| * F fits 32 bits (so features stay exact)
 static int frame_of(const Forest *f, const uint16_t *depth, const uint8_t *rgb, const reloc_intrinsics *K,
                     Frame &fr)
 {
     if (!depth || !rgb || !K) return RELOC_E_ARG;
-    if (K->width < 1 || K->height < 1 || (int64_t)K->width * K->height > (1 << 26)) return RELOC_E_ARG;
+    if (K->width < 1 || K->height < 1 || (int64_t)K->width * K->height > (1 << 26) || K->width >= (1 << 24) ||
+        K->height >= (1 << 24))
+        return RELOC_E_ARG;
     if (!(K->fx > 0.0f) || !(K->fy > 0.0f) || !isfinite(K->cx) || !isfinite(K->cy) || !isfinite(K->fx) ||
         !isfinite(K->fy))
         return RELOC_E_ARG;
     fr.depth = depth; fr.rgb = rgb; fr.W = K->width; fr.H = K->height;
     fr.fx = K->fx; fr.fy = K->fy; fr.cx = K->cx; fr.cy = K->cy;
+    if (!(K->fx < 1048576.0f) || !(K->fy < 1048576.0f)) return RELOC_E_ARG;
     int64_t Fx = focal16(K->fx), Fy = focal16(K->fy);
     if ((int64_t)f->p.offset_pxmm * Fx > 2147483647LL || (int64_t)f->p.offset_pxmm * Fy > 2147483647LL)
         return RELOC_E_ARG;
+    // and every probe offset, at most |offset| * F / (d_min * F_ref) pixels,
+    // stays below 2^23
+    const int64_t den23 = ((int64_t)f->p.depth_min_mm * f->p.f_ref_px16) << 23;
+    if ((int64_t)f->p.offset_pxmm * Fx >= den23 || (int64_t)f->p.offset_pxmm * Fy >= den23) return RELOC_E_ARG;
+    if (Fx >= (1 << 24) || Fy >= (1 << 24)) return RELOC_E_ARG;
     fr.Fx = (int32_t)Fx; fr.Fy = (int32_t)Fy;
     fr.dmin = f->p.depth_min_mm; fr.dmax = f->p.depth_max_mm; fr.Fref = f->p.f_ref_px16;
     return RELOC_OK;
@@ -121,7 +130,8 @@ static void dfree(Forest *f, T **ptr, size_t count)
 // kernels: node generation
 // ---------------------------------------------------------------------------
 
-__global__ void k_gen_nodes(uint64_t *nodes, int T, int L, uint64_t seed, int32_t O, int32_t thr_d, int32_t thr_c)
+__global__ void k_gen_nodes(uint64_t *nodes, DeepNode *deep, int T, int L, uint64_t seed, int32_t O, int32_t thr_d,
+                            int32_t thr_c)
 {
     int64_t n_split = (int64_t)T * (L - 1);
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -143,6 +153,7 @@ __global__ void k_gen_nodes(uint64_t *nodes, int T, int L, uint64_t seed, int32_
     int32_t Tk = kind == 0 ? thr_d : thr_c;
     int32_t thr = (int32_t)((int64_t)uniform_int(u.x[3], (uint64_t)(2 * (int64_t)Tk + 1)) - Tk);
     nodes[i] = pack_node(kind, dx, dy, thr);
+    if (i < n_split) deep[i] = deep_node(nodes[i]);
 }
 
 // ---------------------------------------------------------------------------
@@ -161,8 +172,9 @@ __global__ void __launch_bounds__(256) k_pack(Frame fr, uint64_t *__restrict__ p
 // the tree together (tid, tid + 256, ...)
 constexpr int LEAF_PIX = 4;
 
-__global__ void __launch_bounds__(256) k_leaves(const uint64_t *__restrict__ nodes, int T, int L, Frame fr,
-                                                const uint64_t *__restrict__ packed, int32_t *__restrict__ leaves)
+__global__ void __launch_bounds__(256) k_leaves(const uint64_t *__restrict__ nodes, const DeepNode *__restrict__ deep,
+                                                int T, int L, Frame fr, const uint64_t *__restrict__ packed,
+                                                int32_t *__restrict__ leaves)
 {
     __shared__ ProbeNode top[TOP_NODES];
     const int P = fr.W * fr.H;
@@ -184,7 +196,7 @@ __global__ void __launch_bounds__(256) k_leaves(const uint64_t *__restrict__ nod
         ok[k] = q < P && packed_valid(own[k]);
     }
     int32_t leaf[LEAF_PIX];
-    traverse_packed_k<LEAF_PIX>(top, ntop, tree, L, fr, packed, p, own, ok, leaf);
+    traverse_packed_k<LEAF_PIX>(top, ntop, deep + (int64_t)t * (L - 1), L, fr, packed, p, own, ok, leaf);
 #pragma unroll
     for (int k = 0; k < LEAF_PIX; ++k)
         if (base + k * 256 < P) leaves[(int64_t)t * P + base + k * 256] = leaf[k];
@@ -658,8 +670,7 @@ int traverse_frame(Forest *f, const Frame &fr, hipStream_t s)
     if (rc) return rc;
     RL_LAUNCH("k_pack", k_pack, dim3((unsigned)((P + 255) / 256)), dim3(256), 0, s, fr, f->packed);
     RL_LAUNCH("k_leaves", k_leaves, dim3((unsigned)((P + LEAF_PIX * 256 - 1) / (LEAF_PIX * 256)), (unsigned)f->T),
-              dim3(256), 0, s, f->nodes,
-              f->T, f->L, fr, f->packed, f->leaves);
+              dim3(256), 0, s, f->nodes, f->deep, f->T, f->L, fr, f->packed, f->leaves);
     RL_HIP(hipGetLastError());
     return RELOC_OK;
 }
@@ -705,6 +716,7 @@ static void forest_free(Forest *f)
     int64_t C = (f->cap_P + CHUNK - 1) / CHUNK;
     size_t TL = (size_t)f->T * f->L;
     dfree(f, &f->nodes, (size_t)f->T * (f->L - 1) + 8);
+    dfree(f, &f->deep, (size_t)f->T * (f->L - 1));
     dfree(f, &f->counter, TL);
     dfree(f, &f->base, TL);
     dfree(f, &f->res, TL * f->R);
@@ -741,6 +753,7 @@ extern "C" int reloc_forest_create(const reloc_params *p, void *stream, reloc_fo
     size_t TL = (size_t)f->T * f->L;
     rc = RELOC_OK;
     rc |= dalloc(f, &f->nodes, (size_t)f->T * (f->L - 1) + 8, s);
+    rc |= dalloc(f, &f->deep, (size_t)f->T * (f->L - 1), s);
     rc |= dalloc(f, &f->counter, TL, s);
     rc |= dalloc(f, &f->base, TL, s);
     rc |= dalloc(f, &f->res, TL * f->R, s);
@@ -772,7 +785,7 @@ extern "C" int reloc_forest_create(const reloc_params *p, void *stream, reloc_fo
         return RELOC_E_HIP;
     }
     int64_t nn = (int64_t)f->T * (f->L - 1) + 8;
-    RL_LAUNCH("k_gen_nodes", k_gen_nodes, dim3((unsigned)((nn + 255) / 256)), dim3(256), 0, s, f->nodes, f->T, f->L,
+    RL_LAUNCH("k_gen_nodes", k_gen_nodes, dim3((unsigned)((nn + 255) / 256)), dim3(256), 0, s, f->nodes, f->deep, f->T, f->L,
                        p->seed, p->offset_pxmm, p->thr_depth_mm, p->thr_rgb);
     if (hipGetLastError() != hipSuccess) {
         forest_free(f);
@@ -895,9 +908,18 @@ extern "C" int reloc_debug_set_nodes(reloc_forest *f, const int32_t *kind, const
         }
         h[i] = pack_node(kind[i], dx[i], dy[i], thr[i]);
     }
+    const size_t ns = (size_t)f->T * (f->L - 1);
+    DeepNode *hd = (DeepNode *)malloc(ns * sizeof(DeepNode));
+    if (!hd) {
+        free(h);
+        return RELOC_E_NOMEM;
+    }
+    for (size_t i = 0; i < ns; ++i) hd[i] = deep_node(h[i]);
     int rc = RELOC_OK;
-    if (hipDeviceSynchronize() != hipSuccess || hipMemcpy(f->nodes, h, n * 8, hipMemcpyHostToDevice) != hipSuccess)
+    if (hipDeviceSynchronize() != hipSuccess || hipMemcpy(f->nodes, h, n * 8, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(f->deep, hd, ns * sizeof(DeepNode), hipMemcpyHostToDevice) != hipSuccess)
         rc = RELOC_E_HIP;
+    free(hd);
     free(h);
     return rc;
 }

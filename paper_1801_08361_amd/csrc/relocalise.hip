@@ -103,7 +103,8 @@ __global__ void __launch_bounds__(PIX_BLOCK) k_b_leaves(const Attempt *__restric
             ok[k] = q < A.P && packed_valid(own[k]);
         }
         int32_t leaf[PIX_PER_THREAD];
-        traverse_packed_k<PIX_PER_THREAD>(top, ntop, tree, A.L, fr, A.packed, p, own, ok, leaf);
+        traverse_packed_k<PIX_PER_THREAD>(top, ntop, A.deep + (int64_t)t * (A.L - 1), A.L, fr, A.packed, p, own,
+                                          ok, leaf);
 #pragma unroll
         for (int k = 0; k < PIX_PER_THREAD; ++k)
             if (base + k * PIX_BLOCK < A.P) A.leaves[(int64_t)t * A.P + base + k * PIX_BLOCK] = leaf[k];
@@ -140,7 +141,7 @@ __global__ void __launch_bounds__(64, 4) k_b_weights(const Attempt *__restrict__
             const uint64_t own = A.packed[p];
             ok = packed_valid(own);
             if (ok)
-                pixel_inputs(F, p % A.fr.W, p / A.fr.W, (uint32_t)(own & 0xFFFFull),
+                pixel_inputs(F, p % A.fr.W, p / A.fr.W, packed_depth(own),
                              [&](int t) { return A.leaves[(int64_t)t * A.P + p]; }, x);
         }
         __syncthreads();   // the previous unit's tile is no longer read
@@ -419,10 +420,10 @@ __device__ bool try_hypothesis(const Attempt &A, int np, uint64_t h, uint64_t ta
 #pragma unroll
     for (int j = 0; j < 3; ++j) {
         const uint64_t pw = A.packed[p[j]];   // pool pixels are valid: the word holds their depth
-        dep[j] = (uint32_t)(pw & 0xFFFFull);
-        pr[j] = (uint32_t)(pw >> 16) & 255u;
-        pg[j] = (uint32_t)(pw >> 24) & 255u;
-        pb[j] = (uint32_t)(pw >> 32) & 255u;
+        dep[j] = packed_depth(pw);
+        pr[j] = packed_colour(pw, 0);
+        pg[j] = packed_colour(pw, 1);
+        pb[j] = packed_colour(pw, 2);
     }
     int64_t pick[3];
     float c[3][3], w[3][3];
@@ -522,7 +523,7 @@ __global__ void __launch_bounds__(64) k_b_hypgen(const Attempt *__restrict__ att
                 const U4 x = philox((uint64_t)rr, (uint64_t)i, 0, 0, A.seed, TAG_PIX);
                 const int p = A.pool[uniform_int(x.x[0], (uint64_t)np)];
                 float c[3];
-                cam_point(A.fr, p % A.fr.W, p / A.fr.W, (uint32_t)(A.packed[p] & 0xFFFFull), c);
+                cam_point(A.fr, p % A.fr.W, p / A.fr.W, packed_depth(A.packed[p]), c);
                 A.draws[gi] = make_float4(c[0], c[1], c[2], __int_as_float(p));
                 for (int t = 0; t < A.T; ++t) {
                     const int li = t * A.L + A.leaves[(int64_t)t * A.P + p];
@@ -1472,6 +1473,7 @@ static int run_batch(reloc_batch *b, const reloc_attempt *att, int n, hipStream_
         Attempt A = pl->slices[a];
         A.fr = frames[a];
         A.nodes = f->nodes;
+        A.deep = f->deep;
         A.nmodes = f->nmodes;
         A.modes = f->modes;
         A.mode_rgb = f->mode_rgb;
