@@ -40,7 +40,6 @@ int update_modes(Forest *f, hipStream_t s);
 int frame_from(const Forest *f, const uint16_t *depth, const uint8_t *rgb, const reloc_intrinsics *K, Frame &fr);
 
 constexpr int PIX_BLOCK = 256;
-constexpr int PIX_PER_THREAD = 4;   // pixels traversed together by one thread
 constexpr int POOL_BLOCK = 1024;
 
 __device__ __forceinline__ uint64_t lanemask_lt() { return (1ull << __lane_id()) - 1ull; }
@@ -62,13 +61,16 @@ __device__ __forceinline__ bool round_active(const Attempt &A, int r)
 // features and traversal of every pixel
 // ---------------------------------------------------------------------------
 
-// unit = (tree, block of PIX_PER_THREAD x PIX_BLOCK pixels): each thread
-// walks PIX_PER_THREAD pixels of one tree together (pixels tid, tid +
-// PIX_BLOCK, ...), so that several chains of dependent probe loads are in
-// flight per thread and the trees' units run side by side
+// unit = (tree, block of K x PIX_BLOCK pixels): each thread walks K pixels of
+// one tree together (pixels tid, tid + PIX_BLOCK, ...), so that several
+// chains of dependent probe loads are in flight per thread and the trees'
+// units run side by side. K = 4 keeps a single frame's units numerous enough
+// to fill the chip; K = 8 (more chains per wavefront, fewer wavefronts) suits
+// large batches.
 // The workgroup keeps the top levels of its unit's tree in LDS, scaled for
 // the attempt's frame (restaged only when the (attempt, tree) pair changes
 // between its units).
+template <int K>
 __global__ void __launch_bounds__(PIX_BLOCK) k_b_leaves(const Attempt *__restrict__ att, Stage S)
 {
     __shared__ ProbeNode top[TOP_NODES];
@@ -76,7 +78,7 @@ __global__ void __launch_bounds__(PIX_BLOCK) k_b_leaves(const Attempt *__restric
     FOR_UNITS(S, u) {
         const int a = attempt_of(S, u);
         const Attempt &A = att[a];
-        constexpr int PU = PIX_PER_THREAD * PIX_BLOCK;
+        constexpr int PU = K * PIX_BLOCK;
         const int nb = (A.P + PU - 1) / PU;
         const int local = u - S.off[a];
         const int t = local / nb;
@@ -92,21 +94,21 @@ __global__ void __launch_bounds__(PIX_BLOCK) k_b_leaves(const Attempt *__restric
         }
         const int base = (local % nb) * PU + (int)threadIdx.x;
         if (base >= A.P) continue;
-        int p[PIX_PER_THREAD];
-        uint64_t own[PIX_PER_THREAD];
-        bool ok[PIX_PER_THREAD];
+        int p[K];
+        uint64_t own[K];
+        bool ok[K];
 #pragma unroll
-        for (int k = 0; k < PIX_PER_THREAD; ++k) {
+        for (int k = 0; k < K; ++k) {
             const int q = base + k * PIX_BLOCK;
             p[k] = q < A.P ? q : A.P - 1;
             own[k] = A.packed[p[k]];
             ok[k] = q < A.P && packed_valid(own[k]);
         }
-        int32_t leaf[PIX_PER_THREAD];
-        traverse_packed_k<PIX_PER_THREAD>(top, ntop, A.deep + (int64_t)t * (A.L - 1), A.L, fr, A.packed, p, own,
+        int32_t leaf[K];
+        traverse_packed_k<K>(top, ntop, A.deep + (int64_t)t * (A.L - 1), A.L, fr, A.packed, p, own,
                                           ok, leaf);
 #pragma unroll
-        for (int k = 0; k < PIX_PER_THREAD; ++k)
+        for (int k = 0; k < K; ++k)
             if (base + k * PIX_BLOCK < A.P) A.leaves[(int64_t)t * A.P + base + k * PIX_BLOCK] = leaf[k];
     }
 }
@@ -1044,6 +1046,7 @@ struct Sched {
     int dpu;         // draws per scoring unit, a multiple of GROUP
     int grid;        // persistent grid of the scoring kernel (0: one workgroup per unit)
     int xcd;         // XCD-contiguous unit order
+    int pix;         // pixels per traversal thread (4 or 8)
 };
 
 struct Shape {
@@ -1070,7 +1073,7 @@ struct Plan {
     // traversal when no attempt computes learned weights in the batch
     hipStream_t side = nullptr;
     hipEvent_t fork = nullptr, join = nullptr;
-    Sched sched{GROUP, 0, 0};
+    Sched sched{GROUP, 0, 0, 4};
     std::string desc;
     uint64_t last_use = 0;
 };
@@ -1166,7 +1169,7 @@ static std::vector<int32_t> offsets(const Plan *pl, const Sched &sc)
     };
     auto P = [&](int a) { return (int64_t)pl->shape[a].W * pl->shape[a].H; };
     fill(0, [&](int a) {
-        return pl->shape[a].T * (int)((P(a) + PIX_PER_THREAD * PIX_BLOCK - 1) / (PIX_PER_THREAD * PIX_BLOCK));
+        return pl->shape[a].T * (int)((P(a) + sc.pix * PIX_BLOCK - 1) / (sc.pix * PIX_BLOCK));
     });
     fill(1, [&](int a) { return (int)((P(a) + POOL_BLOCK - 1) / POOL_BLOCK); });
     fill(2, [&](int) { return 1; });
@@ -1217,6 +1220,14 @@ static unsigned grid_of(const Stage &s, int cap, int xcd)
     return (unsigned)g;
 }
 
+static void launch_leaves(const Sched &sc, const Stages &st, int cap, const Attempt *d, hipStream_t s)
+{
+    if (sc.pix == 8)
+        RL_LAUNCH("k_b_leaves", k_b_leaves<8>, dim3(grid_of(st.pix, cap, sc.xcd)), dim3(PIX_BLOCK), 0, s, d, st.pix);
+    else
+        RL_LAUNCH("k_b_leaves", k_b_leaves<4>, dim3(grid_of(st.pix, cap, sc.xcd)), dim3(PIX_BLOCK), 0, s, d, st.pix);
+}
+
 // enqueues every kernel of the batch on `s`
 static int enqueue(const Plan *pl, const Sched &sc, const Stages &st, hipStream_t s)
 {
@@ -1228,7 +1239,7 @@ static int enqueue(const Plan *pl, const Sched &sc, const Stages &st, hipStream_
     RL_LAUNCH("k_b_pack", k_b_pack, dim3(grid_of(st.pb, cap, sc.xcd)), dim3(POOL_BLOCK), 0, s, d, st.pb);
     if (st.wts.total > 0) {
         // learned weights feed the pool's weight prefix: one chain
-        RL_LAUNCH("k_b_leaves", k_b_leaves, dim3(grid_of(st.pix, cap, sc.xcd)), dim3(PIX_BLOCK), 0, s, d, st.pix);
+        launch_leaves(sc, st, cap, d, s);
         RL_LAUNCH("k_b_weights", k_b_weights, dim3(grid_of(st.wts, cap, sc.xcd)), dim3(64), 0, s, d, st.wts);
         RL_LAUNCH("k_b_pool_scan", k_b_pool_scan, dim3(grid_of(att, cap, 0)), dim3(1024), 0, s, d, att);
         RL_LAUNCH("k_b_pool_write", k_b_pool_write, dim3(grid_of(st.pb, cap, sc.xcd)), dim3(POOL_BLOCK), 0, s, d,
@@ -1242,7 +1253,7 @@ static int enqueue(const Plan *pl, const Sched &sc, const Stages &st, hipStream_
         RL_LAUNCH("k_b_pool_write", k_b_pool_write, dim3(grid_of(st.pb, cap, sc.xcd)), dim3(POOL_BLOCK), 0,
                   pl->side, d, st.pb);
         RL_HIP(hipEventRecord(pl->join, pl->side));
-        RL_LAUNCH("k_b_leaves", k_b_leaves, dim3(grid_of(st.pix, cap, sc.xcd)), dim3(PIX_BLOCK), 0, s, d, st.pix);
+        launch_leaves(sc, st, cap, d, s);
         RL_HIP(hipStreamWaitEvent(s, pl->join, 0));
     }
     RL_LAUNCH("k_b_hypgen", k_b_hypgen, dim3(grid_of(st.hyp, 0, sc.xcd)), dim3(64), 0, s, d, st.hyp);
@@ -1307,9 +1318,11 @@ static std::string sched_desc(const Sched &s)
 {
     char buf[160];
     if (s.grid)
-        snprintf(buf, sizeof(buf), "draws_per_unit=%d score_grid=%d xcd_contiguous=%d", s.dpu, s.grid, s.xcd);
+        snprintf(buf, sizeof(buf), "draws_per_unit=%d score_grid=%d xcd_contiguous=%d pix_per_thread=%d", s.dpu,
+                 s.grid, s.xcd, s.pix);
     else
-        snprintf(buf, sizeof(buf), "draws_per_unit=%d score_grid=per-unit xcd_contiguous=%d", s.dpu, s.xcd);
+        snprintf(buf, sizeof(buf), "draws_per_unit=%d score_grid=per-unit xcd_contiguous=%d pix_per_thread=%d",
+                 s.dpu, s.xcd, s.pix);
     return buf;
 }
 
@@ -1327,14 +1340,20 @@ static int run_plan(Plan *pl, hipStream_t s)
 
 static int tune(reloc_batch *b, Plan *pl, hipStream_t s)
 {
+    // traversal work of the batch (pixels x trees): 8 pixels per thread from
+    // about five full-size frames of five trees on, where the units still
+    // fill the chip several times over
+    int64_t work = 0;
+    for (const Shape &sh : pl->shape) work += (int64_t)sh.W * sh.H * sh.T;
+    const int pix = work >= 8000000 ? 8 : 4;
     std::vector<Sched> cands;
-    cands.push_back({GROUP, 0, 0});
+    cands.push_back({GROUP, 0, 0, pix});
     if (b->tune) {
-        cands.push_back({GROUP, 0, 1});
-        cands.push_back({2 * GROUP, 0, 1});
-        cands.push_back({4 * GROUP, 0, 1});
-        cands.push_back({GROUP, 2048, 1});
-        cands.push_back({2 * GROUP, 1024, 1});
+        cands.push_back({GROUP, 0, 1, pix});
+        cands.push_back({2 * GROUP, 0, 1, pix});
+        cands.push_back({4 * GROUP, 0, 1, pix});
+        cands.push_back({GROUP, 2048, 1, pix});
+        cands.push_back({2 * GROUP, 1024, 1, pix});
     }
     hipEvent_t e0 = nullptr, e1 = nullptr;
     RL_HIP(hipEventCreate(&e0));
