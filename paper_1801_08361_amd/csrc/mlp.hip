@@ -366,7 +366,7 @@ __global__ void __launch_bounds__(64) k_mlp_pixels(FeatArgs A, const uint16_t *_
     if (p < P) pixel_features(A, p, x);
     else
         for (int k = 0; k < 24; ++k) x[k] = 0.0f;
-    store_row(S, x);
+    store_row(S.X, x);
     stage_head(S, q, w);
     __syncthreads();
     const float zl = tile_forward_regs(S, q, w);

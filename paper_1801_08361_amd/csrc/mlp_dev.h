@@ -127,35 +127,41 @@ __device__ void tile_forward(Tile &S, const uint16_t *__restrict__ q, const floa
     __syncthreads();
 }
 
+// Layer 1's A operand for hidden rows 16 tj .. + 15 as lane l supplies it:
+// row 16 tj + (l & 15) of W1 (bfloat16, [64][32]), k-block 8 (l >> 4) .. + 7.
+__device__ __forceinline__ bf16x8 w1_operand(const uint16_t *__restrict__ q, int tj, int l)
+{
+    return load8(q + QW1 + (16 * tj + (l & 15)) * 32 + 8 * (l >> 4));
+}
+
+// Layer 2's A operand for hidden rows 16 tk .. + 15 and k-chunk c as lane l
+// supplies it: row 16 tk + (l & 15) of W2, k-slot s of lane group g = l >> 4
+// standing for hidden unit 32 c + 16 (s >> 2) + 4 g + (s & 3)
+__device__ __forceinline__ bf16x8 w2_operand(const uint16_t *__restrict__ q, int tk, int c, int l)
+{
+    const uint16_t *row = q + QW2 + (16 * tk + (l & 15)) * 64 + 32 * c + 4 * (l >> 4);
+    const uint2 lo = *(const uint2 *)row;          // hidden 32 c + 4 g .. + 3
+    const uint2 hi = *(const uint2 *)(row + 16);   // hidden 32 c + 16 + 4 g .. + 3
+    return __builtin_bit_cast(bf16x8, make_uint4(lo.x, lo.y, hi.x, hi.y));
+}
+
 // Forward pass of a 64-row tile for inference, with the activations kept in
 // registers. Row i's 32 inputs (bfloat16: 24 and 8 zeros) are X[32 i ..]
-// (LDS); returns the logit of row `lane`. The layers are computed transposed
-// (hidden units x rows), 16 rows at a time: layer 1 leaves lane l holding row
-// (l & 15) and hidden units 16 tj + 4 (l >> 4) + i (tj, i < 4), which are the
-// 8 + 8 k-values that layer 2's B operand needs from that lane for its two
-// 32-wide k-chunks, once W2's columns are taken in the same order: k-slot s of
-// lane group g in chunk c stands for hidden unit 32 c + 16 (s >> 2) + 4 g +
-// (s & 3) in both operands (an MFMA sums the same products whatever the slot
-// order). H1 and H2 are rounded to bfloat16 (nearest even, by the conversion
-// instruction) after bias and ReLU as in tile_forward; the output dot w3 . h2
-// is summed per lane over its 16 hidden units, then over the four lane groups.
-__device__ __forceinline__ float tile_forward_regs(const InTile &S, const uint16_t *__restrict__ q,
-                                                   const float *__restrict__ w)
+// (LDS); a1, a2 are the lane's weight operands (w1_operand, w2_operand);
+// returns the logit of row `lane` without the output bias. The layers are
+// computed transposed (hidden units x rows), 16 rows at a time: layer 1
+// leaves lane l holding row (l & 15) and hidden units 16 tj + 4 (l >> 4) + i
+// (tj, i < 4), which are the 8 + 8 k-values that layer 2's B operand needs
+// from that lane for its two 32-wide k-chunks, once W2's columns are taken in
+// the same order (w2_operand; an MFMA sums the same products whatever the
+// slot order). H1 and H2 are rounded to bfloat16 (nearest even, by the
+// conversion instruction) after bias and ReLU as in tile_forward; the output
+// dot w3 . h2 is summed per lane over its 16 hidden units, then over the four
+// lane groups.
+__device__ __forceinline__ float tile_forward_core(const uint16_t *X, const bf16x8 a1[4], const bf16x8 a2[4][2],
+                                                   const float *b1, const float *b2, const float *w3)
 {
-    const uint16_t *X = S.X;
     const int l = __lane_id(), col = l & 15, g = l >> 4;
-    bf16x8 a1[4], a2[4][2];
-#pragma unroll
-    for (int tj = 0; tj < 4; ++tj) a1[tj] = load8(q + QW1 + (16 * tj + col) * 32 + 8 * g);
-#pragma unroll
-    for (int tk = 0; tk < 4; ++tk)
-#pragma unroll
-        for (int c = 0; c < 2; ++c) {
-            const uint16_t *row = q + QW2 + (16 * tk + col) * 64 + 32 * c + 4 * g;
-            const uint2 lo = *(const uint2 *)row;          // hidden 32 c + 4 g .. + 3
-            const uint2 hi = *(const uint2 *)(row + 16);   // hidden 32 c + 16 + 4 g .. + 3
-            a2[tk][c] = __builtin_bit_cast(bf16x8, make_uint4(lo.x, lo.y, hi.x, hi.y));
-        }
     float zrow = 0.0f;
 #pragma unroll 1
     for (int ti = 0; ti < 4; ++ti) {
@@ -165,7 +171,7 @@ __device__ __forceinline__ float tile_forward_regs(const InTile &S, const uint16
         for (int tj = 0; tj < 4; ++tj) {
             floatx4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
             acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1[tj], xb, acc, 0, 0, 0);
-            const float4 bb = *(const float4 *)(S.b1 + 16 * tj + 4 * g);
+            const float4 bb = *(const float4 *)(b1 + 16 * tj + 4 * g);
             float hv[4] = {acc[0] + bb.x, acc[1] + bb.y, acc[2] + bb.z, acc[3] + bb.w};
 #pragma unroll
             for (int i = 0; i < 4; ++i) hv[i] = hv[i] > 0.0f ? hv[i] : 0.0f;
@@ -180,14 +186,14 @@ __device__ __forceinline__ float tile_forward_regs(const InTile &S, const uint16
             floatx4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
             acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a2[tk][0], b2lo, acc, 0, 0, 0);
             acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a2[tk][1], b2hi, acc, 0, 0, 0);
-            const float4 bb = *(const float4 *)(S.b2 + 16 * tk + 4 * g);
+            const float4 bb = *(const float4 *)(b2 + 16 * tk + 4 * g);
             float hv[4] = {acc[0] + bb.x, acc[1] + bb.y, acc[2] + bb.z, acc[3] + bb.w};
 #pragma unroll
             for (int i = 0; i < 4; ++i) hv[i] = hv[i] > 0.0f ? hv[i] : 0.0f;
             const uint32_t p01 = bf16_pair(hv[0], hv[1]), p23 = bf16_pair(hv[2], hv[3]);
             const float h2[4] = {__uint_as_float(p01 << 16), __uint_as_float(p01 & 0xFFFF0000u),
                                  __uint_as_float(p23 << 16), __uint_as_float(p23 & 0xFFFF0000u)};
-            const float4 ww = *(const float4 *)(S.w3 + 16 * tk + 4 * g);
+            const float4 ww = *(const float4 *)(w3 + 16 * tk + 4 * g);
             z = fmaf(ww.x, h2[0], z);
             z = fmaf(ww.y, h2[1], z);
             z = fmaf(ww.z, h2[2], z);
@@ -197,7 +203,62 @@ __device__ __forceinline__ float tile_forward_regs(const InTile &S, const uint16
         z = z + __shfl_xor(z, 32, 64);
         if (ti == g) zrow = z;   // lane 16 g + col is row 16 ti + col
     }
-    return zrow + w[OB3];
+    return zrow;
+}
+
+// tile_forward_core with the weight operands loaded from the network's
+// bfloat16 copy and the head from S
+__device__ __forceinline__ float tile_forward_regs(const InTile &S, const uint16_t *__restrict__ q,
+                                                   const float *__restrict__ w)
+{
+    const int l = __lane_id();
+    bf16x8 a1[4], a2[4][2];
+#pragma unroll
+    for (int tj = 0; tj < 4; ++tj) a1[tj] = w1_operand(q, tj, l);
+#pragma unroll
+    for (int tk = 0; tk < 4; ++tk)
+#pragma unroll
+        for (int c = 0; c < 2; ++c) a2[tk][c] = w2_operand(q, tk, c, l);
+    return tile_forward_core(S.X, a1, a2, S.b1, S.b2, S.w3) + w[OB3];
+}
+
+// The network as inference tiles read it, staged once per workgroup in LDS:
+// every lane's weight operands (w1_operand, w2_operand) in lane order, the
+// biases, the output weights (from their bfloat16 copy) and the output bias.
+struct __align__(16) WTile {
+    bf16x8 a1[4][64];
+    bf16x8 a2[4][2][64];
+    float b1[64], b2[64], w3[64];
+    float b3;
+};
+
+// every thread of the workgroup takes part; a barrier must follow
+__device__ __forceinline__ void stage_weights(WTile &W, const uint16_t *__restrict__ q, const float *__restrict__ w)
+{
+    for (int k = threadIdx.x; k < 4 * 64; k += blockDim.x) W.a1[k >> 6][k & 63] = w1_operand(q, k >> 6, k & 63);
+    for (int k = threadIdx.x; k < 8 * 64; k += blockDim.x)
+        W.a2[k >> 7][(k >> 6) & 1][k & 63] = w2_operand(q, k >> 7, (k >> 6) & 1, k & 63);
+    for (int k = threadIdx.x; k < 64; k += blockDim.x) {
+        W.b1[k] = w[OB1 + k];
+        W.b2[k] = w[OB2 + k];
+        W.w3[k] = bf2f(q[QW3 + k]);
+    }
+    if (threadIdx.x == 0) W.b3 = w[OB3];
+}
+
+// tile_forward_regs with the weights from a staged WTile (the same operands,
+// so the same logits)
+__device__ __forceinline__ float tile_forward_staged(const uint16_t *X, const WTile &W)
+{
+    const int l = __lane_id();
+    bf16x8 a1[4], a2[4][2];
+#pragma unroll
+    for (int tj = 0; tj < 4; ++tj) a1[tj] = W.a1[tj][l];
+#pragma unroll
+    for (int tk = 0; tk < 4; ++tk)
+#pragma unroll
+        for (int c = 0; c < 2; ++c) a2[tk][c] = W.a2[tk][c][l];
+    return tile_forward_core(X, a1, a2, W.b1, W.b2, W.w3) + W.b3;
 }
 
 // what the per-pixel inputs need from a forest and a frame
@@ -293,11 +354,12 @@ __device__ __forceinline__ void pixel_features(const FeatArgs &A, int p, float x
                  x);
 }
 
-// lane l's inputs as row l of the tile (bfloat16, 8 zeros of padding)
-__device__ __forceinline__ void store_row(InTile &S, const float x[24])
+// lane l's inputs as row l of a tile's inputs X (bfloat16, 8 zeros of
+// padding)
+__device__ __forceinline__ void store_row(uint16_t *X, const float x[24])
 {
     const int l = __lane_id();
-    uint4 *row = (uint4 *)(S.X + l * 32);
+    uint4 *row = (uint4 *)(X + l * 32);
 #pragma unroll
     for (int k = 0; k < 3; ++k)
         row[k] = make_uint4(bf16_pair(x[8 * k], x[8 * k + 1]), bf16_pair(x[8 * k + 2], x[8 * k + 3]),

@@ -114,20 +114,33 @@ __global__ void __launch_bounds__(PIX_BLOCK) k_b_leaves(const Attempt *__restric
 }
 
 // Learned pick weights from the attempt's own leaves (attempts with a
-// proposal network only): one wavefront per 64 pixels, the 24 inputs of each
-// valid pixel, the network's forward pass on the matrix cores, and
-// floor(sigmoid 65536) + 1 (0 for an invalid pixel), exactly as the
-// stand-alone weight kernel computes them after its own traversal.
-// (at least 4 wavefronts per SIMD: the kernel waits on gathers most of the
-// time, and 4 resident wavefronts with a few spilled registers beat 3 without)
-__global__ void __launch_bounds__(64, 4) k_b_weights(const Attempt *__restrict__ att, Stage S)
+// proposal network only): a unit is WT_WAVES tiles of 64 pixels, one per
+// wavefront; the 24 inputs of each valid pixel, the network's forward pass on
+// the matrix cores, and floor(sigmoid 65536) + 1 (0 for an invalid pixel),
+// exactly as the stand-alone weight kernel computes them after its own
+// traversal. The workgroup keeps the attempt's network in LDS (restaged when
+// the attempt changes between its units); each wavefront's input tile is its
+// own. (At least 4 wavefronts per SIMD: the kernel waits on gathers most of
+// the time, and 4 resident wavefronts with a few spilled registers beat 3
+// without.)
+constexpr int WT_WAVES = 4;
+
+__global__ void __launch_bounds__(64 * WT_WAVES, 4) k_b_weights(const Attempt *__restrict__ att, Stage S)
 {
-    __shared__ InTile T;
-    const int l = __lane_id();
+    __shared__ WTile W;
+    __shared__ __align__(16) uint16_t X[WT_WAVES][ROWS * 32];
+    const int l = __lane_id(), wv = (int)threadIdx.x >> 6;
+    int cached = -1;
     FOR_UNITS(S, u) {
         const int a = attempt_of(S, u);
         const Attempt &A = att[a];
-        const int p = (u - S.off[a]) * ROWS + l;
+        if (a != cached) {
+            __syncthreads();
+            stage_weights(W, A.mq, A.mw);
+            __syncthreads();
+            cached = a;
+        }
+        const int p = (u - S.off[a]) * (ROWS * WT_WAVES) + wv * ROWS + l;
         FeatArgs F;
         F.fr = A.fr;
         F.nodes = A.nodes;
@@ -146,11 +159,15 @@ __global__ void __launch_bounds__(64, 4) k_b_weights(const Attempt *__restrict__
                 pixel_inputs(F, p % A.fr.W, p / A.fr.W, packed_depth(own),
                              [&](int t) { return A.leaves[(int64_t)t * A.P + p]; }, x);
         }
-        __syncthreads();   // the previous unit's tile is no longer read
-        store_row(T, x);
-        stage_head(T, A.mq, A.mw);
-        __syncthreads();
-        const float zl = tile_forward_regs(T, A.mq, A.mw);
+        // the tile is this wavefront's alone: its LDS writes and reads stay in
+        // order, so only the compiler must not move them across each other
+        __builtin_amdgcn_wave_barrier();
+        store_row(X[wv], x);
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        const float zl = tile_forward_staged(X[wv], W);
+        __builtin_amdgcn_wave_barrier();
         const uint32_t w = (p < A.P && ok) ? pick_weight(zl, nullptr) : 0u;
         if (p < A.P) A.wbuf[p] = w;
         // the tile's weight sum into its pixel block's (zeroed by k_b_pack;
@@ -1174,7 +1191,9 @@ static std::vector<int32_t> offsets(const Plan *pl, const Sched &sc)
     fill(1, [&](int a) { return (int)((P(a) + POOL_BLOCK - 1) / POOL_BLOCK); });
     fill(2, [&](int) { return 1; });
     fill(3, [&](int a) { return pl->shape[a].N + (rounds_for(pl->shape[a].N) * pl->shape[a].B + 63) / 64; });
-    fill(4, [&](int a) { return pl->shape[a].weights == 2 ? (int)((P(a) + ROWS - 1) / ROWS) : 0; });
+    fill(4, [&](int a) {
+        return pl->shape[a].weights == 2 ? (int)((P(a) + ROWS * WT_WAVES - 1) / (ROWS * WT_WAVES)) : 0;
+    });
     auto bound = [&](int a, int rr) {
         int bnd = pl->shape[a].N;
         for (int k = 0; k < rr; ++k) bnd = (bnd + 1) / 2;
@@ -1240,7 +1259,8 @@ static int enqueue(const Plan *pl, const Sched &sc, const Stages &st, hipStream_
     if (st.wts.total > 0) {
         // learned weights feed the pool's weight prefix: one chain
         launch_leaves(sc, st, cap, d, s);
-        RL_LAUNCH("k_b_weights", k_b_weights, dim3(grid_of(st.wts, cap, sc.xcd)), dim3(64), 0, s, d, st.wts);
+        RL_LAUNCH("k_b_weights", k_b_weights, dim3(grid_of(st.wts, cap / WT_WAVES, sc.xcd)), dim3(64 * WT_WAVES), 0,
+                  s, d, st.wts);
         RL_LAUNCH("k_b_pool_scan", k_b_pool_scan, dim3(grid_of(att, cap, 0)), dim3(1024), 0, s, d, att);
         RL_LAUNCH("k_b_pool_write", k_b_pool_write, dim3(grid_of(st.pb, cap, sc.xcd)), dim3(POOL_BLOCK), 0, s, d,
                   st.pb);
