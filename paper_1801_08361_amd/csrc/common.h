@@ -783,6 +783,8 @@ struct Attempt {
     int32_t *blockcnt;             // [nb]
     unsigned long long *blockw;    // [nb] weight sums per pixel block
     unsigned long long *cdf;       // [P] inclusive weight prefix over the pool
+    int32_t *guide;                // [P] weighted picks: first pool entry of each draw bucket
+    unsigned long long *gsel;      // [0] total weight [1] bucket multiplier [2] buckets in use
     uint32_t *wbuf;                // [P] learned pick weights (learned proposal only)
     int32_t *misc;                 // [0] pool size [1] live [2] valid [3] rounds done
     Hyp *hyp;                      // [N]

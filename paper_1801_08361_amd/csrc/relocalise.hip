@@ -182,6 +182,38 @@ __global__ void __launch_bounds__(64 * WT_WAVES, 4) k_b_weights(const Attempt *_
 // query pool (valid pixels in raster order) and the pick-weight prefix
 // ---------------------------------------------------------------------------
 
+// Weighted picks find the first pool entry whose inclusive weight prefix
+// exceeds a draw r < total. A guide table narrows that search: draw r falls in
+// bucket f(r) = umulhi(r, M), M = min(floor(G 2^64 / total), 2^64 - 1) with
+// G = min(pool size, total) buckets, so f never decreases and steps by at
+// most 1; guide[g] is the entry whose weight range [prefix - w, prefix)
+// holds the first draw of bucket g. The entry sought for r then lies between
+// guide[f(r)] and guide[f(r) + 1] (the last entry for the last bucket in
+// use), and a binary search over that span returns exactly the entry the
+// search over the whole prefix would.
+__device__ __forceinline__ uint32_t guide_bucket(unsigned long long r, unsigned long long M)
+{
+    return (uint32_t)__umul64hi(r, M);
+}
+
+// floor(G 2^64 / total) for 1 <= G <= total, saturated at 2^64 - 1 (restoring
+// division of G 2^64, one quotient bit at a time)
+__device__ __forceinline__ unsigned long long guide_multiplier(unsigned long long G, unsigned long long total)
+{
+    if (G >= total) return ~0ull;
+    unsigned long long rem = G, q = 0ull;
+    for (int i = 0; i < 64; ++i) {
+        const bool top = (rem >> 63) != 0ull;
+        rem <<= 1;
+        q <<= 1;
+        if (top || rem >= total) {
+            rem -= total;
+            q |= 1ull;
+        }
+    }
+    return q;
+}
+
 __device__ __forceinline__ unsigned long long wave_incl_scan_u64(unsigned long long x)
 {
     const int lane = __lane_id();
@@ -281,6 +313,15 @@ __global__ void __launch_bounds__(1024) k_b_pool_scan(const Attempt *__restrict_
             __syncthreads();
         }
         if (threadIdx.x == 0) {
+            if (A.weights) {
+                // the guide table's parameters (no buckets without weight)
+                const unsigned long long tot = carryw;
+                const unsigned long long G = tot < (unsigned long long)carry ? tot : (unsigned long long)carry;
+                const unsigned long long M = G ? guide_multiplier(G, tot) : 0ull;
+                A.gsel[0] = tot;
+                A.gsel[1] = M;
+                A.gsel[2] = tot ? (unsigned long long)guide_bucket(tot - 1ull, M) + 1ull : 0ull;
+            }
             A.misc[0] = carry;
             A.misc[1] = 0;
             A.misc[2] = 0;
@@ -321,7 +362,16 @@ __global__ void __launch_bounds__(POOL_BLOCK) k_b_pool_write(const Attempt *__re
         const int idx = off + __popcll(m & lanemask_lt());
         if (ok && idx < A.P) {
             A.pool[idx] = p;
-            if (A.weights) A.cdf[idx] = offw + wi;
+            if (A.weights) {
+                const unsigned long long c1 = offw + wi, c0 = c1 - w;
+                A.cdf[idx] = c1;
+                if (w) {
+                    // the buckets whose first draw lies in [c0, c1)
+                    const unsigned long long M = A.gsel[1];
+                    const uint32_t g1 = guide_bucket(c1 - 1ull, M);
+                    for (uint32_t g = c0 ? guide_bucket(c0 - 1ull, M) + 1u : 0u; g <= g1; ++g) A.guide[g] = idx;
+                }
+            }
         }
         __syncthreads();
     }
@@ -374,10 +424,13 @@ __device__ __forceinline__ bool colour_in(uint32_t a, const ColourWin &w)
 __device__ __forceinline__ int pick_pool(const Attempt &A, int np, uint64_t u)
 {
     if (!A.weights) return (int)uniform_int(u, (uint64_t)np);
-    const unsigned long long total = A.cdf[np - 1];
+    const unsigned long long total = A.gsel[0];
     if (total == 0ull) return (int)uniform_int(u, (uint64_t)np);
     const unsigned long long r = uniform_int(u, total);
-    int lo = 0, hi = np - 1;
+    // the span the guide table leaves (see guide_bucket)
+    const uint32_t g = guide_bucket(r, A.gsel[1]);
+    int lo = A.guide[g];
+    int hi = (unsigned long long)g + 1ull < A.gsel[2] ? A.guide[g + 1] : np - 1;
     while (lo < hi) {
         int mid = lo + ((hi - lo) >> 1);
         if (A.cdf[mid] > r) hi = mid; else lo = mid + 1;
@@ -1127,6 +1180,8 @@ static size_t carve(const Shape &s, char *base, Attempt &A)
     A.blockcnt = (int32_t *)take((size_t)nb * 4);
     A.blockw = (unsigned long long *)take((size_t)nb * 8);
     A.cdf = (unsigned long long *)take(s.weights ? (size_t)P * 8 : 8);
+    A.guide = (int32_t *)take(s.weights ? (size_t)P * 4 : 4);
+    A.gsel = (unsigned long long *)take(3 * 8);
     A.wbuf = (uint32_t *)take(s.weights == 2 ? (size_t)P * 4 : 4);
     A.misc = (int32_t *)take(16);
     A.hyp = (Hyp *)take((size_t)s.N * sizeof(Hyp));

@@ -106,13 +106,26 @@ def test_weighted_picks_match_oracle():
         g.adapt_frame(d, c, sc.K, sc.adapt_poses[k])
         o.adapt(d0, c0, sc.K, sc.adapt_poses[k])
     rng = np.random.default_rng(9)
-    for q in (0, 5):
+    # weight patterns: the proposal's range (half of them 1); mostly zero with
+    # a few near 2^32 (one entry spans many draw buckets); a few 1s among
+    # zeros (fewer weight units than pool entries); all zero (uniform picks)
+    cases = [(0, "proposal"), (5, "proposal"), (2, "sparse_huge"), (3, "few_ones"), (4, "zero")]
+    for q, kind in cases:
         d0, c0 = sc.render_query(q)
-        w = rng.integers(1, 65537, size=d0.numel()).astype(np.uint32)
-        w[rng.random(d0.numel()) < 0.5] = 1
+        n = d0.numel()
+        if kind == "proposal":
+            w = rng.integers(1, 65537, size=n).astype(np.uint32)
+            w[rng.random(n) < 0.5] = 1
+        elif kind == "sparse_huge":
+            w = rng.integers(1, 2**32, size=n, dtype=np.uint64).astype(np.uint32)
+            w[rng.random(n) < 0.9] = 0
+        elif kind == "few_ones":
+            w = (rng.random(n) < 0.01).astype(np.uint32)
+        else:
+            w = np.zeros(n, np.uint32)
         d, c = to_dev(d0, c0, dev)
         wd = torch.from_numpy(w.view(np.int32)).to(dev)
-        banner(f"weights relocalise q={q}")
+        banner(f"weights relocalise q={q} {kind}")
         rg = g.relocalise_ex(d, c, sc.K, seed=77 + q, weights=wd)
         tg = g.trace(pp.n_hypotheses)
         so, To, sco, to = o.relocalise(d0, c0, sc.K, seed=77 + q, weights=w, trace=True)
