@@ -1139,10 +1139,6 @@ struct Plan {
     std::vector<Attempt> slices;    // scratch pointers per attempt
     int32_t *d_off = nullptr;       // stage offsets of the chosen schedule
     hipGraphExec_t exec = nullptr;
-    // a second stream and two events: the pool kernels run beside the
-    // traversal when no attempt computes learned weights in the batch
-    hipStream_t side = nullptr;
-    hipEvent_t fork = nullptr, join = nullptr;
     Sched sched{GROUP, 0, 0, 4};
     std::string desc;
     uint64_t last_use = 0;
@@ -1214,9 +1210,6 @@ static void free_plan(reloc_batch *b, Plan *pl)
     if (pl->d_off) (void)hipFree(pl->d_off);
     if (pl->h_att) (void)hipHostFree(pl->h_att);
     if (pl->h_res) (void)hipHostFree(pl->h_res);
-    if (pl->fork) (void)hipEventDestroy(pl->fork);
-    if (pl->join) (void)hipEventDestroy(pl->join);
-    if (pl->side) (void)hipStreamDestroy(pl->side);
     b->bytes -= pl->arena_bytes;
     delete pl;
 }
@@ -1311,26 +1304,13 @@ static int enqueue(const Plan *pl, const Sched &sc, const Stages &st, hipStream_
     Stage att = st.att;
     att.xcd = 0;
     RL_LAUNCH("k_b_pack", k_b_pack, dim3(grid_of(st.pb, cap, sc.xcd)), dim3(POOL_BLOCK), 0, s, d, st.pb);
-    if (st.wts.total > 0) {
-        // learned weights feed the pool's weight prefix: one chain
-        launch_leaves(sc, st, cap, d, s);
+    launch_leaves(sc, st, cap, d, s);
+    // learned weights feed the pool's weight prefix
+    if (st.wts.total > 0)
         RL_LAUNCH("k_b_weights", k_b_weights, dim3(grid_of(st.wts, cap / WT_WAVES, sc.xcd)), dim3(64 * WT_WAVES), 0,
                   s, d, st.wts);
-        RL_LAUNCH("k_b_pool_scan", k_b_pool_scan, dim3(grid_of(att, cap, 0)), dim3(1024), 0, s, d, att);
-        RL_LAUNCH("k_b_pool_write", k_b_pool_write, dim3(grid_of(st.pb, cap, sc.xcd)), dim3(POOL_BLOCK), 0, s, d,
-                  st.pb);
-    } else {
-        // the pool needs only the packed frame's counts (and given weights):
-        // it is built on the side stream while the traversal runs
-        RL_HIP(hipEventRecord(pl->fork, s));
-        RL_HIP(hipStreamWaitEvent(pl->side, pl->fork, 0));
-        RL_LAUNCH("k_b_pool_scan", k_b_pool_scan, dim3(grid_of(att, cap, 0)), dim3(1024), 0, pl->side, d, att);
-        RL_LAUNCH("k_b_pool_write", k_b_pool_write, dim3(grid_of(st.pb, cap, sc.xcd)), dim3(POOL_BLOCK), 0,
-                  pl->side, d, st.pb);
-        RL_HIP(hipEventRecord(pl->join, pl->side));
-        launch_leaves(sc, st, cap, d, s);
-        RL_HIP(hipStreamWaitEvent(s, pl->join, 0));
-    }
+    RL_LAUNCH("k_b_pool_scan", k_b_pool_scan, dim3(grid_of(att, cap, 0)), dim3(1024), 0, s, d, att);
+    RL_LAUNCH("k_b_pool_write", k_b_pool_write, dim3(grid_of(st.pb, cap, sc.xcd)), dim3(POOL_BLOCK), 0, s, d, st.pb);
     RL_LAUNCH("k_b_hypgen", k_b_hypgen, dim3(grid_of(st.hyp, 0, sc.xcd)), dim3(64), 0, s, d, st.hyp);
     RL_LAUNCH("k_b_alive_init", k_b_alive_init, dim3(grid_of(att, cap, 0)), dim3(1024), 0, s, d, att);
     const int nw = score_waves(pl->tm_max);
@@ -1519,10 +1499,7 @@ static Plan *find_or_make_plan(reloc_batch *b, const std::vector<Shape> &shape, 
     if (hipMalloc((void **)&pl->arena, total) != hipSuccess ||
         hipMalloc((void **)&pl->d_att, sizeof(Attempt) * pl->n) != hipSuccess ||
         hipHostMalloc((void **)&pl->h_att, sizeof(Attempt) * pl->n, hipHostMallocDefault) != hipSuccess ||
-        hipHostMalloc((void **)&pl->h_res, sizeof(Result) * pl->n, hipHostMallocDefault) != hipSuccess ||
-        hipStreamCreateWithFlags(&pl->side, hipStreamNonBlocking) != hipSuccess ||
-        hipEventCreateWithFlags(&pl->fork, hipEventDisableTiming) != hipSuccess ||
-        hipEventCreateWithFlags(&pl->join, hipEventDisableTiming) != hipSuccess) {
+        hipHostMalloc((void **)&pl->h_res, sizeof(Result) * pl->n, hipHostMallocDefault) != hipSuccess) {
         pl->arena_bytes = 0;
         free_plan(b, pl);
         *rc = RELOC_E_NOMEM;
