@@ -49,6 +49,17 @@ __device__ __forceinline__ uint64_t lanemask_lt() { return (1ull << __lane_id())
     unit_range(S, u##0_, u##1_, u##s_); \
     for (int u = u##0_; u < u##1_; u += u##s_)
 
+// Orders one wavefront's LDS writes before its later LDS reads of other
+// lanes' data, and its reads before its later writes: a wavefront's LDS
+// operations are performed in issue order, so only the compiler must keep
+// them in place.
+__device__ __forceinline__ void wave_lds_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // round r of attempt A runs when no later round has started and at least one
 // (r = 0) or more than one (r > 0) hypothesis is live
 __device__ __forceinline__ bool round_active(const Attempt &A, int r)
@@ -159,15 +170,11 @@ __global__ void __launch_bounds__(64 * WT_WAVES, 4) k_b_weights(const Attempt *_
                 pixel_inputs(F, p % A.fr.W, p / A.fr.W, packed_depth(own),
                              [&](int t) { return A.leaves[(int64_t)t * A.P + p]; }, x);
         }
-        // the tile is this wavefront's alone: its LDS writes and reads stay in
-        // order, so only the compiler must not move them across each other
-        __builtin_amdgcn_wave_barrier();
+        // the tile is this wavefront's alone
+        wave_lds_sync();
         store_row(X[wv], x);
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        wave_lds_sync();
         const float zl = tile_forward_staged(X[wv], W);
-        __builtin_amdgcn_wave_barrier();
         const uint32_t w = (p < A.P && ok) ? pick_weight(zl, nullptr) : 0u;
         if (p < A.P) A.wbuf[p] = w;
         // the tile's weight sum into its pixel block's (zeroed by k_b_pack;
@@ -815,8 +822,10 @@ __global__ void __launch_bounds__(CULL_THREADS) k_b_cull(const Attempt *__restri
 // of GROUP). The draws of a group are spread over the workgroup's wavefronts;
 // each wavefront takes its draw (pixel and leaves, staged for every round by
 // the hypothesis kernel), stages the draw's modes in (tree, mode) order in
-// its own LDS slice, and scores them against its lanes' hypotheses. The
-// group's energies are then summed per lane in draw order and stored; the
+// its own LDS slice, and scores them against its lanes' hypotheses (only
+// the wavefront itself touches its slice, so the wavefronts do not wait for
+// each other between draws). The group's energies are then summed per lane
+// in draw order and stored; the
 // cull adds the group sums in group order. The units of hypothesis block 0
 // also count each draw's modes.
 __global__ void __launch_bounds__(64 * GROUP) k_b_score(const Attempt *__restrict__ att, Stage S, int r, int dpu,
@@ -871,7 +880,7 @@ __global__ void __launch_bounds__(64 * GROUP) k_b_score(const Attempt *__restric
                         s_base[wv][lane] = base;
                     }
                     if (publish && has && lane == 0 && cnt) atomicAdd(&A.stats[2], (unsigned long long)cnt);
-                    __syncthreads();
+                    wave_lds_sync();
                     for (int j = lane; j < cnt; j += 64) {
                         // the mode's tree: the last tree whose first mode index is <= j
                         int tj = 0;
@@ -887,7 +896,7 @@ __global__ void __launch_bounds__(64 * GROUP) k_b_score(const Attempt *__restric
                         dst[10] = __int_as_float(gidx);
                         dst[11] = 0.0f;
                     }
-                    __syncthreads();
+                    wave_lds_sync();
                     const float y0 = fmaf(R0, dr.x, fmaf(R1, dr.y, fmaf(R2, dr.z, t0)));
                     const float y1 = fmaf(R3, dr.x, fmaf(R4, dr.y, fmaf(R5, dr.z, t1)));
                     const float y2 = fmaf(R6, dr.x, fmaf(R7, dr.y, fmaf(R8, dr.z, t2)));
@@ -917,8 +926,10 @@ __global__ void __launch_bounds__(64 * GROUP) k_b_score(const Attempt *__restric
                     }
                     s_e[slot][lane] = best < 0.0f ? best : 0.0f;
                     if (act && has) A.inl[(int64_t)i * A.N + ap] = gid;
-                    __syncthreads();
+                    // this wavefront's next draw restages its own LDS slice
+                    wave_lds_sync();
                 }
+                __syncthreads();
                 // the group's energy sum per lane, in draw order
                 if (wv == 0) {
                     float g = 0.0f;
