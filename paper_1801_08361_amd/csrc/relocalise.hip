@@ -41,6 +41,7 @@ int frame_from(const Forest *f, const uint16_t *depth, const uint8_t *rgb, const
 
 constexpr int PIX_BLOCK = 256;
 constexpr int POOL_BLOCK = 1024;
+constexpr int PB_PIX = 4;   // pixels per thread in the pixel-block kernels (pack, pool write)
 
 __device__ __forceinline__ uint64_t lanemask_lt() { return (1ull << __lane_id()) - 1ull; }
 
@@ -235,36 +236,55 @@ __device__ __forceinline__ unsigned long long wave_incl_scan_u64(unsigned long l
 // per pixel), the block's count of valid pixels and, for pick weights given
 // by the caller, the block's weight sum (learned weights computed in the
 // batch add theirs in k_b_weights, onto the zero written here)
-__global__ void __launch_bounds__(POOL_BLOCK) k_b_pack(const Attempt *__restrict__ att, Stage S)
+// (POOL_BLOCK / PB_PIX threads per block: thread t handles pixels
+// t + j POOL_BLOCK / PB_PIX of it, all loads first)
+__global__ void __launch_bounds__(POOL_BLOCK / PB_PIX) k_b_pack(const Attempt *__restrict__ att, Stage S)
 {
-    __shared__ unsigned long long wsum[POOL_BLOCK / 64];
+    constexpr int NT = POOL_BLOCK / PB_PIX;
+    __shared__ int32_t wcnt[NT / 64];
+    __shared__ unsigned long long wsum[NT / 64];
+    const int tid = (int)threadIdx.x, wave = tid >> 6;
     FOR_UNITS(S, u) {
         const int a = attempt_of(S, u);
         const Attempt &A = att[a];
         const int b = u - S.off[a];
-        const int p = b * POOL_BLOCK + (int)threadIdx.x;
-        bool ok = false;
-        if (p < A.P) {
-            const uint64_t w = pack_pixel(A.fr, p);
-            A.packed[p] = w;
-            ok = packed_valid(w);
+        uint64_t w[PB_PIX];
+        bool ok[PB_PIX];
+#pragma unroll
+        for (int j = 0; j < PB_PIX; ++j) {
+            const int p = b * POOL_BLOCK + j * NT + tid;
+            w[j] = p < A.P ? pack_pixel(A.fr, p) : 0ull;
         }
-        const int n = __syncthreads_count(ok);
-        if (A.weights && !A.mq) {
-            unsigned long long w = ok ? (unsigned long long)A.weights[p] : 0ull;
-            w = wave_incl_scan_u64(w);
-            if (__lane_id() == 63) wsum[threadIdx.x / 64] = w;
-            __syncthreads();
-            if (threadIdx.x == 0) {
-                unsigned long long tot = 0;
-                for (int k = 0; k < POOL_BLOCK / 64; ++k) tot += wsum[k];
-                A.blockw[b] = tot;
+        int n = 0;
+        unsigned long long ws = 0ull;
+#pragma unroll
+        for (int j = 0; j < PB_PIX; ++j) {
+            const int p = b * POOL_BLOCK + j * NT + tid;
+            ok[j] = p < A.P && packed_valid(w[j]);
+            if (p < A.P) A.packed[p] = w[j];
+            n += __popcll(__ballot(ok[j]));
+            if (A.weights && !A.mq && ok[j]) ws += (unsigned long long)A.weights[p];
+        }
+        // the block's valid pixels and, for given weights, their weight sum
+        if (A.weights && !A.mq)
+            for (int o = 32; o > 0; o >>= 1) ws += __shfl_xor(ws, o, 64);
+        if (__lane_id() == 0) {
+            wcnt[wave] = n;
+            wsum[wave] = ws;
+        }
+        __syncthreads();
+        if (tid == 0) {
+            int tn = 0;
+            unsigned long long tw = 0ull;
+            for (int k = 0; k < NT / 64; ++k) {
+                tn += wcnt[k];
+                tw += wsum[k];
             }
-            __syncthreads();
-        } else if (A.weights && threadIdx.x == 0) {
-            A.blockw[b] = 0ull;
+            A.blockcnt[b] = tn;
+            // learned weights computed in the batch add theirs onto this zero
+            if (A.weights) A.blockw[b] = A.mq ? 0ull : tw;
         }
-        if (threadIdx.x == 0) A.blockcnt[b] = n;
+        __syncthreads();
     }
 }
 
@@ -341,42 +361,66 @@ __global__ void __launch_bounds__(1024) k_b_pool_scan(const Attempt *__restrict_
     }
 }
 
-__global__ void __launch_bounds__(POOL_BLOCK) k_b_pool_write(const Attempt *__restrict__ att, Stage S)
+// (POOL_BLOCK / PB_PIX threads per block, as k_b_pack: the block's 64-pixel
+// chunks c = j (POOL_BLOCK / PB_PIX / 64) + wave, counted and summed in chunk
+// order, which is raster order)
+__global__ void __launch_bounds__(POOL_BLOCK / PB_PIX) k_b_pool_write(const Attempt *__restrict__ att, Stage S)
 {
-    __shared__ int32_t wcnt[POOL_BLOCK / 64];
-    __shared__ unsigned long long wsw[POOL_BLOCK / 64];
+    constexpr int NT = POOL_BLOCK / PB_PIX, NC = POOL_BLOCK / 64;
+    __shared__ int32_t wcnt[NC];
+    __shared__ unsigned long long wsw[NC];
+    const int tid = (int)threadIdx.x, wave = tid >> 6;
     FOR_UNITS(S, u) {
         const int a = attempt_of(S, u);
         const Attempt &A = att[a];
         const int b = u - S.off[a];
-        const int p = b * POOL_BLOCK + (int)threadIdx.x;
-        const bool ok = p < A.P && valid_depth(A.fr, A.fr.depth[p]);
-        const uint64_t m = __ballot(ok);
-        const int wave = threadIdx.x / 64;
-        const unsigned long long w = (ok && A.weights) ? (unsigned long long)A.weights[p] : 0ull;
-        const unsigned long long wi = wave_incl_scan_u64(w);
-        if (__lane_id() == 63) {
-            wcnt[wave] = __popcll(m);
-            wsw[wave] = wi;
+        uint32_t dep[PB_PIX];
+#pragma unroll
+        for (int j = 0; j < PB_PIX; ++j) {
+            const int p = b * POOL_BLOCK + j * NT + tid;
+            dep[j] = p < A.P ? (uint32_t)A.fr.depth[p] : 0u;
+        }
+        bool ok[PB_PIX];
+        uint64_t m[PB_PIX];
+        unsigned long long w[PB_PIX], wi[PB_PIX];
+#pragma unroll
+        for (int j = 0; j < PB_PIX; ++j) {
+            const int p = b * POOL_BLOCK + j * NT + tid;
+            ok[j] = p < A.P && valid_depth(A.fr, dep[j]);
+            m[j] = __ballot(ok[j]);
+            w[j] = (ok[j] && A.weights) ? (unsigned long long)A.weights[p] : 0ull;
+        }
+#pragma unroll
+        for (int j = 0; j < PB_PIX; ++j) {
+            wi[j] = wave_incl_scan_u64(w[j]);
+            if (__lane_id() == 63) {
+                wcnt[j * (NT / 64) + wave] = __popcll(m[j]);
+                wsw[j * (NT / 64) + wave] = wi[j];
+            }
         }
         __syncthreads();
-        int off = A.blockcnt[b];
-        unsigned long long offw = A.weights ? A.blockw[b] : 0ull;
-        for (int k = 0; k < wave; ++k) {
-            off += wcnt[k];
-            offw += wsw[k];
-        }
-        const int idx = off + __popcll(m & lanemask_lt());
-        if (ok && idx < A.P) {
-            A.pool[idx] = p;
-            if (A.weights) {
-                const unsigned long long c1 = offw + wi, c0 = c1 - w;
-                A.cdf[idx] = c1;
-                if (w) {
-                    // the buckets whose first draw lies in [c0, c1)
-                    const unsigned long long M = A.gsel[1];
-                    const uint32_t g1 = guide_bucket(c1 - 1ull, M);
-                    for (uint32_t g = c0 ? guide_bucket(c0 - 1ull, M) + 1u : 0u; g <= g1; ++g) A.guide[g] = idx;
+#pragma unroll
+        for (int j = 0; j < PB_PIX; ++j) {
+            const int p = b * POOL_BLOCK + j * NT + tid;
+            const int c = j * (NT / 64) + wave;
+            int off = A.blockcnt[b];
+            unsigned long long offw = A.weights ? A.blockw[b] : 0ull;
+            for (int k = 0; k < c; ++k) {
+                off += wcnt[k];
+                offw += wsw[k];
+            }
+            const int idx = off + __popcll(m[j] & lanemask_lt());
+            if (ok[j] && idx < A.P) {
+                A.pool[idx] = p;
+                if (A.weights) {
+                    const unsigned long long c1 = offw + wi[j], c0 = c1 - w[j];
+                    A.cdf[idx] = c1;
+                    if (w[j]) {
+                        // the buckets whose first draw lies in [c0, c1)
+                        const unsigned long long M = A.gsel[1];
+                        const uint32_t g1 = guide_bucket(c1 - 1ull, M);
+                        for (uint32_t g = c0 ? guide_bucket(c0 - 1ull, M) + 1u : 0u; g <= g1; ++g) A.guide[g] = idx;
+                    }
                 }
             }
         }
@@ -1314,14 +1358,15 @@ static int enqueue(const Plan *pl, const Sched &sc, const Stages &st, hipStream_
     // one workgroup per attempt: plain round-robin ownership
     Stage att = st.att;
     att.xcd = 0;
-    RL_LAUNCH("k_b_pack", k_b_pack, dim3(grid_of(st.pb, cap, sc.xcd)), dim3(POOL_BLOCK), 0, s, d, st.pb);
+    RL_LAUNCH("k_b_pack", k_b_pack, dim3(grid_of(st.pb, cap, sc.xcd)), dim3(POOL_BLOCK / PB_PIX), 0, s, d, st.pb);
     launch_leaves(sc, st, cap, d, s);
     // learned weights feed the pool's weight prefix
     if (st.wts.total > 0)
         RL_LAUNCH("k_b_weights", k_b_weights, dim3(grid_of(st.wts, cap / WT_WAVES, sc.xcd)), dim3(64 * WT_WAVES), 0,
                   s, d, st.wts);
     RL_LAUNCH("k_b_pool_scan", k_b_pool_scan, dim3(grid_of(att, cap, 0)), dim3(1024), 0, s, d, att);
-    RL_LAUNCH("k_b_pool_write", k_b_pool_write, dim3(grid_of(st.pb, cap, sc.xcd)), dim3(POOL_BLOCK), 0, s, d, st.pb);
+    RL_LAUNCH("k_b_pool_write", k_b_pool_write, dim3(grid_of(st.pb, cap, sc.xcd)), dim3(POOL_BLOCK / PB_PIX), 0, s, d,
+              st.pb);
     RL_LAUNCH("k_b_hypgen", k_b_hypgen, dim3(grid_of(st.hyp, 0, sc.xcd)), dim3(64), 0, s, d, st.hyp);
     RL_LAUNCH("k_b_alive_init", k_b_alive_init, dim3(grid_of(att, cap, 0)), dim3(1024), 0, s, d, att);
     const int nw = score_waves(pl->tm_max);
