@@ -230,6 +230,23 @@ constexpr int RANK_THREADS = 512;
 // Per (chunk, tree): stable rank of each valid pixel among the chunk's pixels
 // in the same leaf (bitonic sort of (leaf, local index) keys in LDS), and the
 // chunk's per-leaf counts into the dense [T][C][L] table (kept zero elsewhere).
+// one bitonic step at distance D < 8 over a thread's eight keys (key i = 8
+// tid + e in register e), for the merge of size k
+template <int D>
+__device__ __forceinline__ void bitonic_in_thread(uint32_t v[8], int tid, int k)
+{
+#pragma unroll
+    for (int e = 0; e < 8; ++e)
+        if ((e & D) == 0) {
+            const bool asc = ((8 * tid + e) & k) == 0;
+            const uint32_t a = v[e], b = v[e + D];
+            if ((a > b) == asc) {
+                v[e] = b;
+                v[e + D] = a;
+            }
+        }
+}
+
 __global__ void __launch_bounds__(RANK_THREADS) k_chunk_rank(const int32_t *__restrict__ leaves, int P, int L,
                                                              int C, uint16_t *__restrict__ rank,
                                                              uint16_t *__restrict__ cnt)
@@ -237,28 +254,64 @@ __global__ void __launch_bounds__(RANK_THREADS) k_chunk_rank(const int32_t *__re
     __shared__ uint32_t keys[CHUNK];
     const int c = blockIdx.x, t = blockIdx.y, tid = threadIdx.x;
     const int64_t base = (int64_t)c * CHUNK;
-    for (int j = tid; j < CHUNK; j += RANK_THREADS) {
-        int64_t p = base + j;
-        int32_t leaf = p < P ? leaves[(int64_t)t * P + p] : -1;
-        keys[j] = leaf >= 0 ? (((uint32_t)leaf << 12) | (uint32_t)j) : 0xFFFFFFFFu;
+    // Bitonic sort with key i (of CHUNK) in register e of thread tid for
+    // i = E tid + e: exchanges at distance j < E stay in the thread, those at
+    // E <= j < 64 E are between lanes of one wavefront (xor shuffles), and
+    // only those at j >= 64 E go through LDS between barriers.
+    constexpr int E = CHUNK / RANK_THREADS;
+    static_assert(E == 8, "eight keys per thread");
+    uint32_t v[E];
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        const int j = E * tid + e;
+        const int64_t p = base + j;
+        const int32_t leaf = p < P ? leaves[(int64_t)t * P + p] : -1;
+        v[e] = leaf >= 0 ? (((uint32_t)leaf << 12) | (uint32_t)j) : 0xFFFFFFFFu;
     }
-    __syncthreads();
     for (int k = 2; k <= CHUNK; k <<= 1) {
-        for (int j = k >> 1; j > 0; j >>= 1) {
-            for (int i = tid; i < CHUNK; i += RANK_THREADS) {
-                int ixj = i ^ j;
-                if (ixj > i) {
-                    uint32_t a = keys[i], b = keys[ixj];
-                    bool asc = (i & k) == 0;
-                    if ((a > b) == asc) {
-                        keys[i] = b;
-                        keys[ixj] = a;
+        int j = k >> 1;
+        if (j >= 64 * E) {
+#pragma unroll
+            for (int e = 0; e < E; ++e) keys[E * tid + e] = v[e];
+            __syncthreads();
+            for (; j >= 64 * E; j >>= 1) {
+                for (int i = tid; i < CHUNK; i += RANK_THREADS) {
+                    const int ixj = i ^ j;
+                    if (ixj > i) {
+                        const uint32_t a = keys[i], b = keys[ixj];
+                        if ((a > b) == ((i & k) == 0)) {
+                            keys[i] = b;
+                            keys[ixj] = a;
+                        }
                     }
                 }
+                __syncthreads();
             }
+#pragma unroll
+            for (int e = 0; e < E; ++e) v[e] = keys[E * tid + e];
             __syncthreads();
         }
+        for (; j >= E; j >>= 1) {
+            const int m = j / E;
+#pragma unroll
+            for (int e = 0; e < E; ++e) {
+                const int i = E * tid + e;
+                const uint32_t o = __shfl_xor(v[e], m, 64);
+                v[e] = (((i & j) == 0) == ((i & k) == 0)) ? min(v[e], o) : max(v[e], o);
+            }
+        }
+        for (; j > 0; j >>= 1) {
+            if (j == 4)
+                bitonic_in_thread<4>(v, tid, k);
+            else if (j == 2)
+                bitonic_in_thread<2>(v, tid, k);
+            else
+                bitonic_in_thread<1>(v, tid, k);
+        }
     }
+#pragma unroll
+    for (int e = 0; e < E; ++e) keys[E * tid + e] = v[e];
+    __syncthreads();
     for (int s = tid; s < CHUNK; s += RANK_THREADS) {
         uint32_t key = keys[s];
         if (key == 0xFFFFFFFFu) continue;
