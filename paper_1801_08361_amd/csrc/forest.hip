@@ -340,14 +340,22 @@ __global__ void k_leaf_scan(int T, int L, int C, uint16_t *__restrict__ cnt, uin
     if (i >= (int64_t)T * L) return;
     int t = (int)(i / L), leaf = (int)(i % L);
     uint32_t run = 0;
-    for (int c = 0; c < C; ++c) {
-        int64_t idx = ((int64_t)t * C + c) * L + leaf;
-        uint32_t v = cnt[idx];
-        if (v) {
-            pref[idx] = run;
-            cnt[idx] = 0;
-            run += v;
-        }
+    // chunks 16 at a time: their counts are loaded before any of them is
+    // cleared (the clears would otherwise order every load after the last)
+    constexpr int CB = 16;
+    for (int c0 = 0; c0 < C; c0 += CB) {
+        uint32_t v[CB];
+#pragma unroll
+        for (int q = 0; q < CB; ++q)
+            v[q] = c0 + q < C ? (uint32_t)cnt[((int64_t)t * C + c0 + q) * L + leaf] : 0u;
+#pragma unroll
+        for (int q = 0; q < CB; ++q)
+            if (v[q]) {
+                const int64_t idx = ((int64_t)t * C + c0 + q) * L + leaf;
+                pref[idx] = run;
+                cnt[idx] = 0;
+                run += v[q];
+            }
     }
     uint32_t k0 = counter[i];
     base[i] = k0;
