@@ -312,20 +312,40 @@ __global__ void __launch_bounds__(RANK_THREADS) k_chunk_rank(const int32_t *__re
 #pragma unroll
     for (int e = 0; e < E; ++e) keys[E * tid + e] = v[e];
     __syncthreads();
-    for (int s = tid; s < CHUNK; s += RANK_THREADS) {
-        uint32_t key = keys[s];
+    // A key's rank is its sorted position s minus the first position of its
+    // leaf's run: the running maximum of the run starts (positions whose leaf
+    // differs from the previous key's), in the thread, over the wavefront's
+    // lanes and over the wavefronts.
+    __shared__ uint32_t wmax[RANK_THREADS / 64];
+    const int lane = tid & 63, wave = tid >> 6;
+    uint32_t m[E];
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        const int s = E * tid + e;
+        const uint32_t prev = e > 0 ? v[e - 1] >> 12 : (s > 0 ? keys[s - 1] >> 12 : 0xFFFFFFFFu);
+        const uint32_t start = (s == 0 || (v[e] >> 12) != prev) ? (uint32_t)s : 0u;
+        m[e] = e > 0 ? max(m[e - 1], start) : start;
+    }
+    uint32_t x = m[E - 1];
+    for (int o = 1; o < 64; o <<= 1) {
+        const uint32_t y = __shfl_up(x, o, 64);
+        if (lane >= o) x = max(x, y);
+    }
+    uint32_t before = __shfl_up(x, 1, 64);
+    if (lane == 0) before = 0u;
+    if (lane == 63) wmax[wave] = x;
+    __syncthreads();
+    for (int w = 0; w < wave; ++w) before = max(before, wmax[w]);
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        const int s = E * tid + e;
+        const uint32_t key = v[e];
         if (key == 0xFFFFFFFFu) continue;
-        uint32_t leaf = key >> 12;
-        // first sorted position of this leaf
-        int lo = 0, hi = s;
-        while (lo < hi) {
-            int mid = (lo + hi) >> 1;
-            if ((keys[mid] >> 12) < leaf) lo = mid + 1; else hi = mid;
-        }
-        int r = s - lo;
+        const uint32_t leaf = key >> 12;
+        const int r = s - (int)max(m[e], before);
         rank[(int64_t)t * P + base + (key & 4095u)] = (uint16_t)r;
-        bool tail = (s == CHUNK - 1) || ((keys[s + 1] >> 12) != leaf);
-        if (tail) cnt[((int64_t)t * C + c) * L + leaf] = (uint16_t)(r + 1);
+        const uint32_t next = e + 1 < E ? v[e + 1] >> 12 : (s + 1 < CHUNK ? keys[s + 1] >> 12 : 0xFFFFFFFFu);
+        if (next != leaf) cnt[((int64_t)t * C + c) * L + leaf] = (uint16_t)(r + 1);
     }
 }
 
