@@ -420,6 +420,7 @@ static FeatArgs feat_args(const Forest *f, const Frame &fr)
     A.modes = f->modes;
     A.leaf_in = f->leaf_in;
     A.packed = nullptr;
+    A.xnodes = nullptr;
     A.T = f->T; A.L = f->L; A.M = f->M; A.R = f->R;
     return A;
 }

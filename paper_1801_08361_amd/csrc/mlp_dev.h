@@ -269,6 +269,7 @@ struct FeatArgs {
     const Mode *modes;
     const float4 *leaf_in;       // [T][L][4] per-leaf summaries written with the modes
     const uint64_t *packed;      // the frame packed for probes, or null (probes read the frame)
+    const ProbeNode *xnodes;     // the 8 extra nodes prepared for the frame (with packed), or null
     int T, L, M, R;
 };
 
@@ -290,20 +291,38 @@ __device__ __forceinline__ void pixel_inputs(const FeatArgs &A, int u, int v, ui
     const PixelDen pd = pixel_den(A.fr, (int32_t)d);
     const uint64_t *extra = A.nodes + (int64_t)A.T * (A.L - 1);
     const uint64_t own = A.packed ? A.packed[v * A.fr.W + u] : 0ull;
-    for (int j = 0; j < 8; ++j) {
-        int32_t r;
-        if (A.packed) {
-            r = probe_response(packed_rsrc(A.packed, A.fr.W * A.fr.H), A.fr.W, A.fr.H, u, v, own, pd,
-                               probe_node(extra[j], A.fr));
-        } else {
-            int32_t thr;
-            r = node_response_d(A.fr, extra[j], u, v, (int32_t)d, pd, thr);
+    if (A.packed && A.xnodes) {
+        // prepared nodes: the 8 probes are independent loads issued together
+        const __amdgpu_buffer_rsrc_t rs = packed_rsrc(A.packed, A.fr.W * A.fr.H);
+        int32_t rr[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) rr[j] = probe_response(rs, A.fr.W, A.fr.H, u, v, own, pd, A.xnodes[j]);
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            int32_t r = rr[j];
+            if ((A.xnodes[j].sh & 63u) == 0) {
+                r = r > 5000 ? 5000 : (r < -5000 ? -5000 : r);
+                x[1 + j] = (float)r / 1000.0f;
+            } else {
+                x[1 + j] = (float)r / 255.0f;
+            }
         }
-        if ((extra[j] & 3u) == 0) {
-            r = r > 5000 ? 5000 : (r < -5000 ? -5000 : r);
-            x[1 + j] = (float)r / 1000.0f;
-        } else {
-            x[1 + j] = (float)r / 255.0f;
+    } else {
+        for (int j = 0; j < 8; ++j) {
+            int32_t r;
+            if (A.packed) {
+                r = probe_response(packed_rsrc(A.packed, A.fr.W * A.fr.H), A.fr.W, A.fr.H, u, v, own, pd,
+                                   probe_node(extra[j], A.fr));
+            } else {
+                int32_t thr;
+                r = node_response_d(A.fr, extra[j], u, v, (int32_t)d, pd, thr);
+            }
+            if ((extra[j] & 3u) == 0) {
+                r = r > 5000 ? 5000 : (r < -5000 ? -5000 : r);
+                x[1 + j] = (float)r / 1000.0f;
+            } else {
+                x[1 + j] = (float)r / 255.0f;
+            }
         }
     }
     // the heaviest three over the leaves' first three modes, ties to the lower

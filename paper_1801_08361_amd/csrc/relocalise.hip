@@ -140,6 +140,7 @@ constexpr int WT_WAVES = 4;
 __global__ void __launch_bounds__(64 * WT_WAVES, 4) k_b_weights(const Attempt *__restrict__ att, Stage S)
 {
     __shared__ WTile W;
+    __shared__ ProbeNode xn[8];
     __shared__ __align__(16) uint16_t X[WT_WAVES][ROWS * 32];
     const int l = __lane_id(), wv = (int)threadIdx.x >> 6;
     int cached = -1;
@@ -147,8 +148,10 @@ __global__ void __launch_bounds__(64 * WT_WAVES, 4) k_b_weights(const Attempt *_
         const int a = attempt_of(S, u);
         const Attempt &A = att[a];
         if (a != cached) {
+            // the attempt's network and its 8 extra nodes prepared for its frame
             __syncthreads();
             stage_weights(W, A.mq, A.mw);
+            if (threadIdx.x < 8) xn[threadIdx.x] = probe_node(A.nodes[(int64_t)A.T * (A.L - 1) + threadIdx.x], A.fr);
             __syncthreads();
             cached = a;
         }
@@ -160,6 +163,7 @@ __global__ void __launch_bounds__(64 * WT_WAVES, 4) k_b_weights(const Attempt *_
         F.modes = A.modes;
         F.leaf_in = A.leaf_in;
         F.packed = A.packed;
+        F.xnodes = xn;
         F.T = A.T; F.L = A.L; F.M = A.M; F.R = A.R;
         float x[24];
         for (int k = 0; k < 24; ++k) x[k] = 0.0f;
