@@ -331,9 +331,15 @@ __device__ __forceinline__ void pixel_inputs(const FeatArgs &A, int u, int v, ui
     float4 b0 = make_float4(-1.0f, 0.0f, 0.0f, 0.0f), b1 = b0, b2 = b0;
     bool h0 = false, h1 = false, h2 = false;
     int64_t fill = 0;
-    for (int t = 0; t < A.T; ++t) {
+    // the first 8 trees' leaf indices loaded together, ahead of the summaries
+    int32_t lv[8];
+#pragma unroll
+    for (int t = 0; t < 8; ++t) lv[t] = t < A.T ? leaf_of(t) : 0;
+#pragma unroll
+    for (int t = 0; t < 16; ++t) {
+        if (t >= A.T) break;
         // the whole summary at once (the mode count selects what is used)
-        const float4 *S = A.leaf_in + ((int64_t)t * A.L + leaf_of(t)) * 4;
+        const float4 *S = A.leaf_in + ((int64_t)t * A.L + (t < 8 ? lv[t] : leaf_of(t))) * 4;
         const float4 head = S[0], m3[3] = {S[1], S[2], S[3]};
         fill += (int64_t)__float_as_uint(head.x);
         const int n3 = __float_as_int(head.y);
