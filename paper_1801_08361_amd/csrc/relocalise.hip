@@ -873,9 +873,8 @@ __global__ void __launch_bounds__(CULL_THREADS) k_b_cull(const Attempt *__restri
 // its own LDS slice, and scores them against its lanes' hypotheses (only
 // the wavefront itself touches its slice, so the wavefronts do not wait for
 // each other between draws). The group's energies are then summed per lane
-// in draw order and stored; the
-// cull adds the group sums in group order. The units of hypothesis block 0
-// also count each draw's modes.
+// in draw order and stored; the cull adds the group sums in group order. The
+// units of hypothesis block 0 also count each draw's modes.
 __global__ void __launch_bounds__(64 * GROUP) k_b_score(const Attempt *__restrict__ att, Stage S, int r, int dpu,
                                                         int tm)
 {
