@@ -601,9 +601,11 @@ __host__ __device__ __forceinline__ bool top_eigvec_horn(const double N[16], con
     double vn = sqrt(((v[0] * v[0] + v[1] * v[1]) + v[2] * v[2]) + v[3] * v[3]);
     if (!(vn > 0.0) || !(vn < INFINITY)) return false;
 #pragma unroll
-    for (int i = 0; i < 4; ++i) v[i] = v[i] / vn;
-    // one step of inverse iteration: solve (N - l I) x = v
+    for (int i = 0; i < 4; ++i) v[i] = v[i] * (1.0 / vn);
+    // one step of inverse iteration: solve (N - l I) x = v (reciprocal
+    // pivots, reused by the back substitution)
     const double floor_ = 1e-17 * lam;
+    double rpiv[4];
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
         int p = k;
@@ -630,9 +632,10 @@ __host__ __device__ __forceinline__ bool top_eigvec_horn(const double N[16], con
         double piv = A[k * 4 + k];
         if (fabs(piv) < floor_) piv = piv < 0.0 ? -floor_ : floor_;
         A[k * 4 + k] = piv;
+        rpiv[k] = 1.0 / piv;
 #pragma unroll
         for (int i = k + 1; i < 4; ++i) {
-            const double f = A[i * 4 + k] / piv;
+            const double f = A[i * 4 + k] * rpiv[k];
 #pragma unroll
             for (int j = k + 1; j < 4; ++j) A[i * 4 + j] = A[i * 4 + j] - f * A[k * 4 + j];
             v[i] = v[i] - f * v[k];
@@ -644,12 +647,12 @@ __host__ __device__ __forceinline__ bool top_eigvec_horn(const double N[16], con
         double r = v[k];
 #pragma unroll
         for (int j = k + 1; j < 4; ++j) r = r - A[k * 4 + j] * x[j];
-        x[k] = r / A[k * 4 + k];
+        x[k] = r * rpiv[k];
     }
     double mx = fmax(fmax(fabs(x[0]), fabs(x[1])), fmax(fabs(x[2]), fabs(x[3])));
     if (!(mx > 0.0) || !(mx < INFINITY)) return false;
 #pragma unroll
-    for (int k = 0; k < 4; ++k) q[k] = x[k] / mx;
+    for (int k = 0; k < 4; ++k) q[k] = x[k] * (1.0 / mx);
     return true;
 }
 
@@ -661,17 +664,20 @@ __device__ __forceinline__ bool pose_from_sums(const double s[NSUM], double R[9]
     double n = s[0];
     if (n < 3.0) return false;
     const double *c = s + 1, *w = s + 4, *cw = s + 7, *cc = s + 16;
+    // one reciprocal per normalisation instead of a division per entry (the
+    // solve is a latency chain on one lane)
+    const double rn = 1.0 / n;
     double H[9], S[6];
 #pragma unroll
     for (int a = 0; a < 3; ++a)
 #pragma unroll
-        for (int b = 0; b < 3; ++b) H[a * 3 + b] = cw[a * 3 + b] - (c[a] * w[b]) / n;
-    S[0] = cc[0] - (c[0] * c[0]) / n;
-    S[1] = cc[1] - (c[0] * c[1]) / n;
-    S[2] = cc[2] - (c[0] * c[2]) / n;
-    S[3] = cc[3] - (c[1] * c[1]) / n;
-    S[4] = cc[4] - (c[1] * c[2]) / n;
-    S[5] = cc[5] - (c[2] * c[2]) / n;
+        for (int b = 0; b < 3; ++b) H[a * 3 + b] = cw[a * 3 + b] - (c[a] * w[b]) * rn;
+    S[0] = cc[0] - (c[0] * c[0]) * rn;
+    S[1] = cc[1] - (c[0] * c[1]) * rn;
+    S[2] = cc[2] - (c[0] * c[2]) * rn;
+    S[3] = cc[3] - (c[1] * c[1]) * rn;
+    S[4] = cc[4] - (c[1] * c[2]) * rn;
+    S[5] = cc[5] - (c[2] * c[2]) * rn;
     double I2 = ((S[0] * S[3] - S[1] * S[1]) + (S[0] * S[5] - S[2] * S[2])) + (S[3] * S[5] - S[4] * S[4]);
     double tr = (S[0] + S[3]) + S[5];
     if (!(I2 >= (1e-4 * n) * tr)) return false;
@@ -680,7 +686,8 @@ __device__ __forceinline__ bool pose_from_sums(const double s[NSUM], double R[9]
     double q[4];
     if (!top_eigvec_horn(N, H, q)) power_top(N, q);
     double qn = sqrt(q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3]);
-    double q0 = q[0] / qn, qx = q[1] / qn, qy = q[2] / qn, qz = q[3] / qn;
+    const double rq = 1.0 / qn;
+    double q0 = q[0] * rq, qx = q[1] * rq, qy = q[2] * rq, qz = q[3] * rq;
     R[0] = q0 * q0 + qx * qx - qy * qy - qz * qz;
     R[1] = 2.0 * (qx * qy - q0 * qz);
     R[2] = 2.0 * (qx * qz + q0 * qy);
@@ -693,8 +700,8 @@ __device__ __forceinline__ bool pose_from_sums(const double s[NSUM], double R[9]
     double cm[3], wm[3];
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
-        cm[k] = c[k] / n;
-        wm[k] = w[k] / n;
+        cm[k] = c[k] * rn;
+        wm[k] = w[k] * rn;
     }
 #pragma unroll
     for (int k = 0; k < 3; ++k)
