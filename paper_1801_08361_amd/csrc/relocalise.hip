@@ -593,13 +593,19 @@ __device__ bool try_hypothesis(const Attempt &A, int np, uint64_t h, uint64_t ta
             sel -= k;
         }
         cam_point(A.fr, p[j] % A.fr.W, p[j] / A.fr.W, dep[j], c[j]);
-    }
-#pragma unroll
-    for (int j = 0; j < 3; ++j) {
         const Mode &md = A.modes[pick[j]];
         w[j][0] = md.mu[0];
         w[j][1] = md.mu[1];
         w[j][2] = md.mu[2];
+        if (j == 1) {
+            // the first pair's checks before the third pixel's loads (every
+            // check is a plain predicate, so their order does not change the
+            // result; lanes that fail here load nothing more)
+            if (pi[0] == pi[1]) return false;
+            const float dc = sq3(c[0], c[1]);
+            const float dw = sq3(w[0], w[1]);
+            if (!(dc >= A.min_pair2) || !(dw <= A.ratio2 * dc) || !(dc <= A.ratio2 * dw)) return false;
+        }
     }
     if (pi[0] == pi[1] || pi[0] == pi[2] || pi[1] == pi[2]) return false;
     const int EA[3] = {0, 0, 1}, EB[3] = {1, 2, 2};
