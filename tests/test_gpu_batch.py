@@ -70,6 +70,26 @@ def test_batch_equals_plain(forests, tune):
     assert sum(ok) >= len(att) // 2
 
 
+def test_batch_eight_pixels_per_thread_equals_plain(forests):
+    """Six 640x480 attempts (about 9.2M pixel-tree walks) take the traversal
+    with 8 pixels per thread; every result equals the plain call's."""
+    import paper_1801_08361_amd as rl
+    dev, fs = forests
+    att = []
+    for i in range(6):
+        sc, g = fs[i % len(fs)]
+        d, c = sc.render_query(i % len(sc.query_poses), device=dev, width=640, height=480)
+        att.append(dict(forest=g, depth=d.contiguous(), rgb=c.contiguous(), K=sr.intrinsics(640, 480),
+                        seed=900 + i, n_hyp=64))
+    b = rl.Batch(tune=False)
+    banner("batch of six 640x480 attempts")
+    res = b.run(att)
+    assert "pix_per_thread=8" in b.schedule()
+    for i, a in enumerate(att):
+        p = a["forest"].relocalise_ex(a["depth"], a["rgb"], a["K"], seed=a["seed"], n_hyp=a["n_hyp"])
+        assert same(res[i], p), (i, res[i], p)
+
+
 def test_batch_single_and_failures(forests):
     import torch
     import paper_1801_08361_amd as rl
