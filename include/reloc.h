@@ -54,10 +54,10 @@ enum reloc_status {
 typedef struct reloc_forest reloc_forest;
 
 /* Intrinsics are rejected (RELOC_E_ARG) unless width and height are in
- * 1..2^24 - 1 with width * height <= 2^26, the focal lengths are positive,
- * below 2^20 px with F = round(16 f) below 2^24, |offset| * F < 2^31 and
- * |offset| * F < 2^23 * depth_min_mm * f_ref (per axis; so every probe offset
- * stays below 2^23 px), and cx, cy are finite. */
+ * 1..8191, the focal lengths are positive, below 2^20 px with F =
+ * round(16 f) below 2^24, |offset| * F < 2^31 and |offset| * F < 2^14 *
+ * depth_min_mm * f_ref (per axis; so every probe offset stays below 2^14
+ * px), and cx, cy are finite. */
 typedef struct {
     int32_t width, height;           /* frame size in pixels */
     float fx, fy, cx, cy;            /* pinhole intrinsics in pixels */

@@ -290,7 +290,8 @@ __device__ __forceinline__ uint32_t packed_colour(uint64_t w, int c)
 // threshold, and where its channel sits in a packed pixel word.
 struct ProbeNode {
     uint32_t ax, ay;   // 2 |dx Fx|, 2 |dy Fy|
-    int32_t sx, sy;    // sign of dx Fx and of dy Fy, +1 or -1
+    uint32_t sxy;      // signs of dx Fx (bits 0-15) and dy Fy (bits 16-31) as 16-bit +1 or -1
+    uint32_t spare;
     int32_t thr;
     uint32_t sh;       // bits 0-5: 16 kind, the field's bit position in the word (bits 0-4: in its
                        // 32-bit half); higher bits are not read
@@ -307,8 +308,8 @@ __device__ __forceinline__ ProbeNode probe_node(uint64_t w, const Frame &fr)
     ProbeNode n;
     n.ax = (uint32_t)(nx < 0 ? -nx : nx) << 1;
     n.ay = (uint32_t)(ny < 0 ? -ny : ny) << 1;
-    n.sx = nx < 0 ? -1 : 1;
-    n.sy = ny < 0 ? -1 : 1;
+    n.sxy = (nx < 0 ? 0xFFFFu : 1u) | ((ny < 0 ? 0xFFFFu : 1u) << 16);
+    n.spare = 0u;
     n.thr = thr;
     n.sh = 16u * (uint32_t)kind;
     n.half = 2u * (uint32_t)(kind & 2);
@@ -348,8 +349,8 @@ __device__ __forceinline__ ProbeNode probe_node_deep(const DeepNode &d, const Fr
     ProbeNode n;
     n.ax = __umul24(d.x, (uint32_t)fr.Fx);
     n.ay = __umul24(d.y, (uint32_t)fr.Fy);
-    n.sx = ((int32_t)d.x >> 31) | 1;
-    n.sy = ((int32_t)d.y >> 31) | 1;
+    n.sxy = ((((int32_t)d.x >> 31) | 1) & 0xFFFF) | ((((int32_t)d.y >> 31) | 1) << 16);
+    n.spare = 0u;
     n.thr = d.thr;
     n.sh = d.meta;
     n.half = __builtin_amdgcn_ubfe(d.meta, 6, 3);
@@ -371,30 +372,31 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t packed_rsrc(const uint64_t *pa
     return __builtin_amdgcn_make_buffer_rsrc((void *)packed, (short)0, P * 8, 0x00020000);
 }
 
-// min(max(x, 0), hi) for hi >= 0, in one instruction
-__device__ __forceinline__ int32_t clamp0(int32_t x, int32_t hi)
-{
-    int32_t r;
-    asm("v_med3_i32 %0, %1, 0, %2" : "=v"(r) : "v"(x), "v"(hi));
-    return r;
-}
+typedef short i16x2 __attribute__((ext_vector_type(2)));
+typedef unsigned short u16x2_t __attribute__((ext_vector_type(2)));
 
 // node_response_d of a prepared node, from the packed frame: `own` is the
 // pixel's own packed word. Branch-free: the probe position is clamped into
 // the image and the field's 32-bit half is loaded; a depth probe whose
 // position was clamped reads its field with width 0, that is as "no depth".
-// The offsets stay below 2^23 and W, H below 2^24 (the host checks both), so
-// 24-bit multiplies place the probe.
+// Both coordinates are placed, clamped and turned into the byte offset
+// together as 16-bit lanes (x low, y high): the host keeps W and H below 8192
+// and every probe offset below 2^14, so u + o, v + o and 8 W fit the lanes.
 __device__ __forceinline__ int32_t probe_response(__amdgpu_buffer_rsrc_t packed, int W, int H, int u, int v,
                                                   uint64_t own, const PixelDen &pd, const ProbeNode &n)
 {
     const uint32_t ox = div_mag2(n.ax, pd), oy = div_mag2(n.ay, pd);
-    const int32_t qx = __mul24((int32_t)ox, n.sx) + u;
-    const int32_t qy = __mul24((int32_t)oy, n.sy) + v;
-    const int32_t cx = clamp0(qx, W - 1), cy = clamp0(qy, H - 1);
-    const uint32_t at = ((uint32_t)__umul24((uint32_t)cy, (uint32_t)W) + (uint32_t)cx) * 8u + n.half;
+    const i16x2 o = __builtin_bit_cast(i16x2, ox | (oy << 16));
+    const i16x2 uv = __builtin_bit_cast(i16x2, (uint32_t)u | ((uint32_t)v << 16));
+    const i16x2 q = o * __builtin_bit_cast(i16x2, n.sxy) + uv;
+    const i16x2 zero = {0, 0};
+    const i16x2 hi = __builtin_bit_cast(i16x2, (uint32_t)(W - 1) | ((uint32_t)(H - 1) << 16));
+    const i16x2 c = __builtin_elementwise_min(__builtin_elementwise_max(q, zero), hi);
+    // (c.y W + c.x) 8 + half
+    const u16x2_t rowb = __builtin_bit_cast(u16x2_t, 8u | ((uint32_t)(8 * W) << 16));
+    const uint32_t at = __builtin_amdgcn_udot2(__builtin_bit_cast(u16x2_t, c), rowb, n.half, false);
     const uint32_t word = __builtin_bit_cast(uint32_t, __builtin_amdgcn_raw_buffer_load_b32(packed, (int)at, 0, 0));
-    const uint32_t width = (qx != cx || qy != cy) ? n.wout : 16u;
+    const uint32_t width = __builtin_bit_cast(uint32_t, q) != __builtin_bit_cast(uint32_t, c) ? n.wout : 16u;
     const uint32_t probed = __builtin_amdgcn_ubfe(word, n.sh, width);
     const uint32_t mine = (uint32_t)(own >> (n.sh & 63u)) & 0xFFFFu;
     return (int32_t)mine - (int32_t)probed;

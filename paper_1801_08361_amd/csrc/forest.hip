@@ -59,15 +59,13 @@ static int params_check(const reloc_params *p)
 
 static int32_t focal16(float f) { return (int32_t)floor((double)f * 16.0 + 0.5); }
 
-// intrinsics valid, width, height and the focal lengths F in 1/16 px below
-// 2^24, and |offset| * F fits 32 bits (so features stay exact)
+// intrinsics valid, width and height at most 8191, the focal lengths F in
+// 1/16 px below 2^24, and |offset| * F fits 32 bits (so features stay exact)
 static int frame_of(const Forest *f, const uint16_t *depth, const uint8_t *rgb, const reloc_intrinsics *K,
                     Frame &fr)
 {
     if (!depth || !rgb || !K) return RELOC_E_ARG;
-    if (K->width < 1 || K->height < 1 || (int64_t)K->width * K->height > (1 << 26) || K->width >= (1 << 24) ||
-        K->height >= (1 << 24))
-        return RELOC_E_ARG;
+    if (K->width < 1 || K->height < 1 || K->width > 8191 || K->height > 8191) return RELOC_E_ARG;
     if (!(K->fx > 0.0f) || !(K->fy > 0.0f) || !isfinite(K->cx) || !isfinite(K->cy) || !isfinite(K->fx) ||
         !isfinite(K->fy))
         return RELOC_E_ARG;
@@ -78,9 +76,9 @@ static int frame_of(const Forest *f, const uint16_t *depth, const uint8_t *rgb, 
     if ((int64_t)f->p.offset_pxmm * Fx > 2147483647LL || (int64_t)f->p.offset_pxmm * Fy > 2147483647LL)
         return RELOC_E_ARG;
     // and every probe offset, at most |offset| * F / (d_min * F_ref) pixels,
-    // stays below 2^23
-    const int64_t den23 = ((int64_t)f->p.depth_min_mm * f->p.f_ref_px16) << 23;
-    if ((int64_t)f->p.offset_pxmm * Fx >= den23 || (int64_t)f->p.offset_pxmm * Fy >= den23) return RELOC_E_ARG;
+    // stays below 2^14
+    const int64_t den14 = ((int64_t)f->p.depth_min_mm * f->p.f_ref_px16) << 14;
+    if ((int64_t)f->p.offset_pxmm * Fx >= den14 || (int64_t)f->p.offset_pxmm * Fy >= den14) return RELOC_E_ARG;
     if (Fx >= (1 << 24) || Fy >= (1 << 24)) return RELOC_E_ARG;
     fr.Fx = (int32_t)Fx; fr.Fy = (int32_t)Fy;
     fr.dmin = f->p.depth_min_mm; fr.dmax = f->p.depth_max_mm; fr.Fref = f->p.f_ref_px16;

@@ -280,7 +280,7 @@ def test_relocalise_failures(dev, adapted_pair):
     banner("failure: focal length beyond the 24-bit probe placement")
     with pytest.raises(rl.RelocError):
         g.relocalise(d, c, (2.0e6, 277.0, 160.0, 120.0), seed=1)
-    banner("failure: probe offsets of 2^23 px or more")
+    banner("failure: probe offsets of 2^14 px or more")
     far = rl.Forest(rl.params_default(depth_min_mm=1, f_ref_px16=1))
     with pytest.raises(rl.RelocError):
         far.adapt_frame(d, c, sc.K, sc.query_poses[2])
