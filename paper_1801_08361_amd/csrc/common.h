@@ -349,7 +349,7 @@ __device__ __forceinline__ ProbeNode probe_node_deep(const DeepNode &d, const Fr
     ProbeNode n;
     n.ax = __umul24(d.x, (uint32_t)fr.Fx);
     n.ay = __umul24(d.y, (uint32_t)fr.Fy);
-    n.sxy = ((((int32_t)d.x >> 31) | 1) & 0xFFFF) | ((((int32_t)d.y >> 31) | 1) << 16);
+    n.sxy = ((uint32_t)(((int32_t)d.x >> 31) | 1) & 0xFFFFu) | ((uint32_t)(((int32_t)d.y >> 31) | 1) << 16);
     n.spare = 0u;
     n.thr = d.thr;
     n.sh = d.meta;
