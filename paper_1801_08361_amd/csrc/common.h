@@ -364,9 +364,9 @@ __device__ __forceinline__ void stage_top(ProbeNode *__restrict__ top, const uin
     for (int k = tid; k < ntop; k += nthreads) top[k] = probe_node(tree[k], fr);
 }
 
-// A buffer resource over a packed frame of P words (P <= 2^26, checked by
-// the host): probe loads take a 32-bit byte offset from it, and the hardware
-// range-checks them against the P * 8 bytes.
+// A buffer resource over a packed frame of P words (P < 2^26: the host keeps
+// width and height at most 8191): probe loads take a 32-bit byte offset from
+// it, and the hardware range-checks them against the P * 8 bytes.
 __device__ __forceinline__ __amdgpu_buffer_rsrc_t packed_rsrc(const uint64_t *packed, int P)
 {
     return __builtin_amdgcn_make_buffer_rsrc((void *)packed, (short)0, P * 8, 0x00020000);
