@@ -245,6 +245,23 @@ __device__ __forceinline__ void bitonic_in_thread(uint32_t v[8], int tid, int k)
         }
 }
 
+// the same in the strided layout (key tid + RANK_THREADS e in register e),
+// for distance D RANK_THREADS
+template <int D>
+__device__ __forceinline__ void bitonic_strided(uint32_t v[8], int tid, int k)
+{
+#pragma unroll
+    for (int e = 0; e < 8; ++e)
+        if ((e & D) == 0) {
+            const bool asc = ((tid + RANK_THREADS * e) & k) == 0;
+            const uint32_t a = v[e], b = v[e + D];
+            if ((a > b) == asc) {
+                v[e] = b;
+                v[e + D] = a;
+            }
+        }
+}
+
 __global__ void __launch_bounds__(RANK_THREADS) k_chunk_rank(const int32_t *__restrict__ leaves, int P, int L,
                                                              int C, uint16_t *__restrict__ rank,
                                                              uint16_t *__restrict__ cnt)
@@ -269,22 +286,25 @@ __global__ void __launch_bounds__(RANK_THREADS) k_chunk_rank(const int32_t *__re
     for (int k = 2; k <= CHUNK; k <<= 1) {
         int j = k >> 1;
         if (j >= 64 * E) {
+            // distances of 512 and more: through LDS into the strided layout
+            // (key tid + 512 e in register e), where they are exchanges
+            // inside the thread, and back
 #pragma unroll
             for (int e = 0; e < E; ++e) keys[E * tid + e] = v[e];
             __syncthreads();
+#pragma unroll
+            for (int e = 0; e < E; ++e) v[e] = keys[tid + RANK_THREADS * e];
             for (; j >= 64 * E; j >>= 1) {
-                for (int i = tid; i < CHUNK; i += RANK_THREADS) {
-                    const int ixj = i ^ j;
-                    if (ixj > i) {
-                        const uint32_t a = keys[i], b = keys[ixj];
-                        if ((a > b) == ((i & k) == 0)) {
-                            keys[i] = b;
-                            keys[ixj] = a;
-                        }
-                    }
-                }
-                __syncthreads();
+                if (j == 4 * RANK_THREADS)
+                    bitonic_strided<4>(v, tid, k);
+                else if (j == 2 * RANK_THREADS)
+                    bitonic_strided<2>(v, tid, k);
+                else
+                    bitonic_strided<1>(v, tid, k);
             }
+#pragma unroll
+            for (int e = 0; e < E; ++e) keys[tid + RANK_THREADS * e] = v[e];
+            __syncthreads();
 #pragma unroll
             for (int e = 0; e < E; ++e) v[e] = keys[E * tid + e];
             __syncthreads();
