@@ -881,6 +881,7 @@ __global__ void __launch_bounds__(CULL_THREADS) k_b_cull(const Attempt *__restri
 // each other between draws). The group's energies are then summed per lane
 // in draw order and stored; the cull adds the group sums in group order. The
 // units of hypothesis block 0 also count each draw's modes.
+template <int U>
 __global__ void __launch_bounds__(64 * GROUP) k_b_score(const Attempt *__restrict__ att, Stage S, int r, int dpu,
                                                         int tm)
 {
@@ -955,6 +956,9 @@ __global__ void __launch_bounds__(64 * GROUP) k_b_score(const Attempt *__restric
                     const float y2 = fmaf(R6, dr.x, fmaf(R7, dr.y, fmaf(R8, dr.z, t2)));
                     float best = INFINITY;
                     int bj = -1;
+                    // (unrolled U times: U modes' LDS reads in flight at once; the
+                    // comparisons still run in mode order)
+#pragma unroll U
                     for (int j = 0; j < cnt; ++j) {
                         const float4 q0 = *(const float4 *)(sm + j * SMODE);
                         const float4 q1 = *(const float4 *)(sm + j * SMODE + 4);
@@ -1181,6 +1185,7 @@ struct Sched {
     int grid;        // persistent grid of the scoring kernel (0: one workgroup per unit)
     int xcd;         // XCD-contiguous unit order
     int pix;         // pixels per traversal thread (4 or 8)
+    int su;          // scoring mode-loop unroll (4 for a single attempt, else 1)
 };
 
 struct Shape {
@@ -1203,7 +1208,7 @@ struct Plan {
     std::vector<Attempt> slices;    // scratch pointers per attempt
     int32_t *d_off = nullptr;       // stage offsets of the chosen schedule
     hipGraphExec_t exec = nullptr;
-    Sched sched{GROUP, 0, 0, 4};
+    Sched sched{GROUP, 0, 0, 4, 1};
     std::string desc;
     uint64_t last_use = 0;
 };
@@ -1381,8 +1386,12 @@ static int enqueue(const Plan *pl, const Sched &sc, const Stages &st, hipStream_
     const int nw = score_waves(pl->tm_max);
     const size_t smem = (size_t)nw * pl->tm_max * SMODE * sizeof(float);
     for (int r = 0; r < pl->rounds; ++r) {
-        RL_LAUNCH("k_b_score", k_b_score, dim3(grid_of(st.score[r], sc.grid, sc.xcd)), dim3(64 * nw), smem, s, d,
-                  st.score[r], r, sc.dpu, pl->tm_max);
+        if (sc.su == 4)
+            RL_LAUNCH("k_b_score", k_b_score<4>, dim3(grid_of(st.score[r], sc.grid, sc.xcd)), dim3(64 * nw), smem,
+                      s, d, st.score[r], r, sc.dpu, pl->tm_max);
+        else
+            RL_LAUNCH("k_b_score", k_b_score<1>, dim3(grid_of(st.score[r], sc.grid, sc.xcd)), dim3(64 * nw), smem,
+                      s, d, st.score[r], r, sc.dpu, pl->tm_max);
         RL_LAUNCH("k_b_cull", k_b_cull, dim3(grid_of(att, cap, 0)), dim3(CULL_THREADS), 0, s, d, att, r);
         if (st.refine[r].total <= FUSED_REFINE) {
             RL_LAUNCH("k_b_refine", k_b_refine, dim3(grid_of(st.refine[r], 0, sc.xcd)), dim3(64), 0, s, d,
@@ -1438,11 +1447,13 @@ static std::string sched_desc(const Sched &s)
 {
     char buf[160];
     if (s.grid)
-        snprintf(buf, sizeof(buf), "draws_per_unit=%d score_grid=%d xcd_contiguous=%d pix_per_thread=%d", s.dpu,
-                 s.grid, s.xcd, s.pix);
+        snprintf(buf, sizeof(buf),
+                 "draws_per_unit=%d score_grid=%d xcd_contiguous=%d pix_per_thread=%d score_unroll=%d", s.dpu,
+                 s.grid, s.xcd, s.pix, s.su);
     else
-        snprintf(buf, sizeof(buf), "draws_per_unit=%d score_grid=per-unit xcd_contiguous=%d pix_per_thread=%d",
-                 s.dpu, s.xcd, s.pix);
+        snprintf(buf, sizeof(buf),
+                 "draws_per_unit=%d score_grid=per-unit xcd_contiguous=%d pix_per_thread=%d score_unroll=%d", s.dpu,
+                 s.xcd, s.pix, s.su);
     return buf;
 }
 
@@ -1466,14 +1477,18 @@ static int tune(reloc_batch *b, Plan *pl, hipStream_t s)
     int64_t work = 0;
     for (const Shape &sh : pl->shape) work += (int64_t)sh.W * sh.H * sh.T;
     const int pix = work >= 8000000 ? 8 : 4;
+    // a single attempt's rounds are short latency chains: the scoring
+    // kernel's mode loop unrolled (more registers, fewer resident
+    // wavefronts) shortens them; batches keep the leaner loop
+    const int su = pl->n == 1 ? 4 : 1;
     std::vector<Sched> cands;
-    cands.push_back({GROUP, 0, 0, pix});
+    cands.push_back({GROUP, 0, 0, pix, su});
     if (b->tune) {
-        cands.push_back({GROUP, 0, 1, pix});
-        cands.push_back({2 * GROUP, 0, 1, pix});
-        cands.push_back({4 * GROUP, 0, 1, pix});
-        cands.push_back({GROUP, 2048, 1, pix});
-        cands.push_back({2 * GROUP, 1024, 1, pix});
+        cands.push_back({GROUP, 0, 1, pix, su});
+        cands.push_back({2 * GROUP, 0, 1, pix, su});
+        cands.push_back({4 * GROUP, 0, 1, pix, su});
+        cands.push_back({GROUP, 2048, 1, pix, su});
+        cands.push_back({2 * GROUP, 1024, 1, pix, su});
     }
     hipEvent_t e0 = nullptr, e1 = nullptr;
     RL_HIP(hipEventCreate(&e0));
