@@ -880,7 +880,7 @@ __global__ void __launch_bounds__(CULL_THREADS) k_b_cull(const Attempt *__restri
 // the wavefront itself touches its slice, so the wavefronts do not wait for
 // each other between draws). The group's energies are then summed per lane
 // in draw order and stored; the cull adds the group sums in group order. The
-// units of hypothesis block 0 also count each draw's modes.
+// units of hypothesis block 0 also count their draws' modes.
 template <int U>
 __global__ void __launch_bounds__(64 * GROUP) k_b_score(const Attempt *__restrict__ att, Stage S, int r, int dpu,
                                                         int tm)
@@ -888,6 +888,7 @@ __global__ void __launch_bounds__(64 * GROUP) k_b_score(const Attempt *__restric
     extern __shared__ __align__(16) float smode[];
     __shared__ int32_t s_ex[GROUP][16], s_base[GROUP][16];
     __shared__ float s_e[GROUP][64];
+    __shared__ uint32_t s_cnt[GROUP];
     const int lane = __lane_id(), wv = (int)(threadIdx.x >> 6), nw = (int)(blockDim.x >> 6);
     float *sm = smode + (size_t)wv * tm * SMODE;
     FOR_UNITS(S, u) {
@@ -908,6 +909,7 @@ __global__ void __launch_bounds__(64 * GROUP) k_b_score(const Attempt *__restric
             const float t0 = lp[9], t1 = lp[10], t2 = lp[11];
             const int i1 = min((ch + 1) * dpu, A.B);
             const int64_t rb = (int64_t)r * A.B;
+            uint32_t wcnt = 0;   // this wavefront's mode count over its draws
             for (int g0 = ch * dpu; g0 < i1; g0 += GROUP) {
                 for (int k = 0; k < GROUP / nw; ++k) {
                     const int slot = k * nw + wv;
@@ -933,7 +935,7 @@ __global__ void __launch_bounds__(64 * GROUP) k_b_score(const Attempt *__restric
                         s_ex[wv][lane] = incl - nm;
                         s_base[wv][lane] = base;
                     }
-                    if (publish && has && lane == 0 && cnt) atomicAdd(&A.stats[2], (unsigned long long)cnt);
+                    wcnt += has ? (uint32_t)cnt : 0u;
                     wave_lds_sync();
                     for (int j = lane; j < cnt; j += 64) {
                         // the mode's tree: the last tree whose first mode index is <= j
@@ -994,6 +996,18 @@ __global__ void __launch_bounds__(64 * GROUP) k_b_score(const Attempt *__restric
                     if (act) A.gs[(int64_t)(g0 / GROUP) * A.N + ap] = g;
                 }
                 __syncthreads();
+            }
+            // one count per unit: the units of hypothesis block 0 add their
+            // draws' modes to the round's count (one atomic per workgroup
+            // instead of one per draw, all on the same counter)
+            if (publish) {
+                if (lane == 0) s_cnt[wv] = wcnt;
+                __syncthreads();
+                if (threadIdx.x == 0) {
+                    uint32_t c = 0;
+                    for (int w = 0; w < nw; ++w) c += s_cnt[w];
+                    if (c) atomicAdd(&A.stats[2], (unsigned long long)c);
+                }
             }
         }
     }
@@ -1095,11 +1109,15 @@ __global__ void __launch_bounds__(64) k_b_refine(const Attempt *__restrict__ att
     FOR_UNITS(S, u) {
         const int a = attempt_of(S, u);
         const Attempt &A = att[a];
-        if (A.misc[3] != r + 1) continue;
         const int sidx = u - S.off[a];
-        if (sidx >= A.misc[1]) continue;
+        // the round's counters and the survivor's slot in one round trip
+        // (sidx is below the planned survivor bound, so within the live
+        // arrays; a slot past the live count is read but not used)
+        const int4 mc = *(const int4 *)A.misc;
+        const int h = A.alive[sidx], ap = A.pos[sidx];
+        if ((mc.w != r + 1) | (sidx >= mc.y) | (h < 0) | (ap < 0)) continue;
         double s[NSUM];
-        const int h = refine_sums_of(A, r, sidx, s);
+        refine_sums_at(A, r, h, ap, s);
         if (__lane_id() == 0) refine_solve_of(A, sidx, h, s);
     }
 }
