@@ -48,6 +48,10 @@ if ROOT not in sys.path:
 FP32_PEAK_TFLOPS = 157.3          # MI355X vector FP32 (published; packed FP32)
 FLOP_PER_MODE_TERM = 25           # d: 3 sub; Sigma^-1 d: 3 mul + 6 fma; q: 1 mul + 2 fma; term: 1 fma
 FLOP_PER_PAIR = 18                # y = R c + t: 9 fma
+# refinement, per survivor besides its B inlier ids (4 B each): running sums
+# (22 doubles) read and written, live slot (hypothesis, position) read, pose
+# written (rotation and translation as doubles and floats, live FP32 copy)
+REFINE_BYTES_PER_SURVIVOR = 2 * 22 * 8 + 8 + 12 * 8 + 12 * 4 + 12 * 4
 
 
 def log(msg: str) -> None:
@@ -140,11 +144,12 @@ TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "relocalise_fullsize_hbm_traffi
 SCORE_SOURCES = ("common.h", "mlp_dev.h", "relocalise.hip")
 
 
-def score_traffic():
-    """HBM bytes per launch of the scoring kernel on the full-size workload,
-    from the committed counter profile (FETCH_SIZE and WRITE_SIZE, each scaled
-    by what the counter reads for a kernel of known traffic); None when the
-    kernel's sources differ from those profiled (sha256 recorded there)."""
+def score_traffic(kernel="k_b_score"):
+    """HBM bytes per launch of `kernel` (the scoring or the refinement kernel)
+    on the full-size workload, from the committed counter profile (FETCH_SIZE
+    and WRITE_SIZE, each scaled by what the counter reads for a kernel of
+    known traffic); None when the kernels' sources differ from those profiled
+    (sha256 recorded there)."""
     import hashlib
     import re
     try:
@@ -152,7 +157,7 @@ def score_traffic():
             text = f.read()
     except OSError:
         return None
-    m_bytes = re.search(r"k_b_score traffic bytes per launch: (\d+)", text)
+    m_bytes = re.search(kernel + r" traffic bytes per launch: (\d+)", text)
     m_hash = re.search(r"sources sha256: ([0-9a-f]{64})", text)
     if not (m_bytes and m_hash):
         return None
@@ -178,14 +183,18 @@ def profiled(run):
     return res, kernels
 
 
-def rooflines(kernels, res, attempts):
+def rooflines(kernels, res, attempts, batch_pixels=500):
     """Roofline entries of one profiled pass: the scoring kernel (FP32 ALU,
     FLOPs counted by the kernels), the traversal kernel (algorithmic bytes: 2 B
     depth + 3 B colour read and 4 B leaf index written per pixel and tree) and,
     where learned pick weights were computed in the pass, the weight kernel
-    (one network forward pass per pixel on the matrix cores). `attempts` are
-    (pixels, trees, learned) per attempt; `dominant` is the kernel with the
-    largest total time."""
+    (one network forward pass per pixel on the matrix cores) and the
+    refinement kernel (HBM: per survivor of a round, its inlier id for each of
+    the round's B draws, its running sums read and written, its slot and its
+    re-solved pose written; the gathers of its inliers' points and modes are
+    not counted, so the figure is a lower bound). `attempts` are (pixels,
+    trees, learned) per attempt, `batch_pixels` the draws per round (B);
+    `dominant` is the kernel with the largest total time."""
     out = {}
 
     def entry(name, bound, work, peak, unit):
@@ -202,6 +211,17 @@ def rooflines(kernels, res, attempts):
     out["k_b_score"] = entry("k_b_score", "alu", flops, FP32_PEAK_TFLOPS, "TFLOP/s")
     leaf_bytes = sum(P * (5 + 4 * T) for P, T, _ in attempts)
     out["k_b_leaves"] = entry("k_b_leaves", "hbm", leaf_bytes, HBM_PEAK_GBS, "GB/s")
+    surv = 0
+    for r in res:
+        na = r["n_valid"]
+        for _ in range(r["n_rounds"]):
+            na = (na + 1) // 2
+            surv += na
+    # (only where every round refined in the one-kernel form: large batched
+    # rounds split the sums and the solve over two kernels)
+    if "k_b_refine_sums" not in kernels:
+        out["k_b_refine"] = entry("k_b_refine", "hbm", surv * (4 * batch_pixels + REFINE_BYTES_PER_SURVIVOR),
+                                  HBM_PEAK_GBS, "GB/s")
     mlp = sum(P * MLP_FLOP_PER_PIXEL for P, _, learned in attempts if learned)
     if mlp:
         out["k_b_weights"] = entry("k_b_weights", "mfma", mlp, BF16_PEAK_TFLOPS, "TFLOP/s")
@@ -257,10 +277,12 @@ def plain_full(args, dev, batched: bool = True):
         ", ".join(f"{k}={v[0]:.2f}ms/{v[1]}" for k, v in sorted(kernels.items(), key=lambda kv: -kv[1][0])))
     P = queries[0][0].numel()
     roofs = rooflines(kernels, res, [(P, g.T, False)] * len(queries))
-    roof = roofs.get("k_b_score")
-    if roof is not None:
-        roof["traffic"] = score_traffic()
-        roof["traffic_source"] = "profiles/relocalise_fullsize_hbm_traffic.md (HBM bytes per launch)"
+    for kn in ("k_b_score", "k_b_refine"):
+        if roofs.get(kn) is not None:
+            roofs[kn]["traffic"] = score_traffic(kn)
+            roofs[kn]["traffic_source"] = "profiles/relocalise_fullsize_hbm_traffic.md (HBM bytes per launch)"
+    # the headline roofline is the dominant kernel's
+    roof = roofs.get(roofs.get("dominant")) or roofs.get("k_b_score")
     if not batched:
         return dict(sc=sc, value=tot / wall, wall=wall, success=ok / max(tot, 1), n=tot, kernels=kernels, roof=roof,
                     rooflines=roofs, adapt_fps=len(adapt) / t_adapt, modes_s=t_modes, mem=g.memory(), forest=g,
@@ -438,7 +460,7 @@ def batched_mixed(args, dev):
     res_prof, kernels_b = profiled(lambda: b.run(att))
     out = {"batched": {"value": n / wall_b, "unit": "relocalisations/s", "schedule": b.schedule(),
                        "success_rate": ok / len(att), "runs_ms": [round(t * 1e3, 3) for t in runs_b],
-                       "rooflines": rooflines(kernels_b, res_prof, [(P, T, False) for P, T in shapes])},
+                       "rooflines": rooflines(kernels_b, res_prof, [(P, T, False) for P, T in shapes], 64)},
            "sequential_plain": {"value": n / wall_p, "unit": "relocalisations/s"},
            "speedup": wall_p / wall_b, "identical_to_plain": identical, "success_rate": ok / len(att),
            "workload": "64 attempts, 8 forests (320x240 rooms, 5 trees depth 10, R=256, 20 frames each); "
@@ -470,7 +492,7 @@ def batched_mixed(args, dev):
         res_prof, kernels_b = profiled(lambda: bb.run(with_weights(n_hyp, use)))
         out[name] = {"value": n / wall, "unit": "relocalisations/s", "success_rate": ok / len(att),
                      "mean_valid_hypotheses": valid, "schedule": bb.schedule(),
-                     "rooflines": rooflines(kernels_b, res_prof, [(P, T, use) for P, T in shapes])}
+                     "rooflines": rooflines(kernels_b, res_prof, [(P, T, use) for P, T in shapes], 64)}
         log(f"{name}: {n / wall:.1f}/s, success {ok}/{len(att)}, valid hypotheses {valid:.1f}")
     return out
 

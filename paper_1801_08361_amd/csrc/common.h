@@ -807,13 +807,24 @@ struct Attempt {
     float4 *draws;                 // [rounds][B] camera point, pixel index bits of every draw
     int2 *dtree;                   // [rounds][B][T] per draw and tree: first global mode index (leaf * M), mode count
     float *gs;                     // [ceil(B / GROUP)][N] energy sum of each group of GROUP draws, per live position
-    int32_t *inl;                  // [B][N] global index (leaf * M + mode) of an inlier's best mode, -1 otherwise
+    int32_t *inl;                  // [ceil(B/8)][N][8] global index (leaf * M + mode) of an inlier's best mode, -1 otherwise
     unsigned long long *stats;     // [0] mode evaluations [1] pair evaluations [2] round mode count
     int32_t *tr_alive;             // [MAX_ROUNDS][N]
     float *tr_energy;              // [MAX_ROUNDS][N]
     int32_t *tr_n_alive;           // [MAX_ROUNDS]
     Result *result;
 };
+
+// The inlier ids are stored in tiles of 8 consecutive draws per live
+// position: a survivor's ids for 8 draws share one 32-byte sector (the
+// refinement reads them per survivor), and the 8 draws of one scoring group,
+// written together by the workgroup's wavefronts, fill whole tiles.
+constexpr int INL_TILE = 8;
+
+__device__ __forceinline__ int64_t inl_at(const Attempt &A, int i, int ap)
+{
+    return ((int64_t)(i / INL_TILE) * A.N + ap) * INL_TILE + (i % INL_TILE);
+}
 
 // work-unit layout of one stage over a batch: the units of attempt a are
 // [off[a], off[a+1]); off has n + 1 entries

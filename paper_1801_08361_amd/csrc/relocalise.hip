@@ -984,7 +984,7 @@ __global__ void __launch_bounds__(64 * GROUP) k_b_score(const Attempt *__restric
                         if ((d0 * d0 + d1 * d1) + d2 * d2 <= A.inl2) gid = __float_as_int(mb[10]);
                     }
                     s_e[slot][lane] = best < 0.0f ? best : 0.0f;
-                    if (act && has) A.inl[(int64_t)i * A.N + ap] = gid;
+                    if (act && has) A.inl[inl_at(A, i, ap)] = gid;
                     // this wavefront's next draw restages its own LDS slice
                     wave_lds_sync();
                 }
@@ -1042,7 +1042,7 @@ __device__ __forceinline__ void refine_sums_at(const Attempt &A, int r, int h, i
 #pragma unroll
         for (int k = 0; k < RB; ++k) {
             const int i = base + k * 64 + lane;
-            gid[k] = i < A.B ? A.inl[(int64_t)i * A.N + ap] : -1;
+            gid[k] = i < A.B ? A.inl[inl_at(A, i, ap)] : -1;
         }
         float c[RB][3], w[RB][3];
 #pragma unroll
@@ -1279,7 +1279,7 @@ static size_t carve(const Shape &s, char *base, Attempt &A)
     A.draws = (float4 *)take((size_t)rounds * s.B * 16);
     A.dtree = (int2 *)take((size_t)rounds * s.B * s.T * 8);
     A.gs = (float *)take((size_t)((s.B + GROUP - 1) / GROUP) * s.N * 4);
-    A.inl = (int32_t *)take((size_t)s.B * s.N * 4);
+    A.inl = (int32_t *)take((size_t)((s.B + INL_TILE - 1) / INL_TILE) * INL_TILE * s.N * 4);
     A.stats = (unsigned long long *)take(3 * 8);
     A.tr_alive = (int32_t *)take((size_t)MAX_ROUNDS * s.N * 4);
     A.tr_energy = (float *)take((size_t)MAX_ROUNDS * s.N * 4);
