@@ -545,7 +545,7 @@ def queue_form(args, dev):
             if r["status"] != 0:
                 continue
             md = scenes[a["forest"]].model_depth(r["pose"], device=dev, width=a["width"], height=a["height"])
-            if not rl.verify(x["depth"], md)[2]:
+            if not rl.verify(md, x["depth"])[2]:
                 continue
             acc += 1
             good = a["overlap"] and success(r["pose"], scenes[a["source"]].query_poses[a["query"]])

@@ -7,7 +7,7 @@
  * RGB-D frames of one agent (Sec. 3.3), which, given an RGB-D frame of
  * another agent's scene, either fails or returns an estimated pose of that
  * frame in its own coordinate system (Sec. 3.3.1, Fig. 4). Its leaves hold a
- * bounded set of 3D modes (at most 10 in the configurations here; Sec. 4.2.1);
+ * bounded set of 3D modes (at most 10 in the configurations here; Sec. 4.2.2);
  * new forests start with empty leaves and improve as frames arrive
  * (Sec. 4.3.1); their training samples can be deleted once trained
  * (Sec. 4.3.2). A relocalisation is correct within 5 cm and 5 degrees
@@ -118,7 +118,7 @@ int reloc_adapt_frame(reloc_forest *f, const uint16_t *depth_dev, const uint8_t 
                       const reloc_intrinsics *K, const double pose_c2w[16], void *stream);
 
 /* Extracts the modes of every leaf changed since the last call (at most
- * max_modes per leaf; Sec. 4.2.1). Relocalisation calls it implicitly.
+ * max_modes per leaf; Sec. 4.2.2). Relocalisation calls it implicitly.
  * Asynchronous on `stream`. */
 int reloc_update_modes(reloc_forest *f, void *stream);
 
@@ -215,13 +215,14 @@ int reloc_forest_memory(const reloc_forest *f, uint64_t *bytes_out);
 const char *reloc_status_string(int code);
 
 /* ---- verification of a proposed pose (Sec. 3.3.1, Eqs. 3-4) ----
- * da_dev, db_dev: device depth images [H][W] in mm, da the frame being
- * relocalised and db a rendering of the scene at the proposed pose; a pixel is
- * valid in an image when its depth is > 0. valid_frac = (pixels valid in da)
- * / (W H); mu_m = mean |da - db| over pixels valid in both, in metres
- * (+inf when there are none); accept = valid_frac > 0.5 and mu_m < 0.05.
- * Sums are exact integers. Synchronous on `stream`; allocates a 24-byte
- * device scratch per call. */
+ * da_dev, db_dev: device depth images [H][W] in mm. da is the depth of the
+ * target sub-scene rendered at the proposed pose (the paper's D_a), db the
+ * depth of the frame that was relocalised (D_b); a pixel is valid in an image
+ * when its depth is > 0. valid_frac = (pixels valid in da) / (W H), the test
+ * that the proposed pose points at the reconstructed sub-scene; mu_m = mean
+ * |da - db| over pixels valid in both, in metres (+inf when there are none);
+ * accept = valid_frac > 0.5 and mu_m < 0.05. Sums are exact integers.
+ * Synchronous on `stream`. */
 int reloc_verify(const uint16_t *da_dev, const uint16_t *db_dev, int32_t W, int32_t H, double *valid_frac,
                  double *mu_m, int32_t *accept, void *stream);
 
@@ -363,9 +364,11 @@ int reloc_debug_unit_owners(int32_t xcd, int32_t total, int32_t grid, int32_t *o
  * eigenvalue) and the device falls back to power iteration. */
 int reloc_debug_horn(const double *h_host, int32_t n, double *q_host);
 
-/* Host run of the probe-offset division (the truncating quotient of the
- * depth-adaptive offset of Sec. 3.2's features, delta F / (d F_ref), formed by
- * multiplication): q_host[i] = trunc(n_host[i] / den_host[i]) for count
+/* Host run of the probe-offset division: the truncating quotient
+ * delta F / (d F_ref) of a split feature's depth-adaptive offset (the forest
+ * of the relocaliser the paper adopts, Sec. 3.3; the paper does not define
+ * the features), formed by multiplication: q_host[i] = trunc(n_host[i] /
+ * den_host[i]) for count
  * entries, host arrays. RELOC_E_ARG if a divisor is below 1 or a numerator is
  * -2^31 (the kernels' range is |n| < 2^31, 1 <= den < 2^31). */
 int reloc_debug_div(const int32_t *n_host, const int32_t *den_host, int32_t count, int32_t *q_host);

@@ -111,6 +111,12 @@ def lib():
         L.oracle_mlp_init.restype = None
         L.oracle_mlp_forward.argtypes = [vp, vp, i32, vp]
         L.oracle_mlp_grad.argtypes = [vp, vp, vp, i32, vp, vp]
+        L.oracle_check_triple.argtypes = [vp, vp, vp, vp, vp, vp]
+        L.oracle_colour_ok.argtypes = [vp, vp, vp]
+        L.oracle_mode_term.argtypes = [vp, vp]
+        L.oracle_mode_term.restype = C.c_float
+        L.oracle_pose_from_sums.argtypes = [vp, vp, vp]
+        L.oracle_preemptive.argtypes = [vp, vp, vp, i32, i32, vp, u64, i32, vp, vp, vp, vp, vp]
         _lib = L
     return _lib
 
@@ -272,6 +278,16 @@ class Forest:
     def total_samples(self) -> int:
         return int(lib().oracle_total_samples(self._h))
 
+    @staticmethod
+    def _trace(N: int):
+        RND = 40
+        bufs = dict(pool_size=np.zeros(1, np.int32), hyp_try=np.full(N, -2, np.int32),
+                    hyp_pose=np.zeros((N, 12)), n_rounds=np.zeros(1, np.int32),
+                    n_alive=np.zeros(RND, np.int32), alive=np.full((RND, N), -1, np.int32),
+                    energy=np.zeros((RND, N), np.float32), n_inliers=np.zeros((RND, N), np.int32),
+                    pose_after=np.zeros((RND, N, 12)), final_hyp=np.full(1, -1, np.int32))
+        return bufs, Trace(cap_hyp=N, cap_rounds=RND, **{k: v.ctypes.data for k, v in bufs.items()})
+
     def relocalise(self, depth, rgb, K, seed: int, n_hyp: int = 0, weights=None, trace: bool = False):
         d = _np(depth).astype(np.uint16, copy=False)
         c = _np(rgb).astype(np.uint8, copy=False)
@@ -282,19 +298,65 @@ class Forest:
         tr = None
         bufs = {}
         if trace:
-            N = n_hyp if n_hyp > 0 else self.params.n_hypotheses
-            RND = 40
-            bufs = dict(pool_size=np.zeros(1, np.int32), hyp_try=np.full(N, -2, np.int32),
-                        hyp_pose=np.zeros((N, 12)), n_rounds=np.zeros(1, np.int32),
-                        n_alive=np.zeros(RND, np.int32), alive=np.full((RND, N), -1, np.int32),
-                        energy=np.zeros((RND, N), np.float32), n_inliers=np.zeros((RND, N), np.int32),
-                        pose_after=np.zeros((RND, N, 12)), final_hyp=np.full(1, -1, np.int32))
-            tr = Trace(cap_hyp=N, cap_rounds=RND, **{k: v.ctypes.data for k, v in bufs.items()})
+            bufs, tr = self._trace(n_hyp if n_hyp > 0 else self.params.n_hypotheses)
         rc = lib().oracle_relocalise(self._h, _p(d), _p(c), W, H, _p(_K(K)), C.c_uint64(seed), n_hyp, _p(w),
                                      _p(pose), C.byref(score), C.byref(tr) if tr is not None else None)
         if rc < 0:
             raise ValueError(rc)
         return rc, pose.reshape(4, 4), score.value, bufs
+
+    def preemptive(self, depth, rgb, K, seed: int, poses, valid):
+        """The preemptive rounds over given hypotheses: poses [n, 12] (R
+        row-major then t), valid [n]. Returns (status, pose, score, trace)."""
+        d = _np(depth).astype(np.uint16, copy=False)
+        c = _np(rgb).astype(np.uint8, copy=False)
+        H, W = d.shape
+        P = np.ascontiguousarray(poses, dtype=np.float64).reshape(-1, 12)
+        v = np.ascontiguousarray(valid, dtype=np.int32).reshape(-1)
+        assert len(P) == len(v)
+        pose = np.zeros(16)
+        score = C.c_float(0)
+        bufs, tr = self._trace(len(P))
+        rc = lib().oracle_preemptive(self._h, _p(d), _p(c), W, H, _p(_K(K)), C.c_uint64(seed), len(P), _p(P), _p(v),
+                                     _p(pose), C.byref(score), C.byref(tr))
+        if rc < 0:
+            raise ValueError(rc)
+        return rc, pose.reshape(4, 4), score.value, bufs
+
+
+TRI_OK, TRI_SAME_PIXEL, TRI_PAIR_DIST, TRI_WORLD_LONGER, TRI_CAMERA_LONGER, TRI_AREA, TRI_DEGENERATE, \
+    TRI_RESIDUAL = range(8)
+
+
+def check_triple(params: Params, pi, c, w):
+    """(check code, R, t) of one hypothesis triple: pool indices pi [3],
+    camera points c [3, 3] and mode means w [3, 3] (FP32)."""
+    pi = np.ascontiguousarray(pi, dtype=np.int32)
+    c = np.ascontiguousarray(c, dtype=np.float32).reshape(9)
+    w = np.ascontiguousarray(w, dtype=np.float32).reshape(9)
+    R = np.zeros(9); t = np.zeros(3)
+    rc = lib().oracle_check_triple(C.byref(params), _p(pi), _p(c), _p(w), _p(R), _p(t))
+    return rc, R.reshape(3, 3), t
+
+
+def colour_ok(params: Params, mode_rgb, px) -> bool:
+    a = np.ascontiguousarray(mode_rgb, dtype=np.uint8)
+    b = np.ascontiguousarray(px, dtype=np.uint8)
+    return lib().oracle_colour_ok(C.byref(params), _p(a), _p(b)) == 1
+
+
+def mode_term(mode: np.ndarray, y) -> float:
+    """The FP32 energy term of one mode (a MODE_DTYPE record) at y."""
+    m = np.ascontiguousarray(np.asarray(mode, dtype=MODE_DTYPE).reshape(1))
+    yy = np.ascontiguousarray(y, dtype=np.float32).reshape(3)
+    return float(lib().oracle_mode_term(_p(m), _p(yy)))
+
+
+def pose_from_sums(sums):
+    s = np.ascontiguousarray(sums, dtype=np.float64).reshape(22)
+    R = np.zeros(9); t = np.zeros(3)
+    rc = lib().oracle_pose_from_sums(_p(s), _p(R), _p(t))
+    return rc, R.reshape(3, 3), t
 
 
 MLP_NPARAM = 5825

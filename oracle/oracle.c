@@ -871,14 +871,65 @@ static int pick_pool(reloc_ctx *rc, const uint64_t *cdf, uint64_t u)
     return lo;
 }
 
+/* The checks of one hypothesis triple, in this order: distinct pool pixels;
+ * for each pair of points (0,1), (0,2), (1,2): camera squared distance
+ * >= min_pair2, world squared distance <= rigid_ratio2 * camera, camera
+ * <= rigid_ratio2 * world (all FP32, squared distances summed as
+ * (dx dx + dy dy) + dz dz); camera triangle |e1 x e2|^2 >= min_area2; a
+ * non-degenerate FP64 alignment of the three pairs; every residual
+ * |R c + t - w| <= resid (FP64). Returns ORACLE_TRI_OK with the pose, or the
+ * first check that fails. */
+int oracle_check_triple(const oracle_params *p, const int32_t pi[3], const float c[9], const float w[9],
+                        double R[9], double t[3])
+{
+    if (!p || !pi || !c || !w || !R || !t) return ORACLE_E_ARG;
+    if (pi[0] == pi[1] || pi[0] == pi[2] || pi[1] == pi[2]) return ORACLE_TRI_SAME_PIXEL;
+    static const int A[3] = {0, 0, 1}, B[3] = {1, 2, 2};
+    for (int e = 0; e < 3; ++e) {
+        float dc = sq3(&c[A[e] * 3], &c[B[e] * 3]);
+        float dw = sq3(&w[A[e] * 3], &w[B[e] * 3]);
+        if (!(dc >= p->min_pair2_m2)) return ORACLE_TRI_PAIR_DIST;
+        if (!(dw <= p->rigid_ratio2 * dc)) return ORACLE_TRI_WORLD_LONGER;
+        if (!(dc <= p->rigid_ratio2 * dw)) return ORACLE_TRI_CAMERA_LONGER;
+    }
+    float e1[3] = {c[3] - c[0], c[4] - c[1], c[5] - c[2]};
+    float e2[3] = {c[6] - c[0], c[7] - c[1], c[8] - c[2]};
+    float cx = e1[1] * e2[2] - e1[2] * e2[1];
+    float cy = e1[2] * e2[0] - e1[0] * e2[2];
+    float cz = e1[0] * e2[1] - e1[1] * e2[0];
+    if (!((cx * cx + cy * cy) + cz * cz >= p->min_area2_m4)) return ORACLE_TRI_AREA;
+    csums s;
+    memset(&s, 0, sizeof(s));
+    for (int j = 0; j < 3; ++j) csums_add_point(&s, &c[j * 3], &w[j * 3]);
+    if (pose_from_sums(&s, R, t)) return ORACLE_TRI_DEGENERATE;
+    double lim = (double)p->resid_m * (double)p->resid_m;
+    for (int j = 0; j < 3; ++j) {
+        double r[3];
+        for (int k = 0; k < 3; ++k)
+            r[k] = (((R[k * 3 + 0] * c[j * 3 + 0] + R[k * 3 + 1] * c[j * 3 + 1]) + R[k * 3 + 2] * c[j * 3 + 2]) + t[k]) -
+                   w[j * 3 + k];
+        if (!((r[0] * r[0] + r[1] * r[1]) + r[2] * r[2] <= lim)) return ORACLE_TRI_RESIDUAL;
+    }
+    return ORACLE_TRI_OK;
+}
+
+/* a mode may be picked for a pixel when its mean colour is within rgb_tol of
+ * the pixel's colour in every channel */
+int oracle_colour_ok(const oracle_params *p, const uint8_t mode_rgb[3], const uint8_t px[3])
+{
+    if (!p || !mode_rgb || !px) return ORACLE_E_ARG;
+    for (int ch = 0; ch < 3; ++ch) {
+        int dcol = (int)mode_rgb[ch] - (int)px[ch];
+        if (dcol < 0) dcol = -dcol;
+        if (dcol > p->rgb_tol) return 0;
+    }
+    return 1;
+}
+
 /* One hypothesis: the first of max_tries tries that passes every check.
  * Try tau draws 3 pool pixels and, for each, one mode uniformly among the
- * modes of M(p) whose mean colour is within rgb_tol of the pixel's colour in
- * every channel (no such mode fails the try).
- * Checks (FP32): distinct pixels; each camera-point pair at least
- * sqrt(min_pair2) apart and the world/camera squared-distance ratio within
- * [1 / rigid_ratio2, rigid_ratio2]; camera triangle |e1 x e2|^2 >= min_area2.
- * Then Kabsch (FP64) and every residual |R c + t - w| <= resid. */
+ * modes of M(p) that pass the colour test (no such mode fails the try); the
+ * triple must then pass oracle_check_triple. */
 static int make_hypothesis(reloc_ctx *rc, uint64_t seed, int h, const uint64_t *cdf, hyp_t *hy)
 {
     const oracle_params *p = &rc->f->p;
@@ -889,59 +940,24 @@ static int make_hypothesis(reloc_ctx *rc, uint64_t seed, int h, const uint64_t *
         uint64_t a[4], b[4];
         draw(seed, TAG_HYP, (uint64_t)h, (uint64_t)tau, 0, 0, a);
         draw(seed, TAG_HYP, (uint64_t)h, (uint64_t)tau, 1, 0, b);
-        int pi[3];
-        float c[3][3], w[3][3];
+        int32_t pi[3];
+        float c[9], w[9];
         int ok = 1;
         for (int j = 0; j < 3 && ok; ++j) {
             pi[j] = pick_pool(rc, cdf, a[j]);
             int cnt = modes_at(rc, pi[j], lst, cap);
-            /* candidate modes: colour within rgb_tol of the pixel in every channel */
             const uint8_t *px = &rc->fc.rgb[(size_t)rc->pool[pi[j]] * 3];
             int nc = 0;
-            for (int m = 0; m < cnt; ++m) {
-                int ok3 = 1;
-                for (int ch = 0; ch < 3; ++ch) {
-                    int dcol = (int)lst[m]->rgb[ch] - (int)px[ch];
-                    if (dcol < 0) dcol = -dcol;
-                    if (dcol > p->rgb_tol) ok3 = 0;
-                }
-                if (ok3) lst[nc++] = lst[m];
-            }
+            for (int m = 0; m < cnt; ++m)
+                if (oracle_colour_ok(p, lst[m]->rgb, px)) lst[nc++] = lst[m];
             if (nc == 0) { ok = 0; break; }
             int m = (int)oracle_uniform_int(b[j], (uint64_t)nc);
-            pool_cam(rc, pi[j], c[j]);
-            for (int k = 0; k < 3; ++k) w[j][k] = lst[m]->mu[k];
+            pool_cam(rc, pi[j], &c[j * 3]);
+            for (int k = 0; k < 3; ++k) w[j * 3 + k] = lst[m]->mu[k];
         }
         if (!ok) continue;
-        if (pi[0] == pi[1] || pi[0] == pi[2] || pi[1] == pi[2]) continue;
-        static const int A[3] = {0, 0, 1}, B[3] = {1, 2, 2};
-        for (int e = 0; e < 3 && ok; ++e) {
-            float dc = sq3(c[A[e]], c[B[e]]);
-            float dw = sq3(w[A[e]], w[B[e]]);
-            if (!(dc >= p->min_pair2_m2)) ok = 0;
-            else if (!(dw <= p->rigid_ratio2 * dc)) ok = 0;
-            else if (!(dc <= p->rigid_ratio2 * dw)) ok = 0;
-        }
-        if (!ok) continue;
-        float e1[3] = {c[1][0] - c[0][0], c[1][1] - c[0][1], c[1][2] - c[0][2]};
-        float e2[3] = {c[2][0] - c[0][0], c[2][1] - c[0][1], c[2][2] - c[0][2]};
-        float cx = e1[1] * e2[2] - e1[2] * e2[1];
-        float cy = e1[2] * e2[0] - e1[0] * e2[2];
-        float cz = e1[0] * e2[1] - e1[1] * e2[0];
-        if (!((cx * cx + cy * cy) + cz * cz >= p->min_area2_m4)) continue;
-        csums s;
-        memset(&s, 0, sizeof(s));
-        for (int j = 0; j < 3; ++j) csums_add_point(&s, c[j], w[j]);
         double R[9], t[3];
-        if (pose_from_sums(&s, R, t)) continue;
-        double lim = (double)p->resid_m * (double)p->resid_m;
-        for (int j = 0; j < 3 && ok; ++j) {
-            double r[3];
-            for (int k = 0; k < 3; ++k)
-                r[k] = (((R[k * 3 + 0] * c[j][0] + R[k * 3 + 1] * c[j][1]) + R[k * 3 + 2] * c[j][2]) + t[k]) - w[j][k];
-            if (!((r[0] * r[0] + r[1] * r[1]) + r[2] * r[2] <= lim)) ok = 0;
-        }
-        if (!ok) continue;
+        if (oracle_check_triple(p, pi, c, w, R, t) != ORACLE_TRI_OK) continue;
         found = tau;
         memcpy(hy->R, R, sizeof(R));
         memcpy(hy->t, t, sizeof(t));
@@ -958,7 +974,8 @@ static int make_hypothesis(reloc_ctx *rc, uint64_t seed, int h, const uint64_t *
 }
 
 /* Energy of one mode at the transformed point y (FP32, fused as written):
- *   d = y - mu; a = Sigma^-1 d; q = d . a; term = 0.5 q + kappa */
+ *   d = y - mu; a = Sigma^-1 d; q = d . a; term = 0.5 q + kappa
+ * which is -log(pi N(y; mu, Sigma)) for the mode's weight pi. */
 static float mode_term(const oracle_mode *md, const float y[3], float dd[3])
 {
     float d0 = y[0] - md->mu[0], d1 = y[1] - md->mu[1], d2 = y[2] - md->mu[2];
@@ -969,6 +986,23 @@ static float mode_term(const oracle_mode *md, const float y[3], float dd[3])
     float q = fmaf(d2, a2, fmaf(d1, a1, d0 * a0));
     dd[0] = d0; dd[1] = d1; dd[2] = d2;
     return fmaf(0.5f, q, md->kappa);
+}
+
+float oracle_mode_term(const oracle_mode *md, const float y[3])
+{
+    float dd[3];
+    return mode_term(md, y, dd);
+}
+
+int oracle_pose_from_sums(const double sums[22], double R[9], double t[3])
+{
+    if (!sums || !R || !t) return ORACLE_E_ARG;
+    csums s;
+    s.n = sums[0];
+    for (int k = 0; k < 3; ++k) { s.c[k] = sums[1 + k]; s.w[k] = sums[4 + k]; }
+    for (int k = 0; k < 9; ++k) s.cw[k] = sums[7 + k];
+    for (int k = 0; k < 6; ++k) s.cc[k] = sums[16 + k];
+    return pose_from_sums(&s, R, t);
 }
 
 typedef struct { float E; int32_t h; } ekey;
@@ -999,6 +1033,140 @@ static void trace_pose(double *dst, const double R[9], const double t[3])
 #define GROUP 8   /* energy partial sums run over groups of 8 consecutive draws */
 #define LANES 64  /* inlier sums: 64 strided partial sums, then an xor butterfly */
 
+/* the query pool (valid pixels in raster order) and each pool pixel's leaf in
+ * every tree */
+static int make_pool(oracle_forest *f, const uint16_t *depth, const uint8_t *rgb, int W, int H, const float K[4],
+                     reloc_ctx *rc)
+{
+    memset(rc, 0, sizeof(*rc));
+    rc->f = f;
+    rc->K = K;
+    make_ctx(f, depth, rgb, W, H, K, &rc->fc);
+    size_t P = (size_t)W * H;
+    rc->pool = (int32_t *)malloc(P * sizeof(int32_t));
+    if (!rc->pool) return ORACLE_E_NOMEM;
+    for (size_t q = 0; q < P; ++q)
+        if (valid_depth(&f->p, depth[q])) rc->pool[rc->np++] = (int32_t)q;
+    if (rc->np == 0) return ORACLE_OK;
+    rc->pool_leaf = (int32_t *)malloc((size_t)rc->np * f->T * sizeof(int32_t));
+    if (!rc->pool_leaf) return ORACLE_E_NOMEM;
+    for (int i = 0; i < rc->np; ++i) {
+        int q = rc->pool[i];
+        for (int t = 0; t < f->T; ++t)
+            rc->pool_leaf[(size_t)i * f->T + t] = traverse(f, &rc->fc, t, q % W, q / W, (int32_t)depth[q]);
+    }
+    return ORACLE_OK;
+}
+
+/* The preemptive loop over hypotheses hy[0..N) (at least one valid). Round r
+ * draws B pool pixels with replacement; every live hypothesis adds, per draw,
+ * min(0, min over the draw's modes of the mode term) to its energy, summed
+ * over groups of GROUP consecutive draws (each group in draw order, groups
+ * in order); the live list is sorted by (energy, index) and the first half,
+ * rounded up, survives; each survivor adds the round's inliers (draws whose
+ * best mode is within inlier_m of the transformed point) to its running
+ * correspondence sums and, with refinement on, is re-aligned on all of them.
+ * Rounds repeat while more than one hypothesis is live (at least one
+ * round). The result is the last survivor's pose and its inlier fraction. */
+static void run_rounds(reloc_ctx *rc, hyp_t *hy, int N, uint64_t attempt_seed, double pose_out[16],
+                       float *score_out, oracle_trace *tr)
+{
+    oracle_forest *f = rc->f;
+    const oracle_params *p = &f->p;
+    int B = p->batch_pixels;
+    int32_t *alive = (int32_t *)malloc((size_t)N * sizeof(int32_t));
+    int na = 0;
+    for (int h = 0; h < N; ++h)
+        if (hy[h].valid) alive[na++] = h;
+    int cap = f->T * f->M;
+    const oracle_mode **lst = (const oracle_mode **)malloc((size_t)cap * sizeof(*lst));
+    int32_t *dpool = (int32_t *)malloc((size_t)B * sizeof(int32_t));
+    float (*dc)[3] = (float (*)[3])malloc((size_t)B * sizeof(*dc));
+    ekey *ek = (ekey *)malloc((size_t)N * sizeof(ekey));
+    csums *lane = (csums *)malloc(LANES * sizeof(csums));
+    csums *tmp = (csums *)malloc(LANES * sizeof(csums));
+    float inl2 = p->inlier_m * p->inlier_m;
+    int r = 0;
+    do {
+        /* draw B pool pixels with replacement */
+        for (int i = 0; i < B; ++i) {
+            uint64_t u[4];
+            draw(attempt_seed, TAG_PIX, (uint64_t)r, (uint64_t)i, 0, 0, u);
+            dpool[i] = (int)oracle_uniform_int(u[0], (uint64_t)rc->np);
+            pool_cam(rc, dpool[i], dc[i]);
+        }
+        if (tr && tr->n_alive && r < tr->cap_rounds) tr->n_alive[r] = na;
+        for (int a = 0; a < na; ++a) {
+            hyp_t *x = &hy[alive[a]];
+            float S = 0.0f, g = 0.0f;
+            memset(lane, 0, LANES * sizeof(csums));
+            for (int i = 0; i < B; ++i) {
+                const float *c = dc[i];
+                float y[3];
+                for (int k = 0; k < 3; ++k)
+                    y[k] = fmaf(x->R32[k * 3 + 0], c[0], fmaf(x->R32[k * 3 + 1], c[1], fmaf(x->R32[k * 3 + 2], c[2], x->t32[k])));
+                int cnt = modes_at(rc, dpool[i], lst, cap);
+                float best = 0.0f;
+                int bm = -1;
+                float bd[3] = {0, 0, 0};
+                for (int m = 0; m < cnt; ++m) {
+                    float dd[3];
+                    float term = mode_term(lst[m], y, dd);
+                    if (bm < 0 || term < best) { best = term; bm = m; bd[0] = dd[0]; bd[1] = dd[1]; bd[2] = dd[2]; }
+                }
+                float e = (bm >= 0 && best < 0.0f) ? best : 0.0f;
+                g = g + e;
+                if ((i % GROUP) == GROUP - 1 || i == B - 1) { S = S + g; g = 0.0f; }
+                if (bm >= 0 && (bd[0] * bd[0] + bd[1] * bd[1]) + bd[2] * bd[2] <= inl2)
+                    csums_add_point(&lane[i % LANES], c, lst[bm]->mu);
+            }
+            x->E = x->E + S;
+            /* xor butterfly over the 64 lane sums; lane 0 holds the total */
+            for (int o = LANES / 2; o >= 1; o /= 2) {
+                for (int l = 0; l < LANES; ++l) { tmp[l] = lane[l]; csums_add(&tmp[l], &lane[l ^ o]); }
+                memcpy(lane, tmp, LANES * sizeof(csums));
+            }
+            csums_add(&x->inl, &lane[0]);
+        }
+        for (int a = 0; a < na; ++a) { ek[a].E = hy[alive[a]].E; ek[a].h = alive[a]; }
+        if (tr && r < tr->cap_rounds) {
+            for (int a = 0; a < na && a < tr->cap_hyp; ++a) {
+                if (tr->alive) tr->alive[(size_t)r * tr->cap_hyp + a] = alive[a];
+                if (tr->energy) tr->energy[(size_t)r * tr->cap_hyp + a] = hy[alive[a]].E;
+                if (tr->n_inliers) tr->n_inliers[(size_t)r * tr->cap_hyp + a] = (int32_t)hy[alive[a]].inl.n;
+            }
+        }
+        qsort(ek, (size_t)na, sizeof(ekey), cmp_ekey);
+        na = (na + 1) / 2;
+        for (int a = 0; a < na; ++a) alive[a] = ek[a].h;
+        for (int a = 0; a < na; ++a) {
+            hyp_t *x = &hy[alive[a]];
+            double R[9], t[3];
+            if (p->refine && pose_from_sums(&x->inl, R, t) == 0) {
+                memcpy(x->R, R, sizeof(R));
+                memcpy(x->t, t, sizeof(t));
+                for (int i = 0; i < 9; ++i) x->R32[i] = (float)R[i];
+                for (int i = 0; i < 3; ++i) x->t32[i] = (float)t[i];
+            }
+            if (tr && tr->pose_after && r < tr->cap_rounds && a < tr->cap_hyp)
+                trace_pose(&tr->pose_after[((size_t)r * tr->cap_hyp + a) * 12], x->R, x->t);
+        }
+        r++;
+    } while (na > 1);
+    int best = alive[0];
+    pose_to_mat(hy[best].R, hy[best].t, pose_out);
+    *score_out = (float)(hy[best].inl.n / ((double)r * (double)B));
+    if (tr && tr->n_rounds) *tr->n_rounds = r;
+    if (tr && tr->final_hyp) *tr->final_hyp = best;
+    free(alive); free(lst); free(dpool); free(dc); free(ek); free(lane); free(tmp);
+}
+
+static void free_ctx(reloc_ctx *rc)
+{
+    free(rc->pool);
+    free(rc->pool_leaf);
+}
+
 int oracle_relocalise(oracle_forest *f, const uint16_t *depth, const uint8_t *rgb, int W, int H,
                       const float K[4], uint64_t attempt_seed, int n_hyp, const uint32_t *pixel_weights,
                       double pose_out[16], float *score_out, oracle_trace *tr)
@@ -1006,27 +1174,13 @@ int oracle_relocalise(oracle_forest *f, const uint16_t *depth, const uint8_t *rg
     if (!frame_args_ok(f, depth, rgb, W, H, K) || !pose_out || !score_out) return ORACLE_E_ARG;
     const oracle_params *p = &f->p;
     int N = n_hyp > 0 ? n_hyp : p->n_hypotheses;
-    int B = p->batch_pixels;
-    reloc_ctx rc;
-    memset(&rc, 0, sizeof(rc));
-    rc.f = f;
-    rc.K = K;
-    make_ctx(f, depth, rgb, W, H, K, &rc.fc);
-    size_t P = (size_t)W * H;
-    rc.pool = (int32_t *)malloc(P * sizeof(int32_t));
-    if (!rc.pool) return ORACLE_E_NOMEM;
-    for (size_t q = 0; q < P; ++q)
-        if (valid_depth(p, depth[q])) rc.pool[rc.np++] = (int32_t)q;
-    if (tr && tr->pool_size) *tr->pool_size = rc.np;
     for (int k = 0; k < 16; ++k) pose_out[k] = (k % 5 == 0) ? 1.0 : 0.0;
     *score_out = 0.0f;
-    if (rc.np == 0) { free(rc.pool); return ORACLE_FAIL_NO_VALID_PIXELS; }
-    rc.pool_leaf = (int32_t *)malloc((size_t)rc.np * f->T * sizeof(int32_t));
-    for (int i = 0; i < rc.np; ++i) {
-        int q = rc.pool[i];
-        for (int t = 0; t < f->T; ++t)
-            rc.pool_leaf[(size_t)i * f->T + t] = traverse(f, &rc.fc, t, q % W, q / W, (int32_t)depth[q]);
-    }
+    reloc_ctx rc;
+    int st = make_pool(f, depth, rgb, W, H, K, &rc);
+    if (st) { free_ctx(&rc); return st; }
+    if (tr && tr->pool_size) *tr->pool_size = rc.np;
+    if (rc.np == 0) { free_ctx(&rc); return ORACLE_FAIL_NO_VALID_PIXELS; }
     uint64_t *cdf = NULL;
     if (pixel_weights) {
         cdf = (uint64_t *)malloc((size_t)rc.np * sizeof(uint64_t));
@@ -1034,113 +1188,64 @@ int oracle_relocalise(oracle_forest *f, const uint16_t *depth, const uint8_t *rg
         for (int i = 0; i < rc.np; ++i) { acc += pixel_weights[rc.pool[i]]; cdf[i] = acc; }
         if (acc == 0) { free(cdf); cdf = NULL; }
     }
-
     hyp_t *hy = (hyp_t *)calloc((size_t)N, sizeof(hyp_t));
-    int32_t *alive = (int32_t *)malloc((size_t)N * sizeof(int32_t));
     int na = 0;
     for (int h = 0; h < N; ++h) {
         int tau = make_hypothesis(&rc, attempt_seed, h, cdf, &hy[h]);
         if (tr && tr->hyp_try && h < tr->cap_hyp) tr->hyp_try[h] = tau;
         if (tr && tr->hyp_pose && h < tr->cap_hyp && tau >= 0) trace_pose(&tr->hyp_pose[(size_t)h * 12], hy[h].R, hy[h].t);
-        if (hy[h].valid) alive[na++] = h;
+        na += hy[h].valid;
     }
     int status = ORACLE_OK;
     if (na == 0) {
         status = f->total_samples == 0 ? ORACLE_FAIL_NO_MODES : ORACLE_FAIL_NO_HYPOTHESIS;
         if (tr && tr->n_rounds) *tr->n_rounds = 0;
-        goto done;
+    } else {
+        run_rounds(&rc, hy, N, attempt_seed, pose_out, score_out, tr);
     }
+    free(hy); free(cdf); free_ctx(&rc);
+    return status;
+}
 
-    {
-        int cap = f->T * f->M;
-        const oracle_mode **lst = (const oracle_mode **)malloc((size_t)cap * sizeof(*lst));
-        int32_t *dpool = (int32_t *)malloc((size_t)B * sizeof(int32_t));
-        float (*dc)[3] = (float (*)[3])malloc((size_t)B * sizeof(*dc));
-        ekey *ek = (ekey *)malloc((size_t)N * sizeof(ekey));
-        csums *lane = (csums *)malloc(LANES * sizeof(csums));
-        csums *tmp = (csums *)malloc(LANES * sizeof(csums));
-        float inl2 = p->inlier_m * p->inlier_m;
-        int r = 0;
-        do {
-            /* draw B pool pixels with replacement */
-            for (int i = 0; i < B; ++i) {
-                uint64_t u[4];
-                draw(attempt_seed, TAG_PIX, (uint64_t)r, (uint64_t)i, 0, 0, u);
-                dpool[i] = (int)oracle_uniform_int(u[0], (uint64_t)rc.np);
-                pool_cam(&rc, dpool[i], dc[i]);
-            }
-            if (tr && tr->n_alive && r < tr->cap_rounds) tr->n_alive[r] = na;
-            for (int a = 0; a < na; ++a) {
-                hyp_t *x = &hy[alive[a]];
-                float S = 0.0f, g = 0.0f;
-                memset(lane, 0, LANES * sizeof(csums));
-                for (int i = 0; i < B; ++i) {
-                    const float *c = dc[i];
-                    float y[3];
-                    for (int k = 0; k < 3; ++k)
-                        y[k] = fmaf(x->R32[k * 3 + 0], c[0], fmaf(x->R32[k * 3 + 1], c[1], fmaf(x->R32[k * 3 + 2], c[2], x->t32[k])));
-                    int cnt = modes_at(&rc, dpool[i], lst, cap);
-                    float best = 0.0f;
-                    int bm = -1;
-                    float bd[3] = {0, 0, 0};
-                    for (int m = 0; m < cnt; ++m) {
-                        float dd[3];
-                        float term = mode_term(lst[m], y, dd);
-                        if (bm < 0 || term < best) { best = term; bm = m; bd[0] = dd[0]; bd[1] = dd[1]; bd[2] = dd[2]; }
-                    }
-                    float e = (bm >= 0 && best < 0.0f) ? best : 0.0f;
-                    g = g + e;
-                    if ((i % GROUP) == GROUP - 1 || i == B - 1) { S = S + g; g = 0.0f; }
-                    if (bm >= 0 && (bd[0] * bd[0] + bd[1] * bd[1]) + bd[2] * bd[2] <= inl2)
-                        csums_add_point(&lane[i % LANES], c, lst[bm]->mu);
-                }
-                x->E = x->E + S;
-                /* xor butterfly over the 64 lane sums; lane 0 holds the total */
-                for (int o = LANES / 2; o >= 1; o /= 2) {
-                    for (int l = 0; l < LANES; ++l) { tmp[l] = lane[l]; csums_add(&tmp[l], &lane[l ^ o]); }
-                    memcpy(lane, tmp, LANES * sizeof(csums));
-                }
-                csums_add(&x->inl, &lane[0]);
-            }
-            for (int a = 0; a < na; ++a) { ek[a].E = hy[alive[a]].E; ek[a].h = alive[a]; }
-            if (tr && r < tr->cap_rounds) {
-                for (int a = 0; a < na && a < tr->cap_hyp; ++a) {
-                    if (tr->alive) tr->alive[(size_t)r * tr->cap_hyp + a] = alive[a];
-                    if (tr->energy) tr->energy[(size_t)r * tr->cap_hyp + a] = hy[alive[a]].E;
-                    if (tr->n_inliers) tr->n_inliers[(size_t)r * tr->cap_hyp + a] = (int32_t)hy[alive[a]].inl.n;
-                }
-            }
-            qsort(ek, (size_t)na, sizeof(ekey), cmp_ekey);
-            na = (na + 1) / 2;
-            for (int a = 0; a < na; ++a) alive[a] = ek[a].h;
-            for (int a = 0; a < na; ++a) {
-                hyp_t *x = &hy[alive[a]];
-                double R[9], t[3];
-                if (p->refine && pose_from_sums(&x->inl, R, t) == 0) {
-                    memcpy(x->R, R, sizeof(R));
-                    memcpy(x->t, t, sizeof(t));
-                    for (int i = 0; i < 9; ++i) x->R32[i] = (float)R[i];
-                    for (int i = 0; i < 3; ++i) x->t32[i] = (float)t[i];
-                }
-                if (tr && tr->pose_after && r < tr->cap_rounds && a < tr->cap_hyp)
-                    trace_pose(&tr->pose_after[((size_t)r * tr->cap_hyp + a) * 12], x->R, x->t);
-            }
-            r++;
-        } while (na > 1);
-        int best = alive[0];
-        pose_to_mat(hy[best].R, hy[best].t, pose_out);
-        *score_out = (float)(hy[best].inl.n / ((double)r * (double)B));
-        if (tr && tr->n_rounds) *tr->n_rounds = r;
-        if (tr && tr->final_hyp) *tr->final_hyp = best;
-        free(lst); free(dpool); free(dc); free(ek); free(lane); free(tmp);
+/* The preemptive loop alone, over caller-given hypotheses: poses [n][12]
+ * (R row-major, then t, FP64), valid [n]; the same rounds as
+ * oracle_relocalise runs after generating its hypotheses. */
+int oracle_preemptive(oracle_forest *f, const uint16_t *depth, const uint8_t *rgb, int W, int H, const float K[4],
+                      uint64_t attempt_seed, int n_hyp, const double *poses, const int32_t *valid, double pose_out[16],
+                      float *score_out, oracle_trace *tr)
+{
+    if (!frame_args_ok(f, depth, rgb, W, H, K) || !pose_out || !score_out || n_hyp < 1 || !poses || !valid)
+        return ORACLE_E_ARG;
+    for (int k = 0; k < 16; ++k) pose_out[k] = (k % 5 == 0) ? 1.0 : 0.0;
+    *score_out = 0.0f;
+    reloc_ctx rc;
+    int st = make_pool(f, depth, rgb, W, H, K, &rc);
+    if (st) { free_ctx(&rc); return st; }
+    if (tr && tr->pool_size) *tr->pool_size = rc.np;
+    if (rc.np == 0) { free_ctx(&rc); return ORACLE_FAIL_NO_VALID_PIXELS; }
+    hyp_t *hy = (hyp_t *)calloc((size_t)n_hyp, sizeof(hyp_t));
+    int na = 0;
+    for (int h = 0; h < n_hyp; ++h) {
+        hy[h].valid = valid[h] != 0;
+        memcpy(hy[h].R, poses + (size_t)h * 12, 9 * sizeof(double));
+        memcpy(hy[h].t, poses + (size_t)h * 12 + 9, 3 * sizeof(double));
+        for (int i = 0; i < 9; ++i) hy[h].R32[i] = (float)hy[h].R[i];
+        for (int i = 0; i < 3; ++i) hy[h].t32[i] = (float)hy[h].t[i];
+        na += hy[h].valid;
     }
-done:
-    free(hy); free(alive); free(rc.pool); free(rc.pool_leaf); free(cdf);
+    int status = ORACLE_OK;
+    if (na == 0) {
+        status = ORACLE_FAIL_NO_HYPOTHESIS;
+        if (tr && tr->n_rounds) *tr->n_rounds = 0;
+    } else {
+        run_rounds(&rc, hy, n_hyp, attempt_seed, pose_out, score_out, tr);
+    }
+    free(hy); free_ctx(&rc);
     return status;
 }
 
 /* ------------------------------------------------------------------------ */
-/* success criterion: <= 5 cm and <= 5 degrees (Sec. 4.2.1, Table 2)        */
+/* success criterion: <= 5 cm and <= 5 degrees (Sec. 4.2.2, Table 2)        */
 /* ------------------------------------------------------------------------ */
 
 int oracle_pose_success(const double est[16], const double gt[16], double *dt_m, double *dang_deg)

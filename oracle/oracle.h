@@ -11,8 +11,8 @@
  * regression-forest relocaliser online for each sub-scene (Sec. 3.3) and uses
  * it as a black box that, given an RGB-D frame, either fails or returns a
  * pose (Sec. 3.3.1, Fig. 4). It fixes the success criterion (<= 5 cm and
- * <= 5 deg, Sec. 4.2.1 / Table 2), the number of leaf modes (at most 10 or 50,
- * Sec. 4.2.1), that forests start with empty leaves and train online
+ * <= 5 deg, Sec. 4.2.2 / Table 2), the number of leaf modes (at most 10 or 50,
+ * Sec. 4.2.2), that forests start with empty leaves and train online
  * (Sec. 4.3.1), and that the training data can be deleted once trained
  * (Sec. 4.3.2). Every other rule below (features, reservoirs, mode finding,
  * hypothesis sampling, energies, culls, refinement) is this implementation's
@@ -121,6 +121,35 @@ int  oracle_relocalise(oracle_forest *f, const uint16_t *depth, const uint8_t *r
                        double pose_out[16], float *score_out, oracle_trace *trace);
 
 int  oracle_pose_success(const double est[16], const double gt[16], double *dt_m, double *dang_deg);
+
+/* ---- single steps of the relocalisation, exported for their pins ---- */
+enum {
+    ORACLE_TRI_OK = 0,            /* the triple passes every check */
+    ORACLE_TRI_SAME_PIXEL = 1,    /* two picks are the same pool pixel */
+    ORACLE_TRI_PAIR_DIST = 2,     /* a camera pair is closer than sqrt(min_pair2) */
+    ORACLE_TRI_WORLD_LONGER = 3,  /* world squared distance > rigid_ratio2 * camera squared distance */
+    ORACLE_TRI_CAMERA_LONGER = 4, /* camera squared distance > rigid_ratio2 * world squared distance */
+    ORACLE_TRI_AREA = 5,          /* camera triangle |e1 x e2|^2 < min_area2 */
+    ORACLE_TRI_DEGENERATE = 6,    /* the alignment is undetermined (see oracle_pose_from_sums) */
+    ORACLE_TRI_RESIDUAL = 7,      /* a residual |R c + t - w| exceeds resid */
+};
+/* checks of one hypothesis triple: pool indices pi[3], camera points c[3][3]
+ * and picked mode means w[3][3]; the pose on ORACLE_TRI_OK */
+int  oracle_check_triple(const oracle_params *p, const int32_t pi[3], const float c[9], const float w[9],
+                         double R[9], double t[3]);
+/* 1 iff the mode's colour is within rgb_tol of the pixel's in every channel */
+int  oracle_colour_ok(const oracle_params *p, const uint8_t mode_rgb[3], const uint8_t px[3]);
+/* the FP32 energy term kappa + q / 2 of a mode at y */
+float oracle_mode_term(const oracle_mode *md, const float y[3]);
+/* pose from correspondence sums {n, sum c (3), sum w (3), sum c w^T (9, row
+ * a col b), sum c c^T (xx xy xz yy yz zz)}; 0 and (R, t), or 1 when fewer
+ * than 3 points or the camera points are degenerate (I2 < 1e-4 n trace) */
+int  oracle_pose_from_sums(const double sums[22], double R[9], double t[3]);
+/* the preemptive rounds over caller-given hypotheses: poses [n][12] (R
+ * row-major then t), valid [n] */
+int  oracle_preemptive(oracle_forest *f, const uint16_t *depth, const uint8_t *rgb, int W, int H, const float K[4],
+                       uint64_t attempt_seed, int n_hyp, const double *poses, const int32_t *valid,
+                       double pose_out[16], float *score_out, oracle_trace *trace);
 
 /* ---- depth-difference verification (Sec. 3.3.1, Eqs. 3-4) ----
  * valid fraction |Omega_a| / |Omega| of the rendered depth da, and the mean

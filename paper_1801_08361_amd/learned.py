@@ -55,13 +55,15 @@ def training_rows(forest: Forest, frames: Iterable[tuple], max_pixels: Optional[
 
 def verified_pose(forest: Forest, depth, rgb, K, seed: int, model_depth: Callable, n_hyp: int = 0):
     """Relocalises a frame and checks the result as the paper does before
-    trusting it (Sec. 3.3.1, Eqs. 3-4): the frame's depth against the scene
-    model's depth rendered at the proposed pose (`model_depth(pose)` returns a
-    device uint16 image of the same size). Returns (pose or None, result)."""
+    trusting it (Sec. 3.3.1, Eqs. 3-4): the scene model's depth rendered at
+    the proposed pose (`model_depth(pose)` returns a device uint16 image of the
+    same size) is the first image, whose valid fraction says whether the pose
+    points at the modelled scene, and the frame's own depth the second.
+    Returns (pose or None, result)."""
     r = forest.relocalise_ex(depth, rgb, K, seed=seed, n_hyp=n_hyp)
     if r["status"] != 0:
         return None, r
-    vf, mu, ok = verify(depth, model_depth(r["pose"]))
+    vf, mu, ok = verify(model_depth(r["pose"]), depth)
     r["verify"] = (vf, mu, ok)
     return (r["pose"] if ok else None), r
 

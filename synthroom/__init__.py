@@ -5,7 +5,7 @@ This module holds none of the relocaliser's arithmetic. It draws box rooms
 with a procedural texture, smooth camera trajectories, and renders depth
 (uint16 millimetres along the optical axis) and RGB8 frames for them. It
 stands in for the 7-Scenes and ZenFone sequences the paper measures on
-(Table 2, Sec. 4.2.1; dataset appendix), neither of which is available.
+(Table 2, Sec. 4.2.2; dataset appendix), neither of which is available.
 
 Conventions
 -----------

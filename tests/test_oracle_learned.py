@@ -40,6 +40,21 @@ def test_verify_closed_forms(orc):
     assert mu == 0.0 and acc
 
 
+def test_verify_valid_fraction_is_the_renders(orc):
+    """|Omega_a| / |Omega| is taken over D_a, the render at the estimated pose:
+    a pose that looks mostly past the modelled scene (render 30 % valid,
+    matching the query where valid) is rejected although the query frame is
+    fully valid; taking the fraction over the query would accept it."""
+    rng = np.random.default_rng(4)
+    query = rng.integers(800, 4000, size=(60, 80)).astype(np.uint16)
+    render = query.copy()
+    render[:, 24:] = 0                       # 24 of 80 columns valid: 30 %
+    vf, mu, acc = orc.verify(render, query)
+    assert vf == pytest.approx(0.3) and mu == 0.0 and not acc
+    vf_q, _, acc_q = orc.verify(query, render)
+    assert vf_q == 1.0 and acc_q
+
+
 def test_bf16_matches_torch(orc):
     rng = np.random.default_rng(1)
     xs = np.concatenate([rng.normal(size=3000).astype(np.float32) * 10.0 ** rng.integers(-6, 6, size=3000),

@@ -1,7 +1,8 @@
 """The kernels' probe-offset division (a multiply-high by a per-pixel
 multiplier instead of a divide) against exact integer truncation, on the host
-build of the same functions. The offset of a depth-adaptive feature (Sec. 3.2)
-is trunc(delta F / (d F_ref)); numerators stay below 2^31 in magnitude and the
+build of the same functions. The offset of a split's depth-adaptive feature
+(this library's definition; the paper leaves the features to the relocaliser
+it adopts) is trunc(delta F / (d F_ref)); numerators stay below 2^31 in magnitude and the
 divisor d F_ref is at least 1."""
 import numpy as np
 import pytest
