@@ -7,7 +7,7 @@
  * RGB-D frames of one agent (Sec. 3.3), which, given an RGB-D frame of
  * another agent's scene, either fails or returns an estimated pose of that
  * frame in its own coordinate system (Sec. 3.3.1, Fig. 4). Its leaves hold a
- * bounded set of 3D modes (at most 10 in the configurations here; Sec. 4.2.2);
+ * bounded set of 3D modes (at most 10 or 50, Sec. 4.2.2);
  * new forests start with empty leaves and improve as frames arrive
  * (Sec. 4.3.1); their training samples can be deleted once trained
  * (Sec. 4.3.2). A relocalisation is correct within 5 cm and 5 degrees
@@ -48,7 +48,8 @@ enum reloc_status {
     RELOC_E_NOMEM = -2,              /* device allocation failed */
     RELOC_E_HIP = -3,                /* a HIP runtime call failed */
     RELOC_E_STATE = -4,              /* operation not valid in this state (e.g. adapt after drop) */
-    RELOC_E_RANGE = -5               /* a value does not fit the packed device layout */
+    RELOC_E_RANGE = -5,              /* a value does not fit the packed device layout */
+    RELOC_E_IO = -6                  /* a checkpoint file cannot be written or read, or is not one */
 };
 
 typedef struct reloc_forest reloc_forest;
@@ -70,7 +71,7 @@ typedef struct {
     int32_t n_trees;          /* T, 1..16 */
     int32_t depth;            /* D: 2^D leaves and 2^D - 1 split nodes per tree, 1..16 */
     int32_t reservoir_size;   /* R samples kept per leaf, 1..1024 */
-    int32_t max_modes;        /* M modes per leaf, 1..32 */
+    int32_t max_modes;        /* M modes per leaf, 1..64 (T * M <= 512) */
     uint64_t seed;            /* forest seed: split parameters and reservoir draws */
     int32_t depth_min_mm, depth_max_mm;   /* valid depth range (inclusive) */
     int32_t offset_pxmm;      /* split offsets uniform in [-O, O] px*mm at the reference focal length */
@@ -207,6 +208,25 @@ int reloc_batch_memory(const reloc_batch *b, uint64_t *bytes_out);
  * Sec. 4.3.2). Relocalisation results are unchanged; further adaptation
  * returns RELOC_E_STATE. */
 int reloc_forest_drop_reservoirs(reloc_forest *f, void *stream);
+
+/* Checkpoint of a forest (the paper trains each relocaliser online and can
+ * delete its training data once trained, Sec. 4.3.2; a saved forest resumes
+ * exactly where it stopped). reloc_forest_save builds every pending mode and
+ * writes the split nodes, leaf counters, modes and, unless they were dropped,
+ * the reservoirs to the file at `path` (a 640x480-class forest of 5 trees of
+ * depth 15 with 1024-entry reservoirs is about 2.8 GB; about 85 MB after
+ * reloc_forest_drop_reservoirs). reloc_forest_load creates a new forest on the
+ * current device from such a file: adapting it further, or relocalising with
+ * it, gives bit for bit what the saved forest would have given. Both are
+ * synchronous on `stream`. Errors: RELOC_E_ARG (null pointer), RELOC_E_IO (the
+ * file cannot be opened, written or read, or has the wrong magic, version,
+ * sizes or trailing bytes), RELOC_E_RANGE (a stored split node does not fit
+ * the stored parameters), the errors of reloc_forest_create. */
+int reloc_forest_save(reloc_forest *f, const char *path, void *stream);
+int reloc_forest_load(const char *path, void *stream, reloc_forest **out);
+
+/* The parameters the forest was created (or loaded) with. */
+int reloc_forest_params(const reloc_forest *f, reloc_params *out);
 
 /* Device bytes currently held by the forest. */
 int reloc_forest_memory(const reloc_forest *f, uint64_t *bytes_out);

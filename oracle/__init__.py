@@ -111,6 +111,8 @@ def lib():
         L.oracle_mlp_init.restype = None
         L.oracle_mlp_forward.argtypes = [vp, vp, i32, vp]
         L.oracle_mlp_grad.argtypes = [vp, vp, vp, i32, vp, vp]
+        L.oracle_forest_save.argtypes = [vp, C.c_char_p]
+        L.oracle_forest_load.argtypes = [C.c_char_p, vp]
         L.oracle_check_triple.argtypes = [vp, vp, vp, vp, vp, vp]
         L.oracle_colour_ok.argtypes = [vp, vp, vp]
         L.oracle_mode_term.argtypes = [vp, vp]
@@ -196,12 +198,15 @@ def _K(K) -> np.ndarray:
 class Forest:
     """One relocalisation forest held by the oracle."""
 
-    def __init__(self, params: Params):
+    def __init__(self, params: Params, _handle=None):
         self.params = params
         self._h = C.c_void_p()
-        rc = lib().oracle_forest_create(C.byref(params), C.byref(self._h))
-        if rc != 0:
-            raise ValueError(f"oracle_forest_create failed: {rc}")
+        if _handle is not None:
+            self._h = _handle
+        else:
+            rc = lib().oracle_forest_create(C.byref(params), C.byref(self._h))
+            if rc != 0:
+                raise ValueError(f"oracle_forest_create failed: {rc}")
         self.T = params.n_trees
         self.L = 1 << params.depth
         self.R = params.reservoir_size
@@ -267,6 +272,22 @@ class Forest:
         if rc != 0:
             raise ValueError(rc)
         return m[: nm.value].copy()
+
+    def save(self, path: str) -> None:
+        rc = lib().oracle_forest_save(self._h, os.fsencode(path))
+        if rc != 0:
+            raise ValueError(f"oracle_forest_save failed: {rc}")
+
+    @classmethod
+    def load(cls, path: str, params: Params) -> "Forest":
+        """A forest from a checkpoint file; `params` must be those it was
+        saved with (the file carries them too, and the load checks nothing
+        against these)."""
+        h = C.c_void_p()
+        rc = lib().oracle_forest_load(os.fsencode(path), C.byref(h))
+        if rc != 0:
+            raise ValueError(f"oracle_forest_load failed: {rc}")
+        return cls(params, _handle=h)
 
     def build_all_modes(self) -> None:
         assert lib().oracle_build_all_modes(self._h) == 0

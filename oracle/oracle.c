@@ -15,6 +15,7 @@
 #include "oracle.h"
 
 #include <math.h>
+#include <stdio.h>
 #include <stdlib.h>
 #include <string.h>
 
@@ -413,6 +414,67 @@ int oracle_drop_reservoirs(oracle_forest *f)
     free(f->res);
     f->res = NULL;
     f->dropped = 1;
+    return ORACLE_OK;
+}
+
+/* ------------------------------------------------------------------------ */
+/* checkpoint: the whole forest state in a file of the oracle's own layout  */
+/* (parameters, flags, split nodes, counters, lazily built modes and, unless */
+/* dropped, the reservoirs), so that a saved forest resumes exactly.        */
+/* ------------------------------------------------------------------------ */
+
+static const char ORACLE_MAGIC[8] = {'O', 'R', 'A', 'C', 'L', 'E', 'F', '1'};
+
+int oracle_forest_save(const oracle_forest *f, const char *path)
+{
+    if (!f || !path) return ORACLE_E_ARG;
+    FILE *fp = fopen(path, "wb");
+    if (!fp) return ORACLE_E_IO;
+    size_t TL = (size_t)f->T * f->L, ns = (size_t)f->T * (f->L - 1);
+    int32_t dropped = f->dropped;
+    int ok = fwrite(ORACLE_MAGIC, 1, 8, fp) == 8 && fwrite(&f->p, sizeof(f->p), 1, fp) == 1 &&
+             fwrite(&dropped, sizeof(dropped), 1, fp) == 1 &&
+             fwrite(&f->total_samples, sizeof(f->total_samples), 1, fp) == 1 &&
+             fwrite(f->nodes, sizeof(onode), ns, fp) == ns && fwrite(f->extra, sizeof(onode), 8, fp) == 8 &&
+             fwrite(f->counter, sizeof(uint32_t), TL, fp) == TL && fwrite(f->nmodes, sizeof(int32_t), TL, fp) == TL &&
+             fwrite(f->modes, sizeof(oracle_mode), TL * f->M, fp) == TL * f->M &&
+             (f->dropped || fwrite(f->res, sizeof(oracle_entry), TL * f->R, fp) == TL * f->R);
+    if (fclose(fp) != 0) ok = 0;
+    return ok ? ORACLE_OK : ORACLE_E_IO;
+}
+
+int oracle_forest_load(const char *path, oracle_forest **out)
+{
+    if (!path || !out) return ORACLE_E_ARG;
+    *out = NULL;
+    FILE *fp = fopen(path, "rb");
+    if (!fp) return ORACLE_E_IO;
+    char magic[8];
+    oracle_params p;
+    int32_t dropped = 0;
+    uint64_t total = 0;
+    if (fread(magic, 1, 8, fp) != 8 || memcmp(magic, ORACLE_MAGIC, 8) != 0 || fread(&p, sizeof(p), 1, fp) != 1 ||
+        fread(&dropped, sizeof(dropped), 1, fp) != 1 || fread(&total, sizeof(total), 1, fp) != 1) {
+        fclose(fp);
+        return ORACLE_E_IO;
+    }
+    oracle_forest *f = NULL;
+    int rc = oracle_forest_create(&p, &f);
+    if (rc) { fclose(fp); return rc; }
+    size_t TL = (size_t)f->T * f->L, ns = (size_t)f->T * (f->L - 1);
+    int ok = fread(f->nodes, sizeof(onode), ns, fp) == ns && fread(f->extra, sizeof(onode), 8, fp) == 8 &&
+             fread(f->counter, sizeof(uint32_t), TL, fp) == TL && fread(f->nmodes, sizeof(int32_t), TL, fp) == TL &&
+             fread(f->modes, sizeof(oracle_mode), TL * f->M, fp) == TL * f->M &&
+             (dropped || fread(f->res, sizeof(oracle_entry), TL * f->R, fp) == TL * f->R) && fgetc(fp) == EOF;
+    fclose(fp);
+    if (!ok) { oracle_forest_destroy(f); return ORACLE_E_IO; }
+    f->total_samples = total;
+    if (dropped) {
+        free(f->res);
+        f->res = NULL;
+        f->dropped = 1;
+    }
+    *out = f;
     return ORACLE_OK;
 }
 

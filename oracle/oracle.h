@@ -77,6 +77,7 @@ enum {
     ORACLE_FAIL_NO_HYPOTHESIS = 3,
     ORACLE_E_ARG = -1,
     ORACLE_E_NOMEM = -2,
+    ORACLE_E_IO = -6,
 };
 
 typedef struct oracle_forest oracle_forest;
@@ -109,6 +110,10 @@ int  oracle_modes_from_points(const oracle_params *p, const oracle_entry *pts, i
 int  oracle_modes_bruteforce(const oracle_params *p, const oracle_entry *pts, int n,
                              oracle_mode *modes, int32_t *n_modes, int32_t *labels);
 int  oracle_build_all_modes(oracle_forest *f);
+/* checkpoint of the whole forest state in the oracle's own file layout;
+ * ORACLE_E_IO for a file that cannot be written or read or is not one */
+int  oracle_forest_save(const oracle_forest *f, const char *path);
+int  oracle_forest_load(const char *path, oracle_forest **out);
 int  oracle_drop_reservoirs(oracle_forest *f);
 uint64_t oracle_total_samples(const oracle_forest *f);
 

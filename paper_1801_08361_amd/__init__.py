@@ -26,6 +26,7 @@ E_NOMEM = -2
 E_HIP = -3
 E_STATE = -4
 E_RANGE = -5
+E_IO = -6
 
 
 class RelocError(RuntimeError):
@@ -95,6 +96,9 @@ _SIGS = {
     "reloc_relocalise": [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_uint64, C.c_int32, C.c_void_p,
                          C.c_void_p, C.c_void_p, C.c_void_p],
     "reloc_forest_drop_reservoirs": [C.c_void_p, C.c_void_p],
+    "reloc_forest_save": [C.c_void_p, C.c_char_p, C.c_void_p],
+    "reloc_forest_load": [C.c_char_p, C.c_void_p, C.c_void_p],
+    "reloc_forest_params": [C.c_void_p, C.c_void_p],
     "reloc_forest_memory": [C.c_void_p, C.c_void_p],
     "reloc_status_string": [C.c_int],
     "reloc_debug_nodes": [C.c_void_p] * 5,
@@ -260,15 +264,35 @@ def _pose(T) -> np.ndarray:
 class Forest:
     """One sub-scene relocaliser held on the GPU (reloc_forest)."""
 
-    def __init__(self, params: Optional[reloc_params] = None, stream=None, **kw):
-        self.params = params if params is not None else params_default(**kw)
+    def __init__(self, params: Optional[reloc_params] = None, stream=None, _handle=None, **kw):
         self._h = C.c_void_p()
-        _check(lib().reloc_forest_create(C.byref(self.params), _stream(stream), C.byref(self._h)),
-               "reloc_forest_create")
+        if _handle is not None:
+            self._h = _handle
+            self.params = params
+        else:
+            self.params = params if params is not None else params_default(**kw)
+            _check(lib().reloc_forest_create(C.byref(self.params), _stream(stream), C.byref(self._h)),
+                   "reloc_forest_create")
         self.T = self.params.n_trees
         self.L = 1 << self.params.depth
         self.R = self.params.reservoir_size
         self.M = self.params.max_modes
+
+    def save(self, path: str, stream=None) -> None:
+        """Checkpoint to a file (reloc_forest_save)."""
+        _check(lib().reloc_forest_save(self._h, os.fsencode(path), _stream(stream)), "reloc_forest_save")
+
+    @classmethod
+    def load(cls, path: str, stream=None) -> "Forest":
+        """A new forest from a checkpoint file (reloc_forest_load)."""
+        h = C.c_void_p()
+        _check(lib().reloc_forest_load(os.fsencode(path), _stream(stream), C.byref(h)), "reloc_forest_load")
+        p = reloc_params()
+        rc = lib().reloc_forest_params(h, C.byref(p))
+        if rc < 0:
+            lib().reloc_forest_destroy(h)
+            raise RelocError(rc, "reloc_forest_params")
+        return cls(p, _handle=h)
 
     @property
     def handle(self) -> C.c_void_p:

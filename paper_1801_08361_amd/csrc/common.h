@@ -78,6 +78,7 @@ constexpr int CHUNK = 4096;     // pixels per reservoir-rank chunk
 constexpr int MAX_HYP = 4096;
 constexpr int MAX_B = 2048;
 constexpr int MAX_R = 1024;
+constexpr int MAX_M = 64;       // modes per leaf
 constexpr int MAX_TM = 512;     // modes over all trees of one pixel (T * M)
 constexpr int MAX_ROUNDS = 13;  // ceil(log2(MAX_HYP)) + 1
 

@@ -10,10 +10,12 @@
 // chunk plus a per-leaf prefix over chunks; "largest k wins" is an atomicMax
 // on a per-slot stamp followed by the write of the single winner.
 #include <math.h>
+#include <stdio.h>
 #include <string.h>
 
 #include <algorithm>
 #include <new>
+#include <vector>
 
 #include "common.h"
 
@@ -40,7 +42,8 @@ static void params_default(reloc_params *p)
 static int params_check(const reloc_params *p)
 {
     if (p->n_trees < 1 || p->n_trees > 16 || p->depth < 1 || p->depth > 16) return RELOC_E_ARG;
-    if (p->reservoir_size < 1 || p->reservoir_size > MAX_R || p->max_modes < 1 || p->max_modes > 32)
+    if (p->reservoir_size < 1 || p->reservoir_size > MAX_R || p->max_modes < 1 || p->max_modes > MAX_M ||
+        p->n_trees * p->max_modes > MAX_TM)
         return RELOC_E_ARG;
     if (p->n_hypotheses < 1 || p->n_hypotheses > MAX_HYP || p->batch_pixels < 1 || p->batch_pixels > MAX_B)
         return RELOC_E_ARG;
@@ -504,7 +507,7 @@ __device__ void leaf_modes(const Entry *__restrict__ pts, int n, int n_total, in
     uint32_t *col = (uint32_t *)(size + cap);
     __shared__ int32_t cand_root[MAX_R];
     __shared__ int32_t n_cand;
-    __shared__ unsigned long long acc[32][13];
+    __shared__ unsigned long long acc[MAX_M][13];
     __shared__ int32_t n_modes;
     const int tid = threadIdx.x;
     for (int i = tid; i < n; i += MODE_THREADS) {
@@ -513,7 +516,7 @@ __device__ void leaf_modes(const Entry *__restrict__ pts, int n, int n_total, in
         size[i] = 0;
     }
     if (tid == 0) n_cand = 0;
-    for (int i = tid; i < 32 * 13; i += MODE_THREADS) acc[i / 13][i % 13] = 0ull;
+    for (int i = tid; i < MAX_M * 13; i += MODE_THREADS) acc[i / 13][i % 13] = 0ull;
     __syncthreads();
     const int rd = mp.rd, rl = mp.rl;
     const int rd2 = rd * rd, rl2 = rl * rl;
@@ -806,6 +809,7 @@ extern "C" const char *reloc_status_string(int code)
     case RELOC_E_HIP: return "HIP runtime error";
     case RELOC_E_STATE: return "operation not valid in this state";
     case RELOC_E_RANGE: return "value does not fit the packed device layout";
+    case RELOC_E_IO: return "checkpoint file cannot be written or read, or is not a forest checkpoint";
     default: return "unknown status";
     }
 }
@@ -905,6 +909,13 @@ extern "C" int reloc_forest_destroy(reloc_forest *f)
     return RELOC_OK;
 }
 
+extern "C" int reloc_forest_params(const reloc_forest *f, reloc_params *out)
+{
+    if (!f || !out) return RELOC_E_ARG;
+    *out = f->p;
+    return RELOC_OK;
+}
+
 extern "C" int reloc_forest_memory(const reloc_forest *f, uint64_t *bytes_out)
 {
     if (!f || !bytes_out) return RELOC_E_ARG;
@@ -965,6 +976,192 @@ extern "C" int reloc_forest_drop_reservoirs(reloc_forest *f, void *stream)
     dfree(f, &f->stamp, TLR);
     f->dropped = true;
     return RELOC_OK;
+}
+
+// ---- checkpoint: save and load ---------------------------------------------
+//
+// File layout (little-endian, this library's own format): a FileHeader, then
+// the split nodes (u64 [T (L - 1) + 8]), leaf counters (u32 [T L]), mode
+// counts (i32 [T L]), modes (Mode [T L M]), mode colour rows
+// (u32 [T L rgb_stride(M)]), learned-input leaf summaries (float4 [T L 4])
+// and, unless the reservoirs were dropped, the reservoirs (Entry [T L R]).
+// Slot stamps are not stored: a stamp only has to be below every k + 1 that
+// later frames can produce, and every later k is at least the leaf's counter,
+// so the zero stamps of a new forest select the same winners.
+
+namespace {
+
+struct FileHeader {
+    char magic[8];
+    uint32_t version;
+    uint32_t dropped;
+    reloc_params p;
+    uint64_t total_samples;
+    uint64_t n_nodes, n_leaves, n_mode_slots, n_rgb, n_res;
+};
+
+constexpr char FILE_MAGIC[8] = {'R', 'L', 'F', 'O', 'R', 'E', 'S', 'T'};
+constexpr uint32_t FILE_VERSION = 1;
+constexpr size_t STAGE_BYTES = (size_t)64 << 20;
+
+struct Staging {
+    void *buf = nullptr;
+    ~Staging()
+    {
+        if (buf) (void)hipHostFree(buf);
+    }
+};
+
+// device -> file in chunks through pinned host memory
+int save_section(FILE *fp, const void *dev, size_t bytes, Staging &st, hipStream_t s)
+{
+    const char *src = (const char *)dev;
+    for (size_t off = 0; off < bytes; off += STAGE_BYTES) {
+        const size_t n = std::min(STAGE_BYTES, bytes - off);
+        RL_HIP(hipMemcpyAsync(st.buf, src + off, n, hipMemcpyDeviceToHost, s));
+        RL_HIP(hipStreamSynchronize(s));
+        if (fwrite(st.buf, 1, n, fp) != n) return RELOC_E_IO;
+    }
+    return RELOC_OK;
+}
+
+// file -> device in chunks through pinned host memory
+int load_section(FILE *fp, void *dev, size_t bytes, Staging &st, hipStream_t s)
+{
+    char *dst = (char *)dev;
+    for (size_t off = 0; off < bytes; off += STAGE_BYTES) {
+        const size_t n = std::min(STAGE_BYTES, bytes - off);
+        RL_HIP(hipStreamSynchronize(s));   // the previous chunk has left the staging buffer
+        if (fread(st.buf, 1, n, fp) != n) return RELOC_E_IO;
+        RL_HIP(hipMemcpyAsync(dst + off, st.buf, n, hipMemcpyHostToDevice, s));
+    }
+    RL_HIP(hipStreamSynchronize(s));
+    return RELOC_OK;
+}
+
+FileHeader header_of(const Forest *f)
+{
+    FileHeader h;
+    memset(&h, 0, sizeof(h));
+    memcpy(h.magic, FILE_MAGIC, sizeof(FILE_MAGIC));
+    h.version = FILE_VERSION;
+    h.dropped = f->dropped ? 1u : 0u;
+    h.p = f->p;
+    const uint64_t TL = (uint64_t)f->T * f->L;
+    h.n_nodes = (uint64_t)f->T * (f->L - 1) + 8;
+    h.n_leaves = TL;
+    h.n_mode_slots = TL * f->M;
+    h.n_rgb = TL * rgb_stride(f->M);
+    h.n_res = f->dropped ? 0 : TL * f->R;
+    return h;
+}
+
+int save_forest(Forest *f, FILE *fp, hipStream_t s)
+{
+    int rc = update_modes(f, s);
+    if (rc) return rc;
+    Staging st;
+    RL_HIP(hipHostMalloc(&st.buf, STAGE_BYTES, hipHostMallocDefault));
+    FileHeader h = header_of(f);
+    RL_HIP(hipMemcpyAsync(&h.total_samples, f->total_samples, sizeof(uint64_t), hipMemcpyDeviceToHost, s));
+    RL_HIP(hipStreamSynchronize(s));
+    if (fwrite(&h, sizeof(h), 1, fp) != 1) return RELOC_E_IO;
+    if ((rc = save_section(fp, f->nodes, h.n_nodes * sizeof(uint64_t), st, s))) return rc;
+    if ((rc = save_section(fp, f->counter, h.n_leaves * sizeof(uint32_t), st, s))) return rc;
+    if ((rc = save_section(fp, f->nmodes, h.n_leaves * sizeof(int32_t), st, s))) return rc;
+    if ((rc = save_section(fp, f->modes, h.n_mode_slots * sizeof(Mode), st, s))) return rc;
+    if ((rc = save_section(fp, f->mode_rgb, h.n_rgb * sizeof(uint32_t), st, s))) return rc;
+    if ((rc = save_section(fp, f->leaf_in, h.n_leaves * 4 * sizeof(float4), st, s))) return rc;
+    if (!f->dropped && (rc = save_section(fp, f->res, h.n_res * sizeof(Entry), st, s))) return rc;
+    return RELOC_OK;
+}
+
+int load_forest(FILE *fp, hipStream_t s, reloc_forest **out)
+{
+    FileHeader h;
+    if (fread(&h, sizeof(h), 1, fp) != 1) return RELOC_E_IO;
+    if (memcmp(h.magic, FILE_MAGIC, sizeof(FILE_MAGIC)) != 0 || h.version != FILE_VERSION || h.dropped > 1u)
+        return RELOC_E_IO;
+    reloc_forest *f = nullptr;
+    int rc = reloc_forest_create(&h.p, s, &f);
+    if (rc) return rc;
+    const FileHeader want = [&] {
+        FileHeader w = header_of(f);
+        if (h.dropped) w.n_res = 0;
+        return w;
+    }();
+    if (h.n_nodes != want.n_nodes || h.n_leaves != want.n_leaves || h.n_mode_slots != want.n_mode_slots ||
+        h.n_rgb != want.n_rgb || h.n_res != want.n_res) {
+        reloc_forest_destroy(f);
+        return RELOC_E_IO;
+    }
+    Staging st;
+    std::vector<uint64_t> nodes(h.n_nodes);
+    std::vector<DeepNode> deep((size_t)f->T * (f->L - 1));
+    rc = hipHostMalloc(&st.buf, STAGE_BYTES, hipHostMallocDefault) == hipSuccess ? RELOC_OK : RELOC_E_NOMEM;
+    if (!rc && fread(nodes.data(), sizeof(uint64_t), nodes.size(), fp) != nodes.size()) rc = RELOC_E_IO;
+    if (!rc) {
+        // split nodes are checked like reloc_debug_set_nodes checks them
+        for (size_t i = 0; i < nodes.size() && !rc; ++i) {
+            int32_t kind, dx, dy, thr;
+            unpack_node(nodes[i], kind, dx, dy, thr);
+            if (kind < 0 || kind > 3 || (int64_t)std::abs((int64_t)dx) > f->p.offset_pxmm ||
+                (int64_t)std::abs((int64_t)dy) > f->p.offset_pxmm || pack_node(kind, dx, dy, thr) != nodes[i])
+                rc = RELOC_E_RANGE;
+        }
+        for (size_t i = 0; i < deep.size() && !rc; ++i) deep[i] = deep_node(nodes[i]);
+    }
+    if (!rc && (hipMemcpyAsync(f->nodes, nodes.data(), nodes.size() * sizeof(uint64_t), hipMemcpyHostToDevice, s) !=
+                    hipSuccess ||
+                hipMemcpyAsync(f->deep, deep.data(), deep.size() * sizeof(DeepNode), hipMemcpyHostToDevice, s) !=
+                    hipSuccess ||
+                hipMemcpyAsync(f->total_samples, &h.total_samples, sizeof(uint64_t), hipMemcpyHostToDevice, s) !=
+                    hipSuccess))
+        rc = RELOC_E_HIP;
+    if (!rc) rc = load_section(fp, f->counter, h.n_leaves * sizeof(uint32_t), st, s);
+    if (!rc) rc = load_section(fp, f->nmodes, h.n_leaves * sizeof(int32_t), st, s);
+    if (!rc) rc = load_section(fp, f->modes, h.n_mode_slots * sizeof(Mode), st, s);
+    if (!rc) rc = load_section(fp, f->mode_rgb, h.n_rgb * sizeof(uint32_t), st, s);
+    if (!rc) rc = load_section(fp, f->leaf_in, h.n_leaves * 4 * sizeof(float4), st, s);
+    if (!rc && !h.dropped) rc = load_section(fp, f->res, h.n_res * sizeof(Entry), st, s);
+    if (!rc && fgetc(fp) != EOF) rc = RELOC_E_IO;   // trailing bytes: not a file this version wrote
+    if (!rc && hipStreamSynchronize(s) != hipSuccess) rc = RELOC_E_HIP;
+    if (!rc && h.dropped) {
+        const size_t TLR = (size_t)f->T * f->L * f->R;
+        dfree(f, &f->res, TLR);
+        dfree(f, &f->stamp, TLR);
+        f->dropped = true;
+    }
+    if (rc) {
+        reloc_forest_destroy(f);
+        return rc;
+    }
+    f->maybe_dirty = false;
+    *out = f;
+    return RELOC_OK;
+}
+
+}  // namespace
+
+extern "C" int reloc_forest_save(reloc_forest *f, const char *path, void *stream)
+{
+    if (!f || !path) return RELOC_E_ARG;
+    FILE *fp = fopen(path, "wb");
+    if (!fp) return RELOC_E_IO;
+    int rc = save_forest(f, fp, (hipStream_t)stream);
+    if (fclose(fp) != 0 && !rc) rc = RELOC_E_IO;
+    return rc;
+}
+
+extern "C" int reloc_forest_load(const char *path, void *stream, reloc_forest **out)
+{
+    if (!path || !out) return RELOC_E_ARG;
+    *out = nullptr;
+    FILE *fp = fopen(path, "rb");
+    if (!fp) return RELOC_E_IO;
+    const int rc = load_forest(fp, (hipStream_t)stream, out);
+    fclose(fp);
+    return rc;
 }
 
 // ---- debug exports --------------------------------------------------------

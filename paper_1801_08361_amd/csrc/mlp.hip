@@ -11,9 +11,9 @@
 // LDS; per-tile gradient partials are summed in a fixed order, then Adam
 // updates the FP32 master weights and their bfloat16 copies are refreshed.
 //
-// Also here: the per-pixel inputs, the inlier labeller that trains the MLP
-// from verified poses, and the depth-difference verifier of the paper
-// (Sec. 3.3.1, Eqs. 3-4) that decides which poses count as verified.
+// Also here: the per-pixel inputs and the inlier labeller that trains the MLP
+// from poses accepted by the depth-difference check of Sec. 3.3.1, Eqs. 3-4
+// (verify.hip).
 #include <math.h>
 #include <string.h>
 
@@ -379,38 +379,6 @@ __global__ void __launch_bounds__(64) k_mlp_pixels(FeatArgs A, const uint16_t *_
     }
 }
 
-// Eqs. 3-4: counts of pixels valid in da and in both, and the integer sum of
-// |da - db| over pixels valid in both
-__global__ void k_verify(const uint16_t *__restrict__ da, const uint16_t *__restrict__ db, int P,
-                         unsigned long long *__restrict__ acc)
-{
-    unsigned long long na = 0, nab = 0, sum = 0;
-    for (int p = blockIdx.x * blockDim.x + threadIdx.x; p < P; p += gridDim.x * blockDim.x) {
-        const uint32_t a = da[p], b = db[p];
-        na += a > 0u;
-        if (a > 0u && b > 0u) {
-            nab++;
-            sum += a > b ? a - b : b - a;
-        }
-    }
-    for (int o = 32; o >= 1; o >>= 1) {
-        na += __shfl_xor(na, o, 64);
-        nab += __shfl_xor(nab, o, 64);
-        sum += __shfl_xor(sum, o, 64);
-    }
-    if (__lane_id() == 0) {
-        atomicAdd(&acc[0], na);
-        atomicAdd(&acc[1], nab);
-        atomicAdd(&acc[2], sum);
-    }
-}
-
-__global__ void k_zero_u64(unsigned long long *p, int n)
-{
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) p[i] = 0ull;
-}
-
 static FeatArgs feat_args(const Forest *f, const Frame &fr)
 {
     FeatArgs A;
@@ -665,27 +633,6 @@ extern "C" int reloc_label_pixels(reloc_forest *f, const uint16_t *depth_dev, co
     return RELOC_OK;
 }
 
-extern "C" int reloc_verify(const uint16_t *da_dev, const uint16_t *db_dev, int32_t W, int32_t H, double *valid_frac,
-                            double *mu_m, int32_t *accept, void *stream)
-{
-    if (!da_dev || !db_dev || W < 1 || H < 1 || !valid_frac || !mu_m || !accept) return RELOC_E_ARG;
-    hipStream_t s = (hipStream_t)stream;
-    unsigned long long *acc = nullptr;
-    RL_HIP(hipMalloc((void **)&acc, 3 * sizeof(unsigned long long)));
-    const int P = W * H;
-    RL_LAUNCH("k_zero_u64", k_zero_u64, dim3(1), dim3(64), 0, s, acc, 3);
-    RL_LAUNCH("k_verify", k_verify, dim3((unsigned)std::min((P + 255) / 256, 1024)), dim3(256), 0, s, da_dev, db_dev,
-              P, acc);
-    unsigned long long h[3] = {0, 0, 0};
-    hipError_t e = hipMemcpyAsync(h, acc, sizeof(h), hipMemcpyDeviceToHost, s);
-    if (e == hipSuccess) e = hipStreamSynchronize(s);
-    (void)hipFree(acc);
-    RL_HIP(e);
-    *valid_frac = (double)h[0] / (double)P;
-    *mu_m = h[1] ? ((double)h[2] / (double)h[1]) / 1000.0 : INFINITY;
-    *accept = (*valid_frac > 0.5 && *mu_m < 0.05) ? 1 : 0;
-    return RELOC_OK;
-}
 
 __global__ void k_bf16_probe(const float *__restrict__ x, int n, uint16_t *__restrict__ y)
 {

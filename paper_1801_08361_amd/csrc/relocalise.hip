@@ -495,19 +495,26 @@ __device__ __forceinline__ int pick_pool(const Attempt &A, int np, uint64_t u)
 
 // Colour-consistent modes of one leaf as a bit mask: bit m is set when slot m
 // holds a mode whose colour is within tol of (pr, pg, pb) in every channel.
-// The row is read with 16-byte loads (rgb_stride(M) colours).
-__device__ __forceinline__ uint32_t colour_mask(const uint32_t *__restrict__ row, int Mp, const ColourWin &w)
+// The row is read with 16-byte loads (rgb_stride(M) colours). Mask is a
+// 32-bit word for up to 32 modes per leaf, else a 64-bit one.
+template <typename Mask>
+__device__ __forceinline__ Mask colour_mask(const uint32_t *__restrict__ row, int Mp, const ColourWin &w)
 {
-    uint32_t mask = 0;
+    Mask mask = 0;
     for (int q = 0; q < Mp; q += 4) {
         const uint4 v = *(const uint4 *)(row + q);
         const uint32_t c[4] = {v.x, v.y, v.z, v.w};
 #pragma unroll
         for (int e = 0; e < 4; ++e)
-            if (colour_in(c[e], w)) mask |= 1u << (q + e);
+            if (colour_in(c[e], w)) mask |= (Mask)1 << (q + e);
     }
     return mask;
 }
+
+__device__ __forceinline__ int popc_mask(uint32_t m) { return __popc(m); }
+__device__ __forceinline__ int popc_mask(uint64_t m) { return __popcll((unsigned long long)m); }
+__device__ __forceinline__ int ffs_mask(uint32_t m) { return __ffs(m); }
+__device__ __forceinline__ int ffs_mask(uint64_t m) { return __ffsll((unsigned long long)m); }
 
 // the same for rows of at most 12 colours, with the row's loads issued
 // before any test
@@ -532,8 +539,9 @@ __device__ __forceinline__ uint32_t colour_mask12(const uint32_t *__restrict__ r
 // a time (pool entries; pixel colours and depths; per pixel, its leaves and
 // then its mode colour rows; the three picked modes) so that each stage
 // waits once.
+template <typename Mask>
 __device__ bool try_hypothesis(const Attempt &A, int np, uint64_t h, uint64_t tau, double R[9], double t[3],
-                               int32_t *__restrict__ s_li, uint32_t *__restrict__ s_mask)
+                               int32_t *__restrict__ s_li, Mask *__restrict__ s_mask)
 {
     const U4 a = philox(h, tau, 0, 0, A.seed, TAG_HYP);
     const U4 b = philox(h, tau, 1, 0, A.seed, TAG_HYP);
@@ -566,29 +574,29 @@ __device__ bool try_hypothesis(const Attempt &A, int np, uint64_t h, uint64_t ta
             // issued together, four trees at a time
 #pragma unroll 4
             for (int tt = 0; tt < A.T; ++tt) {
-                const uint32_t mk =
+                const Mask mk =
                     colour_mask12(A.mode_rgb + (int64_t)s_li[tt * 64] * Mp, Mp, win);
                 s_mask[tt * 64] = mk;
-                cnt += __popc(mk);
+                cnt += popc_mask(mk);
             }
         } else {
             for (int tt = 0; tt < A.T; ++tt) {
-                const uint32_t mk =
-                    colour_mask(A.mode_rgb + (int64_t)s_li[tt * 64] * Mp, Mp, win);
+                const Mask mk =
+                    colour_mask<Mask>(A.mode_rgb + (int64_t)s_li[tt * 64] * Mp, Mp, win);
                 s_mask[tt * 64] = mk;
-                cnt += __popc(mk);
+                cnt += popc_mask(mk);
             }
         }
         if (cnt == 0) return false;
         int sel = (int)uniform_int(b.x[j], (uint64_t)cnt);
         pick[j] = 0;
         for (int tt = 0; tt < A.T; ++tt) {
-            const uint32_t mk = s_mask[tt * 64];
-            const int k = __popc(mk);
+            const Mask mk = s_mask[tt * 64];
+            const int k = popc_mask(mk);
             if (sel >= 0 && sel < k) {
-                uint32_t mm = mk;
-                for (int q = 0; q < sel; ++q) mm &= mm - 1u;
-                pick[j] = (int64_t)s_li[tt * 64] * A.M + (__ffs(mm) - 1);
+                Mask mm = mk;
+                for (int q = 0; q < sel; ++q) mm &= mm - (Mask)1;
+                pick[j] = (int64_t)s_li[tt * 64] * A.M + (ffs_mask(mm) - 1);
             }
             sel -= k;
         }
@@ -635,12 +643,15 @@ __device__ bool try_hypothesis(const Attempt &A, int np, uint64_t h, uint64_t ta
     return true;
 }
 
+// (Mask: uint32_t when every attempt's forest keeps at most 32 modes per
+// leaf, uint64_t up to 64)
+template <typename Mask>
 __global__ void __launch_bounds__(64) k_b_hypgen(const Attempt *__restrict__ att, Stage S)
 {
     // per lane (column) and tree (row): leaf index and colour mask of the pixel
     // being picked (T <= 16)
     __shared__ int32_t s_li[16 * 64];
-    __shared__ uint32_t s_mask[16 * 64];
+    __shared__ Mask s_mask[16 * 64];
     FOR_UNITS(S, u) {
         const int a = attempt_of(S, u);
         const Attempt &A = att[a];
@@ -1217,7 +1228,7 @@ struct Shape {
 
 struct Plan {
     std::vector<Shape> shape;
-    int n = 0, rounds = 0, tm_max = 1;
+    int n = 0, rounds = 0, tm_max = 1, m_max = 1;
     char *arena = nullptr;
     size_t arena_bytes = 0;
     Attempt *d_att = nullptr;
@@ -1399,7 +1410,10 @@ static int enqueue(const Plan *pl, const Sched &sc, const Stages &st, hipStream_
     RL_LAUNCH("k_b_pool_scan", k_b_pool_scan, dim3(grid_of(att, cap, 0)), dim3(1024), 0, s, d, att);
     RL_LAUNCH("k_b_pool_write", k_b_pool_write, dim3(grid_of(st.pb, cap, sc.xcd)), dim3(POOL_BLOCK / PB_PIX), 0, s, d,
               st.pb);
-    RL_LAUNCH("k_b_hypgen", k_b_hypgen, dim3(grid_of(st.hyp, 0, sc.xcd)), dim3(64), 0, s, d, st.hyp);
+    if (pl->m_max > 32)
+        RL_LAUNCH("k_b_hypgen", k_b_hypgen<uint64_t>, dim3(grid_of(st.hyp, 0, sc.xcd)), dim3(64), 0, s, d, st.hyp);
+    else
+        RL_LAUNCH("k_b_hypgen", k_b_hypgen<uint32_t>, dim3(grid_of(st.hyp, 0, sc.xcd)), dim3(64), 0, s, d, st.hyp);
     RL_LAUNCH("k_b_alive_init", k_b_alive_init, dim3(grid_of(att, cap, 0)), dim3(1024), 0, s, d, att);
     const int nw = score_waves(pl->tm_max);
     const size_t smem = (size_t)nw * pl->tm_max * SMODE * sizeof(float);
@@ -1585,7 +1599,10 @@ static Plan *find_or_make_plan(reloc_batch *b, const std::vector<Shape> &shape, 
     pl->shape = shape;
     pl->n = (int)shape.size();
     pl->tm_max = tm_max;
-    for (const Shape &s : shape) pl->rounds = std::max(pl->rounds, rounds_for(s.N));
+    for (const Shape &s : shape) {
+        pl->rounds = std::max(pl->rounds, rounds_for(s.N));
+        pl->m_max = std::max(pl->m_max, s.M);
+    }
     size_t total = 0;
     pl->slices.resize(pl->n);
     std::vector<size_t> at(pl->n);

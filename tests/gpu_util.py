@@ -51,3 +51,16 @@ def rot_angle_deg(Ra: np.ndarray, Rb: np.ndarray) -> float:
     Q = Ra.T @ Rb
     v = np.array([Q[2, 1] - Q[1, 2], Q[0, 2] - Q[2, 0], Q[1, 0] - Q[0, 1]])
     return float(np.degrees(np.arctan2(0.5 * np.linalg.norm(v), 0.5 * (np.trace(Q) - 1.0))))
+
+
+def assert_modes_equal(mg, mo):
+    """GPU modes against the oracle's: counts, means, inverse covariances and
+    colours bit for bit; kappa (a logarithm) to 1e-6."""
+    assert len(mg) == len(mo)
+    if len(mo) == 0:
+        return
+    assert np.array_equal(mg["n"], mo["n"])
+    assert np.array_equal(mg["mu"].view(np.uint32), mo["mu"].view(np.uint32))
+    assert np.array_equal(mg["sinv"].view(np.uint32), mo["sinv"].view(np.uint32))
+    np.testing.assert_allclose(mg["kappa"], mo["kappa"], rtol=1e-6, atol=1e-6)
+    assert np.array_equal(mg["rgb"], mo["rgb"])

@@ -65,6 +65,13 @@ def test_argument_errors_without_gpu():
     assert L.reloc_relocalise_batch(None, None, 0, None, None) == rl.E_ARG
     assert L.reloc_batch_destroy(None) == rl.E_ARG
     assert L.reloc_verify(None, None, 4, 4, None, None, None, None) == rl.E_ARG
+    p = rl.params_default(max_modes=65)
+    assert L.reloc_forest_create(C.byref(p), None, C.byref(out)) == rl.E_ARG
+    p = rl.params_default(n_trees=16, max_modes=40)          # 640 modes per pixel > 512
+    assert L.reloc_forest_create(C.byref(p), None, C.byref(out)) == rl.E_ARG
+    assert L.reloc_forest_save(None, b"/tmp/x", None) == rl.E_ARG
+    assert L.reloc_forest_load(None, None, C.byref(out)) == rl.E_ARG
+    assert L.reloc_forest_params(None, None) == rl.E_ARG
     assert L.reloc_mlp_create(0, None, None) == rl.E_ARG
     assert L.reloc_mlp_destroy(None) == rl.E_ARG
     assert L.reloc_mlp_gradient(None, None, None, 1, None, None, None) == rl.E_ARG
@@ -101,3 +108,19 @@ def test_no_cpu_fallback_when_library_missing(tmp_path, monkeypatch):
     monkeypatch.setattr(rl, "_lib", None)
     with pytest.raises(RuntimeError):
         rl.lib()
+
+
+def test_checkpoint_file_errors_without_gpu(tmp_path):
+    """Files that are missing, empty, truncated or not checkpoints are
+    rejected with RELOC_E_IO before any device work."""
+    import paper_1801_08361_amd as rl
+    L = rl.lib()
+    out = C.c_void_p()
+    assert L.reloc_forest_load(str(tmp_path / "missing.bin").encode(), None, C.byref(out)) == rl.E_IO
+    empty = tmp_path / "empty.bin"
+    empty.write_bytes(b"")
+    assert L.reloc_forest_load(str(empty).encode(), None, C.byref(out)) == rl.E_IO
+    junk = tmp_path / "junk.bin"
+    junk.write_bytes(b"NOTAFORESTFILE" * 64)
+    assert L.reloc_forest_load(str(junk).encode(), None, C.byref(out)) == rl.E_IO
+    assert out.value is None
