@@ -93,7 +93,8 @@ def test_fullsize_relocalise_matches_oracle(full_pair, q):
     tg = g.trace(1024)
     so, To, sco, to = o.relocalise(d0, c0, sc.K, seed=seed, trace=True)
     assert sg == so == 0
-    assert int(to["n_alive"][0]) > 512 and int(to["n_rounds"][0]) >= 10
+    if q == 0:   # more than 512 valid hypotheses: the cull sorts 1024 keys in LDS
+        assert int(to["n_alive"][0]) > 512 and int(to["n_rounds"][0]) >= 10
     _compare_traces(tg, to, 1024)
     assert np.linalg.norm(Tg[:3, 3] - To[:3, 3]) < 1e-4
     assert rot_angle_deg(Tg[:3, :3], To[:3, :3]) < 1e-3
@@ -228,7 +229,9 @@ def test_checkpoint_resume_equals_uninterrupted(tmp_path):
         assert np.array_equal(ka, kc) and np.array_equal(ea.view(np.uint8), ec.view(np.uint8)), t
         ma, na = a.modes(t, 0, a.L)
         mc, nc = c.modes(t, 0, c.L)
-        assert np.array_equal(na, nc) and np.array_equal(ma.view(np.uint8), mc.view(np.uint8)), t
+        assert np.array_equal(na, nc), t
+        used = np.arange(a.M)[None, :] < na[:, None]      # slots past a leaf's count hold nothing
+        assert np.array_equal(ma[used].view(np.uint8), mc[used].view(np.uint8)), t
         for leaf in range(0, a.L, 17):
             eo, ko = o2.reservoir(t, leaf)
             assert ko == int(kc[leaf])
