@@ -246,6 +246,19 @@ const char *reloc_status_string(int code);
 int reloc_verify(const uint16_t *da_dev, const uint16_t *db_dev, int32_t W, int32_t H, double *valid_frac,
                  double *mu_m, int32_t *accept, void *stream);
 
+/* reloc_verify for callers that cannot allocate device memory (code under
+ * graph capture, tight serving loops, harnesses that forbid allocation): the
+ * same kernels and results, with their partial sums in a 48 KiB array the
+ * library holds on each GPU it runs on until the process ends, instead of
+ * scratch taken from the stream's allocator. Frames up to 8191 x 8191
+ * (RELOC_E_ARG beyond); every frame size fits the array, whose partial pass is
+ * capped at 2048 workgroups. Nothing in it needs clearing between calls (each
+ * call writes every partial it reads). Calls that overlap in time on one GPU
+ * share the array and race: serialise them (one stream, or wait for the
+ * previous call). Synchronous on `stream`. */
+int reloc_verify_noalloc(const uint16_t *da_dev, const uint16_t *db_dev, int32_t W, int32_t H, double *valid_frac,
+                         double *mu_m, int32_t *accept, void *stream);
+
 /* ---- learned proposal (an extension; the paper picks pixels uniformly) ----
  * A 24-64-64-1 MLP (ReLU, ReLU, sigmoid) scores each valid pixel of a query
  * frame with the probability that one of its leaf modes lies within 5 cm of

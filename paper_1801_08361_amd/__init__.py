@@ -124,6 +124,8 @@ _SIGS = {
     "reloc_debug_unit_owners": [C.c_int32, C.c_int32, C.c_int32, C.c_void_p],
     "reloc_verify": [C.c_void_p, C.c_void_p, C.c_int32, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p,
                      C.c_void_p],
+    "reloc_verify_noalloc": [C.c_void_p, C.c_void_p, C.c_int32, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p,
+                             C.c_void_p],
     "reloc_mlp_create": [C.c_uint64, C.c_void_p, C.c_void_p],
     "reloc_mlp_destroy": [C.c_void_p],
     "reloc_mlp_get_weights": [C.c_void_p, C.c_void_p],
@@ -479,9 +481,11 @@ class Batch:
 # -- verification and the learned proposal -------------------------------------
 
 
-def verify(da, db) -> Tuple[float, float, bool]:
-    """Depth-difference verification of a proposed pose (reloc_verify):
-    returns (valid fraction of da, mean |da - db| in metres, accepted)."""
+def verify(da, db, noalloc: bool = False) -> Tuple[float, float, bool]:
+    """Depth-difference verification of a proposed pose (reloc_verify, or
+    reloc_verify_noalloc): da is the target scene rendered at the pose, db the
+    relocalised frame; returns (valid fraction of da, mean |da - db| in
+    metres, accepted)."""
     import torch
     for t in (da, db):
         if not (isinstance(t, torch.Tensor) and t.dtype == torch.uint16 and t.is_cuda and t.is_contiguous()):
@@ -490,8 +494,9 @@ def verify(da, db) -> Tuple[float, float, bool]:
         raise ValueError("depth images must both be [H, W]")
     H, W = da.shape
     vf, mu, acc = C.c_double(0), C.c_double(0), C.c_int32(0)
-    _check(lib().reloc_verify(da.data_ptr(), db.data_ptr(), W, H, C.byref(vf), C.byref(mu), C.byref(acc),
-                              _stream(None)), "reloc_verify")
+    fn = lib().reloc_verify_noalloc if noalloc else lib().reloc_verify
+    _check(fn(da.data_ptr(), db.data_ptr(), W, H, C.byref(vf), C.byref(mu), C.byref(acc), _stream(None)),
+           "reloc_verify_noalloc" if noalloc else "reloc_verify")
     return vf.value, mu.value, bool(acc.value)
 
 

@@ -9,6 +9,8 @@
 // adds the partials. No atomics, so nothing has to be cleared before a call.
 #include <math.h>
 
+#include <mutex>
+
 #include "common.h"
 
 namespace rl {
@@ -172,4 +174,49 @@ extern "C" int reloc_verify(const uint16_t *da_dev, const uint16_t *db_dev, int3
     const hipError_t e = hipFreeAsync(work, s);
     if (rc) return rc;
     return e == hipSuccess ? RELOC_OK : RELOC_E_HIP;
+}
+
+// ---- the allocation-free variant ---------------------------------------------
+//
+// For callers that cannot allocate device memory (graph capture, tight
+// serving loops): the partials and totals live in a file-scope device array,
+// one copy per GPU, held until the process ends. Its device address is looked
+// up once per device, with that device current, and kept; the host never
+// passes the array's name itself to a kernel or a copy.
+
+namespace {
+
+constexpr int NOALLOC_WORDS = 3 * VERIFY_MAX_PARTS + 3;   // 49 176 bytes
+constexpr int MAX_DEVICES = 64;
+
+__device__ __align__(256) unsigned long long scratch[NOALLOC_WORDS];
+
+std::mutex scratch_mu;
+unsigned long long *scratch_ptr[MAX_DEVICES] = {};
+
+int scratch_of_current_device(unsigned long long **out)
+{
+    int dev = -1;
+    RL_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= MAX_DEVICES) return RELOC_E_STATE;
+    std::lock_guard<std::mutex> g(scratch_mu);
+    if (!scratch_ptr[dev]) {
+        void *p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return RELOC_E_HIP;
+        scratch_ptr[dev] = (unsigned long long *)p;
+    }
+    *out = scratch_ptr[dev];
+    return RELOC_OK;
+}
+
+}  // namespace
+
+extern "C" int reloc_verify_noalloc(const uint16_t *da_dev, const uint16_t *db_dev, int32_t W, int32_t H,
+                                    double *valid_frac, double *mu_m, int32_t *accept, void *stream)
+{
+    if (!verify_args_ok(da_dev, db_dev, W, H, valid_frac, mu_m, accept)) return RELOC_E_ARG;
+    unsigned long long *work = nullptr;
+    const int rc = scratch_of_current_device(&work);
+    if (rc) return rc;
+    return verify_run(da_dev, db_dev, W, H, work, valid_frac, mu_m, accept, (hipStream_t)stream);
 }
