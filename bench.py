@@ -10,27 +10,32 @@ before the timed region. A step relocalises the 50 held-out query frames
 steps.
 
 Also reported (same JSON line, `forms`): the same 50 queries as one batched
-call (bit-identical results); the learned proposal on the full-size forest (a
-network trained on the GPU from verified relocalisations of extra frames;
-learned picks at 256, 64 and 16 hypotheses against uniform picks at 256, 64,
-16 and 1024); and the batched form on the mixed workload (64 attempts against
-8 small-room forests, frame sizes drawn from 320x240 / 480x360 / 640x480 and
-hypothesis counts from 256 / 512 / 1024) as one batched call versus 64
-sequential plain calls, then batched + learned and batched uniform at 256
-hypotheses.
+call (bit-identical results); the single-relocalisation workload (320 x 240
+rooms, 5 trees of depth 10, 256-entry reservoirs, 256 hypotheses, 64 pixels
+per round; 10 rooms x 20 queries, one plain call each); the learned proposal
+on the full-size forest (a network trained on the GPU from verified
+relocalisations of extra frames; learned picks at 256, 64 and 16 hypotheses
+against uniform picks at 256, 64, 16 and 1024, and the fraction of
+hypotheses within 5 cm / 5 deg of the truth); the batched form on the mixed
+workload (64 attempts against 8 small-room forests, frame sizes drawn from
+320x240 / 480x360 / 640x480 and hypothesis counts from 256 / 512 / 1024) as
+one batched call versus 64 sequential plain calls, then batched + learned and
+batched uniform at 256 hypotheses; and the collaborative-scale queue (16
+full-size forests, 1024 attempts with 30 % true overlap): relocalisation
+success, and the depth-difference check's true/false positives and negatives.
 
 Per-kernel times come from a separate profiled pass over the same work (HIP
-events around each launch on its stream; kernels are then launched one by one
-instead of as a graph). The headline `roofline` is for the scoring kernel:
-its algorithmic FLOPs (25 per (hypothesis, draw, mode) energy term, 18 per
-(hypothesis, draw) transform, counted by the kernels themselves) over its
-average duration, with `traffic` (HBM bytes per launch) taken from the
-committed counter profile while the kernel's sources are unchanged. Every
-form also carries `rooflines`: the scoring kernel, the traversal (HBM, by
-algorithmic bytes) and, for learned forms, the pick-weight kernel (BF16
-matrix FLOPs), plus the kernel with the largest total time.
+events recorded around each launch on its stream; kernels are then launched
+one by one instead of as a graph). The headline `roofline` is the kernel with
+the largest total time in that pass: its algorithmic work per launch (FLOPs
+counted by the kernels for scoring, bytes for traversal and refinement) over
+its average event-bracketed duration, with `traffic` (HBM bytes per launch)
+from the committed counter profile while the kernel's sources are unchanged.
+`cpu_baseline` is the CPU oracle on a forest adapted on the same 200 frames,
+relocalising a sample of the same queries with the same seeds; the bench
+checks that the oracle's poses equal the GPU's there.
 
-Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-batched] [--no-learned] [--queue]
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-batched] [--no-learned] [--no-queue]
 """
 from __future__ import annotations
 
@@ -79,60 +84,76 @@ def success(T, gt) -> bool:
     return dt <= 0.05 and ang <= 5.0
 
 
-def cpu_baseline(sc, budget_s: float = 25.0):
+def cpu_baseline(full, budget_s: float = 20.0, max_queries: int = 16):
     """The CPU oracle on a bounded sample of the same workload: a forest with
-    the same parameters adapted on every 10th adaptation frame (20 frames),
-    then relocalisation of held-out queries. Lazily built leaf modes are
-    computed by an untimed first call per query; the timed call repeats it
-    with the modes cached (the GPU is timed with its modes built). Timed on
-    one thread, then with the same attempts repeated over the host's cores
-    (one thread each; the oracle keeps no global state, its calls release
-    the interpreter lock, and repeated attempts only read the forest)."""
+    the same parameters adapted on the same 200 frames (copied from the GPU
+    renders), then the first held-out queries with the seeds the GPU used.
+    The oracle builds leaf modes lazily, so each query is relocalised once
+    untimed (building the modes its pixels reach; the GPU is timed with its
+    modes built) and once timed, on one thread; then the same attempts are
+    repeated over the host's cores (one thread each; the oracle keeps no
+    global state, its calls release the interpreter lock, and repeated
+    attempts only read the forest). Every sampled pose must equal the GPU's
+    plain result for the same query within 1e-4 m and 1e-3 deg."""
+    import numpy as np
     import oracle
+    sc, gpu_res = full["sc"], full["last_res"]
     po = oracle.default_params()
     gp = full_params()
     for f in ("n_trees", "depth", "reservoir_size", "max_modes", "n_hypotheses", "batch_pixels"):
         setattr(po, f, getattr(gp, f))
     o = oracle.Forest(po)
     t0 = time.time()
-    frames = list(range(0, len(sc.adapt_poses), 10))
-    for k in frames:
-        d, c = sc.render_adapt(k)
-        o.adapt(d, c, sc.K, sc.adapt_poses[k])
-    log(f"oracle adapted {len(frames)} frames in {time.time() - t0:.1f}s")
+    for k, (d, c) in enumerate(full["adapt"]):
+        o.adapt(d.cpu(), c.cpu(), sc.K, sc.adapt_poses[k])
+        if k % 50 == 49:
+            log(f"oracle adapted {k + 1} frames ({time.time() - t0:.1f}s)")
+    t_adapt = time.time() - t0
+    log(f"oracle adapted {len(full['adapt'])} frames in {t_adapt:.1f}s")
     n = 0
     timed = 0.0
     ok = 0
     done = []
-    for q in range(0, len(sc.query_poses), 5):
-        d, c = sc.render_query(q)
+    worst_dt = worst_da = 0.0
+    for q in range(min(max_queries, len(full["queries"]))):
+        d, c = (x.cpu() for x in full["queries"][q])
         o.relocalise(d, c, sc.K, seed=1 + q)
         t = time.perf_counter()
         st, T, _, _ = o.relocalise(d, c, sc.K, seed=1 + q)
         timed += time.perf_counter() - t
         n += 1
         ok += int(st == 0 and success(T, sc.query_poses[q]))
+        g = gpu_res[q]
+        assert st == g["status"], (q, st, g["status"])
+        if st == 0:
+            worst_dt = max(worst_dt, float(np.linalg.norm(T[:3, 3] - g["pose"][:3, 3])))
+            Q = T[:3, :3].T @ g["pose"][:3, :3]
+            v = np.array([Q[2, 1] - Q[1, 2], Q[0, 2] - Q[2, 0], Q[1, 0] - Q[0, 1]])
+            worst_da = max(worst_da, float(np.degrees(np.arctan2(0.5 * np.linalg.norm(v),
+                                                                  0.5 * (np.trace(Q) - 1.0)))))
         done.append((q, d, c, T))
-        if timed > budget_s or time.time() - t0 > 3 * budget_s:
+        log(f"oracle query {q}: {'ok' if st == 0 else st}, {timed:.1f}s timed so far")
+        if timed > budget_s:
             break
+    assert worst_dt < 1e-4 and worst_da < 1e-3, (worst_dt, worst_da)
     single = n / timed
     # the same attempts over the host's cores (at most 16 threads)
     from concurrent.futures import ThreadPoolExecutor
     cores = max(1, min(16, len(os.sched_getaffinity(0))))
-    jobs = [done[k % len(done)] for k in range(3 * cores)]
+    jobs = [done[k % len(done)] for k in range(2 * cores)]
     t = time.perf_counter()
     with ThreadPoolExecutor(max_workers=cores) as ex:
         outs = list(ex.map(lambda j: o.relocalise(j[1], j[2], sc.K, seed=1 + j[0]), jobs))
     multi = len(jobs) / (time.perf_counter() - t)
-    import numpy as np
     same = all(np.array_equal(out[1], j[3]) for out, j in zip(outs, jobs))
     log(f"oracle: {single:.2f} relocalisations/s on 1 thread, {multi:.2f} on {cores} threads")
     return {"value": multi, "unit": "relocalisations/s", "cores": cores, "kind": "oracle",
             "single_thread_value": single, "threads_identical_to_single": same,
-            "sample": f"{n} held-out 640x480 queries relocalised (N=1024, B=500) against a forest adapted on "
-                      f"{len(frames)} of the 200 frames, modes cached by an untimed first call "
-                      f"({ok}/{n} within 5 cm/5 deg), timed once each on one thread; then {len(jobs)} repeats "
-                      f"of those attempts on {cores} threads"}
+            "gpu_equals_oracle": {"queries": n, "max_translation_m": worst_dt, "max_rotation_deg": worst_da},
+            "sample": f"the first {n} of the 50 held-out 640x480 queries (N=1024, B=500, seeds as on the GPU) "
+                      f"against a forest adapted on the same 200 frames ({t_adapt:.0f} s), modes built by an "
+                      f"untimed first call per query ({ok}/{n} within 5 cm/5 deg), each timed once on one "
+                      f"thread; then {len(jobs)} repeats of those attempts on {cores} threads"}
 
 
 HBM_PEAK_GBS = 8000.0              # MI355X HBM3E (published)
@@ -269,6 +290,7 @@ def plain_full(args, dev, batched: bool = True):
             tot += 1
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
+    last_res = res
     log(f"plain full: {tot / wall:.1f} relocalisations/s, success {ok}/{tot}")
 
     # profiled pass: the same step with per-kernel events
@@ -286,7 +308,7 @@ def plain_full(args, dev, batched: bool = True):
     if not batched:
         return dict(sc=sc, value=tot / wall, wall=wall, success=ok / max(tot, 1), n=tot, kernels=kernels, roof=roof,
                     rooflines=roofs, adapt_fps=len(adapt) / t_adapt, modes_s=t_modes, mem=g.memory(), forest=g,
-                    queries=queries, batched=None)
+                    queries=queries, batched=None, adapt=adapt, last_res=last_res)
     # the same 50 queries as one batched call (bit-identical results)
     b = rl.Batch(tune=True)
     att = [dict(forest=g, depth=d, rgb=c, K=sc.K, seed=1 + q) for q, (d, c) in enumerate(queries)]
@@ -311,7 +333,7 @@ def plain_full(args, dev, batched: bool = True):
     return dict(sc=sc, value=tot / wall, wall=wall, success=ok / max(tot, 1), n=tot, kernels=kernels, roof=roof,
                 rooflines=roofs,
                 adapt_fps=len(adapt) / t_adapt, modes_s=t_modes, mem=g.memory(), forest=g, queries=queries,
-                batched=batched)
+                batched=batched, adapt=adapt, last_res=last_res)
 
 
 def train_from_verified(dev, items, max_pixels, seed, epochs):
@@ -395,8 +417,31 @@ def learned_full(args, dev, full):
             res_prof, kernels = profiled(lambda: run(n_hyp, use))
             P = queries[0][0].numel()
             forms[name]["rooflines"] = rooflines(kernels, res_prof, [(P, g.T, use)] * len(queries))
-        log(f"{name}: {forms[name]['value']:.1f}/s, success {ok}/{len(queries)}, valid hypotheses {valid:.1f}")
+        if n_hyp <= 256:
+            forms[name]["good_hypotheses_per_attempt"] = good_hypotheses(g, m if use else None, queries, sc, n_hyp)
+        log(f"{name}: {forms[name]['value']:.1f}/s, success {ok}/{len(queries)}, valid hypotheses {valid:.1f}, "
+            f"good hypotheses {forms[name].get('good_hypotheses_per_attempt', float('nan')):.1f}")
     return forms
+
+
+def good_hypotheses(g, m, queries, sc, n_hyp):
+    """Mean number of an attempt's initial hypotheses within 5 cm / 5 deg of
+    the true pose (what the proposal is for), read from each attempt's trace
+    outside any timed region."""
+    import numpy as np
+    tot = 0
+    for q, (d, c) in enumerate(queries):
+        if m is not None:
+            g.relocalise_learned(m, d, c, sc.K, seed=1 + q, n_hyp=n_hyp)
+        else:
+            g.relocalise_ex(d, c, sc.K, seed=1 + q, n_hyp=n_hyp)
+        tr = g.trace(n_hyp)
+        for h in np.flatnonzero(tr["hyp_try"] >= 0):
+            T = np.eye(4)
+            T[:3, :3] = tr["hyp_pose"][h, :9].reshape(3, 3)
+            T[:3, 3] = tr["hyp_pose"][h, 9:]
+            tot += int(success(T, sc.query_poses[q]))
+    return tot / len(queries)
 
 
 def batched_mixed(args, dev):
@@ -499,16 +544,20 @@ def batched_mixed(args, dev):
 
 def queue_form(args, dev):
     """Collaborative-scale queue: 16 full-size forests (depth 15, R = 1024),
-    each adapted on every second frame of its own room's path; 1024 queued
+    each adapted on the 200 sensor frames of its own room's path; 1024 queued
     attempts, 30 % with a frame from the target's room (a correct answer
     exists) and the rest from other rooms (the correct answer is a rejection),
-    frame sizes mixed from 320x240 to 640x480. Batched plain at 1024
-    hypotheses against batched + learned at 256 (timed: the relocalisation
-    calls only). Every returned pose is then checked, outside the timed
-    region, with the depth-difference test (Sec. 3.3.1, Eqs. 3-4) against the
-    target room's model depth at that pose; success counts accepted correct
-    poses over the attempts with overlap, the false-positive rate accepted
-    wrong poses over all accepted ones."""
+    frame sizes mixed from 320x240 to 640x480. As in the paper's inter-agent
+    relocalisation (Sec. 3.3.1, Fig. 4), each queued frame is a noise-free
+    raycast of its source room at one of that room's held-out poses. Batched
+    plain at 1024 hypotheses against batched + learned at 256 (timed: the
+    relocalisation calls only). Every returned pose is then checked, outside
+    the timed region, by the depth-difference test (Eqs. 3-4) with the target
+    room's model depth at that pose as the first image. Reported as the paper
+    reports its two steps: relocalisation success (<= 5 cm / 5 deg) over the
+    attempts with overlap (Table 2's measure), and the check's true and false
+    positives and negatives, precision, recall and specificity (Table 3's);
+    the false-positive rate is wrong accepted poses over accepted poses."""
     import torch
     import paper_1801_08361_amd as rl
     import synthroom as sr
@@ -518,18 +567,19 @@ def queue_form(args, dev):
     forests = []
     for sc in scenes:
         g = rl.Forest(full_params())
-        for k in range(0, len(sc.adapt_poses), 2):
+        for k in range(len(sc.adapt_poses)):
             d, c = sc.render_adapt(k, device=dev)
             g.adapt_frame(d, c, sc.K, sc.adapt_poses[k])
         g.update_modes()
         forests.append(g)
+        log(f"queue: forest {len(forests)} adapted ({time.time() - t0:.1f}s)")
     torch.cuda.synchronize()
     log(f"queue: {n_f} forests adapted in {time.time() - t0:.1f}s ({forests[0].memory() / 2**30:.2f} GiB each)")
     t0 = time.time()
     plan = sr.queue_attempts(1024, n_f, len(scenes[0].query_poses))
     att = []
     for a in plan:
-        d, c = scenes[a["source"]].render_query(a["query"], device=dev, width=a["width"], height=a["height"])
+        d, c = scenes[a["source"]].render_query_synthetic(a["query"], device=dev, width=a["width"], height=a["height"])
         att.append(dict(forest=forests[a["forest"]], depth=d.contiguous(), rgb=c.contiguous(),
                         K=sr.intrinsics(a["width"], a["height"]), seed=a["seed"]))
     torch.cuda.synchronize()
@@ -540,25 +590,32 @@ def queue_form(args, dev):
 
     def judge(res):
         n_overlap = sum(int(a["overlap"]) for a in plan)
-        acc = correct = fp = 0
+        tp = fp = tn = fn = correct = failed = 0
         for a, r, x in zip(plan, res, att):
             if r["status"] != 0:
+                failed += 1
                 continue
-            md = scenes[a["forest"]].model_depth(r["pose"], device=dev, width=a["width"], height=a["height"])
-            if not rl.verify(md, x["depth"])[2]:
-                continue
-            acc += 1
-            good = a["overlap"] and success(r["pose"], scenes[a["source"]].query_poses[a["query"]])
+            good = bool(a["overlap"]) and success(r["pose"], scenes[a["source"]].query_poses[a["query"]])
             correct += int(good)
-            fp += int(not good)
-        return {"accepted": acc, "accepted_correct": correct, "false_positives": fp,
-                "attempts_with_overlap": n_overlap, "success_rate": correct / max(n_overlap, 1),
-                "false_positive_rate": fp / max(acc, 1)}
+            md = scenes[a["forest"]].model_depth(r["pose"], device=dev, width=a["width"], height=a["height"])
+            acc = rl.verify(md, x["depth"])[2]
+            tp += int(acc and good)
+            fp += int(acc and not good)
+            tn += int(not acc and not good)
+            fn += int(not acc and good)
+        return {"attempts_with_overlap": n_overlap, "relocalised_correct": correct,
+                "success_rate": correct / max(n_overlap, 1), "failed": failed,
+                "verifier": {"TP": tp, "FP": fp, "TN": tn, "FN": fn,
+                             "precision": tp / max(tp + fp, 1), "recall": tp / max(tp + fn, 1),
+                             "specificity": tn / max(tn + fp, 1)},
+                "accepted_correct_rate": tp / max(n_overlap, 1),
+                "false_positive_rate": fp / max(tp + fp, 1)}
 
     out = {"training": info,
-           "workload": "16 full-size forests (5 trees depth 15, R=1024, 100 frames each); 1024 attempts, 30% from "
-                       "the target's room; frames 320x240/480x360/640x480; B=500"}
-    for name, n_hyp, use in (("batched_plain_1024", 1024, False), ("batched_learned_256", 256, True)):
+           "workload": "16 full-size forests (5 trees depth 15, R=1024, 200 frames each); 1024 attempts, 30% from "
+                       "the target's room; noise-free raycast frames 320x240/480x360/640x480; B=500"}
+    for name, n_hyp, use in (("batched_plain_1024", 1024, False), ("batched_learned_256", 256, True),
+                             ("batched_plain_256", 256, False)):
         lst = [dict(x, n_hyp=n_hyp, proposal=m) if use else dict(x, n_hyp=n_hyp) for x in att]
         b = rl.Batch(tune=True)
         b.run(lst)
@@ -572,14 +629,55 @@ def queue_form(args, dev):
         j = judge(res)
         out[name] = dict({"value": len(lst) * args.steps / sum(runs), "unit": "relocalisations/s",
                           "runs_ms": [round(t * 1e3, 2) for t in runs], "schedule": b.schedule()}, **j)
-        log(f"queue {name}: {out[name]['value']:.1f}/s; accepted {j['accepted']}, correct {j['accepted_correct']} "
-            f"of {j['attempts_with_overlap']} with overlap, false positives {j['false_positives']}")
+        v = j["verifier"]
+        log(f"queue {name}: {out[name]['value']:.1f}/s; correct poses {j['relocalised_correct']}/"
+            f"{j['attempts_with_overlap']}; verifier TP {v['TP']} FP {v['FP']} TN {v['TN']} FN {v['FN']}")
         del b
     t1 = time.perf_counter()
     res = [x["forest"].relocalise_ex(x["depth"], x["rgb"], x["K"], seed=x["seed"], n_hyp=1024) for x in att]
     torch.cuda.synchronize()
     out["sequential_plain_1024"] = {"value": len(att) / (time.perf_counter() - t1), "unit": "relocalisations/s"}
     log(f"queue sequential plain: {out['sequential_plain_1024']['value']:.1f}/s")
+    return out
+
+
+def c1_small(args, dev):
+    """The single-relocalisation workload: 10 rooms of 5 x 4 x 2.7 m at
+    320 x 240 (f = 277), a forest of 5 trees of depth 10 with 256-entry
+    reservoirs adapted on 20 frames per room, 256 hypotheses and 64 pixels
+    per round; a step relocalises the 200 held-out queries with one plain
+    call each."""
+    import torch
+    import paper_1801_08361_amd as rl
+    import synthroom as sr
+    work = []
+    for room in range(200, 210):
+        sc = sr.small_scene(room)
+        g = rl.Forest(small_params())
+        for k in range(len(sc.adapt_poses)):
+            d, c = sc.render_adapt(k, device=dev)
+            g.adapt_frame(d, c, sc.K, sc.adapt_poses[k])
+        g.update_modes()
+        for q in range(len(sc.query_poses)):
+            d, c = sc.render_query(q, device=dev)
+            work.append((g, d, c, sc.K, 5000 + q, sc.query_poses[q]))
+    torch.cuda.synchronize()
+
+    def step():
+        return [g.relocalise_ex(d, c, K, seed=s) for g, d, c, K, s, _ in work]
+
+    step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for s in range(args.steps):
+        res = step()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ok = sum(int(r["status"] == 0 and success(r["pose"], w[5])) for r, w in zip(res, work))
+    out = {"value": len(work) * args.steps / wall, "unit": "relocalisations/s", "success_rate": ok / len(work),
+           "attempts": len(work),
+           "workload": "10 rooms 5x4x2.7 m, 320x240, 5 trees depth 10, R=256, 20 frames each; N=256, B=64"}
+    log(f"small rooms plain: {out['value']:.1f}/s, success {ok}/{len(work)}")
     return out
 
 
@@ -592,8 +690,8 @@ def main():
     ap.add_argument("--no-batched", action="store_true",
                     help="skip the batched forms (the full-size batch of the 50 queries and the mixed workload)")
     ap.add_argument("--no-learned", action="store_true")
-    ap.add_argument("--queue", action="store_true",
-                    help="also run the collaborative-scale queue (16 full-size forests, 1024 attempts; minutes)")
+    ap.add_argument("--no-queue", action="store_true",
+                    help="skip the collaborative-scale queue (16 full-size forests, 1024 attempts)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run one 256 MiB device-to-device copy kernel (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -645,11 +743,12 @@ def main():
         forms["learned_full"] = learned_full(args, dev, full)
     if not args.no_batched:
         forms["mixed"] = batched_mixed(args, dev)
-    if args.queue:
+    forms["small_rooms"] = c1_small(args, dev)
+    if not args.no_queue:
         forms["queue"] = queue_form(args, dev)
     out["forms"] = forms
     if not args.no_cpu:
-        out["cpu_baseline"] = cpu_baseline(full["sc"])
+        out["cpu_baseline"] = cpu_baseline(full)
     print(json.dumps(out), flush=True)
 
 

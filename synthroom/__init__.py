@@ -326,6 +326,15 @@ class Scene:
         return render(self.room, self.query_poses[k], w, h, device, self.noise_rel,
                       sub_seed(self.seed, 2, k))
 
+    def render_query_synthetic(self, k: int, device="cpu", width=None, height=None):
+        """A noise-free raycast of the room from query pose k: the synthetic
+        RGB-D image of an agent's reconstructed scene that inter-agent
+        relocalisation relocalises (Sec. 3.3.1, Fig. 4) instead of a sensor
+        frame."""
+        w = width or self.width
+        h = height or self.height
+        return render(self.room, self.query_poses[k], w, h, device, 0.0, 0)
+
     def extra_poses(self, n: int, tag: int = 0) -> np.ndarray:
         """A second camera path of n poses in the same room (for frames that
         neither adapt the forest nor serve as held-out queries)."""
