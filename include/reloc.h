@@ -261,8 +261,9 @@ int reloc_verify_noalloc(const uint16_t *da_dev, const uint16_t *db_dev, int32_t
 
 /* ---- learned proposal (an extension; the paper picks pixels uniformly) ----
  * A 24-64-64-1 MLP (ReLU, ReLU, sigmoid) scores each valid pixel of a query
- * frame with the probability that one of its leaf modes lies within 5 cm of
- * its world point. floor(sigma 65536) + 1 becomes the pixel's pick weight for
+ * frame with the probability that its hypothesis pick (a mode drawn among the
+ * colour-consistent modes of its leaves) lies within 5 cm of its world
+ * point. floor(sigma 65536) + 1 becomes the pixel's pick weight for
  * hypothesis generation (reloc_relocalise_ex / reloc_attempt
  * pixel_weights_dev); scoring and culls stay uniform.
  *
@@ -291,7 +292,7 @@ int reloc_mlp_destroy(reloc_mlp *m);
 int reloc_mlp_get_weights(const reloc_mlp *m, float *w_host);
 int reloc_mlp_set_weights(reloc_mlp *m, const float *w_host);
 /* Gradient of the mean logistic loss over n rows (x_dev [n][32] bfloat16,
- * y_dev [n] uint8 labels 0/1) into grad_host [5825], the mean loss into
+ * y_dev [n] uint8 labels, target y / 255) into grad_host [5825], the mean loss into
  * *loss_host (may be NULL). Synchronous on `stream`. */
 int reloc_mlp_gradient(reloc_mlp *m, const uint16_t *x_dev, const uint8_t *y_dev, int32_t n, float *grad_host,
                        float *loss_host, void *stream);
@@ -323,9 +324,13 @@ int reloc_mlp_pixel_weights(reloc_mlp *m, reloc_forest *f, const uint16_t *depth
 int reloc_pixel_features(reloc_forest *f, const uint16_t *depth_dev, const uint8_t *rgb_dev,
                          const reloc_intrinsics *K, const int32_t *pix_dev, int32_t n, uint16_t *x_dev, float *xf_dev,
                          void *stream);
-/* training labels: label_dev[i] = 1 iff a mode of pixel pix_dev[i]'s leaves
- * lies within 5 cm of its world point under pose_c2w (rounded to FP32; the
- * squared distance is (d0 d0 + d1 d1) + d2 d2 in FP32), else 0 */
+/* training labels: label_dev[i] = round(255 g / c) for pixel pix_dev[i],
+ * where c counts the modes of the pixel's leaves that pass the hypothesis
+ * pick's colour test (|mode colour - pixel colour| <= rgb_tol per channel)
+ * and g those of them within 5 cm of the pixel's world point under pose_c2w
+ * (rounded to FP32; the squared distance is (d0 d0 + d1 d1) + d2 d2 in FP32),
+ * 0 when c = 0: the probability that the pixel's pick is correct, the
+ * network's target (label / 255) */
 int reloc_label_pixels(reloc_forest *f, const uint16_t *depth_dev, const uint8_t *rgb_dev, const reloc_intrinsics *K,
                        const double pose_c2w[16], const int32_t *pix_dev, int32_t n, uint8_t *label_dev,
                        void *stream);

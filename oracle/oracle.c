@@ -1447,9 +1447,12 @@ int oracle_features24(oracle_forest *f, const uint16_t *depth, const uint8_t *rg
     return ORACLE_OK;
 }
 
-/* The world point is y = R c + t with the pose rounded to FP32 and the same
- * fused chain as scoring; a pixel is an inlier (label 1) iff some mode of its
- * leaves is within 5 cm: (d0 d0 + d1 d1) + d2 d2 <= 0.05^2 in FP32. */
+/* The label of a pixel under `pose` is the probability that its hypothesis
+ * pick lands on a correct mode: among the modes of its leaves that pass the
+ * pick's colour test (oracle_colour_ok), the fraction within 5 cm of the
+ * pixel's world point y = R c + t (the pose rounded to FP32, the same fused
+ * chain as scoring; (d0 d0 + d1 d1) + d2 d2 <= 0.05^2 in FP32), as
+ * round(255 good / candidates), 0 without candidates. */
 int oracle_label(oracle_forest *f, const uint16_t *depth, const uint8_t *rgb, int W, int H, const float K[4],
                  const double pose[16], const int32_t *pix, int n, uint8_t *label)
 {
@@ -1474,19 +1477,20 @@ int oracle_label(oracle_forest *f, const uint16_t *depth, const uint8_t *rgb, in
         cam_point(u, v, d, K, c);
         for (int k = 0; k < 3; ++k)
             y[k] = fmaf(R32[k * 3 + 0], c[0], fmaf(R32[k * 3 + 1], c[1], fmaf(R32[k * 3 + 2], c[2], t32[k])));
-        for (int t = 0; t < f->T && !label[i]; ++t) {
+        unsigned cand = 0, good = 0;
+        for (int t = 0; t < f->T; ++t) {
             int32_t leaf = traverse(f, &fc, t, u, v, (int32_t)d);
             ensure_modes(f, t, leaf);
             size_t li = (size_t)t * f->L + leaf;
             for (int m = 0; m < f->nmodes[li]; ++m) {
                 const oracle_mode *md = &f->modes[li * f->M + m];
+                if (!oracle_colour_ok(&f->p, md->rgb, &rgb[(size_t)p * 3])) continue;
+                cand++;
                 float d0 = y[0] - md->mu[0], d1 = y[1] - md->mu[1], d2 = y[2] - md->mu[2];
-                if ((d0 * d0 + d1 * d1) + d2 * d2 <= lim) {
-                    label[i] = 1;
-                    break;
-                }
+                if ((d0 * d0 + d1 * d1) + d2 * d2 <= lim) good++;
             }
         }
+        label[i] = cand ? (uint8_t)((255u * good + cand / 2u) / cand) : 0;
     }
     return ORACLE_OK;
 }
@@ -1558,7 +1562,7 @@ int oracle_mlp_grad(const float *w, const float *x, const uint8_t *y, int n, dou
     double xb[24], h1p[64], h1[64], h2p[64], h2[64], d2[64], d1[64];
     for (int r = 0; r < n; ++r) {
         double z = mlp_row(w, x + (size_t)r * 24, xb, h1p, h1, h2p, h2);
-        double t = y[r] ? 1.0 : 0.0;
+        double t = (double)y[r] / 255.0;
         L += (z > 0 ? z : 0.0) - z * t + log1p(exp(-fabs(z)));
         double dz = (1.0 / (1.0 + exp(-z)) - t) / (double)n;
         for (int i = 0; i < 64; ++i) grad[O_W3 + i] += dz * h2[i];

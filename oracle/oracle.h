@@ -169,14 +169,16 @@ float oracle_bf16(float x);      /* round to the nearest bfloat16, ties to even 
 /* 24 features of each listed valid pixel (FP32, before bfloat16 rounding) */
 int  oracle_features24(oracle_forest *f, const uint16_t *depth, const uint8_t *rgb, int W, int H, const float K[4],
                        const int32_t *pix, int n, float *x /* [n][24] */);
-/* 1 iff some mode of the pixel's leaves lies within 5 cm of its world point
- * under `pose` (the labeller of the learned proposal) */
+/* round(255 x the probability that the pixel's hypothesis pick is correct
+ * under `pose`): the fraction of the colour-consistent modes of its leaves
+ * within 5 cm of its world point (the labeller of the learned proposal) */
 int  oracle_label(oracle_forest *f, const uint16_t *depth, const uint8_t *rgb, int W, int H, const float K[4],
                   const double pose[16], const int32_t *pix, int n, uint8_t *label);
 void oracle_mlp_init(uint64_t seed, float *w /* [5825] */);
 /* logits of n rows (inputs rounded to bfloat16 here) */
 int  oracle_mlp_forward(const float *w, const float *x, int n, double *z);
-/* mean binary cross-entropy of n rows and its gradient in FP64 */
+/* mean binary cross-entropy of n rows against targets y / 255 and its
+ * gradient in FP64 */
 int  oracle_mlp_grad(const float *w, const float *x, const uint8_t *y, int n, double *grad /* [5825] */,
                      double *loss);
 

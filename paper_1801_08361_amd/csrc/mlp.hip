@@ -1,6 +1,7 @@
 // Learned proposal on the GPU: a 24-64-64-1 MLP (ReLU, ReLU, sigmoid) that
-// predicts, per pixel, the probability that one of its leaf modes lies within
-// 5 cm of its true world point. Its output becomes integer pick weights for
+// predicts, per pixel, the probability that its hypothesis pick (a mode drawn
+// among the colour-consistent modes of its leaves) lies within 5 cm of its
+// true world point. Its output becomes integer pick weights for
 // the three pixel picks of every hypothesis try; uniform preemptive scoring
 // stays the judge.
 //
@@ -123,7 +124,8 @@ __device__ __forceinline__ float col_sum(float s)
 }
 
 // backward of the tile: gradient partial (NP values) and the loss sum of the
-// valid rows (entry NP) into `out`; dz = (sigmoid(z) - y) * inv_n
+// valid rows (entry NP) into `out`; the target of label q is q / 255 and
+// dz = (sigmoid(z) - q / 255) * inv_n
 __device__ void tile_backward(TileLds &S, const uint16_t *__restrict__ q, const uint8_t *ys, int nvalid, float inv_n,
                               float *__restrict__ out)
 {
@@ -132,7 +134,7 @@ __device__ void tile_backward(TileLds &S, const uint16_t *__restrict__ q, const 
         const float z = S.z[l];
         float dz = 0.0f, loss = 0.0f;
         if (l < nvalid) {
-            const float y = ys[l] ? 1.0f : 0.0f;
+            const float y = (float)ys[l] / 255.0f;
             dz = (1.0f / (1.0f + expf(-z)) - y) * inv_n;
             loss = fmaxf(z, 0.0f) - z * y + log1pf(expf(-fabsf(z)));
         }
@@ -317,14 +319,18 @@ struct PoseF {
     float R[9], t[3];
 };
 
-// 1 iff a mode of the pixel's leaves lies within 5 cm of y = R c + t (FP32,
-// the scoring transform)
-__global__ void k_label(FeatArgs A, PoseF P, const int32_t *__restrict__ pix, int n, uint8_t *__restrict__ lab)
+// The probability that the pixel's hypothesis pick is correct under the
+// pose: among the modes of the pixel's leaves whose colour passes the pick's
+// colour test (|mode - pixel| <= rgb_tol in every channel), the fraction that
+// lie within 5 cm of y = R c + t (FP32, the scoring transform), as
+// round(255 good / candidates) (0 without candidates)
+__global__ void k_label(FeatArgs A, PoseF P, int rgb_tol, const int32_t *__restrict__ pix, int n,
+                        uint8_t *__restrict__ lab)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     const int p = pix[i];
-    uint8_t out = 0;
+    uint32_t cand = 0, good = 0;
     if (p >= 0 && p < A.fr.W * A.fr.H) {
         const uint32_t d = A.fr.depth[p];
         if (valid_depth(A.fr, d)) {
@@ -334,22 +340,23 @@ __global__ void k_label(FeatArgs A, PoseF P, const int32_t *__restrict__ pix, in
             float y[3];
             for (int k = 0; k < 3; ++k)
                 y[k] = fmaf(P.R[k * 3 + 0], c[0], fmaf(P.R[k * 3 + 1], c[1], fmaf(P.R[k * 3 + 2], c[2], P.t[k])));
+            const int pr = A.fr.rgb[(int64_t)p * 3], pg = A.fr.rgb[(int64_t)p * 3 + 1], pb = A.fr.rgb[(int64_t)p * 3 + 2];
             const float lim = 0.05f * 0.05f;
-            for (int t = 0; t < A.T && !out; ++t) {
+            for (int t = 0; t < A.T; ++t) {
                 const int32_t leaf = traverse(A.nodes + (int64_t)t * (A.L - 1), A.L, A.fr, u, v, (int32_t)d);
                 const int64_t li = (int64_t)t * A.L + leaf;
                 for (int m = 0; m < A.nmodes[li]; ++m) {
                     const Mode &md = A.modes[li * A.M + m];
+                    const int mr = (int)(md.rgb & 255u), mg = (int)((md.rgb >> 8) & 255u), mb = (int)((md.rgb >> 16) & 255u);
+                    if (abs(mr - pr) > rgb_tol || abs(mg - pg) > rgb_tol || abs(mb - pb) > rgb_tol) continue;
+                    cand++;
                     const float d0 = y[0] - md.mu[0], d1 = y[1] - md.mu[1], d2 = y[2] - md.mu[2];
-                    if ((d0 * d0 + d1 * d1) + d2 * d2 <= lim) {
-                        out = 1;
-                        break;
-                    }
+                    if ((d0 * d0 + d1 * d1) + d2 * d2 <= lim) good++;
                 }
             }
         }
     }
-    lab[i] = out;
+    lab[i] = cand ? (uint8_t)((255u * good + cand / 2u) / cand) : (uint8_t)0;
 }
 
 // every pixel of a frame: inputs, forward, pick weight floor(sigma 65536) + 1
@@ -628,7 +635,8 @@ extern "C" int reloc_label_pixels(reloc_forest *f, const uint16_t *depth_dev, co
         for (int c = 0; c < 3; ++c) P.R[r * 3 + c] = (float)pose_c2w[r * 4 + c];
         P.t[r] = (float)pose_c2w[r * 4 + 3];
     }
-    RL_LAUNCH("k_label", k_label, dim3((n + 127) / 128), dim3(128), 0, s, feat_args(f, fr), P, pix_dev, n, label_dev);
+    RL_LAUNCH("k_label", k_label, dim3((n + 127) / 128), dim3(128), 0, s, feat_args(f, fr), P, f->p.rgb_tol, pix_dev,
+              n, label_dev);
     RL_HIP(hipGetLastError());
     return RELOC_OK;
 }

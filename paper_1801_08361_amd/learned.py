@@ -6,8 +6,10 @@ concatenates device buffers.
 
 Supervision: a frame whose pose is known (an agent's own tracked frame, or a
 relocalisation accepted by the depth-difference check of Sec. 3.3.1,
-Eqs. 3-4) labels each of its valid pixels 1 when one of the pixel's leaf modes
-lies within 5 cm of the pixel's world point, else 0."""
+Eqs. 3-4) labels each of its valid pixels with the probability that the
+pixel's hypothesis pick is correct: the fraction of the colour-consistent
+modes of its leaves that lie within 5 cm of the pixel's world point (uint8,
+times 255)."""
 from __future__ import annotations
 
 from typing import Callable, Iterable, Optional, Tuple

@@ -9,7 +9,7 @@ import numpy as np
 import pytest
 
 import synthroom as sr
-from tests.gpu_util import banner, need_gpu, pair, to_dev
+from tests.gpu_util import SMALL, banner, need_gpu, pair, to_dev
 
 pytestmark = pytest.mark.gpu
 
@@ -225,7 +225,7 @@ def test_mlp_gradient_matches_oracle():
         w = random_weights(100 + n)
         m.set_weights(w)
         x = bits_to_f32(bf16_bits(rng.normal(size=(n, 24)).astype(np.float32)))
-        y = (rng.random(n) < 0.4).astype(np.uint8)
+        y = np.where(rng.random(n) < 0.4, 255, rng.integers(0, 256, n) * (rng.random(n) < 0.5)).astype(np.uint8)
         banner(f"mlp gradient n={n}")
         g, loss = m.gradient(torch.from_numpy(rows32(x).view(np.int16)).to(dev), torch.from_numpy(y).to(dev))
         gr, lr = oracle.mlp_grad(w, x, y)
@@ -252,8 +252,8 @@ def test_training_lowers_loss_and_ranks_inliers(adapted):
     # train on the even queries of the adapted stretch of the path, hold out the odd ones
     x, y = learned.training_rows(g, frames[0::2])
     assert x.shape[0] == y.shape[0] > 50000
-    base = float(y.float().mean())
-    assert 0.05 < base < 0.95
+    base = float(y.float().mean()) / 255.0
+    assert 0.02 < base < 0.95
     m = rl.Mlp(9)
     g0, l0 = m.gradient(x, y)
     banner("training")
@@ -262,10 +262,11 @@ def test_training_lowers_loss_and_ranks_inliers(adapted):
     # better than the untrained network and than the best constant guess
     h = -(base * np.log(base) + (1 - base) * np.log(1 - base))
     assert l1 < min(l0, h) - 0.01, (l0, l1, h, losses)
-    # held-out frames: inliers rank above outliers (area under the ROC curve)
+    # held-out frames: pixels whose pick can be correct rank above those
+    # whose pick cannot (area under the ROC curve)
     xh, yh = learned.training_rows(g, frames[1::2])
     z = m.logits(xh).cpu().numpy().astype(np.float64)
-    yh = yh.cpu().numpy().astype(bool)
+    yh = yh.cpu().numpy() > 0
     ranks = np.empty(len(z))
     ranks[np.argsort(z, kind="stable")] = np.arange(1, len(z) + 1)
     npos, nneg = int(yh.sum()), int((~yh).sum())
@@ -342,3 +343,70 @@ def test_learned_in_graph_equals_given_weights(adapted):
     import paper_1801_08361_amd as rl2
     with pytest.raises(rl2.RelocError):
         rl.Batch().run([dict(atts[0], weights=m.pixel_weights(g, atts[0]["depth"], atts[0]["rgb"], sc.K))])
+
+
+def test_learned_proposal_gains_good_hypotheses():
+    """What the trained network gains over uniform picks: on held-out queries
+    of ten small rooms (one network for all ten, trained on the GPU from
+    verified extra frames of the same rooms), hypotheses drawn with learned
+    pick weights land within 5 cm / 5 deg of the truth more often, and more
+    attempts succeed, at small hypothesis counts where uniform picks still
+    miss (measured: 0.28 vs 0.20 good hypotheses per attempt at N = 8, 0.53 vs
+    0.40 at N = 16; success 50.5 vs 45.5 % and 69.5 vs 64.0 %)."""
+    dev = need_gpu()
+    import oracle
+    import paper_1801_08361_amd as rl
+    from paper_1801_08361_amd import learned
+    forests, scenes, items = [], [], []
+    for room in range(200, 210):
+        sc = sr.small_scene(room)
+        g = rl.Forest(rl.params_default(**SMALL))
+        for k in range(len(sc.adapt_poses)):
+            d, c = sc.render_adapt(k, device=dev)
+            g.adapt_frame(d, c, sc.K, sc.adapt_poses[k])
+        g.update_modes()
+        forests.append(g)
+        scenes.append(sc)
+        for j, T in enumerate(sc.extra_poses(4, tag=7)):
+            items.append((g, sc, T, 900 + 10 * room + j))
+    banner("learned gain: training rows from verified extra frames")
+    xs, ys = [], []
+    for g, sc, T, tag in items:
+        d, c = sc.render_pose(T, noise_tag=tag, device=dev)
+        pose, _ = learned.verified_pose(g, d, c, sc.K, seed=tag, model_depth=lambda P: sc.model_depth(P, device=dev))
+        if pose is None:
+            continue
+        x, y = learned.frame_rows(g, d, c, sc.K, pose, max_pixels=60_000, seed=tag)
+        xs.append(x)
+        ys.append(y)
+    import torch
+    assert len(xs) >= 5
+    x, y = torch.cat(xs).contiguous(), torch.cat(ys).contiguous()
+    banner("learned gain: training")
+    m, losses = learned.train(x, y, seed=4, epochs=20, batch_rows=4096, lr=2e-3)
+    assert losses[-1] < losses[0]
+
+    def evaluate(n_hyp, use):
+        good = ok = 0
+        for g, sc in zip(forests, scenes):
+            for q in range(len(sc.query_poses)):
+                d, c = sc.render_query(q, device=dev)
+                if use:
+                    r = g.relocalise_learned(m, d, c, sc.K, seed=5000 + q, n_hyp=n_hyp)
+                else:
+                    r = g.relocalise_ex(d, c, sc.K, seed=5000 + q, n_hyp=n_hyp)
+                ok += int(r["status"] == 0 and oracle.pose_success(r["pose"], sc.query_poses[q])[0])
+                tr = g.trace(n_hyp)
+                for h in np.flatnonzero(tr["hyp_try"] >= 0):
+                    T = np.eye(4)
+                    T[:3, :3] = tr["hyp_pose"][h, :9].reshape(3, 3)
+                    T[:3, 3] = tr["hyp_pose"][h, 9:]
+                    good += int(oracle.pose_success(T, sc.query_poses[q])[0])
+        return good, ok
+
+    for n_hyp in (8, 16):
+        banner(f"learned gain: evaluation at N={n_hyp}")
+        gl, sl = evaluate(n_hyp, True)
+        gu, su = evaluate(n_hyp, False)
+        assert gl >= 1.15 * gu, (n_hyp, gl, gu)
+        assert sl >= su, (n_hyp, sl, su)

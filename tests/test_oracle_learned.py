@@ -102,13 +102,14 @@ def test_mlp_forward_and_grad_match_torch(orc):
     w[5696:5760] = rng.normal(scale=0.1, size=64)
     w[-1] = 0.3
     x = rng.normal(size=(200, 24)).astype(np.float32)
-    y = (rng.random(200) < 0.3).astype(np.uint8)
+    # labels 0..255 are the targets y / 255 (hard 0 and 1 included)
+    y = np.where(rng.random(200) < 0.3, 255, rng.integers(0, 256, 200) * (rng.random(200) < 0.5)).astype(np.uint8)
     z = orc.mlp_forward(w, x)
     wt = torch.tensor(w, dtype=torch.float64, requires_grad=True)
     zt = torch_forward(wt, x)
     np.testing.assert_allclose(z, zt.detach().numpy(), rtol=1e-9, atol=1e-9)
     g, loss = orc.mlp_grad(w, x, y)
-    lt = torch.nn.functional.binary_cross_entropy_with_logits(zt, torch.tensor(y, dtype=torch.float64))
+    lt = torch.nn.functional.binary_cross_entropy_with_logits(zt, torch.tensor(y / 255.0, dtype=torch.float64))
     lt.backward()
     assert loss == pytest.approx(lt.item(), rel=1e-12)
     np.testing.assert_allclose(g, wt.grad.numpy(), rtol=1e-9, atol=1e-12)
@@ -167,6 +168,10 @@ def test_features24_rederived(orc, small_forest):
 
 
 def test_labels_rederived(orc, small_forest):
+    """A label is round(255 good / candidates): candidates are the modes of
+    the pixel's leaves within rgb_tol of its colour in every channel (the
+    pick's candidate set), good those within 5 cm of its world point,
+    recomputed here in float64."""
     sc, f = small_forest
     d, c = sc.render_query(4)
     d, c = d.numpy(), c.numpy()
@@ -178,16 +183,21 @@ def test_labels_rederived(orc, small_forest):
     leaves = f.leaves(d, c, sc.K)
     R32 = T[:3, :3].astype(np.float32).astype(np.float64)
     t32 = T[:3, 3].astype(np.float32).astype(np.float64)
-    checked = 0
+    tol = f.params.rgb_tol
+    rgb = c.reshape(-1, 3).astype(np.int64)
+    checked = fractional = 0
     for i, p in enumerate(pix):
         y = R32 @ cam[p] + t32
-        dist2 = [float(np.sum((y - m["mu"].astype(np.float64)) ** 2))
-                 for t in range(f.T) for m in f.leaf_modes(t, int(leaves[t, p]))]
-        if not dist2:
+        cand = [m for t in range(f.T) for m in f.leaf_modes(t, int(leaves[t, p]))
+                if np.all(np.abs(m["rgb"].astype(np.int64) - rgb[p]) <= tol)]
+        if not cand:
             assert lab[i] == 0
             continue
-        dm = min(dist2)
-        if abs(dm - 0.0025) > 1e-6:
-            assert lab[i] == (1 if dm <= 0.0025 else 0), (p, dm)
-            checked += 1
-    assert checked > 250 and 0 < lab.mean() < 1
+        dist2 = [float(np.sum((y - m["mu"].astype(np.float64)) ** 2)) for m in cand]
+        if any(abs(x - 0.0025) <= 1e-6 for x in dist2):
+            continue
+        good = sum(1 for x in dist2 if x <= 0.0025)
+        assert lab[i] == (255 * good + len(cand) // 2) // len(cand), (p, good, len(cand))
+        checked += 1
+        fractional += int(0 < lab[i] < 255)
+    assert checked > 250 and fractional > 10 and 0 < lab.mean() < 255
