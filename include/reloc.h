@@ -259,6 +259,66 @@ int reloc_verify(const uint16_t *da_dev, const uint16_t *db_dev, int32_t W, int3
 int reloc_verify_noalloc(const uint16_t *da_dev, const uint16_t *db_dev, int32_t W, int32_t H, double *valid_frac,
                          double *mu_m, int32_t *accept, void *stream);
 
+/* ---- inter-agent scheduling and pose optimisation (Sec. 3.3.1, 3.3.2) ----
+ * Host-side steps around the relocaliser; host arrays, no device work.
+ * Poses are row-major FP64 4x4 camera-to-world matrices of a frame in one
+ * sub-scene's coordinates; relative transforms and global poses map the
+ * coordinates of one sub-scene into another's (or the global frame's). */
+
+/* The relative transform sample of a verified relocalisation (Sec. 3.3.1,
+ * after Eq. 4): pose_in_a is the frame's relocalised pose in sub-scene a,
+ * pose_in_b its own pose in sub-scene b; a_T_b = pose_in_a pose_in_b^-1 maps
+ * b's coordinates to a's (the paper's (fT_a)^-1 fT_b, whose poses fT_s map
+ * sub-scene coordinates to the camera's). */
+int reloc_relative_transform(const double pose_in_a[16], const double pose_in_b[16], double a_T_b[16]);
+
+typedef struct reloc_collab reloc_collab;
+
+/* State of one collaborative session over n_scenes sub-scenes (2..4096);
+ * scene 0 is the first agent's, whose global pose is the identity. */
+int reloc_collab_create(int32_t n_scenes, uint64_t seed, reloc_collab **out);
+int reloc_collab_destroy(reloc_collab *c);
+/* the local poses of the frames of one scene: poses [n][16], copied */
+int reloc_collab_set_frames(reloc_collab *c, int32_t scene, const double *poses, int32_t n);
+/* Chooses the next attempt (Sec. 3.3.1): draws n_cand candidates
+ * k = (a, (b, i)), candidate j of scheduling round r from Philox4x64-10 with
+ * key (seed, 7) and counter (r, j, 0, 0): the first output picks an ordered
+ * pair of distinct scenes uniformly (pair index p over n (n - 1): a = p /
+ * (n - 1), then b = the (p mod (n - 1))-th scene other than a), the second a
+ * frame of b uniformly (floor(u m / 2^64)). Each is scored by Phi =
+ * phi_new - phi_conf - phi_homog (Eqs. 1-2): phi_new = 1 if exactly one of a
+ * and b is in the pose graph of the last reloc_collab_optimise, phi_conf =
+ * max(0, max over the pair's clusters of (size - 2)), phi_homog = 5 if frame
+ * i's local pose is within 5 cm and 5 deg of a frame of b already tried
+ * against a (reloc_collab_tried). Writes the first candidate with the largest
+ * score; cands_out (may be NULL) receives [n_cand][7] floats (a, b, i, Phi,
+ * phi_new, phi_conf, phi_homog). RELOC_E_STATE until every scene has frames. */
+int reloc_collab_schedule(reloc_collab *c, int32_t n_cand, int32_t *a_out, int32_t *b_out, int32_t *frame_out,
+                          float *cands_out);
+/* records that frame `frame` of scene b was relocalised against scene a */
+int reloc_collab_tried(reloc_collab *c, int32_t a, int32_t b, int32_t frame);
+/* Adds a verified sample a_T_b (Sec. 3.3.2, Sec. 4.2.4): it joins the first
+ * cluster of the pair {a, b} that holds a sample within 20 deg and 10 cm of
+ * it, or starts a new one; *cluster_size (may be NULL) receives the size of
+ * that cluster. Samples of a pair are compared in one orientation (a b_T_a
+ * is inverted). */
+int reloc_collab_add_sample(reloc_collab *c, int32_t a, int32_t b, const double a_T_b[16], int32_t *cluster_size);
+/* the pair's clusters in creation order: sizes [cap], and (may be NULL) the
+ * dual-quaternion blend of each as a_T_b, blended [cap][16]; *n_out = count */
+int reloc_collab_clusters(const reloc_collab *c, int32_t a, int32_t b, int32_t *sizes, double *blended, int32_t cap,
+                          int32_t *n_out);
+/* Pose-graph optimisation (Sec. 3.3.2, Eq. 5): G' joins every pair whose
+ * largest cluster (the earliest on ties) holds at least 2 samples, with the
+ * equal-weight dual-quaternion blend of that cluster (Kavan et al. 2006) as
+ * the edge's transform; G is the connected component of G' holding scene 0.
+ * Starting from poses chained breadth first from scene 0 (gT_b = gT_a aT_b),
+ * Levenberg-Marquardt minimises the sum over G's edges of
+ * |v(gT_b^-1 gT_a aT_b)|^2, v(T) = (imaginary part of T's rotation quaternion
+ * with non-negative real part, T's translation), with gT_0 = I. Writes
+ * in_graph [n] (1 for scenes of G), global_poses [n][16] (gT_s; identity
+ * outside G) and the final cost (any of them may be NULL). */
+int reloc_collab_optimise(reloc_collab *c, int32_t *in_graph, double *global_poses, double *cost_out);
+
 /* ---- learned proposal (an extension; the paper picks pixels uniformly) ----
  * A 24-64-64-1 MLP (ReLU, ReLU, sigmoid) scores each valid pixel of a query
  * frame with the probability that its hypothesis pick (a mode drawn among the

@@ -126,6 +126,15 @@ _SIGS = {
                      C.c_void_p],
     "reloc_verify_noalloc": [C.c_void_p, C.c_void_p, C.c_int32, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p,
                              C.c_void_p],
+    "reloc_relative_transform": [C.c_void_p, C.c_void_p, C.c_void_p],
+    "reloc_collab_create": [C.c_int32, C.c_uint64, C.c_void_p],
+    "reloc_collab_destroy": [C.c_void_p],
+    "reloc_collab_set_frames": [C.c_void_p, C.c_int32, C.c_void_p, C.c_int32],
+    "reloc_collab_schedule": [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p],
+    "reloc_collab_tried": [C.c_void_p, C.c_int32, C.c_int32, C.c_int32],
+    "reloc_collab_add_sample": [C.c_void_p, C.c_int32, C.c_int32, C.c_void_p, C.c_void_p],
+    "reloc_collab_clusters": [C.c_void_p, C.c_int32, C.c_int32, C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p],
+    "reloc_collab_optimise": [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p],
     "reloc_mlp_create": [C.c_uint64, C.c_void_p, C.c_void_p],
     "reloc_mlp_destroy": [C.c_void_p],
     "reloc_mlp_get_weights": [C.c_void_p, C.c_void_p],
@@ -633,3 +642,76 @@ class Mlp:
                                              pr.data_ptr() if pr is not None else None, _stream(stream)),
                "reloc_mlp_pixel_weights")
         return (w, pr) if with_prob else w
+
+
+# -- inter-agent scheduling and pose optimisation (host code in the library) ----
+
+
+def relative_transform(pose_in_a, pose_in_b) -> np.ndarray:
+    """a_T_b = pose_in_a pose_in_b^-1 (reloc_relative_transform)."""
+    A, B = _pose(pose_in_a), _pose(pose_in_b)
+    out = np.zeros(16)
+    _check(lib().reloc_relative_transform(A.ctypes.data, B.ctypes.data, out.ctypes.data), "reloc_relative_transform")
+    return out.reshape(4, 4)
+
+
+class Collab:
+    """Scheduling, clustering and pose-graph state of a collaborative session
+    (reloc_collab)."""
+
+    def __init__(self, n_scenes: int, seed: int = 0):
+        self.n = int(n_scenes)
+        self._h = C.c_void_p()
+        _check(lib().reloc_collab_create(self.n, C.c_uint64(seed), C.byref(self._h)), "reloc_collab_create")
+
+    def close(self) -> None:
+        if self._h is not None and self._h.value and _lib is not None:
+            _lib.reloc_collab_destroy(self._h)
+        self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_frames(self, scene: int, poses) -> None:
+        P = np.ascontiguousarray(np.asarray(poses, dtype=np.float64).reshape(-1, 16))
+        _check(lib().reloc_collab_set_frames(self._h, int(scene), P.ctypes.data, len(P)), "reloc_collab_set_frames")
+
+    def schedule(self, n_cand: int = 10):
+        """(a, b, frame, candidates [n_cand, 7]: a, b, i, Phi, phi_new, phi_conf, phi_homog)."""
+        a, b, i = C.c_int32(0), C.c_int32(0), C.c_int32(0)
+        cands = np.zeros((n_cand, 7), dtype=np.float32)
+        _check(lib().reloc_collab_schedule(self._h, int(n_cand), C.byref(a), C.byref(b), C.byref(i),
+                                           cands.ctypes.data), "reloc_collab_schedule")
+        return a.value, b.value, i.value, cands
+
+    def tried(self, a: int, b: int, frame: int) -> None:
+        _check(lib().reloc_collab_tried(self._h, int(a), int(b), int(frame)), "reloc_collab_tried")
+
+    def add_sample(self, a: int, b: int, a_T_b) -> int:
+        T = _pose(a_T_b)
+        size = C.c_int32(0)
+        _check(lib().reloc_collab_add_sample(self._h, int(a), int(b), T.ctypes.data, C.byref(size)),
+               "reloc_collab_add_sample")
+        return size.value
+
+    def clusters(self, a: int, b: int, cap: int = 256):
+        """(sizes [k], blended a_T_b [k, 4, 4]) of the pair's clusters."""
+        sizes = np.zeros(cap, dtype=np.int32)
+        blended = np.zeros((cap, 16))
+        n = C.c_int32(0)
+        _check(lib().reloc_collab_clusters(self._h, int(a), int(b), sizes.ctypes.data, blended.ctypes.data, cap,
+                                           C.byref(n)), "reloc_collab_clusters")
+        k = min(n.value, cap)
+        return sizes[:k].copy(), blended[:k].reshape(k, 4, 4).copy()
+
+    def optimise(self):
+        """(in_graph [n] bool, global poses [n, 4, 4], final cost)."""
+        ing = np.zeros(self.n, dtype=np.int32)
+        X = np.zeros((self.n, 16))
+        cost = C.c_double(0)
+        _check(lib().reloc_collab_optimise(self._h, ing.ctypes.data, X.ctypes.data, C.byref(cost)),
+               "reloc_collab_optimise")
+        return ing.astype(bool), X.reshape(self.n, 4, 4), cost.value

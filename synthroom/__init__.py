@@ -412,3 +412,31 @@ def queue_attempts(n_attempts: int, n_forests: int, n_queries: int, overlap: flo
         out.append(dict(forest=f, source=src, overlap=same, width=s[0], height=s[1],
                         query=int(g.integers(0, n_queries)), seed=int(g.integers(1, 1 << 62))))
     return out
+
+
+def collaborative_session(n_agents: int = 3, index: int = 0, n_poses: int = 40, width: int = 320, height: int = 240):
+    """Several agents reconstructing one room, each in its own sub-scene
+    coordinate frame: the room of small_scene(index) and one camera path
+    through it, of which agent k walks poses [k n_poses / 2, k n_poses / 2 +
+    n_poses) (consecutive agents share half of their paths, as agents whose
+    sub-scenes overlap), and per agent a random rigid transform W that maps
+    its sub-scene coordinates to the room's. An agent's local poses are W^-1
+    times its world poses. Returns (scene, world poses [n_agents][n_poses],
+    W [n_agents])."""
+    sc = small_scene(index, width, height)
+    g = rng(17, index, n_agents)
+    half = n_poses // 2
+    path = make_trajectory(sc.room, half * (n_agents - 1) + n_poses, sub_seed(sc.seed, 21))
+    world, frames = [], []
+    for k in range(n_agents):
+        world.append(path[k * half:k * half + n_poses].copy())
+        q = g.normal(size=4)
+        q /= np.linalg.norm(q)
+        w, x, y, z = q
+        W = np.eye(4)
+        W[:3, :3] = [[1 - 2 * (y * y + z * z), 2 * (x * y - w * z), 2 * (x * z + w * y)],
+                     [2 * (x * y + w * z), 1 - 2 * (x * x + z * z), 2 * (y * z - w * x)],
+                     [2 * (x * z - w * y), 2 * (y * z + w * x), 1 - 2 * (x * x + y * y)]]
+        W[:3, 3] = g.uniform(-3.0, 3.0, size=3)
+        frames.append(W)
+    return sc, world, frames
