@@ -796,13 +796,17 @@ struct Attempt {
     int32_t *guide;                // [P] weighted picks: first pool entry of each draw bucket
     unsigned long long *gsel;      // [0] total weight [1] bucket multiplier [2] buckets in use
     uint32_t *wbuf;                // [P] learned pick weights (learned proposal only)
-    int32_t *misc;                 // [0] pool size [1] live [2] valid [3] rounds done
+    int32_t *misc;                 // [0] pool size [2] valid hypotheses
+    int32_t *rl;                   // [MAX_ROUNDS + 1] live hypotheses at the start of round r (r = 0: the
+                                   // valid ones; 0 once the attempt has finished): round r runs iff
+                                   // rl[r] >= 1 (r = 0) or rl[r] > 1; the cull of round r writes rl[r + 1]
     Hyp *hyp;                      // [N]
     double *hyp_init;              // [N][12]
     int32_t *hyp_try;              // [N]
-    float *energy;                 // [N] accumulated energy of the hypothesis at each live position
+    float *energy;                 // [2][N] accumulated energy of the hypothesis at each live position
     double *sums;                  // [N][NSUM] running inlier sums
-    int32_t *alive;                // [N]
+    int32_t *alive;                // [2][N] the live list scored in round r is buffer r & 1; the cull of round r
+                                   // writes buffer (r + 1) & 1, so that it never overwrites what it reads
     int32_t *pos;                  // [N] survivor i's position in the list it was scored in
     float *lpose;                  // [N][12] FP32 pose (R row-major, t) of the hypothesis at each live position
     float4 *draws;                 // [rounds][B] camera point, pixel index bits of every draw

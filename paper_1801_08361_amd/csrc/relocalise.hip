@@ -61,13 +61,17 @@ __device__ __forceinline__ void wave_lds_sync()
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// round r of attempt A runs when no later round has started and at least one
-// (r = 0) or more than one (r > 0) hypothesis is live
+// round r of attempt A runs when at least one (r = 0) or more than one
+// (r > 0) hypothesis is live at its start
 __device__ __forceinline__ bool round_active(const Attempt &A, int r)
 {
-    int done = A.misc[3], na = A.misc[1];
-    return done == r && (r == 0 ? na >= 1 : na > 1);
+    const int na = A.rl[r];
+    return r == 0 ? na >= 1 : na > 1;
 }
+
+// the live list scored in round r (buffer r & 1) and the one its cull writes
+__device__ __forceinline__ int32_t *live_list(const Attempt &A, int r) { return A.alive + (int64_t)(r & 1) * A.N; }
+__device__ __forceinline__ float *live_energy(const Attempt &A, int r) { return A.energy + (int64_t)(r & 1) * A.N; }
 
 // ---------------------------------------------------------------------------
 // features and traversal of every pixel
@@ -354,9 +358,7 @@ __global__ void __launch_bounds__(1024) k_b_pool_scan(const Attempt *__restrict_
                 A.gsel[2] = tot ? (unsigned long long)guide_bucket(tot - 1ull, M) + 1ull : 0ull;
             }
             A.misc[0] = carry;
-            A.misc[1] = 0;
             A.misc[2] = 0;
-            A.misc[3] = 0;
             A.stats[0] = 0ull;
             A.stats[1] = 0ull;
             A.stats[2] = 0ull;
@@ -737,7 +739,7 @@ __global__ void __launch_bounds__(1024) k_b_alive_init(const Attempt *__restrict
             for (int w = 0; w < wave; ++w) off += wcnt[w];
             if (ok) {
                 const int pos = off + __popcll(m & lanemask_lt());
-                A.alive[pos] = h;
+                A.alive[pos] = h;     // buffer 0: the list of round 0
                 A.energy[pos] = 0.0f;
                 for (int k = 0; k < 12; ++k) A.lpose[pos * 12 + k] = pz[k];
             }
@@ -750,9 +752,10 @@ __global__ void __launch_bounds__(1024) k_b_alive_init(const Attempt *__restrict
             __syncthreads();
         }
         if (threadIdx.x == 0) {
-            A.misc[1] = carry;
             A.misc[2] = carry;
+            A.rl[0] = carry;
         }
+        if (threadIdx.x >= 1 && threadIdx.x <= MAX_ROUNDS) A.rl[threadIdx.x] = 0;
         __syncthreads();
     }
 }
@@ -791,12 +794,14 @@ __device__ void cull_round(const Attempt &A, int r, unsigned long long *__restri
 {
     const int nt = (int)blockDim.x;
     const int lane = __lane_id(), wave = (int)(threadIdx.x >> 6);
-    const int na = A.misc[1];
+    const int na = A.rl[r];
+    const int32_t *al = live_list(A, r);
+    const float *en = live_energy(A, r);
     int n2 = 64;
     while (n2 < na) n2 <<= 1;
     for (int ap = threadIdx.x; ap < n2; ap += nt) {
         if (ap < na) {
-            const int h = A.alive[ap];
+            const int h = al[ap];
             const int ng = (A.B + GROUP - 1) / GROUP;
             const float *gs = A.gs + ap;
             // group sums in group order, loaded 32 at a time
@@ -809,7 +814,7 @@ __device__ void cull_round(const Attempt &A, int r, unsigned long long *__restri
                 for (int k = 0; k < 32; ++k)
                     if (k0 + k < ng) Ssum = Ssum + v[k];
             }
-            const float E = A.energy[ap] + Ssum;
+            const float E = en[ap] + Ssum;
             keys[ap] = cull_key(E, h, ap);
             if (r < MAX_ROUNDS) {
                 A.tr_alive[r * A.N + ap] = h;
@@ -853,11 +858,13 @@ __device__ void cull_round(const Attempt &A, int r, unsigned long long *__restri
         __syncthreads();
     }
     const int keep = (na + 1) / 2;
+    int32_t *al_next = live_list(A, r + 1);
+    float *en_next = live_energy(A, r + 1);
     for (int i = threadIdx.x; i < keep; i += nt) {
         const unsigned long long key = keys[i];
-        A.alive[i] = (int32_t)((key >> 12) & 0xFFFFFull);
+        al_next[i] = (int32_t)((key >> 12) & 0xFFFFFull);
         A.pos[i] = (int32_t)(key & 0xFFFull);
-        A.energy[i] = key_float((uint32_t)(key >> 32));   // read above, before the first barrier
+        en_next[i] = key_float((uint32_t)(key >> 32));
     }
     __syncthreads();
     if (threadIdx.x == 0) {
@@ -865,8 +872,7 @@ __device__ void cull_round(const Attempt &A, int r, unsigned long long *__restri
         A.stats[0] += (unsigned long long)na * A.stats[2];
         A.stats[1] += (unsigned long long)na * (unsigned long long)A.B;
         A.stats[2] = 0ull;
-        A.misc[1] = keep;
-        A.misc[3] = r + 1;
+        A.rl[r + 1] = keep;
     }
     __syncthreads();
 }
@@ -906,20 +912,30 @@ __global__ void __launch_bounds__(64 * GROUP) k_b_score(const Attempt *__restric
         const int a = attempt_of(S, u);
         const Attempt &A = att[a];
         const int local = u - S.off[a];
-        const int na = A.misc[1];
+        const int na = A.rl[r];
         const int nch = (A.B + dpu - 1) / dpu;
         const int a0 = (local / nch) * 64;
         const int ch = local % nch;
+        // the lane's pose and the wavefront's first draw are loaded together
+        // with the live count (a lane past the live list reads a row it does
+        // not use; the addresses are within the arrays either way)
+        const int ap = a0 + lane;
+        const float *lp = A.lpose + (int64_t)min(ap, A.N - 1) * 12;
+        const float R0 = lp[0], R1 = lp[1], R2 = lp[2], R3 = lp[3], R4 = lp[4], R5 = lp[5], R6 = lp[6],
+                    R7 = lp[7], R8 = lp[8];
+        const float t0 = lp[9], t1 = lp[10], t2 = lp[11];
+        const int i1 = min((ch + 1) * dpu, A.B);
+        const int64_t rb = (int64_t)r * A.B;
+        const int i_first = ch * dpu + wv;
+        float4 dr_first = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+        int2 e_first = make_int2(0, 0);
+        if (i_first < i1) {
+            dr_first = A.draws[rb + i_first];
+            if (lane < A.T) e_first = A.dtree[(rb + i_first) * A.T + lane];
+        }
         if (round_active(A, r) && a0 < na) {
-            const int ap = a0 + lane;
             const bool act = ap < na;
             const bool publish = a0 == 0;
-            const float *lp = A.lpose + (act ? ap : a0) * 12;
-            const float R0 = lp[0], R1 = lp[1], R2 = lp[2], R3 = lp[3], R4 = lp[4], R5 = lp[5], R6 = lp[6],
-                        R7 = lp[7], R8 = lp[8];
-            const float t0 = lp[9], t1 = lp[10], t2 = lp[11];
-            const int i1 = min((ch + 1) * dpu, A.B);
-            const int64_t rb = (int64_t)r * A.B;
             uint32_t wcnt = 0;   // this wavefront's mode count over its draws
             for (int g0 = ch * dpu; g0 < i1; g0 += GROUP) {
                 for (int k = 0; k < GROUP / nw; ++k) {
@@ -928,7 +944,11 @@ __global__ void __launch_bounds__(64 * GROUP) k_b_score(const Attempt *__restric
                     const bool has = i < i1;
                     float4 dr = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
                     int base = 0, nm = 0;
-                    if (has) {
+                    if (i == i_first) {
+                        dr = dr_first;
+                        base = e_first.x;
+                        nm = e_first.y;
+                    } else if (has) {
                         dr = A.draws[rb + i];
                         if (lane < A.T) {
                             const int2 e = A.dtree[(rb + i) * A.T + lane];
@@ -1082,10 +1102,10 @@ __device__ __forceinline__ void refine_sums_at(const Attempt &A, int r, int h, i
     }
 }
 
-// the same for survivor position sidx; returns the hypothesis index
+// the same for survivor position sidx of round r; returns the hypothesis index
 __device__ __forceinline__ int refine_sums_of(const Attempt &A, int r, int sidx, double s[NSUM])
 {
-    const int h = A.alive[sidx];
+    const int h = live_list(A, r + 1)[sidx];
     refine_sums_at(A, r, h, A.pos[sidx], s);
     return h;
 }
@@ -1121,12 +1141,13 @@ __global__ void __launch_bounds__(64) k_b_refine(const Attempt *__restrict__ att
         const int a = attempt_of(S, u);
         const Attempt &A = att[a];
         const int sidx = u - S.off[a];
-        // the round's counters and the survivor's slot in one round trip
-        // (sidx is below the planned survivor bound, so within the live
-        // arrays; a slot past the live count is read but not used)
-        const int4 mc = *(const int4 *)A.misc;
-        const int h = A.alive[sidx], ap = A.pos[sidx];
-        if ((mc.w != r + 1) | (sidx >= mc.y) | (h < 0) | (ap < 0)) continue;
+        // the survivor count and the survivor's slot loaded together (sidx is
+        // below the planned survivor bound, so within the live arrays; a slot
+        // past the survivor count is read but not used; the count is 0 when
+        // round r did not run)
+        const int keep = A.rl[r + 1];
+        const int h = live_list(A, r + 1)[sidx], ap = A.pos[sidx];
+        if ((sidx >= keep) | (h < 0) | (ap < 0)) continue;
         double s[NSUM];
         refine_sums_at(A, r, h, ap, s);
         if (__lane_id() == 0) refine_solve_of(A, sidx, h, s);
@@ -1139,9 +1160,8 @@ __global__ void __launch_bounds__(64) k_b_refine_sums(const Attempt *__restrict_
     FOR_UNITS(S, u) {
         const int a = attempt_of(S, u);
         const Attempt &A = att[a];
-        if (A.misc[3] != r + 1) continue;
         const int sidx = u - S.off[a];
-        if (sidx >= A.misc[1]) continue;
+        if (sidx >= A.rl[r + 1]) continue;
         double s[NSUM];
         refine_sums_of(A, r, sidx, s);
     }
@@ -1153,15 +1173,85 @@ __global__ void __launch_bounds__(64) k_b_refine_solve(const Attempt *__restrict
     FOR_UNITS(S, u) {
         const int a = attempt_of(S, u);
         const Attempt &A = att[a];
-        if (A.misc[3] != r + 1) continue;
         const int sidx = (u - S.off[a]) * 64 + __lane_id();
-        if (sidx >= A.misc[1]) continue;
-        const int h = A.alive[sidx];
+        if (sidx >= A.rl[r + 1]) continue;
+        const int h = live_list(A, r + 1)[sidx];
         double s[NSUM];
         const double *run = A.sums + (int64_t)h * NSUM;
 #pragma unroll
         for (int k = 0; k < NSUM; ++k) s[k] = run[k];
         refine_solve_of(A, sidx, h, s);
+    }
+}
+
+// Cull and refinement of a small round (at most FUSED_LIVE live hypotheses
+// per attempt) in one kernel: one wavefront per survivor slot. Each
+// wavefront forms every live hypothesis's energy exactly as the cull does
+// (group sums in group order, added to the accumulated energy), ranks the
+// keys (energy, index) itself, takes the hypothesis of rank sidx, writes its
+// entry of the next live list and refines it; the wavefront of slot 0 also
+// writes the round's trace, statistics and survivor count. The lists are
+// double-buffered by round parity, so no wavefront overwrites what another
+// reads.
+constexpr int FUSED_LIVE = 64;    // live hypotheses per attempt up to which a round culls in its refinement
+
+__global__ void __launch_bounds__(64) k_b_cull_refine(const Attempt *__restrict__ att, Stage S, int r)
+{
+    FOR_UNITS(S, u) {
+        const int a = attempt_of(S, u);
+        const Attempt &A = att[a];
+        const int sidx = u - S.off[a];
+        const int lane = __lane_id();
+        if (!round_active(A, r)) continue;
+        const int na = A.rl[r];        // <= FUSED_LIVE: one live position per lane
+        const int keep = (na + 1) / 2;
+        if (sidx >= keep) continue;
+        const int ng = (A.B + GROUP - 1) / GROUP;
+        const bool live = lane < na;
+        const int apl = live ? lane : 0;
+        const int hl = live_list(A, r)[apl];
+        const float El = live_energy(A, r)[apl];
+        // the group sums in group order, loaded 64 at a time
+        const float *gs = A.gs + apl;
+        float Ssum = 0.0f;
+        for (int k0 = 0; k0 < ng; k0 += 64) {
+            float v[64];
+#pragma unroll
+            for (int k = 0; k < 64; ++k) v[k] = k0 + k < ng ? gs[(int64_t)(k0 + k) * A.N] : 0.0f;
+#pragma unroll
+            for (int k = 0; k < 64; ++k)
+                if (k0 + k < ng) Ssum = Ssum + v[k];
+        }
+        const float E = El + Ssum;
+        const unsigned long long key = live ? cull_key(E, hl, lane) : ~0ull;
+        // rank: how many live keys are smaller (keys are distinct)
+        int rank = 0;
+        for (int q = 0; q < na; ++q) rank += __shfl(key, q, 64) < key;
+        const uint64_t m = __ballot(live && rank == sidx);
+        const unsigned long long kk = __shfl(key, __ffsll((unsigned long long)m) - 1, 64);
+        const int h = (int)((kk >> 12) & 0xFFFFFull);
+        const int ap = (int)(kk & 0xFFFull);
+        if (lane == 0) {
+            live_list(A, r + 1)[sidx] = h;
+            live_energy(A, r + 1)[sidx] = key_float((uint32_t)(kk >> 32));
+            A.pos[sidx] = ap;
+        }
+        if (sidx == 0) {
+            if (r < MAX_ROUNDS && live) {
+                A.tr_alive[r * A.N + lane] = hl;
+                A.tr_energy[r * A.N + lane] = E;
+            }
+            if (lane == 0) {
+                if (r < MAX_ROUNDS) A.tr_n_alive[r] = na;
+                A.stats[0] += (unsigned long long)na * A.stats[2];
+                A.stats[1] += (unsigned long long)na * (unsigned long long)A.B;
+                A.stats[2] = 0ull;
+                A.rl[r + 1] = keep;
+            }
+        }
+        double sm[NSUM];
+        refine_sums_at(A, r, h, ap, sm);
+        if (lane == 0) refine_solve_of(A, sidx, h, sm);
     }
 }
 
@@ -1175,7 +1265,14 @@ __global__ void __launch_bounds__(64) k_b_finish(const Attempt *__restrict__ att
         o.score = 0.0f;
         o.pool_size = A.misc[0];
         o.n_valid = A.misc[2];
-        o.n_rounds = A.misc[3];
+        // rounds run: the first r >= 1 that starts with at most one live
+        // hypothesis (none when no hypothesis is valid)
+        int nr = 0;
+        if (A.rl[0] >= 1) {
+            nr = 1;
+            while (nr < MAX_ROUNDS && A.rl[nr] > 1) ++nr;
+        }
+        o.n_rounds = nr;
         o.final_hyp = -1;
         o.mode_evals = A.stats[0];
         o.pair_evals = A.stats[1];
@@ -1184,7 +1281,7 @@ __global__ void __launch_bounds__(64) k_b_finish(const Attempt *__restrict__ att
         } else if (o.n_valid == 0) {
             o.status = *A.total_samples == 0ull ? RELOC_FAIL_NO_MODES : RELOC_FAIL_NO_HYPOTHESIS;
         } else {
-            const int h = A.alive[0];
+            const int h = live_list(A, nr)[0];
             const Hyp &hy = A.hyp[h];
             for (int rr = 0; rr < 3; ++rr) {
                 for (int c = 0; c < 3; ++c) o.pose_c2w[rr * 4 + c] = hy.R[rr * 3 + c];
@@ -1229,6 +1326,7 @@ struct Shape {
 struct Plan {
     std::vector<Shape> shape;
     int n = 0, rounds = 0, tm_max = 1, m_max = 1;
+    int fused_from = 0;             // rounds from here on cull inside their refinement (k_b_cull_refine)
     char *arena = nullptr;
     size_t arena_bytes = 0;
     Attempt *d_att = nullptr;
@@ -1278,12 +1376,13 @@ static size_t carve(const Shape &s, char *base, Attempt &A)
     A.gsel = (unsigned long long *)take(3 * 8);
     A.wbuf = (uint32_t *)take(s.weights == 2 ? (size_t)P * 4 : 4);
     A.misc = (int32_t *)take(16);
+    A.rl = (int32_t *)take((size_t)(MAX_ROUNDS + 1) * 4);
     A.hyp = (Hyp *)take((size_t)s.N * sizeof(Hyp));
     A.hyp_init = (double *)take((size_t)s.N * 12 * 8);
     A.hyp_try = (int32_t *)take((size_t)s.N * 4);
-    A.energy = (float *)take((size_t)s.N * 4);
+    A.energy = (float *)take((size_t)2 * s.N * 4);
     A.sums = (double *)take((size_t)s.N * NSUM * 8);
-    A.alive = (int32_t *)take((size_t)s.N * 4);
+    A.alive = (int32_t *)take((size_t)2 * s.N * 4);
     A.pos = (int32_t *)take((size_t)s.N * 4);
     A.lpose = (float *)take((size_t)s.N * 12 * 4);
     const int rounds = rounds_for(s.N);
@@ -1295,7 +1394,7 @@ static size_t carve(const Shape &s, char *base, Attempt &A)
     A.tr_alive = (int32_t *)take((size_t)MAX_ROUNDS * s.N * 4);
     A.tr_energy = (float *)take((size_t)MAX_ROUNDS * s.N * 4);
     A.tr_n_alive = (int32_t *)take((size_t)MAX_ROUNDS * 4);
-    A.result = (Result *)take(sizeof(Result));
+    A.result = nullptr;   // a slot of the plan's pinned host results, written by k_b_finish
     return off;
 }
 
@@ -1424,6 +1523,11 @@ static int enqueue(const Plan *pl, const Sched &sc, const Stages &st, hipStream_
         else
             RL_LAUNCH("k_b_score", k_b_score<1>, dim3(grid_of(st.score[r], sc.grid, sc.xcd)), dim3(64 * nw), smem,
                       s, d, st.score[r], r, sc.dpu, pl->tm_max);
+        if (r >= pl->fused_from && st.refine[r].total <= FUSED_REFINE) {
+            RL_LAUNCH("k_b_cull_refine", k_b_cull_refine, dim3(grid_of(st.refine[r], 0, sc.xcd)), dim3(64), 0, s, d,
+                      st.refine[r], r);
+            continue;
+        }
         RL_LAUNCH("k_b_cull", k_b_cull, dim3(grid_of(att, cap, 0)), dim3(CULL_THREADS), 0, s, d, att, r);
         if (st.refine[r].total <= FUSED_REFINE) {
             RL_LAUNCH("k_b_refine", k_b_refine, dim3(grid_of(st.refine[r], 0, sc.xcd)), dim3(64), 0, s, d,
@@ -1602,6 +1706,14 @@ static Plan *find_or_make_plan(reloc_batch *b, const std::vector<Shape> &shape, 
     for (const Shape &s : shape) {
         pl->rounds = std::max(pl->rounds, rounds_for(s.N));
         pl->m_max = std::max(pl->m_max, s.M);
+        // the first round whose live list is at most FUSED_LIVE long whatever
+        // the number of valid hypotheses (N halved once per round)
+        int r = 0, bound = s.N;
+        while (bound > FUSED_LIVE) {
+            bound = (bound + 1) / 2;
+            ++r;
+        }
+        pl->fused_from = std::max(pl->fused_from, r);
     }
     size_t total = 0;
     pl->slices.resize(pl->n);
@@ -1614,14 +1726,25 @@ static Plan *find_or_make_plan(reloc_batch *b, const std::vector<Shape> &shape, 
     if (hipMalloc((void **)&pl->arena, total) != hipSuccess ||
         hipMalloc((void **)&pl->d_att, sizeof(Attempt) * pl->n) != hipSuccess ||
         hipHostMalloc((void **)&pl->h_att, sizeof(Attempt) * pl->n, hipHostMallocDefault) != hipSuccess ||
-        hipHostMalloc((void **)&pl->h_res, sizeof(Result) * pl->n, hipHostMallocDefault) != hipSuccess) {
+        hipHostMalloc((void **)&pl->h_res, sizeof(Result) * pl->n, hipHostMallocCoherent) != hipSuccess) {
         pl->arena_bytes = 0;
         free_plan(b, pl);
         *rc = RELOC_E_NOMEM;
         return nullptr;
     }
     b->bytes += total;
-    for (int a = 0; a < pl->n; ++a) carve(shape[a], pl->arena + at[a], pl->slices[a]);
+    // results go straight from k_b_finish into coherent pinned host memory (no
+    // copy per attempt after the graph)
+    Result *d_res = nullptr;
+    if (hipHostGetDevicePointer((void **)&d_res, pl->h_res, 0) != hipSuccess) {
+        free_plan(b, pl);
+        *rc = RELOC_E_HIP;
+        return nullptr;
+    }
+    for (int a = 0; a < pl->n; ++a) {
+        carve(shape[a], pl->arena + at[a], pl->slices[a]);
+        pl->slices[a].result = d_res + a;
+    }
     pl->last_use = ++b->clock;
     b->plans.push_back(pl);
     return pl;
@@ -1686,8 +1809,6 @@ static int run_batch(reloc_batch *b, const reloc_attempt *att, int n, hipStream_
     b->last_desc = pl->desc;
     rc = run_plan(pl, s);
     if (rc) return rc;
-    for (int a = 0; a < n; ++a)
-        RL_HIP(hipMemcpyAsync(&pl->h_res[a], pl->slices[a].result, sizeof(Result), hipMemcpyDeviceToHost, s));
     RL_HIP(hipStreamSynchronize(s));
     if (plan_out) *plan_out = pl;
     return RELOC_OK;
