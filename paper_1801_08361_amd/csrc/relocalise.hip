@@ -1330,7 +1330,8 @@ struct Plan {
     char *arena = nullptr;
     size_t arena_bytes = 0;
     Attempt *d_att = nullptr;
-    Attempt *h_att = nullptr;       // pinned
+    Attempt *h_att = nullptr;       // pinned, mapped: the graph's first kernel copies it to d_att
+    const Attempt *h_att_dev = nullptr;   // its device address
     Result *h_res = nullptr;        // pinned
     std::vector<Attempt> slices;    // scratch pointers per attempt
     int32_t *d_off = nullptr;       // stage offsets of the chosen schedule
@@ -1409,6 +1410,12 @@ static void free_plan(reloc_batch *b, Plan *pl)
     if (pl->h_res) (void)hipHostFree(pl->h_res);
     b->bytes -= pl->arena_bytes;
     delete pl;
+}
+
+// copies n8 8-byte words (the batch's descriptors) from host-mapped memory
+__global__ void __launch_bounds__(256) k_b_desc(const uint2 *__restrict__ src, uint2 *__restrict__ dst, int n8)
+{
+    for (int i = (int)threadIdx.x; i < n8; i += 256) dst[i] = src[i];
 }
 
 // stages of one schedule in launch order
@@ -1497,6 +1504,11 @@ static int enqueue(const Plan *pl, const Sched &sc, const Stages &st, hipStream_
 {
     const Attempt *d = pl->d_att;
     const int cap = 4096;
+    // the attempts' descriptors, written by the host into mapped pinned
+    // memory before each launch, copied to device memory by the first kernel
+    static_assert(sizeof(Attempt) % 8 == 0, "descriptor copied in 8-byte words");
+    RL_LAUNCH("k_b_desc", k_b_desc, dim3(1), dim3(256), 0, s, (const uint2 *)pl->h_att_dev, (uint2 *)pl->d_att,
+              (int)(sizeof(Attempt) / 8) * pl->n);
     // one workgroup per attempt: plain round-robin ownership
     Stage att = st.att;
     att.xcd = 0;
@@ -1725,7 +1737,7 @@ static Plan *find_or_make_plan(reloc_batch *b, const std::vector<Shape> &shape, 
     pl->arena_bytes = total;
     if (hipMalloc((void **)&pl->arena, total) != hipSuccess ||
         hipMalloc((void **)&pl->d_att, sizeof(Attempt) * pl->n) != hipSuccess ||
-        hipHostMalloc((void **)&pl->h_att, sizeof(Attempt) * pl->n, hipHostMallocDefault) != hipSuccess ||
+        hipHostMalloc((void **)&pl->h_att, sizeof(Attempt) * pl->n, hipHostMallocCoherent) != hipSuccess ||
         hipHostMalloc((void **)&pl->h_res, sizeof(Result) * pl->n, hipHostMallocCoherent) != hipSuccess) {
         pl->arena_bytes = 0;
         free_plan(b, pl);
@@ -1736,7 +1748,8 @@ static Plan *find_or_make_plan(reloc_batch *b, const std::vector<Shape> &shape, 
     // results go straight from k_b_finish into coherent pinned host memory (no
     // copy per attempt after the graph)
     Result *d_res = nullptr;
-    if (hipHostGetDevicePointer((void **)&d_res, pl->h_res, 0) != hipSuccess) {
+    if (hipHostGetDevicePointer((void **)&d_res, pl->h_res, 0) != hipSuccess ||
+        hipHostGetDevicePointer((void **)&pl->h_att_dev, pl->h_att, 0) != hipSuccess) {
         free_plan(b, pl);
         *rc = RELOC_E_HIP;
         return nullptr;
@@ -1801,7 +1814,6 @@ static int run_batch(reloc_batch *b, const reloc_attempt *att, int n, hipStream_
         A.seed = x.seed;
         pl->h_att[a] = A;
     }
-    RL_HIP(hipMemcpyAsync(pl->d_att, pl->h_att, sizeof(Attempt) * n, hipMemcpyHostToDevice, s));
     if (!pl->exec) {
         rc = tune(b, pl, s);
         if (rc) return rc;
