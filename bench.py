@@ -19,23 +19,29 @@ against uniform picks at 256, 64, 16 and 1024, and the fraction of
 hypotheses within 5 cm / 5 deg of the truth); the batched form on the mixed
 workload (64 attempts against 8 small-room forests, frame sizes drawn from
 320x240 / 480x360 / 640x480 and hypothesis counts from 256 / 512 / 1024) as
-one batched call versus 64 sequential plain calls, then batched + learned and
-batched uniform at 256 hypotheses; and the collaborative-scale queue (16
+one batched call versus 64 sequential plain calls, then batched + learned at
+256 hypotheses against batched uniform at 256 and at 1024; and the
+collaborative-scale queue (16
 full-size forests, 1024 attempts with 30 % true overlap): relocalisation
 success, and the depth-difference check's true/false positives and negatives.
 
-Per-kernel times come from a separate profiled pass over the same work (HIP
-events recorded around each launch on its stream; kernels are then launched
-one by one instead of as a graph). The headline `roofline` is the kernel with
-the largest total time in that pass: its algorithmic work per launch (FLOPs
-counted by the kernels for scoring, bytes for traversal and refinement) over
-its average event-bracketed duration, with `traffic` (HBM bytes per launch)
-from the committed counter profile while the kernel's sources are unchanged.
+Per-kernel times come from a separate profiled pass over the same work:
+kernels launched one by one instead of as a graph, behind a short fixed
+wait on the GPU so that the host has queued them all before the first runs,
+each bracketed by two HIP events on its stream and followed by a bare pair
+of events whose elapsed time (the events' own cost, about 4.5 us) is
+subtracted; the result agrees with rocprofv3's kernel trace within a few per
+cent. The headline `roofline` is the kernel with the largest total time in
+that pass: its algorithmic work per launch (FLOPs counted by the kernels for
+scoring, bytes for traversal and refinement) over its average duration, with
+`traffic` (HBM bytes per launch) from the committed counter profile while
+the kernel's sources are unchanged.
 `cpu_baseline` is the CPU oracle on a forest adapted on the same 200 frames,
 relocalising a sample of the same queries with the same seeds; the bench
 checks that the oracle's poses equal the GPU's there.
 
-Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-batched] [--no-learned] [--no-queue]
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-batched] [--no-learned]
+                       [--no-queue] [--no-small] [--copy-calibration]
 """
 from __future__ import annotations
 
@@ -57,6 +63,8 @@ FLOP_PER_PAIR = 18                # y = R c + t: 9 fma
 # (22 doubles) read and written, live slot (hypothesis, position) read, pose
 # written (rotation and translation as doubles and floats, live FP32 copy)
 REFINE_BYTES_PER_SURVIVOR = 2 * 22 * 8 + 8 + 12 * 8 + 12 * 4 + 12 * 4
+FUSED_LIVE = 64                   # planned live hypotheses from which a round culls inside its refinement
+FUSED_REFINE = 1024               # planned survivors of a batch up to which a round refines in one kernel
 
 
 def log(msg: str) -> None:
@@ -166,11 +174,11 @@ SCORE_SOURCES = ("common.h", "mlp_dev.h", "relocalise.hip")
 
 
 def score_traffic(kernel="k_b_score"):
-    """HBM bytes per launch of `kernel` (the scoring or the refinement kernel)
-    on the full-size workload, from the committed counter profile (FETCH_SIZE
-    and WRITE_SIZE, each scaled by what the counter reads for a kernel of
-    known traffic); None when the kernels' sources differ from those profiled
-    (sha256 recorded there)."""
+    """HBM bytes per launch of a relocalisation kernel on the full-size plain
+    workload, from the committed counter profile (FETCH_SIZE and WRITE_SIZE,
+    each scaled by what the counter reads for a kernel of known traffic);
+    None when the profile has no figure for the kernel or the kernels'
+    sources differ from those profiled (sha256 recorded there)."""
     import hashlib
     import re
     try:
@@ -190,8 +198,9 @@ def score_traffic(kernel="k_b_score"):
 
 
 def profiled(run):
-    """Runs `run()` once with per-kernel HIP-event timing (kernels launched one
-    by one); returns (its result, {kernel: (total ms, launches)})."""
+    """Runs `run()` once with per-kernel timing (kernels launched one by one,
+    event brackets less the events' own cost); returns (its result, {kernel:
+    (total ms, launches)})."""
     import torch
     import paper_1801_08361_amd as rl
     rl.profile_reset()
@@ -204,18 +213,21 @@ def profiled(run):
     return res, kernels
 
 
-def rooflines(kernels, res, attempts, batch_pixels=500):
+def rooflines(kernels, res, attempts, batch_pixels=500, batched=False):
     """Roofline entries of one profiled pass: the scoring kernel (FP32 ALU,
     FLOPs counted by the kernels), the traversal kernel (algorithmic bytes: 2 B
     depth + 3 B colour read and 4 B leaf index written per pixel and tree) and,
     where learned pick weights were computed in the pass, the weight kernel
     (one network forward pass per pixel on the matrix cores) and the
-    refinement kernel (HBM: per survivor of a round, its inlier id for each of
-    the round's B draws, its running sums read and written, its slot and its
-    re-solved pose written; the gathers of its inliers' points and modes are
-    not counted, so the figure is a lower bound). `attempts` are (pixels,
-    trees, learned) per attempt, `batch_pixels` the draws per round (B);
-    `dominant` is the kernel with the largest total time."""
+    refinement kernels (HBM: per survivor of a round, its inlier id for each
+    of the round's B draws, its running sums read and written, its slot and
+    its re-solved pose written; the gathers of its inliers' points and modes
+    are not counted, so the figure is a lower bound; the late rounds' kernel
+    also reads each live hypothesis's list entry, energy and group sums once
+    and writes the next list). `attempts` are (pixels, trees, learned,
+    hypotheses) per attempt, `batch_pixels` the draws per round (B),
+    `batched` whether they ran as one batch; `dominant` is the kernel with the
+    largest total time."""
     out = {}
 
     def entry(name, bound, work, peak, unit):
@@ -230,20 +242,55 @@ def rooflines(kernels, res, attempts, batch_pixels=500):
 
     flops = sum(r["mode_evals"] * FLOP_PER_MODE_TERM + r["pair_evals"] * FLOP_PER_PAIR for r in res)
     out["k_b_score"] = entry("k_b_score", "alu", flops, FP32_PEAK_TFLOPS, "TFLOP/s")
-    leaf_bytes = sum(P * (5 + 4 * T) for P, T, _ in attempts)
+    leaf_bytes = sum(P * (5 + 4 * T) for P, T, _, _ in attempts)
     out["k_b_leaves"] = entry("k_b_leaves", "hbm", leaf_bytes, HBM_PEAK_GBS, "GB/s")
-    surv = 0
-    for r in res:
+    # Which kernels refine round r, as the library plans a batch: from the
+    # first round whose planned live count (N halved r times) is at most
+    # FUSED_LIVE for every attempt, the cull runs inside the refinement
+    # (k_b_cull_refine) while the batch's planned survivors are at most
+    # FUSED_REFINE; otherwise k_b_cull, then k_b_refine, or k_b_refine_sums
+    # and k_b_refine_solve past FUSED_REFINE survivors. A plain call is a
+    # batch of one.
+    def bound(n_hyp, k):
+        for _ in range(k):
+            n_hyp = (n_hyp + 1) // 2
+        return n_hyp
+
+    def rounds_for(n_hyp):
+        r = 0
+        while (1 << r) < n_hyp:
+            r += 1
+        return max(r, 1)
+
+    def plan(ns):
+        fused_from = max(next(k for k in range(64) if bound(n, k) <= FUSED_LIVE) for n in ns)
+        kinds = []
+        for k in range(max(rounds_for(n) for n in ns)):
+            total = sum(bound(n, k + 1) for n in ns if k < rounds_for(n))
+            kinds.append("fused" if k >= fused_from and total <= FUSED_REFINE
+                         else ("one" if total <= FUSED_REFINE else "split"))
+        return kinds
+
+    groups = (batch_pixels + 7) // 8
+    kinds_b = plan([a[3] for a in attempts]) if batched else None
+    surv = {"one": 0, "split": 0, "fused": 0}
+    cull_fused = 0
+    for r, (_, _, _, n_hyp) in zip(res, attempts):
+        kinds = kinds_b if batched else plan([n_hyp])
         na = r["n_valid"]
-        for _ in range(r["n_rounds"]):
-            na = (na + 1) // 2
-            surv += na
-    # (only where every round refined in the one-kernel form: large batched
-    # rounds split the sums and the solve over two kernels)
-    if "k_b_refine_sums" not in kernels:
-        out["k_b_refine"] = entry("k_b_refine", "hbm", surv * (4 * batch_pixels + REFINE_BYTES_PER_SURVIVOR),
-                                  HBM_PEAK_GBS, "GB/s")
-    mlp = sum(P * MLP_FLOP_PER_PIXEL for P, _, learned in attempts if learned)
+        for k in range(r["n_rounds"]):
+            keep = (na + 1) // 2
+            surv[kinds[k]] += keep
+            if kinds[k] == "fused":
+                # live list, energies and group sums read; next list, energies,
+                # positions and the round's trace written
+                cull_fused += na * (8 + 4 * groups + 8) + keep * 12
+            na = keep
+    per_survivor = 4 * batch_pixels + REFINE_BYTES_PER_SURVIVOR
+    out["k_b_refine"] = entry("k_b_refine", "hbm", surv["one"] * per_survivor, HBM_PEAK_GBS, "GB/s")
+    out["k_b_cull_refine"] = entry("k_b_cull_refine", "hbm", cull_fused + surv["fused"] * per_survivor,
+                                   HBM_PEAK_GBS, "GB/s")
+    mlp = sum(P * MLP_FLOP_PER_PIXEL for P, _, learned, _ in attempts if learned)
     if mlp:
         out["k_b_weights"] = entry("k_b_weights", "mfma", mlp, BF16_PEAK_TFLOPS, "TFLOP/s")
     out = {k: v for k, v in out.items() if v is not None}
@@ -298,11 +345,11 @@ def plain_full(args, dev, batched: bool = True):
     log("kernel totals over one profiled step: " +
         ", ".join(f"{k}={v[0]:.2f}ms/{v[1]}" for k, v in sorted(kernels.items(), key=lambda kv: -kv[1][0])))
     P = queries[0][0].numel()
-    roofs = rooflines(kernels, res, [(P, g.T, False)] * len(queries))
-    for kn in ("k_b_score", "k_b_refine"):
-        if roofs.get(kn) is not None:
-            roofs[kn]["traffic"] = score_traffic(kn)
-            roofs[kn]["traffic_source"] = "profiles/relocalise_fullsize_hbm_traffic.md (HBM bytes per launch)"
+    roofs = rooflines(kernels, res, [(P, g.T, False, full_params().n_hypotheses)] * len(queries))
+    for kn, e in roofs.items():
+        if isinstance(e, dict):
+            e["traffic"] = score_traffic(kn)
+            e["traffic_source"] = "profiles/relocalise_fullsize_hbm_traffic.md (HBM bytes per launch)"
     # the headline roofline is the dominant kernel's
     roof = roofs.get(roofs.get("dominant")) or roofs.get("k_b_score")
     if not batched:
@@ -326,7 +373,8 @@ def plain_full(args, dev, batched: bool = True):
     batched = {"value": len(att) * args.steps / sum(runs), "unit": "relocalisations/s",
                "success_rate": ok_b / len(att), "identical_to_plain": same, "schedule": b.schedule(),
                "runs_ms": [round(t * 1e3, 2) for t in runs],
-               "rooflines": rooflines(kernels_b, res_b, [(P, g.T, False)] * len(att))}
+               "rooflines": rooflines(kernels_b, res_b, [(P, g.T, False, full_params().n_hypotheses)] * len(att),
+                                      batched=True)}
     log(f"full-size batched (50 queries per call): {batched['value']:.1f}/s, success {ok_b}/{len(att)}, "
         f"identical={same}")
     del b
@@ -416,7 +464,7 @@ def learned_full(args, dev, full):
         if name in ("learned_256", "uniform_256"):
             res_prof, kernels = profiled(lambda: run(n_hyp, use))
             P = queries[0][0].numel()
-            forms[name]["rooflines"] = rooflines(kernels, res_prof, [(P, g.T, use)] * len(queries))
+            forms[name]["rooflines"] = rooflines(kernels, res_prof, [(P, g.T, use, n_hyp)] * len(queries))
         if n_hyp <= 256:
             forms[name]["good_hypotheses_per_attempt"] = good_hypotheses(g, m if use else None, queries, sc, n_hyp)
         log(f"{name}: {forms[name]['value']:.1f}/s, success {ok}/{len(queries)}, valid hypotheses {valid:.1f}, "
@@ -501,11 +549,12 @@ def batched_mixed(args, dev):
     n = len(att) * args.steps
     log(f"batched: {n / wall_b:.1f}/s vs sequential plain {n / wall_p:.1f}/s; identical={identical}; "
         f"success {ok}/{len(att)}")
-    shapes = [(a["depth"].numel(), a["forest"].T) for a in att]
+    shapes = [(a["depth"].numel(), a["forest"].T, a["n_hyp"]) for a in att]
     res_prof, kernels_b = profiled(lambda: b.run(att))
     out = {"batched": {"value": n / wall_b, "unit": "relocalisations/s", "schedule": b.schedule(),
                        "success_rate": ok / len(att), "runs_ms": [round(t * 1e3, 3) for t in runs_b],
-                       "rooflines": rooflines(kernels_b, res_prof, [(P, T, False) for P, T in shapes], 64)},
+                       "rooflines": rooflines(kernels_b, res_prof, [(P, T, False, N) for P, T, N in shapes], 64,
+                                              batched=True)},
            "sequential_plain": {"value": n / wall_p, "unit": "relocalisations/s"},
            "speedup": wall_p / wall_b, "identical_to_plain": identical, "success_rate": ok / len(att),
            "workload": "64 attempts, 8 forests (320x240 rooms, 5 trees depth 10, R=256, 20 frames each); "
@@ -523,7 +572,9 @@ def batched_mixed(args, dev):
         # learned: the batch computes each attempt's pick weights itself
         return [dict(a, n_hyp=n_hyp, proposal=m) if use else dict(a, n_hyp=n_hyp) for a in att]
 
-    for name, n_hyp, use in (("batched_learned_256", 256, True), ("batched_uniform_256", 256, False)):
+    # (learned at 256 hypotheses against uniform at 256 and at 1024)
+    for name, n_hyp, use in (("batched_learned_256", 256, True), ("batched_uniform_256", 256, False),
+                             ("batched_uniform_1024", 1024, False)):
         bb = rl.Batch(tune=True)
         bb.run(with_weights(n_hyp, use))
         torch.cuda.synchronize()
@@ -537,7 +588,8 @@ def batched_mixed(args, dev):
         res_prof, kernels_b = profiled(lambda: bb.run(with_weights(n_hyp, use)))
         out[name] = {"value": n / wall, "unit": "relocalisations/s", "success_rate": ok / len(att),
                      "mean_valid_hypotheses": valid, "schedule": bb.schedule(),
-                     "rooflines": rooflines(kernels_b, res_prof, [(P, T, use) for P, T in shapes], 64)}
+                     "rooflines": rooflines(kernels_b, res_prof, [(P, T, use, n_hyp) for P, T, _ in shapes],
+                                           64, batched=True)}
         log(f"{name}: {n / wall:.1f}/s, success {ok}/{len(att)}, valid hypotheses {valid:.1f}")
     return out
 
@@ -692,6 +744,8 @@ def main():
     ap.add_argument("--no-learned", action="store_true")
     ap.add_argument("--no-queue", action="store_true",
                     help="skip the collaborative-scale queue (16 full-size forests, 1024 attempts)")
+    ap.add_argument("--no-small", action="store_true",
+                    help="skip the small-room form (10 rooms, 320x240, N=256)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run one 256 MiB device-to-device copy kernel (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -743,7 +797,8 @@ def main():
         forms["learned_full"] = learned_full(args, dev, full)
     if not args.no_batched:
         forms["mixed"] = batched_mixed(args, dev)
-    forms["small_rooms"] = c1_small(args, dev)
+    if not args.no_small:
+        forms["small_rooms"] = c1_small(args, dev)
     if not args.no_queue:
         forms["queue"] = queue_form(args, dev)
     out["forms"] = forms

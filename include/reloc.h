@@ -396,16 +396,23 @@ int reloc_label_pixels(reloc_forest *f, const uint16_t *depth_dev, const uint8_t
                        void *stream);
 
 /* ---- per-kernel timing (for measurement; off by default) ----
- * When enabled, every kernel the library launches is bracketed by two HIP
- * events recorded on the stream it is launched on. reloc_profile_read sums
- * the elapsed times of all recorded launches of one kernel (waiting for them
- * to finish); reloc_profile_kernels writes the comma-separated kernel names
- * seen so far into `names` (NUL-terminated, truncated to cap - 1 bytes);
+ * When enabled, a relocalisation runs its kernels one by one instead of as
+ * its captured graph, behind a short fixed wait on the GPU (so that the host
+ * has queued every launch before the first one runs), and every launch is
+ * bracketed by two HIP events recorded on its stream, followed by a bare pair
+ * of events recorded back to back. reloc_profile_read sums, over all recorded
+ * launches of one kernel, the bracket's elapsed time minus the bare pair's
+ * (the events' own cost), waiting for them to finish: the kernels' durations
+ * as a profiler's kernel trace gives them (within a few per cent on this
+ * path). reloc_profile_read_raw returns both sums separately.
+ * reloc_profile_kernels writes the comma-separated kernel names seen so far
+ * into `names` (NUL-terminated, truncated to cap - 1 bytes);
  * reloc_profile_reset forgets all launches. Process-wide; not for use while a
  * stream is being captured into a graph. */
 int reloc_profile_enable(int on);
 int reloc_profile_reset(void);
 int reloc_profile_read(const char *kernel, double *total_ms, int64_t *launches);
+int reloc_profile_read_raw(const char *kernel, double *bracket_ms, double *pair_ms, int64_t *launches);
 int reloc_profile_kernels(char *names, int32_t cap);
 
 /* ---- parity and debug exports: synchronous copies into caller HOST buffers ---- */

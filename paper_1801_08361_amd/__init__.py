@@ -112,6 +112,7 @@ _SIGS = {
     "reloc_profile_enable": [C.c_int],
     "reloc_profile_reset": [],
     "reloc_profile_read": [C.c_char_p, C.c_void_p, C.c_void_p],
+    "reloc_profile_read_raw": [C.c_char_p, C.c_void_p, C.c_void_p, C.c_void_p],
     "reloc_profile_kernels": [C.c_char_p, C.c_int32],
     "reloc_relocalise_ex": [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_uint64, C.c_int32, C.c_void_p,
                             C.c_void_p, C.c_void_p],

@@ -28,6 +28,9 @@ namespace rl {
 bool prof_on();
 void *prof_begin(const char *name, hipStream_t s);
 void prof_end(const char *name, void *tok, hipStream_t s);
+// queues a wait of a fixed wall-clock time for a timed pass of `launches`
+// launches (so that the host can queue them all before the first one runs)
+void prof_delay(hipStream_t s, int launches);
 
 #define RL_LAUNCH(name, kern, grid, block, smem, stream, ...)                  \
     do {                                                                      \

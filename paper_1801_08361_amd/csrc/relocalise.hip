@@ -1611,6 +1611,7 @@ static int run_plan(Plan *pl, hipStream_t s)
 {
     if (prof_on()) {
         const std::vector<int32_t> off = offsets(pl, pl->sched);
+        prof_delay(s, 8 + 3 * pl->rounds);
         return enqueue(pl, pl->sched, stages_of(pl, pl->sched, pl->d_off, off), s);
     }
     RL_HIP(hipGraphLaunch(pl->exec, s));
