@@ -90,6 +90,7 @@ def lib():
         L.oracle_leaves.argtypes = [vp, vp, vp, i32, i32, vp, vp]
         L.oracle_features8.argtypes = [vp, vp, vp, i32, i32, vp, vp]
         L.oracle_adapt_frame.argtypes = [vp, vp, vp, i32, i32, vp, vp]
+        L.oracle_train_forest.argtypes = [vp, i32, vp, vp, i32, i32, vp, vp, i32, i32]
         L.oracle_reservoir.argtypes = [vp, i32, i32, vp, vp]
         L.oracle_leaf_modes.argtypes = [vp, i32, i32, vp, vp]
         L.oracle_modes_from_points.argtypes = [vp, vp, i32, vp, vp, vp]
@@ -254,6 +255,19 @@ class Forest:
         H, W = d.shape
         T = np.ascontiguousarray(pose, dtype=np.float64).reshape(16)
         rc = lib().oracle_adapt_frame(self._h, _p(d), _p(c), W, H, _p(_K(K)), _p(T))
+        if rc != 0:
+            raise ValueError(rc)
+
+    def train(self, frames, K, stride: int, n_cand: int) -> None:
+        """Split training (oracle_train_forest) on [(depth, rgb, pose)] of one
+        size and intrinsics; empties every leaf."""
+        ds = [np.ascontiguousarray(_np(d), dtype=np.uint16) for d, _, _ in frames]
+        cs = [np.ascontiguousarray(_np(c), dtype=np.uint8) for _, c, _ in frames]
+        H, W = ds[0].shape
+        dp = (C.c_void_p * len(ds))(*[a.ctypes.data for a in ds])
+        cp = (C.c_void_p * len(cs))(*[a.ctypes.data for a in cs])
+        P = np.ascontiguousarray(np.stack([np.asarray(T, dtype=np.float64).reshape(16) for _, _, T in frames]))
+        rc = lib().oracle_train_forest(self._h, len(ds), dp, cp, W, H, _p(_K(K)), _p(P), int(stride), int(n_cand))
         if rc != 0:
             raise ValueError(rc)
 

@@ -23,7 +23,7 @@
 #define M_PI 3.14159265358979323846
 #endif
 
-enum { TAG_FOREST = 1, TAG_RESERVOIR = 2, TAG_HYP = 3, TAG_PIX = 4 };
+enum { TAG_FOREST = 1, TAG_RESERVOIR = 2, TAG_HYP = 3, TAG_PIX = 4, TAG_TRAIN = 8 };
 
 /* ------------------------------------------------------------------------ */
 /* Philox4x64-10 (Salmon, Moraes, Dror and Shaw, "Parallel random numbers:  */
@@ -106,10 +106,13 @@ int oracle_params_default(oracle_params *p)
     return ORACLE_OK;
 }
 
-static void gen_node(uint64_t seed, const oracle_params *p, uint64_t t, uint64_t i, onode *nd)
+/* a split drawn from the generator keyed by (seed, tag) at counter (c0, c1,
+ * c2, 0): kind, offsets and threshold uniform over their ranges */
+static void draw_node(uint64_t seed, uint64_t tag, const oracle_params *p, uint64_t c0, uint64_t c1, uint64_t c2,
+                      onode *nd)
 {
     uint64_t u[4];
-    draw(seed, TAG_FOREST, t, i, 0, 0, u);
+    draw(seed, tag, c0, c1, c2, 0, u);
     int k = (int)oracle_uniform_int(u[0], 6);
     nd->kind = k < 3 ? 0 : k - 2;                  /* 0: depth, 1..3: colour channel */
     int64_t O = p->offset_pxmm;
@@ -117,6 +120,12 @@ static void gen_node(uint64_t seed, const oracle_params *p, uint64_t t, uint64_t
     nd->dy = (int32_t)((int64_t)oracle_uniform_int(u[2], (uint64_t)(2 * O + 1)) - O);
     int64_t Tk = nd->kind == 0 ? p->thr_depth_mm : p->thr_rgb;
     nd->thr = (int32_t)((int64_t)oracle_uniform_int(u[3], (uint64_t)(2 * Tk + 1)) - Tk);
+}
+
+/* the random split of node i of tree t (t = T: the extra feature nodes) */
+static void gen_node(uint64_t seed, const oracle_params *p, uint64_t t, uint64_t i, onode *nd)
+{
+    draw_node(seed, TAG_FOREST, p, t, i, 0, nd);
 }
 
 int oracle_forest_create(const oracle_params *p, oracle_forest **out)
@@ -1583,5 +1592,145 @@ int oracle_mlp_grad(const float *w, const float *x, const uint8_t *y, int n, dou
         }
     }
     *loss = L / (double)n;
+    return ORACLE_OK;
+}
+
+/* ------------------------------------------------------------------------ */
+/* split training: a split structure learned on one scene, whose leaves are */
+/* then adapted online to others (Sec. 4.2.2, Table 2: a forest pre-trained */
+/* on one scene and adapted to the rest)                                    */
+/* ------------------------------------------------------------------------ */
+
+/* Reading (the paper takes the pre-trained forest from its relocaliser's
+ * authors and gives no training procedure): every node of every tree, level
+ * by level from the root, takes from n_cand candidate splits, drawn like
+ * random ones from the generator keyed by (seed, TRAIN) at counter (tree,
+ * node, candidate), the one that leaves the training samples reaching it
+ * with the smallest summed squared deviation of their world points from
+ * their child's mean (the reduction-in-spatial-variance objective of
+ * scene-coordinate regression forests); ties go to the lower candidate. A
+ * sample is every stride-th pixel in u and v, from stride / 2, of every
+ * training frame with a valid depth, with its world point in integer mm as
+ * adaptation stores it. The per-child sums (count, coordinate sums, sum of
+ * squared norms) are exact integers; the cost of a child with n samples is
+ * S2 - |S|^2 / n in FP64, in that order, summed left then right. */
+
+typedef struct {
+    int frame, u, v;
+    int32_t d;
+    int64_t x, y, z;
+} tsample;
+
+static double split_cost(const int64_t s[10])
+{
+    double c = 0.0;
+    for (int side = 0; side < 2; ++side) {
+        const int64_t *q = s + 5 * side;
+        if (q[0] == 0) continue;
+        double sx = (double)q[1], sy = (double)q[2], sz = (double)q[3];
+        c = c + ((double)q[4] - ((sx * sx + sy * sy) + sz * sz) / (double)q[0]);
+    }
+    return c;
+}
+
+int oracle_train_forest(oracle_forest *f, int n_frames, const uint16_t *const *depth, const uint8_t *const *rgb,
+                        int W, int H, const float K[4], const double *poses, int stride, int n_cand)
+{
+    if (!f || n_frames < 1 || !depth || !rgb || !poses || stride < 1 || n_cand < 1 || n_cand > 64) return ORACLE_E_ARG;
+    if (f->dropped) return ORACLE_E_ARG;
+    for (int k = 0; k < n_frames; ++k)
+        if (!frame_args_ok(f, depth[k], rgb[k], W, H, K) || !is_se3(poses + 16 * k)) return ORACLE_E_ARG;
+    /* samples, frame by frame in raster order of the sampling grid */
+    size_t cap = (size_t)n_frames * (size_t)((W + stride - 1) / stride) * (size_t)((H + stride - 1) / stride);
+    tsample *smp = (tsample *)malloc((cap ? cap : 1) * sizeof(tsample));
+    frame_ctx *ctx = (frame_ctx *)malloc((size_t)n_frames * sizeof(frame_ctx));
+    if (!smp || !ctx) {
+        free(smp); free(ctx);
+        return ORACLE_E_NOMEM;
+    }
+    size_t S = 0;
+    for (int k = 0; k < n_frames; ++k) {
+        make_ctx(f, depth[k], rgb[k], W, H, K, &ctx[k]);
+        const double *P = poses + 16 * k;
+        float R32[9], t32[3];
+        for (int r = 0; r < 3; ++r) {
+            for (int c = 0; c < 3; ++c) R32[r * 3 + c] = (float)P[r * 4 + c];
+            t32[r] = (float)P[r * 4 + 3];
+        }
+        for (int v = stride / 2; v < H; v += stride)
+            for (int u = stride / 2; u < W; u += stride) {
+                uint32_t d = depth[k][(size_t)v * W + u];
+                if (!valid_depth(&f->p, d)) continue;
+                float c[3], w[3];
+                cam_point(u, v, d, K, c);
+                for (int a = 0; a < 3; ++a)
+                    w[a] = ((R32[a * 3 + 0] * c[0] + R32[a * 3 + 1] * c[1]) + R32[a * 3 + 2] * c[2]) + t32[a];
+                tsample *q = &smp[S++];
+                q->frame = k; q->u = u; q->v = v; q->d = (int32_t)d;
+                q->x = (int32_t)rintf(w[0] * 1000.0f);
+                q->y = (int32_t)rintf(w[1] * 1000.0f);
+                q->z = (int32_t)rintf(w[2] * 1000.0f);
+            }
+    }
+    int64_t *node = (int64_t *)malloc((S ? S : 1) * sizeof(int64_t));
+    size_t *order = (size_t *)malloc((S ? S : 1) * sizeof(size_t));
+    size_t *start = (size_t *)malloc(((size_t)f->L + 1) * sizeof(size_t));
+    if (!node || !order || !start) {
+        free(smp); free(ctx); free(node); free(order); free(start);
+        return ORACLE_E_NOMEM;
+    }
+    for (int t = 0; t < f->T; ++t) {
+        onode *tree = &f->nodes[(size_t)t * (f->L - 1)];
+        for (size_t s = 0; s < S; ++s) node[s] = 0;
+        for (int l = 0; l < f->D; ++l) {
+            const int64_t first = ((int64_t)1 << l) - 1, count = (int64_t)1 << l;
+            /* the samples of each node of the level together (counting sort) */
+            for (int64_t j = 0; j <= count; ++j) start[j] = 0;
+            for (size_t s = 0; s < S; ++s) start[node[s] - first + 1]++;
+            for (int64_t j = 0; j < count; ++j) start[j + 1] += start[j];
+            for (size_t s = 0; s < S; ++s) order[start[node[s] - first]++] = s;
+            for (int64_t j = count; j > 0; --j) start[j] = start[j - 1];
+            start[0] = 0;
+            for (int64_t j = 0; j < count; ++j) {
+                const int64_t i = first + j;
+                double best_c = INFINITY;
+                onode chosen;
+                for (int k = 0; k < n_cand; ++k) {
+                    onode cand;
+                    draw_node(f->p.seed, TAG_TRAIN, &f->p, (uint64_t)t, (uint64_t)i, (uint64_t)k, &cand);
+                    int64_t sums[10] = {0};
+                    for (size_t o = start[j]; o < start[j + 1]; ++o) {
+                        const tsample *q = &smp[order[o]];
+                        int32_t r = feature(&ctx[q->frame], &cand, q->u, q->v, q->d);
+                        int64_t *a = sums + (r >= cand.thr ? 5 : 0);
+                        a[0] += 1;
+                        a[1] += q->x; a[2] += q->y; a[3] += q->z;
+                        a[4] += q->x * q->x + q->y * q->y + q->z * q->z;
+                    }
+                    double c = split_cost(sums);
+                    if (c < best_c) {
+                        best_c = c;
+                        chosen = cand;
+                    }
+                }
+                tree[i] = chosen;
+            }
+            /* route every sample one level down */
+            for (size_t s = 0; s < S; ++s) {
+                const tsample *q = &smp[s];
+                const onode *nd = &tree[node[s]];
+                int32_t r = feature(&ctx[q->frame], nd, q->u, q->v, q->d);
+                node[s] = 2 * node[s] + 1 + (r >= nd->thr ? 1 : 0);
+            }
+        }
+    }
+    free(smp); free(ctx); free(node); free(order); free(start);
+    /* the leaves of the new structure start empty */
+    size_t TL = (size_t)f->T * f->L;
+    memset(f->counter, 0, TL * sizeof(uint32_t));
+    memset(f->res, 0, TL * f->R * sizeof(oracle_entry));
+    memset(f->modes, 0, TL * f->M * sizeof(oracle_mode));
+    for (size_t i = 0; i < TL; ++i) f->nmodes[i] = 0;
+    f->total_samples = 0;
     return ORACLE_OK;
 }

@@ -94,6 +94,12 @@ int  oracle_forest_nodes(const oracle_forest *f, int32_t *kind, int32_t *dx, int
 int  oracle_set_nodes(oracle_forest *f, const int32_t *kind, const int32_t *dx, const int32_t *dy,
                       const int32_t *thr);
 
+/* split training on posed frames of equal size and intrinsics (n_cand
+ * candidates per node, 1..64; every stride-th pixel); replaces the split
+ * nodes (not the 8 extra feature nodes) and empties every leaf */
+int  oracle_train_forest(oracle_forest *f, int n_frames, const uint16_t *const *depth, const uint8_t *const *rgb,
+                         int W, int H, const float K[4], const double *poses /* [n][16] */, int stride, int n_cand);
+
 int  oracle_camera_point(const uint16_t *depth, int W, int H, const float K[4], int u, int v,
                          const oracle_params *p, float out[3]);
 int  oracle_leaves(const oracle_forest *f, const uint16_t *depth, const uint8_t *rgb, int W, int H,
