@@ -228,6 +228,37 @@ int reloc_forest_load(const char *path, void *stream, reloc_forest **out);
 /* The parameters the forest was created (or loaded) with. */
 int reloc_forest_params(const reloc_forest *f, reloc_params *out);
 
+/* One posed training frame: device depth (uint16 mm, [H][W]) and colour
+ * (uint8 RGB, [H][W][3]) owned by the caller, its intrinsics and its
+ * camera-to-world pose (row-major 4x4, a rigid motion). */
+typedef struct {
+    const uint16_t *depth_dev;
+    const uint8_t *rgb_dev;
+    reloc_intrinsics K;
+    double pose_c2w[16];
+} reloc_train_frame;
+
+/* Split training: replaces the forest's split nodes (not the 8 extra feature
+ * nodes of the learned proposal) by splits learned from posed frames of one
+ * scene, and empties every leaf; reloc_adapt_frame then fills the leaves
+ * from frames of any scene (the paper's forest is pre-trained on one scene
+ * and adapted online to the others, Sec. 4.2.2, Table 2). Every node, level
+ * by level from the root, takes from n_candidates (1..64) candidate splits,
+ * drawn like random ones from the generator keyed by (seed, 8) at counter
+ * (tree, node, candidate, 0), the one that minimises the summed squared
+ * deviation of its training samples' world points (integer mm, as adaptation
+ * stores them) from their child's mean, ties to the lower candidate; a
+ * sample is every stride-th pixel in u and v, from stride / 2, of every
+ * frame with a valid depth. Synchronous on `stream` (it reads per-level
+ * sample counts back); allocates its scratch with hipMallocAsync on
+ * `stream` and frees it before returning. Errors: RELOC_E_ARG (null
+ * pointers, n_frames < 1, stride < 1, n_candidates outside 1..64, a frame
+ * the forest rejects, a pose that is not a rigid motion), RELOC_E_RANGE
+ * (more than 2^31 samples over the trees), RELOC_E_STATE (reservoirs
+ * dropped), RELOC_E_NOMEM, RELOC_E_HIP. */
+int reloc_forest_train(reloc_forest *f, const reloc_train_frame *frames, int32_t n_frames, int32_t stride,
+                       int32_t n_candidates, void *stream);
+
 /* Device bytes currently held by the forest. */
 int reloc_forest_memory(const reloc_forest *f, uint64_t *bytes_out);
 

@@ -74,6 +74,11 @@ class reloc_result(C.Structure):
                     pair_evals=self.pair_evals)
 
 
+class reloc_train_frame(C.Structure):
+    _fields_ = [("depth_dev", C.c_void_p), ("rgb_dev", C.c_void_p), ("K", reloc_intrinsics),
+                ("pose_c2w", C.c_double * 16)]
+
+
 class reloc_attempt(C.Structure):
     _fields_ = [("forest", C.c_void_p), ("depth_dev", C.c_void_p), ("rgb_dev", C.c_void_p),
                 ("K", reloc_intrinsics), ("seed", C.c_uint64), ("n_hypotheses", C.c_int32),
@@ -99,6 +104,7 @@ _SIGS = {
     "reloc_forest_save": [C.c_void_p, C.c_char_p, C.c_void_p],
     "reloc_forest_load": [C.c_char_p, C.c_void_p, C.c_void_p],
     "reloc_forest_params": [C.c_void_p, C.c_void_p],
+    "reloc_forest_train": [C.c_void_p, C.c_void_p, C.c_int32, C.c_int32, C.c_int32, C.c_void_p],
     "reloc_forest_memory": [C.c_void_p, C.c_void_p],
     "reloc_status_string": [C.c_int],
     "reloc_debug_nodes": [C.c_void_p] * 5,
@@ -328,6 +334,19 @@ class Forest:
         T = _pose(pose)
         _check(lib().reloc_adapt_frame(self._h, d, c, C.byref(k), T.ctypes.data, _stream(stream)),
                "reloc_adapt_frame")
+
+    def train(self, frames, stride: int, n_candidates: int, stream=None) -> None:
+        """Split training (reloc_forest_train) on [(depth, rgb, K, pose)]
+        device frames of one scene; empties every leaf."""
+        arr = (reloc_train_frame * len(frames))()
+        keep = []
+        for x, (depth, rgb, K, pose) in zip(arr, frames):
+            d, c, k = _frame(depth, rgb, K)
+            x.depth_dev, x.rgb_dev, x.K = d, c, k
+            x.pose_c2w[:] = [float(v) for v in _pose(pose)]
+            keep.append((depth, rgb))
+        _check(lib().reloc_forest_train(self._h, arr, len(frames), int(stride), int(n_candidates), _stream(stream)),
+               "reloc_forest_train")
 
     def update_modes(self, stream=None) -> None:
         _check(lib().reloc_update_modes(self._h, _stream(stream)), "reloc_update_modes")

@@ -13,7 +13,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
-SOURCES = ["forest.hip", "relocalise.hip", "mlp.hip", "verify.hip", "collab.hip", "prof.hip"]
+SOURCES = ["forest.hip", "relocalise.hip", "mlp.hip", "verify.hip", "collab.hip", "train.hip", "prof.hip"]
 LIB = os.path.join(HERE, "libreloc.so")
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

@@ -74,7 +74,7 @@ constexpr int NSUM = 22;
 // result of one attempt: the public reloc_result
 using Result = reloc_result;
 
-constexpr uint64_t TAG_FOREST = 1, TAG_RESERVOIR = 2, TAG_HYP = 3, TAG_PIX = 4;
+constexpr uint64_t TAG_FOREST = 1, TAG_RESERVOIR = 2, TAG_HYP = 3, TAG_PIX = 4, TAG_TRAIN = 8;
 
 constexpr int GROUP = 8;        // energy partial sums run over 8 consecutive draws
 constexpr int CHUNK = 4096;     // pixels per reservoir-rank chunk
@@ -141,6 +141,21 @@ __host__ __device__ __forceinline__ void unpack_node(uint64_t w, int32_t &kind, 
     dx = (int32_t)((int64_t)(w << 41) >> 43);
     dy = (int32_t)((int64_t)(w << 20) >> 43);
     thr = (int32_t)((int64_t)w >> 44);
+}
+
+// A split from four generator words: kind from u0 (0-2 depth, 3-5 colour
+// channel 1-3), offsets dx, dy uniform in [-O, O] from u1, u2, threshold
+// uniform in [-T, T] from u3, with T the depth or the colour threshold range
+__device__ __forceinline__ uint64_t split_from_draw(const U4 &u, int32_t O, int32_t thr_d, int32_t thr_c)
+{
+    const int32_t k = (int32_t)uniform_int(u.x[0], 6);
+    const int32_t kind = k < 3 ? 0 : k - 2;
+    const int64_t Ow = 2 * (int64_t)O + 1;
+    const int32_t dx = (int32_t)((int64_t)uniform_int(u.x[1], (uint64_t)Ow) - O);
+    const int32_t dy = (int32_t)((int64_t)uniform_int(u.x[2], (uint64_t)Ow) - O);
+    const int32_t Tk = kind == 0 ? thr_d : thr_c;
+    const int32_t thr = (int32_t)((int64_t)uniform_int(u.x[3], (uint64_t)(2 * (int64_t)Tk + 1)) - Tk);
+    return pack_node(kind, dx, dy, thr);
 }
 
 // ---------------------------------------------------------------------------

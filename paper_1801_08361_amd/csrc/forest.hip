@@ -145,15 +145,7 @@ __global__ void k_gen_nodes(uint64_t *nodes, DeepNode *deep, int T, int L, uint6
         t = (uint64_t)T;
         node = (uint64_t)(i - n_split);
     }
-    U4 u = philox(t, node, 0, 0, seed, TAG_FOREST);
-    int32_t k = (int32_t)uniform_int(u.x[0], 6);
-    int32_t kind = k < 3 ? 0 : k - 2;
-    int64_t Ow = 2 * (int64_t)O + 1;
-    int32_t dx = (int32_t)((int64_t)uniform_int(u.x[1], (uint64_t)Ow) - O);
-    int32_t dy = (int32_t)((int64_t)uniform_int(u.x[2], (uint64_t)Ow) - O);
-    int32_t Tk = kind == 0 ? thr_d : thr_c;
-    int32_t thr = (int32_t)((int64_t)uniform_int(u.x[3], (uint64_t)(2 * (int64_t)Tk + 1)) - Tk);
-    nodes[i] = pack_node(kind, dx, dy, thr);
+    nodes[i] = split_from_draw(philox(t, node, 0, 0, seed, TAG_FOREST), O, thr_d, thr_c);
     if (i < n_split) deep[i] = deep_node(nodes[i]);
 }
 
@@ -780,6 +772,29 @@ int traverse_frame(Forest *f, const Frame &fr, hipStream_t s)
 int frame_from(const Forest *f, const uint16_t *depth, const uint8_t *rgb, const reloc_intrinsics *K, Frame &fr)
 {
     return frame_of(f, depth, rgb, K, fr);
+}
+
+bool pose_is_se3(const double T[16]) { return is_se3(T); }
+
+// every leaf of a forest empty again (the state of a new forest): counters,
+// reservoirs, slot stamps, modes, the learned proposal's leaf summaries,
+// the dirty list and the sample count
+int forest_empty_leaves(Forest *f, hipStream_t s)
+{
+    const size_t TL = (size_t)f->T * f->L;
+    if (f->dropped) return RELOC_E_STATE;
+    if (hipMemsetAsync(f->counter, 0, TL * sizeof(uint32_t), s) != hipSuccess ||
+        hipMemsetAsync(f->stamp, 0, TL * f->R * sizeof(uint32_t), s) != hipSuccess ||
+        hipMemsetAsync(f->res, 0, TL * f->R * sizeof(Entry), s) != hipSuccess ||
+        hipMemsetAsync(f->nmodes, 0, TL * sizeof(int32_t), s) != hipSuccess ||
+        hipMemsetAsync(f->mode_rgb, 0xFF, TL * rgb_stride(f->M) * sizeof(uint32_t), s) != hipSuccess ||
+        hipMemsetAsync(f->leaf_in, 0, TL * 4 * sizeof(float4), s) != hipSuccess ||
+        hipMemsetAsync(f->dirty, 0, TL * sizeof(uint32_t), s) != hipSuccess ||
+        hipMemsetAsync(f->dirty_count, 0, sizeof(uint32_t), s) != hipSuccess ||
+        hipMemsetAsync(f->total_samples, 0, sizeof(unsigned long long), s) != hipSuccess)
+        return RELOC_E_HIP;
+    f->maybe_dirty = false;
+    return RELOC_OK;
 }
 
 }  // namespace rl

@@ -72,6 +72,7 @@ def test_argument_errors_without_gpu():
     assert L.reloc_forest_save(None, b"/tmp/x", None) == rl.E_ARG
     assert L.reloc_forest_load(None, None, C.byref(out)) == rl.E_ARG
     assert L.reloc_forest_params(None, None) == rl.E_ARG
+    assert L.reloc_forest_train(None, None, 1, 1, 1, None) == rl.E_ARG
     assert L.reloc_mlp_create(0, None, None) == rl.E_ARG
     assert L.reloc_mlp_destroy(None) == rl.E_ARG
     assert L.reloc_mlp_gradient(None, None, None, 1, None, None, None) == rl.E_ARG

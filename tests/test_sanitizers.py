@@ -14,7 +14,7 @@ BUILD = os.path.join(ROOT, "_build", "sanitize")
 HIPCC = "/opt/rocm/bin/hipcc"
 CLANG = "/opt/rocm/llvm/bin/clang"
 CSRC = os.path.join(ROOT, "paper_1801_08361_amd", "csrc")
-HIP_SOURCES = ["forest.hip", "relocalise.hip", "mlp.hip", "verify.hip", "collab.hip", "prof.hip"]
+HIP_SOURCES = ["forest.hip", "relocalise.hip", "mlp.hip", "verify.hip", "collab.hip", "train.hip", "prof.hip"]
 
 
 def _digest(paths):
