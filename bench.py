@@ -16,7 +16,10 @@ per round; 10 rooms x 20 queries, one plain call each); the learned proposal
 on the full-size forest (a network trained on the GPU from verified
 relocalisations of extra frames; learned picks at 256, 64 and 16 hypotheses
 against uniform picks at 256, 64, 16 and 1024, and the fraction of
-hypotheses within 5 cm / 5 deg of the truth); the batched form on the mixed
+hypotheses within 5 cm / 5 deg of the truth); a split structure trained on
+a second full-size room with its leaves adapted on the same 200 frames,
+against the random structure at 1024, 64 and 16 hypotheses; the batched
+form on the mixed
 workload (64 attempts against 8 small-room forests, frame sizes drawn from
 320x240 / 480x360 / 640x480 and hypothesis counts from 256 / 512 / 1024) as
 one batched call versus 64 sequential plain calls, then batched + learned at
@@ -41,7 +44,7 @@ relocalising a sample of the same queries with the same seeds; the bench
 checks that the oracle's poses equal the GPU's there.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-batched] [--no-learned]
-                       [--no-queue] [--no-small] [--copy-calibration]
+                       [--no-trained] [--no-queue] [--no-small] [--copy-calibration]
 """
 from __future__ import annotations
 
@@ -429,6 +432,52 @@ def train_from_verified(dev, items, max_pixels, seed, epochs):
     return m, info
 
 
+def trained_full(args, dev, full):
+    """Split structure trained on another room (Sec. 4.2.2: a forest
+    pre-trained on one scene, its leaves adapted to others): splits learned
+    on 50 frames of a second full-size room (every 4th pixel, 64 candidates
+    per node), leaves adapted on the same 200 frames as the random forest,
+    the 50 held-out queries at 1024, 64 and 16 hypotheses against the random
+    structure at the same counts. Reported: training time, success, median
+    translation error."""
+    import numpy as np
+    import torch
+    import paper_1801_08361_amd as rl
+    import synthroom as sr
+    sc, g_rand, queries, adapt = full["sc"], full["forest"], full["queries"], full["adapt"]
+    src = sr.full_scene(1)
+    step = len(src.adapt_poses) // 50
+    frames = [(*src.render_adapt(k * step, device=dev), src.K, src.adapt_poses[k * step]) for k in range(50)]
+    g = rl.Forest(full_params())
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    g.train(frames, 4, 64)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    del frames
+    for k, (d, c) in enumerate(adapt):
+        g.adapt_frame(d, c, sc.K, sc.adapt_poses[k])
+    g.update_modes()
+    torch.cuda.synchronize()
+    out = {"train_s": t_train, "train_frames": 50, "stride": 4, "candidates": 64,
+           "workload": "splits trained on 50 frames of a second 6x8x3 m room, leaves adapted on the 200 frames "
+                       "of the full-size room; its 50 queries"}
+    for name, forest in (("trained", g), ("random", g_rand)):
+        for n_hyp in (1024, 64, 16):
+            ok, errs = 0, []
+            for q, (d, c) in enumerate(queries):
+                r = forest.relocalise_ex(d, c, sc.K, seed=1 + q, n_hyp=n_hyp)
+                ok += int(r["status"] == 0 and success(r["pose"], sc.query_poses[q]))
+                if r["status"] == 0:
+                    errs.append(float(np.linalg.norm(r["pose"][:3, 3] - sc.query_poses[q][:3, 3])))
+            out[f"{name}_{n_hyp}"] = {"success_rate": ok / len(queries),
+                                      "median_t_err_cm": 100 * float(np.median(errs)) if errs else None}
+    log(f"trained splits: {t_train * 1e3:.1f} ms to train; " +
+        ", ".join(f"{k} {v['success_rate']:.2f}/{v['median_t_err_cm']:.2f} cm" for k, v in out.items()
+                  if isinstance(v, dict)))
+    return out
+
+
 def learned_full(args, dev, full):
     """The learned proposal on the full-size forest: a network trained from
     24 extra frames of the same room whose relocalised poses pass the
@@ -744,6 +793,8 @@ def main():
     ap.add_argument("--no-learned", action="store_true")
     ap.add_argument("--no-queue", action="store_true",
                     help="skip the collaborative-scale queue (16 full-size forests, 1024 attempts)")
+    ap.add_argument("--no-trained", action="store_true",
+                    help="skip the trained-split form (splits learned on a second full-size room)")
     ap.add_argument("--no-small", action="store_true",
                     help="skip the small-room form (10 rooms, 320x240, N=256)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -795,6 +846,8 @@ def main():
         forms["batched_full"] = full["batched"]
     if not args.no_learned:
         forms["learned_full"] = learned_full(args, dev, full)
+    if not args.no_trained:
+        forms["trained_full"] = trained_full(args, dev, full)
     if not args.no_batched:
         forms["mixed"] = batched_mixed(args, dev)
     if not args.no_small:
