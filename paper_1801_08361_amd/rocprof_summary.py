@@ -16,6 +16,9 @@
       (rocprofv3 --pmc SQ_INSTS_VALU SQ_ACTIVE_INST_VALU SQ_THREAD_CYCLES_VALU
       SQ_WAVES SQ_INSTS_VALU_FLOPS_FP32 ..., durations from a kernel trace of
       the same command)
+  python -m paper_1801_08361_amd.rocprof_summary mfma PMC_DIR STATS_DIR
+      per-kernel BF16 matrix FLOPs, rate and matrix-core busy
+      (rocprofv3 --pmc SQ_VALU_MFMA_BUSY_CYCLES SQ_INSTS_VALU_MFMA_MOPS_BF16 ...)
 
 Library kernels are those in namespace rl; parameter lists are dropped from
 the names (template arguments are kept: k_b_score<4> and k_b_score<1> are
@@ -129,6 +132,39 @@ def valu(pmc_dir: str, stats_dir: str) -> str:
     return "\n".join(out)
 
 
+def mfma(pmc_dir: str, stats_dir: str) -> str:
+    """Matrix-core use per kernel: BF16 FLOPs = 512 SQ_INSTS_VALU_MFMA_MOPS_BF16
+    per dispatch (mean; the counter's unit is 512 FLOPs), the rate over the
+    kernel's average duration in the kernel trace of stats_dir, and
+    matrix-core busy = SQ_VALU_MFMA_BUSY_CYCLES / (1024 SIMDs x 2.4 GHz x
+    that duration)."""
+    vals = defaultdict(lambda: defaultdict(list))
+    for r in csv.DictReader(open(_one(pmc_dir, "*counter_collection.csv"))):
+        if _is_lib(r["Kernel_Name"]):
+            vals[_short(r["Kernel_Name"])][r["Counter_Name"]].append(float(r["Counter_Value"]))
+    dur = {}
+    for r in csv.DictReader(open(_one(stats_dir, "*kernel_stats.csv"))):
+        if _is_lib(r["Name"]):
+            k = _short(r["Name"])
+            n0, t0 = dur.get(k, (0, 0.0))
+            dur[k] = (n0 + int(r["Calls"]), t0 + float(r["TotalDurationNs"]))
+    out = ["| kernel | dispatches | MFLOP per dispatch | avg us | TFLOP/s | of 2.5 PFLOP/s | matrix-core busy |",
+           "|---|---:|---:|---:|---:|---:|---:|"]
+    mean = lambda v: sum(v) / len(v) if v else 0.0
+    for k in sorted(vals):
+        c = vals[k]
+        fl = 512 * mean(c["SQ_INSTS_VALU_MFMA_MOPS_BF16"])
+        if fl == 0:
+            continue
+        n, tot = dur.get(k, (0, 0.0))
+        avg_s = tot / n * 1e-9 if n else 0.0
+        rate = fl / avg_s / 1e12 if avg_s else 0.0
+        busy = mean(c["SQ_VALU_MFMA_BUSY_CYCLES"]) / (1024 * 2.4e9 * avg_s) if avg_s else 0.0
+        out.append(f"| {k} | {len(c['SQ_INSTS_VALU_MFMA_MOPS_BF16'])} | {fl / 1e6:.1f} | {avg_s * 1e6:.2f} | "
+                   f"{rate:.2f} | {100 * rate / 2500:.2f} % | {100 * busy:.2f} % |")
+    return "\n".join(out)
+
+
 def main(argv) -> None:
     if len(argv) == 2 and argv[0] == "stats":
         print(stats(argv[1]))
@@ -136,6 +172,8 @@ def main(argv) -> None:
         print(counters(argv[1], argv[2]))
     elif len(argv) == 3 and argv[0] == "valu":
         print(valu(argv[1], argv[2]))
+    elif len(argv) == 3 and argv[0] == "mfma":
+        print(mfma(argv[1], argv[2]))
     else:
         raise SystemExit(__doc__)
 
