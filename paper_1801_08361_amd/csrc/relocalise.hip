@@ -1307,12 +1307,24 @@ static int rounds_for(int N)
 }
 
 struct Sched {
-    int dpu;         // draws per scoring unit, a multiple of GROUP
-    int grid;        // persistent grid of the scoring kernel (0: one workgroup per unit)
-    int xcd;         // XCD-contiguous unit order
-    int pix;         // pixels per traversal thread (4 or 8)
-    int su;          // scoring mode-loop unroll (4 for a single attempt, else 1)
+    int dpu[MAX_ROUNDS];   // per round: draws per scoring unit, a multiple of GROUP
+    int grid;              // persistent grid of the scoring kernel (0: one workgroup per unit)
+    int xcd;               // XCD-contiguous unit order
+    int pix;               // pixels per traversal thread (4 or 8)
+    int su;                // scoring mode-loop unroll (4 for a single attempt, else 1)
 };
+
+// a schedule with the same draws per unit in every round
+static Sched uniform_sched(int dpu, int grid, int xcd, int pix, int su)
+{
+    Sched s;
+    for (int r = 0; r < MAX_ROUNDS; ++r) s.dpu[r] = dpu;
+    s.grid = grid;
+    s.xcd = xcd;
+    s.pix = pix;
+    s.su = su;
+    return s;
+}
 
 struct Shape {
     int W, H, N, B, T, L, M, weights;   // weights: 0 uniform, 1 given, 2 learned in the graph
@@ -1336,7 +1348,7 @@ struct Plan {
     std::vector<Attempt> slices;    // scratch pointers per attempt
     int32_t *d_off = nullptr;       // stage offsets of the chosen schedule
     hipGraphExec_t exec = nullptr;
-    Sched sched{GROUP, 0, 0, 4, 1};
+    Sched sched = uniform_sched(GROUP, 0, 0, 4, 1);
     std::string desc;
     uint64_t last_use = 0;
 };
@@ -1454,7 +1466,7 @@ static std::vector<int32_t> offsets(const Plan *pl, const Sched &sc)
     for (int r = 0; r < R; ++r) {
         fill(5 + 3 * r, [&](int a) {
             if (r >= rounds_for(pl->shape[a].N)) return 0;
-            return ((bound(a, r) + 63) / 64) * ((pl->shape[a].B + sc.dpu - 1) / sc.dpu);
+            return ((bound(a, r) + 63) / 64) * ((pl->shape[a].B + sc.dpu[r] - 1) / sc.dpu[r]);
         });
         fill(6 + 3 * r, [&](int a) { return r >= rounds_for(pl->shape[a].N) ? 0 : bound(a, r + 1); });
         fill(7 + 3 * r, [&](int a) { return r >= rounds_for(pl->shape[a].N) ? 0 : (bound(a, r + 1) + 63) / 64; });
@@ -1499,8 +1511,47 @@ static void launch_leaves(const Sched &sc, const Stages &st, int cap, const Atte
         RL_LAUNCH("k_b_leaves", k_b_leaves<4>, dim3(grid_of(st.pix, cap, sc.xcd)), dim3(PIX_BLOCK), 0, s, d, st.pix);
 }
 
-// enqueues every kernel of the batch on `s`
-static int enqueue(const Plan *pl, const Sched &sc, const Stages &st, hipStream_t s)
+// Per-launch timing for the tuner: events around the traversal launch and
+// each round's scoring launch, each pair followed by a bare pair whose
+// elapsed time (the events' own cost) is subtracted
+struct LaunchTimer {
+    hipEvent_t ev[2 * (MAX_ROUNDS + 1)][4] = {};
+    bool ok = false;
+    LaunchTimer()
+    {
+        ok = true;
+        for (auto &e : ev)
+            for (auto &x : e)
+                if (hipEventCreate(&x) != hipSuccess) ok = false;
+    }
+    ~LaunchTimer()
+    {
+        for (auto &e : ev)
+            for (auto &x : e)
+                if (x) (void)hipEventDestroy(x);
+    }
+    // slot 0: traversal; slot 1 + r: scoring of round r
+    void begin(int slot, hipStream_t s) { (void)hipEventRecord(ev[slot][0], s); }
+    void end(int slot, hipStream_t s)
+    {
+        (void)hipEventRecord(ev[slot][1], s);
+        (void)hipEventRecord(ev[slot][2], s);
+        (void)hipEventRecord(ev[slot][3], s);
+    }
+    // milliseconds of slot, < 0 on error
+    float ms(int slot)
+    {
+        float a = 0.0f, b = 0.0f;
+        if (hipEventSynchronize(ev[slot][3]) != hipSuccess || hipEventElapsedTime(&a, ev[slot][0], ev[slot][1]) != hipSuccess ||
+            hipEventElapsedTime(&b, ev[slot][2], ev[slot][3]) != hipSuccess)
+            return -1.0f;
+        return a - b;
+    }
+};
+
+// enqueues every kernel of the batch on `s` (with `tm`, the traversal and
+// the scoring launches are timed)
+static int enqueue(const Plan *pl, const Sched &sc, const Stages &st, hipStream_t s, LaunchTimer *tm = nullptr)
 {
     const Attempt *d = pl->d_att;
     const int cap = 4096;
@@ -1513,7 +1564,9 @@ static int enqueue(const Plan *pl, const Sched &sc, const Stages &st, hipStream_
     Stage att = st.att;
     att.xcd = 0;
     RL_LAUNCH("k_b_pack", k_b_pack, dim3(grid_of(st.pb, cap, sc.xcd)), dim3(POOL_BLOCK / PB_PIX), 0, s, d, st.pb);
+    if (tm) tm->begin(0, s);
     launch_leaves(sc, st, cap, d, s);
+    if (tm) tm->end(0, s);
     // learned weights feed the pool's weight prefix
     if (st.wts.total > 0)
         RL_LAUNCH("k_b_weights", k_b_weights, dim3(grid_of(st.wts, cap / WT_WAVES, sc.xcd)), dim3(64 * WT_WAVES), 0,
@@ -1529,12 +1582,14 @@ static int enqueue(const Plan *pl, const Sched &sc, const Stages &st, hipStream_
     const int nw = score_waves(pl->tm_max);
     const size_t smem = (size_t)nw * pl->tm_max * SMODE * sizeof(float);
     for (int r = 0; r < pl->rounds; ++r) {
+        if (tm) tm->begin(1 + r, s);
         if (sc.su == 4)
             RL_LAUNCH("k_b_score", k_b_score<4>, dim3(grid_of(st.score[r], sc.grid, sc.xcd)), dim3(64 * nw), smem,
-                      s, d, st.score[r], r, sc.dpu, pl->tm_max);
+                      s, d, st.score[r], r, sc.dpu[r], pl->tm_max);
         else
             RL_LAUNCH("k_b_score", k_b_score<1>, dim3(grid_of(st.score[r], sc.grid, sc.xcd)), dim3(64 * nw), smem,
-                      s, d, st.score[r], r, sc.dpu, pl->tm_max);
+                      s, d, st.score[r], r, sc.dpu[r], pl->tm_max);
+        if (tm) tm->end(1 + r, s);
         if (r >= pl->fused_from && st.refine[r].total <= FUSED_REFINE) {
             RL_LAUNCH("k_b_cull_refine", k_b_cull_refine, dim3(grid_of(st.refine[r], 0, sc.xcd)), dim3(64), 0, s, d,
                       st.refine[r], r);
@@ -1591,17 +1646,18 @@ static int capture(reloc_batch *b, const Plan *pl, const Sched &sc, int32_t **d_
     return RELOC_OK;
 }
 
-static std::string sched_desc(const Sched &s)
+static std::string sched_desc(const Sched &s, int rounds)
 {
-    char buf[160];
+    std::string dpu;
+    for (int r = 0; r < rounds && r < MAX_ROUNDS; ++r) dpu += (r ? "/" : "") + std::to_string(s.dpu[r]);
+    char buf[200];
     if (s.grid)
-        snprintf(buf, sizeof(buf),
-                 "draws_per_unit=%d score_grid=%d xcd_contiguous=%d pix_per_thread=%d score_unroll=%d", s.dpu,
-                 s.grid, s.xcd, s.pix, s.su);
+        snprintf(buf, sizeof(buf), "draws_per_unit=%s score_grid=%d xcd_contiguous=%d pix_per_thread=%d score_unroll=%d",
+                 dpu.c_str(), s.grid, s.xcd, s.pix, s.su);
     else
         snprintf(buf, sizeof(buf),
-                 "draws_per_unit=%d score_grid=per-unit xcd_contiguous=%d pix_per_thread=%d score_unroll=%d", s.dpu,
-                 s.xcd, s.pix, s.su);
+                 "draws_per_unit=%s score_grid=per-unit xcd_contiguous=%d pix_per_thread=%d score_unroll=%d",
+                 dpu.c_str(), s.xcd, s.pix, s.su);
     return buf;
 }
 
@@ -1618,26 +1674,94 @@ static int run_plan(Plan *pl, hipStream_t s)
     return RELOC_OK;
 }
 
+// times one uncaptured run of schedule `sc` (launches one by one behind the
+// timing delay): per round, the scoring kernel's duration into t_round[r]
+// (ms); the second of two runs counts (the first warms the caches)
+static int time_rounds(Plan *pl, const Sched &sc, hipStream_t s, LaunchTimer &tm, float *t_round)
+{
+    const std::vector<int32_t> off = offsets(pl, sc);
+    int32_t *d_off = nullptr;
+    RL_HIP(hipMalloc((void **)&d_off, off.size() * 4));
+    int rc = RELOC_OK;
+    if (hipMemcpy(d_off, off.data(), off.size() * 4, hipMemcpyHostToDevice) != hipSuccess) rc = RELOC_E_HIP;
+    const Stages st = stages_of(pl, sc, d_off, off);
+    for (int run = 0; run < 2 && !rc; ++run) {
+        prof_delay(s, 8 + 3 * pl->rounds);
+        rc = enqueue(pl, sc, st, s, &tm);
+        if (!rc && hipStreamSynchronize(s) != hipSuccess) rc = RELOC_E_HIP;
+    }
+    for (int r = 0; r < pl->rounds && !rc; ++r) {
+        t_round[r] = tm.ms(1 + r);
+        if (t_round[r] < 0.0f) rc = RELOC_E_HIP;
+    }
+    (void)hipFree(d_off);
+    return rc;
+}
+
+// Chooses the batch's schedule. Without tuning: every round 8 draws per
+// scoring unit, one workgroup per unit. With tuning: (1) per round, the
+// draws per scoring unit (8, 16, 32 or 64) whose scoring launch was
+// fastest in per-launch timings of uncaptured runs; (2) over that
+// per-round schedule and six uniform ones, with and without a persistent
+// scoring grid and the XCD-contiguous unit order, the captured graph with
+// the lowest median time over three launches. Every schedule computes the
+// same results. Traversal width and the scoring unroll follow fixed rules.
 static int tune(reloc_batch *b, Plan *pl, hipStream_t s)
 {
     // traversal work of the batch (pixels x trees): 8 pixels per thread from
     // about five full-size frames of five trees on, where the units still
     // fill the chip several times over
     int64_t work = 0;
-    for (const Shape &sh : pl->shape) work += (int64_t)sh.W * sh.H * sh.T;
+    int max_B = 1;
+    for (const Shape &sh : pl->shape) {
+        work += (int64_t)sh.W * sh.H * sh.T;
+        max_B = std::max(max_B, sh.B);
+    }
     const int pix = work >= 8000000 ? 8 : 4;
     // a single attempt's rounds are short latency chains: the scoring
     // kernel's mode loop unrolled (more registers, fewer resident
     // wavefronts) shortens them; batches keep the leaner loop
     const int su = pl->n == 1 ? 4 : 1;
     std::vector<Sched> cands;
-    cands.push_back({GROUP, 0, 0, pix, su});
+    cands.push_back(uniform_sched(GROUP, 0, 0, pix, su));
     if (b->tune) {
-        cands.push_back({GROUP, 0, 1, pix, su});
-        cands.push_back({2 * GROUP, 0, 1, pix, su});
-        cands.push_back({4 * GROUP, 0, 1, pix, su});
-        cands.push_back({GROUP, 2048, 1, pix, su});
-        cands.push_back({2 * GROUP, 1024, 1, pix, su});
+        // (1) per-round draws per unit from per-launch timings
+        const bool was_on = prof_on();
+        if (was_on) reloc_profile_enable(0);
+        Sched per = uniform_sched(GROUP, 0, 1, pix, su);
+        float best_t[MAX_ROUNDS];
+        for (float &x : best_t) x = 1e30f;
+        int rc = RELOC_OK;
+        {
+            LaunchTimer tm;
+            if (!tm.ok) rc = RELOC_E_HIP;
+            for (int d = GROUP; d <= 8 * GROUP && !rc; d *= 2) {
+                if (d > GROUP && d / 2 >= max_B) break;
+                float t[MAX_ROUNDS];
+                rc = time_rounds(pl, uniform_sched(d, 0, 1, pix, su), s, tm, t);
+                for (int r = 0; r < pl->rounds && !rc; ++r)
+                    if (t[r] < best_t[r]) {
+                        best_t[r] = t[r];
+                        per.dpu[r] = d;
+                    }
+            }
+        }
+        if (was_on) reloc_profile_enable(1);
+        if (rc) return rc;
+        // (2) whole graphs
+        for (int xcd = 0; xcd < 2; ++xcd) {
+            Sched c = per;
+            c.xcd = xcd;
+            cands.push_back(c);
+        }
+        Sched c = per;
+        c.grid = 2048;
+        cands.push_back(c);
+        cands.push_back(uniform_sched(GROUP, 0, 1, pix, su));
+        cands.push_back(uniform_sched(2 * GROUP, 0, 1, pix, su));
+        cands.push_back(uniform_sched(4 * GROUP, 0, 1, pix, su));
+        cands.push_back(uniform_sched(GROUP, 2048, 1, pix, su));
+        cands.push_back(uniform_sched(2 * GROUP, 1024, 1, pix, su));
     }
     hipEvent_t e0 = nullptr, e1 = nullptr;
     RL_HIP(hipEventCreate(&e0));
@@ -1657,16 +1781,22 @@ static int tune(reloc_batch *b, Plan *pl, hipStream_t s)
         if (rc) break;
         float ms = 0.0f;
         if (cands.size() > 1) {
-            // one warm launch, one timed launch; every launch recomputes the
-            // same results from the uploaded descriptors
-            if (hipGraphLaunch(ex, s) != hipSuccess || hipEventRecord(e0, s) != hipSuccess ||
-                hipGraphLaunch(ex, s) != hipSuccess || hipEventRecord(e1, s) != hipSuccess ||
-                hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+            // one warm launch, then the median of three timed launches; every
+            // launch recomputes the same results from the uploaded descriptors
+            float t[3];
+            bool ok = hipGraphLaunch(ex, s) == hipSuccess;
+            for (int k = 0; k < 3 && ok; ++k)
+                ok = hipEventRecord(e0, s) == hipSuccess && hipGraphLaunch(ex, s) == hipSuccess &&
+                     hipEventRecord(e1, s) == hipSuccess && hipEventSynchronize(e1) == hipSuccess &&
+                     hipEventElapsedTime(&t[k], e0, e1) == hipSuccess;
+            if (!ok) {
                 (void)hipGraphExecDestroy(ex);
                 (void)hipFree(d_off);
                 rc = RELOC_E_HIP;
                 break;
             }
+            std::sort(t, t + 3);
+            ms = t[1];
         }
         if (ms < best_ms) {
             if (best) (void)hipGraphExecDestroy(best);
@@ -1690,7 +1820,7 @@ static int tune(reloc_batch *b, Plan *pl, hipStream_t s)
     pl->exec = best;
     pl->d_off = best_off;
     pl->sched = best_s;
-    pl->desc = sched_desc(best_s) + (cands.size() > 1 ? " (tuned)" : " (fixed)");
+    pl->desc = sched_desc(best_s, pl->rounds) + (cands.size() > 1 ? " (tuned)" : " (fixed)");
     return RELOC_OK;
 }
 
