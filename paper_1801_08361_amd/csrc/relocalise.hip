@@ -1701,10 +1701,11 @@ static int time_rounds(Plan *pl, const Sched &sc, hipStream_t s, LaunchTimer &tm
 // Chooses the batch's schedule. Without tuning: every round 8 draws per
 // scoring unit, one workgroup per unit. With tuning: (1) per round, the
 // draws per scoring unit (8, 16, 32 or 64) whose scoring launch was
-// fastest in per-launch timings of uncaptured runs; (2) over that
-// per-round schedule and six uniform ones, with and without a persistent
-// scoring grid and the XCD-contiguous unit order, the captured graph with
-// the lowest median time over three launches. Every schedule computes the
+// fastest in per-launch timings of uncaptured runs (the lower of two
+// passes); (2) over that per-round schedule and six uniform ones, with and
+// without a persistent scoring grid and the XCD-contiguous unit order, the
+// captured graph with the lowest of three timed launches, the candidates
+// launched in turn after three warm launches. Every schedule computes the
 // same results. Traversal width and the scoring unroll follow fixed rules.
 static int tune(reloc_batch *b, Plan *pl, hipStream_t s)
 {
@@ -1733,18 +1734,30 @@ static int tune(reloc_batch *b, Plan *pl, hipStream_t s)
         for (float &x : best_t) x = 1e30f;
         int rc = RELOC_OK;
         {
+            // two passes over the candidates (the first also warms the chip),
+            // the lower time of each (candidate, round) counting
             LaunchTimer tm;
             if (!tm.ok) rc = RELOC_E_HIP;
-            for (int d = GROUP; d <= 8 * GROUP && !rc; d *= 2) {
+            float t_dpu[4][MAX_ROUNDS];
+            for (auto &row : t_dpu)
+                for (float &x : row) x = 1e30f;
+            int n_dpu = 0;
+            for (int d = GROUP; d <= 8 * GROUP; d *= 2) {
                 if (d > GROUP && d / 2 >= max_B) break;
-                float t[MAX_ROUNDS];
-                rc = time_rounds(pl, uniform_sched(d, 0, 1, pix, su), s, tm, t);
-                for (int r = 0; r < pl->rounds && !rc; ++r)
-                    if (t[r] < best_t[r]) {
-                        best_t[r] = t[r];
-                        per.dpu[r] = d;
-                    }
+                ++n_dpu;
             }
+            for (int pass = 0; pass < 2 && !rc; ++pass)
+                for (int j = 0; j < n_dpu && !rc; ++j) {
+                    float t[MAX_ROUNDS];
+                    rc = time_rounds(pl, uniform_sched(GROUP << j, 0, 1, pix, su), s, tm, t);
+                    for (int r = 0; r < pl->rounds && !rc; ++r) t_dpu[j][r] = std::min(t_dpu[j][r], t[r]);
+                }
+            for (int j = 0; j < n_dpu && !rc; ++j)
+                for (int r = 0; r < pl->rounds; ++r)
+                    if (t_dpu[j][r] < best_t[r]) {
+                        best_t[r] = t_dpu[j][r];
+                        per.dpu[r] = GROUP << j;
+                    }
         }
         if (was_on) reloc_profile_enable(1);
         if (rc) return rc;
@@ -1763,60 +1776,44 @@ static int tune(reloc_batch *b, Plan *pl, hipStream_t s)
         cands.push_back(uniform_sched(GROUP, 2048, 1, pix, su));
         cands.push_back(uniform_sched(2 * GROUP, 1024, 1, pix, su));
     }
-    hipEvent_t e0 = nullptr, e1 = nullptr;
-    RL_HIP(hipEventCreate(&e0));
-    if (hipEventCreate(&e1) != hipSuccess) {
-        (void)hipEventDestroy(e0);
-        return RELOC_E_HIP;
-    }
-    float best_ms = 1e30f;
-    hipGraphExec_t best = nullptr;
-    int32_t *best_off = nullptr;
-    Sched best_s = cands[0];
+    // every candidate captured; then, after three warm launches, three passes
+    // that launch each candidate once, the lowest of its three times counting
+    const size_t nc = cands.size();
+    std::vector<hipGraphExec_t> ex(nc, nullptr);
+    std::vector<int32_t *> offs(nc, nullptr);
+    std::vector<float> t_min(nc, 1e30f);
     int rc = RELOC_OK;
-    for (const Sched &c : cands) {
-        hipGraphExec_t ex = nullptr;
-        int32_t *d_off = nullptr;
-        rc = capture(b, pl, c, &d_off, &ex);
-        if (rc) break;
-        float ms = 0.0f;
-        if (cands.size() > 1) {
-            // one warm launch, then the median of three timed launches; every
-            // launch recomputes the same results from the uploaded descriptors
-            float t[3];
-            bool ok = hipGraphLaunch(ex, s) == hipSuccess;
-            for (int k = 0; k < 3 && ok; ++k)
-                ok = hipEventRecord(e0, s) == hipSuccess && hipGraphLaunch(ex, s) == hipSuccess &&
-                     hipEventRecord(e1, s) == hipSuccess && hipEventSynchronize(e1) == hipSuccess &&
-                     hipEventElapsedTime(&t[k], e0, e1) == hipSuccess;
-            if (!ok) {
-                (void)hipGraphExecDestroy(ex);
-                (void)hipFree(d_off);
-                rc = RELOC_E_HIP;
-                break;
+    for (size_t i = 0; i < nc && !rc; ++i) rc = capture(b, pl, cands[i], &offs[i], &ex[i]);
+    if (!rc && nc > 1) {
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) rc = RELOC_E_HIP;
+        for (int w = 0; w < 3 && !rc; ++w)
+            if (hipGraphLaunch(ex[0], s) != hipSuccess) rc = RELOC_E_HIP;
+        for (int pass = 0; pass < 3 && !rc; ++pass)
+            for (size_t i = 0; i < nc && !rc; ++i) {
+                float ms = 0.0f;
+                if (hipEventRecord(e0, s) != hipSuccess || hipGraphLaunch(ex[i], s) != hipSuccess ||
+                    hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                    hipEventElapsedTime(&ms, e0, e1) != hipSuccess)
+                    rc = RELOC_E_HIP;
+                else
+                    t_min[i] = std::min(t_min[i], ms);
             }
-            std::sort(t, t + 3);
-            ms = t[1];
-        }
-        if (ms < best_ms) {
-            if (best) (void)hipGraphExecDestroy(best);
-            if (best_off) (void)hipFree(best_off);
-            best = ex;
-            best_off = d_off;
-            best_ms = ms;
-            best_s = c;
-        } else {
-            (void)hipGraphExecDestroy(ex);
-            (void)hipFree(d_off);
-        }
+        if (e0) (void)hipEventDestroy(e0);
+        if (e1) (void)hipEventDestroy(e1);
     }
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
-    if (rc) {
-        if (best) (void)hipGraphExecDestroy(best);
-        if (best_off) (void)hipFree(best_off);
-        return rc;
-    }
+    size_t pick = 0;
+    for (size_t i = 1; i < nc; ++i)
+        if (t_min[i] < t_min[pick]) pick = i;
+    for (size_t i = 0; i < nc; ++i)
+        if (rc || i != pick) {
+            if (ex[i]) (void)hipGraphExecDestroy(ex[i]);
+            if (offs[i]) (void)hipFree(offs[i]);
+        }
+    if (rc) return rc;
+    hipGraphExec_t best = ex[pick];
+    int32_t *best_off = offs[pick];
+    const Sched best_s = cands[pick];
     pl->exec = best;
     pl->d_off = best_off;
     pl->sched = best_s;
