@@ -509,6 +509,14 @@ int reloc_debug_horn(const double *h_host, int32_t n, double *q_host);
  * -2^31 (the kernels' range is |n| < 2^31, 1 <= den < 2^31). */
 int reloc_debug_div(const int32_t *n_host, const int32_t *den_host, int32_t count, int32_t *q_host);
 
+/* The kernels' cross-lane helpers applied on one wavefront to v = 1000 + lane:
+ * out_host [12][64] receives, per lane, v of lane ^ 1, 2, 4, 8, 16, 32 (rows
+ * 0-5), v of lane - 1, 2, 4, 8 within the lane's row of 16 lanes or 0 below
+ * the row's start (rows 6-9), the high word of w = (5000 + lane) << 32 | v of
+ * lane ^ 2^(lane mod 6) (row 10) and of lane 37 (row 11). Synchronous; allocates
+ * 3 KiB of device memory for the call. Returns RELOC_E_ARG for a null buffer. */
+int reloc_debug_lane_probe(uint32_t *out_host);
+
 /* One 16x16 product C = A B on the matrix cores as the MLP kernels issue it
  * (bfloat16 operands, FP32 accumulation): a_host [16][32] row-major A,
  * bt_host [16][32] row-major B^T, c_host [16][16] row-major C. Synchronous. */

@@ -157,6 +157,7 @@ _SIGS = {
     "reloc_label_pixels": [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32,
                            C.c_void_p, C.c_void_p],
     "reloc_debug_mfma_probe": [C.c_void_p, C.c_void_p, C.c_void_p],
+    "reloc_debug_lane_probe": [C.c_void_p],
     "reloc_debug_horn": [C.c_void_p, C.c_int32, C.c_void_p],
     "reloc_debug_div": [C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p],
     "reloc_debug_bf16": [C.c_void_p, C.c_int32, C.c_void_p],
@@ -564,6 +565,14 @@ def label_pixels(forest: "Forest", depth, rgb, K, pose, pix, stream=None):
     _check(lib().reloc_label_pixels(forest.handle, d, c, C.byref(k), T.ctypes.data, pix.data_ptr(), n,
                                     y.data_ptr(), _stream(stream)), "reloc_label_pixels")
     return y
+
+
+def lane_probe() -> np.ndarray:
+    """The kernels' cross-lane helpers on one wavefront ([12, 64] uint32,
+    reloc_debug_lane_probe)."""
+    out = np.zeros((12, 64), dtype=np.uint32)
+    _check(lib().reloc_debug_lane_probe(out.ctypes.data), "reloc_debug_lane_probe")
+    return out
 
 
 def mfma_probe(a: np.ndarray, bt: np.ndarray) -> np.ndarray:

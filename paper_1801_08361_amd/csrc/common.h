@@ -162,9 +162,21 @@ __device__ __forceinline__ uint64_t split_from_draw(const U4 &u, int32_t O, int3
 // frames
 // ---------------------------------------------------------------------------
 
+// Pointers that device code reads out of device memory (the batch's attempt
+// descriptors) are generic unless declared global: the compiler then issues
+// flat loads, which also count against the LDS/scalar wait counter, so that
+// every wait for an LDS or scalar result waits for them too. In the device
+// pass these members are global-address-space pointers; the host pass sees
+// plain pointers of the same size.
+#if defined(__HIP_DEVICE_COMPILE__)
+#define RL_GLOBAL __attribute__((address_space(1)))
+#else
+#define RL_GLOBAL
+#endif
+
 struct Frame {
-    const uint16_t *__restrict__ depth;
-    const uint8_t *__restrict__ rgb;
+    const uint16_t RL_GLOBAL *__restrict__ depth;
+    const uint8_t RL_GLOBAL *__restrict__ rgb;
     int32_t W, H;
     float fx, fy, cx, cy;
     int32_t Fx, Fy;       // focal lengths in 1/16 px, rounded half up
@@ -731,6 +743,85 @@ __device__ __forceinline__ bool pose_from_sums(const double s[NSUM], double R[9]
 }
 
 
+// ---------------------------------------------------------------------------
+// cross-lane moves within a wavefront through the VALU (DPP and gfx950's
+// permlane swaps) instead of the LDS crossbar: shorter latency on the serial
+// chains of a single wavefront
+// ---------------------------------------------------------------------------
+
+// v of lane (lane ^ M), every lane active
+template <int M>
+__device__ __forceinline__ uint32_t xor_lane(uint32_t v)
+{
+    static_assert(M == 1 || M == 2 || M == 4 || M == 8 || M == 16 || M == 32, "xor of one lane bit");
+    const int x = (int)v;
+    if constexpr (M == 1) {
+        return (uint32_t)__builtin_amdgcn_mov_dpp(x, 0xB1, 0xF, 0xF, true);     // quad_perm [1, 0, 3, 2]
+    } else if constexpr (M == 2) {
+        return (uint32_t)__builtin_amdgcn_mov_dpp(x, 0x4E, 0xF, 0xF, true);     // quad_perm [2, 3, 0, 1]
+    } else if constexpr (M == 4) {
+        const int up = __builtin_amdgcn_mov_dpp(x, 0x104, 0xF, 0xF, true);     // row_shl:4, lane + 4
+        const int dn = __builtin_amdgcn_mov_dpp(x, 0x114, 0xF, 0xF, true);     // row_shr:4, lane - 4
+        return (uint32_t)((__lane_id() & 4) ? dn : up);
+    } else if constexpr (M == 8) {
+        return (uint32_t)__builtin_amdgcn_mov_dpp(x, 0x128, 0xF, 0xF, true);    // row_ror:8
+    } else if constexpr (M == 16) {
+        // odd rows of the first operand swap with even rows of the second
+        const auto p = __builtin_amdgcn_permlane16_swap(v, v, false, false);
+        return (__lane_id() & 16) ? p[0] : p[1];
+    } else {
+        // upper half of the first operand swaps with the lower half of the second
+        const auto p = __builtin_amdgcn_permlane32_swap(v, v, false, false);
+        return (__lane_id() & 32) ? p[0] : p[1];
+    }
+}
+
+template <int M>
+__device__ __forceinline__ uint64_t xor_lane64(uint64_t v)
+{
+    return ((uint64_t)xor_lane<M>((uint32_t)(v >> 32)) << 32) | xor_lane<M>((uint32_t)v);
+}
+
+template <int M>
+__device__ __forceinline__ double xor_lane_f64(double v)
+{
+    return __longlong_as_double((long long)xor_lane64<M>((uint64_t)__double_as_longlong(v)));
+}
+
+// xor_lane64 for a wavefront-uniform M in {1, 2, 4, 8, 16, 32}
+__device__ __forceinline__ uint64_t xor_lane64_n(uint64_t v, int m)
+{
+    switch (m) {
+    case 1: return xor_lane64<1>(v);
+    case 2: return xor_lane64<2>(v);
+    case 4: return xor_lane64<4>(v);
+    case 8: return xor_lane64<8>(v);
+    case 16: return xor_lane64<16>(v);
+    default: return xor_lane64<32>(v);
+    }
+}
+
+// lane j's value (j wavefront-uniform)
+__device__ __forceinline__ uint64_t lane_u64(uint64_t v, int j)
+{
+    return ((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)(v >> 32), j) << 32) |
+           (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, j);
+}
+
+__device__ __forceinline__ double lane_f64(double v, int j)
+{
+    return __longlong_as_double((long long)lane_u64((uint64_t)__double_as_longlong(v), j));
+}
+
+// the value O lanes below within the lane's row of 16 (0 for the row's first
+// O lanes), O in {1, 2, 4, 8}
+template <int O>
+__device__ __forceinline__ int row_up(int v)
+{
+    static_assert(O == 1 || O == 2 || O == 4 || O == 8, "row shift");
+    return __builtin_amdgcn_mov_dpp(v, 0x110 + O, 0xF, 0xF, true);   // row_shr:O
+}
+
 // float -> uint32 key that sorts like the float (no NaN, no -0 here)
 __device__ __forceinline__ uint32_t float_key(float f)
 {
@@ -790,52 +881,52 @@ struct Forest {
 struct Attempt {
     Frame fr;
     // the target forest (read-only here)
-    const uint64_t *nodes;
-    const DeepNode *deep;
-    const int32_t *nmodes;
-    const Mode *modes;
-    const uint32_t *mode_rgb;
-    const unsigned long long *total_samples;
-    const uint32_t *weights;       // [P] integer pick weights or null
-    const float4 *leaf_in;         // [T][L][4] per-leaf summaries (learned inputs)
-    const uint16_t *mq;            // learned proposal: bfloat16 weight copies, or null
-    const float *mw;               // learned proposal: FP32 parameters
+    const uint64_t RL_GLOBAL *nodes;
+    const DeepNode RL_GLOBAL *deep;
+    const int32_t RL_GLOBAL *nmodes;
+    const Mode RL_GLOBAL *modes;
+    const uint32_t RL_GLOBAL *mode_rgb;
+    const unsigned long long RL_GLOBAL *total_samples;
+    const uint32_t RL_GLOBAL *weights;      // [P] integer pick weights or null
+    const float4 RL_GLOBAL *leaf_in;        // [T][L][4] per-leaf summaries (learned inputs)
+    const uint16_t RL_GLOBAL *mq;           // learned proposal: bfloat16 weight copies, or null
+    const float RL_GLOBAL *mw;              // learned proposal: FP32 parameters
     int32_t T, L, M, R, P, N, B, max_tries, rgb_tol, refine, rounds;
     float ratio2, min_pair2, min_area2, inl2;
     double resid2;
     uint64_t seed;
     // scratch owned by the batch
-    int32_t *leaves;               // [T][P] leaf of each pixel in each tree (-1: invalid pixel)
-    uint64_t *packed;              // [P] the frame packed for probing
-    int32_t *pool;                 // [P]
-    int32_t *blockcnt;             // [nb]
-    unsigned long long *blockw;    // [nb] weight sums per pixel block
-    unsigned long long *cdf;       // [P] inclusive weight prefix over the pool
-    int32_t *guide;                // [P] weighted picks: first pool entry of each draw bucket
-    unsigned long long *gsel;      // [0] total weight [1] bucket multiplier [2] buckets in use
-    uint32_t *wbuf;                // [P] learned pick weights (learned proposal only)
-    int32_t *misc;                 // [0] pool size [2] valid hypotheses
-    int32_t *rl;                   // [MAX_ROUNDS + 1] live hypotheses at the start of round r (r = 0: the
-                                   // valid ones; 0 once the attempt has finished): round r runs iff
-                                   // rl[r] >= 1 (r = 0) or rl[r] > 1; the cull of round r writes rl[r + 1]
-    Hyp *hyp;                      // [N]
-    double *hyp_init;              // [N][12]
-    int32_t *hyp_try;              // [N]
-    float *energy;                 // [2][N] accumulated energy of the hypothesis at each live position
-    double *sums;                  // [N][NSUM] running inlier sums
-    int32_t *alive;                // [2][N] the live list scored in round r is buffer r & 1; the cull of round r
-                                   // writes buffer (r + 1) & 1, so that it never overwrites what it reads
-    int32_t *pos;                  // [N] survivor i's position in the list it was scored in
-    float *lpose;                  // [N][12] FP32 pose (R row-major, t) of the hypothesis at each live position
-    float4 *draws;                 // [rounds][B] camera point, pixel index bits of every draw
-    int2 *dtree;                   // [rounds][B][T] per draw and tree: first global mode index (leaf * M), mode count
-    float *gs;                     // [ceil(B / GROUP)][N] energy sum of each group of GROUP draws, per live position
-    int32_t *inl;                  // [ceil(B/8)][N][8] global index (leaf * M + mode) of an inlier's best mode, -1 otherwise
-    unsigned long long *stats;     // [0] mode evaluations [1] pair evaluations [2] round mode count
-    int32_t *tr_alive;             // [MAX_ROUNDS][N]
-    float *tr_energy;              // [MAX_ROUNDS][N]
-    int32_t *tr_n_alive;           // [MAX_ROUNDS]
-    Result *result;
+    int32_t RL_GLOBAL *leaves;              // [T][P] leaf of each pixel in each tree (-1: invalid pixel)
+    uint64_t RL_GLOBAL *packed;             // [P] the frame packed for probing
+    int32_t RL_GLOBAL *pool;                // [P]
+    int32_t RL_GLOBAL *blockcnt;            // [nb]
+    unsigned long long RL_GLOBAL *blockw;   // [nb] weight sums per pixel block
+    unsigned long long RL_GLOBAL *cdf;      // [P] inclusive weight prefix over the pool
+    int32_t RL_GLOBAL *guide;               // [P] weighted picks: first pool entry of each draw bucket
+    unsigned long long RL_GLOBAL *gsel;     // [0] total weight [1] bucket multiplier [2] buckets in use
+    uint32_t RL_GLOBAL *wbuf;               // [P] learned pick weights (learned proposal only)
+    int32_t RL_GLOBAL *misc;                // [0] pool size [2] valid hypotheses
+    int32_t RL_GLOBAL *rl;                  // [MAX_ROUNDS + 1] live hypotheses at the start of round r (r = 0: the
+                                            // valid ones; 0 once the attempt has finished): round r runs iff
+                                            // rl[r] >= 1 (r = 0) or rl[r] > 1; the cull of round r writes rl[r + 1]
+    Hyp RL_GLOBAL *hyp;                     // [N]
+    double RL_GLOBAL *hyp_init;             // [N][12]
+    int32_t RL_GLOBAL *hyp_try;             // [N]
+    float RL_GLOBAL *energy;                // [2][N] accumulated energy of the hypothesis at each live position
+    double RL_GLOBAL *sums;                 // [N][NSUM] running inlier sums
+    int32_t RL_GLOBAL *alive;               // [2][N] the live list scored in round r is buffer r & 1; the cull of round r
+                                            // writes buffer (r + 1) & 1, so that it never overwrites what it reads
+    int32_t RL_GLOBAL *pos;                 // [N] survivor i's position in the list it was scored in
+    float RL_GLOBAL *lpose;                 // [N][12] FP32 pose (R row-major, t) of the hypothesis at each live position
+    float4 RL_GLOBAL *draws;                // [rounds][B] camera point, pixel index bits of every draw
+    int2 RL_GLOBAL *dtree;                  // [rounds][B][T] per draw and tree: first global mode index (leaf * M), mode count
+    float RL_GLOBAL *gs;                    // [ceil(B / GROUP)][N] energy sum of each group of GROUP draws, per live position
+    int32_t RL_GLOBAL *inl;                 // [ceil(B/8)][N][8] global index (leaf * M + mode) of an inlier's best mode, -1 otherwise
+    unsigned long long RL_GLOBAL *stats;    // [0] mode evaluations [1] pair evaluations [2] round mode count
+    int32_t RL_GLOBAL *tr_alive;            // [MAX_ROUNDS][N]
+    float RL_GLOBAL *tr_energy;             // [MAX_ROUNDS][N]
+    int32_t RL_GLOBAL *tr_n_alive;          // [MAX_ROUNDS]
+    Result RL_GLOBAL *result;
 };
 
 // The inlier ids are stored in tiles of 8 consecutive draws per live

@@ -72,7 +72,7 @@ static int frame_of(const Forest *f, const uint16_t *depth, const uint8_t *rgb, 
     if (!(K->fx > 0.0f) || !(K->fy > 0.0f) || !isfinite(K->cx) || !isfinite(K->cy) || !isfinite(K->fx) ||
         !isfinite(K->fy))
         return RELOC_E_ARG;
-    fr.depth = depth; fr.rgb = rgb; fr.W = K->width; fr.H = K->height;
+    fr.depth = (decltype(fr.depth))depth; fr.rgb = (decltype(fr.rgb))rgb; fr.W = K->width; fr.H = K->height;
     fr.fx = K->fx; fr.fy = K->fy; fr.cx = K->cx; fr.cy = K->cy;
     if (!(K->fx < 1048576.0f) || !(K->fy < 1048576.0f)) return RELOC_E_ARG;
     int64_t Fx = focal16(K->fx), Fy = focal16(K->fy);

@@ -790,6 +790,26 @@ __device__ __forceinline__ unsigned long long cull_key(float E, int h, int ap)
     return ((unsigned long long)float_key(E) << 32) | ((unsigned long long)(uint32_t)h << 12) | (uint32_t)ap;
 }
 
+// Live position ap's energy over a round's groups: its group sums (rows of
+// `stride` floats) added in group order, CH loaded at a time. Loads past the
+// last group read the last one again and add +0 instead (a group sum is
+// never -0, so the total is the same), which keeps them free of branches.
+template <int CH>
+__device__ __forceinline__ float group_total(const float RL_GLOBAL *gs, int ap, int ng, int stride)
+{
+    float S = 0.0f;
+    for (int k0 = 0; k0 < ng; k0 += CH) {
+        float v[CH];
+        const float RL_GLOBAL *row = gs + (int64_t)k0 * stride + ap;
+        const int last = ng - 1 - k0;
+#pragma unroll
+        for (int k = 0; k < CH; ++k) v[k] = row[(int64_t)min(k, last) * stride];
+#pragma unroll
+        for (int k = 0; k < CH; ++k) S = S + (k <= last ? v[k] : 0.0f);
+    }
+    return S;
+}
+
 __device__ void cull_round(const Attempt &A, int r, unsigned long long *__restrict__ keys)
 {
     const int nt = (int)blockDim.x;
@@ -803,18 +823,7 @@ __device__ void cull_round(const Attempt &A, int r, unsigned long long *__restri
         if (ap < na) {
             const int h = al[ap];
             const int ng = (A.B + GROUP - 1) / GROUP;
-            const float *gs = A.gs + ap;
-            // group sums in group order, loaded 32 at a time
-            float Ssum = 0.0f;
-            for (int k0 = 0; k0 < ng; k0 += 32) {
-                float v[32];
-#pragma unroll
-                for (int k = 0; k < 32; ++k) v[k] = k0 + k < ng ? gs[(int64_t)(k0 + k) * A.N] : 0.0f;
-#pragma unroll
-                for (int k = 0; k < 32; ++k)
-                    if (k0 + k < ng) Ssum = Ssum + v[k];
-            }
-            const float E = en[ap] + Ssum;
+            const float E = en[ap] + group_total<32>(A.gs, ap, ng, A.N);
             keys[ap] = cull_key(E, h, ap);
             if (r < MAX_ROUNDS) {
                 A.tr_alive[r * A.N + ap] = h;
@@ -956,12 +965,14 @@ __global__ void __launch_bounds__(64 * GROUP) k_b_score(const Attempt *__restric
                             nm = e.y;
                         }
                     }
+                    // inclusive scan of the mode counts over the trees (lanes
+                    // 0 .. T - 1 of the first row)
                     int incl = nm;
-                    for (int o = 1; o < 16; o <<= 1) {
-                        int y = __shfl_up(incl, o, 64);
-                        if (lane >= o) incl += y;
-                    }
-                    const int cnt = __shfl(incl, A.T - 1, 64);
+                    incl += row_up<1>(incl);
+                    incl += row_up<2>(incl);
+                    incl += row_up<4>(incl);
+                    incl += row_up<8>(incl);
+                    const int cnt = __builtin_amdgcn_readlane(incl, A.T - 1);
                     if (lane < A.T) {
                         s_ex[wv][lane] = incl - nm;
                         s_base[wv][lane] = base;
@@ -1075,13 +1086,19 @@ __device__ __forceinline__ void refine_sums_at(const Attempt &A, int r, int h, i
             const int i = base + k * 64 + lane;
             gid[k] = i < A.B ? A.inl[inl_at(A, i, ap)] : -1;
         }
+        // the draws' camera points load with the ids, the inliers' means after
+        float4 dr[RB];
+#pragma unroll
+        for (int k = 0; k < RB; ++k) {
+            const int i = base + k * 64 + lane;
+            dr[k] = i < A.B ? A.draws[(int64_t)r * A.B + i] : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+        }
         float c[RB][3], w[RB][3];
 #pragma unroll
         for (int k = 0; k < RB; ++k) {
             if (gid[k] >= 0) {
-                const float4 dr = A.draws[(int64_t)r * A.B + base + k * 64 + lane];
                 const Mode &md = A.modes[gid[k]];
-                c[k][0] = dr.x; c[k][1] = dr.y; c[k][2] = dr.z;
+                c[k][0] = dr[k].x; c[k][1] = dr[k].y; c[k][2] = dr[k].z;
                 w[k][0] = md.mu[0]; w[k][1] = md.mu[1]; w[k][2] = md.mu[2];
             }
         }
@@ -1089,12 +1106,21 @@ __device__ __forceinline__ void refine_sums_at(const Attempt &A, int r, int h, i
         for (int k = 0; k < RB; ++k)
             if (gid[k] >= 0) sums_add_point(s, c[k], w[k]);
     }
+    // xor butterfly over the lanes (offsets 32, 16, ..., 1)
 #pragma unroll
-    for (int o = 32; o >= 1; o >>= 1)
+    for (int k = 0; k < NSUM; ++k) s[k] = s[k] + xor_lane_f64<32>(s[k]);
 #pragma unroll
-        for (int k = 0; k < NSUM; ++k) s[k] = s[k] + __shfl_xor(s[k], o, 64);
+    for (int k = 0; k < NSUM; ++k) s[k] = s[k] + xor_lane_f64<16>(s[k]);
 #pragma unroll
-    for (int k = 0; k < NSUM; ++k) s[k] = __shfl(runk, k, 64) + s[k];
+    for (int k = 0; k < NSUM; ++k) s[k] = s[k] + xor_lane_f64<8>(s[k]);
+#pragma unroll
+    for (int k = 0; k < NSUM; ++k) s[k] = s[k] + xor_lane_f64<4>(s[k]);
+#pragma unroll
+    for (int k = 0; k < NSUM; ++k) s[k] = s[k] + xor_lane_f64<2>(s[k]);
+#pragma unroll
+    for (int k = 0; k < NSUM; ++k) s[k] = s[k] + xor_lane_f64<1>(s[k]);
+#pragma unroll
+    for (int k = 0; k < NSUM; ++k) s[k] = lane_f64(runk, k) + s[k];
     if (lane == 0) {
         double *run = A.sums + (int64_t)h * NSUM;
 #pragma unroll
@@ -1202,33 +1228,26 @@ __global__ void __launch_bounds__(64) k_b_cull_refine(const Attempt *__restrict_
         const Attempt &A = att[a];
         const int sidx = u - S.off[a];
         const int lane = __lane_id();
-        if (!round_active(A, r)) continue;
         const int na = A.rl[r];        // <= FUSED_LIVE: one live position per lane
-        const int keep = (na + 1) / 2;
-        if (sidx >= keep) continue;
-        const int ng = (A.B + GROUP - 1) / GROUP;
-        const bool live = lane < na;
-        const int apl = live ? lane : 0;
+        // positions clamped into the lists, so that these loads issue with
+        // the live count
+        const int apl = min(lane, A.N - 1);
         const int hl = live_list(A, r)[apl];
         const float El = live_energy(A, r)[apl];
-        // the group sums in group order, loaded 64 at a time
-        const float *gs = A.gs + apl;
-        float Ssum = 0.0f;
-        for (int k0 = 0; k0 < ng; k0 += 64) {
-            float v[64];
-#pragma unroll
-            for (int k = 0; k < 64; ++k) v[k] = k0 + k < ng ? gs[(int64_t)(k0 + k) * A.N] : 0.0f;
-#pragma unroll
-            for (int k = 0; k < 64; ++k)
-                if (k0 + k < ng) Ssum = Ssum + v[k];
-        }
+        const int ng = (A.B + GROUP - 1) / GROUP;
+        // the group sums in group order, 64 loads at a time
+        const float Ssum = group_total<64>(A.gs, apl, ng, A.N);
+        if (!round_active(A, r)) continue;
+        const int keep = (na + 1) / 2;
+        if (sidx >= keep) continue;
+        const bool live = lane < na;
         const float E = El + Ssum;
         const unsigned long long key = live ? cull_key(E, hl, lane) : ~0ull;
         // rank: how many live keys are smaller (keys are distinct)
         int rank = 0;
-        for (int q = 0; q < na; ++q) rank += __shfl(key, q, 64) < key;
+        for (int q = 0; q < na && q < 64; ++q) rank += lane_u64(key, q) < key;
         const uint64_t m = __ballot(live && rank == sidx);
-        const unsigned long long kk = __shfl(key, __ffsll((unsigned long long)m) - 1, 64);
+        const unsigned long long kk = lane_u64(key, max(__ffsll((unsigned long long)m) - 1, 0));
         const int h = (int)((kk >> 12) & 0xFFFFFull);
         const int ap = (int)(kk & 0xFFFull);
         if (lane == 0) {
@@ -1379,34 +1398,34 @@ static size_t carve(const Shape &s, char *base, Attempt &A)
         off += align256(bytes);
         return p;
     };
-    A.leaves = (int32_t *)take((size_t)s.T * P * 4);
-    A.packed = (uint64_t *)take((size_t)P * 8);
-    A.pool = (int32_t *)take((size_t)P * 4);
-    A.blockcnt = (int32_t *)take((size_t)nb * 4);
-    A.blockw = (unsigned long long *)take((size_t)nb * 8);
-    A.cdf = (unsigned long long *)take(s.weights ? (size_t)P * 8 : 8);
-    A.guide = (int32_t *)take(s.weights ? (size_t)P * 4 : 4);
-    A.gsel = (unsigned long long *)take(3 * 8);
-    A.wbuf = (uint32_t *)take(s.weights == 2 ? (size_t)P * 4 : 4);
-    A.misc = (int32_t *)take(16);
-    A.rl = (int32_t *)take((size_t)(MAX_ROUNDS + 1) * 4);
-    A.hyp = (Hyp *)take((size_t)s.N * sizeof(Hyp));
-    A.hyp_init = (double *)take((size_t)s.N * 12 * 8);
-    A.hyp_try = (int32_t *)take((size_t)s.N * 4);
-    A.energy = (float *)take((size_t)2 * s.N * 4);
-    A.sums = (double *)take((size_t)s.N * NSUM * 8);
-    A.alive = (int32_t *)take((size_t)2 * s.N * 4);
-    A.pos = (int32_t *)take((size_t)s.N * 4);
-    A.lpose = (float *)take((size_t)s.N * 12 * 4);
+    A.leaves = (decltype(A.leaves))take((size_t)s.T * P * 4);
+    A.packed = (decltype(A.packed))take((size_t)P * 8);
+    A.pool = (decltype(A.pool))take((size_t)P * 4);
+    A.blockcnt = (decltype(A.blockcnt))take((size_t)nb * 4);
+    A.blockw = (decltype(A.blockw))take((size_t)nb * 8);
+    A.cdf = (decltype(A.cdf))take(s.weights ? (size_t)P * 8 : 8);
+    A.guide = (decltype(A.guide))take(s.weights ? (size_t)P * 4 : 4);
+    A.gsel = (decltype(A.gsel))take(3 * 8);
+    A.wbuf = (decltype(A.wbuf))take(s.weights == 2 ? (size_t)P * 4 : 4);
+    A.misc = (decltype(A.misc))take(16);
+    A.rl = (decltype(A.rl))take((size_t)(MAX_ROUNDS + 1) * 4);
+    A.hyp = (decltype(A.hyp))take((size_t)s.N * sizeof(Hyp));
+    A.hyp_init = (decltype(A.hyp_init))take((size_t)s.N * 12 * 8);
+    A.hyp_try = (decltype(A.hyp_try))take((size_t)s.N * 4);
+    A.energy = (decltype(A.energy))take((size_t)2 * s.N * 4);
+    A.sums = (decltype(A.sums))take((size_t)s.N * NSUM * 8);
+    A.alive = (decltype(A.alive))take((size_t)2 * s.N * 4);
+    A.pos = (decltype(A.pos))take((size_t)s.N * 4);
+    A.lpose = (decltype(A.lpose))take((size_t)s.N * 12 * 4);
     const int rounds = rounds_for(s.N);
-    A.draws = (float4 *)take((size_t)rounds * s.B * 16);
-    A.dtree = (int2 *)take((size_t)rounds * s.B * s.T * 8);
-    A.gs = (float *)take((size_t)((s.B + GROUP - 1) / GROUP) * s.N * 4);
-    A.inl = (int32_t *)take((size_t)((s.B + INL_TILE - 1) / INL_TILE) * INL_TILE * s.N * 4);
-    A.stats = (unsigned long long *)take(3 * 8);
-    A.tr_alive = (int32_t *)take((size_t)MAX_ROUNDS * s.N * 4);
-    A.tr_energy = (float *)take((size_t)MAX_ROUNDS * s.N * 4);
-    A.tr_n_alive = (int32_t *)take((size_t)MAX_ROUNDS * 4);
+    A.draws = (decltype(A.draws))take((size_t)rounds * s.B * 16);
+    A.dtree = (decltype(A.dtree))take((size_t)rounds * s.B * s.T * 8);
+    A.gs = (decltype(A.gs))take((size_t)((s.B + GROUP - 1) / GROUP) * s.N * 4);
+    A.inl = (decltype(A.inl))take((size_t)((s.B + INL_TILE - 1) / INL_TILE) * INL_TILE * s.N * 4);
+    A.stats = (decltype(A.stats))take(3 * 8);
+    A.tr_alive = (decltype(A.tr_alive))take((size_t)MAX_ROUNDS * s.N * 4);
+    A.tr_energy = (decltype(A.tr_energy))take((size_t)MAX_ROUNDS * s.N * 4);
+    A.tr_n_alive = (decltype(A.tr_n_alive))take((size_t)MAX_ROUNDS * 4);
     A.result = nullptr;   // a slot of the plan's pinned host results, written by k_b_finish
     return off;
 }
@@ -1884,7 +1903,7 @@ static Plan *find_or_make_plan(reloc_batch *b, const std::vector<Shape> &shape, 
     }
     for (int a = 0; a < pl->n; ++a) {
         carve(shape[a], pl->arena + at[a], pl->slices[a]);
-        pl->slices[a].result = d_res + a;
+        pl->slices[a].result = (decltype(pl->slices[a].result))(d_res + a);
     }
     pl->last_use = ++b->clock;
     b->plans.push_back(pl);
@@ -1922,17 +1941,17 @@ static int run_batch(reloc_batch *b, const reloc_attempt *att, int n, hipStream_
         const Forest *f = x.forest;
         Attempt A = pl->slices[a];
         A.fr = frames[a];
-        A.nodes = f->nodes;
-        A.deep = f->deep;
-        A.nmodes = f->nmodes;
-        A.modes = f->modes;
-        A.mode_rgb = f->mode_rgb;
-        A.total_samples = f->total_samples;
-        A.weights = x.proposal ? A.wbuf : x.pixel_weights_dev;
-        A.leaf_in = f->leaf_in;
+        A.nodes = (decltype(A.nodes))f->nodes;
+        A.deep = (decltype(A.deep))f->deep;
+        A.nmodes = (decltype(A.nmodes))f->nmodes;
+        A.modes = (decltype(A.modes))f->modes;
+        A.mode_rgb = (decltype(A.mode_rgb))f->mode_rgb;
+        A.total_samples = (decltype(A.total_samples))f->total_samples;
+        A.weights = x.proposal ? (decltype(A.weights))A.wbuf : (decltype(A.weights))x.pixel_weights_dev;
+        A.leaf_in = (decltype(A.leaf_in))f->leaf_in;
         A.R = f->R;
-        A.mq = x.proposal ? rl_mlp_q(x.proposal) : nullptr;
-        A.mw = x.proposal ? rl_mlp_w(x.proposal) : nullptr;
+        A.mq = x.proposal ? (decltype(A.mq))rl_mlp_q(x.proposal) : nullptr;
+        A.mw = x.proposal ? (decltype(A.mw))rl_mlp_w(x.proposal) : nullptr;
         A.T = f->T; A.L = f->L; A.M = f->M; A.P = frames[a].W * frames[a].H;
         A.N = shape[a].N; A.B = f->p.batch_pixels; A.max_tries = f->p.max_tries; A.rgb_tol = f->p.rgb_tol;
         A.refine = f->p.refine; A.rounds = rounds_for(A.N);
@@ -2100,6 +2119,44 @@ extern "C" int reloc_debug_trace(const reloc_forest *f, reloc_trace *tr)
                              hipMemcpyDeviceToHost));
     }
     return RELOC_OK;
+}
+
+// each cross-lane helper of the kernels applied to v = 1000 + lane
+__global__ void __launch_bounds__(64) k_lane_probe(uint32_t *out)
+{
+    const int lane = __lane_id();
+    const uint32_t v = 1000u + (uint32_t)lane;
+    out[0 * 64 + lane] = xor_lane<1>(v);
+    out[1 * 64 + lane] = xor_lane<2>(v);
+    out[2 * 64 + lane] = xor_lane<4>(v);
+    out[3 * 64 + lane] = xor_lane<8>(v);
+    out[4 * 64 + lane] = xor_lane<16>(v);
+    out[5 * 64 + lane] = xor_lane<32>(v);
+    out[6 * 64 + lane] = (uint32_t)row_up<1>((int)v);
+    out[7 * 64 + lane] = (uint32_t)row_up<2>((int)v);
+    out[8 * 64 + lane] = (uint32_t)row_up<4>((int)v);
+    out[9 * 64 + lane] = (uint32_t)row_up<8>((int)v);
+    const uint64_t w = ((uint64_t)(5000u + (uint32_t)lane) << 32) | v;
+    uint64_t x = 0;
+    for (int k = 0; k < 6; ++k) {   // (the offset is the same for every lane of a call)
+        const uint64_t y = xor_lane64_n(w, 1 << k);
+        if (lane % 6 == k) x = y;
+    }
+    out[10 * 64 + lane] = (uint32_t)(x >> 32);
+    out[11 * 64 + lane] = (uint32_t)(lane_u64(w, 37) >> 32);
+}
+
+extern "C" int reloc_debug_lane_probe(uint32_t *out_host)
+{
+    if (!out_host) return RELOC_E_ARG;
+    uint32_t *d = nullptr;
+    if (hipMalloc((void **)&d, 12 * 64 * 4) != hipSuccess) return RELOC_E_NOMEM;
+    int rc = RELOC_OK;
+    hipLaunchKernelGGL(k_lane_probe, dim3(1), dim3(64), 0, 0, d);
+    if (hipDeviceSynchronize() != hipSuccess || hipMemcpy(out_host, d, 12 * 64 * 4, hipMemcpyDeviceToHost) != hipSuccess)
+        rc = RELOC_E_HIP;
+    (void)hipFree(d);
+    return rc;
 }
 
 extern "C" int reloc_debug_unit_owners(int32_t xcd, int32_t total, int32_t grid, int32_t *owners_host)

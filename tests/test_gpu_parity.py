@@ -22,6 +22,24 @@ def make(pp, po):
     return rl.Forest(pp), oracle.Forest(po)
 
 
+def test_lane_moves(dev):
+    """The cross-lane helpers that the cull's sort, the refinement's
+    butterfly and the scoring's tree scan use move exactly the lanes they
+    name (the butterfly's additions pair the same lanes as the oracle's)."""
+    import paper_1801_08361_amd as rl
+    banner("lane moves")
+    out = rl.lane_probe().astype(np.int64)
+    lane = np.arange(64)
+    v = 1000 + lane
+    for k in range(6):
+        assert np.array_equal(out[k], v[lane ^ (1 << k)]), k
+    for k, o in enumerate((1, 2, 4, 8)):
+        want = np.where(lane % 16 >= o, v[np.maximum(lane - o, 0)], 0)
+        assert np.array_equal(out[6 + k], want), o
+    assert np.array_equal(out[10], 5000 + (lane ^ (1 << (lane % 6))))
+    assert np.all(out[11] == 5037)
+
+
 @pytest.mark.parametrize("cfg", ["small", "full"])
 def test_nodes_match(dev, cfg):
     kw = SMALL if cfg == "small" else FULL
