@@ -1557,14 +1557,15 @@ struct LaunchTimer {
         (void)hipEventRecord(ev[slot][2], s);
         (void)hipEventRecord(ev[slot][3], s);
     }
-    // milliseconds of slot, < 0 on error
+    // milliseconds of slot (at least 0: a launch with nothing to do can take
+    // less than the spread of the events' own cost), < 0 on error
     float ms(int slot)
     {
         float a = 0.0f, b = 0.0f;
         if (hipEventSynchronize(ev[slot][3]) != hipSuccess || hipEventElapsedTime(&a, ev[slot][0], ev[slot][1]) != hipSuccess ||
             hipEventElapsedTime(&b, ev[slot][2], ev[slot][3]) != hipSuccess)
             return -1.0f;
-        return a - b;
+        return a > b ? a - b : 0.0f;
     }
 };
 

@@ -51,6 +51,24 @@ def same(a, b):
             and a["pair_evals"] == b["pair_evals"] and a["pool_size"] == b["pool_size"])
 
 
+def test_tuned_batches_of_tiny_attempts(forests):
+    """The autotuner's per-launch timings of launches with nothing to do (the
+    late rounds of attempts with a handful of hypotheses) can come out below
+    the events' own cost; they count as zero, never as an error. Fresh tuned
+    batches of such attempts equal the plain calls."""
+    import paper_1801_08361_amd as rl
+    dev, fs = forests
+    for rep in range(4):
+        att = attempts(dev, fs, 6, seed=40 + rep)
+        for k, a in enumerate(att):
+            a["n_hyp"] = (2, 3, 5, 1, 8, 4)[k]
+        banner(f"tiny tuned batch {rep}")
+        res = rl.Batch(tune=True).run(att)
+        for a, r in zip(att, res):
+            p = a["forest"].relocalise_ex(a["depth"], a["rgb"], a["K"], seed=a["seed"], n_hyp=a["n_hyp"])
+            assert same(r, p)
+
+
 @pytest.mark.parametrize("tune", [False, True])
 def test_batch_equals_plain(forests, tune):
     import paper_1801_08361_amd as rl
