@@ -415,6 +415,18 @@ int reloc_mlp_pixel_weights(reloc_mlp *m, reloc_forest *f, const uint16_t *depth
 int reloc_pixel_features(reloc_forest *f, const uint16_t *depth_dev, const uint8_t *rgb_dev,
                          const reloc_intrinsics *K, const int32_t *pix_dev, int32_t n, uint16_t *x_dev, float *xf_dev,
                          void *stream);
+/* The valid pixels of an RGB-D frame given to the relocaliser (Sec. 3.3.1):
+ * those whose depth lies in the forest's depth range, the test that the
+ * features, the adaptation and the relocaliser's pixel pool apply. Writes
+ * their indices v W + u, in raster order, to pix_dev (device memory for W H
+ * int32 values, owned by the caller), their number to *n_out (host). The
+ * frame is described as for reloc_pixel_features. Allocates a small device
+ * buffer of block counts for the call and synchronises `stream` before it
+ * returns. Returns RELOC_E_ARG for a null forest, buffer or count pointer or
+ * an invalid frame, RELOC_E_NOMEM when the buffer cannot be allocated. */
+int reloc_valid_pixels(reloc_forest *f, const uint16_t *depth_dev, const uint8_t *rgb_dev, const reloc_intrinsics *K,
+                       int32_t *pix_dev, int32_t *n_out, void *stream);
+
 /* training labels: label_dev[i] = round(255 g / c) for pixel pix_dev[i],
  * where c counts the modes of the pixel's leaves that pass the hypothesis
  * pick's colour test (|mode colour - pixel colour| <= rgb_tol per channel)

@@ -158,6 +158,7 @@ _SIGS = {
                            C.c_void_p, C.c_void_p],
     "reloc_debug_mfma_probe": [C.c_void_p, C.c_void_p, C.c_void_p],
     "reloc_debug_lane_probe": [C.c_void_p],
+    "reloc_valid_pixels": [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p],
     "reloc_debug_horn": [C.c_void_p, C.c_int32, C.c_void_p],
     "reloc_debug_div": [C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p],
     "reloc_debug_bf16": [C.c_void_p, C.c_int32, C.c_void_p],
@@ -537,6 +538,18 @@ def _dev_tensor(t, dtype, shape=None):
     if shape is not None and tuple(t.shape) != tuple(shape):
         raise ValueError(f"expected shape {tuple(shape)}, got {tuple(t.shape)}")
     return t.data_ptr()
+
+
+def valid_pixels(forest: "Forest", depth, rgb, K, stream=None):
+    """int32 GPU tensor of the indices v W + u of the frame's valid pixels
+    (depth in the forest's range), raster order (reloc_valid_pixels)."""
+    import torch
+    d, c, k = _frame(depth, rgb, K)
+    pix = torch.empty(int(depth.numel()), dtype=torch.int32, device=depth.device)
+    n = C.c_int32(0)
+    _check(lib().reloc_valid_pixels(forest.handle, d, c, C.byref(k), pix.data_ptr(), C.byref(n), _stream(stream)),
+           "reloc_valid_pixels")
+    return pix[:n.value]
 
 
 def pixel_features(forest: "Forest", depth, rgb, K, pix, with_fp32: bool = False, stream=None):

@@ -435,6 +435,83 @@ static int mlp_gradient(reloc_mlp *m, const uint16_t *X, const uint8_t *Y, const
     return RELOC_OK;
 }
 
+// Valid pixels of a frame (the depth test of the features and of the
+// relocaliser's pool) as indices v W + u in raster order: per block of
+// VP_BLOCK pixels a count, one workgroup's exclusive scan of the counts, then
+// each block's indices at its offset. Each of VP_THREADS threads takes
+// pixels t + j VP_THREADS of its block, so its wavefront's 64-pixel chunks
+// c = j (VP_THREADS / 64) + wave run in raster order.
+constexpr int VP_BLOCK = 1024, VP_THREADS = 256, VP_CH = VP_BLOCK / 64;
+
+__global__ void __launch_bounds__(VP_THREADS) k_valid_count(Frame fr, int P, int32_t *__restrict__ cnt)
+{
+    __shared__ int32_t wc[VP_THREADS / 64];
+    const int b = blockIdx.x, t = threadIdx.x;
+    int n = 0;
+    for (int j = 0; j < VP_BLOCK / VP_THREADS; ++j) {
+        const int p = b * VP_BLOCK + j * VP_THREADS + t;
+        n += __popcll(__ballot(p < P && valid_depth(fr, fr.depth[p])));
+    }
+    if (__lane_id() == 0) wc[t >> 6] = n;
+    __syncthreads();
+    if (t == 0) {
+        int s = 0;
+        for (int w = 0; w < VP_THREADS / 64; ++w) s += wc[w];
+        cnt[b] = s;
+    }
+}
+
+// exclusive scan of nb counts in place; the total to cnt[nb]
+__global__ void __launch_bounds__(1024) k_valid_scan(int32_t *__restrict__ cnt, int nb)
+{
+    __shared__ int32_t ws[16];
+    __shared__ int32_t carry;
+    const int lane = __lane_id(), wave = threadIdx.x >> 6;
+    if (threadIdx.x == 0) carry = 0;
+    __syncthreads();
+    for (int base = 0; base < nb; base += 1024) {
+        const int i = base + (int)threadIdx.x;
+        const int v = i < nb ? cnt[i] : 0;
+        int x = v;
+        for (int o = 1; o < 64; o <<= 1) {
+            const int y = __shfl_up(x, o, 64);
+            if (lane >= o) x += y;
+        }
+        if (lane == 63) ws[wave] = x;
+        __syncthreads();
+        int off = carry;
+        for (int w = 0; w < wave; ++w) off += ws[w];
+        __syncthreads();
+        if (i < nb) cnt[i] = off + x - v;
+        if (threadIdx.x == 1023) carry = off + x;
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) cnt[nb] = carry;
+}
+
+__global__ void __launch_bounds__(VP_THREADS) k_valid_emit(Frame fr, int P, const int32_t *__restrict__ off,
+                                                           int32_t *__restrict__ pix)
+{
+    __shared__ int32_t wc[VP_CH];
+    const int b = blockIdx.x, t = threadIdx.x, wave = t >> 6;
+    constexpr int J = VP_BLOCK / VP_THREADS;
+    bool ok[J];
+    uint64_t m[J];
+    for (int j = 0; j < J; ++j) {
+        const int p = b * VP_BLOCK + j * VP_THREADS + t;
+        ok[j] = p < P && valid_depth(fr, fr.depth[p]);
+        m[j] = __ballot(ok[j]);
+        if (__lane_id() == 0) wc[j * (VP_THREADS / 64) + wave] = __popcll(m[j]);
+    }
+    __syncthreads();
+    for (int j = 0; j < J; ++j) {
+        const int c = j * (VP_THREADS / 64) + wave;
+        int o = off[b];
+        for (int k = 0; k < c; ++k) o += wc[k];
+        if (ok[j]) pix[o + __popcll(m[j] & ((1ull << __lane_id()) - 1ull))] = b * VP_BLOCK + j * VP_THREADS + t;
+    }
+}
+
 static int mlp_pack(reloc_mlp *m, hipStream_t s)
 {
     RL_LAUNCH("k_mlp_pack", k_mlp_pack, dim3(16), dim3(256), 0, s, m->w, m->q);
@@ -615,6 +692,30 @@ extern "C" int reloc_pixel_features(reloc_forest *f, const uint16_t *depth_dev, 
     RL_LAUNCH("k_pixel_features", k_pixel_features, dim3((n + 127) / 128), dim3(128), 0, s, feat_args(f, fr), pix_dev,
               n, x_dev, xf_dev);
     RL_HIP(hipGetLastError());
+    return RELOC_OK;
+}
+
+extern "C" int reloc_valid_pixels(reloc_forest *f, const uint16_t *depth_dev, const uint8_t *rgb_dev,
+                                  const reloc_intrinsics *K, int32_t *pix_dev, int32_t *n_out, void *stream)
+{
+    if (!f || !pix_dev || !n_out) return RELOC_E_ARG;
+    Frame fr;
+    int rc = frame_from(f, depth_dev, rgb_dev, K, fr);
+    if (rc) return rc;
+    hipStream_t s = (hipStream_t)stream;
+    const int P = fr.W * fr.H, nb = (P + VP_BLOCK - 1) / VP_BLOCK;
+    int32_t *cnt = nullptr;
+    if (hipMalloc((void **)&cnt, (size_t)(nb + 1) * 4) != hipSuccess) return RELOC_E_NOMEM;
+    RL_LAUNCH("k_valid_count", k_valid_count, dim3(nb), dim3(VP_THREADS), 0, s, fr, P, cnt);
+    RL_LAUNCH("k_valid_scan", k_valid_scan, dim3(1), dim3(1024), 0, s, cnt, nb);
+    RL_LAUNCH("k_valid_emit", k_valid_emit, dim3(nb), dim3(VP_THREADS), 0, s, fr, P, cnt, pix_dev);
+    int32_t n = 0;
+    if (hipGetLastError() != hipSuccess || hipMemcpyAsync(&n, cnt + nb, 4, hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+        rc = RELOC_E_HIP;
+    (void)hipFree(cnt);
+    if (rc) return rc;
+    *n_out = n;
     return RELOC_OK;
 }
 

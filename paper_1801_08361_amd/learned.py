@@ -16,14 +16,7 @@ from typing import Callable, Iterable, Optional, Tuple
 
 import numpy as np
 
-from . import Forest, Mlp, label_pixels, pixel_features, verify
-
-
-def valid_pixels(depth, depth_min: int, depth_max: int):
-    """int32 device tensor of the pixel indices v W + u with depth in range."""
-    import torch
-    d = depth.reshape(-1).to(torch.int32)
-    return torch.nonzero((d >= depth_min) & (d <= depth_max)).reshape(-1).to(torch.int32).contiguous()
+from . import Forest, Mlp, label_pixels, pixel_features, valid_pixels, verify
 
 
 def frame_rows(forest: Forest, depth, rgb, K, pose, max_pixels: Optional[int] = None,
@@ -32,8 +25,7 @@ def frame_rows(forest: Forest, depth, rgb, K, pose, max_pixels: Optional[int] = 
     one posed frame, or of max_pixels of them drawn without replacement by a
     seeded numpy generator."""
     import torch
-    p = forest.params
-    pix = valid_pixels(depth, p.depth_min_mm, p.depth_max_mm)
+    pix = valid_pixels(forest, depth, rgb, K)
     if max_pixels is not None and pix.numel() > max_pixels:
         sel = np.sort(np.random.default_rng(seed).choice(pix.numel(), max_pixels, replace=False))
         pix = pix[torch.from_numpy(sel).to(pix.device)].contiguous()

@@ -84,6 +84,7 @@ def test_argument_errors_without_gpu():
     assert L.reloc_label_pixels(None, None, None, None, None, None, 0, None, None) == rl.E_ARG
     assert L.reloc_debug_mfma_probe(None, None, None) == rl.E_ARG
     assert L.reloc_debug_lane_probe(None) == rl.E_ARG
+    assert L.reloc_valid_pixels(None, None, None, None, None, None, None) == rl.E_ARG
     assert L.reloc_relocalise_learned(None, None, None, None, None, 0, 0, None, None) == rl.E_ARG
     for code in (0, 1, 2, 3, -1, -2, -3, -4, -5, 99):
         assert isinstance(rl.status_string(code), str)

@@ -88,6 +88,33 @@ def test_leaves_and_features_rendered(dev, size):
     assert (lg >= 0).any() and (lg < 0).sum() == (lo < 0).sum()
 
 
+@pytest.mark.parametrize("size", [(97, 61), (161, 97), (640, 480)])
+def test_valid_pixels_match_oracle(dev, size):
+    """reloc_valid_pixels lists exactly the pixels the oracle gives a leaf
+    (valid depth), in raster order, over several 1024-pixel blocks and a
+    ragged last one; depths on both ends of the range, out of range and all
+    invalid frames included."""
+    import paper_1801_08361_amd as rl
+    import torch
+    W, H = size
+    pp, po = pair(**SMALL)
+    g, o = make(pp, po)
+    sc = sr.small_scene(7, W, H)
+    d0, c0 = sc.render_query(3)
+    dn = d0.numpy().copy()
+    flat = dn.reshape(-1)
+    rng = np.random.default_rng(W)
+    for val in (0, pp.depth_min_mm - 1, pp.depth_min_mm, pp.depth_max_mm, pp.depth_max_mm + 1, 65535):
+        flat[rng.choice(flat.size, max(1, flat.size // 50), replace=False)] = val
+    d0 = torch.from_numpy(dn)
+    banner(f"valid pixels {W}x{H}")
+    for dd in (d0, torch.zeros_like(d0)):
+        d, c = to_dev(dd, c0, dev)
+        got = rl.valid_pixels(g, d, c, sc.K).cpu().numpy()
+        want = np.nonzero(o.leaves(dd.numpy(), c0.numpy(), sc.K)[0].reshape(-1) >= 0)[0]
+        assert np.array_equal(got, want)
+
+
 def test_leaves_special_thresholds(dev):
     pp, po = pair(n_trees=3, depth=6, reservoir_size=8)
     g, o = make(pp, po)
