@@ -788,19 +788,6 @@ __device__ __forceinline__ double xor_lane_f64(double v)
     return __longlong_as_double((long long)xor_lane64<M>((uint64_t)__double_as_longlong(v)));
 }
 
-// xor_lane64 for a wavefront-uniform M in {1, 2, 4, 8, 16, 32}
-__device__ __forceinline__ uint64_t xor_lane64_n(uint64_t v, int m)
-{
-    switch (m) {
-    case 1: return xor_lane64<1>(v);
-    case 2: return xor_lane64<2>(v);
-    case 4: return xor_lane64<4>(v);
-    case 8: return xor_lane64<8>(v);
-    case 16: return xor_lane64<16>(v);
-    default: return xor_lane64<32>(v);
-    }
-}
-
 // lane j's value (j wavefront-uniform)
 __device__ __forceinline__ uint64_t lane_u64(uint64_t v, int j)
 {

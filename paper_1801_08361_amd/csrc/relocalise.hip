@@ -2138,12 +2138,9 @@ __global__ void __launch_bounds__(64) k_lane_probe(uint32_t *out)
     out[8 * 64 + lane] = (uint32_t)row_up<4>((int)v);
     out[9 * 64 + lane] = (uint32_t)row_up<8>((int)v);
     const uint64_t w = ((uint64_t)(5000u + (uint32_t)lane) << 32) | v;
-    uint64_t x = 0;
-    for (int k = 0; k < 6; ++k) {   // (the offset is the same for every lane of a call)
-        const uint64_t y = xor_lane64_n(w, 1 << k);
-        if (lane % 6 == k) x = y;
-    }
-    out[10 * 64 + lane] = (uint32_t)(x >> 32);
+    const uint64_t y[6] = {xor_lane64<1>(w), xor_lane64<2>(w), xor_lane64<4>(w),
+                           xor_lane64<8>(w), xor_lane64<16>(w), xor_lane64<32>(w)};
+    out[10 * 64 + lane] = (uint32_t)(y[lane % 6] >> 32);
     out[11 * 64 + lane] = (uint32_t)(lane_u64(w, 37) >> 32);
 }
 
