@@ -1210,6 +1210,51 @@ __global__ void __launch_bounds__(64) k_b_refine_solve(const Attempt *__restrict
     }
 }
 
+// The attempt's result, from its final live list, into its slot of the
+// plan's results (mapped host memory); by one thread
+__device__ void finish_attempt(const Attempt &A)
+{
+    Result o;
+    for (int k = 0; k < 16; ++k) o.pose_c2w[k] = (k % 5 == 0) ? 1.0 : 0.0;
+    o.score = 0.0f;
+    o.pool_size = A.misc[0];
+    o.n_valid = A.misc[2];
+    // rounds run: the first r >= 1 that starts with at most one live
+    // hypothesis (none when no hypothesis is valid)
+    int nr = 0;
+    if (A.rl[0] >= 1) {
+        nr = 1;
+        while (nr < MAX_ROUNDS && A.rl[nr] > 1) ++nr;
+    }
+    o.n_rounds = nr;
+    o.final_hyp = -1;
+    o.mode_evals = A.stats[0];
+    o.pair_evals = A.stats[1];
+    if (o.pool_size == 0) {
+        o.status = RELOC_FAIL_NO_VALID_PIXELS;
+    } else if (o.n_valid == 0) {
+        o.status = *A.total_samples == 0ull ? RELOC_FAIL_NO_MODES : RELOC_FAIL_NO_HYPOTHESIS;
+    } else {
+        const int h = live_list(A, nr)[0];
+        const Hyp &hy = A.hyp[h];
+        for (int rr = 0; rr < 3; ++rr) {
+            for (int c = 0; c < 3; ++c) o.pose_c2w[rr * 4 + c] = hy.R[rr * 3 + c];
+            o.pose_c2w[rr * 4 + 3] = hy.t[rr];
+        }
+        o.score = (float)(A.sums[(int64_t)h * NSUM] / ((double)o.n_rounds * (double)A.B));
+        o.status = RELOC_OK;
+        o.final_hyp = h;
+    }
+    *A.result = o;
+}
+
+__global__ void __launch_bounds__(64) k_b_finish(const Attempt *__restrict__ att, Stage S)
+{
+    FOR_UNITS(S, u) {
+        if (threadIdx.x == 0) finish_attempt(att[u]);
+    }
+}
+
 // Cull and refinement of a small round (at most FUSED_LIVE live hypotheses
 // per attempt) in one kernel: one wavefront per survivor slot. Each
 // wavefront forms every live hypothesis's energy exactly as the cull does
@@ -1218,10 +1263,13 @@ __global__ void __launch_bounds__(64) k_b_refine_solve(const Attempt *__restrict
 // entry of the next live list and refines it; the wavefront of slot 0 also
 // writes the round's trace, statistics and survivor count. The lists are
 // double-buffered by round parity, so no wavefront overwrites what another
-// reads.
+// reads. With `fin` (the plan's last round, a lone attempt) lane 0 of slot 0
+// then writes the attempt's result too, after its own refinement (all that
+// the result reads was written by that lane or by earlier launches), in
+// place of a separate finishing launch.
 constexpr int FUSED_LIVE = 64;    // live hypotheses per attempt up to which a round culls in its refinement
 
-__global__ void __launch_bounds__(64) k_b_cull_refine(const Attempt *__restrict__ att, Stage S, int r)
+__global__ void __launch_bounds__(64) k_b_cull_refine(const Attempt *__restrict__ att, Stage S, int r, int fin)
 {
     FOR_UNITS(S, u) {
         const int a = attempt_of(S, u);
@@ -1237,7 +1285,11 @@ __global__ void __launch_bounds__(64) k_b_cull_refine(const Attempt *__restrict_
         const int ng = (A.B + GROUP - 1) / GROUP;
         // the group sums in group order, 64 loads at a time
         const float Ssum = group_total<64>(A.gs, apl, ng, A.N);
-        if (!round_active(A, r)) continue;
+        const bool last = fin && sidx == 0;
+        if (!round_active(A, r)) {
+            if (last && lane == 0) finish_attempt(A);
+            continue;
+        }
         const int keep = (na + 1) / 2;
         if (sidx >= keep) continue;
         const bool live = lane < na;
@@ -1271,46 +1323,7 @@ __global__ void __launch_bounds__(64) k_b_cull_refine(const Attempt *__restrict_
         double sm[NSUM];
         refine_sums_at(A, r, h, ap, sm);
         if (lane == 0) refine_solve_of(A, sidx, h, sm);
-    }
-}
-
-__global__ void __launch_bounds__(64) k_b_finish(const Attempt *__restrict__ att, Stage S)
-{
-    FOR_UNITS(S, u) {
-        if (threadIdx.x != 0) continue;
-        const Attempt &A = att[u];
-        Result o;
-        for (int k = 0; k < 16; ++k) o.pose_c2w[k] = (k % 5 == 0) ? 1.0 : 0.0;
-        o.score = 0.0f;
-        o.pool_size = A.misc[0];
-        o.n_valid = A.misc[2];
-        // rounds run: the first r >= 1 that starts with at most one live
-        // hypothesis (none when no hypothesis is valid)
-        int nr = 0;
-        if (A.rl[0] >= 1) {
-            nr = 1;
-            while (nr < MAX_ROUNDS && A.rl[nr] > 1) ++nr;
-        }
-        o.n_rounds = nr;
-        o.final_hyp = -1;
-        o.mode_evals = A.stats[0];
-        o.pair_evals = A.stats[1];
-        if (o.pool_size == 0) {
-            o.status = RELOC_FAIL_NO_VALID_PIXELS;
-        } else if (o.n_valid == 0) {
-            o.status = *A.total_samples == 0ull ? RELOC_FAIL_NO_MODES : RELOC_FAIL_NO_HYPOTHESIS;
-        } else {
-            const int h = live_list(A, nr)[0];
-            const Hyp &hy = A.hyp[h];
-            for (int rr = 0; rr < 3; ++rr) {
-                for (int c = 0; c < 3; ++c) o.pose_c2w[rr * 4 + c] = hy.R[rr * 3 + c];
-                o.pose_c2w[rr * 4 + 3] = hy.t[rr];
-            }
-            o.score = (float)(A.sums[(int64_t)h * NSUM] / ((double)o.n_rounds * (double)A.B));
-            o.status = RELOC_OK;
-            o.final_hyp = h;
-        }
-        *A.result = o;
+        if (last && lane == 0) finish_attempt(A);
     }
 }
 
@@ -1601,6 +1614,7 @@ static int enqueue(const Plan *pl, const Sched &sc, const Stages &st, hipStream_
     RL_LAUNCH("k_b_alive_init", k_b_alive_init, dim3(grid_of(att, cap, 0)), dim3(1024), 0, s, d, att);
     const int nw = score_waves(pl->tm_max);
     const size_t smem = (size_t)nw * pl->tm_max * SMODE * sizeof(float);
+    bool finished = false;
     for (int r = 0; r < pl->rounds; ++r) {
         if (tm) tm->begin(1 + r, s);
         if (sc.su == 4)
@@ -1611,8 +1625,11 @@ static int enqueue(const Plan *pl, const Sched &sc, const Stages &st, hipStream_
                       s, d, st.score[r], r, sc.dpu[r], pl->tm_max);
         if (tm) tm->end(1 + r, s);
         if (r >= pl->fused_from && st.refine[r].total <= FUSED_REFINE) {
+            // a lone attempt's last round also writes its result
+            const int fin = (pl->n == 1 && r == pl->rounds - 1) ? 1 : 0;
             RL_LAUNCH("k_b_cull_refine", k_b_cull_refine, dim3(grid_of(st.refine[r], 0, sc.xcd)), dim3(64), 0, s, d,
-                      st.refine[r], r);
+                      st.refine[r], r, fin);
+            finished |= fin != 0;
             continue;
         }
         RL_LAUNCH("k_b_cull", k_b_cull, dim3(grid_of(att, cap, 0)), dim3(CULL_THREADS), 0, s, d, att, r);
@@ -1626,7 +1643,7 @@ static int enqueue(const Plan *pl, const Sched &sc, const Stages &st, hipStream_
                       d, st.solve[r], r);
         }
     }
-    RL_LAUNCH("k_b_finish", k_b_finish, dim3(grid_of(att, cap, 0)), dim3(64), 0, s, d, att);
+    if (!finished) RL_LAUNCH("k_b_finish", k_b_finish, dim3(grid_of(att, cap, 0)), dim3(64), 0, s, d, att);
     RL_HIP(hipGetLastError());
     return RELOC_OK;
 }
