@@ -251,7 +251,8 @@ def rooflines(kernels, res, attempts, batch_pixels=500, batched=False):
     # first round whose planned live count (N halved r times) is at most
     # FUSED_LIVE for every attempt, the cull runs inside the refinement
     # (k_b_cull_refine) while the batch's planned survivors are at most
-    # FUSED_REFINE; otherwise k_b_cull, then k_b_refine, or k_b_refine_sums
+    # FUSED_REFINE; otherwise a cull (k_b_cull_rank or k_b_cull), then
+    # k_b_refine, or k_b_refine_sums
     # and k_b_refine_solve past FUSED_REFINE survivors. A plain call is a
     # batch of one.
     def bound(n_hyp, k):

@@ -15,9 +15,11 @@
 //    stages the draw's modes once in LDS and reads them back as broadcasts
 //    while every lane evaluates its own pose; energies are summed per group
 //    of 8 draws in draw order and the group sums go to memory;
-//  - cull: one workgroup per attempt adds the group sums in group order,
-//    sorts the live hypotheses by (energy, index) in LDS and keeps the first
-//    half, rounded up;
+//  - cull: the group sums are added in group order and the live hypotheses
+//    ordered by (energy, index); the first half, rounded up, survives. Rounds
+//    of at most 1024 live hypotheses (in batches needing few workgroups) rank
+//    each key by counting the smaller ones, a workgroup per 64 keys; other
+//    rounds sort the keys in LDS, one workgroup per attempt;
 //  - refinement: one wavefront per survivor sums its inliers of the round
 //    (lanes over draws, xor butterfly) into its running sums and the pose is
 //    re-aligned from them (Horn's method, FP64), by lane 0 of that wavefront
@@ -296,90 +298,74 @@ __global__ void __launch_bounds__(POOL_BLOCK / PB_PIX) k_b_pack(const Attempt *_
     }
 }
 
-// per attempt: exclusive scans of the block counts and weights, pool size,
-// and the attempt's counters reset
-__global__ void __launch_bounds__(1024) k_b_pool_scan(const Attempt *__restrict__ att, Stage S)
-{
-    __shared__ int32_t wsum[16];
-    __shared__ unsigned long long wsumw[16];
-    __shared__ int32_t carry;
-    __shared__ unsigned long long carryw;
-    const int lane = __lane_id(), wave = threadIdx.x / 64;
-    FOR_UNITS(S, u) {
-        const Attempt &A = att[u];
-        const int nb = (A.P + POOL_BLOCK - 1) / POOL_BLOCK;
-        if (threadIdx.x == 0) {
-            carry = 0;
-            carryw = 0ull;
-        }
-        __syncthreads();
-        for (int base = 0; base < nb; base += 1024) {
-            const int i = base + (int)threadIdx.x;
-            const int v = i < nb ? A.blockcnt[i] : 0;
-            const unsigned long long vw = (i < nb && A.weights) ? A.blockw[i] : 0ull;
-            int x = v;
-            for (int o = 1; o < 64; o <<= 1) {
-                int y = __shfl_up(x, o, 64);
-                if (lane >= o) x += y;
-            }
-            unsigned long long xw = wave_incl_scan_u64(vw);
-            if (lane == 63) {
-                wsum[wave] = x;
-                wsumw[wave] = xw;
-            }
-            __syncthreads();
-            int woff = 0;
-            unsigned long long woffw = 0ull;
-            for (int w = 0; w < wave; ++w) {
-                woff += wsum[w];
-                woffw += wsumw[w];
-            }
-            const int excl = carry + woff + x - v;
-            const unsigned long long exclw = carryw + woffw + xw - vw;
-            __syncthreads();
-            if (i < nb) {
-                A.blockcnt[i] = excl;
-                if (A.weights) A.blockw[i] = exclw;
-            }
-            if (threadIdx.x == 1023) {
-                carry = excl + v;
-                carryw = exclw + vw;
-            }
-            __syncthreads();
-        }
-        if (threadIdx.x == 0) {
-            if (A.weights) {
-                // the guide table's parameters (no buckets without weight)
-                const unsigned long long tot = carryw;
-                const unsigned long long G = tot < (unsigned long long)carry ? tot : (unsigned long long)carry;
-                const unsigned long long M = G ? guide_multiplier(G, tot) : 0ull;
-                A.gsel[0] = tot;
-                A.gsel[1] = M;
-                A.gsel[2] = tot ? (unsigned long long)guide_bucket(tot - 1ull, M) + 1ull : 0ull;
-            }
-            A.misc[0] = carry;
-            A.misc[2] = 0;
-            A.stats[0] = 0ull;
-            A.stats[1] = 0ull;
-            A.stats[2] = 0ull;
-        }
-        __syncthreads();
-    }
-}
-
-// (POOL_BLOCK / PB_PIX threads per block, as k_b_pack: the block's 64-pixel
-// chunks c = j (POOL_BLOCK / PB_PIX / 64) + wave, counted and summed in chunk
-// order, which is raster order)
+// unit = block of POOL_BLOCK pixels: its valid pixels' indices into the
+// pool (valid pixels in raster order) and, with pick weights, their inclusive
+// weight prefix and guide-table entries. Each block adds up the counts and
+// weight sums of the blocks before it and of all blocks itself (integer
+// sums, exact in any order), so no separate scan launch is needed; block 0
+// stores the pool size and the guide table's parameters and resets the
+// attempt's counters. (POOL_BLOCK / PB_PIX threads per block, as k_b_pack:
+// the block's 64-pixel chunks c = j (POOL_BLOCK / PB_PIX / 64) + wave,
+// counted and summed in chunk order, which is raster order.)
 __global__ void __launch_bounds__(POOL_BLOCK / PB_PIX) k_b_pool_write(const Attempt *__restrict__ att, Stage S)
 {
     constexpr int NT = POOL_BLOCK / PB_PIX, NC = POOL_BLOCK / 64;
     __shared__ int32_t wcnt[NC];
     __shared__ unsigned long long wsw[NC];
+    __shared__ unsigned long long s_part[4][NT / 64];
     const int tid = (int)threadIdx.x, wave = tid >> 6;
     FOR_UNITS(S, u) {
         const int a = attempt_of(S, u);
         const Attempt &A = att[a];
         const int b = u - S.off[a];
+        const int nb = (A.P + POOL_BLOCK - 1) / POOL_BLOCK;
+        // the blocks' counts and weight sums: before this block, and in all
+        unsigned long long pc = 0ull, pw = 0ull, tc = 0ull, tw = 0ull;
+        for (int i = tid; i < nb; i += NT) {
+            const unsigned long long c = (unsigned long long)A.blockcnt[i];
+            const unsigned long long w = A.weights ? A.blockw[i] : 0ull;
+            tc += c;
+            tw += w;
+            if (i < b) {
+                pc += c;
+                pw += w;
+            }
+        }
+        for (int o = 32; o > 0; o >>= 1) {
+            pc += __shfl_xor(pc, o, 64);
+            pw += __shfl_xor(pw, o, 64);
+            tc += __shfl_xor(tc, o, 64);
+            tw += __shfl_xor(tw, o, 64);
+        }
+        if (__lane_id() == 0) {
+            s_part[0][wave] = pc;
+            s_part[1][wave] = pw;
+            s_part[2][wave] = tc;
+            s_part[3][wave] = tw;
+        }
+        __syncthreads();
+        unsigned long long blk_c = 0ull, blk_w = 0ull, tot_c = 0ull, tot_w = 0ull;
+        for (int w = 0; w < NT / 64; ++w) {
+            blk_c += s_part[0][w];
+            blk_w += s_part[1][w];
+            tot_c += s_part[2][w];
+            tot_w += s_part[3][w];
+        }
+        // the guide table's multiplier (no buckets without weight)
+        const unsigned long long G = tot_w < tot_c ? tot_w : tot_c;
+        const unsigned long long gM = (A.weights && G) ? guide_multiplier(G, tot_w) : 0ull;
+        if (b == 0 && tid == 0) {
+            if (A.weights) {
+                A.gsel[0] = tot_w;
+                A.gsel[1] = gM;
+                A.gsel[2] = tot_w ? (unsigned long long)guide_bucket(tot_w - 1ull, gM) + 1ull : 0ull;
+            }
+            A.misc[0] = (int32_t)tot_c;
+            A.misc[2] = 0;
+            A.stats[0] = 0ull;
+            A.stats[1] = 0ull;
+            A.stats[2] = 0ull;
+        }
         uint32_t dep[PB_PIX];
 #pragma unroll
         for (int j = 0; j < PB_PIX; ++j) {
@@ -409,8 +395,8 @@ __global__ void __launch_bounds__(POOL_BLOCK / PB_PIX) k_b_pool_write(const Atte
         for (int j = 0; j < PB_PIX; ++j) {
             const int p = b * POOL_BLOCK + j * NT + tid;
             const int c = j * (NT / 64) + wave;
-            int off = A.blockcnt[b];
-            unsigned long long offw = A.weights ? A.blockw[b] : 0ull;
+            int off = (int)blk_c;
+            unsigned long long offw = blk_w;
             for (int k = 0; k < c; ++k) {
                 off += wcnt[k];
                 offw += wsw[k];
@@ -423,7 +409,7 @@ __global__ void __launch_bounds__(POOL_BLOCK / PB_PIX) k_b_pool_write(const Atte
                     A.cdf[idx] = c1;
                     if (w[j]) {
                         // the buckets whose first draw lies in [c0, c1)
-                        const unsigned long long M = A.gsel[1];
+                        const unsigned long long M = gM;
                         const uint32_t g1 = guide_bucket(c1 - 1ull, M);
                         for (uint32_t g = c0 ? guide_bucket(c0 - 1ull, M) + 1u : 0u; g <= g1; ++g) A.guide[g] = idx;
                     }
@@ -895,6 +881,69 @@ __global__ void __launch_bounds__(CULL_THREADS) k_b_cull(const Attempt *__restri
     FOR_UNITS(S, u) {
         const Attempt &A = att[u];
         if (round_active(A, r)) cull_round(A, r, keys);
+    }
+}
+
+// The same cull with ranks counted instead of sorted, for rounds of at most
+// RANK_MAX live hypotheses: unit = (attempt, block of 64 live positions).
+// Every workgroup forms all of the round's keys in LDS as cull_round does,
+// then ranks its block's keys, 16 threads per key, each counting the smaller
+// keys among every 16th one (the counts added across the 16 lanes). Keys are
+// distinct, so a key's rank is its position in cull_round's sorted order: the
+// survivors, their order, positions and energies are the same. The work is
+// spread over a workgroup per 64 live hypotheses instead of one per attempt,
+// and there is no sorting network.
+constexpr int RANK_MAX = 1024;
+constexpr int RANK_UNITS = 64;   // rank workgroups of a round up to which it culls by ranks
+
+__global__ void __launch_bounds__(CULL_THREADS) k_b_cull_rank(const Attempt *__restrict__ att, Stage S, int r)
+{
+    __shared__ unsigned long long keys[RANK_MAX];
+    FOR_UNITS(S, u) {
+        const int a = attempt_of(S, u);
+        const Attempt &A = att[a];
+        const int blk = u - S.off[a];
+        const int na = A.rl[r];
+        // (uniform over the workgroup: the round did not run, or the block
+        // lies past the live list)
+        if (!round_active(A, r) || blk * 64 >= na) continue;
+        __syncthreads();   // the previous unit's reads of `keys` are done
+        const int32_t *al = live_list(A, r);
+        const float *en = live_energy(A, r);
+        const int ng = (A.B + GROUP - 1) / GROUP;
+        for (int ap = (int)threadIdx.x; ap < na; ap += CULL_THREADS)
+            keys[ap] = cull_key(en[ap] + group_total<32>(A.gs, ap, ng, A.N), al[ap], ap);
+        __syncthreads();
+        const int i = blk * 64 + (int)(threadIdx.x >> 4), sl = (int)(threadIdx.x & 15);
+        const unsigned long long key = keys[i < na ? i : na - 1];
+        uint32_t cnt = 0;
+        for (int q = sl; q < na; q += 16) cnt += keys[q] < key ? 1u : 0u;
+        // every lane is active here (the 16 lanes of a key form one DPP row)
+        cnt += xor_lane<8>(cnt);
+        cnt += xor_lane<4>(cnt);
+        cnt += xor_lane<2>(cnt);
+        cnt += xor_lane<1>(cnt);
+        const int keep = (na + 1) / 2;
+        if (sl == 0 && i < na) {
+            const int h = (int)((key >> 12) & 0xFFFFFull);
+            const float E = key_float((uint32_t)(key >> 32));
+            if (r < MAX_ROUNDS) {
+                A.tr_alive[r * A.N + i] = h;
+                A.tr_energy[r * A.N + i] = E;
+            }
+            if ((int)cnt < keep) {
+                live_list(A, r + 1)[cnt] = h;
+                A.pos[cnt] = i;
+                live_energy(A, r + 1)[cnt] = E;
+            }
+        }
+        if (blk == 0 && threadIdx.x == 0) {
+            if (r < MAX_ROUNDS) A.tr_n_alive[r] = na;
+            A.stats[0] += (unsigned long long)na * A.stats[2];
+            A.stats[1] += (unsigned long long)na * (unsigned long long)A.B;
+            A.stats[2] = 0ull;
+            A.rl[r + 1] = keep;
+        }
     }
 }
 
@@ -1465,15 +1514,15 @@ __global__ void __launch_bounds__(256) k_b_desc(const uint2 *__restrict__ src, u
 // stages of one schedule in launch order
 struct Stages {
     Stage pix, pb, att, hyp, wts;
-    std::vector<Stage> score, refine, solve;
+    std::vector<Stage> score, refine, solve, cull;
 };
 
 // host offsets of every stage for schedule `sc`: pix, pb, att, hyp, wts, then
-// per round (score, refine, solve)
+// per round (score, refine, solve, cull by ranks)
 static std::vector<int32_t> offsets(const Plan *pl, const Sched &sc)
 {
     const int n = pl->n, R = pl->rounds;
-    const int n_stage = 5 + 3 * R;
+    const int n_stage = 5 + 4 * R;
     std::vector<int32_t> off((size_t)n_stage * (n + 1), 0);
     auto fill = [&](int k, auto units) {
         int32_t *o = off.data() + (size_t)k * (n + 1);
@@ -1496,12 +1545,13 @@ static std::vector<int32_t> offsets(const Plan *pl, const Sched &sc)
         return bnd;
     };
     for (int r = 0; r < R; ++r) {
-        fill(5 + 3 * r, [&](int a) {
+        fill(5 + 4 * r, [&](int a) {
             if (r >= rounds_for(pl->shape[a].N)) return 0;
             return ((bound(a, r) + 63) / 64) * ((pl->shape[a].B + sc.dpu[r] - 1) / sc.dpu[r]);
         });
-        fill(6 + 3 * r, [&](int a) { return r >= rounds_for(pl->shape[a].N) ? 0 : bound(a, r + 1); });
-        fill(7 + 3 * r, [&](int a) { return r >= rounds_for(pl->shape[a].N) ? 0 : (bound(a, r + 1) + 63) / 64; });
+        fill(6 + 4 * r, [&](int a) { return r >= rounds_for(pl->shape[a].N) ? 0 : bound(a, r + 1); });
+        fill(7 + 4 * r, [&](int a) { return r >= rounds_for(pl->shape[a].N) ? 0 : (bound(a, r + 1) + 63) / 64; });
+        fill(8 + 4 * r, [&](int a) { return r >= rounds_for(pl->shape[a].N) ? 0 : (bound(a, r) + 63) / 64; });
     }
     return off;
 }
@@ -1520,9 +1570,10 @@ static Stages stages_of(const Plan *pl, const Sched &sc, const int32_t *d_off, c
     Stages st;
     st.pix = mk(0); st.pb = mk(1); st.att = mk(2); st.hyp = mk(3); st.wts = mk(4);
     for (int r = 0; r < pl->rounds; ++r) {
-        st.score.push_back(mk(5 + 3 * r));
-        st.refine.push_back(mk(6 + 3 * r));
-        st.solve.push_back(mk(7 + 3 * r));
+        st.score.push_back(mk(5 + 4 * r));
+        st.refine.push_back(mk(6 + 4 * r));
+        st.solve.push_back(mk(7 + 4 * r));
+        st.cull.push_back(mk(8 + 4 * r));
     }
     return st;
 }
@@ -1604,7 +1655,6 @@ static int enqueue(const Plan *pl, const Sched &sc, const Stages &st, hipStream_
     if (st.wts.total > 0)
         RL_LAUNCH("k_b_weights", k_b_weights, dim3(grid_of(st.wts, cap / WT_WAVES, sc.xcd)), dim3(64 * WT_WAVES), 0,
                   s, d, st.wts);
-    RL_LAUNCH("k_b_pool_scan", k_b_pool_scan, dim3(grid_of(att, cap, 0)), dim3(1024), 0, s, d, att);
     RL_LAUNCH("k_b_pool_write", k_b_pool_write, dim3(grid_of(st.pb, cap, sc.xcd)), dim3(POOL_BLOCK / PB_PIX), 0, s, d,
               st.pb);
     if (pl->m_max > 32)
@@ -1614,6 +1664,18 @@ static int enqueue(const Plan *pl, const Sched &sc, const Stages &st, hipStream_
     RL_LAUNCH("k_b_alive_init", k_b_alive_init, dim3(grid_of(att, cap, 0)), dim3(1024), 0, s, d, att);
     const int nw = score_waves(pl->tm_max);
     const size_t smem = (size_t)nw * pl->tm_max * SMODE * sizeof(float);
+    // a round culls by ranks when every attempt's live list fits RANK_MAX and
+    // the round needs few rank workgroups (each one reads all of its
+    // attempt's group sums); otherwise by one sorting workgroup per attempt
+    auto rank_cull = [&](int r) {
+        if (st.cull[r].total > RANK_UNITS) return false;
+        for (const Shape &sh : pl->shape) {
+            int bnd = sh.N;
+            for (int k = 0; k < r; ++k) bnd = (bnd + 1) / 2;
+            if (bnd > RANK_MAX) return false;
+        }
+        return true;
+    };
     bool finished = false;
     for (int r = 0; r < pl->rounds; ++r) {
         if (tm) tm->begin(1 + r, s);
@@ -1632,7 +1694,11 @@ static int enqueue(const Plan *pl, const Sched &sc, const Stages &st, hipStream_
             finished |= fin != 0;
             continue;
         }
-        RL_LAUNCH("k_b_cull", k_b_cull, dim3(grid_of(att, cap, 0)), dim3(CULL_THREADS), 0, s, d, att, r);
+        if (rank_cull(r))
+            RL_LAUNCH("k_b_cull_rank", k_b_cull_rank, dim3(grid_of(st.cull[r], 0, sc.xcd)), dim3(CULL_THREADS), 0, s,
+                      d, st.cull[r], r);
+        else
+            RL_LAUNCH("k_b_cull", k_b_cull, dim3(grid_of(att, cap, 0)), dim3(CULL_THREADS), 0, s, d, att, r);
         if (st.refine[r].total <= FUSED_REFINE) {
             RL_LAUNCH("k_b_refine", k_b_refine, dim3(grid_of(st.refine[r], 0, sc.xcd)), dim3(64), 0, s, d,
                       st.refine[r], r);
