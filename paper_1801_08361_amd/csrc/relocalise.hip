@@ -1105,9 +1105,9 @@ __global__ void __launch_bounds__(64 * GROUP) k_b_score(const Attempt *__restric
 }
 
 // Refinement of the survivors of round r. A survivor's inliers of the round
-// are summed by one wavefront: lane-strided in draw order, combined by an xor
-// butterfly (every lane ends with the same sums); lane 0 adds them to the
-// survivor's running sums. With refinement on, the pose is then re-solved
+// are summed by one wavefront: lane-strided in draw order, combined with the
+// values of an xor butterfly (each total then sits in its own lane, which
+// adds it to the survivor's running sum and stores it). With refinement on, the pose is then re-solved
 // from the running sums (Kabsch on all of its inliers so far). Small rounds
 // run both steps in one kernel (the solve on lane 0 of each wavefront); large
 // rounds (batches) solve in a second kernel with one lane per survivor, so
@@ -1116,14 +1116,63 @@ __global__ void __launch_bounds__(64 * GROUP) k_b_score(const Attempt *__restric
 constexpr int RB = 8;              // draws per lane per load batch in refinement
 constexpr int FUSED_REFINE = 1024; // survivors up to which a round refines in one kernel
 
+// The lane-sum combination below is the xor butterfly (offsets 32, 16, ...,
+// 1) with every lane keeping only the values it still needs (a
+// reduce-scatter): at offset o the lanes with bit o clear keep the first half
+// of their values and the others the second half, and each kept value is the
+// lane's own plus its partner's, exactly as in the full butterfly (whose
+// lanes all end with the same totals). Lane L ends with the total of sum
+// rs_sum_of(L) (-1: a padding slot); lane rs_lane_of(k) holds sum k.
+__host__ __device__ constexpr int rs_sum_of(int L)
+{
+    // 22 sums -> 11 (offset 32) -> 12 with one zero -> 6 (16) -> 3 (8) -> 4
+    // with one zero -> 2 (4) -> 1 (2); offset 1 adds the last pair whole
+    return (((L >> 1) & 1) + 2 * ((L >> 2) & 1) < 3 &&
+            ((L >> 1) & 1) + 2 * ((L >> 2) & 1) + 3 * ((L >> 3) & 1) + 6 * ((L >> 4) & 1) < 11)
+               ? ((L >> 1) & 1) + 2 * ((L >> 2) & 1) + 3 * ((L >> 3) & 1) + 6 * ((L >> 4) & 1) + 11 * ((L >> 5) & 1)
+               : -1;
+}
+__host__ __device__ constexpr int rs_lane_of(int k)
+{
+    return (k >= 11 ? 32 : 0) + ((k % 11) >= 6 ? 16 : 0) + (((k % 11) % 6) >= 3 ? 8 : 0) +
+           ((((k % 11) % 6) % 3) >= 2 ? 4 : 0) + ((((k % 11) % 6) % 3) % 2 == 1 ? 2 : 0);
+}
+static_assert(NSUM == 22, "the reduce-scatter below is laid out for 22 sums");
+
+// one reduce-scatter step at offset M: lanes with bit M clear return a plus
+// their partner's a, the others their partner's b plus b
+template <int M>
+__device__ __forceinline__ double rs_pair(double a, double b)
+{
+    if constexpr (M == 32 || M == 16) {
+        // gfx950 permlane swaps: the upper half (M = 32) or the odd rows of
+        // 16 (M = 16) of the first operand trade places with the lower half
+        // or even rows of the second, which is each lane's partner exchange
+        const uint64_t ai = (uint64_t)__double_as_longlong(a), bi = (uint64_t)__double_as_longlong(b);
+        const auto lo = M == 32 ? __builtin_amdgcn_permlane32_swap((uint32_t)ai, (uint32_t)bi, false, false)
+                                : __builtin_amdgcn_permlane16_swap((uint32_t)ai, (uint32_t)bi, false, false);
+        const auto hi = M == 32 ? __builtin_amdgcn_permlane32_swap((uint32_t)(ai >> 32), (uint32_t)(bi >> 32), false, false)
+                                : __builtin_amdgcn_permlane16_swap((uint32_t)(ai >> 32), (uint32_t)(bi >> 32), false, false);
+        const double p0 = __longlong_as_double((long long)(((uint64_t)(uint32_t)hi[0] << 32) | (uint32_t)lo[0]));
+        const double p1 = __longlong_as_double((long long)(((uint64_t)(uint32_t)hi[1] << 32) | (uint32_t)lo[1]));
+        return p0 + p1;
+    } else {
+        const bool up = (__lane_id() & M) != 0;
+        const double keep = up ? b : a, send = up ? a : b;
+        return keep + xor_lane_f64<M>(send);
+    }
+}
+
 // this round's inlier sums of hypothesis h (scored at live position ap),
-// added to its running sums (every lane ends with the totals; lane 0 stores
-// them)
+// added to its running sums and stored; s receives the totals (wavefront-
+// uniform values)
 __device__ __forceinline__ void refine_sums_at(const Attempt &A, int r, int h, int ap, double s[NSUM])
 {
     const int lane = __lane_id();
-    // the running sums, one per lane, fetched while this round's are formed
-    const double runk = lane < NSUM ? A.sums[(int64_t)h * NSUM + lane] : 0.0;
+    const int mine = rs_sum_of(lane);
+    // the running sum of the lane's own total, fetched while this round's are
+    // formed
+    const double runk = mine >= 0 ? A.sums[(int64_t)h * NSUM + mine] : 0.0;
 #pragma unroll
     for (int k = 0; k < NSUM; ++k) s[k] = 0.0;
     // lane-strided draws, RB per lane at a time: all inlier ids first, then the
@@ -1155,26 +1204,24 @@ __device__ __forceinline__ void refine_sums_at(const Attempt &A, int r, int h, i
         for (int k = 0; k < RB; ++k)
             if (gid[k] >= 0) sums_add_point(s, c[k], w[k]);
     }
-    // xor butterfly over the lanes (offsets 32, 16, ..., 1)
+    // reduce-scatter of the 64 lane sums (every lane active)
+    double w11[12], x6[6], y4[4], z2[2];
 #pragma unroll
-    for (int k = 0; k < NSUM; ++k) s[k] = s[k] + xor_lane_f64<32>(s[k]);
+    for (int i = 0; i < 11; ++i) w11[i] = rs_pair<32>(s[i], s[i + 11]);
+    w11[11] = 0.0;
 #pragma unroll
-    for (int k = 0; k < NSUM; ++k) s[k] = s[k] + xor_lane_f64<16>(s[k]);
+    for (int i = 0; i < 6; ++i) x6[i] = rs_pair<16>(w11[i], w11[i + 6]);
 #pragma unroll
-    for (int k = 0; k < NSUM; ++k) s[k] = s[k] + xor_lane_f64<8>(s[k]);
+    for (int i = 0; i < 3; ++i) y4[i] = rs_pair<8>(x6[i], x6[i + 3]);
+    y4[3] = 0.0;
 #pragma unroll
-    for (int k = 0; k < NSUM; ++k) s[k] = s[k] + xor_lane_f64<4>(s[k]);
+    for (int i = 0; i < 2; ++i) z2[i] = rs_pair<4>(y4[i], y4[i + 2]);
+    double u = rs_pair<2>(z2[0], z2[1]);
+    u = u + xor_lane_f64<1>(u);
+    const double tot = runk + u;
+    if (mine >= 0 && (lane & 1) == 0) A.sums[(int64_t)h * NSUM + mine] = tot;
 #pragma unroll
-    for (int k = 0; k < NSUM; ++k) s[k] = s[k] + xor_lane_f64<2>(s[k]);
-#pragma unroll
-    for (int k = 0; k < NSUM; ++k) s[k] = s[k] + xor_lane_f64<1>(s[k]);
-#pragma unroll
-    for (int k = 0; k < NSUM; ++k) s[k] = lane_f64(runk, k) + s[k];
-    if (lane == 0) {
-        double *run = A.sums + (int64_t)h * NSUM;
-#pragma unroll
-        for (int k = 0; k < NSUM; ++k) run[k] = s[k];
-    }
+    for (int k = 0; k < NSUM; ++k) s[k] = lane_f64(tot, rs_lane_of(k));
 }
 
 // the same for survivor position sidx of round r; returns the hypothesis index
