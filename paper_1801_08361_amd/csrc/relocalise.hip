@@ -1163,10 +1163,34 @@ __device__ __forceinline__ double rs_pair(double a, double b)
     }
 }
 
-// this round's inlier sums of hypothesis h (scored at live position ap),
-// added to its running sums and stored; s receives the totals (wavefront-
-// uniform values)
-__device__ __forceinline__ void refine_sums_at(const Attempt &A, int r, int h, int ap, double s[NSUM])
+// one batch of RB draws per lane of live position ap's round-r inliers: the
+// inlier ids (global mode index, -1: not an inlier) and the draws' camera
+// points
+struct RefBatch {
+    int32_t gid[RB];
+    float4 dr[RB];
+};
+
+__device__ __forceinline__ void refine_batch_load(const Attempt &A, int r, int ap, int base, RefBatch &q)
+{
+    const int lane = __lane_id();
+#pragma unroll
+    for (int k = 0; k < RB; ++k) {
+        const int i = base + k * 64 + lane;
+        q.gid[k] = i < A.B ? A.inl[inl_at(A, i, ap)] : -1;
+    }
+#pragma unroll
+    for (int k = 0; k < RB; ++k) {
+        const int i = base + k * 64 + lane;
+        q.dr[k] = i < A.B ? A.draws[(int64_t)r * A.B + i] : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    }
+}
+
+// this round's inlier sums of hypothesis h (scored at live position ap), its
+// first batch already loaded, added to its running sums and stored; s
+// receives the totals (wavefront-uniform values)
+__device__ __forceinline__ void refine_sums_pre(const Attempt &A, int r, int h, int ap, const RefBatch &q0,
+                                                double s[NSUM])
 {
     const int lane = __lane_id();
     const int mine = rs_sum_of(lane);
@@ -1178,31 +1202,23 @@ __device__ __forceinline__ void refine_sums_at(const Attempt &A, int r, int h, i
     // lane-strided draws, RB per lane at a time: all inlier ids first, then the
     // camera points and mode means of the inliers, then the sums in draw order
     for (int base = 0; base < A.B; base += 64 * RB) {
-        int32_t gid[RB];
-#pragma unroll
-        for (int k = 0; k < RB; ++k) {
-            const int i = base + k * 64 + lane;
-            gid[k] = i < A.B ? A.inl[inl_at(A, i, ap)] : -1;
-        }
-        // the draws' camera points load with the ids, the inliers' means after
-        float4 dr[RB];
-#pragma unroll
-        for (int k = 0; k < RB; ++k) {
-            const int i = base + k * 64 + lane;
-            dr[k] = i < A.B ? A.draws[(int64_t)r * A.B + i] : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-        }
+        RefBatch q;
+        if (base == 0)
+            q = q0;
+        else
+            refine_batch_load(A, r, ap, base, q);
         float c[RB][3], w[RB][3];
 #pragma unroll
         for (int k = 0; k < RB; ++k) {
-            if (gid[k] >= 0) {
-                const Mode &md = A.modes[gid[k]];
-                c[k][0] = dr[k].x; c[k][1] = dr[k].y; c[k][2] = dr[k].z;
+            if (q.gid[k] >= 0) {
+                const Mode &md = A.modes[q.gid[k]];
+                c[k][0] = q.dr[k].x; c[k][1] = q.dr[k].y; c[k][2] = q.dr[k].z;
                 w[k][0] = md.mu[0]; w[k][1] = md.mu[1]; w[k][2] = md.mu[2];
             }
         }
 #pragma unroll
         for (int k = 0; k < RB; ++k)
-            if (gid[k] >= 0) sums_add_point(s, c[k], w[k]);
+            if (q.gid[k] >= 0) sums_add_point(s, c[k], w[k]);
     }
     // reduce-scatter of the 64 lane sums (every lane active)
     double w11[12], x6[6], y4[4], z2[2];
@@ -1222,6 +1238,13 @@ __device__ __forceinline__ void refine_sums_at(const Attempt &A, int r, int h, i
     if (mine >= 0 && (lane & 1) == 0) A.sums[(int64_t)h * NSUM + mine] = tot;
 #pragma unroll
     for (int k = 0; k < NSUM; ++k) s[k] = lane_f64(tot, rs_lane_of(k));
+}
+
+__device__ __forceinline__ void refine_sums_at(const Attempt &A, int r, int h, int ap, double s[NSUM])
+{
+    RefBatch q0;
+    refine_batch_load(A, r, ap, 0, q0);
+    refine_sums_pre(A, r, h, ap, q0, s);
 }
 
 // the same for survivor position sidx of round r; returns the hypothesis index
@@ -1352,12 +1375,15 @@ __global__ void __launch_bounds__(64) k_b_finish(const Attempt *__restrict__ att
 }
 
 // Cull and refinement of a small round (at most FUSED_LIVE live hypotheses
-// per attempt) in one kernel: one wavefront per survivor slot. Each
+// per attempt) in one kernel: one wavefront per live position w. Each
 // wavefront forms every live hypothesis's energy exactly as the cull does
-// (group sums in group order, added to the accumulated energy), ranks the
-// keys (energy, index) itself, takes the hypothesis of rank sidx, writes its
-// entry of the next live list and refines it; the wavefront of slot 0 also
-// writes the round's trace, statistics and survivor count. The lists are
+// (group sums in group order, added to the accumulated energy, one position
+// per lane) and counts the keys (energy, index) below position w's: that
+// rank is w's place in the sorted order, so the positions of rank below
+// ceil(n / 2) survive, each into the slot of its rank, and are refined by
+// their own wavefront (whose inlier ids and draws, indexed by w, were
+// loaded together with the group sums). The wavefront of slot 0 writes the
+// round's trace, statistics and survivor count. The lists are
 // double-buffered by round parity, so no wavefront overwrites what another
 // reads. With `fin` (the plan's last round, a lone attempt) lane 0 of slot 0
 // then writes the attempt's result too, after its own refinement (all that
@@ -1370,38 +1396,38 @@ __global__ void __launch_bounds__(64) k_b_cull_refine(const Attempt *__restrict_
     FOR_UNITS(S, u) {
         const int a = attempt_of(S, u);
         const Attempt &A = att[a];
-        const int sidx = u - S.off[a];
+        const int w = u - S.off[a];    // below the planned live bound, so within the lists
         const int lane = __lane_id();
         const int na = A.rl[r];        // <= FUSED_LIVE: one live position per lane
         // positions clamped into the lists, so that these loads issue with
-        // the live count
+        // the live count, and position w's first batch of inlier ids and
+        // draws with them
         const int apl = min(lane, A.N - 1);
         const int hl = live_list(A, r)[apl];
         const float El = live_energy(A, r)[apl];
+        RefBatch q0;
+        refine_batch_load(A, r, w, 0, q0);
         const int ng = (A.B + GROUP - 1) / GROUP;
         // the group sums in group order, 64 loads at a time
         const float Ssum = group_total<64>(A.gs, apl, ng, A.N);
-        const bool last = fin && sidx == 0;
         if (!round_active(A, r)) {
-            if (last && lane == 0) finish_attempt(A);
+            if (fin && w == 0 && lane == 0) finish_attempt(A);
             continue;
         }
+        if (w >= na) continue;
         const int keep = (na + 1) / 2;
-        if (sidx >= keep) continue;
         const bool live = lane < na;
         const float E = El + Ssum;
         const unsigned long long key = live ? cull_key(E, hl, lane) : ~0ull;
-        // rank: how many live keys are smaller (keys are distinct)
-        int rank = 0;
-        for (int q = 0; q < na && q < 64; ++q) rank += lane_u64(key, q) < key;
-        const uint64_t m = __ballot(live && rank == sidx);
-        const unsigned long long kk = lane_u64(key, max(__ffsll((unsigned long long)m) - 1, 0));
-        const int h = (int)((kk >> 12) & 0xFFFFFull);
-        const int ap = (int)(kk & 0xFFFull);
+        // rank of position w: how many live keys are smaller (keys are distinct)
+        const unsigned long long kw = lane_u64(key, w);
+        const int sidx = __popcll(__ballot(live && key < kw));
+        if (sidx >= keep) continue;
+        const int h = (int)((kw >> 12) & 0xFFFFFull);
         if (lane == 0) {
             live_list(A, r + 1)[sidx] = h;
-            live_energy(A, r + 1)[sidx] = key_float((uint32_t)(kk >> 32));
-            A.pos[sidx] = ap;
+            live_energy(A, r + 1)[sidx] = key_float((uint32_t)(kw >> 32));
+            A.pos[sidx] = w;
         }
         if (sidx == 0) {
             if (r < MAX_ROUNDS && live) {
@@ -1417,9 +1443,9 @@ __global__ void __launch_bounds__(64) k_b_cull_refine(const Attempt *__restrict_
             }
         }
         double sm[NSUM];
-        refine_sums_at(A, r, h, ap, sm);
+        refine_sums_pre(A, r, h, w, q0, sm);
         if (lane == 0) refine_solve_of(A, sidx, h, sm);
-        if (last && lane == 0) finish_attempt(A);
+        if (fin && sidx == 0 && lane == 0) finish_attempt(A);
     }
 }
 
@@ -1561,15 +1587,15 @@ __global__ void __launch_bounds__(256) k_b_desc(const uint2 *__restrict__ src, u
 // stages of one schedule in launch order
 struct Stages {
     Stage pix, pb, att, hyp, wts;
-    std::vector<Stage> score, refine, solve, cull;
+    std::vector<Stage> score, refine, solve, cull, live;
 };
 
 // host offsets of every stage for schedule `sc`: pix, pb, att, hyp, wts, then
-// per round (score, refine, solve, cull by ranks)
+// per round (score, refine, solve, cull by ranks, live positions)
 static std::vector<int32_t> offsets(const Plan *pl, const Sched &sc)
 {
     const int n = pl->n, R = pl->rounds;
-    const int n_stage = 5 + 4 * R;
+    const int n_stage = 5 + 5 * R;
     std::vector<int32_t> off((size_t)n_stage * (n + 1), 0);
     auto fill = [&](int k, auto units) {
         int32_t *o = off.data() + (size_t)k * (n + 1);
@@ -1592,13 +1618,14 @@ static std::vector<int32_t> offsets(const Plan *pl, const Sched &sc)
         return bnd;
     };
     for (int r = 0; r < R; ++r) {
-        fill(5 + 4 * r, [&](int a) {
+        fill(5 + 5 * r, [&](int a) {
             if (r >= rounds_for(pl->shape[a].N)) return 0;
             return ((bound(a, r) + 63) / 64) * ((pl->shape[a].B + sc.dpu[r] - 1) / sc.dpu[r]);
         });
-        fill(6 + 4 * r, [&](int a) { return r >= rounds_for(pl->shape[a].N) ? 0 : bound(a, r + 1); });
-        fill(7 + 4 * r, [&](int a) { return r >= rounds_for(pl->shape[a].N) ? 0 : (bound(a, r + 1) + 63) / 64; });
-        fill(8 + 4 * r, [&](int a) { return r >= rounds_for(pl->shape[a].N) ? 0 : (bound(a, r) + 63) / 64; });
+        fill(6 + 5 * r, [&](int a) { return r >= rounds_for(pl->shape[a].N) ? 0 : bound(a, r + 1); });
+        fill(7 + 5 * r, [&](int a) { return r >= rounds_for(pl->shape[a].N) ? 0 : (bound(a, r + 1) + 63) / 64; });
+        fill(8 + 5 * r, [&](int a) { return r >= rounds_for(pl->shape[a].N) ? 0 : (bound(a, r) + 63) / 64; });
+        fill(9 + 5 * r, [&](int a) { return r >= rounds_for(pl->shape[a].N) ? 0 : bound(a, r); });
     }
     return off;
 }
@@ -1617,10 +1644,11 @@ static Stages stages_of(const Plan *pl, const Sched &sc, const int32_t *d_off, c
     Stages st;
     st.pix = mk(0); st.pb = mk(1); st.att = mk(2); st.hyp = mk(3); st.wts = mk(4);
     for (int r = 0; r < pl->rounds; ++r) {
-        st.score.push_back(mk(5 + 4 * r));
-        st.refine.push_back(mk(6 + 4 * r));
-        st.solve.push_back(mk(7 + 4 * r));
-        st.cull.push_back(mk(8 + 4 * r));
+        st.score.push_back(mk(5 + 5 * r));
+        st.refine.push_back(mk(6 + 5 * r));
+        st.solve.push_back(mk(7 + 5 * r));
+        st.cull.push_back(mk(8 + 5 * r));
+        st.live.push_back(mk(9 + 5 * r));
     }
     return st;
 }
@@ -1736,8 +1764,8 @@ static int enqueue(const Plan *pl, const Sched &sc, const Stages &st, hipStream_
         if (r >= pl->fused_from && st.refine[r].total <= FUSED_REFINE) {
             // a lone attempt's last round also writes its result
             const int fin = (pl->n == 1 && r == pl->rounds - 1) ? 1 : 0;
-            RL_LAUNCH("k_b_cull_refine", k_b_cull_refine, dim3(grid_of(st.refine[r], 0, sc.xcd)), dim3(64), 0, s, d,
-                      st.refine[r], r, fin);
+            RL_LAUNCH("k_b_cull_refine", k_b_cull_refine, dim3(grid_of(st.live[r], 0, sc.xcd)), dim3(64), 0, s, d,
+                      st.live[r], r, fin);
             finished |= fin != 0;
             continue;
         }
