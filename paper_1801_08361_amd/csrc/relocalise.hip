@@ -956,9 +956,14 @@ __global__ void __launch_bounds__(CULL_THREADS) k_b_cull_rank(const Attempt *__r
 // each other between draws). The group's energies are then summed per lane
 // in draw order and stored; the cull adds the group sums in group order. The
 // units of hypothesis block 0 also count their draws' modes.
+// With lph > 0 (rounds in which every attempt has at most 64 >> lph live
+// hypotheses) each hypothesis takes 2^lph lanes, which split the draw's modes
+// (lane j of the group takes modes j, j + 2^lph, ...) and then combine their
+// first minima, ties to the lower mode, which is the first minimum in mode
+// order: the same best mode and energy as one lane looping over all modes.
 template <int U>
 __global__ void __launch_bounds__(64 * GROUP) k_b_score(const Attempt *__restrict__ att, Stage S, int r, int dpu,
-                                                        int tm)
+                                                        int tm, int lph)
 {
     extern __shared__ __align__(16) float smode[];
     __shared__ int32_t s_ex[GROUP][16], s_base[GROUP][16];
@@ -977,7 +982,8 @@ __global__ void __launch_bounds__(64 * GROUP) k_b_score(const Attempt *__restric
         // the lane's pose and the wavefront's first draw are loaded together
         // with the live count (a lane past the live list reads a row it does
         // not use; the addresses are within the arrays either way)
-        const int ap = a0 + lane;
+        const int sub = lane & ((1 << lph) - 1);
+        const int ap = a0 + (lane >> lph);
         const float *lp = A.lpose + (int64_t)min(ap, A.N - 1) * 12;
         const float R0 = lp[0], R1 = lp[1], R2 = lp[2], R3 = lp[3], R4 = lp[4], R5 = lp[5], R6 = lp[6],
                     R7 = lp[7], R8 = lp[8];
@@ -1049,23 +1055,40 @@ __global__ void __launch_bounds__(64 * GROUP) k_b_score(const Attempt *__restric
                     const float y2 = fmaf(R6, dr.x, fmaf(R7, dr.y, fmaf(R8, dr.z, t2)));
                     float best = INFINITY;
                     int bj = -1;
+                    // modes j0, j0 + js, ... of the draw against the lane's pose
                     // (unrolled U times: U modes' LDS reads in flight at once; the
                     // comparisons still run in mode order)
+                    auto scan = [&](int j0, int js) {
 #pragma unroll U
-                    for (int j = 0; j < cnt; ++j) {
-                        const float4 q0 = *(const float4 *)(sm + j * SMODE);
-                        const float4 q1 = *(const float4 *)(sm + j * SMODE + 4);
-                        const float2 q2 = *(const float2 *)(sm + j * SMODE + 8);
-                        const float d0 = y0 - q0.x, d1 = y1 - q0.y, d2 = y2 - q0.z;
-                        const float s0 = q0.w, s1 = q1.x, s2 = q1.y, s3 = q1.z, s4 = q1.w, s5 = q2.x;
-                        const float a0v = fmaf(s2, d2, fmaf(s1, d1, s0 * d0));
-                        const float a1v = fmaf(s4, d2, fmaf(s3, d1, s1 * d0));
-                        const float a2v = fmaf(s5, d2, fmaf(s4, d1, s2 * d0));
-                        const float q = fmaf(d2, a2v, fmaf(d1, a1v, d0 * a0v));
-                        const float term = fmaf(0.5f, q, q2.y);
-                        if (term < best) {
-                            best = term;
-                            bj = j;
+                        for (int j = j0; j < cnt; j += js) {
+                            const float4 q0 = *(const float4 *)(sm + j * SMODE);
+                            const float4 q1 = *(const float4 *)(sm + j * SMODE + 4);
+                            const float2 q2 = *(const float2 *)(sm + j * SMODE + 8);
+                            const float d0 = y0 - q0.x, d1 = y1 - q0.y, d2 = y2 - q0.z;
+                            const float s0 = q0.w, s1 = q1.x, s2 = q1.y, s3 = q1.z, s4 = q1.w, s5 = q2.x;
+                            const float a0v = fmaf(s2, d2, fmaf(s1, d1, s0 * d0));
+                            const float a1v = fmaf(s4, d2, fmaf(s3, d1, s1 * d0));
+                            const float a2v = fmaf(s5, d2, fmaf(s4, d1, s2 * d0));
+                            const float q = fmaf(d2, a2v, fmaf(d1, a1v, d0 * a0v));
+                            const float term = fmaf(0.5f, q, q2.y);
+                            if (term < best) {
+                                best = term;
+                                bj = j;
+                            }
+                        }
+                    };
+                    if (lph == 0)
+                        scan(0, 1);
+                    else
+                        scan(sub, 1 << lph);
+                    // the lanes of a hypothesis combine their minima (every
+                    // lane is active here; best is +inf exactly when bj < 0)
+                    for (int o = 1; o < (1 << lph); o <<= 1) {
+                        const float ob = __shfl_xor(best, o, 64);
+                        const int oj = __shfl_xor(bj, o, 64);
+                        if (ob < best || (ob == best && oj < bj)) {
+                            best = ob;
+                            bj = oj;
                         }
                     }
                     int32_t gid = -1;
@@ -1074,17 +1097,18 @@ __global__ void __launch_bounds__(64 * GROUP) k_b_score(const Attempt *__restric
                         const float d0 = y0 - mb[0], d1 = y1 - mb[1], d2 = y2 - mb[2];
                         if ((d0 * d0 + d1 * d1) + d2 * d2 <= A.inl2) gid = __float_as_int(mb[10]);
                     }
-                    s_e[slot][lane] = best < 0.0f ? best : 0.0f;
-                    if (act && has) A.inl[inl_at(A, i, ap)] = gid;
+                    if (sub == 0) s_e[slot][lane >> lph] = best < 0.0f ? best : 0.0f;
+                    if (act && has && sub == 0) A.inl[inl_at(A, i, ap)] = gid;
                     // this wavefront's next draw restages its own LDS slice
                     wave_lds_sync();
                 }
                 __syncthreads();
                 // the group's energy sum per lane, in draw order
                 if (wv == 0) {
+                    // lane = hypothesis of the block here
                     float g = 0.0f;
                     for (int w = 0; w < GROUP && g0 + w < i1; ++w) g = g + s_e[w][lane];
-                    if (act) A.gs[(int64_t)(g0 / GROUP) * A.N + ap] = g;
+                    if (lane < (64 >> lph) && a0 + lane < na) A.gs[(int64_t)(g0 / GROUP) * A.N + a0 + lane] = g;
                 }
                 __syncthreads();
             }
@@ -1751,15 +1775,29 @@ static int enqueue(const Plan *pl, const Sched &sc, const Stages &st, hipStream_
         }
         return true;
     };
+    // lanes per hypothesis (log2) in the scoring of round r: the largest
+    // planned live count of the round's attempts, rounded up to a power of
+    // two, takes 64 >> lph lanes (at least 2 hypotheses per block)
+    auto lph_of = [&](int r) {
+        int mx = 0;
+        for (const Shape &sh : pl->shape) {
+            int bnd = sh.N;
+            for (int k = 0; k < r; ++k) bnd = (bnd + 1) / 2;
+            mx = bnd > mx ? bnd : mx;
+        }
+        int l = 0;
+        while (l < 5 && (64 >> (l + 1)) >= mx) ++l;
+        return l;
+    };
     bool finished = false;
     for (int r = 0; r < pl->rounds; ++r) {
         if (tm) tm->begin(1 + r, s);
         if (sc.su == 4)
             RL_LAUNCH("k_b_score", k_b_score<4>, dim3(grid_of(st.score[r], sc.grid, sc.xcd)), dim3(64 * nw), smem,
-                      s, d, st.score[r], r, sc.dpu[r], pl->tm_max);
+                      s, d, st.score[r], r, sc.dpu[r], pl->tm_max, lph_of(r));
         else
             RL_LAUNCH("k_b_score", k_b_score<1>, dim3(grid_of(st.score[r], sc.grid, sc.xcd)), dim3(64 * nw), smem,
-                      s, d, st.score[r], r, sc.dpu[r], pl->tm_max);
+                      s, d, st.score[r], r, sc.dpu[r], pl->tm_max, lph_of(r));
         if (tm) tm->end(1 + r, s);
         if (r >= pl->fused_from && st.refine[r].total <= FUSED_REFINE) {
             // a lone attempt's last round also writes its result
