@@ -32,6 +32,7 @@
 #include <algorithm>
 #include <new>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "mlp_dev.h"
@@ -550,58 +551,102 @@ __device__ bool try_hypothesis(const Attempt &A, int np, uint64_t h, uint64_t ta
     }
     int64_t pick[3];
     float c[3][3], w[3][3];
+    // The colour-consistent modes of pixels j0 .. j0 + NJ - 1, tree by tree
+    // (all of the pixels' rows of a tree loaded before their tests): the leaf
+    // indices are in s_li, the masks go to s_mask (LDS, per pixel 16 rows of
+    // 64 lanes, per tree one row); cnt[j] receives pixel j's count
+    auto masks = [&](auto nj, int j0, int *cnt) {
+        constexpr int NJ = decltype(nj)::value;
+        ColourWin win[NJ];
 #pragma unroll
-    for (int j = 0; j < 3; ++j) {
-        // this lane's leaf and colour mask per tree, in LDS columns (stride 64)
-#pragma unroll 4
-        for (int tt = 0; tt < A.T; ++tt) s_li[tt * 64] = tt * A.L + A.leaves[(int64_t)tt * A.P + p[j]];
-        const ColourWin win = colour_win(pr[j], pg[j], pb[j], A.rgb_tol);
-        int cnt = 0;
+        for (int j = 0; j < NJ; ++j) {
+            win[j] = colour_win(pr[j0 + j], pg[j0 + j], pb[j0 + j], A.rgb_tol);
+            cnt[j] = 0;
+        }
         if (Mp <= 12) {
             // up to 12 modes per leaf: each row's three 16-byte loads are
             // issued together, four trees at a time
 #pragma unroll 4
             for (int tt = 0; tt < A.T; ++tt) {
-                const Mask mk =
-                    colour_mask12(A.mode_rgb + (int64_t)s_li[tt * 64] * Mp, Mp, win);
-                s_mask[tt * 64] = mk;
-                cnt += popc_mask(mk);
+                Mask mk[NJ];
+#pragma unroll
+                for (int j = 0; j < NJ; ++j)
+                    mk[j] = colour_mask12(A.mode_rgb + (int64_t)s_li[(j0 + j) * 1024 + tt * 64] * Mp, Mp, win[j]);
+#pragma unroll
+                for (int j = 0; j < NJ; ++j) {
+                    s_mask[(j0 + j) * 1024 + tt * 64] = mk[j];
+                    cnt[j] += popc_mask(mk[j]);
+                }
             }
         } else {
             for (int tt = 0; tt < A.T; ++tt) {
-                const Mask mk =
-                    colour_mask<Mask>(A.mode_rgb + (int64_t)s_li[tt * 64] * Mp, Mp, win);
-                s_mask[tt * 64] = mk;
-                cnt += popc_mask(mk);
+#pragma unroll
+                for (int j = 0; j < NJ; ++j) {
+                    const Mask mk = colour_mask<Mask>(A.mode_rgb + (int64_t)s_li[(j0 + j) * 1024 + tt * 64] * Mp, Mp,
+                                                      win[j]);
+                    s_mask[(j0 + j) * 1024 + tt * 64] = mk;
+                    cnt[j] += popc_mask(mk);
+                }
             }
         }
-        if (cnt == 0) return false;
-        int sel = (int)uniform_int(b.x[j], (uint64_t)cnt);
-        pick[j] = 0;
+    };
+    // the sel-th colour-consistent mode of pixel j in (tree, mode) order
+    auto pick_of = [&](int j, int sel) {
+        int64_t pk = 0;
         for (int tt = 0; tt < A.T; ++tt) {
-            const Mask mk = s_mask[tt * 64];
+            const Mask mk = s_mask[j * 1024 + tt * 64];
             const int k = popc_mask(mk);
             if (sel >= 0 && sel < k) {
                 Mask mm = mk;
                 for (int q = 0; q < sel; ++q) mm &= mm - (Mask)1;
-                pick[j] = (int64_t)s_li[tt * 64] * A.M + (ffs_mask(mm) - 1);
+                pk = (int64_t)s_li[j * 1024 + tt * 64] * A.M + (ffs_mask(mm) - 1);
             }
             sel -= k;
         }
+        return pk;
+    };
+    // pixels 0 and 1 stage by stage together (their leaves, then their mode
+    // colour rows, then their picked modes), then the first pair's checks
+    // before any load of pixel 2 (every check is a plain predicate, so their
+    // order does not change the result; lanes that fail load nothing more)
+#pragma unroll 4
+    for (int tt = 0; tt < A.T; ++tt) {
+        const int32_t l0 = A.leaves[(int64_t)tt * A.P + p[0]], l1 = A.leaves[(int64_t)tt * A.P + p[1]];
+        s_li[tt * 64] = tt * A.L + l0;
+        s_li[1024 + tt * 64] = tt * A.L + l1;
+    }
+    int cnt01[2];
+    masks(std::integral_constant<int, 2>(), 0, cnt01);
+    if (cnt01[0] == 0 || cnt01[1] == 0) return false;
+    pick[0] = pick_of(0, (int)uniform_int(b.x[0], (uint64_t)cnt01[0]));
+    pick[1] = pick_of(1, (int)uniform_int(b.x[1], (uint64_t)cnt01[1]));
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
         cam_point(A.fr, p[j] % A.fr.W, p[j] / A.fr.W, dep[j], c[j]);
         const Mode &md = A.modes[pick[j]];
         w[j][0] = md.mu[0];
         w[j][1] = md.mu[1];
         w[j][2] = md.mu[2];
-        if (j == 1) {
-            // the first pair's checks before the third pixel's loads (every
-            // check is a plain predicate, so their order does not change the
-            // result; lanes that fail here load nothing more)
-            if (pi[0] == pi[1]) return false;
-            const float dc = sq3(c[0], c[1]);
-            const float dw = sq3(w[0], w[1]);
-            if (!(dc >= A.min_pair2) || !(dw <= A.ratio2 * dc) || !(dc <= A.ratio2 * dw)) return false;
-        }
+    }
+    {
+        if (pi[0] == pi[1]) return false;
+        const float dc = sq3(c[0], c[1]);
+        const float dw = sq3(w[0], w[1]);
+        if (!(dc >= A.min_pair2) || !(dw <= A.ratio2 * dc) || !(dc <= A.ratio2 * dw)) return false;
+    }
+    // pixel 2
+#pragma unroll 4
+    for (int tt = 0; tt < A.T; ++tt) s_li[2048 + tt * 64] = tt * A.L + A.leaves[(int64_t)tt * A.P + p[2]];
+    int cnt2[1];
+    masks(std::integral_constant<int, 1>(), 2, cnt2);
+    if (cnt2[0] == 0) return false;
+    pick[2] = pick_of(2, (int)uniform_int(b.x[2], (uint64_t)cnt2[0]));
+    cam_point(A.fr, p[2] % A.fr.W, p[2] / A.fr.W, dep[2], c[2]);
+    {
+        const Mode &md = A.modes[pick[2]];
+        w[2][0] = md.mu[0];
+        w[2][1] = md.mu[1];
+        w[2][2] = md.mu[2];
     }
     if (pi[0] == pi[1] || pi[0] == pi[2] || pi[1] == pi[2]) return false;
     const int EA[3] = {0, 0, 1}, EB[3] = {1, 2, 2};
@@ -638,8 +683,8 @@ __global__ void __launch_bounds__(64) k_b_hypgen(const Attempt *__restrict__ att
 {
     // per lane (column) and tree (row): leaf index and colour mask of the pixel
     // being picked (T <= 16)
-    __shared__ int32_t s_li[16 * 64];
-    __shared__ Mask s_mask[16 * 64];
+    __shared__ int32_t s_li[3 * 16 * 64];
+    __shared__ Mask s_mask[3 * 16 * 64];
     FOR_UNITS(S, u) {
         const int a = attempt_of(S, u);
         const Attempt &A = att[a];
