@@ -530,7 +530,7 @@ __device__ __forceinline__ uint32_t colour_mask12(const uint32_t *__restrict__ r
 // waits once.
 template <typename Mask>
 __device__ bool try_hypothesis(const Attempt &A, int np, uint64_t h, uint64_t tau, double R[9], double t[3],
-                               int32_t *__restrict__ s_li, Mask *__restrict__ s_mask)
+                               int32_t *__restrict__ s_li, Mask *__restrict__ s_mask, int ps)
 {
     const U4 a = philox(h, tau, 0, 0, A.seed, TAG_HYP);
     const U4 b = philox(h, tau, 1, 0, A.seed, TAG_HYP);
@@ -551,16 +551,16 @@ __device__ bool try_hypothesis(const Attempt &A, int np, uint64_t h, uint64_t ta
     }
     int64_t pick[3];
     float c[3][3], w[3][3];
-    // The colour-consistent modes of pixels j0 .. j0 + NJ - 1, tree by tree
-    // (all of the pixels' rows of a tree loaded before their tests): the leaf
-    // indices are in s_li, the masks go to s_mask (LDS, per pixel 16 rows of
-    // 64 lanes, per tree one row); cnt[j] receives pixel j's count
-    auto masks = [&](auto nj, int j0, int *cnt) {
+    // The colour-consistent modes of pixels q0 .. q0 + NJ - 1, held in LDS
+    // slots j0 .. j0 + NJ - 1, tree by tree (all of the pixels' rows of a tree loaded before their
+    // tests): the leaf indices are in s_li, the masks go to s_mask (slot
+    // stride ps, one row of 64 lanes per tree); cnt[j] receives the count
+    auto masks = [&](auto nj, int j0, int q0, int *cnt) {
         constexpr int NJ = decltype(nj)::value;
         ColourWin win[NJ];
 #pragma unroll
         for (int j = 0; j < NJ; ++j) {
-            win[j] = colour_win(pr[j0 + j], pg[j0 + j], pb[j0 + j], A.rgb_tol);
+            win[j] = colour_win(pr[q0 + j], pg[q0 + j], pb[q0 + j], A.rgb_tol);
             cnt[j] = 0;
         }
         if (Mp <= 12) {
@@ -571,10 +571,10 @@ __device__ bool try_hypothesis(const Attempt &A, int np, uint64_t h, uint64_t ta
                 Mask mk[NJ];
 #pragma unroll
                 for (int j = 0; j < NJ; ++j)
-                    mk[j] = colour_mask12(A.mode_rgb + (int64_t)s_li[(j0 + j) * 1024 + tt * 64] * Mp, Mp, win[j]);
+                    mk[j] = colour_mask12(A.mode_rgb + (int64_t)s_li[(j0 + j) * ps + tt * 64] * Mp, Mp, win[j]);
 #pragma unroll
                 for (int j = 0; j < NJ; ++j) {
-                    s_mask[(j0 + j) * 1024 + tt * 64] = mk[j];
+                    s_mask[(j0 + j) * ps + tt * 64] = mk[j];
                     cnt[j] += popc_mask(mk[j]);
                 }
             }
@@ -582,24 +582,25 @@ __device__ bool try_hypothesis(const Attempt &A, int np, uint64_t h, uint64_t ta
             for (int tt = 0; tt < A.T; ++tt) {
 #pragma unroll
                 for (int j = 0; j < NJ; ++j) {
-                    const Mask mk = colour_mask<Mask>(A.mode_rgb + (int64_t)s_li[(j0 + j) * 1024 + tt * 64] * Mp, Mp,
+                    const Mask mk = colour_mask<Mask>(A.mode_rgb + (int64_t)s_li[(j0 + j) * ps + tt * 64] * Mp, Mp,
                                                       win[j]);
-                    s_mask[(j0 + j) * 1024 + tt * 64] = mk;
+                    s_mask[(j0 + j) * ps + tt * 64] = mk;
                     cnt[j] += popc_mask(mk);
                 }
             }
         }
     };
-    // the sel-th colour-consistent mode of pixel j in (tree, mode) order
+    // the sel-th colour-consistent mode of the pixel in slot j, in (tree,
+    // mode) order
     auto pick_of = [&](int j, int sel) {
         int64_t pk = 0;
         for (int tt = 0; tt < A.T; ++tt) {
-            const Mask mk = s_mask[j * 1024 + tt * 64];
+            const Mask mk = s_mask[j * ps + tt * 64];
             const int k = popc_mask(mk);
             if (sel >= 0 && sel < k) {
                 Mask mm = mk;
                 for (int q = 0; q < sel; ++q) mm &= mm - (Mask)1;
-                pk = (int64_t)s_li[j * 1024 + tt * 64] * A.M + (ffs_mask(mm) - 1);
+                pk = (int64_t)s_li[j * ps + tt * 64] * A.M + (ffs_mask(mm) - 1);
             }
             sel -= k;
         }
@@ -613,10 +614,10 @@ __device__ bool try_hypothesis(const Attempt &A, int np, uint64_t h, uint64_t ta
     for (int tt = 0; tt < A.T; ++tt) {
         const int32_t l0 = A.leaves[(int64_t)tt * A.P + p[0]], l1 = A.leaves[(int64_t)tt * A.P + p[1]];
         s_li[tt * 64] = tt * A.L + l0;
-        s_li[1024 + tt * 64] = tt * A.L + l1;
+        s_li[ps + tt * 64] = tt * A.L + l1;
     }
     int cnt01[2];
-    masks(std::integral_constant<int, 2>(), 0, cnt01);
+    masks(std::integral_constant<int, 2>(), 0, 0, cnt01);
     if (cnt01[0] == 0 || cnt01[1] == 0) return false;
     pick[0] = pick_of(0, (int)uniform_int(b.x[0], (uint64_t)cnt01[0]));
     pick[1] = pick_of(1, (int)uniform_int(b.x[1], (uint64_t)cnt01[1]));
@@ -634,13 +635,13 @@ __device__ bool try_hypothesis(const Attempt &A, int np, uint64_t h, uint64_t ta
         const float dw = sq3(w[0], w[1]);
         if (!(dc >= A.min_pair2) || !(dw <= A.ratio2 * dc) || !(dc <= A.ratio2 * dw)) return false;
     }
-    // pixel 2
+    // pixel 2, in slot 0 (the first two pixels' picks are done)
 #pragma unroll 4
-    for (int tt = 0; tt < A.T; ++tt) s_li[2048 + tt * 64] = tt * A.L + A.leaves[(int64_t)tt * A.P + p[2]];
+    for (int tt = 0; tt < A.T; ++tt) s_li[tt * 64] = tt * A.L + A.leaves[(int64_t)tt * A.P + p[2]];
     int cnt2[1];
-    masks(std::integral_constant<int, 1>(), 2, cnt2);
+    masks(std::integral_constant<int, 1>(), 0, 2, cnt2);
     if (cnt2[0] == 0) return false;
-    pick[2] = pick_of(2, (int)uniform_int(b.x[2], (uint64_t)cnt2[0]));
+    pick[2] = pick_of(0, (int)uniform_int(b.x[2], (uint64_t)cnt2[0]));
     cam_point(A.fr, p[2] % A.fr.W, p[2] / A.fr.W, dep[2], c[2]);
     {
         const Mode &md = A.modes[pick[2]];
@@ -678,13 +679,16 @@ __device__ bool try_hypothesis(const Attempt &A, int np, uint64_t h, uint64_t ta
 
 // (Mask: uint32_t when every attempt's forest keeps at most 32 modes per
 // leaf, uint64_t up to 64)
+// LDS: per lane (column) and tree (row) the leaf index and the colour mask of
+// the pixels being picked, two pixel slots of tmax rows (the plan's largest
+// tree count)
 template <typename Mask>
-__global__ void __launch_bounds__(64) k_b_hypgen(const Attempt *__restrict__ att, Stage S)
+__global__ void __launch_bounds__(64) k_b_hypgen(const Attempt *__restrict__ att, Stage S, int tmax)
 {
-    // per lane (column) and tree (row): leaf index and colour mask of the pixel
-    // being picked (T <= 16)
-    __shared__ int32_t s_li[3 * 16 * 64];
-    __shared__ Mask s_mask[3 * 16 * 64];
+    extern __shared__ __align__(16) char hg_lds[];
+    const int ps = tmax * 64;
+    int32_t *s_li = (int32_t *)hg_lds;
+    Mask *s_mask = (Mask *)(hg_lds + (size_t)2 * ps * sizeof(int32_t));
     FOR_UNITS(S, u) {
         const int a = attempt_of(S, u);
         const Attempt &A = att[a];
@@ -714,7 +718,7 @@ __global__ void __launch_bounds__(64) k_b_hypgen(const Attempt *__restrict__ att
         for (int chunk = 0; chunk * 64 < A.max_tries && found < 0; ++chunk) {
             const int tau = chunk * 64 + lane;
             const bool ok = tau < A.max_tries && np > 0 &&
-                            try_hypothesis(A, np, (uint64_t)h, (uint64_t)tau, R, t, s_li + lane, s_mask + lane);
+                            try_hypothesis(A, np, (uint64_t)h, (uint64_t)tau, R, t, s_li + lane, s_mask + lane, ps);
             const uint64_t m = __ballot(ok);
             if (m) {
                 const int first = __ffsll((unsigned long long)m) - 1;
@@ -1801,10 +1805,14 @@ static int enqueue(const Plan *pl, const Sched &sc, const Stages &st, hipStream_
                   s, d, st.wts);
     RL_LAUNCH("k_b_pool_write", k_b_pool_write, dim3(grid_of(st.pb, cap, sc.xcd)), dim3(POOL_BLOCK / PB_PIX), 0, s, d,
               st.pb);
+    int t_max = 1;
+    for (const Shape &sh : pl->shape) t_max = sh.T > t_max ? sh.T : t_max;
     if (pl->m_max > 32)
-        RL_LAUNCH("k_b_hypgen", k_b_hypgen<uint64_t>, dim3(grid_of(st.hyp, 0, sc.xcd)), dim3(64), 0, s, d, st.hyp);
+        RL_LAUNCH("k_b_hypgen", k_b_hypgen<uint64_t>, dim3(grid_of(st.hyp, 0, sc.xcd)), dim3(64),
+                  (size_t)2 * t_max * 64 * (4 + 8), s, d, st.hyp, t_max);
     else
-        RL_LAUNCH("k_b_hypgen", k_b_hypgen<uint32_t>, dim3(grid_of(st.hyp, 0, sc.xcd)), dim3(64), 0, s, d, st.hyp);
+        RL_LAUNCH("k_b_hypgen", k_b_hypgen<uint32_t>, dim3(grid_of(st.hyp, 0, sc.xcd)), dim3(64),
+                  (size_t)2 * t_max * 64 * (4 + 4), s, d, st.hyp, t_max);
     RL_LAUNCH("k_b_alive_init", k_b_alive_init, dim3(grid_of(att, cap, 0)), dim3(1024), 0, s, d, att);
     const int nw = score_waves(pl->tm_max);
     const size_t smem = (size_t)nw * pl->tm_max * SMODE * sizeof(float);
