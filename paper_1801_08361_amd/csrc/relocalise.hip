@@ -1151,19 +1151,29 @@ __global__ void __launch_bounds__(64 * GROUP) k_b_score(const Attempt *__restric
                     }
                     wcnt += has ? (uint32_t)cnt : 0u;
                     wave_lds_sync();
-                    for (int j = lane; j < cnt; j += 64) {
-                        // the mode's tree: the last tree whose first mode index is <= j
-                        int tj = 0;
-                        for (int t = 1; t < A.T; ++t)
-                            if (j >= s_ex[wv][t]) tj = t;
-                        const int gidx = s_base[wv][tj] + (j - s_ex[wv][tj]);
-                        const Mode md = A.modes[gidx];
+                    // staged up to a multiple of 4 modes: the padding slots
+                    // hold a zero form and kappa = +inf, so their term is +inf
+                    // and never below the best (which starts at +inf)
+                    const int cnt4 = (cnt + 3) & ~3;
+                    for (int j = lane; j < cnt4; j += 64) {
                         float *dst = sm + j * SMODE;
-                        dst[0] = md.mu[0]; dst[1] = md.mu[1]; dst[2] = md.mu[2];
-                        dst[3] = md.sinv[0]; dst[4] = md.sinv[1]; dst[5] = md.sinv[2];
-                        dst[6] = md.sinv[3]; dst[7] = md.sinv[4]; dst[8] = md.sinv[5];
-                        dst[9] = md.kappa;
-                        dst[10] = __int_as_float(gidx);
+                        if (j < cnt) {
+                            // the mode's tree: the last tree whose first mode index is <= j
+                            int tj = 0;
+                            for (int t = 1; t < A.T; ++t)
+                                if (j >= s_ex[wv][t]) tj = t;
+                            const int gidx = s_base[wv][tj] + (j - s_ex[wv][tj]);
+                            const Mode md = A.modes[gidx];
+                            dst[0] = md.mu[0]; dst[1] = md.mu[1]; dst[2] = md.mu[2];
+                            dst[3] = md.sinv[0]; dst[4] = md.sinv[1]; dst[5] = md.sinv[2];
+                            dst[6] = md.sinv[3]; dst[7] = md.sinv[4]; dst[8] = md.sinv[5];
+                            dst[9] = md.kappa;
+                            dst[10] = __int_as_float(gidx);
+                        } else {
+                            for (int k = 0; k < 9; ++k) dst[k] = 0.0f;
+                            dst[9] = INFINITY;
+                            dst[10] = __int_as_float(-1);
+                        }
                         dst[11] = 0.0f;
                     }
                     wave_lds_sync();
@@ -1175,29 +1185,49 @@ __global__ void __launch_bounds__(64 * GROUP) k_b_score(const Attempt *__restric
                     // modes j0, j0 + js, ... of the draw against the lane's pose
                     // (unrolled U times: U modes' LDS reads in flight at once; the
                     // comparisons still run in mode order)
-                    auto scan = [&](int j0, int js) {
-#pragma unroll U
-                        for (int j = j0; j < cnt; j += js) {
-                            const float4 q0 = *(const float4 *)(sm + j * SMODE);
-                            const float4 q1 = *(const float4 *)(sm + j * SMODE + 4);
-                            const float2 q2 = *(const float2 *)(sm + j * SMODE + 8);
-                            const float d0 = y0 - q0.x, d1 = y1 - q0.y, d2 = y2 - q0.z;
-                            const float s0 = q0.w, s1 = q1.x, s2 = q1.y, s3 = q1.z, s4 = q1.w, s5 = q2.x;
-                            const float a0v = fmaf(s2, d2, fmaf(s1, d1, s0 * d0));
-                            const float a1v = fmaf(s4, d2, fmaf(s3, d1, s1 * d0));
-                            const float a2v = fmaf(s5, d2, fmaf(s4, d1, s2 * d0));
-                            const float q = fmaf(d2, a2v, fmaf(d1, a1v, d0 * a0v));
-                            const float term = fmaf(0.5f, q, q2.y);
+                    auto term_of = [&](int j) {
+                        const float4 q0 = *(const float4 *)(sm + j * SMODE);
+                        const float4 q1 = *(const float4 *)(sm + j * SMODE + 4);
+                        const float2 q2 = *(const float2 *)(sm + j * SMODE + 8);
+                        const float d0 = y0 - q0.x, d1 = y1 - q0.y, d2 = y2 - q0.z;
+                        const float s0 = q0.w, s1 = q1.x, s2 = q1.y, s3 = q1.z, s4 = q1.w, s5 = q2.x;
+                        const float a0v = fmaf(s2, d2, fmaf(s1, d1, s0 * d0));
+                        const float a1v = fmaf(s4, d2, fmaf(s3, d1, s1 * d0));
+                        const float a2v = fmaf(s5, d2, fmaf(s4, d1, s2 * d0));
+                        const float q = fmaf(d2, a2v, fmaf(d1, a1v, d0 * a0v));
+                        return fmaf(0.5f, q, q2.y);
+                    };
+                    if (lph == 0 && U == 4) {
+                        // every staged mode, four at a time over the padded
+                        // count (no bounds test per mode; the comparisons run
+                        // in mode order)
+                        for (int j = 0; j < cnt4; j += 4) {
+#pragma unroll
+                            for (int e = 0; e < 4; ++e) {
+                                const float term = term_of(j + e);
+                                if (term < best) {
+                                    best = term;
+                                    bj = j + e;
+                                }
+                            }
+                        }
+                    } else if (lph == 0) {
+                        for (int j = 0; j < cnt; ++j) {
+                            const float term = term_of(j);
                             if (term < best) {
                                 best = term;
                                 bj = j;
                             }
                         }
-                    };
-                    if (lph == 0)
-                        scan(0, 1);
-                    else
-                        scan(sub, 1 << lph);
+                    } else {
+                        for (int j = sub; j < cnt; j += 1 << lph) {
+                            const float term = term_of(j);
+                            if (term < best) {
+                                best = term;
+                                bj = j;
+                            }
+                        }
+                    }
                     // the lanes of a hypothesis combine their minima (every
                     // lane is active here; best is +inf exactly when bj < 0)
                     for (int o = 1; o < (1 << lph); o <<= 1) {
@@ -1889,8 +1919,10 @@ static int enqueue(const Plan *pl, const Sched &sc, const Stages &st, hipStream_
         RL_LAUNCH("k_b_hypgen", k_b_hypgen<uint32_t>, dim3(grid_of(st.hyp, 0, sc.xcd)), dim3(64),
                   (size_t)2 * t_max * 64 * (4 + 4), s, d, st.hyp, t_max);
     RL_LAUNCH("k_b_alive_init", k_b_alive_init, dim3(grid_of(att, cap, 0)), dim3(1024), 0, s, d, att);
-    const int nw = score_waves(pl->tm_max);
-    const size_t smem = (size_t)nw * pl->tm_max * SMODE * sizeof(float);
+    // the LDS slice of a wavefront holds a draw's modes padded to a multiple of 4
+    const int tm4 = (pl->tm_max + 3) & ~3;
+    const int nw = score_waves(tm4);
+    const size_t smem = (size_t)nw * tm4 * SMODE * sizeof(float);
     // a round culls by ranks when every attempt's live list fits RANK_MAX and
     // the round needs few rank workgroups (each one reads all of its
     // attempt's group sums); otherwise by one sorting workgroup per attempt
@@ -1922,10 +1954,10 @@ static int enqueue(const Plan *pl, const Sched &sc, const Stages &st, hipStream_
         if (tm) tm->begin(1 + r, s);
         if (sc.su == 4)
             RL_LAUNCH("k_b_score", k_b_score<4>, dim3(grid_of(st.score[r], sc.grid, sc.xcd)), dim3(64 * nw), smem,
-                      s, d, st.score[r], r, sc.dpu[r], pl->tm_max, lph_of(r));
+                      s, d, st.score[r], r, sc.dpu[r], tm4, lph_of(r));
         else
             RL_LAUNCH("k_b_score", k_b_score<1>, dim3(grid_of(st.score[r], sc.grid, sc.xcd)), dim3(64 * nw), smem,
-                      s, d, st.score[r], r, sc.dpu[r], pl->tm_max, lph_of(r));
+                      s, d, st.score[r], r, sc.dpu[r], tm4, lph_of(r));
         if (tm) tm->end(1 + r, s);
         if (r >= pl->fused_from && st.refine[r].total <= FUSED_REFINE) {
             // a lone attempt's last round also writes its result
