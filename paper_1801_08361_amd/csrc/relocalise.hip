@@ -82,20 +82,21 @@ __device__ __forceinline__ float *live_energy(const Attempt &A, int r) { return 
 
 // The pool entries of pool block b for uniform picks, by the PIX_BLOCK
 // threads of a traversal workgroup (thread tid holds pixels
-// b POOL_BLOCK + j PIX_BLOCK + tid, j < 4, valid where ok[j]): the block adds
-// up the valid counts of the blocks before it and of all blocks (integer
-// sums), then places its valid pixels in raster order; block 0 stores the
+// b POOL_BLOCK + j PIX_BLOCK + tid, j < 4, valid where ok[j]): each wavefront
+// adds up the valid counts of the blocks before this one and of all blocks
+// itself (integer sums), the wavefronts share only their 64-pixel chunks'
+// counts (16 bytes of LDS, so that the traversal keeps five workgroups per
+// CU), and the valid pixels are placed in raster order; block 0 stores the
 // pool size and resets the attempt's counters. Every thread of the
 // workgroup takes part (barriers).
 static_assert(POOL_BLOCK == 4 * PIX_BLOCK, "a pool block is four traversal rows of a workgroup");
 
-__device__ void pool_block_uniform(const Attempt &A, int b, const bool ok[4], int32_t *wcnt,
-                                   unsigned long long *s_part)
+__device__ void pool_block_uniform(const Attempt &A, int b, const bool ok[4], uint8_t *wcnt)
 {
-    const int tid = (int)threadIdx.x, wave = tid >> 6;
+    const int tid = (int)threadIdx.x, wave = tid >> 6, lane = __lane_id();
     const int nb = (A.P + POOL_BLOCK - 1) / POOL_BLOCK;
     unsigned long long pc = 0ull, tc = 0ull;
-    for (int i = tid; i < nb; i += PIX_BLOCK) {
+    for (int i = lane; i < nb; i += 64) {
         const unsigned long long c = (unsigned long long)A.blockcnt[i];
         tc += c;
         if (i < b) pc += c;
@@ -107,20 +108,13 @@ __device__ void pool_block_uniform(const Attempt &A, int b, const bool ok[4], in
     uint64_t m[4];
 #pragma unroll
     for (int j = 0; j < 4; ++j) m[j] = __ballot(ok[j]);
-    if (__lane_id() == 0) {
-        s_part[wave] = pc;
-        s_part[PIX_BLOCK / 64 + wave] = tc;
+    if (lane == 0) {
 #pragma unroll
-        for (int j = 0; j < 4; ++j) wcnt[j * (PIX_BLOCK / 64) + wave] = __popcll(m[j]);
+        for (int j = 0; j < 4; ++j) wcnt[j * (PIX_BLOCK / 64) + wave] = (uint8_t)__popcll(m[j]);
     }
     __syncthreads();
-    unsigned long long blk = 0ull, tot = 0ull;
-    for (int w = 0; w < PIX_BLOCK / 64; ++w) {
-        blk += s_part[w];
-        tot += s_part[PIX_BLOCK / 64 + w];
-    }
     if (b == 0 && tid == 0) {
-        A.misc[0] = (int32_t)tot;
+        A.misc[0] = (int32_t)tc;
         A.misc[2] = 0;
         A.stats[0] = 0ull;
         A.stats[1] = 0ull;
@@ -129,7 +123,7 @@ __device__ void pool_block_uniform(const Attempt &A, int b, const bool ok[4], in
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
         const int c = j * (PIX_BLOCK / 64) + wave;
-        int off = (int)blk;
+        int off = (int)pc;
         for (int k = 0; k < c; ++k) off += wcnt[k];
         const int idx = off + __popcll(m[j] & lanemask_lt());
         if (ok[j] && idx < A.P) A.pool[idx] = b * POOL_BLOCK + j * PIX_BLOCK + tid;
@@ -150,8 +144,7 @@ template <int K>
 __global__ void __launch_bounds__(PIX_BLOCK) k_b_leaves(const Attempt *__restrict__ att, Stage S, int do_pool)
 {
     __shared__ ProbeNode top[TOP_NODES];
-    __shared__ int32_t p_wcnt[4 * (PIX_BLOCK / 64)];
-    __shared__ unsigned long long p_part[2 * (PIX_BLOCK / 64)];
+    __shared__ uint8_t p_wcnt[K == 4 ? 4 * (PIX_BLOCK / 64) : 1];
     int cached_a = -1, cached_t = -1;
     FOR_UNITS(S, u) {
         const int a = attempt_of(S, u);
@@ -171,6 +164,21 @@ __global__ void __launch_bounds__(PIX_BLOCK) k_b_leaves(const Attempt *__restric
             cached_t = t;
         }
         const int base = (local % nb) * PU + (int)threadIdx.x;
+        if constexpr (K == 4) {
+            // the units of tree 0 also write the pool of their pixel block
+            // when no attempt of the plan has pick weights (uniform per
+            // workgroup; every thread takes part)
+            if (do_pool && t == 0) {
+                bool okp[4];
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    const int q = base + k * PIX_BLOCK;
+                    okp[k] = q < A.P && packed_valid(A.packed[q < A.P ? q : A.P - 1]);
+                }
+                pool_block_uniform(A, local % nb, okp, p_wcnt);
+            }
+        }
+        if (base >= A.P) continue;
         int p[K];
         uint64_t own[K];
         bool ok[K];
@@ -181,16 +189,6 @@ __global__ void __launch_bounds__(PIX_BLOCK) k_b_leaves(const Attempt *__restric
             own[k] = A.packed[p[k]];
             ok[k] = q < A.P && packed_valid(own[k]);
         }
-        // the units of tree 0 also write the pool of their pixel blocks when
-        // no attempt of the plan has pick weights (uniform per workgroup)
-        if (do_pool && t == 0) {
-#pragma unroll
-            for (int q4 = 0; q4 < K / 4; ++q4) {
-                const bool okq[4] = {ok[4 * q4], ok[4 * q4 + 1], ok[4 * q4 + 2], ok[4 * q4 + 3]};
-                pool_block_uniform(A, (local % nb) * (K / 4) + q4, okq, p_wcnt, p_part);
-            }
-        }
-        if (base >= A.P) continue;
         int32_t leaf[K];
         traverse_packed_k<K>(top, ntop, A.deep + (int64_t)t * (A.L - 1), A.L, fr, A.packed, p, own,
                                           ok, leaf);
@@ -1896,18 +1894,19 @@ static int enqueue(const Plan *pl, const Sched &sc, const Stages &st, hipStream_
     Stage att = st.att;
     att.xcd = 0;
     RL_LAUNCH("k_b_pack", k_b_pack, dim3(grid_of(st.pb, cap, sc.xcd)), dim3(POOL_BLOCK / PB_PIX), 0, s, d, st.pb);
-    // without pick weights the traversal's tree-0 units write the pool;
-    // with them the pool (and its weight prefix) follows the weights
+    // without pick weights the 4-pixel traversal's tree-0 units write the
+    // pool; otherwise the pool (and its weight prefix) follows the weights
     bool weighted = false;
     for (const Shape &sh : pl->shape) weighted |= sh.weights != 0;
+    const bool pool_in_leaves = !weighted && sc.pix == 4;
     if (tm) tm->begin(0, s);
-    launch_leaves(sc, st, cap, d, s, weighted ? 0 : 1);
+    launch_leaves(sc, st, cap, d, s, pool_in_leaves ? 1 : 0);
     if (tm) tm->end(0, s);
     // learned weights feed the pool's weight prefix
     if (st.wts.total > 0)
         RL_LAUNCH("k_b_weights", k_b_weights, dim3(grid_of(st.wts, cap / WT_WAVES, sc.xcd)), dim3(64 * WT_WAVES), 0,
                   s, d, st.wts);
-    if (weighted)
+    if (!pool_in_leaves)
         RL_LAUNCH("k_b_pool_write", k_b_pool_write, dim3(grid_of(st.pb, cap, sc.xcd)), dim3(POOL_BLOCK / PB_PIX), 0,
                   s, d, st.pb);
     int t_max = 1;
