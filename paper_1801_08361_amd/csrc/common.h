@@ -518,6 +518,24 @@ __device__ __forceinline__ void sums_add_point(double s[NSUM], const float c[3],
     s[21] = s[21] + cd[2] * cd[2];
 }
 
+// Reciprocal for the alignment's normalisations, pivots and Newton steps
+// (none of which needs a correctly rounded quotient): on the device the
+// hardware estimate refined by two Newton-Raphson steps (each squares the
+// relative error), within about an ulp; on the host the division. The
+// divisors here are finite and non-zero where the reciprocal is used.
+__host__ __device__ __forceinline__ double rcp_d(double b)
+{
+#if defined(__HIP_DEVICE_COMPILE__)
+    double r = __builtin_amdgcn_rcp(b);
+    double e = fma(-b, r, 1.0);
+    r = fma(r, e, r);
+    e = fma(-b, r, 1.0);
+    return fma(r, e, r);
+#else
+    return 1.0 / b;
+#endif
+}
+
 // Top-eigenspace vector of a symmetric 4x4 matrix by power iteration on
 // N + s I with s = sqrt(tr N^2) (which makes every eigenvalue non-negative,
 // the largest one largest in magnitude), from (1, 0, 0, 0). Only the
@@ -610,7 +628,7 @@ __host__ __device__ __forceinline__ bool top_eigvec_horn(const double N[16], con
         const double disc = c2 * c2 - 4.0 * c0;
         double x = sqrt(0.5 * (sqrt(disc > 0.0 ? disc : 0.0) - c2));
         const double p0 = ((x * x + c2) * x + c1) * x + c0, d0 = (4.0 * (x * x) + 2.0 * c2) * x + c1;
-        if (d0 > 0.0) x = x - p0 / d0;
+        if (d0 > 0.0) x = x - p0 * rcp_d(d0);
         x = x * (1.0 + 1e-9);
         const double p1 = ((x * x + c2) * x + c1) * x + c0, d1 = (4.0 * (x * x) + 2.0 * c2) * x + c1;
         if (p1 >= 0.0 && d1 > 0.0 && 12.0 * (x * x) + 2.0 * c2 > 0.0 && x > 0.0 && x < lam) lam = x;
@@ -620,7 +638,7 @@ __host__ __device__ __forceinline__ bool top_eigvec_horn(const double N[16], con
         const double p = ((l2 + c2) * lam + c1) * lam + c0;
         const double dp = (4.0 * l2 + 2.0 * c2) * lam + c1;
         if (!(dp > 0.0)) break;
-        const double st = p / dp;
+        const double st = p * rcp_d(dp);
         if (!(st > 1e-15 * lam)) {
             if (st > 0.0) lam = lam - st;
             break;
@@ -657,7 +675,7 @@ __host__ __device__ __forceinline__ bool top_eigvec_horn(const double N[16], con
     double vn = sqrt(((v[0] * v[0] + v[1] * v[1]) + v[2] * v[2]) + v[3] * v[3]);
     if (!(vn > 0.0) || !(vn < INFINITY)) return false;
 #pragma unroll
-    for (int i = 0; i < 4; ++i) v[i] = v[i] * (1.0 / vn);
+    for (int i = 0; i < 4; ++i) v[i] = v[i] * rcp_d(vn);
     // one step of inverse iteration: solve (N - l I) x = v (reciprocal
     // pivots, reused by the back substitution)
     const double floor_ = 1e-17 * lam;
@@ -688,7 +706,7 @@ __host__ __device__ __forceinline__ bool top_eigvec_horn(const double N[16], con
         double piv = A[k * 4 + k];
         if (fabs(piv) < floor_) piv = piv < 0.0 ? -floor_ : floor_;
         A[k * 4 + k] = piv;
-        rpiv[k] = 1.0 / piv;
+        rpiv[k] = rcp_d(piv);
 #pragma unroll
         for (int i = k + 1; i < 4; ++i) {
             const double f = A[i * 4 + k] * rpiv[k];
@@ -708,7 +726,7 @@ __host__ __device__ __forceinline__ bool top_eigvec_horn(const double N[16], con
     double mx = fmax(fmax(fabs(x[0]), fabs(x[1])), fmax(fabs(x[2]), fabs(x[3])));
     if (!(mx > 0.0) || !(mx < INFINITY)) return false;
 #pragma unroll
-    for (int k = 0; k < 4; ++k) q[k] = x[k] * (1.0 / mx);
+    for (int k = 0; k < 4; ++k) q[k] = x[k] * rcp_d(mx);
     return true;
 }
 
@@ -722,7 +740,7 @@ __device__ __forceinline__ bool pose_from_sums(const double s[NSUM], double R[9]
     const double *c = s + 1, *w = s + 4, *cw = s + 7, *cc = s + 16;
     // one reciprocal per normalisation instead of a division per entry (the
     // solve is a latency chain on one lane)
-    const double rn = 1.0 / n;
+    const double rn = rcp_d(n);
     double H[9], S[6];
 #pragma unroll
     for (int a = 0; a < 3; ++a)
@@ -742,7 +760,7 @@ __device__ __forceinline__ bool pose_from_sums(const double s[NSUM], double R[9]
     double q[4];
     if (!top_eigvec_horn(N, H, q)) power_top(N, q);
     double qn = sqrt(q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3]);
-    const double rq = 1.0 / qn;
+    const double rq = rcp_d(qn);
     double q0 = q[0] * rq, qx = q[1] * rq, qy = q[2] * rq, qz = q[3] * rq;
     R[0] = q0 * q0 + qx * qx - qy * qy - qz * qz;
     R[1] = 2.0 * (qx * qy - q0 * qz);
