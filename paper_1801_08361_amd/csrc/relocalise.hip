@@ -1307,6 +1307,21 @@ __host__ __device__ constexpr int rs_lane_of(int k)
            ((((k % 11) % 6) % 3) >= 2 ? 4 : 0) + ((((k % 11) % 6) % 3) % 2 == 1 ? 2 : 0);
 }
 static_assert(NSUM == 22, "the reduce-scatter below is laid out for 22 sums");
+// every sum has exactly one even lane (and its odd neighbour) holding it
+__host__ __device__ constexpr bool rs_maps_agree()
+{
+    int held = 0;
+    for (int L = 0; L < 64; L += 2) {
+        const int k = rs_sum_of(L);
+        if (k >= NSUM || rs_sum_of(L + 1) != k) return false;
+        if (k >= 0) {
+            if (rs_lane_of(k) != L) return false;
+            ++held;
+        }
+    }
+    return held == NSUM;
+}
+static_assert(rs_maps_agree(), "lane and sum maps of the reduce-scatter disagree");
 
 // one reduce-scatter step at offset M: lanes with bit M clear return a plus
 // their partner's a, the others their partner's b plus b
